@@ -1,0 +1,202 @@
+"""Seeded synthetic inputs: grids, material fields, manufactured solutions.
+
+This module holds input generation only (mappings, random material fields,
+analytic manufactured-solution data).  It contains none of the discretisation:
+no SBP operators, no SATs, no time stepping.  Tests, the smoke check and the
+benchmark feed the same arrays to the HIP library and to the CPU oracle.
+
+Recipes (all in reference coordinates x in [0, 1]^2, physical X = X(x)):
+
+* ``identity``             X = x.
+* ``gaussian_topography``  X1 = x1, X2 = x2 + A exp(-((x1 - 0.5)/w)^2) (1 - x2),
+                           A = 0.1, w = 0.1: a Gaussian bump on the face x2 = 0.
+* ``sine_warp``            X = x + eps sin(pi x1) sin(pi x2) (1, 1), eps = 0.05, one
+                           smooth global map that is split into conforming blocks.
+* ``smooth_random_material``  rho and the six Voigt entries (c11, c12, c16, c22,
+  c26, c66) are mean * (1 + 0.3/8 sum_{m<8} a_m cos(2 pi (kx_m X1 + ky_m X2) + phi_m))
+  with integer kx, ky in [-4, 4], a ~ U(-1, 1), phi ~ U(0, 2 pi) drawn from
+  numpy.random.default_rng(seed) field by field in the order rho, c11, c12,
+  c16, c22, c26, c66; the 3x3 Voigt matrix is then clipped to eigenvalues
+  >= 0.2 and rho to >= 0.2 at every point.
+* ``paper_random_material``  rho = 1 + U(0, 1) and every independent
+  component of a major-symmetric (not minor-symmetric) tensor drawn from
+  U(0, 1), plus 4 on the C_IJIJ entries: the recipe of the paper's
+  self-adjointness experiment (Sec. 7.2).
+* ``mms_c1``  u_L = sin(2 pi X1 + L) cos(2 pi X2) cos(2 sqrt(2) pi t), L = 1, 2,
+  with constant stiffness; forcing rho u_tt - C_IJKL d_I d_K u_L and traction
+  data n_I C_IJKL d_K u_L are returned as space parts multiplying cos(omega t).
+"""
+import numpy as np
+
+VOIGT_C1 = (4.0, 1.0, 0.5, 3.0, 0.3, 1.5)        # c11, c12, c16, c22, c26, c66
+
+
+# ------------------------------------------------------------------ mappings
+class Mapping:
+    """X(x) and its analytic Jacobian dX_I/dx_i."""
+
+    def __call__(self, x1, x2):
+        raise NotImplementedError
+
+    def jac(self, x1, x2):
+        raise NotImplementedError
+
+
+class Identity(Mapping):
+    def __call__(self, x1, x2):
+        return x1 + 0.0 * x2, x2 + 0.0 * x1
+
+    def jac(self, x1, x2):
+        o, z = np.ones_like(x1 + x2), np.zeros_like(x1 + x2)
+        return np.array([[o, z], [z, o]])        # [i][I]
+
+
+class GaussianTopography(Mapping):
+    def __init__(self, amp=0.1, width=0.1):
+        self.A, self.w = amp, width
+
+    def __call__(self, x1, x2):
+        g = self.A * np.exp(-((x1 - 0.5) / self.w) ** 2)
+        return x1 + 0.0 * x2, x2 + g * (1.0 - x2)
+
+    def jac(self, x1, x2):
+        g = self.A * np.exp(-((x1 - 0.5) / self.w) ** 2)
+        dg = g * (-2.0 * (x1 - 0.5) / self.w ** 2)
+        o, z = np.ones_like(x1 + x2), np.zeros_like(x1 + x2)
+        return np.array([[o, dg * (1.0 - x2)], [z, 1.0 - g + 0.0 * x1]])
+
+
+class SineWarp(Mapping):
+    def __init__(self, eps=0.05):
+        self.e = eps
+
+    def __call__(self, x1, x2):
+        s = self.e * np.sin(np.pi * x1) * np.sin(np.pi * x2)
+        return x1 + s, x2 + s
+
+    def jac(self, x1, x2):
+        d1 = self.e * np.pi * np.cos(np.pi * x1) * np.sin(np.pi * x2)
+        d2 = self.e * np.pi * np.sin(np.pi * x1) * np.cos(np.pi * x2)
+        return np.array([[1.0 + d1, d1], [d2, 1.0 + d2]])
+
+
+MAPPINGS = {'identity': Identity, 'gaussian_topography': GaussianTopography,
+            'sine_warp': SineWarp}
+
+
+def reference_grid(n1, n2, x1lim=(0.0, 1.0), x2lim=(0.0, 1.0)):
+    x1 = np.linspace(x1lim[0], x1lim[1], n1)
+    x2 = np.linspace(x2lim[0], x2lim[1], n2)
+    return np.meshgrid(x1, x2)            # arrays (n2, n1), x1 fastest
+
+
+def grid(mapping, n1, n2, x1lim=(0.0, 1.0), x2lim=(0.0, 1.0)):
+    """Physical grid coordinates (X1, X2), arrays of shape (n2, n1)."""
+    x1, x2 = reference_grid(n1, n2, x1lim, x2lim)
+    X1, X2 = mapping(x1, x2)
+    return np.ascontiguousarray(X1), np.ascontiguousarray(X2)
+
+
+def outward_normal(mapping, face, n1, n2, x1lim=(0.0, 1.0), x2lim=(0.0, 1.0)):
+    """Exact unit outward physical normal on a face of a (sub)block, shape (2, nf)."""
+    x1, x2 = reference_grid(n1, n2, x1lim, x2lim)
+    sel = [(slice(None), 0), (slice(None), -1), (0, slice(None)), (-1, slice(None))][face]
+    A = mapping.jac(x1[sel], x2[sel])                   # A[i][I] = dX_I/dx_i
+    a = 0 if face < 2 else 1
+    t = 1 - a
+    tang = np.array([A[t][0], A[t][1]])
+    n = np.array([tang[1], -tang[0]])                  # rotate the tangent by -90 deg
+    # orient outward: compare with the covariant normal direction a_a
+    nor = np.array([A[a][0], A[a][1]])
+    sgn = -1.0 if face in (0, 2) else 1.0
+    s = np.sign(np.sum(n * nor, axis=0)) * sgn
+    n = n * s
+    return n / np.sqrt(n[0] ** 2 + n[1] ** 2)
+
+
+# --------------------------------------------------------- material fields
+def voigt_to_c10(V):
+    """Voigt (6, ...) -> the 10 major-symmetric components in the library order
+    C1111, C1112, C1121, C1122, C1212, C1221, C1222, C2121, C2122, C2222."""
+    c11, c12, c16, c22, c26, c66 = V
+    return np.stack([c11, c16, c16, c12, c66, c66, c26, c66, c26, c22])
+
+
+def smooth_random_material(X1, X2, seed, rho_mean=1.0, voigt_mean=VOIGT_C1,
+                           nmodes=8, kmax=4, rel_amp=0.3, min_eig=0.2):
+    rng = np.random.default_rng(seed)
+    fields = []
+    for mean in (rho_mean,) + tuple(voigt_mean):
+        kx = rng.integers(-kmax, kmax + 1, nmodes)
+        ky = rng.integers(-kmax, kmax + 1, nmodes)
+        ph = rng.uniform(0.0, 2.0 * np.pi, nmodes)
+        a = rng.uniform(-1.0, 1.0, nmodes)
+        s = np.zeros_like(X1)
+        for m in range(nmodes):
+            s += a[m] * np.cos(2.0 * np.pi * (kx[m] * X1 + ky[m] * X2) + ph[m])
+        fields.append(mean * (1.0 + rel_amp * s / nmodes))
+    rho = np.maximum(fields[0], min_eig)
+    c11, c12, c16, c22, c26, c66 = fields[1:]
+    M = np.stack([np.stack([c11, c12, c16], -1), np.stack([c12, c22, c26], -1),
+                  np.stack([c16, c26, c66], -1)], -2)
+    lam, Q = np.linalg.eigh(M)
+    lam = np.maximum(lam, min_eig)
+    M = np.einsum('...ik,...k,...jk->...ij', Q, lam, Q)
+    V = np.stack([M[..., 0, 0], M[..., 0, 1], M[..., 0, 2], M[..., 1, 1], M[..., 1, 2], M[..., 2, 2]])
+    return np.ascontiguousarray(rho), np.ascontiguousarray(V)
+
+
+def paper_random_material(shape, seed):
+    """rho (shape) and C10 (10, *shape), Cosserat (major symmetry only)."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + rng.uniform(0.0, 1.0, shape)
+    C10 = rng.uniform(0.0, 1.0, (10,) + tuple(shape))
+    for m in (0, 4, 7, 9):                  # C1111, C1212, C2121, C2222 (the C_IJIJ entries)
+        C10[m] += 4.0
+    return rho, C10
+
+
+def c10_to_full(C10):
+    order = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 1), (1, 2), (1, 3), (2, 2), (2, 3), (3, 3)]
+    pairs = [(0, 0), (0, 1), (1, 0), (1, 1)]
+    C = np.zeros((2, 2, 2, 2) + C10.shape[1:])
+    for m, (p, q) in enumerate(order):
+        C[pairs[p] + pairs[q]] = C10[m]
+        C[pairs[q] + pairs[p]] = C10[m]
+    return C
+
+
+# ------------------------------------------------- manufactured solution
+OMEGA_C1 = 2.0 * np.sqrt(2.0) * np.pi
+
+
+def mms_c1(X1, X2, C10, rho=1.0):
+    """Space parts of u, forcing and tractions for the C1 manufactured solution.
+
+    Constant stiffness C10 (10,), constant rho.  Returns dict with
+    ``u`` (2, n2, n1), ``f`` (2, n2, n1) and ``grad`` (2 [L], 2 [K], n2, n1) so
+    that u(t) = u cos(omega t), f(t) = f cos(omega t); the traction data on a
+    face with unit normal n is n_I C_IJKL grad[L, K] (see ``traction_data``).
+    """
+    C = c10_to_full(np.asarray(C10, dtype=float))
+    tp = 2.0 * np.pi
+    u = np.stack([np.sin(tp * X1 + L) * np.cos(tp * X2) for L in (1, 2)])
+    grad = np.stack([np.stack([tp * np.cos(tp * X1 + L) * np.cos(tp * X2),
+                               -tp * np.sin(tp * X1 + L) * np.sin(tp * X2)]) for L in (1, 2)])
+    hess = np.empty((2, 2, 2) + X1.shape)        # [L, I, K]
+    for Li, L in enumerate((1, 2)):
+        s = np.sin(tp * X1 + L) * np.cos(tp * X2)
+        m = np.cos(tp * X1 + L) * np.sin(tp * X2)
+        hess[Li, 0, 0] = -tp ** 2 * s
+        hess[Li, 1, 1] = -tp ** 2 * s
+        hess[Li, 0, 1] = -tp ** 2 * m
+        hess[Li, 1, 0] = -tp ** 2 * m
+    div = np.einsum('IJKL,LIK...->J...', C, hess)
+    f = -rho * OMEGA_C1 ** 2 * u - div
+    return dict(u=u, f=f, grad=grad, C=C, omega=OMEGA_C1)
+
+
+def traction_data(mms, face_idx, normal):
+    """n_I C_IJKL d_K u_L at the face points (flat indices), shape (2, nf)."""
+    g = mms['grad'].reshape(2, 2, -1)[..., face_idx]
+    return np.einsum('If,IJKL,LKf->Jf', normal, mms['C'], g)

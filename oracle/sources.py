@@ -29,9 +29,12 @@ def weights_1d(x0, n):
     m0 = int(np.floor(x0 / h)) - 1
     m0 = min(max(m0, 0), n - 4)
     idx = np.arange(m0, m0 + 4)
-    x = idx * h
-    V = np.vstack([x ** p for p in range(4)])
-    w = np.linalg.solve(V, np.array([x0 ** p for p in range(4)]))
+    # the moment conditions are solved in local coordinates xi = (x - x_m0)/h,
+    # which span the same cubic polynomials and keep the system well conditioned
+    xi = np.arange(4.0)
+    xi0 = (x0 - m0 * h) / h
+    V = np.vstack([xi ** p for p in range(4)])
+    w = np.linalg.solve(V, np.array([xi0 ** p for p in range(4)]))
     return idx, w
 
 

@@ -1,0 +1,191 @@
+/*
+ * sbpe.h -- C ABI of the MI355X (gfx950) SBP-SAT anisotropic elastic wave library.
+ *
+ * The library evaluates the right-hand side of the semidiscrete scheme of
+ * Almquist & Dunham, "Elastic wave propagation in anisotropic solids using
+ * energy-stable finite differences with weakly enforced boundary and interface
+ * conditions" (arXiv 2003.12811):
+ *
+ *     rho u_tt = D^Omega(C) u + f + SAT                      (Sec. 5, eq. semidiscrete_general)
+ *
+ * on curvilinear multiblock 2-D grids, with the narrow fully compatible
+ * operator DD_ik(c_ijkl) (Sec. 4.6-4.7), Robin/traction SATs (Sec. 5.1,
+ * eq. sat_traction), displacement SATs (Sec. 5.2, eq. dirichlet_ansatz,
+ * Theorem 2) and interface SATs (Sec. 6, eq. scheme_interface), and advances it
+ * with classical fourth-order Runge-Kutta (Sec. 7.1).
+ *
+ * Conventions used by every call:
+ *   - A block is the image of the reference square [0,1]^2 with n1 x n2 grid
+ *     points, x1 = i/(n1-1), x2 = j/(n2-1).  Grid functions are row-major
+ *     [n2][n1] (x1 fastest); vector fields are two such arrays back to back
+ *     ([2][n2][n1], Cartesian components u_1 then u_2).
+ *   - Host arrays are read during the call (or at sbpe_finalize for arrays
+ *     registered with sbpe_add_block / sbpe_set_bc_data / sbpe_set_forcing,
+ *     which are copied at the call itself); the caller keeps ownership.
+ *   - Device pointers (for example torch tensor data_ptr() values) are owned by
+ *     the caller, must hold n1*n2*2 elements of the context dtype, and are
+ *     accessed on the context stream in enqueue order; the call returns before
+ *     the GPU work completes unless stated otherwise.
+ *   - Every call returns SBPE_OK (0) or a negative sbpe_status; arguments are
+ *     validated on the host before anything is enqueued, and a failed call
+ *     leaves the context unchanged.  sbpe_last_error() gives a message.
+ *   - A context is used from one host thread at a time.
+ */
+#ifndef SBPE_H
+#define SBPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbpe_ctx* sbpe_ctx_t;
+typedef int32_t sbpe_status;
+
+enum {
+    SBPE_OK = 0,
+    SBPE_EINVAL = -1,      /* invalid argument */
+    SBPE_ENONPOS_J = -2,   /* discrete Jacobian J <= 0 somewhere (Sec. 3.3) */
+    SBPE_ENOT_PSD = -3,    /* stiffness not major-symmetric positive semidefinite (Sec. 3, eq. definite_phys) */
+    SBPE_EIFACE = -4,      /* faces of an interface are not conforming (Sec. 6) */
+    SBPE_ENOMEM = -5,      /* device allocation failed */
+    SBPE_EHIP = -6,        /* HIP runtime error */
+    SBPE_EUNSTABLE = -7,   /* energy guard tripped: discrete energy grew or became non-finite */
+    SBPE_ESTATE = -8       /* call not valid in the current context state */
+};
+
+enum { SBPE_F64 = 0, SBPE_F32 = 1 };                 /* storage and arithmetic precision */
+enum { SBPE_FACE_X1LO = 0, SBPE_FACE_X1HI = 1, SBPE_FACE_X2LO = 2, SBPE_FACE_X2HI = 3 };
+enum { SBPE_BC_TRACTION = 0, SBPE_BC_ROBIN = 1, SBPE_BC_DISPLACEMENT = 2, SBPE_BC_INTERFACE = 3 };
+/* time functions tau(t) multiplying separable data g(x) tau(t):
+ *   ZERO: 0;  ONE: 1;  COS: cos(p0 t + p1);  RICKER: (1 - 2 a) exp(-a), a = (pi p0 (t - p1))^2
+ *   (Ricker wavelet with peak frequency p0 centred at p1, Sec. 7.3). */
+enum { SBPE_TIME_ZERO = 0, SBPE_TIME_ONE = 1, SBPE_TIME_COS = 2, SBPE_TIME_RICKER = 3 };
+
+/* Create a context bound to HIP device `device` and stream `stream` (NULL = the
+ * default stream).  dtype: SBPE_F64 or SBPE_F32.  order: 2 or 4 (interior order
+ * of the SBP operators, Sec. 4).  beta >= 1 scales the displacement and
+ * interface penalties (Theorem 2; the paper uses beta = 1).  device = -1 makes
+ * a host-only context: setup and the sbpe_host_* / sbpe_get_* queries work,
+ * every call that needs a GPU returns SBPE_ESTATE. */
+sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double beta, sbpe_ctx_t* out);
+
+/* Free all device memory owned by the context (after synchronising its stream). */
+sbpe_status sbpe_destroy(sbpe_ctx_t ctx);
+
+/* Message of the last failed call on this context (never NULL; static storage
+ * for ctx == NULL). */
+const char* sbpe_last_error(sbpe_ctx_t ctx);
+
+/* Add a block (Sec. 3.2): physical grid coordinates X1, X2, density rho (all
+ * [n2][n1]) and stiffness C10 ([10][n2][n1]: the major-symmetric components
+ * C1111, C1112, C1121, C1122, C1212, C1221, C1222, C2121, C2122, C2222; minor
+ * symmetry is not assumed, Sec. 3).  Arrays are copied.  All faces start as
+ * homogeneous traction.  n1, n2 >= 13 for order 4, >= 6 for order 2. */
+sbpe_status sbpe_add_block(sbpe_ctx_t ctx, int n1, int n2, const double* X1, const double* X2,
+                           const double* rho, const double* C10, int* block_id);
+
+/* Convert Voigt stiffness (c11, c12, c16, c22, c26, c66 per point, [6][npts],
+ * no factor 2, index 6 <-> 12) of a normal material to the C10 layout. */
+sbpe_status sbpe_voigt_to_c10(const double* voigt, size_t npts, double* C10);
+
+/* Boundary condition of a face (Sec. 5): traction, Robin (U: [2][2][nf]
+ * symmetric positive semidefinite U_JL at the face points, row-major JL;
+ * required for Robin, ignored otherwise) or displacement.  Interfaces are made
+ * with sbpe_connect. */
+sbpe_status sbpe_set_bc(sbpe_ctx_t ctx, int block, int face, int bc, const double* U);
+
+/* Separable boundary data g_J(x) tau(t) of a face: g [2][nf] (traction data for
+ * traction/Robin faces, boundary displacement for displacement faces), copied. */
+sbpe_status sbpe_set_bc_data(sbpe_ctx_t ctx, int block, int face, const double* g,
+                             int time_fn, const double* time_params);
+
+/* Conforming interface between face faceA of block blkA and face faceB of block
+ * blkB (Sec. 6, eq. scheme_interface); reversed != 0 when the two faces run in
+ * opposite directions.  Both faces need the same number of points. */
+sbpe_status sbpe_connect(sbpe_ctx_t ctx, int blkA, int faceA, int blkB, int faceB, int reversed);
+
+/* Separable body force f_J(x) tau(t) of a block: F [2][n2][n1], copied. */
+sbpe_status sbpe_set_forcing(sbpe_ctx_t ctx, int block, const double* F, int time_fn,
+                             const double* time_params);
+
+/* Point force f = (f1, f2) amp W(t) delta(X - X(x0)) at reference position
+ * (x1, x2) in [0,1]^2 with Ricker time function W of peak frequency peak_hz
+ * centred at t0 (Sec. 7.3).  The discrete delta uses four-point moment-matching
+ * weights per direction (exact for cubics). */
+sbpe_status sbpe_add_source(sbpe_ctx_t ctx, int block, double x1, double x2, double f1, double f2,
+                            double amp, double peak_hz, double t0);
+
+/* Receivers at reference positions (x1[k], x2[k]); they record
+ * sum_p w_p u(p) with the source weights after every RK4 step. */
+sbpe_status sbpe_add_receivers(sbpe_ctx_t ctx, int block, int n, const double* x1, const double* x2);
+
+/* Compute metric terms (Sec. 3.3: F from D1 of the scheme's order, J, Jhat,
+ * Nanson normals), the transformed stiffness c = F J C F and rho~ = J rho
+ * (eq. transf_density_stiffness), checks (J > 0, symmetry and PSD of C), build
+ * launch plans and upload everything to the device. */
+sbpe_status sbpe_finalize(sbpe_ctx_t ctx);
+
+/* Largest stable time step estimate dt = cfl * min h / v_max with v_max from
+ * the Christoffel matrix of (rho~, c) maximised over directions (Sec. 7). */
+sbpe_status sbpe_dt_cfl(sbpe_ctx_t ctx, double cfl, double* dt);
+
+/* Grid size of a block. */
+sbpe_status sbpe_block_size(sbpe_ctx_t ctx, int block, int* n1, int* n2);
+
+/* One right-hand-side evaluation on the device: for every block b,
+ * a[b] = rho~^{-1} (DD(c) u + J f(t) + J SAT(u, t)), i.e. the acceleration of
+ * the semidiscrete scheme.  homogeneous != 0 drops all data, forcing and
+ * sources (the operator D^tot of Sec. 5.3 scaled by rho^{-1}).  u[b], a[b] are
+ * device pointers of 2*n1*n2 elements; a must not alias any u. */
+sbpe_status sbpe_apply(sbpe_ctx_t ctx, const void* const* u, void* const* a, double t, int homogeneous);
+
+/* Bind caller-owned device state buffers u[b], v[b] (displacement and
+ * velocity, 2*n1*n2 elements each) and set the current time.  The buffers are
+ * read and written in place by sbpe_advance and must stay valid while bound. */
+sbpe_status sbpe_bind_state(sbpe_ctx_t ctx, void* const* u, void* const* v, double t);
+
+/* Advance the bound state by nsteps classical RK4 steps of size dt (Sec. 7.1). */
+sbpe_status sbpe_advance(sbpe_ctx_t ctx, int nsteps, double dt);
+
+/* Current time of the bound state. */
+sbpe_status sbpe_get_time(sbpe_ctx_t ctx, double* t);
+
+/* Copy receiver traces recorded since the last sbpe_bind_state into out
+ * ([nsteps][nrec][2], FP64, host), at most max_steps steps; synchronises. */
+sbpe_status sbpe_read_receivers(sbpe_ctx_t ctx, double* out, int max_steps, int* nsteps_out);
+
+/* Discrete energy eps = 1/2 (v^T P H v - u^T A u), A = diag(JH) D^tot, of the
+ * bound state (Sec. 5 and 7.2), accumulated in FP64; synchronises. */
+sbpe_status sbpe_energy(sbpe_ctx_t ctx, double* eps);
+
+/* Energy guard: every `every` steps sbpe_advance computes the energy and fails
+ * with SBPE_EUNSTABLE if it is not finite or exceeds (1 + rel_growth) times the
+ * energy at the start of the call.  every = 0 disables it (default). */
+sbpe_status sbpe_set_energy_guard(sbpe_ctx_t ctx, int every, double rel_growth);
+
+/* Wait for all work enqueued on the context stream. */
+sbpe_status sbpe_synchronize(sbpe_ctx_t ctx);
+
+/* ---------------------------------------------------------------- host-side
+ * Queries of the library's own setup, for checking it on a machine without a
+ * GPU.  They run on the host only. */
+
+/* The adapted fully compatible D2^FC(b) (Sec. 4.1) and D1 of the library
+ * applied to one grid line of n points with h = 1/(n-1): out = D2^FC(b) u and
+ * out = D1 u. */
+sbpe_status sbpe_host_d2fc_line(int order, int n, const double* b, const double* u, double* out);
+sbpe_status sbpe_host_d1_line(int order, int n, const double* u, double* out);
+
+/* After sbpe_finalize: transformed stiffness of a block in the C10 layout
+ * ([10][n2][n1]), J ([n2][n1]) and the surface scale factor of each face
+ * (Jhat, [4][max(n1,n2)], face f uses its first n2 (f < 2) or n1 entries). */
+sbpe_status sbpe_get_block_fields(sbpe_ctx_t ctx, int block, double* c10, double* J, double* jhat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBPE_H */

@@ -1,0 +1,1177 @@
+// Host side of the SBP-SAT elastic wave library: context, setup of the metric
+// terms and transformed coefficients, launch plans and the C ABI of sbpe.h.
+//
+// Setup follows Sec. 3.2-3.3 of Almquist & Dunham (arXiv 2003.12811):
+//   F^{-1}_{iI} = dX_I/dx_i from D1 of the scheme's order, J = det F^{-1},
+//   c_ijkl = F_Ii J C_IjKl F_Kk, rho~ = J rho (eq. transf_density_stiffness),
+//   Jhat = |a_t| on each face (eq. surfj_app_2d); J <= 0 is rejected.
+// The time step follows Sec. 7: dt = CFL min h / v_max with v_max^2 the largest
+// eigenvalue of xi_i c_ijkl xi_k / rho~ maximised over directions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sbpe.h"
+#include "sbpe_internal.h"
+#include "sbpe_tables.h"
+
+namespace sbpe {
+
+// ------------------------------------------------------------- 1-D tables
+static int nb_of(int order) { return order == 4 ? O4_NB : O2_NB; }
+
+double norm_weight(int order, int n, int k) {
+    const int nb = nb_of(order);
+    const double* H = order == 4 ? O4_H : O2_H;
+    if (k < nb) return H[k];
+    if (k > n - 1 - nb) return H[n - 1 - k];
+    return 1.0;
+}
+
+// row r of the dimensionless D1: start column and weights (up to 6)
+static int d1_row(int order, int r, int n, int& start, double w[6]) {
+    const int nb = nb_of(order);
+    const double(*B)[6] = order == 4 ? O4_D1B : O2_D1B;
+    if (r < nb) {
+        start = 0;
+        for (int c = 0; c < 6; ++c) w[c] = B[r][c];
+        return 6;
+    }
+    if (r > n - 1 - nb) {
+        const int rr = n - 1 - r;
+        start = n - 6;
+        for (int k = 0; k < 6; ++k) w[k] = -B[rr][5 - k];
+        return 6;
+    }
+    const int half = order == 4 ? 2 : 1;
+    const double* I = order == 4 ? O4_D1I : O2_D1I;
+    start = r - half;
+    for (int k = 0; k < 2 * half + 1; ++k) w[k] = I[k];
+    return 2 * half + 1;
+}
+
+void dense_d1(int order, int n, double* D) {
+    std::fill(D, D + (size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r) {
+        int s0;
+        double w[6];
+        const int len = d1_row(order, r, n, s0, w);
+        for (int k = 0; k < len; ++k)
+            if (s0 + k >= 0 && s0 + k < n) D[(size_t)r * n + s0 + k] += w[k];
+    }
+}
+
+// remainder windows of h R(b) on a line of n points: for every window its
+// first point, stencil, weight gamma and the shares defining B(b).
+struct Window {
+    int c;
+    int len;
+    double d[5];
+    double g;
+    int nsh;
+    int shp[2];
+    double shw[2];
+};
+
+static std::vector<Window> windows(int order, int n) {
+    std::vector<Window> out;
+    if (order == 2) {
+        for (int c = 0; c + 2 < n; ++c) {
+            Window w{c, 3, {1, -2, 1, 0, 0}, O2_G2, 1, {c + 1, 0}, {1.0, 0.0}};
+            out.push_back(w);
+        }
+        return out;
+    }
+    const int n3 = n - 3;
+    for (int c = 0; c < n3; ++c) {
+        double g = O4_G3;
+        if (c < 3) g = O4_G3_BND[c];
+        else if (n3 - 1 - c < 3) g = O4_G3_BND[n3 - 1 - c];
+        Window w{c, 4, {-1, 3, -3, 1, 0}, g, 2, {c + 1, c + 2}, {0.5, 0.5}};
+        out.push_back(w);
+    }
+    for (int c = 0; c + 4 < n; ++c) {
+        Window w{c, 5, {1, -4, 6, -4, 1}, O4_G4, 1, {c + 2, 0}, {1.0, 0.0}};
+        out.push_back(w);
+    }
+    return out;
+}
+
+void derive_d2_closure(int order, double* T) {
+    const int R0 = order == 4 ? O4_R0 : O2_R0;
+    const int W = order == 4 ? O4_W : O2_W;
+    const int n = 32;
+    std::vector<double> D((size_t)n * n);
+    dense_d1(order, n, D.data());
+    std::fill(T, T + (size_t)R0 * W * W, 0.0);
+    const auto wins = windows(order, n);
+    for (int r = 0; r < R0; ++r) {
+        const double ir = 1.0 / norm_weight(order, n, r);
+        for (int m = 0; m < W; ++m) {
+            for (int s = 0; s < W; ++s) {
+                // -D1^T H b D1
+                double v = -D[(size_t)s * n + r] * norm_weight(order, n, s) * D[(size_t)s * n + m];
+                // -R(b)
+                for (const auto& w : wins) {
+                    if (r < w.c || r >= w.c + w.len || m < w.c || m >= w.c + w.len) continue;
+                    for (int q = 0; q < w.nsh; ++q)
+                        if (w.shp[q] == s) v -= w.g * w.shw[q] * w.d[r - w.c] * w.d[m - w.c];
+                }
+                // -e0 b0 e0^T D1 (boundary derivative replaced by D1: fully compatible)
+                if (r == 0 && s == 0) v -= D[m];
+                T[((size_t)r * W + m) * W + s] = v * ir;
+            }
+        }
+    }
+}
+
+// banded host application of D1 along a strided line (with 1/h)
+static void d1_apply(int order, int n, double h, const double* u, long st, double* out, long ost) {
+    for (int r = 0; r < n; ++r) {
+        int s0;
+        double w[6];
+        const int len = d1_row(order, r, n, s0, w);
+        double acc = 0.0;
+        for (int k = 0; k < len; ++k) acc += w[k] * u[(long)(s0 + k) * st];
+        out[(long)r * ost] = acc / h;
+    }
+}
+
+// ------------------------------------------------------------- context
+struct HostFace {
+    int kind = BC_TRACTION;
+    std::vector<double> U;      // [4][nf] physical U_JL
+    std::vector<double> g;      // [2][nf]
+    TimeFn tf{TF_ZERO, 0, {0.0, 0.0}};
+    int partner = -1, pface = -1, reversed = 0, side = 0;
+    std::vector<double> jhat;   // computed
+};
+
+struct HostBlock {
+    int n1 = 0, n2 = 0;
+    double h1 = 0, h2 = 0;
+    std::vector<double> X1, X2, rho, C10;
+    std::vector<double> F;      // forcing space part [2][np]
+    TimeFn ftf{TF_ZERO, 0, {0.0, 0.0}};
+    HostFace face[4];
+    // computed at finalize
+    std::vector<double> coef;   // [NCOEF][np]
+    std::vector<double> J;
+    std::vector<double> c10t;   // transformed stiffness, C10 layout
+    // device memory owned by the context
+    void* d_coef = nullptr;
+    void* d_force = nullptr;
+    void* d_a1 = nullptr;
+    void* d_a2 = nullptr;
+    void* d_face[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    void* u = nullptr;
+    void* v = nullptr;
+    long np() const { return (long)n1 * n2; }
+    int nf(int f) const { return f < 2 ? n2 : n1; }
+};
+
+struct Source {
+    int block;
+    double x1, x2, f1, f2, amp, fp, t0;
+};
+struct Receiver {
+    int block;
+    double x1, x2;
+};
+
+}  // namespace sbpe
+
+using namespace sbpe;
+
+struct sbpe_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int dtype = SBPE_F64;
+    int order = 4;
+    double beta = 1.0;
+    bool host_only = false;
+    std::string err;
+    std::vector<HostBlock> blocks;
+    std::vector<Source> sources;
+    std::vector<Receiver> receivers;
+    bool finalized = false;
+    // plan
+    std::vector<BlockDesc> desc;
+    BlockDesc* d_desc = nullptr;
+    Entry* d_entries = nullptr;
+    Range* d_tile_ranges = nullptr;
+    Range* d_frame_ranges = nullptr;
+    TimeFn* d_src_tf = nullptr;
+    int total_tiles = 0, total_frame_wg = 0;
+    // state
+    bool bound = false;
+    double t = 0.0;
+    double* d_rec = nullptr;
+    long rec_cap = 0;       // steps of capacity
+    long rec_steps = 0;     // steps recorded
+    double* d_epart = nullptr;
+    double* d_eout = nullptr;
+    int npartial = 0;
+    int guard_every = 0;
+    double guard_growth = 0.0;
+};
+
+static thread_local std::string g_static_err;
+
+static sbpe_status fail(sbpe_ctx* c, sbpe_status code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_static_err = msg;
+    return code;
+}
+
+static size_t esize(const sbpe_ctx* c) { return c->dtype == SBPE_F64 ? 8 : 4; }
+
+#define HIPCHECK(ctx, expr)                                                                       \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, SBPE_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+// upload a double host array to device memory of the context dtype
+static sbpe_status upload(sbpe_ctx* c, const std::vector<double>& h, void** d) {
+    const size_t n = h.size();
+    if (hipMalloc(d, n * esize(c)) != hipSuccess) return fail(c, SBPE_ENOMEM, "device allocation failed");
+    if (c->dtype == SBPE_F64) {
+        HIPCHECK(c, hipMemcpy(*d, h.data(), n * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(h.begin(), h.end());
+        HIPCHECK(c, hipMemcpy(*d, f.data(), n * 4, hipMemcpyHostToDevice));
+    }
+    return SBPE_OK;
+}
+
+// ---------------------------------------------------------- eigen helpers
+// smallest and largest eigenvalue of a symmetric 4x4 matrix (cyclic Jacobi)
+static void eig4(const double Ain[16], double& lmin, double& lmax) {
+    double a[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) a[i][j] = Ain[4 * i + j];
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) off += a[p][q] * a[p][q];
+        if (off < 1e-30) break;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                if (std::fabs(a[p][q]) < 1e-300) continue;
+                const double th = 0.5 * (a[q][q] - a[p][p]) / a[p][q];
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 4; ++k) {
+                    const double akp = a[k][p], akq = a[k][q];
+                    a[k][p] = cs * akp - sn * akq;
+                    a[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double apk = a[p][k], aqk = a[q][k];
+                    a[p][k] = cs * apk - sn * aqk;
+                    a[q][k] = sn * apk + cs * aqk;
+                }
+            }
+    }
+    lmin = lmax = a[0][0];
+    for (int i = 1; i < 4; ++i) {
+        lmin = std::min(lmin, a[i][i]);
+        lmax = std::max(lmax, a[i][i]);
+    }
+}
+
+// pair index (IJ) -> 0..3 with 11, 12, 21, 22; C10 upper triangle order
+static const int C10P[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+
+static void c10_to_mat(const double* c10, long np, long p, double M[16]) {
+    for (int m = 0; m < 10; ++m) {
+        const double v = c10[m * np + p];
+        M[4 * C10P[m][0] + C10P[m][1]] = v;
+        M[4 * C10P[m][1] + C10P[m][0]] = v;
+    }
+}
+
+// ------------------------------------------------------------- setup
+static sbpe_status setup_block(sbpe_ctx* c, int b) {
+    HostBlock& B = c->blocks[b];
+    const int n1 = B.n1, n2 = B.n2, o = c->order;
+    const long np = B.np();
+    B.h1 = 1.0 / (n1 - 1);
+    B.h2 = 1.0 / (n2 - 1);
+    // A[i][I] = dX_I / dx_i
+    std::vector<double> A00(np), A01(np), A10(np), A11(np);
+    for (int j = 0; j < n2; ++j) {
+        d1_apply(o, n1, B.h1, &B.X1[(long)j * n1], 1, &A00[(long)j * n1], 1);
+        d1_apply(o, n1, B.h1, &B.X2[(long)j * n1], 1, &A01[(long)j * n1], 1);
+    }
+    for (int i = 0; i < n1; ++i) {
+        d1_apply(o, n2, B.h2, &B.X1[i], n1, &A10[i], n1);
+        d1_apply(o, n2, B.h2, &B.X2[i], n1, &A11[i], n1);
+    }
+    B.J.assign(np, 0.0);
+    B.coef.assign((size_t)NCOEF * np, 0.0);
+    B.c10t.assign((size_t)10 * np, 0.0);
+    for (long p = 0; p < np; ++p) {
+        const double J = A00[p] * A11[p] - A01[p] * A10[p];
+        if (!(J > 0.0)) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "block %d: discrete Jacobian %.3e <= 0 at point (%ld, %ld)", b, J,
+                          p % n1, p / n1);
+            return fail(c, SBPE_ENONPOS_J, buf);
+        }
+        B.J[p] = J;
+        // F[I][i] = dx_i / dX_I
+        const double F[2][2] = {{A11[p] / J, -A01[p] / J}, {-A10[p] / J, A00[p] / J}};
+        double Cm[16];
+        c10_to_mat(B.C10.data(), np, p, Cm);
+        double lmin, lmax;
+        eig4(Cm, lmin, lmax);
+        if (lmin < -1e-10 * std::max(1.0, std::fabs(lmax))) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "block %d: stiffness not positive semidefinite at point (%ld, %ld)", b,
+                          p % n1, p / n1);
+            return fail(c, SBPE_ENOT_PSD, buf);
+        }
+        // c_ijkl = J F_Ii C_IjKl F_Kk ; C pair index (IJ) -> 2I + J
+        double cc[2][2][2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int k = 0; k < 2; ++k)
+                    for (int l = 0; l < 2; ++l) {
+                        double s = 0.0;
+                        for (int I = 0; I < 2; ++I)
+                            for (int K = 0; K < 2; ++K) s += F[I][i] * Cm[4 * (2 * I + j) + (2 * K + l)] * F[K][k];
+                        cc[i][j][k][l] = J * s;
+                    }
+        double* q = B.coef.data();
+        q[K_C1111 * np + p] = cc[0][0][0][0];
+        q[K_C1112 * np + p] = cc[0][0][0][1];
+        q[K_C1212 * np + p] = cc[0][1][0][1];
+        q[K_C2121 * np + p] = cc[1][0][1][0];
+        q[K_C2122 * np + p] = cc[1][0][1][1];
+        q[K_C2222 * np + p] = cc[1][1][1][1];
+        q[K_C1121 * np + p] = cc[0][0][1][0];
+        q[K_C1122 * np + p] = cc[0][0][1][1];
+        q[K_C1221 * np + p] = cc[0][1][1][0];
+        q[K_C1222 * np + p] = cc[0][1][1][1];
+        q[K_IRHO * np + p] = 1.0 / (J * B.rho[p]);
+        const int pr[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
+        for (int m = 0; m < 10; ++m) {
+            const int* a = pr[C10P[m][0]];
+            const int* d = pr[C10P[m][1]];
+            B.c10t[m * np + p] = cc[a[0]][a[1]][d[0]][d[1]];
+        }
+    }
+    // surface scale factors: Jhat = |a_t|, a_t = dX/dx_t
+    for (int f = 0; f < 4; ++f) {
+        const int nf = B.nf(f);
+        B.face[f].jhat.assign(nf, 0.0);
+        for (int t = 0; t < nf; ++t) {
+            long p;
+            if (f < 2) p = (long)t * n1 + (f == 0 ? 0 : n1 - 1);
+            else p = (long)(f == 2 ? 0 : n2 - 1) * n1 + t;
+            B.face[f].jhat[t] = f < 2 ? std::hypot(A10[p], A11[p]) : std::hypot(A00[p], A01[p]);
+        }
+    }
+    return SBPE_OK;
+}
+
+// v_max^2 = max over xi of the largest eigenvalue of xi_i c_ijkl xi_k / rho~ at point p
+static double christoffel_lmax(const HostBlock& B, long p, double th) {
+    const long np = B.np();
+    const double* q = B.coef.data();
+    const double cs = std::cos(th), sn = std::sin(th);
+    // Gamma_jl = sum_ik xi_i c_ijkl xi_k
+    const double c1111 = q[K_C1111 * np + p], c1112 = q[K_C1112 * np + p], c1212 = q[K_C1212 * np + p];
+    const double c2121 = q[K_C2121 * np + p], c2122 = q[K_C2122 * np + p], c2222 = q[K_C2222 * np + p];
+    const double c1121 = q[K_C1121 * np + p], c1122 = q[K_C1122 * np + p], c1221 = q[K_C1221 * np + p],
+                 c1222 = q[K_C1222 * np + p];
+    // c_1j2l = M_jl, c_2j1l = M_lj
+    const double G00 = cs * cs * c1111 + sn * sn * c2121 + 2 * cs * sn * c1121;
+    const double G11 = cs * cs * c1212 + sn * sn * c2222 + 2 * cs * sn * c1222;
+    const double G01 = cs * cs * c1112 + sn * sn * c2122 + cs * sn * (c1122 + c1221);
+    const double tr = G00 + G11, df = G00 - G11;
+    return 0.5 * (tr + std::sqrt(df * df + 4 * G01 * G01)) * q[K_IRHO * np + p];
+}
+
+static double block_vmax2(const HostBlock& B) {
+    const int nang = 180;
+    const long np = B.np();
+    struct Cand {
+        double val;
+        long p;
+        int k;
+    };
+    std::vector<Cand> top;
+    const size_t keep = 64;
+    for (long p = 0; p < np; ++p) {
+        double best = -1.0;
+        int bk = 0;
+        for (int k = 0; k < nang; ++k) {
+            const double v = christoffel_lmax(B, p, M_PI * k / nang);
+            if (v > best) {
+                best = v;
+                bk = k;
+            }
+        }
+        if (top.size() < keep) {
+            top.push_back({best, p, bk});
+            if (top.size() == keep)
+                std::make_heap(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.val > b.val; });
+        } else if (best > top.front().val) {
+            std::pop_heap(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.val > b.val; });
+            top.back() = {best, p, bk};
+            std::push_heap(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.val > b.val; });
+        }
+    }
+    double vmax = 0.0;
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (const auto& cnd : top) {
+        // golden-section search on [th - d, th + d] (lambda is smooth near its maximum)
+        const double d = M_PI / nang;
+        double a = M_PI * cnd.k / nang - d, b = M_PI * cnd.k / nang + d;
+        double x1 = b - gr * (b - a), x2 = a + gr * (b - a);
+        double f1 = christoffel_lmax(B, cnd.p, x1), f2 = christoffel_lmax(B, cnd.p, x2);
+        for (int it = 0; it < 60; ++it) {
+            if (f1 < f2) {
+                a = x1;
+                x1 = x2;
+                f1 = f2;
+                x2 = a + gr * (b - a);
+                f2 = christoffel_lmax(B, cnd.p, x2);
+            } else {
+                b = x2;
+                x2 = x1;
+                f2 = f1;
+                x1 = b - gr * (b - a);
+                f1 = christoffel_lmax(B, cnd.p, x1);
+            }
+        }
+        vmax = std::max(vmax, std::max(cnd.val, std::max(f1, f2)));
+    }
+    return vmax;
+}
+
+// moment-matching weights on the four nearest points (cubic Lagrange)
+static void weights_1d(double x0, int n, int& m0, double w[4]) {
+    const double h = 1.0 / (n - 1);
+    m0 = (int)std::floor(x0 / h) - 1;
+    m0 = std::min(std::max(m0, 0), n - 4);
+    for (int k = 0; k < 4; ++k) {
+        double v = 1.0;
+        for (int l = 0; l < 4; ++l)
+            if (l != k) v *= (x0 - (m0 + l) * h) / ((k - l) * h);
+        w[k] = v;
+    }
+}
+
+// frame index of point (i, j) of a block (inverse of the k_frame mapping)
+static long frame_index(const HostBlock& B, int R, int i, int j) {
+    const int n1 = B.n1, n2 = B.n2;
+    if (j < R) return (long)j * n1 + i;
+    if (j >= n2 - R) return (long)R * n1 + (long)(j - (n2 - R)) * n1 + i;
+    const int cc = i < R ? i : i - (n1 - 2 * R);
+    return 2L * R * n1 + (long)(j - R) * 2 * R + cc;
+}
+
+static sbpe_status build_plan(sbpe_ctx* c) {
+    const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
+    const int nb = (int)c->blocks.size();
+    c->desc.assign(nb, BlockDesc{});
+    int tiles = 0, fwg = 0;
+    for (int b = 0; b < nb; ++b) {
+        HostBlock& H = c->blocks[b];
+        BlockDesc& D = c->desc[b];
+        D.n1 = H.n1;
+        D.n2 = H.n2;
+        D.h1 = H.h1;
+        D.h2 = H.h2;
+        D.coef = H.d_coef;
+        D.force = H.d_force;
+        D.ftf = H.ftf;
+        D.a1 = H.d_a1;
+        D.a2 = H.d_a2;
+        D.u = H.u;
+        D.v = H.v;
+        const int ix = H.n1 - 2 * R, iy = H.n2 - 2 * R;
+        D.tiles_x = ix > 0 ? (ix + TILE_X - 1) / TILE_X : 0;
+        D.tiles_y = iy > 0 ? (iy + TILE_Y - 1) / TILE_Y : 0;
+        D.tile_beg = tiles;
+        tiles += D.tiles_x * D.tiles_y;
+        D.frame_n = 2 * R * H.n1 + 2 * R * std::max(0, H.n2 - 2 * R);
+        D.frame_wg = (D.frame_n + FRAME_WG - 1) / FRAME_WG;
+        D.frame_beg = fwg;
+        fwg += D.frame_wg;
+        for (int f = 0; f < 4; ++f) {
+            const HostFace& HF = H.face[f];
+            FaceDesc& F = D.face[f];
+            F.kind = HF.kind;
+            F.nf = H.nf(f);
+            const int a = f >> 1;
+            F.w = (a == 0 ? H.h1 : H.h2) * norm_weight(c->order, a == 0 ? H.n1 : H.n2, 0);
+            F.tf = HF.tf;
+            F.g = H.d_face[f][0];
+            F.U = H.d_face[f][1];
+            F.partner = HF.partner;
+            F.pface = HF.pface;
+            F.reversed = HF.reversed;
+            F.vsign = HF.side == 0 ? 1.0 : -1.0;
+            F.V = nullptr;
+            F.Th = nullptr;
+            F.vtf = TimeFn{TF_ZERO, 0, {0.0, 0.0}};
+            if (HF.kind == BC_INTERFACE) {
+                const HostBlock& P = c->blocks[HF.partner];
+                const int pa = HF.pface >> 1;
+                F.pw = (pa == 0 ? P.h1 : P.h2) * norm_weight(c->order, pa == 0 ? P.n1 : P.n2, 0);
+            }
+        }
+    }
+    c->total_tiles = tiles;
+    c->total_frame_wg = fwg;
+    // point entries (sources, receivers), bucketed by workgroup
+    struct E2 {
+        int frame;
+        int wg;
+        Entry e;
+    };
+    std::vector<E2> ents;
+    auto add_point = [&](int b, int i, int j, const Entry& e) {
+        const HostBlock& H = c->blocks[b];
+        const BlockDesc& D = c->desc[b];
+        E2 x;
+        x.e = e;
+        x.e.p = j * H.n1 + i;
+        if (i >= R && i <= H.n1 - 1 - R && j >= R && j <= H.n2 - 1 - R) {
+            x.frame = 0;
+            x.wg = D.tile_beg + ((j - R) / TILE_Y) * D.tiles_x + (i - R) / TILE_X;
+        } else {
+            x.frame = 1;
+            x.wg = D.frame_beg + (int)(frame_index(H, R, i, j) / FRAME_WG);
+        }
+        ents.push_back(x);
+    };
+    std::vector<TimeFn> stf;
+    for (size_t s = 0; s < c->sources.size(); ++s) {
+        const Source& S = c->sources[s];
+        const HostBlock& H = c->blocks[S.block];
+        int i0, j0;
+        double wi[4], wj[4];
+        weights_1d(S.x1, H.n1, i0, wi);
+        weights_1d(S.x2, H.n2, j0, wj);
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 4; ++d) {
+                const int i = i0 + d, j = j0 + a;
+                const double Hp = H.h1 * H.h2 * norm_weight(c->order, H.n1, i) * norm_weight(c->order, H.n2, j);
+                const double w = wi[d] * wj[a] / Hp;
+                Entry e{0, 0, (int)s, 0, S.amp * S.f1 * w, S.amp * S.f2 * w};
+                add_point(S.block, i, j, e);
+            }
+        stf.push_back(TimeFn{TF_RICKER, 0, {S.fp, S.t0}});
+    }
+    for (size_t r = 0; r < c->receivers.size(); ++r) {
+        const Receiver& Rv = c->receivers[r];
+        const HostBlock& H = c->blocks[Rv.block];
+        int i0, j0;
+        double wi[4], wj[4];
+        weights_1d(Rv.x1, H.n1, i0, wi);
+        weights_1d(Rv.x2, H.n2, j0, wj);
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 4; ++d) {
+                Entry e{0, 1, (int)(r * 16 + 4 * a + d), 0, wi[d] * wj[a], 0.0};
+                add_point(Rv.block, i0 + d, j0 + a, e);
+            }
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const E2& x, const E2& y) {
+        return x.frame != y.frame ? x.frame < y.frame : x.wg < y.wg;
+    });
+    std::vector<Entry> flat;
+    std::vector<Range> tr(std::max(tiles, 1), Range{0, 0}), fr(std::max(fwg, 1), Range{0, 0});
+    for (size_t k = 0; k < ents.size(); ++k) {
+        const int idx = (int)flat.size();
+        flat.push_back(ents[k].e);
+        Range& rg = ents[k].frame ? fr[ents[k].wg] : tr[ents[k].wg];
+        if (rg.end == rg.beg) rg.beg = idx;
+        rg.end = idx + 1;
+    }
+    if (c->host_only) return SBPE_OK;
+    if (flat.empty()) flat.push_back(Entry{-1, -1, 0, 0, 0.0, 0.0});
+    if (stf.empty()) stf.push_back(TimeFn{TF_ZERO, 0, {0.0, 0.0}});
+    HIPCHECK(c, hipMalloc(&c->d_entries, flat.size() * sizeof(Entry)));
+    HIPCHECK(c, hipMemcpy(c->d_entries, flat.data(), flat.size() * sizeof(Entry), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMalloc(&c->d_tile_ranges, tr.size() * sizeof(Range)));
+    HIPCHECK(c, hipMemcpy(c->d_tile_ranges, tr.data(), tr.size() * sizeof(Range), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMalloc(&c->d_frame_ranges, fr.size() * sizeof(Range)));
+    HIPCHECK(c, hipMemcpy(c->d_frame_ranges, fr.data(), fr.size() * sizeof(Range), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMalloc(&c->d_src_tf, stf.size() * sizeof(TimeFn)));
+    HIPCHECK(c, hipMemcpy(c->d_src_tf, stf.data(), stf.size() * sizeof(TimeFn), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMalloc(&c->d_desc, nb * sizeof(BlockDesc)));
+    HIPCHECK(c, hipMemcpy(c->d_desc, c->desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice));
+    c->npartial = 1024;
+    HIPCHECK(c, hipMalloc(&c->d_epart, c->npartial * sizeof(double)));
+    HIPCHECK(c, hipMalloc(&c->d_eout, sizeof(double)));
+    return SBPE_OK;
+}
+
+static sbpe_status sync_desc(sbpe_ctx* c) {
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        c->desc[b].u = c->blocks[b].u;
+        c->desc[b].v = c->blocks[b].v;
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->d_desc, c->desc.data(), c->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return SBPE_OK;
+}
+
+static PassArgs base_args(const sbpe_ctx* c) {
+    PassArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.blocks = c->d_desc;
+    a.nblocks = (int)c->blocks.size();
+    a.beta = c->beta;
+    a.entries = c->d_entries;
+    a.tile_ranges = c->d_tile_ranges;
+    a.frame_ranges = c->d_frame_ranges;
+    a.src_tf = c->d_src_tf;
+    return a;
+}
+
+static sbpe_status run_pass(sbpe_ctx* c, const PassArgs& a) {
+    const int e = launch_pass(c->dtype, c->order, a, c->total_tiles, c->total_frame_wg, c->stream);
+    if (e != 0) return fail(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+static bool check_ctx(sbpe_ctx* c) { return c != nullptr; }
+
+static sbpe_status need_gpu(sbpe_ctx* c) {
+    if (c->host_only) return fail(c, SBPE_ESTATE, "host-only context");
+    if (!c->finalized) return fail(c, SBPE_ESTATE, "context not finalized");
+    return SBPE_OK;
+}
+
+static void set_time_fn(int kind, const double* p, TimeFn& tf) {
+    tf.kind = kind;
+    tf.pad = 0;
+    tf.p[0] = p ? p[0] : 0.0;
+    tf.p[1] = p ? p[1] : 0.0;
+}
+
+// ================================================================ C ABI
+extern "C" {
+
+sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double beta, sbpe_ctx_t* out) {
+    if (!out) return fail(nullptr, SBPE_EINVAL, "out is NULL");
+    if (dtype != SBPE_F64 && dtype != SBPE_F32) return fail(nullptr, SBPE_EINVAL, "dtype must be SBPE_F64 or SBPE_F32");
+    if (order != 2 && order != 4) return fail(nullptr, SBPE_EINVAL, "order must be 2 or 4");
+    if (!(beta >= 1.0)) return fail(nullptr, SBPE_EINVAL, "beta must be >= 1 (Theorem 2)");
+    sbpe_ctx* c = new sbpe_ctx;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->dtype = dtype;
+    c->order = order;
+    c->beta = beta;
+    c->host_only = device < 0;
+    if (!c->host_only) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+            delete c;
+            return fail(nullptr, SBPE_EHIP, "no such HIP device");
+        }
+        if (hipSetDevice(device) != hipSuccess) {
+            delete c;
+            return fail(nullptr, SBPE_EHIP, "hipSetDevice failed");
+        }
+        std::vector<double> t4((size_t)O4_R0 * O4_W * O4_W), t2((size_t)O2_R0 * O2_W * O2_W);
+        derive_d2_closure(4, t4.data());
+        derive_d2_closure(2, t2.data());
+        const int e = upload_tables(t4.data(), t2.data());
+        if (e != 0) {
+            delete c;
+            return fail(nullptr, SBPE_EHIP, std::string("table upload: ") + hip_error_string(e));
+        }
+    }
+    *out = c;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_destroy(sbpe_ctx_t c) {
+    if (!c) return SBPE_OK;
+    if (!c->host_only) {
+        (void)hipStreamSynchronize(c->stream);
+        for (auto& B : c->blocks) {
+            (void)hipFree(B.d_coef);
+            (void)hipFree(B.d_force);
+            (void)hipFree(B.d_a1);
+            (void)hipFree(B.d_a2);
+            for (int f = 0; f < 4; ++f)
+                for (int k = 0; k < 2; ++k) (void)hipFree(B.d_face[f][k]);
+        }
+        (void)hipFree(c->d_desc);
+        (void)hipFree(c->d_entries);
+        (void)hipFree(c->d_tile_ranges);
+        (void)hipFree(c->d_frame_ranges);
+        (void)hipFree(c->d_src_tf);
+        (void)hipFree(c->d_rec);
+        (void)hipFree(c->d_epart);
+        (void)hipFree(c->d_eout);
+    }
+    delete c;
+    return SBPE_OK;
+}
+
+const char* sbpe_last_error(sbpe_ctx_t c) { return c ? c->err.c_str() : g_static_err.c_str(); }
+
+sbpe_status sbpe_voigt_to_c10(const double* V, size_t npts, double* C10) {
+    if (!V || !C10) return fail(nullptr, SBPE_EINVAL, "NULL array");
+    for (size_t p = 0; p < npts; ++p) {
+        const double c11 = V[p], c12 = V[npts + p], c16 = V[2 * npts + p], c22 = V[3 * npts + p],
+                     c26 = V[4 * npts + p], c66 = V[5 * npts + p];
+        // C1111, C1112, C1121, C1122, C1212, C1221, C1222, C2121, C2122, C2222
+        const double vals[10] = {c11, c16, c16, c12, c66, c66, c26, c66, c26, c22};
+        for (int m = 0; m < 10; ++m) C10[m * npts + p] = vals[m];
+    }
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_add_block(sbpe_ctx_t c, int n1, int n2, const double* X1, const double* X2, const double* rho,
+                           const double* C10, int* block_id) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
+    const int nmin = c->order == 4 ? 13 : 6;
+    if (n1 < nmin || n2 < nmin) return fail(c, SBPE_EINVAL, "block too small for the operator order");
+    if (!X1 || !X2 || !rho || !C10) return fail(c, SBPE_EINVAL, "NULL array");
+    const long np = (long)n1 * n2;
+    for (long p = 0; p < np; ++p)
+        if (!(rho[p] > 0.0)) return fail(c, SBPE_EINVAL, "density must be positive");
+    HostBlock B;
+    B.n1 = n1;
+    B.n2 = n2;
+    B.X1.assign(X1, X1 + np);
+    B.X2.assign(X2, X2 + np);
+    B.rho.assign(rho, rho + np);
+    B.C10.assign(C10, C10 + 10 * np);
+    c->blocks.push_back(std::move(B));
+    if (block_id) *block_id = (int)c->blocks.size() - 1;
+    return SBPE_OK;
+}
+
+static sbpe_status check_face(sbpe_ctx* c, int block, int face) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
+    if (block < 0 || block >= (int)c->blocks.size()) return fail(c, SBPE_EINVAL, "no such block");
+    if (face < 0 || face > 3) return fail(c, SBPE_EINVAL, "face must be 0..3");
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_set_bc(sbpe_ctx_t c, int block, int face, int bc, const double* U) {
+    sbpe_status s = check_face(c, block, face);
+    if (s) return s;
+    if (bc != SBPE_BC_TRACTION && bc != SBPE_BC_ROBIN && bc != SBPE_BC_DISPLACEMENT)
+        return fail(c, SBPE_EINVAL, "bc must be traction, Robin or displacement (use sbpe_connect for interfaces)");
+    HostFace& F = c->blocks[block].face[face];
+    if (F.kind == BC_INTERFACE) return fail(c, SBPE_ESTATE, "face is part of an interface");
+    const int nf = c->blocks[block].nf(face);
+    if (bc == SBPE_BC_ROBIN) {
+        if (!U) return fail(c, SBPE_EINVAL, "Robin condition needs U");
+        for (int t = 0; t < nf; ++t) {
+            const double a = U[t], b = U[nf + t], b2 = U[2 * nf + t], d = U[3 * nf + t];
+            if (std::fabs(b - b2) > 1e-12 * (std::fabs(a) + std::fabs(d) + 1e-300) || a < 0 || d < 0 ||
+                a * d - b * b < -1e-12 * (a * d + 1e-300))
+                return fail(c, SBPE_EINVAL, "U must be symmetric positive semidefinite");
+        }
+        F.U.assign(U, U + 4 * nf);
+    } else {
+        F.U.clear();
+    }
+    F.kind = bc;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_set_bc_data(sbpe_ctx_t c, int block, int face, const double* g, int time_fn, const double* tp) {
+    sbpe_status s = check_face(c, block, face);
+    if (s) return s;
+    if (time_fn < SBPE_TIME_ZERO || time_fn > SBPE_TIME_RICKER) return fail(c, SBPE_EINVAL, "bad time function");
+    HostFace& F = c->blocks[block].face[face];
+    const int nf = c->blocks[block].nf(face);
+    if (g) F.g.assign(g, g + 2 * nf);
+    else F.g.clear();
+    set_time_fn(time_fn, tp, F.tf);
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_connect(sbpe_ctx_t c, int bA, int fA, int bB, int fB, int reversed) {
+    sbpe_status s = check_face(c, bA, fA);
+    if (s) return s;
+    s = check_face(c, bB, fB);
+    if (s) return s;
+    if (bA == bB && fA == fB) return fail(c, SBPE_EINVAL, "a face cannot be connected to itself");
+    HostFace& A = c->blocks[bA].face[fA];
+    HostFace& B = c->blocks[bB].face[fB];
+    if (A.kind == BC_INTERFACE || B.kind == BC_INTERFACE) return fail(c, SBPE_ESTATE, "face already connected");
+    if (c->blocks[bA].nf(fA) != c->blocks[bB].nf(fB)) return fail(c, SBPE_EIFACE, "faces have different point counts");
+    A.kind = B.kind = BC_INTERFACE;
+    A.partner = bB;
+    A.pface = fB;
+    B.partner = bA;
+    B.pface = fA;
+    A.reversed = B.reversed = reversed ? 1 : 0;
+    A.side = 0;
+    B.side = 1;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_set_forcing(sbpe_ctx_t c, int block, const double* F, int time_fn, const double* tp) {
+    sbpe_status s = check_face(c, block, 0);
+    if (s) return s;
+    if (time_fn < SBPE_TIME_ZERO || time_fn > SBPE_TIME_RICKER) return fail(c, SBPE_EINVAL, "bad time function");
+    HostBlock& B = c->blocks[block];
+    if (F) B.F.assign(F, F + 2 * B.np());
+    else B.F.clear();
+    set_time_fn(time_fn, tp, B.ftf);
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_add_source(sbpe_ctx_t c, int block, double x1, double x2, double f1, double f2, double amp,
+                            double peak_hz, double t0) {
+    sbpe_status s = check_face(c, block, 0);
+    if (s) return s;
+    if (!(x1 >= 0 && x1 <= 1 && x2 >= 0 && x2 <= 1)) return fail(c, SBPE_EINVAL, "source outside [0,1]^2");
+    c->sources.push_back(Source{block, x1, x2, f1, f2, amp, peak_hz, t0});
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_add_receivers(sbpe_ctx_t c, int block, int n, const double* x1, const double* x2) {
+    sbpe_status s = check_face(c, block, 0);
+    if (s) return s;
+    if (n < 0 || (n > 0 && (!x1 || !x2))) return fail(c, SBPE_EINVAL, "bad receiver arrays");
+    for (int k = 0; k < n; ++k)
+        if (!(x1[k] >= 0 && x1[k] <= 1 && x2[k] >= 0 && x2[k] <= 1))
+            return fail(c, SBPE_EINVAL, "receiver outside [0,1]^2");
+    for (int k = 0; k < n; ++k) c->receivers.push_back(Receiver{block, x1[k], x2[k]});
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_finalize(sbpe_ctx_t c) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
+    if (c->blocks.empty()) return fail(c, SBPE_ESTATE, "no blocks");
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        sbpe_status s = setup_block(c, (int)b);
+        if (s) return s;
+    }
+    // interfaces: conforming faces must share Jhat (Sec. 6)
+    for (size_t b = 0; b < c->blocks.size(); ++b)
+        for (int f = 0; f < 4; ++f) {
+            const HostFace& F = c->blocks[b].face[f];
+            if (F.kind != BC_INTERFACE) continue;
+            const HostFace& P = c->blocks[F.partner].face[F.pface];
+            const int nf = (int)F.jhat.size();
+            for (int t = 0; t < nf; ++t) {
+                const double a = F.jhat[t], q = P.jhat[F.reversed ? nf - 1 - t : t];
+                if (std::fabs(a - q) > 1e-8 * std::max(a, q))
+                    return fail(c, SBPE_EIFACE, "interface faces do not coincide (Jhat differs)");
+            }
+        }
+    if (!c->host_only) {
+        if (hipSetDevice(c->device) != hipSuccess) return fail(c, SBPE_EHIP, "hipSetDevice failed");
+        for (auto& B : c->blocks) {
+            sbpe_status s = upload(c, B.coef, &B.d_coef);
+            if (s) return s;
+            const long np = B.np();
+            if (!B.F.empty()) {
+                std::vector<double> JF(2 * np);
+                for (long p = 0; p < np; ++p) {
+                    JF[p] = B.J[p] * B.F[p];
+                    JF[np + p] = B.J[p] * B.F[np + p];
+                }
+                s = upload(c, JF, &B.d_force);
+                if (s) return s;
+            }
+            if (hipMalloc(&B.d_a1, 2 * np * esize(c)) != hipSuccess ||
+                hipMalloc(&B.d_a2, 2 * np * esize(c)) != hipSuccess)
+                return fail(c, SBPE_ENOMEM, "device allocation failed");
+            for (int f = 0; f < 4; ++f) {
+                HostFace& F = B.face[f];
+                const int nf = B.nf(f);
+                const int a = f >> 1;
+                const double w = (a == 0 ? B.h1 : B.h2) * norm_weight(c->order, a == 0 ? B.n1 : B.n2, 0);
+                if (!F.g.empty() && (F.kind == BC_TRACTION || F.kind == BC_ROBIN || F.kind == BC_DISPLACEMENT)) {
+                    std::vector<double> g(F.g);
+                    if (F.kind != BC_DISPLACEMENT)
+                        for (int t = 0; t < nf; ++t) {
+                            g[t] *= F.jhat[t] / w;
+                            g[nf + t] *= F.jhat[t] / w;
+                        }
+                    s = upload(c, g, &B.d_face[f][0]);
+                    if (s) return s;
+                }
+                if (F.kind == BC_ROBIN) {
+                    std::vector<double> U(F.U);
+                    for (int k = 0; k < 4; ++k)
+                        for (int t = 0; t < nf; ++t) U[k * nf + t] *= F.jhat[t] / w;
+                    s = upload(c, U, &B.d_face[f][1]);
+                    if (s) return s;
+                }
+            }
+        }
+    }
+    sbpe_status s = build_plan(c);
+    if (s) return s;
+    c->finalized = true;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_dt_cfl(sbpe_ctx_t c, double cfl, double* dt) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->finalized) return fail(c, SBPE_ESTATE, "context not finalized");
+    if (!dt || !(cfl > 0)) return fail(c, SBPE_EINVAL, "bad arguments");
+    double best = INFINITY;
+    for (const auto& B : c->blocks) {
+        const double v2 = block_vmax2(B);
+        best = std::min(best, std::min(B.h1, B.h2) / std::sqrt(v2));
+    }
+    *dt = cfl * best;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_block_size(sbpe_ctx_t c, int block, int* n1, int* n2) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (block < 0 || block >= (int)c->blocks.size()) return fail(c, SBPE_EINVAL, "no such block");
+    if (n1) *n1 = c->blocks[block].n1;
+    if (n2) *n2 = c->blocks[block].n2;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_apply(sbpe_ctx_t c, const void* const* u, void* const* a, double t, int homogeneous) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    const int nb = (int)c->blocks.size();
+    if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "sbpe_apply supports at most 16 blocks");
+    if (!u || !a) return fail(c, SBPE_EINVAL, "NULL pointer array");
+    for (int b = 0; b < nb; ++b) {
+        if (!u[b] || !a[b]) return fail(c, SBPE_EINVAL, "NULL block pointer");
+        for (int q = 0; q < nb; ++q)
+            if (a[b] == u[q]) return fail(c, SBPE_EINVAL, "output aliases an input");
+    }
+    PassArgs pa = base_args(c);
+    pa.pass = PASS_APPLY;
+    pa.homogeneous = homogeneous ? 1 : 0;
+    pa.t = t;
+    for (int b = 0; b < nb; ++b) {
+        pa.in[b] = u[b];
+        pa.out[b] = a[b];
+    }
+    return run_pass(c, pa);
+}
+
+sbpe_status sbpe_bind_state(sbpe_ctx_t c, void* const* u, void* const* v, double t) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (!u || !v) return fail(c, SBPE_EINVAL, "NULL pointer array");
+    for (size_t b = 0; b < c->blocks.size(); ++b)
+        if (!u[b] || !v[b] || u[b] == v[b]) return fail(c, SBPE_EINVAL, "bad state pointers");
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        c->blocks[b].u = u[b];
+        c->blocks[b].v = v[b];
+    }
+    s = sync_desc(c);
+    if (s) return s;
+    c->bound = true;
+    c->t = t;
+    c->rec_steps = 0;
+    return SBPE_OK;
+}
+
+static sbpe_status energy_now(sbpe_ctx* c, double* eps) {
+    PassArgs pa = base_args(c);
+    pa.pass = PASS_APPLY;
+    pa.homogeneous = 1;
+    for (size_t b = 0; b < c->blocks.size(); ++b) {
+        pa.in[b] = c->blocks[b].u;
+        pa.out[b] = c->blocks[b].d_a1;
+    }
+    sbpe_status s = run_pass(c, pa);
+    if (s) return s;
+    const int e = launch_energy(c->dtype, c->order, c->d_desc, (int)c->blocks.size(), c->d_epart, c->npartial,
+                                c->d_eout, c->stream);
+    if (e != 0) return fail(c, SBPE_EHIP, std::string("energy launch: ") + hip_error_string(e));
+    HIPCHECK(c, hipMemcpyAsync(eps, c->d_eout, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_energy(sbpe_ctx_t c, double* eps) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (!c->bound) return fail(c, SBPE_ESTATE, "no state bound");
+    if (!eps) return fail(c, SBPE_EINVAL, "NULL eps");
+    return energy_now(c, eps);
+}
+
+sbpe_status sbpe_set_energy_guard(sbpe_ctx_t c, int every, double rel_growth) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (every < 0 || !(rel_growth >= 0)) return fail(c, SBPE_EINVAL, "bad guard parameters");
+    c->guard_every = every;
+    c->guard_growth = rel_growth;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (!c->bound) return fail(c, SBPE_ESTATE, "no state bound");
+    if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(c, SBPE_EINVAL, "bad nsteps or dt");
+    const long nrec = (long)c->receivers.size();
+    const long slots = nrec * 16 * 2;
+    if (nrec > 0 && c->rec_steps + nsteps > c->rec_cap) {
+        long cap = std::max<long>(c->rec_steps + nsteps, 2 * c->rec_cap);
+        double* nd = nullptr;
+        if (hipMalloc(&nd, cap * slots * sizeof(double)) != hipSuccess) return fail(c, SBPE_ENOMEM, "receiver buffer");
+        if (c->d_rec && c->rec_steps > 0)
+            HIPCHECK(c, hipMemcpyAsync(nd, c->d_rec, c->rec_steps * slots * sizeof(double), hipMemcpyDeviceToDevice,
+                                       c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        (void)hipFree(c->d_rec);
+        c->d_rec = nd;
+        c->rec_cap = cap;
+    }
+    double e0 = 0.0;
+    if (c->guard_every > 0) {
+        s = energy_now(c, &e0);
+        if (s) return s;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        PassArgs p1 = base_args(c);
+        p1.pass = PASS_RK1;
+        p1.t = c->t;
+        p1.dt = dt;
+        s = run_pass(c, p1);
+        if (s) return s;
+        PassArgs p2 = p1;
+        p2.pass = PASS_RK2;
+        p2.rec_out = nrec > 0 ? c->d_rec + (c->rec_steps + k) * slots : nullptr;
+        s = run_pass(c, p2);
+        if (s) return s;
+        c->t += dt;
+        if (c->guard_every > 0 && (k + 1) % c->guard_every == 0) {
+            double e = 0.0;
+            s = energy_now(c, &e);
+            if (s) return s;
+            if (!std::isfinite(e) || e > (1.0 + c->guard_growth) * e0) {
+                c->rec_steps += k + 1;
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "energy guard: energy %.6e after step %d exceeds %.6e", e, k + 1,
+                              (1.0 + c->guard_growth) * e0);
+                return fail(c, SBPE_EUNSTABLE, buf);
+            }
+        }
+    }
+    c->rec_steps += nsteps;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_get_time(sbpe_ctx_t c, double* t) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (!t) return fail(c, SBPE_EINVAL, "NULL t");
+    *t = c->t;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_read_receivers(sbpe_ctx_t c, double* out, int max_steps, int* nsteps_out) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    const long nrec = (long)c->receivers.size();
+    const long n = std::min<long>(c->rec_steps, std::max(max_steps, 0));
+    if (nsteps_out) *nsteps_out = (int)n;
+    if (nrec == 0 || n == 0) return SBPE_OK;
+    if (!out) return fail(c, SBPE_EINVAL, "NULL out");
+    std::vector<double> raw(n * nrec * 32);
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(raw.data(), c->d_rec, raw.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (long st = 0; st < n; ++st)
+        for (long r = 0; r < nrec; ++r)
+            for (int cmp = 0; cmp < 2; ++cmp) {
+                double acc = 0.0;
+                for (int sl = 0; sl < 16; ++sl) acc += raw[((st * nrec + r) * 16 + sl) * 2 + cmp];
+                out[(st * nrec + r) * 2 + cmp] = acc;
+            }
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_synchronize(sbpe_ctx_t c) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->host_only) return SBPE_OK;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_host_d1_line(int order, int n, const double* u, double* out) {
+    if ((order != 2 && order != 4) || n < (order == 4 ? 13 : 6) || !u || !out)
+        return fail(nullptr, SBPE_EINVAL, "bad arguments");
+    d1_apply(order, n, 1.0 / (n - 1), u, 1, out, 1);
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_host_d2fc_line(int order, int n, const double* b, const double* u, double* out) {
+    if ((order != 2 && order != 4) || n < (order == 4 ? 13 : 6) || !b || !u || !out)
+        return fail(nullptr, SBPE_EINVAL, "bad arguments");
+    const int R0 = order == 4 ? O4_R0 : O2_R0, W = order == 4 ? O4_W : O2_W;
+    std::vector<double> T((size_t)R0 * W * W);
+    derive_d2_closure(order, T.data());
+    const double ih2 = double(n - 1) * double(n - 1);
+    for (int r = 0; r < n; ++r) {
+        double acc = 0.0;
+        if (r >= R0 && r <= n - 1 - R0) {
+            if (order == 4) {
+                const double* B = b + r;
+                const double* U = u + r;
+                const double km2 = B[-1] / 6 - 0.125 * (B[-2] + B[0]);
+                const double km1 = (B[-2] + B[1]) / 6 + 0.5 * (B[-1] + B[0]);
+                const double kp1 = (B[-1] + B[2]) / 6 + 0.5 * (B[0] + B[1]);
+                const double kp2 = B[1] / 6 - 0.125 * (B[0] + B[2]);
+                acc = km2 * (U[-2] - U[0]) + km1 * (U[-1] - U[0]) + kp1 * (U[1] - U[0]) + kp2 * (U[2] - U[0]);
+            } else {
+                acc = 0.5 * (b[r - 1] + b[r]) * (u[r - 1] - u[r]) + 0.5 * (b[r] + b[r + 1]) * (u[r + 1] - u[r]);
+            }
+        } else {
+            const bool lo = r < R0;
+            const int rr = lo ? r : n - 1 - r;
+            for (int m = 0; m < W; ++m)
+                for (int s = 0; s < W; ++s) {
+                    const double tv = T[((size_t)rr * W + m) * W + s];
+                    if (tv != 0.0) acc += tv * b[lo ? s : n - 1 - s] * (u[lo ? m : n - 1 - m] - u[r]);
+                }
+        }
+        out[r] = acc * ih2;
+    }
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_get_block_fields(sbpe_ctx_t c, int block, double* c10, double* J, double* jhat) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->finalized) return fail(c, SBPE_ESTATE, "context not finalized");
+    if (block < 0 || block >= (int)c->blocks.size()) return fail(c, SBPE_EINVAL, "no such block");
+    const HostBlock& B = c->blocks[block];
+    if (c10) std::copy(B.c10t.begin(), B.c10t.end(), c10);
+    if (J) std::copy(B.J.begin(), B.J.end(), J);
+    if (jhat) {
+        const int m = std::max(B.n1, B.n2);
+        for (int f = 0; f < 4; ++f) std::copy(B.face[f].jhat.begin(), B.face[f].jhat.end(), jhat + (size_t)f * m);
+    }
+    return SBPE_OK;
+}
+
+}  // extern "C"

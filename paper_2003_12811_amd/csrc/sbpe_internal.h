@@ -1,0 +1,124 @@
+// Device-side descriptors shared by the host setup (sbpe_host.cpp) and the
+// kernels (sbpe_kernels.hip).  Plain structs of pointers and sizes; every
+// pointer is device memory owned by the context (coefficients, workspace) or
+// by the caller (bound state, sbpe_apply operands).
+#pragma once
+#include <cstdint>
+
+namespace sbpe {
+
+enum { BC_TRACTION = 0, BC_ROBIN = 1, BC_DISPLACEMENT = 2, BC_INTERFACE = 3 };
+enum { TF_ZERO = 0, TF_ONE = 1, TF_COS = 2, TF_RICKER = 3 };
+// kernel passes
+//   APPLY: out = rho~^-1 (L in + data(t))
+//   RK1  : a1 = rho~^-1 (L u + data(t)),  a2 = rho~^-1 (L u + dt/2 L v + data(t + dt/2))
+//   RK2  : with A1 = a1, A2 = a2 (stages 1, 2 of classical RK4 on (u, u_t)),
+//          A3 = A2 + dt^2/4 rho~^-1 L A1,
+//          A4 = 2 A2 - A1 + dt^2/2 rho~^-1 (L A2 + 2/dt^2 (data(t) - 2 data(t + dt/2) + data(t + dt))),
+//          u += dt v + dt^2/6 (A1 + A2 + A3),  v += dt/6 (A1 + 2 A2 + 2 A3 + A4)
+// L is linear and data(t) is affine in the time functions, so these are the
+// four stages of classical RK4 regrouped into two sweeps over the grid.
+enum { PASS_APPLY = 0, PASS_RK1 = 1, PASS_RK2 = 2 };
+// which bound field a device routine reads
+enum { FLD_U = 0, FLD_V = 1, FLD_A1 = 2, FLD_A2 = 3, FLD_IN = 4 };
+
+// coefficient field order in the per-block coefficient array [NCOEF][n2][n1]
+enum {
+    K_C1111 = 0, K_C1112 = 1, K_C1212 = 2,   // x1 narrow second derivative
+    K_C2121 = 3, K_C2122 = 4, K_C2222 = 5,   // x2 narrow second derivative
+    K_C1121 = 6, K_C1122 = 7, K_C1221 = 8, K_C1222 = 9,  // mixed terms
+    K_IRHO = 10,                              // 1 / (J rho)
+    NCOEF = 11
+};
+
+struct TimeFn {
+    int kind;
+    int pad;
+    double p[2];
+};
+
+struct FaceDesc {
+    int kind;          // BC_*
+    int partner;       // interface: index of the partner block in the descriptor table
+    int pface;         // interface: partner face
+    int reversed;      // interface: faces run in opposite directions
+    int nf;            // number of face points
+    int pad;
+    double w;          // first norm weight of the face-normal direction, h_a * H^_0
+    double pw;         // interface: the partner's first norm weight
+    double vsign;      // interface: +1 on the side that owns the jump data order, -1 on the other
+    TimeFn tf;         // time function of g
+    const void* g;     // [2][nf]: traction/Robin: Jhat g / w; displacement: g; or null
+    const void* U;     // [4][nf]: Robin Jhat U_JL / w (row-major JL), or null
+    TimeFn vtf;        // time function of the interface jump data
+    const void* V;     // [2][nf] displacement jump in this face's order (interface), or null
+    const void* Th;    // [2][nf] Jhat Theta / (2 w) in this face's order (interface), or null
+};
+
+struct BlockDesc {
+    int n1, n2;
+    double h1, h2;
+    const void* coef;   // [NCOEF][n2][n1]
+    const void* force;  // [2][n2][n1] J f space part, or null
+    TimeFn ftf;
+    void* u;            // bound displacement [2][n2][n1]
+    void* v;            // bound velocity
+    void* a1;           // RK workspace
+    void* a2;
+    FaceDesc face[4];
+    int tiles_x, tiles_y, tile_beg;     // interior launch geometry
+    int frame_n, frame_wg, frame_beg;   // frame launch geometry (points, workgroups, first workgroup)
+};
+
+// point entries: sources add to the right-hand side, receivers record u
+struct Entry {
+    int p;        // flat grid index in its block
+    int kind;     // 0 source, 1 receiver
+    int id;       // source: index of its time function; receiver: rec * 16 + slot
+    int pad;
+    double c0, c1;  // source: amp dir_J w / H (J f contribution); receiver: weight, unused
+};
+
+struct Range {
+    int beg, end;
+};
+
+struct TimeComb {   // tau_eff = sum_k w[k] tau(t[k])
+    int n;
+    int pad;
+    double t[3];
+    double w[3];
+};
+
+constexpr int MAX_APPLY_BLOCKS = 16;
+
+struct PassArgs {
+    const BlockDesc* blocks;
+    int nblocks;
+    int pass;
+    int homogeneous;
+    int pad;
+    double t, dt, beta;
+    const void* in[MAX_APPLY_BLOCKS];   // sbpe_apply operands per block
+    void* out[MAX_APPLY_BLOCKS];
+    const Entry* entries;
+    const Range* tile_ranges;    // per interior workgroup
+    const Range* frame_ranges;   // per frame workgroup
+    const TimeFn* src_tf;        // per source
+    double* rec_out;             // receiver slots of the current step [nrec*16][2], or null
+};
+
+// interior tile shape of the simple kernel
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 4;
+constexpr int FRAME_WG = 256;
+
+// host-side launchers (sbpe_kernels.hip)
+int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg,
+                void* stream);
+int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
+                  int npartial, double* result_dev, void* stream);
+int upload_tables(const double* t4, const double* t2);
+const char* hip_error_string(int code);
+
+}  // namespace sbpe

@@ -1,0 +1,62 @@
+// Coefficients of the one-dimensional diagonal-norm SBP operators used by the
+// library (Sec. 4 of Almquist & Dunham, arXiv 2003.12811), and the derivation
+// of the boundary-closure table of the adapted fully compatible narrow second
+// derivative D2^FC(b) (Sec. 4.1) from its SBP form
+//
+//   H D2^FC(b) = -D1^T H b D1 - R(b) - e0 b0 e0^T D1 + eN bN eN^T D1,
+//   R(b)       = (1/h) sum_windows gamma_w B_w(b) d_w d_w^T      (eq. B_structure_1d).
+//
+// All coefficients are dimensionless (h = 1); kernels scale by 1/h or 1/h^2.
+//
+// Order 4: the classical diagonal norm 17/48, 59/48, 43/48, 49/48 and its
+// first-derivative boundary rows; remainder windows d3 = (-1,3,-3,1) with
+// weight 1/18 (B = mean of the two middle b values) and d4 = (1,-4,6,-4,1)
+// with weight 1/144 (B = centre b).  The three d3 windows touching each end
+// carry the weights 181507/1719312, 293/4214, 185/3528, which make rows 1..5
+// of D2^FC second-order accurate for variable b (row 0 keeps the end-point
+// order of the adapted operators).  Order 2: norm 1/2 at the ends,
+// D1 boundary rows (-1, 1), windows d2 = (1,-2,1) with weight 1/4 and B = centre b.
+#pragma once
+
+namespace sbpe {
+
+// ---- order 4 ---------------------------------------------------------------
+constexpr int O4_NB = 4;                 // number of D1 / H boundary rows
+constexpr int O4_R0 = 6;                 // number of D2^FC closure rows
+constexpr int O4_W = 8;                  // closure row width (u and b indices 0..7)
+constexpr double O4_H[O4_NB] = {17.0 / 48.0, 59.0 / 48.0, 43.0 / 48.0, 49.0 / 48.0};
+constexpr double O4_D1B[O4_NB][6] = {
+    {-24.0 / 17.0, 59.0 / 34.0, -4.0 / 17.0, -3.0 / 34.0, 0.0, 0.0},
+    {-0.5, 0.0, 0.5, 0.0, 0.0, 0.0},
+    {4.0 / 43.0, -59.0 / 86.0, 0.0, 59.0 / 86.0, -4.0 / 43.0, 0.0},
+    {3.0 / 98.0, 0.0, -59.0 / 98.0, 0.0, 32.0 / 49.0, -4.0 / 49.0}};
+constexpr double O4_D1I[5] = {1.0 / 12.0, -2.0 / 3.0, 0.0, 2.0 / 3.0, -1.0 / 12.0};
+constexpr double O4_G3_BND[3] = {181507.0 / 1719312.0, 293.0 / 4214.0, 185.0 / 3528.0};
+constexpr double O4_G3 = 1.0 / 18.0;
+constexpr double O4_G4 = 1.0 / 144.0;
+
+// ---- order 2 ---------------------------------------------------------------
+constexpr int O2_NB = 1;
+constexpr int O2_R0 = 1;
+constexpr int O2_W = 2;
+constexpr double O2_H[O2_NB] = {0.5};
+constexpr double O2_D1B[O2_NB][6] = {{-1.0, 1.0, 0.0, 0.0, 0.0, 0.0}};
+constexpr double O2_D1I[3] = {-0.5, 0.0, 0.5};
+constexpr double O2_G2 = 0.25;
+
+// Number of points adjacent to each face that need boundary-aware treatment
+// (closure rows or displacement/interface SAT reach); the rest is interior.
+template <int ORD> struct Frame;
+template <> struct Frame<4> { static constexpr int R = 6; };
+template <> struct Frame<2> { static constexpr int R = 2; };
+
+// Derive the closure table T[r][m][s] (r < R0, m, s < W) such that
+// h^2 (D2^FC(b) u)_r = sum_{m,s} T[r][m][s] b_s u_m on the lower end of a line.
+// The upper end follows by reflection: (D2 u)_{N-r} uses b_{N-s}, u_{N-m}.
+void derive_d2_closure(int order, double* T);
+// Dimensionless norm weight of point k on a line of n points.
+double norm_weight(int order, int n, int k);
+// Dense dimensionless D1 of n points (row-major n*n), for host-side setup.
+void dense_d1(int order, int n, double* D);
+
+}  // namespace sbpe

@@ -1,0 +1,250 @@
+"""ctypes binding of libsbpe.so with the names of include/sbpe.h.
+
+Argument marshalling only: every computation runs in the HIP library.  Host
+arrays are NumPy float64 arrays; device operands are integer device pointers
+(``torch.Tensor.data_ptr()``).  A failed call raises ``SbpeError`` carrying the
+status code and the library's message.  The library must have been built
+(``python -m paper_2003_12811_amd.build``); importing this module never falls
+back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'lib', 'libsbpe.so')
+
+OK, EINVAL, ENONPOS_J, ENOT_PSD, EIFACE, ENOMEM, EHIP, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+F64, F32 = 0, 1
+FACE_X1LO, FACE_X1HI, FACE_X2LO, FACE_X2HI = 0, 1, 2, 3
+BC_TRACTION, BC_ROBIN, BC_DISPLACEMENT, BC_INTERFACE = 0, 1, 2, 3
+TIME_ZERO, TIME_ONE, TIME_COS, TIME_RICKER = 0, 1, 2, 3
+
+
+class SbpeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__('sbpe error %d: %s' % (code, msg))
+        self.code = code
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+_PROTOS = {
+    'sbpe_create': [_I, _P, _I, _I, _D, ctypes.POINTER(_P)],
+    'sbpe_destroy': [_P],
+    'sbpe_add_block': [_P, _I, _I, _DP, _DP, _DP, _DP, _IP],
+    'sbpe_voigt_to_c10': [_DP, ctypes.c_size_t, _DP],
+    'sbpe_set_bc': [_P, _I, _I, _I, _DP],
+    'sbpe_set_bc_data': [_P, _I, _I, _DP, _I, _DP],
+    'sbpe_connect': [_P, _I, _I, _I, _I, _I],
+    'sbpe_set_forcing': [_P, _I, _DP, _I, _DP],
+    'sbpe_add_source': [_P, _I, _D, _D, _D, _D, _D, _D, _D],
+    'sbpe_add_receivers': [_P, _I, _I, _DP, _DP],
+    'sbpe_finalize': [_P],
+    'sbpe_dt_cfl': [_P, _D, _DP],
+    'sbpe_block_size': [_P, _I, _IP, _IP],
+    'sbpe_apply': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _I],
+    'sbpe_bind_state': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D],
+    'sbpe_advance': [_P, _I, _D],
+    'sbpe_get_time': [_P, _DP],
+    'sbpe_read_receivers': [_P, _DP, _I, _IP],
+    'sbpe_energy': [_P, _DP],
+    'sbpe_set_energy_guard': [_P, _I, _D],
+    'sbpe_synchronize': [_P],
+    'sbpe_host_d2fc_line': [_I, _I, _DP, _DP, _DP],
+    'sbpe_host_d1_line': [_I, _I, _DP, _DP],
+    'sbpe_get_block_fields': [_P, _I, _DP, _DP, _DP],
+}
+
+
+def lib():
+    """Load libsbpe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError('libsbpe.so not found at %s; build it with '
+                               '`python -m paper_2003_12811_amd.build`' % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _PROTOS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.sbpe_last_error.argtypes = [_P]
+        L.sbpe_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(ctx, code):
+    if code != OK:
+        msg = lib().sbpe_last_error(ctx)
+        raise SbpeError(code, msg.decode() if msg else '')
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptrs(ptrs):
+    arr = (_P * len(ptrs))(*[int(p) for p in ptrs])
+    return arr
+
+
+def _tparams(p):
+    p = np.zeros(2) if p is None else np.ascontiguousarray(np.resize(np.asarray(p, dtype=np.float64), 2))
+    return p
+
+
+# ----------------------------------------------------------- C-named calls
+def sbpe_create(device, stream, dtype, order, beta=1.0):
+    h = _P()
+    _check(None, lib().sbpe_create(device, _P(stream or 0), dtype, order, beta, ctypes.byref(h)))
+    return h
+
+
+def sbpe_destroy(ctx):
+    _check(None, lib().sbpe_destroy(ctx))
+
+
+def sbpe_last_error(ctx):
+    m = lib().sbpe_last_error(ctx)
+    return m.decode() if m else ''
+
+
+def sbpe_add_block(ctx, X1, X2, rho, C10):
+    X1, X2, rho, C10 = _f64(X1), _f64(X2), _f64(rho), _f64(C10)
+    n2, n1 = X1.shape
+    if X2.shape != X1.shape or rho.shape != X1.shape or C10.shape != (10, n2, n1):
+        raise ValueError('shape mismatch')
+    bid = _I()
+    _check(ctx, lib().sbpe_add_block(ctx, n1, n2, _dp(X1), _dp(X2), _dp(rho), _dp(C10), ctypes.byref(bid)))
+    return bid.value
+
+
+def sbpe_voigt_to_c10(voigt):
+    V = _f64(voigt)
+    shp = V.shape[1:]
+    out = np.empty((10,) + shp)
+    _check(None, lib().sbpe_voigt_to_c10(_dp(V), int(np.prod(shp)), _dp(out)))
+    return out
+
+
+def sbpe_set_bc(ctx, block, face, bc, U=None):
+    U = _f64(U)
+    _check(ctx, lib().sbpe_set_bc(ctx, block, face, bc, _dp(U)))
+
+
+def sbpe_set_bc_data(ctx, block, face, g, time_fn, time_params=None):
+    g = _f64(g)
+    tp = _tparams(time_params)
+    _check(ctx, lib().sbpe_set_bc_data(ctx, block, face, _dp(g), time_fn, _dp(tp)))
+
+
+def sbpe_connect(ctx, blkA, faceA, blkB, faceB, reversed=False):
+    _check(ctx, lib().sbpe_connect(ctx, blkA, faceA, blkB, faceB, 1 if reversed else 0))
+
+
+def sbpe_set_forcing(ctx, block, F, time_fn, time_params=None):
+    F = _f64(F)
+    tp = _tparams(time_params)
+    _check(ctx, lib().sbpe_set_forcing(ctx, block, _dp(F), time_fn, _dp(tp)))
+
+
+def sbpe_add_source(ctx, block, x1, x2, f1, f2, amp, peak_hz, t0):
+    _check(ctx, lib().sbpe_add_source(ctx, block, x1, x2, f1, f2, amp, peak_hz, t0))
+
+
+def sbpe_add_receivers(ctx, block, x1, x2):
+    x1, x2 = _f64(np.atleast_1d(x1)), _f64(np.atleast_1d(x2))
+    _check(ctx, lib().sbpe_add_receivers(ctx, block, len(x1), _dp(x1), _dp(x2)))
+
+
+def sbpe_finalize(ctx):
+    _check(ctx, lib().sbpe_finalize(ctx))
+
+
+def sbpe_dt_cfl(ctx, cfl):
+    dt = _D()
+    _check(ctx, lib().sbpe_dt_cfl(ctx, cfl, ctypes.byref(dt)))
+    return dt.value
+
+
+def sbpe_block_size(ctx, block):
+    a, b = _I(), _I()
+    _check(ctx, lib().sbpe_block_size(ctx, block, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def sbpe_apply(ctx, u_ptrs, a_ptrs, t=0.0, homogeneous=False):
+    _check(ctx, lib().sbpe_apply(ctx, _ptrs(u_ptrs), _ptrs(a_ptrs), t, 1 if homogeneous else 0))
+
+
+def sbpe_bind_state(ctx, u_ptrs, v_ptrs, t=0.0):
+    _check(ctx, lib().sbpe_bind_state(ctx, _ptrs(u_ptrs), _ptrs(v_ptrs), t))
+
+
+def sbpe_advance(ctx, nsteps, dt):
+    _check(ctx, lib().sbpe_advance(ctx, nsteps, dt))
+
+
+def sbpe_get_time(ctx):
+    t = _D()
+    _check(ctx, lib().sbpe_get_time(ctx, ctypes.byref(t)))
+    return t.value
+
+
+def sbpe_read_receivers(ctx, nrec, max_steps):
+    out = np.zeros((max(max_steps, 0), nrec, 2))
+    n = _I()
+    _check(ctx, lib().sbpe_read_receivers(ctx, _dp(out), max_steps, ctypes.byref(n)))
+    return out[:n.value]
+
+
+def sbpe_energy(ctx):
+    e = _D()
+    _check(ctx, lib().sbpe_energy(ctx, ctypes.byref(e)))
+    return e.value
+
+
+def sbpe_set_energy_guard(ctx, every, rel_growth):
+    _check(ctx, lib().sbpe_set_energy_guard(ctx, every, rel_growth))
+
+
+def sbpe_synchronize(ctx):
+    _check(ctx, lib().sbpe_synchronize(ctx))
+
+
+def sbpe_host_d2fc_line(order, b, u):
+    b, u = _f64(b), _f64(u)
+    out = np.empty_like(u)
+    _check(None, lib().sbpe_host_d2fc_line(order, len(u), _dp(b), _dp(u), _dp(out)))
+    return out
+
+
+def sbpe_host_d1_line(order, u):
+    u = _f64(u)
+    out = np.empty_like(u)
+    _check(None, lib().sbpe_host_d1_line(order, len(u), _dp(u), _dp(out)))
+    return out
+
+
+def sbpe_get_block_fields(ctx, block):
+    n1, n2 = sbpe_block_size(ctx, block)
+    c10 = np.empty((10, n2, n1))
+    J = np.empty((n2, n1))
+    m = max(n1, n2)
+    jh = np.empty((4, m))
+    _check(ctx, lib().sbpe_get_block_fields(ctx, block, _dp(c10), _dp(J), _dp(jh)))
+    jhat = [jh[f, :(n2 if f < 2 else n1)].copy() for f in range(4)]
+    return c10, J, jhat

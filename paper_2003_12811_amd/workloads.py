@@ -200,3 +200,100 @@ def traction_data(mms, face_idx, normal):
     """n_I C_IJKL d_K u_L at the face points (flat indices), shape (2, nf)."""
     g = mms['grad'].reshape(2, 2, -1)[..., face_idx]
     return np.einsum('If,IJKL,LKf->Jf', normal, mms['C'], g)
+
+
+# ------------------------------------------------------------ problem specs
+# A spec is a plain dict consumed by both the library front end
+# (paper_2003_12811_amd.solver) and the tests' oracle builder:
+#   order, blocks: [dict(X1, X2, rho, C10, bc=[(kind, g, time_fn, time_params, U)] * 4,
+#                        forcing=None | (F, time_fn, time_params))],
+#   interfaces: [(block_a, face_a, block_b, face_b, reversed)],
+#   sources: [(block, x1, x2, f1, f2, amp, peak_hz, t0)], receivers: [(block, x1[], x2[])]
+# Boundary kinds / time functions use the numbering of include/sbpe.h.
+TRACTION, ROBIN, DISPLACEMENT = 0, 1, 2
+T_ZERO, T_ONE, T_COS, T_RICKER = 0, 1, 2, 3
+
+
+def _free_faces():
+    return [(TRACTION, None, T_ZERO, None, None) for _ in range(4)]
+
+
+def face_flat_index(face, n1, n2):
+    if face < 2:
+        return np.arange(n2) * n1 + (0 if face == 0 else n1 - 1)
+    return (0 if face == 2 else n2 - 1) * n1 + np.arange(n1)
+
+
+def spec_c1(n=65, order=4):
+    """Plain method: 65^2 Cartesian block, constant anisotropic C, MMS, traction SATs."""
+    X1, X2 = grid(Identity(), n, n)
+    C10c = voigt_to_c10(np.array(VOIGT_C1))
+    mm = mms_c1(X1, X2, C10c)
+    C10 = C10c[:, None, None] * np.ones((1, n, n))
+    bc = []
+    for f in range(4):
+        g = traction_data(mm, face_flat_index(f, n, n), outward_normal(Identity(), f, n, n))
+        bc.append((TRACTION, g, T_COS, (mm['omega'], 0.0), None))
+    blk = dict(X1=X1, X2=X2, rho=np.ones((n, n)), C10=C10, bc=bc,
+               forcing=(mm['f'], T_COS, (mm['omega'], 0.0)))
+    return dict(order=order, blocks=[blk], interfaces=[], sources=[], receivers=[],
+                mms=mm, T=0.5, cfl=0.5)
+
+
+def spec_c2(n=1025, seed=0, order=4, nrec=16):
+    """Curvilinear block with Gaussian topography, random smooth SPD material,
+    displacement on the bumped face x2 = 0, traction elsewhere, Ricker point force."""
+    X1, X2 = grid(GaussianTopography(), n, n)
+    rho, V = smooth_random_material(X1, X2, seed)
+    bc = _free_faces()
+    bc[2] = (DISPLACEMENT, None, T_ZERO, None, None)
+    blk = dict(X1=X1, X2=X2, rho=rho, C10=voigt_to_c10(V), bc=bc, forcing=None)
+    xr = np.linspace(0.05, 0.95, nrec) if nrec else np.zeros(0)
+    return dict(order=order, blocks=[blk], interfaces=[],
+                sources=[(0, 0.5, 0.75, 0.0, -1.0, 1.0, 10.0, 0.1)],
+                receivers=[(0, xr, np.ones_like(xr))] if nrec else [],
+                steps=2000, cfl=0.5)
+
+
+def spec_c3(n=2049, seed=0, order=4, nrec=16):
+    """2x2 conforming curvilinear blocks of one smooth map, material contrast 3
+    in a checkerboard, traction on the top and left outer faces, displacement on
+    the bottom and right ones, 16 receivers on the top face."""
+    m = SineWarp()
+    blocks = []
+    for by in range(2):
+        for bx in range(2):
+            lim1 = (0.5 * bx, 0.5 * bx + 0.5)
+            lim2 = (0.5 * by, 0.5 * by + 0.5)
+            X1, X2 = grid(m, n, n, lim1, lim2)
+            rho, V = smooth_random_material(X1, X2, seed)
+            fac = 3.0 if (bx + by) % 2 else 1.0
+            bc = _free_faces()
+            if bx == 1:
+                bc[1] = (DISPLACEMENT, None, T_ZERO, None, None)
+            if by == 0:
+                bc[2] = (DISPLACEMENT, None, T_ZERO, None, None)
+            blocks.append(dict(X1=X1, X2=X2, rho=fac * rho, C10=fac * voigt_to_c10(V), bc=bc, forcing=None))
+    itfs = [(0, 1, 1, 0, False), (2, 1, 3, 0, False), (0, 3, 2, 2, False), (1, 3, 3, 2, False)]
+    half = nrec // 2
+    xr = (np.arange(half) + 0.5) / half
+    recs = [(2, xr, np.ones(half)), (3, xr, np.ones(half))] if nrec else []
+    return dict(order=order, blocks=blocks, interfaces=itfs,
+                sources=[(2, 0.6, 0.3, 0.0, -1.0, 1.0, 10.0, 0.1)],
+                receivers=recs, steps=1000, cfl=0.5)
+
+
+def spec_shot(n, seed, order=4, nrec=64):
+    """One served shot: Gaussian-topography block of n^2 points, its own random
+    material (seed), Ricker source at a random interior point, receivers on x2 = 1."""
+    rng = np.random.default_rng(10_000 + seed)
+    X1, X2 = grid(GaussianTopography(), n, n)
+    rho, V = smooth_random_material(X1, X2, seed)
+    bc = _free_faces()
+    bc[2] = (DISPLACEMENT, None, T_ZERO, None, None)
+    xs = rng.uniform(0.1, 0.9, 2)
+    xr = np.linspace(0.02, 0.98, nrec)
+    return dict(order=order,
+                blocks=[dict(X1=X1, X2=X2, rho=rho, C10=voigt_to_c10(V), bc=bc, forcing=None)],
+                interfaces=[], sources=[(0, xs[0], xs[1], 0.0, -1.0, 1.0, 10.0, 0.1)],
+                receivers=[(0, xr, np.ones(nrec))], steps=1500, cfl=0.5)

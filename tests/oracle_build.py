@@ -1,0 +1,45 @@
+"""Build an oracle Problem from a spec of paper_2003_12811_amd.workloads (test helper)."""
+import numpy as np
+
+from oracle import elastic as E, material as M, sources as Src
+
+
+def tfun(kind, p):
+    p = (0.0, 0.0) if p is None else tuple(p) + (0.0,) * (2 - len(p))
+    if kind == 0:
+        return lambda t: 0.0
+    if kind == 1:
+        return lambda t: 1.0
+    if kind == 2:
+        return lambda t: np.cos(p[0] * t + p[1])
+    if kind == 3:
+        return lambda t: Src.ricker(t, p[0], p[1])
+    raise ValueError(kind)
+
+
+def build(spec, beta=1.0):
+    blocks = []
+    for b in spec['blocks']:
+        blocks.append(E.Block(b['X1'], b['X2'], b['rho'], M.full_from_c10(b['C10']),
+                              order=spec['order'], beta=beta))
+    itfs = [E.Interface(a, fa, bb, fb, reversed=bool(rev)) for (a, fa, bb, fb, rev) in spec.get('interfaces', [])]
+    P = E.Problem(blocks, itfs, beta=beta)
+    for k, b in enumerate(spec['blocks']):
+        for f, (kind, g, tk, tp, U) in enumerate(b['bc']):
+            if blocks[k].bc[f]['kind'] == E.INTERFACE:
+                continue
+            P.set_bc(k, f, kind, g=g, tfun=tfun(tk, tp) if g is not None else None, U=U)
+        if b.get('forcing') is not None:
+            F, tk, tp = b['forcing']
+            P.forcing[k] = (F, tfun(tk, tp))
+    for (bid, x1, x2, f1, f2, amp, fp, t0) in spec.get('sources', []):
+        P.sources.append(Src.point_source(bid, blocks[bid], x1, x2, (f1, f2), amp, fp, t0))
+    return P
+
+
+def receivers(spec, us):
+    out = []
+    for (bid, x1, x2) in spec.get('receivers', []):
+        for a, b in zip(x1, x2):
+            out.append(Src.sample(us[bid], a, b))
+    return np.array(out)

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Tolerances (relative L2): FP64 1e-11, FP32 1e-5.  FP32 cases feed both sides
+the same FP32-rounded inputs (the oracle promotes them to FP64).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import elastic as E, timestep as T
+from paper_2003_12811_amd import sbpe as S
+from paper_2003_12811_amd import workloads as W
+
+from oracle_build import build, receivers
+
+pytestmark = pytest.mark.gpu
+TOL = {'f64': 1e-11, 'f32': 1e-5}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def solver(spec, dtype='f64', **kw):
+    from paper_2003_12811_amd.solver import Solver
+    return Solver(spec, dtype=dtype, **kw)
+
+
+def rounded(x, dtype):
+    return x.astype(np.float32).astype(np.float64) if dtype == 'f32' else x
+
+
+def mixed_spec(n1, n2, order=4, seed=3):
+    """One curvilinear block, Cosserat random material, every boundary type with data,
+    forcing and a point source."""
+    X1, X2 = W.grid(W.GaussianTopography(0.15, 0.2), n1, n2)
+    rho, C10 = W.paper_random_material((n2, n1), seed)
+    rng = np.random.default_rng(seed)
+    nf = [n2, n2, n1, n1]
+    Q = rng.uniform(0, 1, (2, 2, n2))
+    U = np.einsum('ikf,jkf->ijf', Q, Q)
+    bc = [(W.DISPLACEMENT, rng.normal(size=(2, nf[0])), W.T_COS, (3.0, 0.2), None),
+          (W.ROBIN, rng.normal(size=(2, nf[1])), W.T_RICKER, (5.0, 0.1), U),
+          (W.TRACTION, rng.normal(size=(2, nf[2])), W.T_COS, (2.0, -0.4), None),
+          (W.DISPLACEMENT, None, W.T_ZERO, None, None)]
+    F = rng.normal(size=(2, n2, n1))
+    blk = dict(X1=X1, X2=X2, rho=rho, C10=C10, bc=bc, forcing=(F, W.T_COS, (1.5, 0.3)))
+    return dict(order=order, blocks=[blk], interfaces=[],
+                sources=[(0, 0.37, 0.61, 0.3, -1.0, 2.0, 8.0, 0.05), (0, 0.0, 0.96, 1.0, 0.0, 1.0, 6.0, 0.02)],
+                receivers=[])
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+@pytest.mark.parametrize("order", [4, 2])
+@pytest.mark.parametrize("shape", [(97, 83), (13 + 64, 13)])
+def test_apply_single_block_all_bcs(dtype, order, shape):
+    n1, n2 = shape
+    if order == 2:
+        n1, n2 = n1 - 3, n2 + 2
+    say('apply single block', dtype, order, n1, n2)
+    spec = mixed_spec(n1, n2, order)
+    P = build(spec)
+    sol = solver(spec, dtype)
+    rng = np.random.default_rng(11)
+    u = rounded(rng.normal(size=(2, n2, n1)), dtype)
+    for t, hom in ((0.13, False), (0.0, True)):
+        got = sol.apply([u], t=t, homogeneous=hom)[0].double().cpu().numpy()
+        if hom:
+            L = P.total_operator([u], t, homogeneous=True)[0]
+            B = P.blocks[0]
+            ref = (L / B.rho.ravel()).reshape(2, n2, n1)
+        else:
+            ref = P.rhs([u], t)[0]
+        err = rel(got, ref)
+        say('  t', t, 'hom', hom, 'rel L2', err)
+        assert err < TOL[dtype]
+    sol.close()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+@pytest.mark.parametrize("n", [45, 77])
+def test_apply_multiblock_c3_geometry(dtype, n):
+    say('apply 2x2 blocks', dtype, n)
+    spec = W.spec_c3(n=n)
+    P = build(spec)
+    sol = solver(spec, dtype)
+    rng = np.random.default_rng(5)
+    us = [rounded(rng.normal(size=(2, n, n)), dtype) for _ in range(4)]
+    got = [x.double().cpu().numpy() for x in sol.apply(us, t=0.11)]
+    ref = P.rhs(us, 0.11)
+    err = rel(np.concatenate([g.ravel() for g in got]), np.concatenate([r.ravel() for r in ref]))
+    say('  rel L2', err)
+    assert err < TOL[dtype]
+    sol.close()
+
+
+@pytest.mark.parametrize("order", [4, 2])
+def test_apply_reversed_interface(order):
+    n = 29
+    say('apply reversed interface', order)
+    XA = W.grid(W.SineWarp(0.05), n, n, (0, 0.5), (0, 1))
+
+    class Flip(W.Mapping):
+        def __call__(self, x1, x2):
+            return W.SineWarp(0.05)(x1, 1.0 - x2)
+    XB = W.grid(Flip(), n, n, (0.5, 1), (0, 1))
+    XB = (np.ascontiguousarray(XB[0][:, ::-1]), np.ascontiguousarray(XB[1][:, ::-1]))
+    ra, Ca = W.paper_random_material((n, n), 2)
+    rb, Cb = W.paper_random_material((n, n), 3)
+    free = [(W.TRACTION, None, W.T_ZERO, None, None)] * 4
+    bcA = list(free)
+    bcA[0] = (W.DISPLACEMENT, None, W.T_ZERO, None, None)
+    spec = dict(order=order, blocks=[dict(X1=XA[0], X2=XA[1], rho=ra, C10=Ca, bc=bcA, forcing=None),
+                                     dict(X1=XB[0], X2=XB[1], rho=rb, C10=Cb, bc=list(free), forcing=None)],
+                interfaces=[(0, 1, 1, 1, True)], sources=[], receivers=[])
+    P = build(spec)
+    sol = solver(spec, 'f64')
+    rng = np.random.default_rng(8)
+    us = [rng.normal(size=(2, n, n)) for _ in range(2)]
+    got = [x.cpu().numpy() for x in sol.apply(us)]
+    ref = P.rhs(us, 0.0)
+    err = rel(np.concatenate([g.ravel() for g in got]), np.concatenate([r.ravel() for r in ref]))
+    say('  rel L2', err)
+    assert err < 1e-11
+    sol.close()
+
+
+def test_advance_mms_c1_fp64():
+    """Config 1 end to end: 65^2, MMS forcing and traction data, CFL 0.5 to t = 0.5."""
+    spec = W.spec_c1(65)
+    say('advance C1 MMS 65^2 fp64')
+    P = build(spec)
+    dt_lib = None
+    sol = solver(spec, 'f64')
+    dt_lib = sol.dt_cfl(0.5)
+    dt_or = T.dt_cfl(P, 0.5)
+    assert abs(dt_lib / dt_or - 1) < 1e-6
+    nst, dt = T.steps_for(0.5, dt_or)
+    assert nst == 140
+    u0 = spec['mms']['u']
+    sol.set_state([u0], None, 0.0)
+    sol.advance(nst, dt)
+    ug, vg = sol.state_numpy()
+    u, v, t = [u0.copy()], [np.zeros_like(u0)], 0.0
+    for _ in range(nst):
+        u, v = T.rk4_step(P, u, v, t, dt)
+        t += dt
+    eu, ev = rel(ug[0], u[0]), rel(vg[0], v[0])
+    say('  rel L2 u', eu, 'v', ev, 't', sol.time())
+    assert eu < 1e-11 and ev < 1e-11
+    assert abs(sol.time() - 0.5) < 1e-12
+    exact = u0 * np.cos(spec['mms']['omega'] * 0.5)
+    B = P.blocks[0]
+    err = np.sqrt(np.sum(B.J * B.H * ((ug[0] - exact) ** 2).sum(0)))
+    say('  MMS l2 error', err)
+    assert err < 2e-5
+    sol.close()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_advance_source_receivers_c2_small(dtype):
+    n, nsteps = 97, 60
+    say('advance C2 geometry', n, dtype)
+    spec = W.spec_c2(n=n, nrec=8)
+    P = build(spec)
+    sol = solver(spec, dtype)
+    dt = T.dt_cfl(P, 0.5)
+    sol.set_state(None, None, 0.0)
+    sol.advance(nsteps, dt)
+    ug, vg = sol.state_numpy()
+    rg = sol.receivers()
+    u, v, t = [np.zeros((2, n, n))], [np.zeros((2, n, n))], 0.0
+    rec = []
+    for _ in range(nsteps):
+        u, v = T.rk4_step(P, u, v, t, dt)
+        t += dt
+        rec.append(receivers(spec, u))
+    rec = np.array(rec)
+    eu, ev, er = rel(ug[0], u[0]), rel(vg[0], v[0]), rel(rg, rec)
+    say('  rel L2 u', eu, 'v', ev, 'receivers', er, 'max|u|', np.abs(u[0]).max())
+    assert rg.shape == rec.shape
+    assert np.abs(u[0]).max() > 0
+    assert max(eu, ev, er) < TOL[dtype]
+    sol.close()
+
+
+def test_energy_and_determinism():
+    n = 61
+    say('energy and determinism', n)
+    spec = W.spec_c2(n=n, nrec=0)
+    spec['sources'] = []
+    P = build(spec)
+    sol = solver(spec, 'f64')
+    rng = np.random.default_rng(4)
+    u0 = rng.normal(size=(2, n, n))
+    v0 = rng.normal(size=(2, n, n))
+    sol.set_state([u0], [v0], 0.0)
+    e_lib = sol.energy()
+    e_or = P.energy([u0], [v0])
+    say('  energy lib', e_lib, 'oracle', e_or)
+    assert abs(e_lib / e_or - 1) < 1e-11
+    dt = T.dt_cfl(P, 0.5)
+    prev = e_lib
+    for _ in range(5):
+        sol.advance(10, dt)
+        e = sol.energy()
+        assert e <= prev * (1 + 1e-12)
+        prev = e
+    u1, v1 = sol.state_numpy()
+    sol.set_state([u0], [v0], 0.0)
+    sol.advance(50, dt)
+    u2, v2 = sol.state_numpy()
+    assert np.array_equal(u1[0], u2[0]) and np.array_equal(v1[0], v2[0])
+    sol.close()
+
+
+def test_energy_guard_trips_on_oversized_step():
+    n = 41
+    say('energy guard', n)
+    spec = W.spec_c2(n=n, nrec=0)
+    spec['sources'] = []
+    sol = solver(spec, 'f64')
+    rng = np.random.default_rng(1)
+    sol.set_state([rng.normal(size=(2, n, n))], None, 0.0)
+    S.sbpe_set_energy_guard(sol.ctx, 2, 1e-6)
+    dt = sol.dt_cfl(0.5) * 6.0
+    with pytest.raises(S.SbpeError) as e:
+        sol.advance(40, dt)
+    assert e.value.code == S.EUNSTABLE
+    sol.close()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_full_size_c2_apply(dtype):
+    """Config 2 at its full size (1025^2), in the kernels the benchmark times."""
+    n = 1025
+    say('full size C2 apply', dtype)
+    spec = W.spec_c2(n=n, nrec=0)
+    P = build(spec)
+    sol = solver(spec, dtype)
+    x1, x2 = W.reference_grid(n, n)
+    u = rounded(np.stack([np.sin(7 * x1) * np.cos(5 * x2), np.cos(3 * x1 + 2 * x2)]) +
+                1e-3 * np.random.default_rng(0).normal(size=(2, n, n)), dtype)
+    got = sol.apply([u], t=0.1)[0].double().cpu().numpy()
+    ref = P.rhs([u], 0.1)[0]
+    err = rel(got, ref)
+    say('  rel L2', err)
+    assert err < TOL[dtype]
+    sol.close()

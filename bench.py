@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the RK4-advanced SBP-SAT anisotropic elastic solver on one MI355X.
+
+Workload (the single-GPU configuration the headline metric is quoted on): one
+curvilinear block of 1025 x 1025 points with Gaussian topography, smooth random
+SPD stiffness and density (8 Fourier modes per field, seed 0), displacement SAT
+on the bottom face and traction SATs elsewhere, a 10 Hz Ricker point force and
+16 surface receivers; classical RK4 at CFL 0.5.  A step is one full RK4 step
+(four right-hand-side evaluations fused into two sweeps over the grid,
+sources, receivers).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line on stdout; progress goes to stderr.  The primary result is
+FP64; the FP32 variant, the plain operator apply and a working set larger than
+the MALL (2x2 blocks of 2049^2, FP32) are reported beside it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# algorithmic words per interior point of each kernel launch:
+#   first sweep : u, v in (4) + 11 coefficient fields + a1, a2 out (4)
+#   second sweep: a1, a2 in (4) + 11 coefficients + u, v in (4) + u, v out (4)
+#   apply       : u in (2) + 11 coefficients + a out (2)
+WORDS = {'interior_rk1': 19, 'interior_rk2': 23, 'interior_apply': 15}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def roofline(kind, ms, points, wbytes, traffic=None):
+    byts = WORDS[kind] * wbytes * points
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kind, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "avg_ms": round(ms, 5), "bytes_per_launch": byts}
+
+
+def run_gpu(spec, dtype, steps, warmup, apply_reps=0):
+    import torch
+    from paper_2003_12811_amd import sbpe as S
+    from paper_2003_12811_amd.solver import Solver
+    sol = Solver(spec, dtype)
+    dt = sol.dt_cfl(spec.get('cfl', 0.5))
+    sol.set_state(None, None, 0.0)
+    plan = S.sbpe_plan_info(sol.ctx)
+    npts = sum(b['X1'].size for b in spec['blocks'])
+    sol.advance(warmup, dt)
+    sol.synchronize()
+    S.sbpe_set_kernel_timing(sol.ctx, 1)
+    S.sbpe_get_kernel_timing(sol.ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol.advance(steps, dt)
+    sol.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = S.sbpe_get_kernel_timing(sol.ctx)
+    wall = t1 - t0
+    res = dict(dtype=dtype, points=npts, steps=steps, wall_s=wall, ms_per_step=1e3 * wall / steps,
+               updates_per_s=npts * steps / wall, dt=dt, kernels=kt, plan=plan)
+    if apply_reps:
+        u = [torch.zeros((2,) + b['X1'].shape, dtype=sol.tdtype, device=sol.device) for b in spec['blocks']]
+        for x in u:
+            x.normal_()
+        out = [torch.empty_like(x) for x in u]
+        sol.apply(u, 0.0, False, out)
+        S.sbpe_get_kernel_timing(sol.ctx)
+        for _ in range(apply_reps):
+            sol.apply(u, 0.0, False, out)
+        res['apply_kernels'] = S.sbpe_get_kernel_timing(sol.ctx)
+    S.sbpe_set_kernel_timing(sol.ctx, 0)
+    sol.close()
+    return res
+
+
+def dominant(res):
+    best, kind = -1.0, None
+    for k, (ms, cnt) in res['kernels'].items():
+        if k.startswith('interior') and ms * cnt > best:
+            best, kind = ms * cnt, k
+    return kind
+
+
+def cpu_baseline(n, steps):
+    """Oracle RK4 steps on the host (single thread), in a child process."""
+    env = dict(os.environ, OMP_NUM_THREADS='1', OPENBLAS_NUM_THREADS='1', MKL_NUM_THREADS='1')
+    cmd = [sys.executable, os.path.abspath(__file__), '--cpu-baseline-child', '--n', str(n),
+           '--cpu-steps', str(steps)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+    if r.returncode != 0:
+        log(r.stderr[-2000:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline_child(n, steps):
+    import numpy as np
+    from paper_2003_12811_amd import workloads as W
+    from oracle import spec as OS, timestep as T
+    spec = W.spec_c2(n=n)
+    P = OS.build(spec)
+    dt = T.dt_cfl(P, 0.5)
+    u = [np.zeros((2, n, n))]
+    v = [np.zeros((2, n, n))]
+    t = 0.0
+    u, v = T.rk4_step(P, u, v, t, dt)       # warm-up step
+    t += dt
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, v = T.rk4_step(P, u, v, t, dt)
+        t += dt
+    wall = time.perf_counter() - t0
+    print(json.dumps({"value": n * n * steps / wall, "unit": "grid-point updates/s", "cores": 1,
+                      "kind": "oracle", "sample": "%d RK4 steps of the %dx%d workload (FP64, NumPy/SciPy, "
+                      "one thread), %.1f s" % (steps, n, n, wall)}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=400)
+    ap.add_argument('--warmup', type=int, default=40)
+    ap.add_argument('--n', type=int, default=1025)
+    ap.add_argument('--cpu-steps', type=int, default=10)
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-large', action='store_true')
+    ap.add_argument('--large-n', type=int, default=2049)
+    ap.add_argument('--cpu-baseline-child', action='store_true')
+    args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.n, args.cpu_steps)
+        return
+    world = int(os.environ.get('WORLD_SIZE', '1'))
+    if args.gpus != 1 or world != 1:
+        print('this build measures one GPU only: run bench.py with --gpus 1 (the multi-GPU '
+              'sharding by blocks is described in DESIGN.md, not implemented)', file=sys.stderr)
+        sys.exit(2)
+    from paper_2003_12811_amd import workloads as W
+    log('building workload %dx%d' % (args.n, args.n))
+    spec = W.spec_c2(n=args.n)
+    log('fp64 run')
+    r64 = run_gpu(spec, 'f64', args.steps, args.warmup, apply_reps=50)
+    log('  %.3f ms/step, %.3e updates/s' % (r64['ms_per_step'], r64['updates_per_s']))
+    log('fp32 run')
+    r32 = run_gpu(spec, 'f32', args.steps, args.warmup, apply_reps=50)
+    log('  %.3f ms/step, %.3e updates/s' % (r32['ms_per_step'], r32['updates_per_s']))
+    pts = r64['plan']['interior_points']
+    k = dominant(r64)
+    line = {
+        "metric": "grid-point updates/s", "value": r64['updates_per_s'], "unit": "grid-point updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64['ms_per_step'],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single curvilinear block %dx%d, Gaussian topography, random smooth SPD C/rho "
+                               "(seed 0), displacement bottom + traction SATs, 10 Hz Ricker force, 16 receivers, "
+                               "4th-order SBP-SAT, RK4 CFL 0.5" % (args.n, args.n),
+                   "points": r64['points'], "dt": r64['dt'], "parallelism": "1 GPU"},
+        "roofline": roofline(k, r64['kernels'][k][0], pts, 8),
+        "kernels_ms": {kk: v[0] for kk, v in r64['kernels'].items() if v[1]},
+        "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8),
+        "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'],
+                "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4),
+                "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4)},
+    }
+    if not args.no_large:
+        log('large working set: 2x2 blocks of %d^2, fp32' % args.large_n)
+        t0 = time.time()
+        sp3 = W.spec_c3(n=args.large_n)
+        log('  workload built in %.1f s' % (time.time() - t0))
+        r3 = run_gpu(sp3, 'f32', max(args.steps // 4, 20), 10)
+        k3 = dominant(r3)
+        line["large"] = {"workload": "2x2 blocks of %d^2 with interfaces, FP32" % args.large_n,
+                         "value": r3['updates_per_s'], "ms_per_step": r3['ms_per_step'],
+                         "roofline": roofline(k3, r3['kernels'][k3][0], r3['plan']['interior_points'], 4),
+                         "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]}}
+        log('  %.3f ms/step, %.3e updates/s' % (r3['ms_per_step'], r3['updates_per_s']))
+    if not args.no_cpu_baseline:
+        log('cpu baseline (oracle, 1 thread, %d steps)' % args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -154,7 +154,9 @@ sbpe_status sbpe_advance(sbpe_ctx_t ctx, int nsteps, double dt);
 sbpe_status sbpe_get_time(sbpe_ctx_t ctx, double* t);
 
 /* Copy receiver traces recorded since the last sbpe_bind_state into out
- * ([nsteps][nrec][2], FP64, host), at most max_steps steps; synchronises. */
+ * ([nsteps][nrec][2], FP64, host), at most max_steps steps; synchronises.
+ * With out == NULL only *nsteps_out (the number of steps available, capped at
+ * max_steps) is returned. */
 sbpe_status sbpe_read_receivers(sbpe_ctx_t ctx, double* out, int max_steps, int* nsteps_out);
 
 /* Discrete energy eps = 1/2 (v^T P H v - u^T A u), A = diag(JH) D^tot, of the
@@ -168,6 +170,20 @@ sbpe_status sbpe_set_energy_guard(sbpe_ctx_t ctx, int every, double rel_growth);
 
 /* Wait for all work enqueued on the context stream. */
 sbpe_status sbpe_synchronize(sbpe_ctx_t ctx);
+
+/* Kernel timing for measurement: while enabled, every kernel launch of
+ * sbpe_advance and sbpe_apply is bracketed by HIP events on the context stream.
+ * sbpe_get_kernel_timing synchronises and returns, for the six launch kinds
+ * (interior, frame) x (first RK4 sweep, second RK4 sweep, apply), the average
+ * duration in milliseconds (ms_avg[6]) and the number of launches (count[6]),
+ * then clears the accumulators. */
+sbpe_status sbpe_set_kernel_timing(sbpe_ctx_t ctx, int enable);
+sbpe_status sbpe_get_kernel_timing(sbpe_ctx_t ctx, double* ms_avg, int* count);
+
+/* Launch plan after sbpe_finalize: info[0] = interior points, info[1] = frame
+ * points (summed over blocks), info[2] = interior workgroups, info[3] = frame
+ * workgroups, info[4] = frame width in points. */
+sbpe_status sbpe_plan_info(sbpe_ctx_t ctx, long long* info);
 
 /* ---------------------------------------------------------------- host-side
  * Queries of the library's own setup, for checking it on a machine without a

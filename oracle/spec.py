@@ -1,7 +1,13 @@
-"""Build an oracle Problem from a spec of paper_2003_12811_amd.workloads (test helper)."""
+"""Build an oracle Problem from a plain problem spec (oracle, test infrastructure only).
+
+A spec is a dict of NumPy arrays and tuples (the seeded workloads produce them):
+order, blocks [X1, X2, rho, C10, bc = 4 x (kind, g, time_fn, time_params, U),
+forcing], interfaces, sources, receivers.  Time functions: 0 zero, 1 one,
+2 cos(p0 t + p1), 3 Ricker(peak p0, centre p1) (Sec. 7.3).
+"""
 import numpy as np
 
-from oracle import elastic as E, material as M, sources as Src
+from . import elastic as E, material as M, sources as Src
 
 
 def tfun(kind, p):

@@ -13,6 +13,7 @@ LIB = os.path.join(HERE, 'lib', 'libsbpe.so')
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 
 SOURCES = ['sbpe_host.cpp', 'sbpe_kernels.hip']
+HOST_ONLY_FLAGS = {'sbpe_host.cpp': ['-fopenmp']}
 # packed FP32 instructions are disabled for every device compile
 DEVICE_FLAGS = ['--offload-arch=gfx950', '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops']
 COMMON = ['-O3', '-std=c++17', '-fPIC', '-Wall', '-I', os.path.join(ROOT, 'include')]
@@ -23,7 +24,7 @@ def build(verbose=False):
     objs = []
     for src in SOURCES:
         obj = os.path.join(os.path.dirname(LIB), src.rsplit('.', 1)[0] + '.o')
-        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ['-c', os.path.join(CSRC, src), '-o', obj]
+        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + HOST_ONLY_FLAGS.get(src, []) + ['-c', os.path.join(CSRC, src), '-o', obj]
         if verbose:
             print(' '.join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -34,7 +35,7 @@ def build(verbose=False):
             print(err)
         objs.append(obj)
     tmp = LIB + '.tmp'
-    cmd = [HIPCC, '-shared', '-fPIC', '--offload-arch=gfx950'] + objs + ['-o', tmp]
+    cmd = [HIPCC, '-shared', '-fPIC', '--offload-arch=gfx950', '-fopenmp'] + objs + ['-o', tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError('link failed:\n' + r.stderr)

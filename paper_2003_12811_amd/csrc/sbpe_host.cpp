@@ -66,67 +66,15 @@ void dense_d1(int order, int n, double* D) {
     }
 }
 
-// remainder windows of h R(b) on a line of n points: for every window its
-// first point, stencil, weight gamma and the shares defining B(b).
-struct Window {
-    int c;
-    int len;
-    double d[5];
-    double g;
-    int nsh;
-    int shp[2];
-    double shw[2];
-};
-
-static std::vector<Window> windows(int order, int n) {
-    std::vector<Window> out;
-    if (order == 2) {
-        for (int c = 0; c + 2 < n; ++c) {
-            Window w{c, 3, {1, -2, 1, 0, 0}, O2_G2, 1, {c + 1, 0}, {1.0, 0.0}};
-            out.push_back(w);
-        }
-        return out;
-    }
-    const int n3 = n - 3;
-    for (int c = 0; c < n3; ++c) {
-        double g = O4_G3;
-        if (c < 3) g = O4_G3_BND[c];
-        else if (n3 - 1 - c < 3) g = O4_G3_BND[n3 - 1 - c];
-        Window w{c, 4, {-1, 3, -3, 1, 0}, g, 2, {c + 1, c + 2}, {0.5, 0.5}};
-        out.push_back(w);
-    }
-    for (int c = 0; c + 4 < n; ++c) {
-        Window w{c, 5, {1, -4, 6, -4, 1}, O4_G4, 1, {c + 2, 0}, {1.0, 0.0}};
-        out.push_back(w);
-    }
-    return out;
-}
-
 void derive_d2_closure(int order, double* T) {
-    const int R0 = order == 4 ? O4_R0 : O2_R0;
-    const int W = order == 4 ? O4_W : O2_W;
-    const int n = 32;
-    std::vector<double> D((size_t)n * n);
-    dense_d1(order, n, D.data());
-    std::fill(T, T + (size_t)R0 * W * W, 0.0);
-    const auto wins = windows(order, n);
-    for (int r = 0; r < R0; ++r) {
-        const double ir = 1.0 / norm_weight(order, n, r);
-        for (int m = 0; m < W; ++m) {
-            for (int s = 0; s < W; ++s) {
-                // -D1^T H b D1
-                double v = -D[(size_t)s * n + r] * norm_weight(order, n, s) * D[(size_t)s * n + m];
-                // -R(b)
-                for (const auto& w : wins) {
-                    if (r < w.c || r >= w.c + w.len || m < w.c || m >= w.c + w.len) continue;
-                    for (int q = 0; q < w.nsh; ++q)
-                        if (w.shp[q] == s) v -= w.g * w.shw[q] * w.d[r - w.c] * w.d[m - w.c];
-                }
-                // -e0 b0 e0^T D1 (boundary derivative replaced by D1: fully compatible)
-                if (r == 0 && s == 0) v -= D[m];
-                T[((size_t)r * W + m) * W + s] = v * ir;
-            }
-        }
+    if (order == 4) {
+        for (int r = 0; r < O4_R0; ++r)
+            for (int m = 0; m < O4_W; ++m)
+                for (int s = 0; s < O4_W; ++s) T[((size_t)r * O4_W + m) * O4_W + s] = D2T4.t[r][m][s];
+    } else {
+        for (int r = 0; r < O2_R0; ++r)
+            for (int m = 0; m < O2_W; ++m)
+                for (int s = 0; s < O2_W; ++s) T[((size_t)r * O2_W + m) * O2_W + s] = D2T2.t[r][m][s];
     }
 }
 
@@ -191,6 +139,10 @@ using namespace sbpe;
 struct sbpe_ctx {
     int device = -1;
     hipStream_t stream = nullptr;
+    // the frame kernel runs on a second stream, concurrently with the interior
+    // kernel; the two streams are joined at every sweep boundary
+    hipStream_t side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr;
     int dtype = SBPE_F64;
     int order = 4;
     double beta = 1.0;
@@ -206,7 +158,10 @@ struct sbpe_ctx {
     Entry* d_entries = nullptr;
     Range* d_tile_ranges = nullptr;
     Range* d_frame_ranges = nullptr;
-    TimeFn* d_src_tf = nullptr;
+    TimeFn* d_items = nullptr;      // time functions of the data items (k_tau)
+    int nitems = 0;
+    double* d_tau = nullptr;        // tabulated time functions [steps][nitems][3]
+    long tau_cap = 0;               // steps of capacity
     int total_tiles = 0, total_frame_wg = 0;
     // state
     bool bound = false;
@@ -219,6 +174,13 @@ struct sbpe_ctx {
     int npartial = 0;
     int guard_every = 0;
     double guard_growth = 0.0;
+    // kernel timing: pending (kind, start, stop) event records and sums
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_kind;
+    double t_sum[6] = {0, 0, 0, 0, 0, 0};
+    int t_cnt[6] = {0, 0, 0, 0, 0, 0};
 };
 
 static thread_local std::string g_static_err;
@@ -307,10 +269,12 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
     B.h2 = 1.0 / (n2 - 1);
     // A[i][I] = dX_I / dx_i
     std::vector<double> A00(np), A01(np), A10(np), A11(np);
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < n2; ++j) {
         d1_apply(o, n1, B.h1, &B.X1[(long)j * n1], 1, &A00[(long)j * n1], 1);
         d1_apply(o, n1, B.h1, &B.X2[(long)j * n1], 1, &A01[(long)j * n1], 1);
     }
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n1; ++i) {
         d1_apply(o, n2, B.h2, &B.X1[i], n1, &A10[i], n1);
         d1_apply(o, n2, B.h2, &B.X2[i], n1, &A11[i], n1);
@@ -318,13 +282,14 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
     B.J.assign(np, 0.0);
     B.coef.assign((size_t)NCOEF * np, 0.0);
     B.c10t.assign((size_t)10 * np, 0.0);
+    long bad_j = -1, bad_c = -1;
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < np; ++p) {
         const double J = A00[p] * A11[p] - A01[p] * A10[p];
         if (!(J > 0.0)) {
-            char buf[160];
-            std::snprintf(buf, sizeof buf, "block %d: discrete Jacobian %.3e <= 0 at point (%ld, %ld)", b, J,
-                          p % n1, p / n1);
-            return fail(c, SBPE_ENONPOS_J, buf);
+#pragma omp critical
+            bad_j = (bad_j < 0 || p < bad_j) ? p : bad_j;
+            continue;
         }
         B.J[p] = J;
         // F[I][i] = dx_i / dX_I
@@ -334,10 +299,9 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
         double lmin, lmax;
         eig4(Cm, lmin, lmax);
         if (lmin < -1e-10 * std::max(1.0, std::fabs(lmax))) {
-            char buf[160];
-            std::snprintf(buf, sizeof buf, "block %d: stiffness not positive semidefinite at point (%ld, %ld)", b,
-                          p % n1, p / n1);
-            return fail(c, SBPE_ENOT_PSD, buf);
+#pragma omp critical
+            bad_c = (bad_c < 0 || p < bad_c) ? p : bad_c;
+            continue;
         }
         // c_ijkl = J F_Ii C_IjKl F_Kk ; C pair index (IJ) -> 2I + J
         double cc[2][2][2][2];
@@ -368,6 +332,19 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
             const int* d = pr[C10P[m][1]];
             B.c10t[m * np + p] = cc[a[0]][a[1]][d[0]][d[1]];
         }
+    }
+    if (bad_j >= 0) {
+        const double J = A00[bad_j] * A11[bad_j] - A01[bad_j] * A10[bad_j];
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "block %d: discrete Jacobian %.3e <= 0 at point (%ld, %ld)", b, J,
+                      bad_j % n1, bad_j / n1);
+        return fail(c, SBPE_ENONPOS_J, buf);
+    }
+    if (bad_c >= 0) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "block %d: stiffness not positive semidefinite at point (%ld, %ld)", b,
+                      bad_c % n1, bad_c / n1);
+        return fail(c, SBPE_ENOT_PSD, buf);
     }
     // surface scale factors: Jhat = |a_t|, a_t = dX/dx_t
     for (int f = 0; f < 4; ++f) {
@@ -402,59 +379,54 @@ static double christoffel_lmax(const HostBlock& B, long p, double th) {
 }
 
 static double block_vmax2(const HostBlock& B) {
-    const int nang = 180;
+    // coarse sweep over directions at every point, then golden-section
+    // refinement of the best candidates (lambda_max is smooth near its maximum)
+    const int nang = 36;
     const long np = B.np();
-    struct Cand {
-        double val;
-        long p;
-        int k;
-    };
-    std::vector<Cand> top;
-    const size_t keep = 64;
+    std::vector<double> best(np);
+    std::vector<int> bk(np);
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < np; ++p) {
-        double best = -1.0;
-        int bk = 0;
+        double bv = -1.0;
+        int kk = 0;
         for (int k = 0; k < nang; ++k) {
             const double v = christoffel_lmax(B, p, M_PI * k / nang);
-            if (v > best) {
-                best = v;
-                bk = k;
+            if (v > bv) {
+                bv = v;
+                kk = k;
             }
         }
-        if (top.size() < keep) {
-            top.push_back({best, p, bk});
-            if (top.size() == keep)
-                std::make_heap(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.val > b.val; });
-        } else if (best > top.front().val) {
-            std::pop_heap(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.val > b.val; });
-            top.back() = {best, p, bk};
-            std::push_heap(top.begin(), top.end(), [](const Cand& a, const Cand& b) { return a.val > b.val; });
-        }
+        best[p] = bv;
+        bk[p] = kk;
     }
+    const long keep = std::min<long>(256, np);
+    std::vector<long> idx(np);
+    for (long p = 0; p < np; ++p) idx[p] = p;
+    std::partial_sort(idx.begin(), idx.begin() + keep, idx.end(), [&](long a, long b) { return best[a] > best[b]; });
     double vmax = 0.0;
     const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
-    for (const auto& cnd : top) {
-        // golden-section search on [th - d, th + d] (lambda is smooth near its maximum)
+    for (long q = 0; q < keep; ++q) {
+        const long p = idx[q];
         const double d = M_PI / nang;
-        double a = M_PI * cnd.k / nang - d, b = M_PI * cnd.k / nang + d;
+        double a = M_PI * bk[p] / nang - d, b = M_PI * bk[p] / nang + d;
         double x1 = b - gr * (b - a), x2 = a + gr * (b - a);
-        double f1 = christoffel_lmax(B, cnd.p, x1), f2 = christoffel_lmax(B, cnd.p, x2);
+        double f1 = christoffel_lmax(B, p, x1), f2 = christoffel_lmax(B, p, x2);
         for (int it = 0; it < 60; ++it) {
             if (f1 < f2) {
                 a = x1;
                 x1 = x2;
                 f1 = f2;
                 x2 = a + gr * (b - a);
-                f2 = christoffel_lmax(B, cnd.p, x2);
+                f2 = christoffel_lmax(B, p, x2);
             } else {
                 b = x2;
                 x2 = x1;
                 f2 = f1;
                 x1 = b - gr * (b - a);
-                f1 = christoffel_lmax(B, cnd.p, x1);
+                f1 = christoffel_lmax(B, p, x1);
             }
         }
-        vmax = std::max(vmax, std::max(cnd.val, std::max(f1, f2)));
+        vmax = std::max(vmax, std::max(best[p], std::max(f1, f2)));
     }
     return vmax;
 }
@@ -495,7 +467,7 @@ static sbpe_status build_plan(sbpe_ctx* c) {
         D.h2 = H.h2;
         D.coef = H.d_coef;
         D.force = H.d_force;
-        D.ftf = H.ftf;
+        D.item_f = b * ITEMS_PER_BLOCK + 8;
         D.a1 = H.d_a1;
         D.a2 = H.d_a2;
         D.u = H.u;
@@ -506,7 +478,7 @@ static sbpe_status build_plan(sbpe_ctx* c) {
         D.tile_beg = tiles;
         tiles += D.tiles_x * D.tiles_y;
         D.frame_n = 2 * R * H.n1 + 2 * R * std::max(0, H.n2 - 2 * R);
-        D.frame_wg = (D.frame_n + FRAME_WG - 1) / FRAME_WG;
+        D.frame_wg = (D.frame_n + FRAME_PTS - 1) / FRAME_PTS;
         D.frame_beg = fwg;
         fwg += D.frame_wg;
         for (int f = 0; f < 4; ++f) {
@@ -516,7 +488,8 @@ static sbpe_status build_plan(sbpe_ctx* c) {
             F.nf = H.nf(f);
             const int a = f >> 1;
             F.w = (a == 0 ? H.h1 : H.h2) * norm_weight(c->order, a == 0 ? H.n1 : H.n2, 0);
-            F.tf = HF.tf;
+            F.item_g = b * ITEMS_PER_BLOCK + f;
+            F.item_v = b * ITEMS_PER_BLOCK + 4 + f;
             F.g = H.d_face[f][0];
             F.U = H.d_face[f][1];
             F.partner = HF.partner;
@@ -525,7 +498,6 @@ static sbpe_status build_plan(sbpe_ctx* c) {
             F.vsign = HF.side == 0 ? 1.0 : -1.0;
             F.V = nullptr;
             F.Th = nullptr;
-            F.vtf = TimeFn{TF_ZERO, 0, {0.0, 0.0}};
             if (HF.kind == BC_INTERFACE) {
                 const HostBlock& P = c->blocks[HF.partner];
                 const int pa = HF.pface >> 1;
@@ -553,11 +525,16 @@ static sbpe_status build_plan(sbpe_ctx* c) {
             x.wg = D.tile_beg + ((j - R) / TILE_Y) * D.tiles_x + (i - R) / TILE_X;
         } else {
             x.frame = 1;
-            x.wg = D.frame_beg + (int)(frame_index(H, R, i, j) / FRAME_WG);
+            x.wg = D.frame_beg + (int)(frame_index(H, R, i, j) / FRAME_PTS);
         }
         ents.push_back(x);
     };
-    std::vector<TimeFn> stf;
+    // time-function items: per block 4 faces (g), 4 faces (jump data), forcing; then sources
+    std::vector<TimeFn> items((size_t)nb * ITEMS_PER_BLOCK + c->sources.size(), TimeFn{TF_ZERO, 0, {0.0, 0.0}});
+    for (int b = 0; b < nb; ++b) {
+        for (int f = 0; f < 4; ++f) items[(size_t)b * ITEMS_PER_BLOCK + f] = c->blocks[b].face[f].tf;
+        items[(size_t)b * ITEMS_PER_BLOCK + 8] = c->blocks[b].ftf;
+    }
     for (size_t s = 0; s < c->sources.size(); ++s) {
         const Source& S = c->sources[s];
         const HostBlock& H = c->blocks[S.block];
@@ -570,10 +547,10 @@ static sbpe_status build_plan(sbpe_ctx* c) {
                 const int i = i0 + d, j = j0 + a;
                 const double Hp = H.h1 * H.h2 * norm_weight(c->order, H.n1, i) * norm_weight(c->order, H.n2, j);
                 const double w = wi[d] * wj[a] / Hp;
-                Entry e{0, 0, (int)s, 0, S.amp * S.f1 * w, S.amp * S.f2 * w};
+                Entry e{0, 0, nb * ITEMS_PER_BLOCK + (int)s, 0, S.amp * S.f1 * w, S.amp * S.f2 * w};
                 add_point(S.block, i, j, e);
             }
-        stf.push_back(TimeFn{TF_RICKER, 0, {S.fp, S.t0}});
+        items[(size_t)nb * ITEMS_PER_BLOCK + s] = TimeFn{TF_RICKER, 0, {S.fp, S.t0}};
     }
     for (size_t r = 0; r < c->receivers.size(); ++r) {
         const Receiver& Rv = c->receivers[r];
@@ -602,15 +579,18 @@ static sbpe_status build_plan(sbpe_ctx* c) {
     }
     if (c->host_only) return SBPE_OK;
     if (flat.empty()) flat.push_back(Entry{-1, -1, 0, 0, 0.0, 0.0});
-    if (stf.empty()) stf.push_back(TimeFn{TF_ZERO, 0, {0.0, 0.0}});
+    c->nitems = (int)items.size();
     HIPCHECK(c, hipMalloc(&c->d_entries, flat.size() * sizeof(Entry)));
     HIPCHECK(c, hipMemcpy(c->d_entries, flat.data(), flat.size() * sizeof(Entry), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMalloc(&c->d_tile_ranges, tr.size() * sizeof(Range)));
     HIPCHECK(c, hipMemcpy(c->d_tile_ranges, tr.data(), tr.size() * sizeof(Range), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMalloc(&c->d_frame_ranges, fr.size() * sizeof(Range)));
     HIPCHECK(c, hipMemcpy(c->d_frame_ranges, fr.data(), fr.size() * sizeof(Range), hipMemcpyHostToDevice));
-    HIPCHECK(c, hipMalloc(&c->d_src_tf, stf.size() * sizeof(TimeFn)));
-    HIPCHECK(c, hipMemcpy(c->d_src_tf, stf.data(), stf.size() * sizeof(TimeFn), hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMalloc(&c->d_items, items.size() * sizeof(TimeFn)));
+    HIPCHECK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(TimeFn), hipMemcpyHostToDevice));
+    c->tau_cap = 1;
+    HIPCHECK(c, hipMalloc(&c->d_tau, (size_t)c->nitems * 3 * sizeof(double)));
+    HIPCHECK(c, hipMemset(c->d_tau, 0, (size_t)c->nitems * 3 * sizeof(double)));
     HIPCHECK(c, hipMalloc(&c->d_desc, nb * sizeof(BlockDesc)));
     HIPCHECK(c, hipMemcpy(c->d_desc, c->desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice));
     c->npartial = 1024;
@@ -639,17 +619,96 @@ static PassArgs base_args(const sbpe_ctx* c) {
     a.entries = c->d_entries;
     a.tile_ranges = c->d_tile_ranges;
     a.frame_ranges = c->d_frame_ranges;
-    a.src_tf = c->d_src_tf;
+    a.tau = c->d_tau;
     return a;
 }
 
+static hipEvent_t next_event(sbpe_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// sum the elapsed times of all recorded event pairs (synchronises)
+static sbpe_status collect_timing(sbpe_ctx* c) {
+    if (c->ev_used == 0) return SBPE_OK;
+    HIPCHECK(c, hipStreamSynchronize(c->side));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < c->ev_kind.size(); ++k) {
+        float ms = 0.f;
+        HIPCHECK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+        c->t_sum[c->ev_kind[k]] += ms;
+        c->t_cnt[c->ev_kind[k]] += 1;
+    }
+    c->ev_used = 0;
+    c->ev_kind.clear();
+    return SBPE_OK;
+}
+
+// join the two streams: each waits for the work already enqueued on the other
+static sbpe_status join_streams(sbpe_ctx* c) {
+    HIPCHECK(c, hipEventRecord(c->ev_main, c->stream));
+    HIPCHECK(c, hipStreamWaitEvent(c->side, c->ev_main, 0));
+    HIPCHECK(c, hipEventRecord(c->ev_side, c->side));
+    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_side, 0));
+    return SBPE_OK;
+}
+
 static sbpe_status run_pass(sbpe_ctx* c, const PassArgs& a) {
-    const int e = launch_pass(c->dtype, c->order, a, c->total_tiles, c->total_frame_wg, c->stream);
-    if (e != 0) return fail(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+    // launch kinds: 2 * pass index (RK1 = 0, RK2 = 1, APPLY = 2) + (0 interior, 1 frame)
+    const int pk = a.pass == PASS_RK1 ? 0 : a.pass == PASS_RK2 ? 1 : 2;
+    sbpe_status s = join_streams(c);
+    if (s) return s;
+    for (int part = 0; part < 2; ++part) {
+        hipStream_t st = part == 0 ? c->stream : c->side;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            if (c->ev_kind.size() >= 4096) {
+                s = collect_timing(c);
+                if (s) return s;
+            }
+            e0 = next_event(c);
+            e1 = next_event(c);
+            if (!e0 || !e1) return fail(c, SBPE_EHIP, "hipEventCreate failed");
+            HIPCHECK(c, hipEventRecord(e0, st));
+        }
+        const int e = part == 0 ? launch_interior(c->dtype, c->order, a, c->total_tiles, st)
+                                : launch_frame(c->dtype, c->order, a, c->total_frame_wg, st);
+        if (e != 0) return fail(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+        if (c->timing) {
+            HIPCHECK(c, hipEventRecord(e1, st));
+            c->ev_kind.push_back(2 * pk + part);
+        }
+    }
+    return SBPE_OK;
+}
+
+// make the caller's stream wait for everything enqueued on the side stream
+static sbpe_status finish_passes(sbpe_ctx* c) {
+    HIPCHECK(c, hipEventRecord(c->ev_side, c->side));
+    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->ev_side, 0));
     return SBPE_OK;
 }
 
 static bool check_ctx(sbpe_ctx* c) { return c != nullptr; }
+
+// tabulate the time functions of nsteps steps starting at t0 into d_tau
+static sbpe_status fill_tau(sbpe_ctx* c, int nsteps, double t0, double dt) {
+    if (nsteps > c->tau_cap) {
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        (void)hipFree(c->d_tau);
+        c->d_tau = nullptr;
+        if (hipMalloc(&c->d_tau, (size_t)nsteps * c->nitems * 3 * sizeof(double)) != hipSuccess)
+            return fail(c, SBPE_ENOMEM, "time-function table");
+        c->tau_cap = nsteps;
+    }
+    const int e = launch_tau(c->d_items, c->nitems, nsteps, t0, dt, c->d_tau, c->stream);
+    if (e != 0) return fail(c, SBPE_EHIP, std::string("tau launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
 
 static sbpe_status need_gpu(sbpe_ctx* c) {
     if (c->host_only) return fail(c, SBPE_ESTATE, "host-only context");
@@ -689,13 +748,11 @@ sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double b
             delete c;
             return fail(nullptr, SBPE_EHIP, "hipSetDevice failed");
         }
-        std::vector<double> t4((size_t)O4_R0 * O4_W * O4_W), t2((size_t)O2_R0 * O2_W * O2_W);
-        derive_d2_closure(4, t4.data());
-        derive_d2_closure(2, t2.data());
-        const int e = upload_tables(t4.data(), t2.data());
-        if (e != 0) {
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess) {
             delete c;
-            return fail(nullptr, SBPE_EHIP, std::string("table upload: ") + hip_error_string(e));
+            return fail(nullptr, SBPE_EHIP, "stream/event creation failed");
         }
     }
     *out = c;
@@ -718,10 +775,16 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
         (void)hipFree(c->d_entries);
         (void)hipFree(c->d_tile_ranges);
         (void)hipFree(c->d_frame_ranges);
-        (void)hipFree(c->d_src_tf);
+        (void)hipFree(c->d_items);
+        (void)hipFree(c->d_tau);
         (void)hipFree(c->d_rec);
         (void)hipFree(c->d_epart);
         (void)hipFree(c->d_eout);
+        for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+        (void)hipStreamSynchronize(c->side);
+        (void)hipEventDestroy(c->ev_main);
+        (void)hipEventDestroy(c->ev_side);
+        (void)hipStreamDestroy(c->side);
     }
     delete c;
     return SBPE_OK;
@@ -962,15 +1025,22 @@ sbpe_status sbpe_apply(sbpe_ctx_t c, const void* const* u, void* const* a, doubl
         for (int q = 0; q < nb; ++q)
             if (a[b] == u[q]) return fail(c, SBPE_EINVAL, "output aliases an input");
     }
+    if (!homogeneous) {
+        sbpe_status s2 = fill_tau(c, 1, t, 0.0);
+        if (s2) return s2;
+    }
     PassArgs pa = base_args(c);
     pa.pass = PASS_APPLY;
     pa.homogeneous = homogeneous ? 1 : 0;
     pa.t = t;
+    pa.wa[0] = homogeneous ? 0.0 : 1.0;
     for (int b = 0; b < nb; ++b) {
         pa.in[b] = u[b];
         pa.out[b] = a[b];
     }
-    return run_pass(c, pa);
+    sbpe_status s2 = run_pass(c, pa);
+    if (s2) return s2;
+    return finish_passes(c);
 }
 
 sbpe_status sbpe_bind_state(sbpe_ctx_t c, void* const* u, void* const* v, double t) {
@@ -1001,6 +1071,8 @@ static sbpe_status energy_now(sbpe_ctx* c, double* eps) {
         pa.out[b] = c->blocks[b].d_a1;
     }
     sbpe_status s = run_pass(c, pa);
+    if (s) return s;
+    s = finish_passes(c);
     if (s) return s;
     const int e = launch_energy(c->dtype, c->order, c->d_desc, (int)c->blocks.size(), c->d_epart, c->npartial,
                                 c->d_eout, c->stream);
@@ -1052,20 +1124,34 @@ sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
         s = energy_now(c, &e0);
         if (s) return s;
     }
+    if (nsteps > 0) {
+        s = fill_tau(c, nsteps, c->t, dt);
+        if (s) return s;
+    }
     for (int k = 0; k < nsteps; ++k) {
         PassArgs p1 = base_args(c);
         p1.pass = PASS_RK1;
         p1.t = c->t;
         p1.dt = dt;
+        p1.tau = c->d_tau + (size_t)k * c->nitems * 3;
+        p1.wa[0] = 1.0;     // tau(t)
+        p1.wb[1] = 1.0;     // tau(t + dt/2)
         s = run_pass(c, p1);
         if (s) return s;
         PassArgs p2 = p1;
         p2.pass = PASS_RK2;
+        const double w2 = 2.0 / (dt * dt);   // 2/dt^2 (tau(t) - 2 tau(t + dt/2) + tau(t + dt))
+        p2.wa[0] = p2.wa[1] = p2.wa[2] = 0.0;
+        p2.wb[0] = w2;
+        p2.wb[1] = -2.0 * w2;
+        p2.wb[2] = w2;
         p2.rec_out = nrec > 0 ? c->d_rec + (c->rec_steps + k) * slots : nullptr;
         s = run_pass(c, p2);
         if (s) return s;
         c->t += dt;
         if (c->guard_every > 0 && (k + 1) % c->guard_every == 0) {
+            s = finish_passes(c);
+            if (s) return s;
             double e = 0.0;
             s = energy_now(c, &e);
             if (s) return s;
@@ -1079,7 +1165,7 @@ sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
         }
     }
     c->rec_steps += nsteps;
-    return SBPE_OK;
+    return finish_passes(c);
 }
 
 sbpe_status sbpe_get_time(sbpe_ctx_t c, double* t) {
@@ -1096,8 +1182,7 @@ sbpe_status sbpe_read_receivers(sbpe_ctx_t c, double* out, int max_steps, int* n
     const long nrec = (long)c->receivers.size();
     const long n = std::min<long>(c->rec_steps, std::max(max_steps, 0));
     if (nsteps_out) *nsteps_out = (int)n;
-    if (nrec == 0 || n == 0) return SBPE_OK;
-    if (!out) return fail(c, SBPE_EINVAL, "NULL out");
+    if (nrec == 0 || n == 0 || !out) return SBPE_OK;
     std::vector<double> raw(n * nrec * 32);
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     HIPCHECK(c, hipMemcpy(raw.data(), c->d_rec, raw.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1115,6 +1200,51 @@ sbpe_status sbpe_synchronize(sbpe_ctx_t c) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (c->host_only) return SBPE_OK;
     HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_set_kernel_timing(sbpe_ctx_t c, int enable) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (!enable) {
+        s = collect_timing(c);
+        if (s) return s;
+    }
+    c->timing = enable != 0;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_get_kernel_timing(sbpe_ctx_t c, double* ms_avg, int* count) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    s = collect_timing(c);
+    if (s) return s;
+    for (int k = 0; k < 6; ++k) {
+        if (ms_avg) ms_avg[k] = c->t_cnt[k] ? c->t_sum[k] / c->t_cnt[k] : 0.0;
+        if (count) count[k] = c->t_cnt[k];
+        c->t_sum[k] = 0.0;
+        c->t_cnt[k] = 0;
+    }
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_plan_info(sbpe_ctx_t c, long long* info) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->finalized) return fail(c, SBPE_ESTATE, "context not finalized");
+    if (!info) return fail(c, SBPE_EINVAL, "NULL info");
+    const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
+    long long ip = 0, fp = 0;
+    for (const auto& B : c->blocks) {
+        ip += (long long)(B.n1 - 2 * R) * (B.n2 - 2 * R);
+        fp += (long long)B.n1 * B.n2 - (long long)(B.n1 - 2 * R) * (B.n2 - 2 * R);
+    }
+    info[0] = ip;
+    info[1] = fp;
+    info[2] = c->total_tiles;
+    info[3] = c->total_frame_wg;
+    info[4] = R;
     return SBPE_OK;
 }
 

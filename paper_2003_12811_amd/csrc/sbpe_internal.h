@@ -47,10 +47,10 @@ struct FaceDesc {
     double w;          // first norm weight of the face-normal direction, h_a * H^_0
     double pw;         // interface: the partner's first norm weight
     double vsign;      // interface: +1 on the side that owns the jump data order, -1 on the other
-    TimeFn tf;         // time function of g
+    int item_g;        // time-function item of g
+    int item_v;        // time-function item of the interface jump data
     const void* g;     // [2][nf]: traction/Robin: Jhat g / w; displacement: g; or null
     const void* U;     // [4][nf]: Robin Jhat U_JL / w (row-major JL), or null
-    TimeFn vtf;        // time function of the interface jump data
     const void* V;     // [2][nf] displacement jump in this face's order (interface), or null
     const void* Th;    // [2][nf] Jhat Theta / (2 w) in this face's order (interface), or null
 };
@@ -60,7 +60,8 @@ struct BlockDesc {
     double h1, h2;
     const void* coef;   // [NCOEF][n2][n1]
     const void* force;  // [2][n2][n1] J f space part, or null
-    TimeFn ftf;
+    int item_f;         // time-function item of the forcing
+    int pad_f;
     void* u;            // bound displacement [2][n2][n1]
     void* v;            // bound velocity
     void* a1;           // RK workspace
@@ -74,7 +75,7 @@ struct BlockDesc {
 struct Entry {
     int p;        // flat grid index in its block
     int kind;     // 0 source, 1 receiver
-    int id;       // source: index of its time function; receiver: rec * 16 + slot
+    int id;       // source: its time-function item; receiver: rec * 16 + slot
     int pad;
     double c0, c1;  // source: amp dir_J w / H (J f contribution); receiver: weight, unused
 };
@@ -83,12 +84,10 @@ struct Range {
     int beg, end;
 };
 
-struct TimeComb {   // tau_eff = sum_k w[k] tau(t[k])
-    int n;
-    int pad;
-    double t[3];
-    double w[3];
-};
+// Time functions are tabulated per RK4 step by k_tau: tau[(step * nitems + item) * 3 + k]
+// = tau_item(t_step + c_k dt), c = (0, 1/2, 1).  Items: per block 9 (face g x4,
+// face jump data x4, forcing), then one per source.
+constexpr int ITEMS_PER_BLOCK = 9;
 
 constexpr int MAX_APPLY_BLOCKS = 16;
 
@@ -97,28 +96,30 @@ struct PassArgs {
     int nblocks;
     int pass;
     int homogeneous;
-    int pad;
+    int total_tiles;                    // interior workgroups over all blocks
     double t, dt, beta;
+    const double* tau;                  // time-function values of this step [nitems][3]
+    double wa[3], wb[3];                // weights of the tabulated values: first / second evaluation
     const void* in[MAX_APPLY_BLOCKS];   // sbpe_apply operands per block
     void* out[MAX_APPLY_BLOCKS];
     const Entry* entries;
     const Range* tile_ranges;    // per interior workgroup
     const Range* frame_ranges;   // per frame workgroup
-    const TimeFn* src_tf;        // per source
     double* rec_out;             // receiver slots of the current step [nrec*16][2], or null
 };
 
-// interior tile shape of the simple kernel
+// interior tile: one wave of 64 columns marching over TILE_Y rows
 constexpr int TILE_X = 64;
-constexpr int TILE_Y = 4;
+constexpr int TILE_Y = 16;
 constexpr int FRAME_WG = 256;
+constexpr int FRAME_PTS = FRAME_WG / 2;   // frame points per workgroup (two lanes per point)
 
 // host-side launchers (sbpe_kernels.hip)
-int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg,
-                void* stream);
+int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream);
+int launch_frame(int dtype, int order, const PassArgs& a, int total_frame_wg, void* stream);
+int launch_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt, double* tau, void* stream);
 int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
                   int npartial, double* result_dev, void* stream);
-int upload_tables(const double* t4, const double* t2);
 const char* hip_error_string(int code);
 
 }  // namespace sbpe

@@ -1,12 +1,17 @@
 // HIP kernels (gfx950, wave64) of the SBP-SAT anisotropic elastic operator.
 //
 // One right-hand-side evaluation is split by grid region:
-//   * k_interior: points at least Frame<ORD>::R from every face, where all
-//     1-D operators use their repeating interior stencils (Sec. 4.3-4.7);
-//   * k_frame:    the band of width R along the faces, where the boundary
-//     closures of D1 and D2^FC and the SATs of Sec. 5 and 6 act.
+//   * k_march: points at least Frame<ORD>::R from every face, where all 1-D
+//     operators use their repeating interior stencils (Sec. 4.3-4.7).  One
+//     wave owns 64 consecutive columns and marches over TILE_Y rows: input
+//     rows are staged once in an LDS ring (x1 neighbours and the x2 window of
+//     the own column), coefficient windows stay in registers, and the two
+//     mixed terms go through LDS rows of their inner products;
+//   * k_frame: the band of width R along the faces, where the boundary
+//     closures of D1 and D2^FC and the SATs of Sec. 5 and 6 act; one thread
+//     per point, closure rows unrolled from compile-time tables.
 // Both are fused with the two-sweep form of classical RK4 described in
-// sbpe_internal.h, so one RK4 step reads the coefficient fields twice.
+// sbpe_internal.h, so one RK4 step streams the coefficient fields twice.
 //
 // Reference-frame forms used here (all follow from the paper's definitions):
 //   * volume: DD_ik(c_ijkl) u_l = D_11^FC(c_1j1l) u_l + D_22^FC(c_2j2l) u_l
@@ -16,6 +21,8 @@
 //     over both sides at interfaces), from Nanson's formula (eq. nanson)
 //   * J (JH)^{-1} e_f Jhat H_f = (1 / h_1) at the face points (H = H_x1 (x) H_x2)
 //   * H_t^{-1} D_t^T H_t = -D_t + H_t^{-1} (e_N e_N^T - e_0 e_0^T)  (SBP property, Sec. 4)
+// Second differences are formed from differences u_m - u_r first (every row of
+// D2^FC and D1 sums to zero), which keeps FP32 cancellation small.
 #include <hip/hip_runtime.h>
 
 #include "sbpe_internal.h"
@@ -23,23 +30,41 @@
 
 namespace sbpe {
 
-__constant__ double c_d2c4[O4_R0][O4_W][O4_W];
-__constant__ double c_d2c2[O2_R0][O2_W][O2_W];
+// Every field lives in global memory; loads and stores go through
+// address-space-1 pointers so that they compile to global (not flat) accesses,
+// which the compiler can batch freely around LDS traffic.
+#define GLB __attribute__((address_space(1)))
+template <typename T> using gcp = const GLB T*;
+template <typename T> using gp = GLB T*;
+template <typename T>
+__device__ __forceinline__ gcp<T> gc(const void* p) { return (gcp<T>)p; }
+template <typename T>
+__device__ __forceinline__ gp<T> gm(void* p) { return (gp<T>)p; }
+using BlockRef = const GLB BlockDesc&;
+__device__ __forceinline__ BlockRef blk(const PassArgs& A, int b) { return ((const GLB BlockDesc*)A.blocks)[b]; }
+__device__ __forceinline__ const GLB Entry& entry(const PassArgs& A, int e) { return ((const GLB Entry*)A.entries)[e]; }
+__device__ __forceinline__ Range load_range(const Range* base, int k) {
+    const GLB Range& r = ((const GLB Range*)base)[k];
+    Range o;
+    o.beg = r.beg;
+    o.end = r.end;
+    return o;
+}
 
 template <int ORD> struct Op;
 template <> struct Op<4> {
     static constexpr int R0 = O4_R0, W = O4_W, NB = O4_NB, HALF = 2, REACH = 4;
-    __device__ static double d2c(int r, int m, int s) { return c_d2c4[r][m][s]; }
-    __device__ static double d1b(int r, int c) { return O4_D1B[r][c]; }
-    __device__ static double d1i(int k) { return O4_D1I[k]; }
-    __device__ static double hb(int k) { return O4_H[k]; }
+    __host__ __device__ static constexpr double d2c(int r, int m, int s) { return D2T4.t[r][m][s]; }
+    __host__ __device__ static constexpr double d1b(int r, int c) { return O4_D1B[r][c]; }
+    __host__ __device__ static constexpr double d1i(int k) { return O4_D1I[k]; }
+    __host__ __device__ static constexpr double hb(int k) { return O4_H[k]; }
 };
 template <> struct Op<2> {
     static constexpr int R0 = O2_R0, W = O2_W, NB = O2_NB, HALF = 1, REACH = 2;
-    __device__ static double d2c(int r, int m, int s) { return c_d2c2[r][m][s]; }
-    __device__ static double d1b(int r, int c) { return O2_D1B[r][c]; }
-    __device__ static double d1i(int k) { return O2_D1I[k]; }
-    __device__ static double hb(int k) { return O2_H[k]; }
+    __host__ __device__ static constexpr double d2c(int r, int m, int s) { return D2T2.t[r][m][s]; }
+    __host__ __device__ static constexpr double d1b(int r, int c) { return O2_D1B[r][c]; }
+    __host__ __device__ static constexpr double d1i(int k) { return O2_D1I[k]; }
+    __host__ __device__ static constexpr double hb(int k) { return O2_H[k]; }
 };
 
 // dimensionless norm weight of point k on a line of n points
@@ -63,60 +88,76 @@ __device__ __forceinline__ double tfun(const TimeFn& f, double t) {
     }
 }
 
-__device__ __forceinline__ double tcomb(const TimeFn& f, const TimeComb& c) {
-    double s = 0.0;
-    for (int k = 0; k < c.n; ++k) s += c.w[k] * tfun(f, c.t[k]);
-    return s;
+// weights of the three tabulated values tau(t), tau(t + dt/2), tau(t + dt)
+struct W3 {
+    double w0, w1, w2;
+    __device__ bool any() const { return w0 != 0.0 || w1 != 0.0 || w2 != 0.0; }
+};
+__device__ __forceinline__ W3 weights_a(const PassArgs& A) { return W3{A.wa[0], A.wa[1], A.wa[2]}; }
+__device__ __forceinline__ W3 weights_b(const PassArgs& A) { return W3{A.wb[0], A.wb[1], A.wb[2]}; }
+
+// weighted time-function value of an item in this step
+__device__ __forceinline__ double tval(const PassArgs& A, int item, const W3& w) {
+    const GLB double* t = (const GLB double*)A.tau + 3 * item;
+    return w.w0 * t[0] + w.w1 * t[1] + w.w2 * t[2];
 }
 
 template <typename T>
-__device__ __forceinline__ const T* field_ptr(const PassArgs& A, int b, int fld) {
-    const BlockDesc& B = A.blocks[b];
+__device__ __forceinline__ gcp<T> field_ptr(const PassArgs& A, int b, int fld) {
+    BlockRef B = blk(A, b);
     switch (fld) {
-        case FLD_U: return static_cast<const T*>(B.u);
-        case FLD_V: return static_cast<const T*>(B.v);
-        case FLD_A1: return static_cast<const T*>(B.a1);
-        case FLD_A2: return static_cast<const T*>(B.a2);
-        default: return static_cast<const T*>(A.in[b]);
+        case FLD_U: return gc<T>(B.u);
+        case FLD_V: return gc<T>(B.v);
+        case FLD_A1: return gc<T>(B.a1);
+        case FLD_A2: return gc<T>(B.a2);
+        default: return gc<T>(A.in[b]);
     }
 }
 
 // ------------------------------------------------------------ 1-D rows
-// Row r of D1 on a line of n points: start index, up to 6 weights (times h).
-template <int ORD>
-__device__ __forceinline__ int d1_entries(int r, int n, int& start, double w[6]) {
+// D1 row r of a line of n points: calls f(index, weight * h) for its nonzero
+// entries; closure rows are unrolled from the compile-time tables.
+template <int ORD, int RR, typename F>
+__device__ __forceinline__ void d1_closure_foreach(bool lo, int n, F&& f) {
     using O = Op<ORD>;
-    if (r < O::NB) {
-        start = 0;
-        for (int c = 0; c < 6; ++c) w[c] = O::d1b(r, c);
-        return 6;
-    }
-    if (r > n - 1 - O::NB) {
-        const int rr = n - 1 - r;
-        start = n - 6;
-        for (int k = 0; k < 6; ++k) w[k] = -O::d1b(rr, 5 - k);
-        return 6;
-    }
-    start = r - O::HALF;
-    for (int k = 0; k < 2 * O::HALF + 1; ++k) w[k] = O::d1i(k);
-    return 2 * O::HALF + 1;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        if (O::d1b(RR, c) != 0.0) f(lo ? c : n - 1 - c, lo ? O::d1b(RR, c) : -O::d1b(RR, c));
 }
 
-// h (D1 u)_r on a line with element stride `st`
+template <int ORD, int RR, typename F>
+__device__ __forceinline__ void d1_dispatch(int rr, bool lo, int n, F&& f) {
+    if constexpr (RR < Op<ORD>::NB) {
+        if (rr == RR) d1_closure_foreach<ORD, RR>(lo, n, f);
+        else d1_dispatch<ORD, RR + 1>(rr, lo, n, f);
+    }
+}
+
+template <int ORD, typename F>
+__device__ __forceinline__ void d1_foreach(int r, int n, F&& f) {
+    using O = Op<ORD>;
+    if (r >= O::NB && r <= n - 1 - O::NB) {
+#pragma unroll
+        for (int k = -O::HALF; k <= O::HALF; ++k)
+            if (k != 0) f(r + k, O::d1i(k + O::HALF));
+        return;
+    }
+    const bool lo = r < O::NB;
+    d1_dispatch<ORD, 0>(lo ? r : n - 1 - r, lo, n, f);
+}
+
+// h (D1 u)_r on a line with element stride st (difference form)
 template <typename T, int ORD>
-__device__ T d1_line(const T* u, long st, int r, int n) {
-    int s0;
-    double w[6];
-    const int len = d1_entries<ORD>(r, n, s0, w);
+__device__ __forceinline__ T d1_line(gcp<T> u, long st, int r, int n) {
+    const T ur = u[(long)r * st];
     T acc = 0;
-    for (int k = 0; k < len; ++k)
-        if (w[k] != 0.0) acc += static_cast<T>(w[k]) * u[(long)(s0 + k) * st];
+    d1_foreach<ORD>(r, n, [&](int k, double w) { acc += static_cast<T>(w) * (u[(long)k * st] - ur); });
     return acc;
 }
 
 // h^2 (D2^FC(b) u)_r at an interior row; b, u point at the row.
-template <typename T, int ORD>
-__device__ __forceinline__ T d2_interior(const T* b, const T* u, long st) {
+template <typename T, int ORD, typename PB, typename PU>
+__device__ __forceinline__ T d2_interior(PB b, PU u, long st) {
     const T u0 = u[0];
     if constexpr (ORD == 4) {
         const T bm2 = b[-2 * st], bm1 = b[-st], b0 = b[0], bp1 = b[st], bp2 = b[2 * st];
@@ -132,40 +173,57 @@ __device__ __forceinline__ T d2_interior(const T* b, const T* u, long st) {
     }
 }
 
-// h^2 (D2^FC(b) u)_r on a line of n points; b, u point at index 0 of the line.
-template <typename T, int ORD>
-__device__ T d2_line(const T* b, const T* u, long st, int r, int n) {
+// closure row RR (from the lower end, or mirrored at the upper end)
+template <typename T, int ORD, int RR>
+__device__ __forceinline__ T d2_closure(gcp<T> b, gcp<T> u, long st, bool lo, int n) {
     using O = Op<ORD>;
-    if (r >= O::R0 && r <= n - 1 - O::R0) return d2_interior<T, ORD>(b + r * st, u + r * st, st);
-    const bool lo = r < O::R0;
-    const int rr = lo ? r : n - 1 - r;
-    const T ur = u[(long)r * st];
+    const T ur = u[(long)(lo ? RR : n - 1 - RR) * st];
     T acc = 0;
+#pragma unroll
     for (int m = 0; m < O::W; ++m) {
-        const long pm = lo ? m : n - 1 - m;
+        if (m == RR) continue;
         T cf = 0;
         bool any = false;
+#pragma unroll
         for (int s = 0; s < O::W; ++s) {
-            const double tv = O::d2c(rr, m, s);
-            if (tv != 0.0) {
-                cf += static_cast<T>(tv) * b[(long)(lo ? s : n - 1 - s) * st];
+            if (O::d2c(RR, m, s) != 0.0) {
+                cf += static_cast<T>(O::d2c(RR, m, s)) * b[(long)(lo ? s : n - 1 - s) * st];
                 any = true;
             }
         }
-        if (any) acc += cf * (u[pm * st] - ur);
+        if (any) acc += cf * (u[(long)(lo ? m : n - 1 - m) * st] - ur);
     }
     return acc;
+}
+
+template <typename T, int ORD, int RR>
+__device__ __forceinline__ T d2_dispatch(int rr, gcp<T> b, gcp<T> u, long st, bool lo, int n) {
+    if constexpr (RR < Op<ORD>::R0) {
+        if (rr == RR) return d2_closure<T, ORD, RR>(b, u, st, lo, n);
+        return d2_dispatch<T, ORD, RR + 1>(rr, b, u, st, lo, n);
+    } else {
+        return T(0);
+    }
+}
+
+// h^2 (D2^FC(b) u)_r on a line of n points; b, u point at index 0 of the line.
+template <typename T, int ORD>
+__device__ __forceinline__ T d2_line(gcp<T> b, gcp<T> u, long st, int r, int n) {
+    using O = Op<ORD>;
+    if (r >= O::R0 && r <= n - 1 - O::R0) return d2_interior<T, ORD>(b + r * st, u + r * st, st);
+    const bool lo = r < O::R0;
+    return d2_dispatch<T, ORD, 0>(lo ? r : n - 1 - r, b, u, st, lo, n);
 }
 
 // -------------------------------------------------- volume at one point
 // DD_ik(c_ijkl) u_l at (i, j) with boundary-aware 1-D rows (frame points).
 template <typename T, int ORD>
-__device__ void volume_general(const BlockDesc& B, const T* u, int i, int j, T& r0, T& r1) {
+__device__ __forceinline__ void volume_general(BlockRef B, gcp<T> u, int i, int j, T& r0, T& r1) {
     const int n1 = B.n1, n2 = B.n2;
     const long np = (long)n1 * n2;
-    const T* c = static_cast<const T*>(B.coef);
-    const T* u0 = u;
-    const T* u1 = u + np;
+    gcp<T> c = gc<T>(B.coef);
+    gcp<T> u0 = u;
+    gcp<T> u1 = u + np;
     const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
     const long rj = (long)j * n1;
     // x1 narrow, line j
@@ -181,36 +239,28 @@ __device__ void volume_general(const BlockDesc& B, const T* u, int i, int j, T& 
     r0 = (a00 + a01) * ih1 * ih1 + (b00 + b01) * ih2 * ih2;
     r1 = (a10 + a11) * ih1 * ih1 + (b10 + b11) * ih2 * ih2;
     // D_1 (M D_2 u), M_jl = c_1j2l
-    int s0;
-    double w[6];
-    int len = d1_entries<ORD>(i, n1, s0, w);
     T g0 = 0, g1 = 0;
-    for (int k = 0; k < len; ++k) {
-        if (w[k] == 0.0) continue;
-        const int ii = s0 + k;
+    d1_foreach<ORD>(i, n1, [&](int ii, double w) {
         const T w20 = d1_line<T, ORD>(u0 + ii, n1, j, n2);
         const T w21 = d1_line<T, ORD>(u1 + ii, n1, j, n2);
         const long q = rj + ii;
         const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
         const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
-        g0 += static_cast<T>(w[k]) * (m00 * w20 + m01 * w21);
-        g1 += static_cast<T>(w[k]) * (m10 * w20 + m11 * w21);
-    }
+        g0 += static_cast<T>(w) * (m00 * w20 + m01 * w21);
+        g1 += static_cast<T>(w) * (m10 * w20 + m11 * w21);
+    });
     // D_2 (M^T D_1 u), c_2j1l = c_1l2j
-    len = d1_entries<ORD>(j, n2, s0, w);
     T e0 = 0, e1 = 0;
-    for (int k = 0; k < len; ++k) {
-        if (w[k] == 0.0) continue;
-        const int jj = s0 + k;
+    d1_foreach<ORD>(j, n2, [&](int jj, double w) {
         const long rjj = (long)jj * n1;
         const T w10 = d1_line<T, ORD>(u0 + rjj, 1, i, n1);
         const T w11 = d1_line<T, ORD>(u1 + rjj, 1, i, n1);
         const long q = rjj + i;
         const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
         const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
-        e0 += static_cast<T>(w[k]) * (m00 * w10 + m10 * w11);
-        e1 += static_cast<T>(w[k]) * (m01 * w10 + m11 * w11);
-    }
+        e0 += static_cast<T>(w) * (m00 * w10 + m10 * w11);
+        e1 += static_cast<T>(w) * (m01 * w10 + m11 * w11);
+    });
     const T ihh = ih1 * ih2;
     r0 += (g0 + e0) * ihh;
     r1 += (g1 + e1) * ihh;
@@ -221,7 +271,7 @@ struct FacePt {
     int i, j;   // grid point
 };
 
-__device__ __forceinline__ FacePt face_point(const BlockDesc& B, int f, int t) {
+__device__ __forceinline__ FacePt face_point(BlockRef B, int f, int t) {
     const int a = f >> 1, s = f & 1;
     FacePt q;
     if (a == 0) {
@@ -236,7 +286,7 @@ __device__ __forceinline__ FacePt face_point(const BlockDesc& B, int f, int t) {
 
 // normal-narrow matrix N_a (c_ajal) and mixed matrix M (c_1j2l) at flat index q
 template <typename T>
-__device__ __forceinline__ void coef_mats(const T* c, long np, long q, int a, T N[2][2], T M[2][2]) {
+__device__ __forceinline__ void coef_mats(gcp<T> c, long np, long q, int a, T N[2][2], T M[2][2]) {
     if (a == 0) {
         N[0][0] = c[K_C1111 * np + q];
         N[0][1] = N[1][0] = c[K_C1112 * np + q];
@@ -254,14 +304,14 @@ __device__ __forceinline__ void coef_mats(const T* c, long np, long q, int a, T 
 
 // Jhat T_jl u_l = nu_a c_ajkl D_k u_l at point t of face f
 template <typename T, int ORD>
-__device__ void traction_at(const BlockDesc& B, const T* u, int f, int t, T& tr0, T& tr1) {
+__device__ __forceinline__ void traction_at(BlockRef B, gcp<T> u, int f, int t, T& tr0, T& tr1) {
     const int n1 = B.n1, n2 = B.n2;
     const long np = (long)n1 * n2;
     const int a = f >> 1;
     const T nu = (f & 1) ? T(1) : T(-1);
     const FacePt q = face_point(B, f, t);
     const long p = (long)q.j * n1 + q.i;
-    const T* c = static_cast<const T*>(B.coef);
+    gcp<T> c = gc<T>(B.coef);
     T d1[2], d2[2];
     for (int l = 0; l < 2; ++l) {
         d1[l] = d1_line<T, ORD>(u + l * np + (long)q.j * n1, 1, q.i, n1) * T(1.0 / B.h1);
@@ -282,20 +332,20 @@ __device__ void traction_at(const BlockDesc& B, const T* u, int f, int t, T& tr0
 //   HOM:  field on this face (minus the partner's field at an interface)
 //   DATA: -tau g (displacement) or -vsign tau V (interface)
 template <typename T, bool DATA>
-__device__ __forceinline__ void face_delta(const PassArgs& A, int b, int f, int t, int fld,
-                                           const TimeComb& tc, T& d0, T& d1) {
-    const BlockDesc& B = A.blocks[b];
-    const FaceDesc& F = B.face[f];
+__device__ __forceinline__ void face_delta(const PassArgs& A, int b, int f, int t, int fld, const W3& tc, T& d0,
+                                           T& d1) {
+    BlockRef B = blk(A, b);
+    const GLB FaceDesc& F = B.face[f];
     const long np = (long)B.n1 * B.n2;
     if (!DATA) {
-        const T* u = field_ptr<T>(A, b, fld);
+        gcp<T> u = field_ptr<T>(A, b, fld);
         const FacePt q = face_point(B, f, t);
         const long p = (long)q.j * B.n1 + q.i;
         d0 = u[p];
         d1 = u[np + p];
         if (F.kind == BC_INTERFACE) {
-            const BlockDesc& P = A.blocks[F.partner];
-            const T* v = field_ptr<T>(A, F.partner, fld);
+            BlockRef P = blk(A, F.partner);
+            gcp<T> v = field_ptr<T>(A, F.partner, fld);
             const int tp = F.reversed ? F.nf - 1 - t : t;
             const FacePt qp = face_point(P, F.pface, tp);
             const long pp = (long)qp.j * P.n1 + qp.i;
@@ -307,13 +357,13 @@ __device__ __forceinline__ void face_delta(const PassArgs& A, int b, int f, int 
         d0 = 0;
         d1 = 0;
         if (F.kind == BC_DISPLACEMENT && F.g) {
-            const T tau = static_cast<T>(tcomb(F.tf, tc));
-            const T* g = static_cast<const T*>(F.g);
+            const T tau = static_cast<T>(tval(A, F.item_g, tc));
+            gcp<T> g = gc<T>(F.g);
             d0 = -tau * g[t];
             d1 = -tau * g[F.nf + t];
         } else if (F.kind == BC_INTERFACE && F.V) {
-            const T tau = static_cast<T>(F.vsign * tcomb(F.vtf, tc));
-            const T* V = static_cast<const T*>(F.V);
+            const T tau = static_cast<T>(F.vsign * tval(A, F.item_v, tc));
+            gcp<T> V = gc<T>(F.V);
             d0 = -tau * V[t];
             d1 = -tau * V[F.nf + t];
         }
@@ -324,15 +374,14 @@ __device__ __forceinline__ void face_delta(const PassArgs& A, int b, int f, int 
 // normal, t = index along the face).  DATA selects the data part (time
 // combination tc) instead of the homogeneous part acting on field `fld`.
 template <typename T, int ORD, bool DATA>
-__device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld,
-                         const TimeComb& tc, T& r0, T& r1) {
+__device__ __forceinline__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld, const W3& tc, T& r0, T& r1) {
     using O = Op<ORD>;
-    const BlockDesc& B = A.blocks[b];
+    BlockRef B = blk(A, b);
     const double beta = A.beta;
-    const FaceDesc& F = B.face[f];
+    const GLB FaceDesc& F = B.face[f];
     const int a = f >> 1;
     const long np = (long)B.n1 * B.n2;
-    const T* c = static_cast<const T*>(B.coef);
+    gcp<T> c = gc<T>(B.coef);
     const T nu = (f & 1) ? T(1) : T(-1);
     const double ha = a == 0 ? B.h1 : B.h2;
     const int na = a == 0 ? B.n1 : B.n2;
@@ -343,13 +392,13 @@ __device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld
     if (F.kind == BC_TRACTION || F.kind == BC_ROBIN) {
         if (dn != 0) return;
         if (!DATA) {
-            const T* u = field_ptr<T>(A, b, fld);
+            gcp<T> u = field_ptr<T>(A, b, fld);
             T tr0, tr1;
             traction_at<T, ORD>(B, u, f, t, tr0, tr1);
             r0 -= iw * tr0;
             r1 -= iw * tr1;
             if (F.kind == BC_ROBIN && F.U) {
-                const T* U = static_cast<const T*>(F.U);
+                gcp<T> U = gc<T>(F.U);
                 const FacePt q = face_point(B, f, t);
                 const long p = (long)q.j * B.n1 + q.i;
                 const T x0 = u[p], x1 = u[np + p];
@@ -357,8 +406,8 @@ __device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld
                 r1 -= U[2 * F.nf + t] * x0 + U[3 * F.nf + t] * x1;
             }
         } else if (F.g) {
-            const T tau = static_cast<T>(tcomb(F.tf, tc));
-            const T* g = static_cast<const T*>(F.g);
+            const T tau = static_cast<T>(tval(A, F.item_g, tc));
+            gcp<T> g = gc<T>(F.g);
             r0 += tau * g[t];
             r1 += tau * g[F.nf + t];
         }
@@ -383,20 +432,12 @@ __device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld
     if (dn != 0) return;
     // tangential part: (1/w) (H_t^{-1} D_t^T H_t qv)(t), qv = nu c_altj delta_l
     {
-        int s0;
-        double w[6];
-        const int len = d1_entries<ORD>(t, nt, s0, w);
-        T dq0 = 0, dq1 = 0, qe0 = 0, qe1 = 0;
-        for (int k = 0; k < len; ++k) {
-            const int tt = s0 + k;
-            const bool endp = (t == 0 && tt == 0) || (t == nt - 1 && tt == nt - 1);
-            if (w[k] == 0.0 && !endp) continue;
+        auto qv = [&](int tt, T& q0, T& q1) {
             T e0, e1;
             face_delta<T, DATA>(A, b, f, tt, fld, tc, e0, e1);
             const FacePt qq = face_point(B, f, tt);
             T Nq[2][2], Mq[2][2];
             coef_mats(c, np, (long)qq.j * B.n1 + qq.i, a, Nq, Mq);
-            T q0, q1;
             if (a == 0) {   // c_1l2j = M_lj
                 q0 = nu * (Mq[0][0] * e0 + Mq[1][0] * e1);
                 q1 = nu * (Mq[0][1] * e0 + Mq[1][1] * e1);
@@ -404,24 +445,27 @@ __device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld
                 q0 = nu * (Mq[0][0] * e0 + Mq[0][1] * e1);
                 q1 = nu * (Mq[1][0] * e0 + Mq[1][1] * e1);
             }
-            dq0 += static_cast<T>(w[k]) * q0;
-            dq1 += static_cast<T>(w[k]) * q1;
-            if (tt == t) {
-                qe0 = q0;
-                qe1 = q1;
-            }
-        }
+        };
+        T qt0, qt1;
+        qv(t, qt0, qt1);
+        T dq0 = 0, dq1 = 0;
+        d1_foreach<ORD>(t, nt, [&](int tt, double w) {
+            T q0, q1;
+            qv(tt, q0, q1);
+            dq0 += static_cast<T>(w) * (q0 - qt0);
+            dq1 += static_cast<T>(w) * (q1 - qt1);
+        });
         const T iht = T(1.0 / ht);
         T s0v = -dq0 * iht, s1v = -dq1 * iht;
         if (t == 0) {
             const T ih0 = T(1.0 / (ht * hnorm<ORD>(0, nt)));
-            s0v -= qe0 * ih0;
-            s1v -= qe1 * ih0;
+            s0v -= qt0 * ih0;
+            s1v -= qt1 * ih0;
         }
         if (t == nt - 1) {
             const T ihN = T(1.0 / (ht * hnorm<ORD>(nt - 1, nt)));
-            s0v += qe0 * ihN;
-            s1v += qe1 * ihN;
+            s0v += qt0 * ihN;
+            s1v += qt1 * ihN;
         }
         r0 += half * iw * s0v;
         r1 += half * iw * s1v;
@@ -432,12 +476,12 @@ __device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld
         r0 -= pen * (N[0][0] * d0 + N[0][1] * d1);
         r1 -= pen * (N[1][0] * d0 + N[1][1] * d1);
     } else {
-        const BlockDesc& P = A.blocks[F.partner];
+        BlockRef P = blk(A, F.partner);
         const int tp = F.reversed ? F.nf - 1 - t : t;
         const FacePt qp = face_point(P, F.pface, tp);
         const long npp = (long)P.n1 * P.n2;
         T Np[2][2], Mp[2][2];
-        coef_mats(static_cast<const T*>(P.coef), npp, (long)qp.j * P.n1 + qp.i, F.pface >> 1, Np, Mp);
+        coef_mats(gc<T>(P.coef), npp, (long)qp.j * P.n1 + qp.i, F.pface >> 1, Np, Mp);
         const T ipw = T(1.0 / F.pw);
         const T qf = static_cast<T>(beta * 2.0 * 0.25);
         T Z[2][2];
@@ -453,8 +497,8 @@ __device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld
             r0 -= T(0.5) * iw * (tu0 + tv0);
             r1 -= T(0.5) * iw * (tu1 + tv1);
         } else if (F.Th) {
-            const T tau = static_cast<T>(tcomb(F.vtf, tc));
-            const T* Th = static_cast<const T*>(F.Th);
+            const T tau = static_cast<T>(tval(A, F.item_v, tc));
+            gcp<T> Th = gc<T>(F.Th);
             r0 += tau * Th[t];
             r1 += tau * Th[F.nf + t];
         }
@@ -463,82 +507,60 @@ __device__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld
 
 // all SAT contributions of the four faces at (i, j)
 template <typename T, int ORD, bool DATA>
-__device__ void sat_point(const PassArgs& A, int b, int i, int j, int fld, const TimeComb& tc, T& r0, T& r1) {
+__device__ __forceinline__ void sat_point(const PassArgs& A, int b, int i, int j, int fld, const W3& tc, T& r0, T& r1) {
     using O = Op<ORD>;
-    const BlockDesc& B = A.blocks[b];
-    const int dist[4] = {i, B.n1 - 1 - i, j, B.n2 - 1 - j};
-    for (int f = 0; f < 4; ++f) {
-        const int dn = dist[f];
-        if (dn >= O::REACH) continue;
-        const int t = (f < 2) ? j : i;
-        face_sat<T, ORD, DATA>(A, b, f, dn, t, fld, tc, r0, r1);
-    }
+    BlockRef B = blk(A, b);
+    const int n1 = B.n1, n2 = B.n2;
+    if (i < O::REACH) face_sat<T, ORD, DATA>(A, b, 0, i, j, fld, tc, r0, r1);
+    if (n1 - 1 - i < O::REACH) face_sat<T, ORD, DATA>(A, b, 1, n1 - 1 - i, j, fld, tc, r0, r1);
+    if (j < O::REACH) face_sat<T, ORD, DATA>(A, b, 2, j, i, fld, tc, r0, r1);
+    if (n2 - 1 - j < O::REACH) face_sat<T, ORD, DATA>(A, b, 3, n2 - 1 - j, i, fld, tc, r0, r1);
 }
 
-// forcing and sources at flat point p for a time combination
+// sources (and, in the frame, the forcing) at flat point p
 template <typename T>
-__device__ __forceinline__ void point_data(const BlockDesc& B, long p, const PassArgs& A, const Range& rg,
-                                           const TimeComb& tc, T& r0, T& r1) {
-    if (B.force) {
-        const T* F = static_cast<const T*>(B.force);
-        const T tau = static_cast<T>(tcomb(B.ftf, tc));
-        r0 += tau * F[p];
-        r1 += tau * F[(long)B.n1 * B.n2 + p];
-    }
+__device__ __forceinline__ void point_sources(const PassArgs& A, const Range& rg, long p, const W3& tc, T& r0, T& r1) {
     for (int e = rg.beg; e < rg.end; ++e) {
-        const Entry& E = A.entries[e];
+        const GLB Entry& E = entry(A, e);
         if (E.kind == 0 && E.p == p) {
-            const double tau = tcomb(A.src_tf[E.id], tc);
+            const double tau = tval(A, E.id, tc);
             r0 += static_cast<T>(E.c0 * tau);
             r1 += static_cast<T>(E.c1 * tau);
         }
     }
 }
 
-__device__ __forceinline__ TimeComb comb1(double t, double w) {
-    TimeComb c;
-    c.n = 1;
-    c.pad = 0;
-    c.t[0] = t;
-    c.w[0] = w;
-    c.t[1] = c.t[2] = 0.0;
-    c.w[1] = c.w[2] = 0.0;
-    return c;
-}
-
-// combination 2/dt^2 (tau(t) - 2 tau(t + dt/2) + tau(t + dt)) used by the second sweep
-__device__ __forceinline__ TimeComb comb_rk2(double t, double dt) {
-    TimeComb c;
-    c.n = 3;
-    c.pad = 0;
-    const double s = 2.0 / (dt * dt);
-    c.t[0] = t;
-    c.t[1] = t + 0.5 * dt;
-    c.t[2] = t + dt;
-    c.w[0] = s;
-    c.w[1] = -2.0 * s;
-    c.w[2] = s;
-    return c;
+template <typename T>
+__device__ __forceinline__ void point_data(BlockRef B, long p, const PassArgs& A, const Range& rg, const W3& tc,
+                                           T& r0, T& r1) {
+    if (B.force) {
+        gcp<T> F = gc<T>(B.force);
+        const T tau = static_cast<T>(tval(A, B.item_f, tc));
+        r0 += tau * F[p];
+        r1 += tau * F[(long)B.n1 * B.n2 + p];
+    }
+    point_sources<T>(A, rg, p, tc, r0, r1);
 }
 
 // Given L f0 (l0), L f1 (l1) and the data sums of the two evaluations at p,
 // write the pass outputs (see the pass definitions in sbpe_internal.h).
+// A1, A2 are the stage values at p in the second sweep.
 template <typename T>
-__device__ __forceinline__ void finish_point(const PassArgs& A, int b, long p, T irho,
-                                             T l00, T l01, T l10, T l11, T da0, T da1, T db0, T db1,
+__device__ __forceinline__ void finish_point(const PassArgs& A, int b, long p, T irho, T l00, T l01, T l10, T l11,
+                                             T da0, T da1, T db0, T db1, T A10, T A11, T A20, T A21,
                                              const Range& rg) {
-    const BlockDesc& B = A.blocks[b];
+    BlockRef B = blk(A, b);
     const long np = (long)B.n1 * B.n2;
     if (A.pass == PASS_APPLY) {
-        T* o = static_cast<T*>(A.out[b]);
+        gp<T> o = gm<T>(A.out[b]);
         o[p] = irho * (l00 + da0);
         o[np + p] = irho * (l01 + da1);
         return;
     }
     const T dt = static_cast<T>(A.dt);
-    T* a1 = static_cast<T*>(B.a1);
-    T* a2 = static_cast<T*>(B.a2);
     if (A.pass == PASS_RK1) {
+        gp<T> a1 = gm<T>(B.a1);
+        gp<T> a2 = gm<T>(B.a2);
         const T hdt = T(0.5) * dt;
         a1[p] = irho * (l00 + da0);
         a1[np + p] = irho * (l01 + da1);
@@ -547,14 +569,15 @@ __device__ __forceinline__ void finish_point(const PassArgs& A, int b, long p, T
         return;
     }
     // PASS_RK2
-    T* u = static_cast<T*>(B.u);
-    T* v = static_cast<T*>(B.v);
+    gp<T> u = gm<T>(B.u);
+    gp<T> v = gm<T>(B.v);
     const T dt2 = dt * dt;
     const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
     T un[2];
+#pragma unroll
     for (int cmp = 0; cmp < 2; ++cmp) {
         const long q = cmp * np + p;
-        const T A1 = a1[q], A2 = a2[q];
+        const T A1 = cmp ? A11 : A10, A2 = cmp ? A21 : A20;
         const T L1 = cmp ? l01 : l00;
         const T L2 = cmp ? l11 : l10;
         const T D2 = cmp ? db1 : db0;
@@ -566,11 +589,12 @@ __device__ __forceinline__ void finish_point(const PassArgs& A, int b, long p, T
         v[q] = vo + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4);
     }
     if (A.rec_out) {
+        gp<double> ro = gm<double>(A.rec_out);
         for (int e = rg.beg; e < rg.end; ++e) {
-            const Entry& E = A.entries[e];
+            const GLB Entry& E = entry(A, e);
             if (E.kind == 1 && E.p == p) {
-                A.rec_out[2 * E.id] = E.c0 * static_cast<double>(un[0]);
-                A.rec_out[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);
+                ro[2 * E.id] = E.c0 * static_cast<double>(un[0]);
+                ro[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);
             }
         }
     }
@@ -579,178 +603,492 @@ __device__ __forceinline__ void finish_point(const PassArgs& A, int b, long p, T
 __device__ __forceinline__ int find_block(const PassArgs& A, int wg, bool frame) {
     int b = 0;
     for (int k = 1; k < A.nblocks; ++k) {
-        const int beg = frame ? A.blocks[k].frame_beg : A.blocks[k].tile_beg;
+        const int beg = frame ? blk(A, k).frame_beg : blk(A, k).tile_beg;
         if (wg >= beg) b = k;
     }
     return b;
 }
 
 // ---------------------------------------------------------------- frame
+// Two lanes per frame point: in the RK sweeps lane s evaluates L and the data
+// of field s (u / v, or A1 / A2); for sbpe_apply lane 0 evaluates L and lane 1
+// the data.  The partial results are exchanged between the lane pair and lane
+// s writes component s of the outputs.
 template <typename T, int ORD>
 __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     constexpr int R = Frame<ORD>::R;
     const int wg = blockIdx.x;
     const int b = find_block(A, wg, true);
-    const BlockDesc& B = A.blocks[b];
-    const int k = (wg - B.frame_beg) * FRAME_WG + threadIdx.x;
-    const Range rg = A.frame_ranges[wg];
-    if (k >= B.frame_n) return;
+    BlockRef B = blk(A, b);
+    const int sub = threadIdx.x & 1;
+    const int k = (wg - B.frame_beg) * FRAME_PTS + (threadIdx.x >> 1);
+    const Range rg = load_range(A.frame_ranges, wg);
     const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const bool valid = k < B.frame_n;
+    const int kk0 = valid ? k : 0;
     int i, j;
-    if (k < R * n1) {
-        j = k / n1;
-        i = k - j * n1;
-    } else if (k < 2 * R * n1) {
-        const int kk = k - R * n1;
+    if (kk0 < R * n1) {
+        j = kk0 / n1;
+        i = kk0 - j * n1;
+    } else if (kk0 < 2 * R * n1) {
+        const int kk = kk0 - R * n1;
         j = n2 - R + kk / n1;
         i = kk % n1;
     } else {
-        const int kk = k - 2 * R * n1;
+        const int kk = kk0 - 2 * R * n1;
         const int row = kk / (2 * R), cc = kk % (2 * R);
         j = R + row;
         i = cc < R ? cc : n1 - 2 * R + cc;
     }
     const long p = (long)j * n1 + i;
-    const T irho = static_cast<const T*>(B.coef)[(long)K_IRHO * n1 * n2 + p];
-    const TimeComb none = comb1(0.0, 0.0);
-    int f0, f1;
-    TimeComb ca, cb;
+    const W3 none{0.0, 0.0, 0.0};
+    const W3 ca = weights_a(A), cb = weights_b(A);
+    T l0 = 0, l1 = 0, d0 = 0, d1 = 0;
+    if (valid) {
+        if (A.pass == PASS_APPLY) {
+            if (sub == 0) {
+                volume_general<T, ORD>(B, field_ptr<T>(A, b, FLD_IN), i, j, l0, l1);
+                sat_point<T, ORD, false>(A, b, i, j, FLD_IN, none, l0, l1);
+            } else if (ca.any()) {
+                sat_point<T, ORD, true>(A, b, i, j, FLD_IN, ca, d0, d1);
+                point_data<T>(B, p, A, rg, ca, d0, d1);
+            }
+        } else {
+            const int fld = A.pass == PASS_RK1 ? (sub ? FLD_V : FLD_U) : (sub ? FLD_A2 : FLD_A1);
+            volume_general<T, ORD>(B, field_ptr<T>(A, b, fld), i, j, l0, l1);
+            sat_point<T, ORD, false>(A, b, i, j, fld, none, l0, l1);
+            const W3 cw = sub ? cb : ca;
+            if (cw.any()) {
+                sat_point<T, ORD, true>(A, b, i, j, fld, cw, d0, d1);
+                point_data<T>(B, p, A, rg, cw, d0, d1);
+            }
+        }
+    }
+    // exchange with the partner lane
+    const T ol0 = __shfl_xor(l0, 1), ol1 = __shfl_xor(l1, 1);
+    const T od0 = __shfl_xor(d0, 1), od1 = __shfl_xor(d1, 1);
+    if (!valid) return;
+    const T irho = gc<T>(B.coef)[(long)K_IRHO * np + p];
+    const long q = (long)sub * np + p;   // component written by this lane
     if (A.pass == PASS_APPLY) {
-        f0 = FLD_IN;
-        f1 = FLD_IN;
-        ca = comb1(A.t, A.homogeneous ? 0.0 : 1.0);
-        cb = none;
-    } else if (A.pass == PASS_RK1) {
-        f0 = FLD_U;
-        f1 = FLD_V;
-        ca = comb1(A.t, 1.0);
-        cb = comb1(A.t + 0.5 * A.dt, 1.0);
-    } else {
-        f0 = FLD_A1;
-        f1 = FLD_A2;
-        ca = none;
-        cb = comb_rk2(A.t, A.dt);
+        // lane 0 holds L, lane 1 the data
+        const T L = sub ? ol1 : l0;
+        const T D = sub ? d1 : od0;
+        gm<T>(A.out[b])[q] = irho * (L + D);
+        return;
     }
-    T l00, l01, l10 = 0, l11 = 0;
-    volume_general<T, ORD>(B, field_ptr<T>(A, b, f0), i, j, l00, l01);
-    sat_point<T, ORD, false>(A, b, i, j, f0, none, l00, l01);
-    if (A.pass != PASS_APPLY) {
-        volume_general<T, ORD>(B, field_ptr<T>(A, b, f1), i, j, l10, l11);
-        sat_point<T, ORD, false>(A, b, i, j, f1, none, l10, l11);
+    // field 0 (lane 0) and field 1 (lane 1) results, component sub
+    const T La = sub ? ol1 : l0;     // L f0, component sub
+    const T Lb = sub ? l1 : ol0;     // L f1, component sub
+    const T Da = sub ? od1 : d0;
+    const T Db = sub ? d1 : od0;
+    const T dt = static_cast<T>(A.dt);
+    if (A.pass == PASS_RK1) {
+        gm<T>(B.a1)[q] = irho * (La + Da);
+        gm<T>(B.a2)[q] = irho * (La + T(0.5) * dt * Lb + Db);
+        return;
     }
-    T da0 = 0, da1 = 0, db0 = 0, db1 = 0;
-    if (ca.w[0] != 0.0) {
-        sat_point<T, ORD, true>(A, b, i, j, f0, ca, da0, da1);
-        point_data<T>(B, p, A, rg, ca, da0, da1);
+    const T A1 = gc<T>(B.a1)[q], A2 = gc<T>(B.a2)[q];
+    gp<T> u = gm<T>(B.u);
+    gp<T> v = gm<T>(B.v);
+    const T dt2 = dt * dt;
+    const T A3 = A2 + T(0.25) * dt2 * irho * La;
+    const T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * irho * (Lb + Db);
+    const T uo = u[q], vo = v[q];
+    const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
+    u[q] = un;
+    v[q] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
+    if (A.rec_out) {
+        gp<double> ro = gm<double>(A.rec_out);
+        for (int e = rg.beg; e < rg.end; ++e) {
+            const GLB Entry& E = entry(A, e);
+            if (E.kind == 1 && E.p == p) ro[2 * E.id + sub] = E.c0 * static_cast<double>(un);
+        }
     }
-    if (A.pass != PASS_APPLY) {
-        sat_point<T, ORD, true>(A, b, i, j, f1, cb, db0, db1);
-        point_data<T>(B, p, A, rg, cb, db0, db1);
-    }
-    finish_point<T>(A, b, p, irho, l00, l01, l10, l11, da0, da1, db0, db1, rg);
 }
 
 // ------------------------------------------------------------- interior
-// Repeating interior stencils only; one thread per point, operands read
-// straight from global memory (L1/L2 serve the neighbour reuse).
-template <typename T, int ORD>
-__device__ __forceinline__ void volume_interior(const BlockDesc& B, const T* u, long p, T& r0, T& r1) {
+// Marching kernel: one wave, 64 columns i0..i0+63 of the interior, rows
+// jb..je.  Per output row j the wave
+//   * stages input row j+H (H = stencil half width) in an LDS ring of 2H+1
+//     rows with an H-column halo on each side,
+//   * forms E(j+H) = M^T D_1 w from the staged row (M_jl = c_1j2l) into an
+//     LDS ring of its own column,
+//   * forms G(j) = M D_2 w from the ring (own column and halo columns) into an
+//     LDS row, then D_1 G,
+//   * evaluates the narrow x1 term from the staged row and the x1 coefficient
+//     row, the narrow x2 term from the ring and register windows of the x2
+//     coefficients, and D_2 E from the E ring.
+// All global loads of a row are issued together before its LDS writes; the
+// loads of row j+1 are issued before the arithmetic of row j.
+// PASS_APPLY evaluates one input field, the RK sweeps two.
+template <typename T, int NF>
+struct RowLoad {
+    T w[NF][2];      // input fields at (i, j + H)
+    T wh[NF][2];     // halo column of the input fields (lanes < 2H)
+    T b2[3];         // x2-narrow coefficients at (i, j + H)
+    T m[4];          // mixed coefficients at (i, j + H)
+    T b1[3];         // x1-narrow coefficients at (i, j)
+    T b1h[3];        // same at the halo column
+    T mh[4];         // mixed coefficients at the halo column, row j
+    T irho;
+    T x[4];          // second sweep: u, v at (i, j); forcing at (i, j) in x[0..1] otherwise
+};
+
+template <typename T, int ORD, int PASS>
+__global__ void __launch_bounds__(64) k_march(PassArgs A) {
     using O = Op<ORD>;
     constexpr int HF = O::HALF;
-    const int n1 = B.n1;
-    const long np = (long)n1 * B.n2;
-    const T* c = static_cast<const T*>(B.coef);
-    const T* u0 = u;
-    const T* u1 = u + np;
-    const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
-    const T a00 = d2_interior<T, ORD>(c + K_C1111 * np + p, u0 + p, 1);
-    const T a01 = d2_interior<T, ORD>(c + K_C1112 * np + p, u1 + p, 1);
-    const T a10 = d2_interior<T, ORD>(c + K_C1112 * np + p, u0 + p, 1);
-    const T a11 = d2_interior<T, ORD>(c + K_C1212 * np + p, u1 + p, 1);
-    const T b00 = d2_interior<T, ORD>(c + K_C2121 * np + p, u0 + p, n1);
-    const T b01 = d2_interior<T, ORD>(c + K_C2122 * np + p, u1 + p, n1);
-    const T b10 = d2_interior<T, ORD>(c + K_C2122 * np + p, u0 + p, n1);
-    const T b11 = d2_interior<T, ORD>(c + K_C2222 * np + p, u1 + p, n1);
-    r0 = (a00 + a01) * ih1 * ih1 + (b00 + b01) * ih2 * ih2;
-    r1 = (a10 + a11) * ih1 * ih1 + (b10 + b11) * ih2 * ih2;
-    T g0 = 0, g1 = 0, e0 = 0, e1 = 0;
-#pragma unroll
-    for (int k = -HF; k <= HF; ++k) {
-        if (k == 0) continue;
-        const T wk = static_cast<T>(O::d1i(k + HF));
-        // D_1 (M D_2 u): column p + k
-        {
-            const long q = p + k;
-            T w20 = 0, w21 = 0;
-#pragma unroll
-            for (int m = -HF; m <= HF; ++m) {
-                if (m == 0) continue;
-                const T wm = static_cast<T>(O::d1i(m + HF));
-                w20 += wm * (u0[q + (long)m * n1] - u0[q]);
-                w21 += wm * (u1[q + (long)m * n1] - u1[q]);
-            }
-            g0 += wk * (c[K_C1121 * np + q] * w20 + c[K_C1122 * np + q] * w21);
-            g1 += wk * (c[K_C1221 * np + q] * w20 + c[K_C1222 * np + q] * w21);
-        }
-        // D_2 (M^T D_1 u): row p + k n1
-        {
-            const long q = p + (long)k * n1;
-            T w10 = 0, w11 = 0;
-#pragma unroll
-            for (int m = -HF; m <= HF; ++m) {
-                if (m == 0) continue;
-                const T wm = static_cast<T>(O::d1i(m + HF));
-                w10 += wm * (u0[q + m] - u0[q]);
-                w11 += wm * (u1[q + m] - u1[q]);
-            }
-            e0 += wk * (c[K_C1121 * np + q] * w10 + c[K_C1221 * np + q] * w11);
-            e1 += wk * (c[K_C1122 * np + q] * w10 + c[K_C1222 * np + q] * w11);
-        }
-    }
-    const T ihh = ih1 * ih2;
-    r0 += (g0 + e0) * ihh;
-    r1 += (g1 + e1) * ihh;
-}
-
-template <typename T, int ORD>
-__global__ void __launch_bounds__(TILE_X * TILE_Y) k_interior(PassArgs A) {
+    constexpr int NW = 2 * HF + 1;
+    constexpr int LW = 64 + 2 * HF;
+    constexpr int NF = PASS == PASS_APPLY ? 1 : 2;
     constexpr int R = Frame<ORD>::R;
-    const int wg = blockIdx.x;
+    __shared__ T s_w[NW][NF][2][LW];
+    __shared__ T s_e[NW][NF][2][64];
+    __shared__ T s_g[NF][2][LW];
+    __shared__ T s_b[3][LW];
+
+    // workgroup order: consecutive tiles on the same XCD (ids are dealt round-robin to 8 XCDs)
+    const int total = A.total_tiles;
+    const int per = (total + 7) / 8;
+    const int wg = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (wg >= total) return;
     const int b = find_block(A, wg, false);
-    const BlockDesc& B = A.blocks[b];
+    BlockRef B = blk(A, b);
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
     const int tl = wg - B.tile_beg;
     const int ty = tl / B.tiles_x, tx = tl - ty * B.tiles_x;
-    const int i = R + tx * TILE_X + (threadIdx.x % TILE_X);
-    const int j = R + ty * TILE_Y + (threadIdx.x / TILE_X);
-    const Range rg = A.tile_ranges[wg];
-    if (i > B.n1 - 1 - R || j > B.n2 - 1 - R) return;
-    const long p = (long)j * B.n1 + i;
-    const T irho = static_cast<const T*>(B.coef)[(long)K_IRHO * B.n1 * B.n2 + p];
-    int f0, f1;
-    TimeComb ca, cb;
-    const TimeComb none = comb1(0.0, 0.0);
-    if (A.pass == PASS_APPLY) {
-        f0 = f1 = FLD_IN;
-        ca = comb1(A.t, A.homogeneous ? 0.0 : 1.0);
-        cb = none;
-    } else if (A.pass == PASS_RK1) {
-        f0 = FLD_U;
-        f1 = FLD_V;
-        ca = comb1(A.t, 1.0);
-        cb = comb1(A.t + 0.5 * A.dt, 1.0);
-    } else {
-        f0 = FLD_A1;
-        f1 = FLD_A2;
-        ca = none;
-        cb = comb_rk2(A.t, A.dt);
+    const int lane = threadIdx.x;
+    const int i0 = R + tx * 64;
+    const int i = i0 + lane;
+    const bool act = i <= n1 - 1 - R;
+    const int ic = i < n1 - 1 ? i : n1 - 1;
+    const int jb = R + ty * TILE_Y;
+    const int je = (jb + TILE_Y < n2 - R ? jb + TILE_Y : n2 - R) - 1;
+    const bool halo = lane < 2 * HF;
+    int hcol = ic, hpos = lane + HF;
+    if (lane < HF) {
+        hcol = i0 - HF + lane;
+        hpos = lane;
+    } else if (halo) {
+        hcol = i0 + 64 + (lane - HF);
+        if (hcol > n1 - 1) hcol = n1 - 1;
+        hpos = 64 + lane;
     }
-    T l00, l01, l10 = 0, l11 = 0;
-    volume_interior<T, ORD>(B, field_ptr<T>(A, b, f0), p, l00, l01);
-    if (A.pass != PASS_APPLY) volume_interior<T, ORD>(B, field_ptr<T>(A, b, f1), p, l10, l11);
-    T da0 = 0, da1 = 0, db0 = 0, db1 = 0;
-    if (ca.w[0] != 0.0) point_data<T>(B, p, A, rg, ca, da0, da1);
-    if (A.pass != PASS_APPLY) point_data<T>(B, p, A, rg, cb, db0, db1);
-    finish_point<T>(A, b, p, irho, l00, l01, l10, l11, da0, da1, db0, db1, rg);
+    gcp<T> c = gc<T>(B.coef);
+    gcp<T> fin[NF];
+    if constexpr (PASS == PASS_APPLY) {
+        fin[0] = gc<T>(A.in[b]);
+    } else if constexpr (PASS == PASS_RK1) {
+        fin[0] = gc<T>(B.u);
+        fin[1] = gc<T>(B.v);
+    } else {
+        fin[0] = gc<T>(B.a1);
+        fin[1] = gc<T>(B.a2);
+    }
+    const bool force = B.force != nullptr;
+    gcp<T> frc = gc<T>(B.force);
+    const Range rg = load_range(A.tile_ranges, wg);
+    const W3 ca = weights_a(A), cb = weights_b(A);
+    T tauf_a = 0, tauf_b = 0;
+    if (force) {
+        tauf_a = static_cast<T>(tval(A, B.item_f, ca));
+        tauf_b = static_cast<T>(tval(A, B.item_f, cb));
+    }
+    const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
+    const T i11 = ih1 * ih1, i22 = ih2 * ih2, i12 = ih1 * ih2;
+    const T dt = static_cast<T>(A.dt);
+
+    // all global loads for output row j (leading row j + HF)
+    auto load_row = [&](int j, RowLoad<T, NF>& L) {
+        const long qn = (long)(j + HF) * n1;
+        const long qj = (long)j * n1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) L.w[f][q] = fin[f][q * np + qn + ic];
+        L.b2[0] = c[K_C2121 * np + qn + ic];
+        L.b2[1] = c[K_C2122 * np + qn + ic];
+        L.b2[2] = c[K_C2222 * np + qn + ic];
+        L.m[0] = c[K_C1121 * np + qn + ic];
+        L.m[1] = c[K_C1122 * np + qn + ic];
+        L.m[2] = c[K_C1221 * np + qn + ic];
+        L.m[3] = c[K_C1222 * np + qn + ic];
+        L.b1[0] = c[K_C1111 * np + qj + ic];
+        L.b1[1] = c[K_C1112 * np + qj + ic];
+        L.b1[2] = c[K_C1212 * np + qj + ic];
+        L.irho = c[K_IRHO * np + qj + ic];
+        if constexpr (PASS == PASS_RK2) {
+            gcp<T> u = gc<T>(B.u);
+            gcp<T> v = gc<T>(B.v);
+            L.x[0] = u[qj + ic];
+            L.x[1] = u[np + qj + ic];
+            L.x[2] = v[qj + ic];
+            L.x[3] = v[np + qj + ic];
+        }
+        if (halo) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) L.wh[f][q] = fin[f][q * np + qn + hcol];
+            L.b1h[0] = c[K_C1111 * np + qj + hcol];
+            L.b1h[1] = c[K_C1112 * np + qj + hcol];
+            L.b1h[2] = c[K_C1212 * np + qj + hcol];
+            L.mh[0] = c[K_C1121 * np + qj + hcol];
+            L.mh[1] = c[K_C1122 * np + qj + hcol];
+            L.mh[2] = c[K_C1221 * np + qj + hcol];
+            L.mh[3] = c[K_C1222 * np + qj + hcol];
+        }
+    };
+    // E(i, j) = M^T (h D_1 w)(i, j) into the E ring
+    auto ecompute = [&](int j, const T m0, const T m1, const T m2, const T m3) {
+        const int s = j % NW;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            T w1[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const T wc = s_w[s][f][q][lane + HF];
+                T acc = 0;
+#pragma unroll
+                for (int k = -HF; k <= HF; ++k)
+                    if (k != 0) acc += static_cast<T>(O::d1i(k + HF)) * (s_w[s][f][q][lane + HF + k] - wc);
+                w1[q] = acc;
+            }
+            s_e[s][f][0][lane] = m0 * w1[0] + m2 * w1[1];
+            s_e[s][f][1][lane] = m1 * w1[0] + m3 * w1[1];
+        }
+    };
+
+    // register windows: x2-narrow coefficients (rows j-HF..j+HF) and M (rows j..j+HF)
+    T b2w[3][NW];
+    T mq[HF + 1][4];
+    // prologue: rows jb-HF .. jb+HF-1 staged, their E formed
+    {
+        T pw[2 * HF][NF][2], ph[2 * HF][NF][2], pm[2 * HF][4];
+#pragma unroll
+        for (int r = 0; r < 2 * HF; ++r) {
+            const long q = (long)(jb - HF + r) * n1;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq) {
+                    pw[r][f][qq] = fin[f][qq * np + q + ic];
+                    ph[r][f][qq] = fin[f][qq * np + q + hcol];
+                }
+            b2w[0][r] = c[K_C2121 * np + q + ic];
+            b2w[1][r] = c[K_C2122 * np + q + ic];
+            b2w[2][r] = c[K_C2222 * np + q + ic];
+            pm[r][0] = c[K_C1121 * np + q + ic];
+            pm[r][1] = c[K_C1122 * np + q + ic];
+            pm[r][2] = c[K_C1221 * np + q + ic];
+            pm[r][3] = c[K_C1222 * np + q + ic];
+        }
+#pragma unroll
+        for (int r = 0; r < 2 * HF; ++r) {
+            const int s = (jb - HF + r) % NW;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq) {
+                    s_w[s][f][qq][lane + HF] = pw[r][f][qq];
+                    s_w[s][f][qq][hpos] = ph[r][f][qq];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2 * HF; ++r) {
+            ecompute(jb - HF + r, pm[r][0], pm[r][1], pm[r][2], pm[r][3]);
+            if (r >= HF)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) mq[r - HF][m] = pm[r][m];
+        }
+    }
+
+    RowLoad<T, NF> cur, nxt;
+    load_row(jb, cur);
+    for (int j = jb; j <= je; ++j) {
+        if (j < je) load_row(j + 1, nxt);
+        T f0 = 0, f1 = 0;
+        if (force) {
+            f0 = frc[(long)j * n1 + ic];
+            f1 = frc[np + (long)j * n1 + ic];
+        }
+        const int jn = j + HF;
+        __syncthreads();
+        // (1) stage row jn and the x1 coefficient row j
+        {
+            const int s = jn % NW;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    s_w[s][f][q][lane + HF] = cur.w[f][q];
+                    if (halo) s_w[s][f][q][hpos] = cur.wh[f][q];
+                }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s_b[k][lane + HF] = cur.b1[k];
+                if (halo) s_b[k][hpos] = cur.b1h[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) b2w[k][NW - 1] = cur.b2[k];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) mq[HF][m] = cur.m[m];
+        }
+        __syncthreads();
+        // (2) E at the leading row; G at row j (own column and halo); narrow terms
+        ecompute(jn, mq[HF][0], mq[HF][1], mq[HF][2], mq[HF][3]);
+        const int s0 = j % NW;
+        T lx[NF][2];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            T wcol[2][NW];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int k = 0; k < NW; ++k) wcol[q][k] = s_w[(j - HF + k) % NW][f][q][lane + HF];
+            T w2[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                T acc = 0;
+#pragma unroll
+                for (int k = -HF; k <= HF; ++k)
+                    if (k != 0) acc += static_cast<T>(O::d1i(k + HF)) * (wcol[q][HF + k] - wcol[q][HF]);
+                w2[q] = acc;
+            }
+            s_g[f][0][lane + HF] = mq[0][0] * w2[0] + mq[0][1] * w2[1];
+            s_g[f][1][lane + HF] = mq[0][2] * w2[0] + mq[0][3] * w2[1];
+            if (halo) {
+                T h2[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const T wc = s_w[s0][f][q][hpos];
+                    T acc = 0;
+#pragma unroll
+                    for (int k = -HF; k <= HF; ++k)
+                        if (k != 0) acc += static_cast<T>(O::d1i(k + HF)) * (s_w[(j + k) % NW][f][q][hpos] - wc);
+                    h2[q] = acc;
+                }
+                s_g[f][0][hpos] = cur.mh[0] * h2[0] + cur.mh[1] * h2[1];
+                s_g[f][1][hpos] = cur.mh[2] * h2[0] + cur.mh[3] * h2[1];
+            }
+            // narrow x2 term: own column of the ring, coefficient window in registers
+            const T bx0 = d2_interior<T, ORD>(&b2w[0][HF], &wcol[0][HF], 1);   // c2121 u1
+            const T bx1 = d2_interior<T, ORD>(&b2w[1][HF], &wcol[1][HF], 1);   // c2122 u2
+            const T bx2 = d2_interior<T, ORD>(&b2w[1][HF], &wcol[0][HF], 1);   // c2122 u1
+            const T bx3 = d2_interior<T, ORD>(&b2w[2][HF], &wcol[1][HF], 1);   // c2222 u2
+            // narrow x1 term: staged row and x1 coefficient row
+            const T ax0 = d2_interior<T, ORD>(&s_b[0][lane + HF], &s_w[s0][f][0][lane + HF], 1);
+            const T ax1 = d2_interior<T, ORD>(&s_b[1][lane + HF], &s_w[s0][f][1][lane + HF], 1);
+            const T ax2 = d2_interior<T, ORD>(&s_b[1][lane + HF], &s_w[s0][f][0][lane + HF], 1);
+            const T ax3 = d2_interior<T, ORD>(&s_b[2][lane + HF], &s_w[s0][f][1][lane + HF], 1);
+            lx[f][0] = (ax0 + ax1) * i11 + (bx0 + bx1) * i22;
+            lx[f][1] = (ax2 + ax3) * i11 + (bx2 + bx3) * i22;
+        }
+        __syncthreads();
+        // (3) D_1 G and D_2 E
+        T L[NF][2];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const T gc0 = s_g[f][q][lane + HF];
+                const T ec0 = s_e[s0][f][q][lane];
+                T ag = 0, ae = 0;
+#pragma unroll
+                for (int k = -HF; k <= HF; ++k) {
+                    if (k == 0) continue;
+                    const T w = static_cast<T>(O::d1i(k + HF));
+                    ag += w * (s_g[f][q][lane + HF + k] - gc0);
+                    ae += w * (s_e[(j + k) % NW][f][q][lane] - ec0);
+                }
+                L[f][q] = lx[f][q] + (ag + ae) * i12;
+            }
+        // (4) data, RK arithmetic, stores
+        const long p = (long)j * n1 + i;
+        if (act) {
+            T da0 = tauf_a * f0, da1 = tauf_a * f1, db0 = tauf_b * f0, db1 = tauf_b * f1;
+            if (rg.end > rg.beg) {
+                if (ca.any()) point_sources<T>(A, rg, p, ca, da0, da1);
+                if (NF == 2 && cb.any()) point_sources<T>(A, rg, p, cb, db0, db1);
+            }
+            const T irho = cur.irho;
+            if constexpr (PASS == PASS_APPLY) {
+                gp<T> o = gm<T>(A.out[b]);
+                o[p] = irho * (L[0][0] + da0);
+                o[np + p] = irho * (L[0][1] + da1);
+            } else if constexpr (PASS == PASS_RK1) {
+                gp<T> a1 = gm<T>(B.a1);
+                gp<T> a2 = gm<T>(B.a2);
+                const T hdt = T(0.5) * dt;
+                a1[p] = irho * (L[0][0] + da0);
+                a1[np + p] = irho * (L[0][1] + da1);
+                a2[p] = irho * (L[0][0] + hdt * L[NF - 1][0] + db0);
+                a2[np + p] = irho * (L[0][1] + hdt * L[NF - 1][1] + db1);
+            } else {
+                gp<T> u = gm<T>(B.u);
+                gp<T> v = gm<T>(B.v);
+                const T dt2 = dt * dt;
+                const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
+                T un[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const T A1 = s_w[s0][0][q][lane + HF];
+                    const T A2 = s_w[s0][NF - 1][q][lane + HF];
+                    const T A3 = A2 + q4 * irho * L[0][q];
+                    const T A4 = T(2) * A2 - A1 + q2 * irho * (L[NF - 1][q] + (q ? db1 : db0));
+                    un[q] = cur.x[q] + dt * cur.x[2 + q] + s6 * (A1 + A2 + A3);
+                    u[q * np + p] = un[q];
+                    v[q * np + p] = cur.x[2 + q] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4);
+                }
+                if (A.rec_out && rg.end > rg.beg) {
+                    gp<double> ro = gm<double>(A.rec_out);
+                    for (int e = rg.beg; e < rg.end; ++e) {
+                        const GLB Entry& E = entry(A, e);
+                        if (E.kind == 1 && E.p == p) {
+                            ro[2 * E.id] = E.c0 * static_cast<double>(un[0]);
+                            ro[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);
+                        }
+                    }
+                }
+            }
+        }
+        // (5) rotate register windows
+#pragma unroll
+        for (int k = 0; k < NW - 1; ++k) {
+            b2w[0][k] = b2w[0][k + 1];
+            b2w[1][k] = b2w[1][k + 1];
+            b2w[2][k] = b2w[2][k + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < HF; ++k)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) mq[k][m] = mq[k + 1][m];
+        cur = nxt;
+    }
+}
+
+// ---------------------------------------------------------- tau table
+// tau[(s * nitems + it) * 3 + k] = tau_it(t0 + s dt + c_k dt), c = (0, 1/2, 1)
+__global__ void __launch_bounds__(256) k_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt,
+                                             double* tau) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long)nitems * nsteps) return;
+    const int s = (int)(idx / nitems), it = (int)(idx - (long)s * nitems);
+    const GLB TimeFn& g = ((const GLB TimeFn*)items)[it];
+    TimeFn f;
+    f.kind = g.kind;
+    f.pad = 0;
+    f.p[0] = g.p[0];
+    f.p[1] = g.p[1];
+    const double t = t0 + s * dt;
+    gp<double> o = gm<double>(tau) + 3 * idx;
+    o[0] = tfun(f, t);
+    o[1] = tfun(f, t + 0.5 * dt);
+    o[2] = tfun(f, t + dt);
 }
 
 // -------------------------------------------------------------- energy
@@ -763,12 +1101,12 @@ __global__ void __launch_bounds__(256) k_energy_partial(const BlockDesc* blocks,
     long gid = (long)blockIdx.x * 256 + threadIdx.x;
     const long stride = (long)gridDim.x * 256;
     for (int b = 0; b < nblocks; ++b) {
-        const BlockDesc& B = blocks[b];
+        const GLB BlockDesc& B = ((const GLB BlockDesc*)blocks)[b];
         const long np = (long)B.n1 * B.n2;
-        const T* u = static_cast<const T*>(B.u);
-        const T* v = static_cast<const T*>(B.v);
-        const T* a = static_cast<const T*>(B.a1);
-        const T* c = static_cast<const T*>(B.coef);
+        gcp<T> u = gc<T>(B.u);
+        gcp<T> v = gc<T>(B.v);
+        gcp<T> a = gc<T>(B.a1);
+        gcp<T> c = gc<T>(B.coef);
         for (long p = gid; p < np; p += stride) {
             const int j = (int)(p / B.n1), i = (int)(p - (long)j * B.n1);
             const double H = B.h1 * B.h2 * hnorm<ORD>(i, B.n1) * hnorm<ORD>(j, B.n2);
@@ -802,20 +1140,48 @@ __global__ void __launch_bounds__(256) k_energy_final(const double* partial, int
 
 // ---------------------------------------------------------- launchers
 template <typename T, int ORD>
-static int launch_pass_t(const PassArgs& a, int total_tiles, int total_frame_wg, hipStream_t s) {
-    if (total_tiles > 0) hipLaunchKernelGGL((k_interior<T, ORD>), dim3(total_tiles), dim3(TILE_X * TILE_Y), 0, s, a);
-    if (total_frame_wg > 0) hipLaunchKernelGGL((k_frame<T, ORD>), dim3(total_frame_wg), dim3(FRAME_WG), 0, s, a);
+static void launch_march_t(const PassArgs& a, int total_tiles, hipStream_t s) {
+    const dim3 g(((total_tiles + 7) / 8) * 8), bl(64);
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_march<T, ORD, PASS_APPLY>), g, bl, 0, s, a);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK1>), g, bl, 0, s, a);
+    else hipLaunchKernelGGL((k_march<T, ORD, PASS_RK2>), g, bl, 0, s, a);
+}
+
+int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (total_tiles <= 0) return 0;
+    PassArgs b = a;
+    b.total_tiles = total_tiles;
+    if (dtype == 0) {
+        if (order == 4) launch_march_t<double, 4>(b, total_tiles, s);
+        else launch_march_t<double, 2>(b, total_tiles, s);
+    } else {
+        if (order == 4) launch_march_t<float, 4>(b, total_tiles, s);
+        else launch_march_t<float, 2>(b, total_tiles, s);
+    }
     return static_cast<int>(hipGetLastError());
 }
 
-int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg, void* stream) {
+int launch_frame(int dtype, int order, const PassArgs& a, int total_frame_wg, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (total_frame_wg <= 0) return 0;
+    const dim3 g(total_frame_wg), b(FRAME_WG);
     if (dtype == 0) {
-        return order == 4 ? launch_pass_t<double, 4>(a, total_tiles, total_frame_wg, s)
-                          : launch_pass_t<double, 2>(a, total_tiles, total_frame_wg, s);
+        if (order == 4) hipLaunchKernelGGL((k_frame<double, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_frame<double, 2>), g, b, 0, s, a);
+    } else {
+        if (order == 4) hipLaunchKernelGGL((k_frame<float, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_frame<float, 2>), g, b, 0, s, a);
     }
-    return order == 4 ? launch_pass_t<float, 4>(a, total_tiles, total_frame_wg, s)
-                      : launch_pass_t<float, 2>(a, total_tiles, total_frame_wg, s);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt, double* tau, void* stream) {
+    const long n = (long)nitems * nsteps;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_tau, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), items,
+                       nitems, nsteps, t0, dt, tau);
+    return static_cast<int>(hipGetLastError());
 }
 
 int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
@@ -830,12 +1196,6 @@ int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks
     }
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, partial_dev, npartial, result_dev);
     return static_cast<int>(hipGetLastError());
-}
-
-int upload_tables(const double* t4, const double* t2) {
-    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_d2c4), t4, sizeof(double) * O4_R0 * O4_W * O4_W);
-    if (e != hipSuccess) return static_cast<int>(e);
-    return static_cast<int>(hipMemcpyToSymbol(HIP_SYMBOL(c_d2c2), t2, sizeof(double) * O2_R0 * O2_W * O2_W));
 }
 
 const char* hip_error_string(int code) { return hipGetErrorString(static_cast<hipError_t>(code)); }

@@ -50,9 +50,84 @@ template <int ORD> struct Frame;
 template <> struct Frame<4> { static constexpr int R = 6; };
 template <> struct Frame<2> { static constexpr int R = 2; };
 
-// Derive the closure table T[r][m][s] (r < R0, m, s < W) such that
-// h^2 (D2^FC(b) u)_r = sum_{m,s} T[r][m][s] b_s u_m on the lower end of a line.
-// The upper end follows by reflection: (D2 u)_{N-r} uses b_{N-s}, u_{N-m}.
+// ---- closure tables, derived at compile time --------------------------------
+// T[r][m][s] (r < R0, m, s < W) with h^2 (D2^FC(b) u)_r = sum_{m,s} T[r][m][s] b_s u_m
+// on the lower end of a line (rows r < R0); the upper end follows by reflection:
+// (D2^FC u)_{N-r} uses b_{N-s}, u_{N-m}.  Derived on a 32-point line from
+//   -H^{-1} ( D1^T H b D1 + R(b) + e0 b0 e0^T D1 )   restricted to rows r < R0.
+template <int R0, int W> struct D2Table {
+    double t[R0][W][W];
+};
+
+constexpr double table_norm(int order, int n, int k) {
+    if (order == 4) return k < O4_NB ? O4_H[k] : (k > n - 1 - O4_NB ? O4_H[n - 1 - k] : 1.0);
+    return k < O2_NB ? O2_H[k] : (k > n - 1 - O2_NB ? O2_H[n - 1 - k] : 1.0);
+}
+
+constexpr D2Table<O4_R0, O4_W> make_d2_table4() {
+    constexpr int n = 32;
+    double D[n][n] = {};
+    for (int r = 0; r < O4_NB; ++r)
+        for (int c = 0; c < 6; ++c) {
+            D[r][c] = O4_D1B[r][c];
+            D[n - 1 - r][n - 1 - c] = -O4_D1B[r][c];
+        }
+    for (int r = O4_NB; r < n - O4_NB; ++r)
+        for (int k = 0; k < 5; ++k) D[r][r - 2 + k] = O4_D1I[k];
+    const double d3[4] = {-1, 3, -3, 1};
+    const double d4[5] = {1, -4, 6, -4, 1};
+    D2Table<O4_R0, O4_W> T{};
+    for (int r = 0; r < O4_R0; ++r)
+        for (int m = 0; m < O4_W; ++m)
+            for (int s = 0; s < O4_W; ++s) {
+                double v = -D[s][r] * table_norm(4, n, s) * D[s][m];
+                const int n3 = n - 3;
+                for (int c = 0; c < n3; ++c) {          // d3 windows, B = (b_{c+1} + b_{c+2}) / 2
+                    if (r < c || r > c + 3 || m < c || m > c + 3) continue;
+                    double g = O4_G3;
+                    if (c < 3) g = O4_G3_BND[c];
+                    else if (n3 - 1 - c < 3) g = O4_G3_BND[n3 - 1 - c];
+                    if (s == c + 1 || s == c + 2) v -= g * 0.5 * d3[r - c] * d3[m - c];
+                }
+                for (int c = 0; c + 4 < n; ++c) {       // d4 windows, B = b_{c+2}
+                    if (r < c || r > c + 4 || m < c || m > c + 4) continue;
+                    if (s == c + 2) v -= O4_G4 * d4[r - c] * d4[m - c];
+                }
+                if (r == 0 && s == 0) v -= D[0][m];     // boundary derivative = D1 (fully compatible)
+                T.t[r][m][s] = v / table_norm(4, n, r);
+            }
+    return T;
+}
+
+constexpr D2Table<O2_R0, O2_W> make_d2_table2() {
+    constexpr int n = 16;
+    double D[n][n] = {};
+    D[0][0] = O2_D1B[0][0];
+    D[0][1] = O2_D1B[0][1];
+    D[n - 1][n - 1] = -O2_D1B[0][0];
+    D[n - 1][n - 2] = -O2_D1B[0][1];
+    for (int r = 1; r < n - 1; ++r)
+        for (int k = 0; k < 3; ++k) D[r][r - 1 + k] = O2_D1I[k];
+    const double d2[3] = {1, -2, 1};
+    D2Table<O2_R0, O2_W> T{};
+    for (int r = 0; r < O2_R0; ++r)
+        for (int m = 0; m < O2_W; ++m)
+            for (int s = 0; s < O2_W; ++s) {
+                double v = -D[s][r] * table_norm(2, n, s) * D[s][m];
+                for (int c = 0; c + 2 < n; ++c) {       // d2 windows, B = b_{c+1}
+                    if (r < c || r > c + 2 || m < c || m > c + 2) continue;
+                    if (s == c + 1) v -= O2_G2 * d2[r - c] * d2[m - c];
+                }
+                if (r == 0 && s == 0) v -= D[0][m];
+                T.t[r][m][s] = v / table_norm(2, n, r);
+            }
+    return T;
+}
+
+constexpr D2Table<O4_R0, O4_W> D2T4 = make_d2_table4();
+constexpr D2Table<O2_R0, O2_W> D2T2 = make_d2_table2();
+
+// Host copies of the derived closure tables (T[r][m][s], row-major).
 void derive_d2_closure(int order, double* T);
 // Dimensionless norm weight of point k on a line of n points.
 double norm_weight(int order, int n, int k);

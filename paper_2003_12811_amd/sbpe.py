@@ -59,6 +59,9 @@ _PROTOS = {
     'sbpe_host_d2fc_line': [_I, _I, _DP, _DP, _DP],
     'sbpe_host_d1_line': [_I, _I, _DP, _DP],
     'sbpe_get_block_fields': [_P, _I, _DP, _DP, _DP],
+    'sbpe_set_kernel_timing': [_P, _I],
+    'sbpe_get_kernel_timing': [_P, _DP, _IP],
+    'sbpe_plan_info': [_P, ctypes.POINTER(ctypes.c_longlong)],
 }
 
 
@@ -204,10 +207,11 @@ def sbpe_get_time(ctx):
     return t.value
 
 
-def sbpe_read_receivers(ctx, nrec, max_steps):
-    out = np.zeros((max(max_steps, 0), nrec, 2))
+def sbpe_read_receivers(ctx, nrec, max_steps=2 ** 31 - 1):
     n = _I()
-    _check(ctx, lib().sbpe_read_receivers(ctx, _dp(out), max_steps, ctypes.byref(n)))
+    _check(ctx, lib().sbpe_read_receivers(ctx, None, max_steps, ctypes.byref(n)))
+    out = np.zeros((n.value, nrec, 2))
+    _check(ctx, lib().sbpe_read_receivers(ctx, _dp(out), n.value, ctypes.byref(n)))
     return out[:n.value]
 
 
@@ -248,3 +252,24 @@ def sbpe_get_block_fields(ctx, block):
     _check(ctx, lib().sbpe_get_block_fields(ctx, block, _dp(c10), _dp(J), _dp(jh)))
     jhat = [jh[f, :(n2 if f < 2 else n1)].copy() for f in range(4)]
     return c10, J, jhat
+
+
+KERNEL_KINDS = ('interior_rk1', 'frame_rk1', 'interior_rk2', 'frame_rk2', 'interior_apply', 'frame_apply')
+
+
+def sbpe_set_kernel_timing(ctx, enable):
+    _check(ctx, lib().sbpe_set_kernel_timing(ctx, 1 if enable else 0))
+
+
+def sbpe_get_kernel_timing(ctx):
+    ms = np.zeros(6)
+    cnt = (ctypes.c_int * 6)()
+    _check(ctx, lib().sbpe_get_kernel_timing(ctx, _dp(ms), cnt))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def sbpe_plan_info(ctx):
+    info = (ctypes.c_longlong * 5)()
+    _check(ctx, lib().sbpe_plan_info(ctx, info))
+    return dict(interior_points=info[0], frame_points=info[1], interior_workgroups=info[2],
+                frame_workgroups=info[3], frame_width=info[4])

@@ -96,8 +96,8 @@ class Solver:
     def time(self):
         return S.sbpe_get_time(self.ctx)
 
-    def receivers(self, max_steps=10 ** 7):
-        return S.sbpe_read_receivers(self.ctx, self.nrec, max_steps)
+    def receivers(self):
+        return S.sbpe_read_receivers(self.ctx, self.nrec)
 
     def synchronize(self):
         S.sbpe_synchronize(self.ctx)

@@ -12,7 +12,7 @@ from oracle import elastic as E, timestep as T
 from paper_2003_12811_amd import sbpe as S
 from paper_2003_12811_amd import workloads as W
 
-from oracle_build import build, receivers
+from oracle.spec import build, receivers
 
 pytestmark = pytest.mark.gpu
 TOL = {'f64': 1e-11, 'f32': 1e-5}

@@ -83,6 +83,18 @@ def run_gpu(spec, dtype, steps, warmup, apply_reps=0):
     return res
 
 
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device='cuda')
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log('copy probe: 3 copies of %d MiB' % mib)
+    del src, dst
+
+
 def dominant(res):
     best, kind = -1.0, None
     for k, (ms, cnt) in res['kernels'].items():
@@ -136,6 +148,9 @@ def main():
     ap.add_argument('--no-large', action='store_true')
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
+    ap.add_argument('--copy-probe-mib', type=int, default=0,
+                    help='first run a plain device-to-device copy of this many MiB (calibrates '
+                         'the HBM byte counters of a profiler)')
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_baseline_child(args.n, args.cpu_steps)
@@ -145,6 +160,8 @@ def main():
         print('this build measures one GPU only: run bench.py with --gpus 1 (the multi-GPU '
               'sharding by blocks is described in DESIGN.md, not implemented)', file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
     from paper_2003_12811_amd import workloads as W
     log('building workload %dx%d' % (args.n, args.n))
     spec = W.spec_c2(n=args.n)

@@ -1,0 +1,1099 @@
+// HIP kernels (gfx950, wave64) of the SBP-SAT anisotropic elastic operator.
+//
+// One right-hand-side evaluation is split by grid region:
+//   * k_march: points at least Frame<ORD>::R from every face, where all 1-D
+//     operators use their repeating interior stencils (Sec. 4.3-4.7).  One
+//     wave spans 64 consecutive columns, writes the central 64 - 2H of them
+//     and marches over the rows of its tile: input rows are staged once in
+//     an LDS ring (x1 neighbours and the x2 window of the own column),
+//     coefficient windows stay in registers, and the mixed terms go through
+//     an LDS row (D_1 G) and a register window (D_2 E);
+//   * k_frame: the band of width R along the faces, where the boundary
+//     closures of D1 and D2^FC and the SATs of Sec. 5 and 6 act; one thread
+//     per point, closure rows unrolled from compile-time tables.
+// Both are fused with the two-sweep form of classical RK4 described in
+// sbpe_internal.h, so one RK4 step streams the coefficient fields twice.
+//
+// Reference-frame forms used here (all follow from the paper's definitions):
+//   * volume: DD_ik(c_ijkl) u_l = D_11^FC(c_1j1l) u_l + D_22^FC(c_2j2l) u_l
+//             + D_1 (c_1j2l D_2 u_l) + D_2 (c_2j1l D_1 u_l)   (eq. def_cd, Sec. 4.7)
+//   * Jhat T_jl = nu_i c_ijkl D_k                              (eq. n-C_conversion)
+//   * Jhat Z_jl = beta d / h_1 nu_i c_ijkl nu_k (displacement; / 4 and summed
+//     over both sides at interfaces), from Nanson's formula (eq. nanson)
+//   * J (JH)^{-1} e_f Jhat H_f = (1 / h_1) at the face points (H = H_x1 (x) H_x2)
+//   * H_t^{-1} D_t^T H_t = -D_t + H_t^{-1} (e_N e_N^T - e_0 e_0^T)  (SBP property, Sec. 4)
+// Second differences are formed from differences u_m - u_r first (every row of
+// D2^FC and D1 sums to zero), which keeps FP32 cancellation small.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "sbpe_internal.h"
+#include "sbpe_tables.h"
+
+namespace sbpe {
+
+// Every field lives in global memory; loads and stores go through
+// address-space-1 pointers so that they compile to global (not flat) accesses,
+// which the compiler can batch freely around LDS traffic.
+#define GLB __attribute__((address_space(1)))
+template <typename T> using gcp = const GLB T*;
+template <typename T> using gp = GLB T*;
+template <typename T>
+__device__ __forceinline__ gcp<T> gc(const void* p) { return (gcp<T>)p; }
+template <typename T>
+__device__ __forceinline__ gp<T> gm(void* p) { return (gp<T>)p; }
+using BlockRef = const GLB BlockDesc&;
+__device__ __forceinline__ BlockRef blk(const PassArgs& A, int b) { return ((const GLB BlockDesc*)A.blocks)[b]; }
+__device__ __forceinline__ const GLB Entry& entry(const PassArgs& A, int e) { return ((const GLB Entry*)A.entries)[e]; }
+__device__ __forceinline__ Range load_range(const Range* base, int k) {
+    const GLB Range& r = ((const GLB Range*)base)[k];
+    Range o;
+    o.beg = r.beg;
+    o.end = r.end;
+    return o;
+}
+
+template <int ORD> struct Op;
+template <> struct Op<4> {
+    static constexpr int R0 = O4_R0, W = O4_W, NB = O4_NB, HALF = 2, REACH = 4;
+    __host__ __device__ static constexpr double d2c(int r, int m, int s) { return D2T4.t[r][m][s]; }
+    __host__ __device__ static constexpr double d1b(int r, int c) { return O4_D1B[r][c]; }
+    __host__ __device__ static constexpr double d1i(int k) { return O4_D1I[k]; }
+    __host__ __device__ static constexpr double hb(int k) { return O4_H[k]; }
+};
+template <> struct Op<2> {
+    static constexpr int R0 = O2_R0, W = O2_W, NB = O2_NB, HALF = 1, REACH = 2;
+    __host__ __device__ static constexpr double d2c(int r, int m, int s) { return D2T2.t[r][m][s]; }
+    __host__ __device__ static constexpr double d1b(int r, int c) { return O2_D1B[r][c]; }
+    __host__ __device__ static constexpr double d1i(int k) { return O2_D1I[k]; }
+    __host__ __device__ static constexpr double hb(int k) { return O2_H[k]; }
+};
+
+// weight of u_{i+2} - u_{i-2} in the interior first derivative (0 at order 2)
+template <int ORD>
+__host__ __device__ constexpr double d1_outer() {
+    if constexpr (Op<ORD>::HALF > 1) return Op<ORD>::d1i(Op<ORD>::HALF + 2);
+    else return 0.0;
+}
+
+// dimensionless norm weight of point k on a line of n points
+template <int ORD>
+__device__ __forceinline__ double hnorm(int k, int n) {
+    using O = Op<ORD>;
+    if (k < O::NB) return O::hb(k);
+    if (k > n - 1 - O::NB) return O::hb(n - 1 - k);
+    return 1.0;
+}
+
+__device__ __forceinline__ double tfun(const TimeFn& f, double t) {
+    switch (f.kind) {
+        case TF_ONE: return 1.0;
+        case TF_COS: return cos(f.p[0] * t + f.p[1]);
+        case TF_RICKER: {
+            const double a = (M_PI * f.p[0] * (t - f.p[1])) * (M_PI * f.p[0] * (t - f.p[1]));
+            return (1.0 - 2.0 * a) * exp(-a);
+        }
+        default: return 0.0;
+    }
+}
+
+// weights of the three tabulated values tau(t), tau(t + dt/2), tau(t + dt)
+struct W3 {
+    double w0, w1, w2;
+    __device__ bool any() const { return w0 != 0.0 || w1 != 0.0 || w2 != 0.0; }
+};
+__device__ __forceinline__ W3 weights_a(const PassArgs& A) { return W3{A.wa[0], A.wa[1], A.wa[2]}; }
+__device__ __forceinline__ W3 weights_b(const PassArgs& A) { return W3{A.wb[0], A.wb[1], A.wb[2]}; }
+
+// weighted time-function value of an item in this step
+__device__ __forceinline__ double tval(const PassArgs& A, int item, const W3& w) {
+    const GLB double* t = (const GLB double*)A.tau + 3 * item;
+    return w.w0 * t[0] + w.w1 * t[1] + w.w2 * t[2];
+}
+
+template <typename T>
+__device__ __forceinline__ gcp<T> field_ptr(const PassArgs& A, int b, int fld) {
+    BlockRef B = blk(A, b);
+    switch (fld) {
+        case FLD_U: return gc<T>(B.u);
+        case FLD_V: return gc<T>(B.v);
+        case FLD_A1: return gc<T>(B.a1);
+        case FLD_A2: return gc<T>(B.a2);
+        default: return gc<T>(A.in[b]);
+    }
+}
+
+// ------------------------------------------------------------ 1-D rows
+// D1 row r of a line of n points: calls f(index, weight * h) for its nonzero
+// entries; closure rows are unrolled from the compile-time tables.
+template <int ORD, int RR, typename F>
+__device__ __forceinline__ void d1_closure_foreach(bool lo, int n, F&& f) {
+    using O = Op<ORD>;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        if (O::d1b(RR, c) != 0.0) f(lo ? c : n - 1 - c, lo ? O::d1b(RR, c) : -O::d1b(RR, c));
+}
+
+template <int ORD, int RR, typename F>
+__device__ __forceinline__ void d1_dispatch(int rr, bool lo, int n, F&& f) {
+    if constexpr (RR < Op<ORD>::NB) {
+        if (rr == RR) d1_closure_foreach<ORD, RR>(lo, n, f);
+        else d1_dispatch<ORD, RR + 1>(rr, lo, n, f);
+    }
+}
+
+template <int ORD, typename F>
+__device__ __forceinline__ void d1_foreach(int r, int n, F&& f) {
+    using O = Op<ORD>;
+    if (r >= O::NB && r <= n - 1 - O::NB) {
+#pragma unroll
+        for (int k = -O::HALF; k <= O::HALF; ++k)
+            if (k != 0) f(r + k, O::d1i(k + O::HALF));
+        return;
+    }
+    const bool lo = r < O::NB;
+    d1_dispatch<ORD, 0>(lo ? r : n - 1 - r, lo, n, f);
+}
+
+// h (D1 u)_r on a line with element stride st (difference form)
+template <typename T, int ORD>
+__device__ __forceinline__ T d1_line(gcp<T> u, long st, int r, int n) {
+    const T ur = u[(long)r * st];
+    T acc = 0;
+    d1_foreach<ORD>(r, n, [&](int k, double w) { acc += static_cast<T>(w) * (u[(long)k * st] - ur); });
+    return acc;
+}
+
+// h^2 (D2^FC(b) u)_r at an interior row; b, u point at the row.
+template <typename T, int ORD, typename PB, typename PU>
+__device__ __forceinline__ T d2_interior(PB b, PU u, long st) {
+    const T u0 = u[0];
+    if constexpr (ORD == 4) {
+        const T bm2 = b[-2 * st], bm1 = b[-st], b0 = b[0], bp1 = b[st], bp2 = b[2 * st];
+        const T s6 = T(1) / T(6), e8 = T(0.125), hf = T(0.5);
+        const T km2 = s6 * bm1 - e8 * (bm2 + b0);
+        const T km1 = s6 * (bm2 + bp1) + hf * (bm1 + b0);
+        const T kp1 = s6 * (bm1 + bp2) + hf * (b0 + bp1);
+        const T kp2 = s6 * bp1 - e8 * (b0 + bp2);
+        return km2 * (u[-2 * st] - u0) + km1 * (u[-st] - u0) + kp1 * (u[st] - u0) + kp2 * (u[2 * st] - u0);
+    } else {
+        const T hf = T(0.5);
+        return hf * (b[-st] + b[0]) * (u[-st] - u0) + hf * (b[0] + b[st]) * (u[st] - u0);
+    }
+}
+
+// closure row RR (from the lower end, or mirrored at the upper end)
+template <typename T, int ORD, int RR>
+__device__ __forceinline__ T d2_closure(gcp<T> b, gcp<T> u, long st, bool lo, int n) {
+    using O = Op<ORD>;
+    const T ur = u[(long)(lo ? RR : n - 1 - RR) * st];
+    T acc = 0;
+#pragma unroll
+    for (int m = 0; m < O::W; ++m) {
+        if (m == RR) continue;
+        T cf = 0;
+        bool any = false;
+#pragma unroll
+        for (int s = 0; s < O::W; ++s) {
+            if (O::d2c(RR, m, s) != 0.0) {
+                cf += static_cast<T>(O::d2c(RR, m, s)) * b[(long)(lo ? s : n - 1 - s) * st];
+                any = true;
+            }
+        }
+        if (any) acc += cf * (u[(long)(lo ? m : n - 1 - m) * st] - ur);
+    }
+    return acc;
+}
+
+template <typename T, int ORD, int RR>
+__device__ __forceinline__ T d2_dispatch(int rr, gcp<T> b, gcp<T> u, long st, bool lo, int n) {
+    if constexpr (RR < Op<ORD>::R0) {
+        if (rr == RR) return d2_closure<T, ORD, RR>(b, u, st, lo, n);
+        return d2_dispatch<T, ORD, RR + 1>(rr, b, u, st, lo, n);
+    } else {
+        return T(0);
+    }
+}
+
+// h^2 (D2^FC(b) u)_r on a line of n points; b, u point at index 0 of the line.
+template <typename T, int ORD>
+__device__ __forceinline__ T d2_line(gcp<T> b, gcp<T> u, long st, int r, int n) {
+    using O = Op<ORD>;
+    if (r >= O::R0 && r <= n - 1 - O::R0) return d2_interior<T, ORD>(b + r * st, u + r * st, st);
+    const bool lo = r < O::R0;
+    return d2_dispatch<T, ORD, 0>(lo ? r : n - 1 - r, b, u, st, lo, n);
+}
+
+// -------------------------------------------------- volume at one point
+// DD_ik(c_ijkl) u_l at (i, j) with boundary-aware 1-D rows (frame points).
+template <typename T, int ORD>
+__device__ __forceinline__ void volume_general(BlockRef B, gcp<T> u, int i, int j, T& r0, T& r1) {
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    gcp<T> c = gc<T>(B.coef);
+    gcp<T> u0 = u;
+    gcp<T> u1 = u + np;
+    const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
+    const long rj = (long)j * n1;
+    // x1 narrow, line j
+    const T a00 = d2_line<T, ORD>(c + K_C1111 * np + rj, u0 + rj, 1, i, n1);
+    const T a01 = d2_line<T, ORD>(c + K_C1112 * np + rj, u1 + rj, 1, i, n1);
+    const T a10 = d2_line<T, ORD>(c + K_C1112 * np + rj, u0 + rj, 1, i, n1);
+    const T a11 = d2_line<T, ORD>(c + K_C1212 * np + rj, u1 + rj, 1, i, n1);
+    // x2 narrow, line i
+    const T b00 = d2_line<T, ORD>(c + K_C2121 * np + i, u0 + i, n1, j, n2);
+    const T b01 = d2_line<T, ORD>(c + K_C2122 * np + i, u1 + i, n1, j, n2);
+    const T b10 = d2_line<T, ORD>(c + K_C2122 * np + i, u0 + i, n1, j, n2);
+    const T b11 = d2_line<T, ORD>(c + K_C2222 * np + i, u1 + i, n1, j, n2);
+    r0 = (a00 + a01) * ih1 * ih1 + (b00 + b01) * ih2 * ih2;
+    r1 = (a10 + a11) * ih1 * ih1 + (b10 + b11) * ih2 * ih2;
+    // D_1 (M D_2 u), M_jl = c_1j2l
+    T g0 = 0, g1 = 0;
+    d1_foreach<ORD>(i, n1, [&](int ii, double w) {
+        const T w20 = d1_line<T, ORD>(u0 + ii, n1, j, n2);
+        const T w21 = d1_line<T, ORD>(u1 + ii, n1, j, n2);
+        const long q = rj + ii;
+        const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
+        const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
+        g0 += static_cast<T>(w) * (m00 * w20 + m01 * w21);
+        g1 += static_cast<T>(w) * (m10 * w20 + m11 * w21);
+    });
+    // D_2 (M^T D_1 u), c_2j1l = c_1l2j
+    T e0 = 0, e1 = 0;
+    d1_foreach<ORD>(j, n2, [&](int jj, double w) {
+        const long rjj = (long)jj * n1;
+        const T w10 = d1_line<T, ORD>(u0 + rjj, 1, i, n1);
+        const T w11 = d1_line<T, ORD>(u1 + rjj, 1, i, n1);
+        const long q = rjj + i;
+        const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
+        const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
+        e0 += static_cast<T>(w) * (m00 * w10 + m10 * w11);
+        e1 += static_cast<T>(w) * (m01 * w10 + m11 * w11);
+    });
+    const T ihh = ih1 * ih2;
+    r0 += (g0 + e0) * ihh;
+    r1 += (g1 + e1) * ihh;
+}
+
+// --------------------------------------------------------- face helpers
+struct FacePt {
+    int i, j;   // grid point
+};
+
+__device__ __forceinline__ FacePt face_point(BlockRef B, int f, int t) {
+    const int a = f >> 1, s = f & 1;
+    FacePt q;
+    if (a == 0) {
+        q.i = s ? B.n1 - 1 : 0;
+        q.j = t;
+    } else {
+        q.i = t;
+        q.j = s ? B.n2 - 1 : 0;
+    }
+    return q;
+}
+
+// normal-narrow matrix N_a (c_ajal) and mixed matrix M (c_1j2l) at flat index q
+template <typename T>
+__device__ __forceinline__ void coef_mats(gcp<T> c, long np, long q, int a, T N[2][2], T M[2][2]) {
+    if (a == 0) {
+        N[0][0] = c[K_C1111 * np + q];
+        N[0][1] = N[1][0] = c[K_C1112 * np + q];
+        N[1][1] = c[K_C1212 * np + q];
+    } else {
+        N[0][0] = c[K_C2121 * np + q];
+        N[0][1] = N[1][0] = c[K_C2122 * np + q];
+        N[1][1] = c[K_C2222 * np + q];
+    }
+    M[0][0] = c[K_C1121 * np + q];
+    M[0][1] = c[K_C1122 * np + q];
+    M[1][0] = c[K_C1221 * np + q];
+    M[1][1] = c[K_C1222 * np + q];
+}
+
+// Jhat T_jl u_l = nu_a c_ajkl D_k u_l at point t of face f
+template <typename T, int ORD>
+__device__ __forceinline__ void traction_at(BlockRef B, gcp<T> u, int f, int t, T& tr0, T& tr1) {
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const int a = f >> 1;
+    const T nu = (f & 1) ? T(1) : T(-1);
+    const FacePt q = face_point(B, f, t);
+    const long p = (long)q.j * n1 + q.i;
+    gcp<T> c = gc<T>(B.coef);
+    T d1[2], d2[2];
+    for (int l = 0; l < 2; ++l) {
+        d1[l] = d1_line<T, ORD>(u + l * np + (long)q.j * n1, 1, q.i, n1) * T(1.0 / B.h1);
+        d2[l] = d1_line<T, ORD>(u + l * np + q.i, n1, q.j, n2) * T(1.0 / B.h2);
+    }
+    T N[2][2], M[2][2];
+    coef_mats(c, np, p, a, N, M);
+    if (a == 0) {   // c_1j1l D1 u_l + c_1j2l D2 u_l
+        tr0 = nu * (N[0][0] * d1[0] + N[0][1] * d1[1] + M[0][0] * d2[0] + M[0][1] * d2[1]);
+        tr1 = nu * (N[1][0] * d1[0] + N[1][1] * d1[1] + M[1][0] * d2[0] + M[1][1] * d2[1]);
+    } else {        // c_2j1l D1 u_l + c_2j2l D2 u_l, c_2j1l = M_lj
+        tr0 = nu * (M[0][0] * d1[0] + M[1][0] * d1[1] + N[0][0] * d2[0] + N[0][1] * d2[1]);
+        tr1 = nu * (M[0][1] * d1[0] + M[1][1] * d1[1] + N[1][0] * d2[0] + N[1][1] * d2[1]);
+    }
+}
+
+// displacement-type jump delta at point t of face f:
+//   HOM:  field on this face (minus the partner's field at an interface)
+//   DATA: -tau g (displacement) or -vsign tau V (interface)
+template <typename T, bool DATA>
+__device__ __forceinline__ void face_delta(const PassArgs& A, int b, int f, int t, int fld, const W3& tc, T& d0,
+                                           T& d1) {
+    BlockRef B = blk(A, b);
+    const GLB FaceDesc& F = B.face[f];
+    const long np = (long)B.n1 * B.n2;
+    if (!DATA) {
+        gcp<T> u = field_ptr<T>(A, b, fld);
+        const FacePt q = face_point(B, f, t);
+        const long p = (long)q.j * B.n1 + q.i;
+        d0 = u[p];
+        d1 = u[np + p];
+        if (F.kind == BC_INTERFACE) {
+            BlockRef P = blk(A, F.partner);
+            gcp<T> v = field_ptr<T>(A, F.partner, fld);
+            const int tp = F.reversed ? F.nf - 1 - t : t;
+            const FacePt qp = face_point(P, F.pface, tp);
+            const long pp = (long)qp.j * P.n1 + qp.i;
+            const long npp = (long)P.n1 * P.n2;
+            d0 -= v[pp];
+            d1 -= v[npp + pp];
+        }
+    } else {
+        d0 = 0;
+        d1 = 0;
+        if (F.kind == BC_DISPLACEMENT && F.g) {
+            const T tau = static_cast<T>(tval(A, F.item_g, tc));
+            gcp<T> g = gc<T>(F.g);
+            d0 = -tau * g[t];
+            d1 = -tau * g[F.nf + t];
+        } else if (F.kind == BC_INTERFACE && F.V) {
+            const T tau = static_cast<T>(F.vsign * tval(A, F.item_v, tc));
+            gcp<T> V = gc<T>(F.V);
+            d0 = -tau * V[t];
+            d1 = -tau * V[F.nf + t];
+        }
+    }
+}
+
+// Contribution of face f to r at (i, j) (dn = distance from the face along its
+// normal, t = index along the face).  DATA selects the data part (time
+// combination tc) instead of the homogeneous part acting on field `fld`.
+template <typename T, int ORD, bool DATA>
+__device__ __forceinline__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld, const W3& tc, T& r0, T& r1) {
+    using O = Op<ORD>;
+    BlockRef B = blk(A, b);
+    const double beta = A.beta;
+    const GLB FaceDesc& F = B.face[f];
+    const int a = f >> 1;
+    const long np = (long)B.n1 * B.n2;
+    gcp<T> c = gc<T>(B.coef);
+    const T nu = (f & 1) ? T(1) : T(-1);
+    const double ha = a == 0 ? B.h1 : B.h2;
+    const int na = a == 0 ? B.n1 : B.n2;
+    const int nt = a == 0 ? B.n2 : B.n1;
+    const double ht = a == 0 ? B.h2 : B.h1;
+    const T iw = T(1.0 / F.w);
+
+    if (F.kind == BC_TRACTION || F.kind == BC_ROBIN) {
+        if (dn != 0) return;
+        if (!DATA) {
+            gcp<T> u = field_ptr<T>(A, b, fld);
+            T tr0, tr1;
+            traction_at<T, ORD>(B, u, f, t, tr0, tr1);
+            r0 -= iw * tr0;
+            r1 -= iw * tr1;
+            if (F.kind == BC_ROBIN && F.U) {
+                gcp<T> U = gc<T>(F.U);
+                const FacePt q = face_point(B, f, t);
+                const long p = (long)q.j * B.n1 + q.i;
+                const T x0 = u[p], x1 = u[np + p];
+                r0 -= U[t] * x0 + U[F.nf + t] * x1;
+                r1 -= U[2 * F.nf + t] * x0 + U[3 * F.nf + t] * x1;
+            }
+        } else if (F.g) {
+            const T tau = static_cast<T>(tval(A, F.item_g, tc));
+            gcp<T> g = gc<T>(F.g);
+            r0 += tau * g[t];
+            r1 += tau * g[F.nf + t];
+        }
+        return;
+    }
+    // displacement or interface
+    const bool itf = F.kind == BC_INTERFACE;
+    const T half = itf ? T(0.5) : T(1);
+    const FacePt q = face_point(B, f, t);
+    const long pf = (long)q.j * B.n1 + q.i;
+    T d0, d1;
+    face_delta<T, DATA>(A, b, f, t, fld, tc, d0, d1);
+    T N[2][2], M[2][2];
+    coef_mats(c, np, pf, a, N, M);
+    if (dn < O::REACH) {
+        // normal part: nu_a D1[face row][dn] / H_a[dn] c_alaj delta_l
+        const double hn = hnorm<ORD>(dn, na);
+        const T cf = half * static_cast<T>(-O::d1b(0, dn) / (ha * ha * hn));
+        r0 += cf * (N[0][0] * d0 + N[0][1] * d1);
+        r1 += cf * (N[1][0] * d0 + N[1][1] * d1);
+    }
+    if (dn != 0) return;
+    // tangential part: (1/w) (H_t^{-1} D_t^T H_t qv)(t), qv = nu c_altj delta_l
+    {
+        auto qv = [&](int tt, T& q0, T& q1) {
+            T e0, e1;
+            face_delta<T, DATA>(A, b, f, tt, fld, tc, e0, e1);
+            const FacePt qq = face_point(B, f, tt);
+            T Nq[2][2], Mq[2][2];
+            coef_mats(c, np, (long)qq.j * B.n1 + qq.i, a, Nq, Mq);
+            if (a == 0) {   // c_1l2j = M_lj
+                q0 = nu * (Mq[0][0] * e0 + Mq[1][0] * e1);
+                q1 = nu * (Mq[0][1] * e0 + Mq[1][1] * e1);
+            } else {        // c_2l1j = c_1j2l = M_jl
+                q0 = nu * (Mq[0][0] * e0 + Mq[0][1] * e1);
+                q1 = nu * (Mq[1][0] * e0 + Mq[1][1] * e1);
+            }
+        };
+        T qt0, qt1;
+        qv(t, qt0, qt1);
+        T dq0 = 0, dq1 = 0;
+        d1_foreach<ORD>(t, nt, [&](int tt, double w) {
+            T q0, q1;
+            qv(tt, q0, q1);
+            dq0 += static_cast<T>(w) * (q0 - qt0);
+            dq1 += static_cast<T>(w) * (q1 - qt1);
+        });
+        const T iht = T(1.0 / ht);
+        T s0v = -dq0 * iht, s1v = -dq1 * iht;
+        if (t == 0) {
+            const T ih0 = T(1.0 / (ht * hnorm<ORD>(0, nt)));
+            s0v -= qt0 * ih0;
+            s1v -= qt1 * ih0;
+        }
+        if (t == nt - 1) {
+            const T ihN = T(1.0 / (ht * hnorm<ORD>(nt - 1, nt)));
+            s0v += qt0 * ihN;
+            s1v += qt1 * ihN;
+        }
+        r0 += half * iw * s0v;
+        r1 += half * iw * s1v;
+    }
+    // penalty
+    if (!itf) {
+        const T pen = static_cast<T>(beta * 2.0) * iw * iw;
+        r0 -= pen * (N[0][0] * d0 + N[0][1] * d1);
+        r1 -= pen * (N[1][0] * d0 + N[1][1] * d1);
+    } else {
+        BlockRef P = blk(A, F.partner);
+        const int tp = F.reversed ? F.nf - 1 - t : t;
+        const FacePt qp = face_point(P, F.pface, tp);
+        const long npp = (long)P.n1 * P.n2;
+        T Np[2][2], Mp[2][2];
+        coef_mats(gc<T>(P.coef), npp, (long)qp.j * P.n1 + qp.i, F.pface >> 1, Np, Mp);
+        const T ipw = T(1.0 / F.pw);
+        const T qf = static_cast<T>(beta * 2.0 * 0.25);
+        T Z[2][2];
+        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 2; ++y) Z[x][y] = qf * (N[x][y] * iw + Np[x][y] * ipw);
+        r0 -= iw * (Z[0][0] * d0 + Z[0][1] * d1);
+        r1 -= iw * (Z[1][0] * d0 + Z[1][1] * d1);
+        // traction average
+        if (!DATA) {
+            T tu0, tu1, tv0, tv1;
+            traction_at<T, ORD>(B, field_ptr<T>(A, b, fld), f, t, tu0, tu1);
+            traction_at<T, ORD>(P, field_ptr<T>(A, F.partner, fld), F.pface, tp, tv0, tv1);
+            r0 -= T(0.5) * iw * (tu0 + tv0);
+            r1 -= T(0.5) * iw * (tu1 + tv1);
+        } else if (F.Th) {
+            const T tau = static_cast<T>(tval(A, F.item_v, tc));
+            gcp<T> Th = gc<T>(F.Th);
+            r0 += tau * Th[t];
+            r1 += tau * Th[F.nf + t];
+        }
+    }
+}
+
+// all SAT contributions of the four faces at (i, j)
+template <typename T, int ORD, bool DATA>
+__device__ __forceinline__ void sat_point(const PassArgs& A, int b, int i, int j, int fld, const W3& tc, T& r0, T& r1) {
+    using O = Op<ORD>;
+    BlockRef B = blk(A, b);
+    const int n1 = B.n1, n2 = B.n2;
+    if (i < O::REACH) face_sat<T, ORD, DATA>(A, b, 0, i, j, fld, tc, r0, r1);
+    if (n1 - 1 - i < O::REACH) face_sat<T, ORD, DATA>(A, b, 1, n1 - 1 - i, j, fld, tc, r0, r1);
+    if (j < O::REACH) face_sat<T, ORD, DATA>(A, b, 2, j, i, fld, tc, r0, r1);
+    if (n2 - 1 - j < O::REACH) face_sat<T, ORD, DATA>(A, b, 3, n2 - 1 - j, i, fld, tc, r0, r1);
+}
+
+// sources (and, in the frame, the forcing) at flat point p
+template <typename T>
+__device__ __forceinline__ void point_sources(const PassArgs& A, const Range& rg, long p, const W3& tc, T& r0, T& r1) {
+    for (int e = rg.beg; e < rg.end; ++e) {
+        const GLB Entry& E = entry(A, e);
+        if (E.kind == 0 && E.p == p) {
+            const double tau = tval(A, E.id, tc);
+            r0 += static_cast<T>(E.c0 * tau);
+            r1 += static_cast<T>(E.c1 * tau);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void point_data(BlockRef B, long p, const PassArgs& A, const Range& rg, const W3& tc,
+                                           T& r0, T& r1) {
+    if (B.force) {
+        gcp<T> F = gc<T>(B.force);
+        const T tau = static_cast<T>(tval(A, B.item_f, tc));
+        r0 += tau * F[p];
+        r1 += tau * F[(long)B.n1 * B.n2 + p];
+    }
+    point_sources<T>(A, rg, p, tc, r0, r1);
+}
+
+__device__ __forceinline__ int find_block(const PassArgs& A, int wg, bool frame) {
+    int b = 0;
+    for (int k = 1; k < A.nblocks; ++k) {
+        const int beg = frame ? blk(A, k).frame_beg : blk(A, k).tile_beg;
+        if (wg >= beg) b = k;
+    }
+    return b;
+}
+
+// ---------------------------------------------------------------- frame
+// Two lanes per frame point: in the RK sweeps lane s evaluates L and the data
+// of field s (u / v, or A1 / A2); for sbpe_apply lane 0 evaluates L and lane 1
+// the data.  The partial results are exchanged between the lane pair and lane
+// s writes component s of the outputs.
+template <typename T, int ORD>
+__global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
+    constexpr int R = Frame<ORD>::R;
+    const int wg = blockIdx.x;
+    const int b = find_block(A, wg, true);
+    BlockRef B = blk(A, b);
+    const int sub = threadIdx.x & 1;
+    const int k = (wg - B.frame_beg) * FRAME_PTS + (threadIdx.x >> 1);
+    const Range rg = load_range(A.frame_ranges, wg);
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const bool valid = k < B.frame_n;
+    const int kk0 = valid ? k : 0;
+    int i, j;
+    if (kk0 < R * n1) {
+        j = kk0 / n1;
+        i = kk0 - j * n1;
+    } else if (kk0 < 2 * R * n1) {
+        const int kk = kk0 - R * n1;
+        j = n2 - R + kk / n1;
+        i = kk % n1;
+    } else {
+        const int kk = kk0 - 2 * R * n1;
+        const int row = kk / (2 * R), cc = kk % (2 * R);
+        j = R + row;
+        i = cc < R ? cc : n1 - 2 * R + cc;
+    }
+    const long p = (long)j * n1 + i;
+    const W3 none{0.0, 0.0, 0.0};
+    const W3 ca = weights_a(A), cb = weights_b(A);
+    T l0 = 0, l1 = 0, d0 = 0, d1 = 0;
+    if (valid) {
+        if (A.pass == PASS_APPLY) {
+            if (sub == 0) {
+                volume_general<T, ORD>(B, field_ptr<T>(A, b, FLD_IN), i, j, l0, l1);
+                sat_point<T, ORD, false>(A, b, i, j, FLD_IN, none, l0, l1);
+            } else if (ca.any()) {
+                sat_point<T, ORD, true>(A, b, i, j, FLD_IN, ca, d0, d1);
+                point_data<T>(B, p, A, rg, ca, d0, d1);
+            }
+        } else {
+            const int fld = A.pass == PASS_RK1 ? (sub ? FLD_V : FLD_U) : (sub ? FLD_A2 : FLD_A1);
+            volume_general<T, ORD>(B, field_ptr<T>(A, b, fld), i, j, l0, l1);
+            sat_point<T, ORD, false>(A, b, i, j, fld, none, l0, l1);
+            const W3 cw = sub ? cb : ca;
+            if (cw.any()) {
+                sat_point<T, ORD, true>(A, b, i, j, fld, cw, d0, d1);
+                point_data<T>(B, p, A, rg, cw, d0, d1);
+            }
+        }
+    }
+    // exchange with the partner lane
+    const T ol0 = __shfl_xor(l0, 1), ol1 = __shfl_xor(l1, 1);
+    const T od0 = __shfl_xor(d0, 1), od1 = __shfl_xor(d1, 1);
+    if (!valid) return;
+    const T irho = gc<T>(B.coef)[(long)K_IRHO * np + p];
+    const long q = (long)sub * np + p;   // component written by this lane
+    if (A.pass == PASS_APPLY) {
+        // lane 0 holds L, lane 1 the data
+        const T L = sub ? ol1 : l0;
+        const T D = sub ? d1 : od0;
+        gm<T>(A.out[b])[q] = irho * (L + D);
+        return;
+    }
+    // field 0 (lane 0) and field 1 (lane 1) results, component sub
+    const T La = sub ? ol1 : l0;     // L f0, component sub
+    const T Lb = sub ? l1 : ol0;     // L f1, component sub
+    const T Da = sub ? od1 : d0;
+    const T Db = sub ? d1 : od0;
+    const T dt = static_cast<T>(A.dt);
+    if (A.pass == PASS_RK1) {
+        gm<T>(B.a1)[q] = irho * (La + Da);
+        gm<T>(B.a2)[q] = irho * (La + T(0.5) * dt * Lb + Db);
+        return;
+    }
+    const T A1 = gc<T>(B.a1)[q], A2 = gc<T>(B.a2)[q];
+    gp<T> u = gm<T>(B.u);
+    gp<T> v = gm<T>(B.v);
+    const T dt2 = dt * dt;
+    const T A3 = A2 + T(0.25) * dt2 * irho * La;
+    const T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * irho * (Lb + Db);
+    const T uo = u[q], vo = v[q];
+    const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
+    u[q] = un;
+    v[q] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
+    if (A.rec_out) {
+        gp<double> ro = gm<double>(A.rec_out);
+        for (int e = rg.beg; e < rg.end; ++e) {
+            const GLB Entry& E = entry(A, e);
+            if (E.kind == 1 && E.p == p) ro[2 * E.id + sub] = E.c0 * static_cast<double>(un);
+        }
+    }
+}
+
+// ------------------------------------------------------------- interior
+// Marching kernel: one wave covers the 64 columns i0 .. i0+63 and writes the
+// OUTW = 64 - 2H central ones (H = half width of the interior stencils), so
+// every x1 neighbour a lane needs is another lane's column and no halo
+// column is loaded.  The wave marches over the rows jb .. je of its tile;
+// for output row j it
+//   * stages the input fields of the leading row j+H in an LDS ring of 2H+1
+//     rows (x1 neighbours for the staged row, x2 window of the own column),
+//   * forms E(j+H) = M^T D_1 w (M_jl = c_1j2l) into a register window,
+//   * forms G(j) = M D_2 w at all 64 columns into an LDS row, then D_1 G,
+//   * evaluates the narrow x1 term from the staged row j and the x1
+//     coefficient row, the narrow x2 term from the ring and the register
+//     window of the x2 coefficients, and D_2 E from the E window,
+//   * applies the pass arithmetic (sbpe_internal.h) and stores row j.
+// The row loop is unrolled by 2H+1, so every ring slot and register window
+// position is a compile-time constant (no window shifting).  The global
+// loads of the next row are issued before the arithmetic of the current one
+// into a buffer that is consumed at the start of the next row.
+template <typename T, int NS>
+struct Lead {
+    T w[NS];   // input fields at (i, j + H)
+    T b2[3];   // x2-narrow coefficients at (i, j + H)
+    T m[4];    // mixed coefficients at (i, j + H)
+    T b1[3];   // x1-narrow coefficients at (i, j)
+};
+
+template <typename T, int ORD, int PASS>
+__global__ void __launch_bounds__(64) k_march(PassArgs A) {
+    using O = Op<ORD>;
+    constexpr int HF = O::HALF;
+    constexpr int NW = 2 * HF + 1;
+    constexpr int NF = PASS == PASS_APPLY ? 1 : 2;
+    constexpr int NS = 2 * NF;
+    constexpr int R = Frame<ORD>::R;
+    constexpr T C1 = static_cast<T>(O::d1i(HF + 1));
+    constexpr T C2 = static_cast<T>(d1_outer<ORD>());
+    __shared__ T s_x[NW][NS][64];
+    __shared__ T s_b[3][64];
+    __shared__ T s_g[NS][64];
+
+    // workgroup order: consecutive tiles on the same XCD (ids are dealt round-robin to 8 XCDs)
+    const int total = A.total_tiles;
+    const int per = (total + 7) / 8;
+    const int wg = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (wg >= total) return;
+    const int b = find_block(A, wg, false);
+    BlockRef B = blk(A, b);
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const int tl = wg - B.tile_beg;
+    const int ty = tl / B.tiles_x, tx = tl - ty * B.tiles_x;
+    const int lane = threadIdx.x;
+    const int i = R - HF + tx * (64 - 2 * HF) + lane;
+    const bool act = lane >= HF && lane < 64 - HF && i <= n1 - 1 - R;
+    const int ic = i < n1 - 1 ? i : n1 - 1;
+    const int jb = R + ty * B.tile_y;
+    const int je = (jb + B.tile_y < n2 - R ? jb + B.tile_y : n2 - R) - 1;
+    gcp<T> c = gc<T>(B.coef);
+    gcp<T> fin[NF];
+    if constexpr (PASS == PASS_APPLY) {
+        fin[0] = gc<T>(A.in[b]);
+    } else if constexpr (PASS == PASS_RK1) {
+        fin[0] = gc<T>(B.u);
+        fin[1] = gc<T>(B.v);
+    } else {
+        fin[0] = gc<T>(B.a1);
+        fin[1] = gc<T>(B.a2);
+    }
+    const bool force = B.force != nullptr;
+    gcp<T> frc = gc<T>(B.force);
+    const Range rg = load_range(A.tile_ranges, wg);
+    const W3 ca = weights_a(A), cb = weights_b(A);
+    T tauf_a = 0, tauf_b = 0;
+    if (force) {
+        tauf_a = static_cast<T>(tval(A, B.item_f, ca));
+        tauf_b = static_cast<T>(tval(A, B.item_f, cb));
+    }
+    const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
+    const T i11 = ih1 * ih1, i22 = ih2 * ih2, i12 = ih1 * ih2;
+    const T dt = static_cast<T>(A.dt);
+
+    // interior first derivative (times h) from the four neighbours
+    auto d1 = [&](T um2, T um1, T up1, T up2) -> T {
+        if constexpr (HF == 2) return C1 * (up1 - um1) + C2 * (up2 - um2);
+        else return C1 * (up1 - um1);
+    };
+    // leading-row loads for output row j
+    auto load_lead = [&](int j, Lead<T, NS>& L) {
+        const long qn = (long)(j + HF) * n1 + ic;
+        const long qj = (long)j * n1 + ic;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) L.w[s] = fin[s >> 1][(s & 1) * np + qn];
+        L.b2[0] = c[K_C2121 * np + qn];
+        L.b2[1] = c[K_C2122 * np + qn];
+        L.b2[2] = c[K_C2222 * np + qn];
+        L.m[0] = c[K_C1121 * np + qn];
+        L.m[1] = c[K_C1122 * np + qn];
+        L.m[2] = c[K_C1221 * np + qn];
+        L.m[3] = c[K_C1222 * np + qn];
+        L.b1[0] = c[K_C1111 * np + qj];
+        L.b1[1] = c[K_C1112 * np + qj];
+        L.b1[2] = c[K_C1212 * np + qj];
+    };
+
+    // register windows indexed by ring slot: slot(r) = (r - jb + HF) mod NW
+    T b2w[3][NW];     // x2-narrow coefficients
+    T mw[4][NW];      // mixed coefficients
+    T ew[NS][NW];     // E = M^T D_1 w
+
+    // E at a staged row (slot s), from the x1 neighbours in the ring
+    auto e_row = [&](const int s) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            T w1[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int x = 2 * f + q;
+                w1[q] = d1(HF > 1 ? s_x[s][x][lane - 2 < 0 ? 0 : lane - 2] : T(0),
+                           s_x[s][x][lane - 1 < 0 ? 0 : lane - 1], s_x[s][x][lane + 1 > 63 ? 63 : lane + 1],
+                           HF > 1 ? s_x[s][x][lane + 2 > 63 ? 63 : lane + 2] : T(0));
+            }
+            ew[2 * f][s] = mw[0][s] * w1[0] + mw[2][s] * w1[1];
+            ew[2 * f + 1][s] = mw[1][s] * w1[0] + mw[3][s] * w1[1];
+        }
+    };
+
+    // prologue: rows jb-HF .. jb+HF-1 staged, their E formed
+    {
+#pragma unroll
+        for (int r = 0; r < 2 * HF; ++r) {
+            const long q = (long)(jb - HF + r) * n1 + ic;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) s_x[r][s][lane] = fin[s >> 1][(s & 1) * np + q];
+            b2w[0][r] = c[K_C2121 * np + q];
+            b2w[1][r] = c[K_C2122 * np + q];
+            b2w[2][r] = c[K_C2222 * np + q];
+            mw[0][r] = c[K_C1121 * np + q];
+            mw[1][r] = c[K_C1122 * np + q];
+            mw[2][r] = c[K_C1221 * np + q];
+            mw[3][r] = c[K_C1222 * np + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2 * HF; ++r) e_row(r);
+    }
+
+    Lead<T, NS> P;
+    load_lead(jb, P);
+
+    // one output row; K is the position in the unrolled group (slot of row j is K + HF)
+    auto step = [&](auto KC, const int j) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int s0 = (K + HF) % NW;        // row j
+        constexpr int sn = (K + 2 * HF) % NW;    // leading row j + HF
+        __builtin_amdgcn_sched_barrier(0);
+        // (1) consume the leading-row buffer
+#pragma unroll
+        for (int s = 0; s < NS; ++s) s_x[sn][s][lane] = P.w[s];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_b[k][lane] = P.b1[k];
+            b2w[k][sn] = P.b2[k];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) mw[m][sn] = P.m[m];
+        const T b1c[3] = {P.b1[0], P.b1[1], P.b1[2]};
+        // (2) per-point operands of row j, then the leading row of j + 1
+        const long p = (long)j * n1 + ic;
+        const T irho = c[K_IRHO * np + p];
+        T f0 = 0, f1 = 0;
+        if (force) {
+            f0 = frc[p];
+            f1 = frc[np + p];
+        }
+        T xo[4];
+        if constexpr (PASS == PASS_RK2) {
+            gcp<T> u = gc<T>(B.u);
+            gcp<T> v = gc<T>(B.v);
+            xo[0] = u[p];
+            xo[1] = u[np + p];
+            xo[2] = v[p];
+            xo[3] = v[np + p];
+        }
+        if (j < je) load_lead(j + 1, P);
+        __syncthreads();
+        // (3) E at the leading row
+        e_row(sn);
+        // (4) G at row j (all 64 columns), narrow terms
+        T lx[NF][2];
+        T wc[NS];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            T wcol[2][NW];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int k = 0; k < NW; ++k) wcol[q][k] = s_x[(K + k) % NW][2 * f + q][lane];
+            T w2[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                w2[q] = d1(HF > 1 ? wcol[q][0] : T(0), wcol[q][HF - 1], wcol[q][HF + 1],
+                           HF > 1 ? wcol[q][NW - 1] : T(0));
+                wc[2 * f + q] = wcol[q][HF];
+            }
+            s_g[2 * f][lane] = mw[0][s0] * w2[0] + mw[1][s0] * w2[1];
+            s_g[2 * f + 1][lane] = mw[2][s0] * w2[0] + mw[3][s0] * w2[1];
+            T bc[3][NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) bc[m][k] = b2w[m][(K + k) % NW];
+            const T bx0 = d2_interior<T, ORD>(&bc[0][HF], &wcol[0][HF], 1);   // c2121 u1
+            const T bx1 = d2_interior<T, ORD>(&bc[1][HF], &wcol[1][HF], 1);   // c2122 u2
+            const T bx2 = d2_interior<T, ORD>(&bc[1][HF], &wcol[0][HF], 1);   // c2122 u1
+            const T bx3 = d2_interior<T, ORD>(&bc[2][HF], &wcol[1][HF], 1);   // c2222 u2
+            // x1 rows of the staged row j and of the x1 coefficients
+            T ur[2][NW], br[3][NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                const int l = lane + k - HF;
+                const int lc = l < 0 ? 0 : (l > 63 ? 63 : l);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) ur[q][k] = k == HF ? wcol[q][HF] : s_x[s0][2 * f + q][lc];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) br[m][k] = k == HF ? b1c[m] : s_b[m][lc];
+            }
+            const T ax0 = d2_interior<T, ORD>(&br[0][HF], &ur[0][HF], 1);
+            const T ax1 = d2_interior<T, ORD>(&br[1][HF], &ur[1][HF], 1);
+            const T ax2 = d2_interior<T, ORD>(&br[1][HF], &ur[0][HF], 1);
+            const T ax3 = d2_interior<T, ORD>(&br[2][HF], &ur[1][HF], 1);
+            lx[f][0] = (ax0 + ax1) * i11 + (bx0 + bx1) * i22;
+            lx[f][1] = (ax2 + ax3) * i11 + (bx2 + bx3) * i22;
+        }
+        __syncthreads();
+        // (5) D_1 G and D_2 E
+        T L[NF][2];
+#pragma unroll
+        for (int x = 0; x < NS; ++x) {
+            const int lm2 = lane - 2 < 0 ? 0 : lane - 2, lm1 = lane - 1 < 0 ? 0 : lane - 1;
+            const int lp1 = lane + 1 > 63 ? 63 : lane + 1, lp2 = lane + 2 > 63 ? 63 : lane + 2;
+            const T ag = d1(HF > 1 ? s_g[x][lm2] : T(0), s_g[x][lm1], s_g[x][lp1], HF > 1 ? s_g[x][lp2] : T(0));
+            const T ae = d1(HF > 1 ? ew[x][K % NW] : T(0), ew[x][(K + HF - 1) % NW], ew[x][(K + HF + 1) % NW],
+                            HF > 1 ? ew[x][(K + 2 * HF) % NW] : T(0));
+            L[x >> 1][x & 1] = lx[x >> 1][x & 1] + (ag + ae) * i12;
+        }
+        // (6) data, pass arithmetic, stores
+        if (act) {
+            const long po = (long)j * n1 + i;
+            T da0 = tauf_a * f0, da1 = tauf_a * f1, db0 = tauf_b * f0, db1 = tauf_b * f1;
+            if (rg.end > rg.beg) {
+                if (ca.any()) point_sources<T>(A, rg, po, ca, da0, da1);
+                if (NF == 2 && cb.any()) point_sources<T>(A, rg, po, cb, db0, db1);
+            }
+            if constexpr (PASS == PASS_APPLY) {
+                gp<T> o = gm<T>(A.out[b]);
+                o[po] = irho * (L[0][0] + da0);
+                o[np + po] = irho * (L[0][1] + da1);
+            } else if constexpr (PASS == PASS_RK1) {
+                gp<T> a1 = gm<T>(B.a1);
+                gp<T> a2 = gm<T>(B.a2);
+                const T hdt = T(0.5) * dt;
+                a1[po] = irho * (L[0][0] + da0);
+                a1[np + po] = irho * (L[0][1] + da1);
+                a2[po] = irho * (L[0][0] + hdt * L[NF - 1][0] + db0);
+                a2[np + po] = irho * (L[0][1] + hdt * L[NF - 1][1] + db1);
+            } else {
+                gp<T> u = gm<T>(B.u);
+                gp<T> v = gm<T>(B.v);
+                const T dt2 = dt * dt;
+                const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
+                T un[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const T A1 = wc[q];
+                    const T A2 = wc[2 + q];
+                    const T A3 = A2 + q4 * irho * L[0][q];
+                    const T A4 = T(2) * A2 - A1 + q2 * irho * (L[1][q] + (q ? db1 : db0));
+                    un[q] = xo[q] + dt * xo[2 + q] + s6 * (A1 + A2 + A3);
+                    u[q * np + po] = un[q];
+                    v[q * np + po] = xo[2 + q] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4);
+                }
+                if (A.rec_out && rg.end > rg.beg) {
+                    gp<double> ro = gm<double>(A.rec_out);
+                    for (int e = rg.beg; e < rg.end; ++e) {
+                        const GLB Entry& E = entry(A, e);
+                        if (E.kind == 1 && E.p == po) {
+                            ro[2 * E.id] = E.c0 * static_cast<double>(un[0]);
+                            ro[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    };
+
+    for (int j0 = jb; j0 <= je; j0 += NW) {
+        step(std::integral_constant<int, 0>{}, j0);
+        if (j0 + 1 <= je) step(std::integral_constant<int, 1>{}, j0 + 1);
+        if (j0 + 2 <= je) step(std::integral_constant<int, 2>{}, j0 + 2);
+        if constexpr (NW > 3) {
+            if (j0 + 3 <= je) step(std::integral_constant<int, 3 % NW>{}, j0 + 3);
+            if (j0 + 4 <= je) step(std::integral_constant<int, 4 % NW>{}, j0 + 4);
+        }
+    }
+}
+
+// ---------------------------------------------------------- tau table
+// tau[(s * nitems + it) * 3 + k] = tau_it(t0 + s dt + c_k dt), c = (0, 1/2, 1)
+__global__ void __launch_bounds__(256) k_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt,
+                                             double* tau) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long)nitems * nsteps) return;
+    const int s = (int)(idx / nitems), it = (int)(idx - (long)s * nitems);
+    const GLB TimeFn& g = ((const GLB TimeFn*)items)[it];
+    TimeFn f;
+    f.kind = g.kind;
+    f.pad = 0;
+    f.p[0] = g.p[0];
+    f.p[1] = g.p[1];
+    const double t = t0 + s * dt;
+    gp<double> o = gm<double>(tau) + 3 * idx;
+    o[0] = tfun(f, t);
+    o[1] = tfun(f, t + 0.5 * dt);
+    o[2] = tfun(f, t + dt);
+}
+
+// -------------------------------------------------------------- energy
+// per point H_p rho~_p (|v|^2 - u . a) with a = rho~^{-1} D^tot u already in a1;
+// partial sums per workgroup in FP64, then one workgroup sums them in order.
+template <typename T, int ORD>
+__global__ void __launch_bounds__(256) k_energy_partial(const BlockDesc* blocks, int nblocks, double* partial) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    const long stride = (long)gridDim.x * 256;
+    for (int b = 0; b < nblocks; ++b) {
+        const GLB BlockDesc& B = ((const GLB BlockDesc*)blocks)[b];
+        const long np = (long)B.n1 * B.n2;
+        gcp<T> u = gc<T>(B.u);
+        gcp<T> v = gc<T>(B.v);
+        gcp<T> a = gc<T>(B.a1);
+        gcp<T> c = gc<T>(B.coef);
+        for (long p = gid; p < np; p += stride) {
+            const int j = (int)(p / B.n1), i = (int)(p - (long)j * B.n1);
+            const double H = B.h1 * B.h2 * hnorm<ORD>(i, B.n1) * hnorm<ORD>(j, B.n2);
+            const double rt = 1.0 / static_cast<double>(c[(long)K_IRHO * np + p]);
+            const double v0 = v[p], v1 = v[np + p];
+            const double x0 = u[p], x1 = u[np + p];
+            acc += H * rt * (v0 * v0 + v1 * v1 - x0 * static_cast<double>(a[p]) - x1 * static_cast<double>(a[np + p]));
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_energy_final(const double* partial, int n, double* out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) acc += partial[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = 0.5 * red[0];
+}
+
+// ---------------------------------------------------------- launchers
+template <typename T, int ORD>
+static void launch_march_t(const PassArgs& a, int total_tiles, hipStream_t s) {
+    const dim3 g(((total_tiles + 7) / 8) * 8), bl(64);
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_march<T, ORD, PASS_APPLY>), g, bl, 0, s, a);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK1>), g, bl, 0, s, a);
+    else hipLaunchKernelGGL((k_march<T, ORD, PASS_RK2>), g, bl, 0, s, a);
+}
+
+int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (total_tiles <= 0) return 0;
+    PassArgs b = a;
+    b.total_tiles = total_tiles;
+    if (dtype == 0) {
+        if (order == 4) launch_march_t<double, 4>(b, total_tiles, s);
+        else launch_march_t<double, 2>(b, total_tiles, s);
+    } else {
+        if (order == 4) launch_march_t<float, 4>(b, total_tiles, s);
+        else launch_march_t<float, 2>(b, total_tiles, s);
+    }
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_frame(int dtype, int order, const PassArgs& a, int total_frame_wg, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (total_frame_wg <= 0) return 0;
+    const dim3 g(total_frame_wg), b(FRAME_WG);
+    if (dtype == 0) {
+        if (order == 4) hipLaunchKernelGGL((k_frame<double, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_frame<double, 2>), g, b, 0, s, a);
+    } else {
+        if (order == 4) hipLaunchKernelGGL((k_frame<float, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_frame<float, 2>), g, b, 0, s, a);
+    }
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt, double* tau, void* stream) {
+    const long n = (long)nitems * nsteps;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_tau, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), items,
+                       nitems, nsteps, t0, dt, tau);
+    return static_cast<int>(hipGetLastError());
+}
+
+int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
+                  int npartial, double* result_dev, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == 0) {
+        if (order == 4) hipLaunchKernelGGL((k_energy_partial<double, 4>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
+        else hipLaunchKernelGGL((k_energy_partial<double, 2>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
+    } else {
+        if (order == 4) hipLaunchKernelGGL((k_energy_partial<float, 4>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
+        else hipLaunchKernelGGL((k_energy_partial<float, 2>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
+    }
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, partial_dev, npartial, result_dev);
+    return static_cast<int>(hipGetLastError());
+}
+
+const char* hip_error_string(int code) { return hipGetErrorString(static_cast<hipError_t>(code)); }
+
+}  // namespace sbpe

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -456,6 +457,10 @@ static long frame_index(const HostBlock& B, int R, int i, int j) {
 static sbpe_status build_plan(sbpe_ctx* c) {
     const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
     const int nb = (int)c->blocks.size();
+    // interior tiles: 64 lanes, of which the central 64 - 2 * half-width are written
+    const int tile_w = TILE_LANES - 2 * (c->order / 2);
+    int tile_y = TILE_Y_DEFAULT;
+    if (const char* e = std::getenv("SBPE_TILE_ROWS")) tile_y = std::max(1, std::atoi(e));
     c->desc.assign(nb, BlockDesc{});
     int tiles = 0, fwg = 0;
     for (int b = 0; b < nb; ++b) {
@@ -473,8 +478,9 @@ static sbpe_status build_plan(sbpe_ctx* c) {
         D.u = H.u;
         D.v = H.v;
         const int ix = H.n1 - 2 * R, iy = H.n2 - 2 * R;
-        D.tiles_x = ix > 0 ? (ix + TILE_X - 1) / TILE_X : 0;
-        D.tiles_y = iy > 0 ? (iy + TILE_Y - 1) / TILE_Y : 0;
+        D.tile_y = tile_y;
+        D.tiles_x = ix > 0 ? (ix + tile_w - 1) / tile_w : 0;
+        D.tiles_y = iy > 0 ? (iy + tile_y - 1) / tile_y : 0;
         D.tile_beg = tiles;
         tiles += D.tiles_x * D.tiles_y;
         D.frame_n = 2 * R * H.n1 + 2 * R * std::max(0, H.n2 - 2 * R);
@@ -522,7 +528,7 @@ static sbpe_status build_plan(sbpe_ctx* c) {
         x.e.p = j * H.n1 + i;
         if (i >= R && i <= H.n1 - 1 - R && j >= R && j <= H.n2 - 1 - R) {
             x.frame = 0;
-            x.wg = D.tile_beg + ((j - R) / TILE_Y) * D.tiles_x + (i - R) / TILE_X;
+            x.wg = D.tile_beg + ((j - R) / D.tile_y) * D.tiles_x + (i - R) / tile_w;
         } else {
             x.frame = 1;
             x.wg = D.frame_beg + (int)(frame_index(H, R, i, j) / FRAME_PTS);

@@ -68,6 +68,7 @@ struct BlockDesc {
     void* a2;
     FaceDesc face[4];
     int tiles_x, tiles_y, tile_beg;     // interior launch geometry
+    int tile_y, pad_t;                  // output rows per interior tile
     int frame_n, frame_wg, frame_beg;   // frame launch geometry (points, workgroups, first workgroup)
 };
 
@@ -108,9 +109,10 @@ struct PassArgs {
     double* rec_out;             // receiver slots of the current step [nrec*16][2], or null
 };
 
-// interior tile: one wave of 64 columns marching over TILE_Y rows
-constexpr int TILE_X = 64;
-constexpr int TILE_Y = 16;
+// interior tile: one wave spanning 64 columns writes the central
+// 64 - 2 * half-width of them and marches over tile_y rows
+constexpr int TILE_LANES = 64;
+constexpr int TILE_Y_DEFAULT = 10;
 constexpr int FRAME_WG = 256;
 constexpr int FRAME_PTS = FRAME_WG / 2;   // frame points per workgroup (two lanes per point)
 

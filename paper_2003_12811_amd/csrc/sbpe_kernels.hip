@@ -3,10 +3,11 @@
 // One right-hand-side evaluation is split by grid region:
 //   * k_march: points at least Frame<ORD>::R from every face, where all 1-D
 //     operators use their repeating interior stencils (Sec. 4.3-4.7).  One
-//     wave owns 64 consecutive columns and marches over TILE_Y rows: input
-//     rows are staged once in an LDS ring (x1 neighbours and the x2 window of
-//     the own column), coefficient windows stay in registers, and the two
-//     mixed terms go through LDS rows of their inner products;
+//     wave spans 64 consecutive columns, writes the central 64 - 2H of them
+//     and marches over the rows of its tile: input rows are staged once in
+//     an LDS ring (x1 neighbours and the x2 window of the own column),
+//     coefficient windows stay in registers, and the mixed terms go through
+//     an LDS row (D_1 G) and a register window (D_2 E);
 //   * k_frame: the band of width R along the faces, where the boundary
 //     closures of D1 and D2^FC and the SATs of Sec. 5 and 6 act; one thread
 //     per point, closure rows unrolled from compile-time tables.
@@ -24,6 +25,8 @@
 // Second differences are formed from differences u_m - u_r first (every row of
 // D2^FC and D1 sums to zero), which keeps FP32 cancellation small.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "sbpe_internal.h"
 #include "sbpe_tables.h"
@@ -66,6 +69,13 @@ template <> struct Op<2> {
     __host__ __device__ static constexpr double d1i(int k) { return O2_D1I[k]; }
     __host__ __device__ static constexpr double hb(int k) { return O2_H[k]; }
 };
+
+// weight of u_{i+2} - u_{i-2} in the interior first derivative (0 at order 2)
+template <int ORD>
+__host__ __device__ constexpr double d1_outer() {
+    if constexpr (Op<ORD>::HALF > 1) return Op<ORD>::d1i(Op<ORD>::HALF + 2);
+    else return 0.0;
+}
 
 // dimensionless norm weight of point k on a line of n points
 template <int ORD>
@@ -542,64 +552,6 @@ __device__ __forceinline__ void point_data(BlockRef B, long p, const PassArgs& A
     point_sources<T>(A, rg, p, tc, r0, r1);
 }
 
-// Given L f0 (l0), L f1 (l1) and the data sums of the two evaluations at p,
-// write the pass outputs (see the pass definitions in sbpe_internal.h).
-// A1, A2 are the stage values at p in the second sweep.
-template <typename T>
-__device__ __forceinline__ void finish_point(const PassArgs& A, int b, long p, T irho, T l00, T l01, T l10, T l11,
-                                             T da0, T da1, T db0, T db1, T A10, T A11, T A20, T A21,
-                                             const Range& rg) {
-    BlockRef B = blk(A, b);
-    const long np = (long)B.n1 * B.n2;
-    if (A.pass == PASS_APPLY) {
-        gp<T> o = gm<T>(A.out[b]);
-        o[p] = irho * (l00 + da0);
-        o[np + p] = irho * (l01 + da1);
-        return;
-    }
-    const T dt = static_cast<T>(A.dt);
-    if (A.pass == PASS_RK1) {
-        gp<T> a1 = gm<T>(B.a1);
-        gp<T> a2 = gm<T>(B.a2);
-        const T hdt = T(0.5) * dt;
-        a1[p] = irho * (l00 + da0);
-        a1[np + p] = irho * (l01 + da1);
-        a2[p] = irho * (l00 + hdt * l10 + db0);
-        a2[np + p] = irho * (l01 + hdt * l11 + db1);
-        return;
-    }
-    // PASS_RK2
-    gp<T> u = gm<T>(B.u);
-    gp<T> v = gm<T>(B.v);
-    const T dt2 = dt * dt;
-    const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
-    T un[2];
-#pragma unroll
-    for (int cmp = 0; cmp < 2; ++cmp) {
-        const long q = cmp * np + p;
-        const T A1 = cmp ? A11 : A10, A2 = cmp ? A21 : A20;
-        const T L1 = cmp ? l01 : l00;
-        const T L2 = cmp ? l11 : l10;
-        const T D2 = cmp ? db1 : db0;
-        const T A3 = A2 + q4 * irho * L1;
-        const T A4 = T(2) * A2 - A1 + q2 * irho * (L2 + D2);
-        const T uo = u[q], vo = v[q];
-        un[cmp] = uo + dt * vo + s6 * (A1 + A2 + A3);
-        u[q] = un[cmp];
-        v[q] = vo + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4);
-    }
-    if (A.rec_out) {
-        gp<double> ro = gm<double>(A.rec_out);
-        for (int e = rg.beg; e < rg.end; ++e) {
-            const GLB Entry& E = entry(A, e);
-            if (E.kind == 1 && E.p == p) {
-                ro[2 * E.id] = E.c0 * static_cast<double>(un[0]);
-                ro[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);
-            }
-        }
-    }
-}
-
 __device__ __forceinline__ int find_block(const PassArgs& A, int wg, bool frame) {
     int b = 0;
     for (int k = 1; k < A.nblocks; ++k) {
@@ -709,31 +661,38 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
 }
 
 // ------------------------------------------------------------- interior
-// Marching kernel: one wave, 64 columns i0..i0+63 of the interior, rows
-// jb..je.  Per output row j the wave
-//   * stages input row j+H (H = stencil half width) in an LDS ring of 2H+1
-//     rows with an H-column halo on each side,
-//   * forms E(j+H) = M^T D_1 w from the staged row (M_jl = c_1j2l) into an
-//     LDS ring of its own column,
-//   * forms G(j) = M D_2 w from the ring (own column and halo columns) into an
-//     LDS row, then D_1 G,
-//   * evaluates the narrow x1 term from the staged row and the x1 coefficient
-//     row, the narrow x2 term from the ring and register windows of the x2
-//     coefficients, and D_2 E from the E ring.
-// All global loads of a row are issued together before its LDS writes; the
-// loads of row j+1 are issued before the arithmetic of row j.
-// PASS_APPLY evaluates one input field, the RK sweeps two.
-template <typename T, int NF>
-struct RowLoad {
-    T w[NF][2];      // input fields at (i, j + H)
-    T wh[NF][2];     // halo column of the input fields (lanes < 2H)
-    T b2[3];         // x2-narrow coefficients at (i, j + H)
-    T m[4];          // mixed coefficients at (i, j + H)
-    T b1[3];         // x1-narrow coefficients at (i, j)
-    T b1h[3];        // same at the halo column
-    T mh[4];         // mixed coefficients at the halo column, row j
-    T irho;
-    T x[4];          // second sweep: u, v at (i, j); forcing at (i, j) in x[0..1] otherwise
+// Marching kernel: one wave covers the 64 columns i0 .. i0+63 and writes the
+// OUTW = 64 - 2H central ones (H = half width of the interior stencils), so
+// every x1 neighbour a lane needs is another lane's column and no halo
+// column is loaded.  The wave marches over the rows jb .. je of its tile;
+// for output row j it
+//   * stages the input fields of the leading row j+H in an LDS ring of 2H+1
+//     rows (x1 neighbours for the staged row, x2 window of the own column),
+//   * forms E(j+H) = M^T D_1 w (M_jl = c_1j2l) into a register window,
+//   * forms G(j) = M D_2 w at all 64 columns into an LDS row, then D_1 G,
+//   * evaluates the narrow x1 term from the staged row j and the x1
+//     coefficient row, the narrow x2 term from the ring and the register
+//     window of the x2 coefficients, and D_2 E from the E window,
+//   * applies the pass arithmetic (sbpe_internal.h) and stores row j.
+// The row loop is unrolled by 2H+1, so every ring slot and register window
+// position is a compile-time constant (no window shifting).  The global
+// loads of the next row are issued before the arithmetic of the current one
+// into a buffer that is consumed at the start of the next row.
+template <typename T>
+__device__ __forceinline__ T ldo(const char* base, unsigned off) {
+    return *(const GLB T*)((const GLB char*)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(char* base, unsigned off, T v) {
+    *(GLB T*)((GLB char*)base + off) = v;
+}
+
+template <typename T, int NS>
+struct Lead {
+    T w[NS];   // input fields at (i, j + H)
+    T b2[3];   // x2-narrow coefficients at (i, j + H)
+    T m[4];    // mixed coefficients at (i, j + H)
+    T b1[3];   // x1-narrow coefficients at (i, j)
 };
 
 template <typename T, int ORD, int PASS>
@@ -741,13 +700,14 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
     using O = Op<ORD>;
     constexpr int HF = O::HALF;
     constexpr int NW = 2 * HF + 1;
-    constexpr int LW = 64 + 2 * HF;
     constexpr int NF = PASS == PASS_APPLY ? 1 : 2;
+    constexpr int NS = 2 * NF;
     constexpr int R = Frame<ORD>::R;
-    __shared__ T s_w[NW][NF][2][LW];
-    __shared__ T s_e[NW][NF][2][64];
-    __shared__ T s_g[NF][2][LW];
-    __shared__ T s_b[3][LW];
+    constexpr T C1 = static_cast<T>(O::d1i(HF + 1));
+    constexpr T C2 = static_cast<T>(d1_outer<ORD>());
+    __shared__ T s_x[NW][NS][64];
+    __shared__ T s_b[3][64];
+    __shared__ T s_g[NS][64];
 
     // workgroup order: consecutive tiles on the same XCD (ids are dealt round-robin to 8 XCDs)
     const int total = A.total_tiles;
@@ -761,35 +721,31 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
     const int tl = wg - B.tile_beg;
     const int ty = tl / B.tiles_x, tx = tl - ty * B.tiles_x;
     const int lane = threadIdx.x;
-    const int i0 = R + tx * 64;
-    const int i = i0 + lane;
-    const bool act = i <= n1 - 1 - R;
+    const int i = R - HF + tx * (64 - 2 * HF) + lane;
+    const bool act = lane >= HF && lane < 64 - HF && i <= n1 - 1 - R;
     const int ic = i < n1 - 1 ? i : n1 - 1;
-    const int jb = R + ty * TILE_Y;
-    const int je = (jb + TILE_Y < n2 - R ? jb + TILE_Y : n2 - R) - 1;
-    const bool halo = lane < 2 * HF;
-    int hcol = ic, hpos = lane + HF;
-    if (lane < HF) {
-        hcol = i0 - HF + lane;
-        hpos = lane;
-    } else if (halo) {
-        hcol = i0 + 64 + (lane - HF);
-        if (hcol > n1 - 1) hcol = n1 - 1;
-        hpos = 64 + lane;
+    const int jb = R + ty * B.tile_y;
+    const int je = (jb + B.tile_y < n2 - R ? jb + B.tile_y : n2 - R) - 1;
+    // Every field is addressed as a uniform base plus a 32-bit per-lane byte
+    // offset (one field of a block is below 4 GiB, checked on the host), so
+    // the loads use scalar base registers and a single offset register.
+    const unsigned fb = (unsigned)np * (unsigned)sizeof(T);    // bytes of one scalar field
+    const unsigned rowb = (unsigned)n1 * (unsigned)sizeof(T);  // bytes of one grid row
+    const unsigned lo = (unsigned)ic * (unsigned)sizeof(T);
+    const char* cbase = (const char*)B.coef;
+    auto cf = [&](int k) { return cbase + (size_t)k * fb; };
+    const char* fin[NS];
+    {
+        const void* f0p = PASS == PASS_APPLY ? A.in[b] : (PASS == PASS_RK1 ? B.u : B.a1);
+        const void* f1p = PASS == PASS_RK1 ? B.v : B.a2;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) fin[s] = (const char*)(s < 2 ? f0p : f1p) + (s & 1) * (size_t)fb;
     }
-    gcp<T> c = gc<T>(B.coef);
-    gcp<T> fin[NF];
-    if constexpr (PASS == PASS_APPLY) {
-        fin[0] = gc<T>(A.in[b]);
-    } else if constexpr (PASS == PASS_RK1) {
-        fin[0] = gc<T>(B.u);
-        fin[1] = gc<T>(B.v);
-    } else {
-        fin[0] = gc<T>(B.a1);
-        fin[1] = gc<T>(B.a2);
-    }
+    // without forcing, the forcing loads read the 1/rho~ field (cached) and
+    // are multiplied by zero, so that every load of a row is unconditional
     const bool force = B.force != nullptr;
-    gcp<T> frc = gc<T>(B.force);
+    const char* frc = force ? (const char*)B.force : cbase + (size_t)K_IRHO * fb;
+    const unsigned frc1 = force ? fb : 0u;
     const Range rg = load_range(A.tile_ranges, wg);
     const W3 ca = weights_a(A), cb = weights_b(A);
     T tauf_a = 0, tauf_b = 0;
@@ -801,254 +757,207 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
     const T i11 = ih1 * ih1, i22 = ih2 * ih2, i12 = ih1 * ih2;
     const T dt = static_cast<T>(A.dt);
 
-    // all global loads for output row j (leading row j + HF)
-    auto load_row = [&](int j, RowLoad<T, NF>& L) {
-        const long qn = (long)(j + HF) * n1;
-        const long qj = (long)j * n1;
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) L.w[f][q] = fin[f][q * np + qn + ic];
-        L.b2[0] = c[K_C2121 * np + qn + ic];
-        L.b2[1] = c[K_C2122 * np + qn + ic];
-        L.b2[2] = c[K_C2222 * np + qn + ic];
-        L.m[0] = c[K_C1121 * np + qn + ic];
-        L.m[1] = c[K_C1122 * np + qn + ic];
-        L.m[2] = c[K_C1221 * np + qn + ic];
-        L.m[3] = c[K_C1222 * np + qn + ic];
-        L.b1[0] = c[K_C1111 * np + qj + ic];
-        L.b1[1] = c[K_C1112 * np + qj + ic];
-        L.b1[2] = c[K_C1212 * np + qj + ic];
-        L.irho = c[K_IRHO * np + qj + ic];
-        if constexpr (PASS == PASS_RK2) {
-            gcp<T> u = gc<T>(B.u);
-            gcp<T> v = gc<T>(B.v);
-            L.x[0] = u[qj + ic];
-            L.x[1] = u[np + qj + ic];
-            L.x[2] = v[qj + ic];
-            L.x[3] = v[np + qj + ic];
-        }
-        if (halo) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) L.wh[f][q] = fin[f][q * np + qn + hcol];
-            L.b1h[0] = c[K_C1111 * np + qj + hcol];
-            L.b1h[1] = c[K_C1112 * np + qj + hcol];
-            L.b1h[2] = c[K_C1212 * np + qj + hcol];
-            L.mh[0] = c[K_C1121 * np + qj + hcol];
-            L.mh[1] = c[K_C1122 * np + qj + hcol];
-            L.mh[2] = c[K_C1221 * np + qj + hcol];
-            L.mh[3] = c[K_C1222 * np + qj + hcol];
-        }
+    // interior first derivative (times h) from the four neighbours
+    auto d1 = [&](T um2, T um1, T up1, T up2) -> T {
+        if constexpr (HF == 2) return C1 * (up1 - um1) + C2 * (up2 - um2);
+        else return C1 * (up1 - um1);
     };
-    // E(i, j) = M^T (h D_1 w)(i, j) into the E ring
-    auto ecompute = [&](int j, const T m0, const T m1, const T m2, const T m3) {
-        const int s = j % NW;
+    // leading-row loads for output row j
+    auto load_lead = [&](int j, Lead<T, NS>& L) {
+        const int jj = j < je ? j : je;
+        const unsigned qn = (unsigned)(jj + HF) * rowb + lo;
+        const unsigned qj = (unsigned)jj * rowb + lo;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) L.w[s] = ldo<T>(fin[s], qn);
+        L.b2[0] = ldo<T>(cf(K_C2121), qn);
+        L.b2[1] = ldo<T>(cf(K_C2122), qn);
+        L.b2[2] = ldo<T>(cf(K_C2222), qn);
+        L.m[0] = ldo<T>(cf(K_C1121), qn);
+        L.m[1] = ldo<T>(cf(K_C1122), qn);
+        L.m[2] = ldo<T>(cf(K_C1221), qn);
+        L.m[3] = ldo<T>(cf(K_C1222), qn);
+        L.b1[0] = ldo<T>(cf(K_C1111), qj);
+        L.b1[1] = ldo<T>(cf(K_C1112), qj);
+        L.b1[2] = ldo<T>(cf(K_C1212), qj);
+    };
+
+    // register windows indexed by ring slot: slot(r) = (r - jb + HF) mod NW
+    T b2w[3][NW];     // x2-narrow coefficients
+    T mw[4][NW];      // mixed coefficients
+    T ew[NS][NW];     // E = M^T D_1 w
+
+    // E at a staged row (slot s), from the x1 neighbours in the ring
+    auto e_row = [&](const int s) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             T w1[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const T wc = s_w[s][f][q][lane + HF];
-                T acc = 0;
-#pragma unroll
-                for (int k = -HF; k <= HF; ++k)
-                    if (k != 0) acc += static_cast<T>(O::d1i(k + HF)) * (s_w[s][f][q][lane + HF + k] - wc);
-                w1[q] = acc;
+                const int x = 2 * f + q;
+                w1[q] = d1(HF > 1 ? s_x[s][x][lane - 2 < 0 ? 0 : lane - 2] : T(0),
+                           s_x[s][x][lane - 1 < 0 ? 0 : lane - 1], s_x[s][x][lane + 1 > 63 ? 63 : lane + 1],
+                           HF > 1 ? s_x[s][x][lane + 2 > 63 ? 63 : lane + 2] : T(0));
             }
-            s_e[s][f][0][lane] = m0 * w1[0] + m2 * w1[1];
-            s_e[s][f][1][lane] = m1 * w1[0] + m3 * w1[1];
+            ew[2 * f][s] = mw[0][s] * w1[0] + mw[2][s] * w1[1];
+            ew[2 * f + 1][s] = mw[1][s] * w1[0] + mw[3][s] * w1[1];
         }
     };
 
-    // register windows: x2-narrow coefficients (rows j-HF..j+HF) and M (rows j..j+HF)
-    T b2w[3][NW];
-    T mq[HF + 1][4];
     // prologue: rows jb-HF .. jb+HF-1 staged, their E formed
     {
-        T pw[2 * HF][NF][2], ph[2 * HF][NF][2], pm[2 * HF][4];
 #pragma unroll
         for (int r = 0; r < 2 * HF; ++r) {
-            const long q = (long)(jb - HF + r) * n1;
+            const unsigned q = (unsigned)(jb - HF + r) * rowb + lo;
 #pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int qq = 0; qq < 2; ++qq) {
-                    pw[r][f][qq] = fin[f][qq * np + q + ic];
-                    ph[r][f][qq] = fin[f][qq * np + q + hcol];
-                }
-            b2w[0][r] = c[K_C2121 * np + q + ic];
-            b2w[1][r] = c[K_C2122 * np + q + ic];
-            b2w[2][r] = c[K_C2222 * np + q + ic];
-            pm[r][0] = c[K_C1121 * np + q + ic];
-            pm[r][1] = c[K_C1122 * np + q + ic];
-            pm[r][2] = c[K_C1221 * np + q + ic];
-            pm[r][3] = c[K_C1222 * np + q + ic];
-        }
-#pragma unroll
-        for (int r = 0; r < 2 * HF; ++r) {
-            const int s = (jb - HF + r) % NW;
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int qq = 0; qq < 2; ++qq) {
-                    s_w[s][f][qq][lane + HF] = pw[r][f][qq];
-                    s_w[s][f][qq][hpos] = ph[r][f][qq];
-                }
+            for (int s = 0; s < NS; ++s) s_x[r][s][lane] = ldo<T>(fin[s], q);
+            b2w[0][r] = ldo<T>(cf(K_C2121), q);
+            b2w[1][r] = ldo<T>(cf(K_C2122), q);
+            b2w[2][r] = ldo<T>(cf(K_C2222), q);
+            mw[0][r] = ldo<T>(cf(K_C1121), q);
+            mw[1][r] = ldo<T>(cf(K_C1122), q);
+            mw[2][r] = ldo<T>(cf(K_C1221), q);
+            mw[3][r] = ldo<T>(cf(K_C1222), q);
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 2 * HF; ++r) {
-            ecompute(jb - HF + r, pm[r][0], pm[r][1], pm[r][2], pm[r][3]);
-            if (r >= HF)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) mq[r - HF][m] = pm[r][m];
-        }
+        for (int r = 0; r < 2 * HF; ++r) e_row(r);
     }
 
-    RowLoad<T, NF> cur, nxt;
-    load_row(jb, cur);
-    for (int j = jb; j <= je; ++j) {
-        if (j < je) load_row(j + 1, nxt);
-        T f0 = 0, f1 = 0;
-        if (force) {
-            f0 = frc[(long)j * n1 + ic];
-            f1 = frc[np + (long)j * n1 + ic];
+    Lead<T, NS> P;
+    load_lead(jb, P);
+
+    // one output row; K is the position in the unrolled group (slot of row j is K + HF)
+    auto step = [&](auto KC, const int j) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int s0 = (K + HF) % NW;        // row j
+        constexpr int sn = (K + 2 * HF) % NW;    // leading row j + HF
+        // (1) consume the leading-row buffer
+#pragma unroll
+        for (int s = 0; s < NS; ++s) s_x[sn][s][lane] = P.w[s];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_b[k][lane] = P.b1[k];
+            b2w[k][sn] = P.b2[k];
         }
-        const int jn = j + HF;
-        __syncthreads();
-        // (1) stage row jn and the x1 coefficient row j
-        {
-            const int s = jn % NW;
 #pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    s_w[s][f][q][lane + HF] = cur.w[f][q];
-                    if (halo) s_w[s][f][q][hpos] = cur.wh[f][q];
-                }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                s_b[k][lane + HF] = cur.b1[k];
-                if (halo) s_b[k][hpos] = cur.b1h[k];
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) b2w[k][NW - 1] = cur.b2[k];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) mq[HF][m] = cur.m[m];
+        for (int m = 0; m < 4; ++m) mw[m][sn] = P.m[m];
+        const T b1c[3] = {P.b1[0], P.b1[1], P.b1[2]};
+        // (2) per-point operands of row j, then the leading row of j + 1
+        const bool live = j <= je;
+        const unsigned p = (unsigned)(live ? j : je) * rowb + lo;
+        const T irho = ldo<T>(cf(K_IRHO), p);
+        const T f0 = ldo<T>(frc, p);
+        const T f1 = ldo<T>(frc + frc1, p);
+        T xo[4];
+        if constexpr (PASS == PASS_RK2) {
+            xo[0] = ldo<T>((const char*)B.u, p);
+            xo[1] = ldo<T>((const char*)B.u + fb, p);
+            xo[2] = ldo<T>((const char*)B.v, p);
+            xo[3] = ldo<T>((const char*)B.v + fb, p);
         }
+        load_lead(j + 1, P);
         __syncthreads();
-        // (2) E at the leading row; G at row j (own column and halo); narrow terms
-        ecompute(jn, mq[HF][0], mq[HF][1], mq[HF][2], mq[HF][3]);
-        const int s0 = j % NW;
+        // (3) E at the leading row
+        e_row(sn);
+        // (4) G at row j (all 64 columns), narrow terms
         T lx[NF][2];
+        T wc[NS];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             T wcol[2][NW];
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int k = 0; k < NW; ++k) wcol[q][k] = s_w[(j - HF + k) % NW][f][q][lane + HF];
+                for (int k = 0; k < NW; ++k) wcol[q][k] = s_x[(K + k) % NW][2 * f + q][lane];
             T w2[2];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                T acc = 0;
-#pragma unroll
-                for (int k = -HF; k <= HF; ++k)
-                    if (k != 0) acc += static_cast<T>(O::d1i(k + HF)) * (wcol[q][HF + k] - wcol[q][HF]);
-                w2[q] = acc;
+                w2[q] = d1(HF > 1 ? wcol[q][0] : T(0), wcol[q][HF - 1], wcol[q][HF + 1],
+                           HF > 1 ? wcol[q][NW - 1] : T(0));
+                wc[2 * f + q] = wcol[q][HF];
             }
-            s_g[f][0][lane + HF] = mq[0][0] * w2[0] + mq[0][1] * w2[1];
-            s_g[f][1][lane + HF] = mq[0][2] * w2[0] + mq[0][3] * w2[1];
-            if (halo) {
-                T h2[2];
+            s_g[2 * f][lane] = mw[0][s0] * w2[0] + mw[1][s0] * w2[1];
+            s_g[2 * f + 1][lane] = mw[2][s0] * w2[0] + mw[3][s0] * w2[1];
+            T bc[3][NW];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const T wc = s_w[s0][f][q][hpos];
-                    T acc = 0;
+            for (int k = 0; k < NW; ++k)
 #pragma unroll
-                    for (int k = -HF; k <= HF; ++k)
-                        if (k != 0) acc += static_cast<T>(O::d1i(k + HF)) * (s_w[(j + k) % NW][f][q][hpos] - wc);
-                    h2[q] = acc;
-                }
-                s_g[f][0][hpos] = cur.mh[0] * h2[0] + cur.mh[1] * h2[1];
-                s_g[f][1][hpos] = cur.mh[2] * h2[0] + cur.mh[3] * h2[1];
+                for (int m = 0; m < 3; ++m) bc[m][k] = b2w[m][(K + k) % NW];
+            const T bx0 = d2_interior<T, ORD>(&bc[0][HF], &wcol[0][HF], 1);   // c2121 u1
+            const T bx1 = d2_interior<T, ORD>(&bc[1][HF], &wcol[1][HF], 1);   // c2122 u2
+            const T bx2 = d2_interior<T, ORD>(&bc[1][HF], &wcol[0][HF], 1);   // c2122 u1
+            const T bx3 = d2_interior<T, ORD>(&bc[2][HF], &wcol[1][HF], 1);   // c2222 u2
+            // x1 rows of the staged row j and of the x1 coefficients
+            T ur[2][NW], br[3][NW];
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+                const int l = lane + k - HF;
+                const int lc = l < 0 ? 0 : (l > 63 ? 63 : l);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) ur[q][k] = k == HF ? wcol[q][HF] : s_x[s0][2 * f + q][lc];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) br[m][k] = k == HF ? b1c[m] : s_b[m][lc];
             }
-            // narrow x2 term: own column of the ring, coefficient window in registers
-            const T bx0 = d2_interior<T, ORD>(&b2w[0][HF], &wcol[0][HF], 1);   // c2121 u1
-            const T bx1 = d2_interior<T, ORD>(&b2w[1][HF], &wcol[1][HF], 1);   // c2122 u2
-            const T bx2 = d2_interior<T, ORD>(&b2w[1][HF], &wcol[0][HF], 1);   // c2122 u1
-            const T bx3 = d2_interior<T, ORD>(&b2w[2][HF], &wcol[1][HF], 1);   // c2222 u2
-            // narrow x1 term: staged row and x1 coefficient row
-            const T ax0 = d2_interior<T, ORD>(&s_b[0][lane + HF], &s_w[s0][f][0][lane + HF], 1);
-            const T ax1 = d2_interior<T, ORD>(&s_b[1][lane + HF], &s_w[s0][f][1][lane + HF], 1);
-            const T ax2 = d2_interior<T, ORD>(&s_b[1][lane + HF], &s_w[s0][f][0][lane + HF], 1);
-            const T ax3 = d2_interior<T, ORD>(&s_b[2][lane + HF], &s_w[s0][f][1][lane + HF], 1);
+            const T ax0 = d2_interior<T, ORD>(&br[0][HF], &ur[0][HF], 1);
+            const T ax1 = d2_interior<T, ORD>(&br[1][HF], &ur[1][HF], 1);
+            const T ax2 = d2_interior<T, ORD>(&br[1][HF], &ur[0][HF], 1);
+            const T ax3 = d2_interior<T, ORD>(&br[2][HF], &ur[1][HF], 1);
             lx[f][0] = (ax0 + ax1) * i11 + (bx0 + bx1) * i22;
             lx[f][1] = (ax2 + ax3) * i11 + (bx2 + bx3) * i22;
         }
         __syncthreads();
-        // (3) D_1 G and D_2 E
+        // (5) D_1 G and D_2 E
         T L[NF][2];
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const T gc0 = s_g[f][q][lane + HF];
-                const T ec0 = s_e[s0][f][q][lane];
-                T ag = 0, ae = 0;
-#pragma unroll
-                for (int k = -HF; k <= HF; ++k) {
-                    if (k == 0) continue;
-                    const T w = static_cast<T>(O::d1i(k + HF));
-                    ag += w * (s_g[f][q][lane + HF + k] - gc0);
-                    ae += w * (s_e[(j + k) % NW][f][q][lane] - ec0);
-                }
-                L[f][q] = lx[f][q] + (ag + ae) * i12;
-            }
-        // (4) data, RK arithmetic, stores
-        const long p = (long)j * n1 + i;
-        if (act) {
+        for (int x = 0; x < NS; ++x) {
+            const int lm2 = lane - 2 < 0 ? 0 : lane - 2, lm1 = lane - 1 < 0 ? 0 : lane - 1;
+            const int lp1 = lane + 1 > 63 ? 63 : lane + 1, lp2 = lane + 2 > 63 ? 63 : lane + 2;
+            const T ag = d1(HF > 1 ? s_g[x][lm2] : T(0), s_g[x][lm1], s_g[x][lp1], HF > 1 ? s_g[x][lp2] : T(0));
+            const T ae = d1(HF > 1 ? ew[x][K % NW] : T(0), ew[x][(K + HF - 1) % NW], ew[x][(K + HF + 1) % NW],
+                            HF > 1 ? ew[x][(K + 2 * HF) % NW] : T(0));
+            L[x >> 1][x & 1] = lx[x >> 1][x & 1] + (ag + ae) * i12;
+        }
+        // (6) data, pass arithmetic, stores
+        if (act && live) {
+            const long po = (long)j * n1 + i;
             T da0 = tauf_a * f0, da1 = tauf_a * f1, db0 = tauf_b * f0, db1 = tauf_b * f1;
             if (rg.end > rg.beg) {
-                if (ca.any()) point_sources<T>(A, rg, p, ca, da0, da1);
-                if (NF == 2 && cb.any()) point_sources<T>(A, rg, p, cb, db0, db1);
+                if (ca.any()) point_sources<T>(A, rg, po, ca, da0, da1);
+                if (NF == 2 && cb.any()) point_sources<T>(A, rg, po, cb, db0, db1);
             }
-            const T irho = cur.irho;
             if constexpr (PASS == PASS_APPLY) {
-                gp<T> o = gm<T>(A.out[b]);
-                o[p] = irho * (L[0][0] + da0);
-                o[np + p] = irho * (L[0][1] + da1);
+                char* o = (char*)A.out[b];
+                sto<T>(o, p, irho * (L[0][0] + da0));
+                sto<T>(o + fb, p, irho * (L[0][1] + da1));
             } else if constexpr (PASS == PASS_RK1) {
-                gp<T> a1 = gm<T>(B.a1);
-                gp<T> a2 = gm<T>(B.a2);
+                char* a1 = (char*)B.a1;
+                char* a2 = (char*)B.a2;
                 const T hdt = T(0.5) * dt;
-                a1[p] = irho * (L[0][0] + da0);
-                a1[np + p] = irho * (L[0][1] + da1);
-                a2[p] = irho * (L[0][0] + hdt * L[NF - 1][0] + db0);
-                a2[np + p] = irho * (L[0][1] + hdt * L[NF - 1][1] + db1);
+                sto<T>(a1, p, irho * (L[0][0] + da0));
+                sto<T>(a1 + fb, p, irho * (L[0][1] + da1));
+                sto<T>(a2, p, irho * (L[0][0] + hdt * L[NF - 1][0] + db0));
+                sto<T>(a2 + fb, p, irho * (L[0][1] + hdt * L[NF - 1][1] + db1));
             } else {
-                gp<T> u = gm<T>(B.u);
-                gp<T> v = gm<T>(B.v);
+                char* u = (char*)B.u;
+                char* v = (char*)B.v;
                 const T dt2 = dt * dt;
                 const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
                 T un[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const T A1 = s_w[s0][0][q][lane + HF];
-                    const T A2 = s_w[s0][NF - 1][q][lane + HF];
+                    const T A1 = wc[q];
+                    const T A2 = wc[2 + q];
                     const T A3 = A2 + q4 * irho * L[0][q];
-                    const T A4 = T(2) * A2 - A1 + q2 * irho * (L[NF - 1][q] + (q ? db1 : db0));
-                    un[q] = cur.x[q] + dt * cur.x[2 + q] + s6 * (A1 + A2 + A3);
-                    u[q * np + p] = un[q];
-                    v[q * np + p] = cur.x[2 + q] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4);
+                    const T A4 = T(2) * A2 - A1 + q2 * irho * (L[1][q] + (q ? db1 : db0));
+                    un[q] = xo[q] + dt * xo[2 + q] + s6 * (A1 + A2 + A3);
+                    sto<T>(u + q * fb, p, un[q]);
+                    sto<T>(v + q * fb, p, xo[2 + q] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4));
                 }
                 if (A.rec_out && rg.end > rg.beg) {
                     gp<double> ro = gm<double>(A.rec_out);
                     for (int e = rg.beg; e < rg.end; ++e) {
                         const GLB Entry& E = entry(A, e);
-                        if (E.kind == 1 && E.p == p) {
+                        if (E.kind == 1 && E.p == po) {
                             ro[2 * E.id] = E.c0 * static_cast<double>(un[0]);
                             ro[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);
                         }
@@ -1056,18 +965,19 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
                 }
             }
         }
-        // (5) rotate register windows
-#pragma unroll
-        for (int k = 0; k < NW - 1; ++k) {
-            b2w[0][k] = b2w[0][k + 1];
-            b2w[1][k] = b2w[1][k + 1];
-            b2w[2][k] = b2w[2][k + 1];
+        __syncthreads();
+    };
+
+    // rows past je (at most NW - 1 in the last group) are evaluated on
+    // clamped rows and not stored
+    for (int j0 = jb; j0 <= je; j0 += NW) {
+        step(std::integral_constant<int, 0>{}, j0);
+        step(std::integral_constant<int, 1>{}, j0 + 1);
+        step(std::integral_constant<int, 2>{}, j0 + 2);
+        if constexpr (NW > 3) {
+            step(std::integral_constant<int, 3 % NW>{}, j0 + 3);
+            step(std::integral_constant<int, 4 % NW>{}, j0 + 4);
         }
-#pragma unroll
-        for (int k = 0; k < HF; ++k)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) mq[k][m] = mq[k + 1][m];
-        cur = nxt;
     }
 }
 

@@ -450,8 +450,9 @@ static long frame_index(const HostBlock& B, int R, int i, int j) {
     const int n1 = B.n1, n2 = B.n2;
     if (j < R) return (long)j * n1 + i;
     if (j >= n2 - R) return (long)R * n1 + (long)(j - (n2 - R)) * n1 + i;
+    // side bands column by column, so that the points of a wave share their x1 closure row
     const int cc = i < R ? i : i - (n1 - 2 * R);
-    return 2L * R * n1 + (long)(j - R) * 2 * R + cc;
+    return 2L * R * n1 + (long)cc * (n2 - 2 * R) + (j - R);
 }
 
 static sbpe_status build_plan(sbpe_ctx* c) {

@@ -114,7 +114,7 @@ struct PassArgs {
 constexpr int TILE_LANES = 64;
 constexpr int TILE_Y_DEFAULT = 10;
 constexpr int FRAME_WG = 256;
-constexpr int FRAME_PTS = FRAME_WG / 2;   // frame points per workgroup (two lanes per point)
+constexpr int FRAME_PTS = 32;   // frame points per workgroup: four waves, two lanes per point in each
 
 // host-side launchers (sbpe_kernels.hip)
 int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream);

@@ -183,6 +183,33 @@ __device__ __forceinline__ T d2_interior(PB b, PU u, long st) {
     }
 }
 
+// The interior row of h^2 D2^FC(b) in edge form: weights k of the differences
+// u_m - u_0 for m = -H..-1, 1..H, from b on the 2H+1 points of the row.
+template <typename T, int ORD>
+__device__ __forceinline__ void d2_weights(const T* b, T* k) {
+    if constexpr (ORD == 4) {
+        const T s6 = T(1) / T(6), e8 = T(0.125), hf = T(0.5);
+        k[0] = s6 * b[1] - e8 * (b[0] + b[2]);
+        k[1] = s6 * (b[0] + b[3]) + hf * (b[1] + b[2]);
+        k[2] = s6 * (b[1] + b[4]) + hf * (b[2] + b[3]);
+        k[3] = s6 * b[3] - e8 * (b[2] + b[4]);
+    } else {
+        const T hf = T(0.5);
+        k[0] = hf * (b[0] + b[1]);
+        k[1] = hf * (b[1] + b[2]);
+    }
+}
+template <typename T, int ORD>
+__device__ __forceinline__ T d2_edges(const T* k, const T* u) {
+    if constexpr (ORD == 4) {
+        const T u0 = u[2];
+        return k[0] * (u[0] - u0) + k[1] * (u[1] - u0) + k[2] * (u[3] - u0) + k[3] * (u[4] - u0);
+    } else {
+        const T u0 = u[1];
+        return k[0] * (u[0] - u0) + k[1] * (u[2] - u0);
+    }
+}
+
 // closure row RR (from the lower end, or mirrored at the upper end)
 template <typename T, int ORD, int RR>
 __device__ __forceinline__ T d2_closure(gcp<T> b, gcp<T> u, long st, bool lo, int n) {
@@ -226,9 +253,12 @@ __device__ __forceinline__ T d2_line(gcp<T> b, gcp<T> u, long st, int r, int n) 
 }
 
 // -------------------------------------------------- volume at one point
-// DD_ik(c_ijkl) u_l at (i, j) with boundary-aware 1-D rows (frame points).
-template <typename T, int ORD>
-__device__ __forceinline__ void volume_general(BlockRef B, gcp<T> u, int i, int j, T& r0, T& r1) {
+// One of the four term groups of DD_ik(c_ijkl) u_l at (i, j) with
+// boundary-aware 1-D rows (frame points):
+//   PART 0: D_11^FC(c_1j1l) u_l        PART 1: D_22^FC(c_2j2l) u_l
+//   PART 2: D_1 (c_1j2l D_2 u_l)       PART 3: D_2 (c_2j1l D_1 u_l)
+template <typename T, int ORD, int PART>
+__device__ __forceinline__ void volume_part(BlockRef B, gcp<T> u, int i, int j, T& r0, T& r1) {
     const int n1 = B.n1, n2 = B.n2;
     const long np = (long)n1 * n2;
     gcp<T> c = gc<T>(B.coef);
@@ -236,44 +266,50 @@ __device__ __forceinline__ void volume_general(BlockRef B, gcp<T> u, int i, int 
     gcp<T> u1 = u + np;
     const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
     const long rj = (long)j * n1;
-    // x1 narrow, line j
-    const T a00 = d2_line<T, ORD>(c + K_C1111 * np + rj, u0 + rj, 1, i, n1);
-    const T a01 = d2_line<T, ORD>(c + K_C1112 * np + rj, u1 + rj, 1, i, n1);
-    const T a10 = d2_line<T, ORD>(c + K_C1112 * np + rj, u0 + rj, 1, i, n1);
-    const T a11 = d2_line<T, ORD>(c + K_C1212 * np + rj, u1 + rj, 1, i, n1);
-    // x2 narrow, line i
-    const T b00 = d2_line<T, ORD>(c + K_C2121 * np + i, u0 + i, n1, j, n2);
-    const T b01 = d2_line<T, ORD>(c + K_C2122 * np + i, u1 + i, n1, j, n2);
-    const T b10 = d2_line<T, ORD>(c + K_C2122 * np + i, u0 + i, n1, j, n2);
-    const T b11 = d2_line<T, ORD>(c + K_C2222 * np + i, u1 + i, n1, j, n2);
-    r0 = (a00 + a01) * ih1 * ih1 + (b00 + b01) * ih2 * ih2;
-    r1 = (a10 + a11) * ih1 * ih1 + (b10 + b11) * ih2 * ih2;
-    // D_1 (M D_2 u), M_jl = c_1j2l
-    T g0 = 0, g1 = 0;
-    d1_foreach<ORD>(i, n1, [&](int ii, double w) {
-        const T w20 = d1_line<T, ORD>(u0 + ii, n1, j, n2);
-        const T w21 = d1_line<T, ORD>(u1 + ii, n1, j, n2);
-        const long q = rj + ii;
-        const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
-        const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
-        g0 += static_cast<T>(w) * (m00 * w20 + m01 * w21);
-        g1 += static_cast<T>(w) * (m10 * w20 + m11 * w21);
-    });
-    // D_2 (M^T D_1 u), c_2j1l = c_1l2j
-    T e0 = 0, e1 = 0;
-    d1_foreach<ORD>(j, n2, [&](int jj, double w) {
-        const long rjj = (long)jj * n1;
-        const T w10 = d1_line<T, ORD>(u0 + rjj, 1, i, n1);
-        const T w11 = d1_line<T, ORD>(u1 + rjj, 1, i, n1);
-        const long q = rjj + i;
-        const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
-        const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
-        e0 += static_cast<T>(w) * (m00 * w10 + m10 * w11);
-        e1 += static_cast<T>(w) * (m01 * w10 + m11 * w11);
-    });
-    const T ihh = ih1 * ih2;
-    r0 += (g0 + e0) * ihh;
-    r1 += (g1 + e1) * ihh;
+    if constexpr (PART == 0) {
+        const T a00 = d2_line<T, ORD>(c + K_C1111 * np + rj, u0 + rj, 1, i, n1);
+        const T a01 = d2_line<T, ORD>(c + K_C1112 * np + rj, u1 + rj, 1, i, n1);
+        const T a10 = d2_line<T, ORD>(c + K_C1112 * np + rj, u0 + rj, 1, i, n1);
+        const T a11 = d2_line<T, ORD>(c + K_C1212 * np + rj, u1 + rj, 1, i, n1);
+        r0 += (a00 + a01) * ih1 * ih1;
+        r1 += (a10 + a11) * ih1 * ih1;
+    } else if constexpr (PART == 1) {
+        const T b00 = d2_line<T, ORD>(c + K_C2121 * np + i, u0 + i, n1, j, n2);
+        const T b01 = d2_line<T, ORD>(c + K_C2122 * np + i, u1 + i, n1, j, n2);
+        const T b10 = d2_line<T, ORD>(c + K_C2122 * np + i, u0 + i, n1, j, n2);
+        const T b11 = d2_line<T, ORD>(c + K_C2222 * np + i, u1 + i, n1, j, n2);
+        r0 += (b00 + b01) * ih2 * ih2;
+        r1 += (b10 + b11) * ih2 * ih2;
+    } else if constexpr (PART == 2) {
+        // D_1 (M D_2 u), M_jl = c_1j2l
+        T g0 = 0, g1 = 0;
+        d1_foreach<ORD>(i, n1, [&](int ii, double w) {
+            const T w20 = d1_line<T, ORD>(u0 + ii, n1, j, n2);
+            const T w21 = d1_line<T, ORD>(u1 + ii, n1, j, n2);
+            const long q = rj + ii;
+            const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
+            const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
+            g0 += static_cast<T>(w) * (m00 * w20 + m01 * w21);
+            g1 += static_cast<T>(w) * (m10 * w20 + m11 * w21);
+        });
+        r0 += g0 * ih1 * ih2;
+        r1 += g1 * ih1 * ih2;
+    } else {
+        // D_2 (M^T D_1 u), c_2j1l = c_1l2j
+        T e0 = 0, e1 = 0;
+        d1_foreach<ORD>(j, n2, [&](int jj, double w) {
+            const long rjj = (long)jj * n1;
+            const T w10 = d1_line<T, ORD>(u0 + rjj, 1, i, n1);
+            const T w11 = d1_line<T, ORD>(u1 + rjj, 1, i, n1);
+            const long q = rjj + i;
+            const T m00 = c[K_C1121 * np + q], m01 = c[K_C1122 * np + q];
+            const T m10 = c[K_C1221 * np + q], m11 = c[K_C1222 * np + q];
+            e0 += static_cast<T>(w) * (m00 * w10 + m10 * w11);
+            e1 += static_cast<T>(w) * (m01 * w10 + m11 * w11);
+        });
+        r0 += e0 * ih1 * ih2;
+        r1 += e1 * ih1 * ih2;
+    }
 }
 
 // --------------------------------------------------------- face helpers
@@ -515,16 +551,16 @@ __device__ __forceinline__ void face_sat(const PassArgs& A, int b, int f, int dn
     }
 }
 
-// all SAT contributions of the four faces at (i, j)
-template <typename T, int ORD, bool DATA>
+// SAT contributions of the faces FB .. FE - 1 at (i, j)
+template <typename T, int ORD, bool DATA, int FB = 0, int FE = 4>
 __device__ __forceinline__ void sat_point(const PassArgs& A, int b, int i, int j, int fld, const W3& tc, T& r0, T& r1) {
     using O = Op<ORD>;
     BlockRef B = blk(A, b);
     const int n1 = B.n1, n2 = B.n2;
-    if (i < O::REACH) face_sat<T, ORD, DATA>(A, b, 0, i, j, fld, tc, r0, r1);
-    if (n1 - 1 - i < O::REACH) face_sat<T, ORD, DATA>(A, b, 1, n1 - 1 - i, j, fld, tc, r0, r1);
-    if (j < O::REACH) face_sat<T, ORD, DATA>(A, b, 2, j, i, fld, tc, r0, r1);
-    if (n2 - 1 - j < O::REACH) face_sat<T, ORD, DATA>(A, b, 3, n2 - 1 - j, i, fld, tc, r0, r1);
+    if (FB <= 0 && 0 < FE && i < O::REACH) face_sat<T, ORD, DATA>(A, b, 0, i, j, fld, tc, r0, r1);
+    if (FB <= 1 && 1 < FE && n1 - 1 - i < O::REACH) face_sat<T, ORD, DATA>(A, b, 1, n1 - 1 - i, j, fld, tc, r0, r1);
+    if (FB <= 2 && 2 < FE && j < O::REACH) face_sat<T, ORD, DATA>(A, b, 2, j, i, fld, tc, r0, r1);
+    if (FB <= 3 && 3 < FE && n2 - 1 - j < O::REACH) face_sat<T, ORD, DATA>(A, b, 3, n2 - 1 - j, i, fld, tc, r0, r1);
 }
 
 // sources (and, in the frame, the forcing) at flat point p
@@ -562,18 +598,28 @@ __device__ __forceinline__ int find_block(const PassArgs& A, int wg, bool frame)
 }
 
 // ---------------------------------------------------------------- frame
-// Two lanes per frame point: in the RK sweeps lane s evaluates L and the data
-// of field s (u / v, or A1 / A2); for sbpe_apply lane 0 evaluates L and lane 1
-// the data.  The partial results are exchanged between the lane pair and lane
-// s writes component s of the outputs.
+// A workgroup of four waves takes FRAME_PTS frame points.  Wave w evaluates
+// term group w for every point (two lanes per point), so the long chains of
+// closure-row loads are split over four waves:
+//   wave 0: D_11^FC term and the homogeneous SATs of the x1 faces
+//   wave 1: D_22^FC term and the homogeneous SATs of the x2 faces
+//   wave 2: D_1 (c_1j2l D_2 u_l)
+//   wave 3: D_2 (c_2j1l D_1 u_l), the data SATs, forcing and sources.
+// In the RK sweeps lane s of a pair works on field s (u / v, or A1 / A2);
+// for sbpe_apply lane 0 evaluates L and lane 1 of wave 3 the data.  The
+// partial sums meet in LDS; wave 0 combines them and lane s of each pair
+// writes component s of the outputs.
 template <typename T, int ORD>
 __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     constexpr int R = Frame<ORD>::R;
+    __shared__ T s_r[4][64][4];
     const int wg = blockIdx.x;
     const int b = find_block(A, wg, true);
     BlockRef B = blk(A, b);
-    const int sub = threadIdx.x & 1;
-    const int k = (wg - B.frame_beg) * FRAME_PTS + (threadIdx.x >> 1);
+    const int part = threadIdx.x >> 6;   // wave-uniform term group
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 1;
+    const int k = (wg - B.frame_beg) * FRAME_PTS + (lane >> 1);
     const Range rg = load_range(A.frame_ranges, wg);
     const int n1 = B.n1, n2 = B.n2;
     const long np = (long)n1 * n2;
@@ -588,8 +634,9 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
         j = n2 - R + kk / n1;
         i = kk % n1;
     } else {
+        // side bands column by column: the points of a wave share their x1 closure row
         const int kk = kk0 - 2 * R * n1;
-        const int row = kk / (2 * R), cc = kk % (2 * R);
+        const int cc = kk / (n2 - 2 * R), row = kk - cc * (n2 - 2 * R);
         j = R + row;
         i = cc < R ? cc : n1 - 2 * R + cc;
     }
@@ -598,24 +645,43 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     const W3 ca = weights_a(A), cb = weights_b(A);
     T l0 = 0, l1 = 0, d0 = 0, d1 = 0;
     if (valid) {
-        if (A.pass == PASS_APPLY) {
-            if (sub == 0) {
-                volume_general<T, ORD>(B, field_ptr<T>(A, b, FLD_IN), i, j, l0, l1);
-                sat_point<T, ORD, false>(A, b, i, j, FLD_IN, none, l0, l1);
-            } else if (ca.any()) {
-                sat_point<T, ORD, true>(A, b, i, j, FLD_IN, ca, d0, d1);
-                point_data<T>(B, p, A, rg, ca, d0, d1);
+        const bool apply = A.pass == PASS_APPLY;
+        const int fld = apply ? FLD_IN : (A.pass == PASS_RK1 ? (sub ? FLD_V : FLD_U) : (sub ? FLD_A2 : FLD_A1));
+        const bool hom = !apply || sub == 0;    // this lane evaluates L of its field
+        gcp<T> u = field_ptr<T>(A, b, fld);
+        if (part == 0) {
+            if (hom) {
+                volume_part<T, ORD, 0>(B, u, i, j, l0, l1);
+                sat_point<T, ORD, false, 0, 2>(A, b, i, j, fld, none, l0, l1);
             }
+        } else if (part == 1) {
+            if (hom) {
+                volume_part<T, ORD, 1>(B, u, i, j, l0, l1);
+                sat_point<T, ORD, false, 2, 4>(A, b, i, j, fld, none, l0, l1);
+            }
+        } else if (part == 2) {
+            if (hom) volume_part<T, ORD, 2>(B, u, i, j, l0, l1);
         } else {
-            const int fld = A.pass == PASS_RK1 ? (sub ? FLD_V : FLD_U) : (sub ? FLD_A2 : FLD_A1);
-            volume_general<T, ORD>(B, field_ptr<T>(A, b, fld), i, j, l0, l1);
-            sat_point<T, ORD, false>(A, b, i, j, fld, none, l0, l1);
-            const W3 cw = sub ? cb : ca;
-            if (cw.any()) {
+            if (hom) volume_part<T, ORD, 3>(B, u, i, j, l0, l1);
+            const W3 cw = apply ? ca : (sub ? cb : ca);
+            if ((!apply || sub == 1) && cw.any()) {
                 sat_point<T, ORD, true>(A, b, i, j, fld, cw, d0, d1);
                 point_data<T>(B, p, A, rg, cw, d0, d1);
             }
         }
+    }
+    s_r[part][lane][0] = l0;
+    s_r[part][lane][1] = l1;
+    s_r[part][lane][2] = d0;
+    s_r[part][lane][3] = d1;
+    __syncthreads();
+    if (part != 0) return;
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+        l0 += s_r[w][lane][0];
+        l1 += s_r[w][lane][1];
+        d0 += s_r[w][lane][2];
+        d1 += s_r[w][lane][3];
     }
     // exchange with the partner lane
     const T ol0 = __shfl_xor(l0, 1), ol1 = __shfl_xor(l1, 1);
@@ -642,15 +708,15 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
         return;
     }
     const T A1 = gc<T>(B.a1)[q], A2 = gc<T>(B.a2)[q];
-    gp<T> u = gm<T>(B.u);
-    gp<T> v = gm<T>(B.v);
+    gp<T> uu = gm<T>(B.u);
+    gp<T> vv = gm<T>(B.v);
     const T dt2 = dt * dt;
     const T A3 = A2 + T(0.25) * dt2 * irho * La;
     const T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * irho * (Lb + Db);
-    const T uo = u[q], vo = v[q];
+    const T uo = uu[q], vo = vv[q];
     const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
-    u[q] = un;
-    v[q] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
+    uu[q] = un;
+    vv[q] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
     if (A.rec_out) {
         gp<double> ro = gm<double>(A.rec_out);
         for (int e = rg.beg; e < rg.end; ++e) {
@@ -859,51 +925,73 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
         __syncthreads();
         // (3) E at the leading row
         e_row(sn);
-        // (4) G at row j (all 64 columns), narrow terms
+        // (4) G at row j (all 64 columns) and the narrow x2 term, then the
+        // narrow x1 term; each direction forms its edge weights once for
+        // both fields, which keeps few values live at a time
         T lx[NF][2];
         T wc[NS];
+        {
+            T ky[3][2 * HF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            T wcol[2][NW];
+            for (int m = 0; m < 3; ++m) {
+                T bb[NW];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int k = 0; k < NW; ++k) wcol[q][k] = s_x[(K + k) % NW][2 * f + q][lane];
-            T w2[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                w2[q] = d1(HF > 1 ? wcol[q][0] : T(0), wcol[q][HF - 1], wcol[q][HF + 1],
-                           HF > 1 ? wcol[q][NW - 1] : T(0));
-                wc[2 * f + q] = wcol[q][HF];
+                for (int k = 0; k < NW; ++k) bb[k] = b2w[m][(K + k) % NW];
+                d2_weights<T, ORD>(bb, ky[m]);
             }
-            s_g[2 * f][lane] = mw[0][s0] * w2[0] + mw[1][s0] * w2[1];
-            s_g[2 * f + 1][lane] = mw[2][s0] * w2[0] + mw[3][s0] * w2[1];
-            T bc[3][NW];
 #pragma unroll
-            for (int k = 0; k < NW; ++k)
+            for (int f = 0; f < NF; ++f) {
+                T wcol[2][NW];
 #pragma unroll
-                for (int m = 0; m < 3; ++m) bc[m][k] = b2w[m][(K + k) % NW];
-            const T bx0 = d2_interior<T, ORD>(&bc[0][HF], &wcol[0][HF], 1);   // c2121 u1
-            const T bx1 = d2_interior<T, ORD>(&bc[1][HF], &wcol[1][HF], 1);   // c2122 u2
-            const T bx2 = d2_interior<T, ORD>(&bc[1][HF], &wcol[0][HF], 1);   // c2122 u1
-            const T bx3 = d2_interior<T, ORD>(&bc[2][HF], &wcol[1][HF], 1);   // c2222 u2
-            // x1 rows of the staged row j and of the x1 coefficients
-            T ur[2][NW], br[3][NW];
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int k = 0; k < NW; ++k) {
-                const int l = lane + k - HF;
-                const int lc = l < 0 ? 0 : (l > 63 ? 63 : l);
+                    for (int k = 0; k < NW; ++k) wcol[q][k] = s_x[(K + k) % NW][2 * f + q][lane];
+                T w2[2];
 #pragma unroll
-                for (int q = 0; q < 2; ++q) ur[q][k] = k == HF ? wcol[q][HF] : s_x[s0][2 * f + q][lc];
-#pragma unroll
-                for (int m = 0; m < 3; ++m) br[m][k] = k == HF ? b1c[m] : s_b[m][lc];
+                for (int q = 0; q < 2; ++q) {
+                    w2[q] = d1(HF > 1 ? wcol[q][0] : T(0), wcol[q][HF - 1], wcol[q][HF + 1],
+                               HF > 1 ? wcol[q][NW - 1] : T(0));
+                    wc[2 * f + q] = wcol[q][HF];
+                }
+                s_g[2 * f][lane] = mw[0][s0] * w2[0] + mw[1][s0] * w2[1];
+                s_g[2 * f + 1][lane] = mw[2][s0] * w2[0] + mw[3][s0] * w2[1];
+                const T by0 = d2_edges<T, ORD>(ky[0], wcol[0]);   // c2121 u1
+                const T by1 = d2_edges<T, ORD>(ky[1], wcol[1]);   // c2122 u2
+                const T by2 = d2_edges<T, ORD>(ky[1], wcol[0]);   // c2122 u1
+                const T by3 = d2_edges<T, ORD>(ky[2], wcol[1]);   // c2222 u2
+                lx[f][0] = (by0 + by1) * i22;
+                lx[f][1] = (by2 + by3) * i22;
             }
-            const T ax0 = d2_interior<T, ORD>(&br[0][HF], &ur[0][HF], 1);
-            const T ax1 = d2_interior<T, ORD>(&br[1][HF], &ur[1][HF], 1);
-            const T ax2 = d2_interior<T, ORD>(&br[1][HF], &ur[0][HF], 1);
-            const T ax3 = d2_interior<T, ORD>(&br[2][HF], &ur[1][HF], 1);
-            lx[f][0] = (ax0 + ax1) * i11 + (bx0 + bx1) * i22;
-            lx[f][1] = (ax2 + ax3) * i11 + (bx2 + bx3) * i22;
+        }
+        {
+            T kx[3][2 * HF];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                T bb[NW];
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    const int l = lane + k - HF;
+                    bb[k] = k == HF ? b1c[m] : s_b[m][l < 0 ? 0 : (l > 63 ? 63 : l)];
+                }
+                d2_weights<T, ORD>(bb, kx[m]);
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                T ur[2][NW];
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    const int l = lane + k - HF;
+                    const int lc = l < 0 ? 0 : (l > 63 ? 63 : l);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) ur[q][k] = k == HF ? wc[2 * f + q] : s_x[s0][2 * f + q][lc];
+                }
+                const T ax0 = d2_edges<T, ORD>(kx[0], ur[0]);   // c1111 u1
+                const T ax1 = d2_edges<T, ORD>(kx[1], ur[1]);   // c1112 u2
+                const T ax2 = d2_edges<T, ORD>(kx[1], ur[0]);   // c1112 u1
+                const T ax3 = d2_edges<T, ORD>(kx[2], ur[1]);   // c1212 u2
+                lx[f][0] += (ax0 + ax1) * i11;
+                lx[f][1] += (ax2 + ax3) * i11;
+            }
         }
         __syncthreads();
         // (5) D_1 G and D_2 E

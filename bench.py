@@ -37,9 +37,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roofline(kind, ms, points, wbytes, traffic=None):
+# measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+# of the 1025^2 workload; ignored once the kernel source has changed
+TRAFFIC_PROFILE = os.path.join(ROOT, 'profiles', 'hbm_traffic_c2_1025.md')
+
+
+def roofline(kind, ms, points, wbytes, traffic_key=None):
     byts = WORDS[kind] * wbytes * points
     gbs = byts / (ms * 1e-3) / 1e9
+    traffic = None
+    if traffic_key is not None:
+        from paper_2003_12811_amd import profiling
+        t = profiling.read_traffic(TRAFFIC_PROFILE)
+        traffic = t.get(traffic_key) if t else None
     return {"bound": "hbm", "kernel": kind, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
             "avg_ms": round(ms, 5), "bytes_per_launch": byts}
@@ -182,7 +192,8 @@ def main():
                                "(seed 0), displacement bottom + traction SATs, 10 Hz Ricker force, 16 receivers, "
                                "4th-order SBP-SAT, RK4 CFL 0.5" % (args.n, args.n),
                    "points": r64['points'], "dt": r64['dt'], "parallelism": "1 GPU"},
-        "roofline": roofline(k, r64['kernels'][k][0], pts, 8),
+        "roofline": roofline(k, r64['kernels'][k][0], pts, 8,
+                             traffic_key=('%s/f64/o4' % k) if args.n == 1025 else None),
         "kernels_ms": {kk: v[0] for kk, v in r64['kernels'].items() if v[1]},
         "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8),
         "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'],

@@ -112,6 +112,24 @@ __device__ __forceinline__ double tval(const PassArgs& A, int item, const W3& w)
     return w.w0 * t[0] + w.w1 * t[1] + w.w2 * t[2];
 }
 
+// sbpe_apply operand of block b.  The kernel argument is read through an
+// unrolled select: indexing it with a runtime block number would make the
+// compiler copy the whole argument block into per-lane scratch memory.
+__device__ __forceinline__ const void* apply_in(const PassArgs& A, int b) {
+    const void* p = A.in[0];
+#pragma unroll
+    for (int k = 1; k < MAX_APPLY_BLOCKS; ++k)
+        if (b == k) p = A.in[k];
+    return p;
+}
+__device__ __forceinline__ void* apply_out(const PassArgs& A, int b) {
+    void* p = A.out[0];
+#pragma unroll
+    for (int k = 1; k < MAX_APPLY_BLOCKS; ++k)
+        if (b == k) p = A.out[k];
+    return p;
+}
+
 template <typename T>
 __device__ __forceinline__ gcp<T> field_ptr(const PassArgs& A, int b, int fld) {
     BlockRef B = blk(A, b);
@@ -120,7 +138,7 @@ __device__ __forceinline__ gcp<T> field_ptr(const PassArgs& A, int b, int fld) {
         case FLD_V: return gc<T>(B.v);
         case FLD_A1: return gc<T>(B.a1);
         case FLD_A2: return gc<T>(B.a2);
-        default: return gc<T>(A.in[b]);
+        default: return gc<T>(apply_in(A, b));
     }
 }
 
@@ -663,7 +681,9 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
             if (hom) volume_part<T, ORD, 2>(B, u, i, j, l0, l1);
         } else {
             if (hom) volume_part<T, ORD, 3>(B, u, i, j, l0, l1);
-            const W3 cw = apply ? ca : (sub ? cb : ca);
+            // member-wise select (a runtime choice between two structs goes through scratch memory)
+            const bool second = !apply && sub;
+            const W3 cw{second ? cb.w0 : ca.w0, second ? cb.w1 : ca.w1, second ? cb.w2 : ca.w2};
             if ((!apply || sub == 1) && cw.any()) {
                 sat_point<T, ORD, true>(A, b, i, j, fld, cw, d0, d1);
                 point_data<T>(B, p, A, rg, cw, d0, d1);
@@ -693,7 +713,7 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
         // lane 0 holds L, lane 1 the data
         const T L = sub ? ol1 : l0;
         const T D = sub ? d1 : od0;
-        gm<T>(A.out[b])[q] = irho * (L + D);
+        gm<T>(apply_out(A, b))[q] = irho * (L + D);
         return;
     }
     // field 0 (lane 0) and field 1 (lane 1) results, component sub
@@ -802,7 +822,7 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
     auto cf = [&](int k) { return cbase + (size_t)k * fb; };
     const char* fin[NS];
     {
-        const void* f0p = PASS == PASS_APPLY ? A.in[b] : (PASS == PASS_RK1 ? B.u : B.a1);
+        const void* f0p = PASS == PASS_APPLY ? apply_in(A, b) : (PASS == PASS_RK1 ? B.u : B.a1);
         const void* f1p = PASS == PASS_RK1 ? B.v : B.a2;
 #pragma unroll
         for (int s = 0; s < NS; ++s) fin[s] = (const char*)(s < 2 ? f0p : f1p) + (s & 1) * (size_t)fb;
@@ -1014,7 +1034,7 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
                 if (NF == 2 && cb.any()) point_sources<T>(A, rg, po, cb, db0, db1);
             }
             if constexpr (PASS == PASS_APPLY) {
-                char* o = (char*)A.out[b];
+                char* o = (char*)apply_out(A, b);
                 sto<T>(o, p, irho * (L[0][0] + da0));
                 sto<T>(o + fb, p, irho * (L[0][1] + da1));
             } else if constexpr (PASS == PASS_RK1) {

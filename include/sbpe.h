@@ -185,6 +185,50 @@ sbpe_status sbpe_get_kernel_timing(sbpe_ctx_t ctx, double* ms_avg, int* count);
  * workgroups, info[4] = frame width in points. */
 sbpe_status sbpe_plan_info(sbpe_ctx_t ctx, long long* info);
 
+/* ------------------------------------------------------------------ batches
+ * Continuous batching of independent solves (many contexts, e.g. one shot
+ * each).  A batch advances the bound states of its members with one kernel
+ * launch per RK4 sweep over the union of their blocks, each member with its
+ * own time step, sources and receivers.  The arithmetic per block is exactly
+ * that of sbpe_advance, so a member's result does not depend on which other
+ * members share the launch.  Members join and leave between calls to
+ * sbpe_batch_advance; the caller decides admission (for example by an HBM
+ * budget).  All members must use the batch's device, dtype and order.  A
+ * batch is driven from one host thread.
+ *
+ * Errors: SBPE_EINVAL for bad arguments, SBPE_ESTATE when a context is not
+ * finalized with a bound state or already belongs to a batch, SBPE_ENOMEM,
+ * SBPE_EHIP; the message is returned by sbpe_batch_last_error(batch). */
+typedef struct sbpe_batch* sbpe_batch_t;
+
+/* Create a batch whose work is enqueued on hip_stream of hip_device. */
+sbpe_status sbpe_batch_create(int hip_device, void* hip_stream, int dtype, int order, sbpe_batch_t* out);
+sbpe_status sbpe_batch_destroy(sbpe_batch_t batch);
+const char* sbpe_batch_last_error(sbpe_batch_t batch);
+
+/* Admit a finalized context with a bound state for nsteps RK4 steps of size
+ * dt starting at its current time.  Its time functions for all nsteps steps
+ * are tabulated and its receiver buffer is sized here.  While it is a member,
+ * sbpe_advance, sbpe_apply and sbpe_bind_state on it fail with SBPE_ESTATE. */
+sbpe_status sbpe_batch_add(sbpe_batch_t batch, sbpe_ctx_t ctx, int nsteps, double dt);
+
+/* Remove a member (normally once its remaining step count is 0).  Work later
+ * enqueued on the context's own stream (sbpe_read_receivers, copies of the
+ * state) is ordered after the batch's work. */
+sbpe_status sbpe_batch_remove(sbpe_batch_t batch, sbpe_ctx_t ctx);
+
+/* Advance every member by nsteps steps; nsteps must not exceed any member's
+ * remaining step count. */
+sbpe_status sbpe_batch_advance(sbpe_batch_t batch, int nsteps);
+
+/* Remaining steps of a member; number of members, smallest remaining step
+ * count and total grid points of all members. */
+sbpe_status sbpe_batch_remaining(sbpe_batch_t batch, sbpe_ctx_t ctx, int* remaining);
+sbpe_status sbpe_batch_info(sbpe_batch_t batch, int* members, int* min_remaining, long long* points);
+
+/* Wait for all work enqueued by the batch. */
+sbpe_status sbpe_batch_synchronize(sbpe_batch_t batch);
+
 /* ---------------------------------------------------------------- host-side
  * Queries of the library's own setup, for checking it on a machine without a
  * GPU.  They run on the host only. */

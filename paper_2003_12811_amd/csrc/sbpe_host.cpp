@@ -175,6 +175,8 @@ struct sbpe_ctx {
     int npartial = 0;
     int guard_every = 0;
     double guard_growth = 0.0;
+    // member of a batch (sbpe_batch_add): the batch owns the stepping
+    void* batch = nullptr;
     // kernel timing: pending (kind, start, stop) event records and sums
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -598,6 +600,19 @@ static sbpe_status build_plan(sbpe_ctx* c) {
     c->tau_cap = 1;
     HIPCHECK(c, hipMalloc(&c->d_tau, (size_t)c->nitems * 3 * sizeof(double)));
     HIPCHECK(c, hipMemset(c->d_tau, 0, (size_t)c->nitems * 3 * sizeof(double)));
+    for (int b = 0; b < nb; ++b) {
+        BlockDesc& D = c->desc[b];
+        D.dt = 0.0;
+        D.beta = c->beta;
+        D.tau = c->d_tau;
+        D.nitems = c->nitems;
+        D.step0 = 0;
+        D.entries = c->d_entries;
+        D.tile_rng = c->d_tile_ranges + D.tile_beg;
+        D.frame_rng = c->d_frame_ranges + D.frame_beg;
+        D.rec = nullptr;
+        D.rec_stride = (long)c->receivers.size() * 16 * 2;
+    }
     HIPCHECK(c, hipMalloc(&c->d_desc, nb * sizeof(BlockDesc)));
     HIPCHECK(c, hipMemcpy(c->d_desc, c->desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice));
     c->npartial = 1024;
@@ -622,12 +637,27 @@ static PassArgs base_args(const sbpe_ctx* c) {
     std::memset(&a, 0, sizeof a);
     a.blocks = c->d_desc;
     a.nblocks = (int)c->blocks.size();
-    a.beta = c->beta;
-    a.entries = c->d_entries;
-    a.tile_ranges = c->d_tile_ranges;
-    a.frame_ranges = c->d_frame_ranges;
-    a.tau = c->d_tau;
     return a;
+}
+
+// Per-context sweep data in the block descriptors (time step, time-function
+// table, receiver buffer).  Uploaded only when something changed.
+static sbpe_status refresh_desc(sbpe_ctx* c, double dt) {
+    bool changed = false;
+    const long nrec = (long)c->receivers.size();
+    for (size_t b = 0; b < c->desc.size(); ++b) {
+        BlockDesc& D = c->desc[b];
+        double* rec = nrec > 0 ? c->d_rec : nullptr;
+        if (D.dt != dt || D.tau != c->d_tau || D.rec != rec) changed = true;
+        D.dt = dt;
+        D.tau = c->d_tau;
+        D.rec = rec;
+    }
+    if (!changed) return SBPE_OK;
+    HIPCHECK(c, hipStreamSynchronize(c->side));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(c->d_desc, c->desc.data(), c->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
+    return SBPE_OK;
 }
 
 static hipEvent_t next_event(sbpe_ctx* c) {
@@ -1021,6 +1051,7 @@ sbpe_status sbpe_block_size(sbpe_ctx_t c, int block, int* n1, int* n2) {
 }
 
 sbpe_status sbpe_apply(sbpe_ctx_t c, const void* const* u, void* const* a, double t, int homogeneous) {
+    if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     sbpe_status s = need_gpu(c);
     if (s) return s;
@@ -1036,10 +1067,13 @@ sbpe_status sbpe_apply(sbpe_ctx_t c, const void* const* u, void* const* a, doubl
         sbpe_status s2 = fill_tau(c, 1, t, 0.0);
         if (s2) return s2;
     }
+    {
+        sbpe_status s2 = refresh_desc(c, c->desc.empty() ? 0.0 : c->desc[0].dt);
+        if (s2) return s2;
+    }
     PassArgs pa = base_args(c);
     pa.pass = PASS_APPLY;
     pa.homogeneous = homogeneous ? 1 : 0;
-    pa.t = t;
     pa.wa[0] = homogeneous ? 0.0 : 1.0;
     for (int b = 0; b < nb; ++b) {
         pa.in[b] = u[b];
@@ -1051,6 +1085,7 @@ sbpe_status sbpe_apply(sbpe_ctx_t c, const void* const* u, void* const* a, doubl
 }
 
 sbpe_status sbpe_bind_state(sbpe_ctx_t c, void* const* u, void* const* v, double t) {
+    if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     sbpe_status s = need_gpu(c);
     if (s) return s;
@@ -1107,6 +1142,7 @@ sbpe_status sbpe_set_energy_guard(sbpe_ctx_t c, int every, double rel_growth) {
 }
 
 sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
+    if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     sbpe_status s = need_gpu(c);
     if (s) return s;
@@ -1134,25 +1170,25 @@ sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
     if (nsteps > 0) {
         s = fill_tau(c, nsteps, c->t, dt);
         if (s) return s;
+        s = refresh_desc(c, dt);
+        if (s) return s;
     }
     for (int k = 0; k < nsteps; ++k) {
         PassArgs p1 = base_args(c);
         p1.pass = PASS_RK1;
-        p1.t = c->t;
-        p1.dt = dt;
-        p1.tau = c->d_tau + (size_t)k * c->nitems * 3;
+        p1.step = k;
+        p1.rec_base = (int)c->rec_steps;
         p1.wa[0] = 1.0;     // tau(t)
         p1.wb[1] = 1.0;     // tau(t + dt/2)
         s = run_pass(c, p1);
         if (s) return s;
         PassArgs p2 = p1;
         p2.pass = PASS_RK2;
-        const double w2 = 2.0 / (dt * dt);   // 2/dt^2 (tau(t) - 2 tau(t + dt/2) + tau(t + dt))
+        // 2/dt^2 (tau(t) - 2 tau(t + dt/2) + tau(t + dt)); the kernels apply 2/dt^2
         p2.wa[0] = p2.wa[1] = p2.wa[2] = 0.0;
-        p2.wb[0] = w2;
-        p2.wb[1] = -2.0 * w2;
-        p2.wb[2] = w2;
-        p2.rec_out = nrec > 0 ? c->d_rec + (c->rec_steps + k) * slots : nullptr;
+        p2.wb[0] = 1.0;
+        p2.wb[1] = -2.0;
+        p2.wb[2] = 1.0;
         s = run_pass(c, p2);
         if (s) return s;
         c->t += dt;
@@ -1312,3 +1348,263 @@ sbpe_status sbpe_get_block_fields(sbpe_ctx_t c, int block, double* c10, double* 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches
+// A batch advances the bound states of several finalized contexts with one
+// kernel launch per sweep over the union of their blocks (each block carries
+// its own time step, time-function table and receiver buffer).  Members join
+// and leave between calls to sbpe_batch_advance.
+struct BatchMember {
+    sbpe_ctx* ctx;
+    double dt;
+    int remaining;   // steps still to take
+    int step0;       // batch step index at which the member joined
+    long rec0;       // receiver row of the member at its first batch step
+};
+
+struct sbpe_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    int dtype = SBPE_F64, order = 4;
+    std::string err;
+    std::vector<BatchMember> members;
+    std::vector<BlockDesc> desc;
+    BlockDesc* d_desc = nullptr;
+    size_t desc_cap = 0;
+    int total_tiles = 0, total_frame_wg = 0;
+    int step = 0;
+    bool dirty = true;
+};
+
+static sbpe_status bfail(sbpe_batch* b, sbpe_status code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_static_err = msg;
+    return code;
+}
+
+#define BHIPCHECK(bt, expr)                                                                        \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return bfail(bt, SBPE_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" {
+
+sbpe_status sbpe_batch_create(int device, void* stream, int dtype, int order, sbpe_batch_t* out) {
+    if (!out) return bfail(nullptr, SBPE_EINVAL, "out is NULL");
+    if (dtype != SBPE_F64 && dtype != SBPE_F32) return bfail(nullptr, SBPE_EINVAL, "bad dtype");
+    if (order != 2 && order != 4) return bfail(nullptr, SBPE_EINVAL, "order must be 2 or 4");
+    int n = 0;
+    if (device < 0 || hipGetDeviceCount(&n) != hipSuccess || device >= n) return bfail(nullptr, SBPE_EHIP, "no such HIP device");
+    if (hipSetDevice(device) != hipSuccess) return bfail(nullptr, SBPE_EHIP, "hipSetDevice failed");
+    sbpe_batch* b = new sbpe_batch;
+    b->device = device;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->dtype = dtype;
+    b->order = order;
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_side, hipEventDisableTiming) != hipSuccess) {
+        delete b;
+        return bfail(nullptr, SBPE_EHIP, "stream/event creation failed");
+    }
+    *out = b;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_batch_destroy(sbpe_batch_t b) {
+    if (!b) return SBPE_OK;
+    (void)hipStreamSynchronize(b->side);
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& m : b->members) m.ctx->batch = nullptr;
+    (void)hipFree(b->d_desc);
+    (void)hipEventDestroy(b->ev_main);
+    (void)hipEventDestroy(b->ev_side);
+    (void)hipStreamDestroy(b->side);
+    delete b;
+    return SBPE_OK;
+}
+
+const char* sbpe_batch_last_error(sbpe_batch_t b) { return b ? b->err.c_str() : g_static_err.c_str(); }
+
+sbpe_status sbpe_batch_add(sbpe_batch_t b, sbpe_ctx_t c, int nsteps, double dt) {
+    if (!b || !c) return bfail(b, SBPE_EINVAL, "NULL batch or context");
+    if (c->host_only || !c->finalized || !c->bound) return bfail(b, SBPE_ESTATE, "context must be finalized with a bound state");
+    if (c->batch) return bfail(b, SBPE_ESTATE, "context already belongs to a batch");
+    if (c->device != b->device || c->dtype != b->dtype || c->order != b->order)
+        return bfail(b, SBPE_EINVAL, "context device, dtype or order differs from the batch");
+    if (nsteps <= 0 || !(dt > 0) || !std::isfinite(dt)) return bfail(b, SBPE_EINVAL, "bad nsteps or dt");
+    // time functions for all its steps, receiver rows for all its steps
+    sbpe_status s = fill_tau(c, nsteps, c->t, dt);
+    if (s) return bfail(b, s, c->err);
+    const long nrec = (long)c->receivers.size();
+    const long slots = nrec * 16 * 2;
+    if (nrec > 0 && c->rec_steps + nsteps > c->rec_cap) {
+        const long cap = c->rec_steps + nsteps;
+        double* nd = nullptr;
+        if (hipMalloc(&nd, cap * slots * sizeof(double)) != hipSuccess) return bfail(b, SBPE_ENOMEM, "receiver buffer");
+        if (c->d_rec && c->rec_steps > 0)
+            BHIPCHECK(b, hipMemcpyAsync(nd, c->d_rec, c->rec_steps * slots * sizeof(double), hipMemcpyDeviceToDevice,
+                                        c->stream));
+        BHIPCHECK(b, hipStreamSynchronize(c->stream));
+        (void)hipFree(c->d_rec);
+        c->d_rec = nd;
+        c->rec_cap = cap;
+    }
+    // the batch streams wait for everything already enqueued on the context
+    BHIPCHECK(b, hipEventRecord(c->ev_main, c->stream));
+    BHIPCHECK(b, hipStreamWaitEvent(b->stream, c->ev_main, 0));
+    BHIPCHECK(b, hipStreamWaitEvent(b->side, c->ev_main, 0));
+    c->batch = b;
+    b->members.push_back(BatchMember{c, dt, nsteps, b->step, c->rec_steps});
+    b->dirty = true;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_batch_remove(sbpe_batch_t b, sbpe_ctx_t c) {
+    if (!b || !c) return bfail(b, SBPE_EINVAL, "NULL batch or context");
+    size_t k = 0;
+    while (k < b->members.size() && b->members[k].ctx != c) ++k;
+    if (k == b->members.size()) return bfail(b, SBPE_EINVAL, "context is not a member");
+    // later work on the context's stream waits for the batch's work
+    BHIPCHECK(b, hipEventRecord(b->ev_side, b->side));
+    BHIPCHECK(b, hipStreamWaitEvent(c->stream, b->ev_side, 0));
+    BHIPCHECK(b, hipEventRecord(b->ev_main, b->stream));
+    BHIPCHECK(b, hipStreamWaitEvent(c->stream, b->ev_main, 0));
+    c->batch = nullptr;
+    b->members.erase(b->members.begin() + k);
+    b->dirty = true;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_batch_remaining(sbpe_batch_t b, sbpe_ctx_t c, int* remaining) {
+    if (!b || !c || !remaining) return bfail(b, SBPE_EINVAL, "NULL argument");
+    for (auto& m : b->members)
+        if (m.ctx == c) {
+            *remaining = m.remaining;
+            return SBPE_OK;
+        }
+    return bfail(b, SBPE_EINVAL, "context is not a member");
+}
+
+sbpe_status sbpe_batch_info(sbpe_batch_t b, int* members, int* min_remaining, long long* points) {
+    if (!b) return bfail(nullptr, SBPE_EINVAL, "NULL batch");
+    int mr = 0;
+    long long pts = 0;
+    for (size_t k = 0; k < b->members.size(); ++k) {
+        mr = k == 0 ? b->members[k].remaining : std::min(mr, b->members[k].remaining);
+        for (auto& B : b->members[k].ctx->blocks) pts += (long long)B.n1 * B.n2;
+    }
+    if (members) *members = (int)b->members.size();
+    if (min_remaining) *min_remaining = mr;
+    if (points) *points = pts;
+    return SBPE_OK;
+}
+
+}  // extern "C"
+
+// concatenated descriptors of all members (blocks renumbered, launch ranges rebased)
+static sbpe_status batch_rebuild(sbpe_batch* b) {
+    b->desc.clear();
+    int tiles = 0, fwg = 0;
+    for (auto& m : b->members) {
+        sbpe_ctx* c = m.ctx;
+        const int base = (int)b->desc.size();
+        const long nrec = (long)c->receivers.size();
+        for (size_t k = 0; k < c->desc.size(); ++k) {
+            BlockDesc D = c->desc[k];
+            D.tile_beg = tiles;
+            tiles += D.tiles_x * D.tiles_y;
+            D.frame_beg = fwg;
+            fwg += D.frame_wg;
+            for (int f = 0; f < 4; ++f)
+                if (D.face[f].kind == BC_INTERFACE) D.face[f].partner += base;
+            D.dt = m.dt;
+            D.tau = c->d_tau;
+            D.step0 = m.step0;
+            D.rec = nrec > 0 ? c->d_rec + m.rec0 * D.rec_stride : nullptr;
+            b->desc.push_back(D);
+        }
+    }
+    b->total_tiles = tiles;
+    b->total_frame_wg = fwg;
+    if (b->desc.empty()) {
+        b->dirty = false;
+        return SBPE_OK;
+    }
+    BHIPCHECK(b, hipStreamSynchronize(b->side));
+    BHIPCHECK(b, hipStreamSynchronize(b->stream));
+    if (b->desc.size() > b->desc_cap) {
+        (void)hipFree(b->d_desc);
+        b->d_desc = nullptr;
+        const size_t cap = std::max(b->desc.size(), 2 * b->desc_cap);
+        if (hipMalloc(&b->d_desc, cap * sizeof(BlockDesc)) != hipSuccess) return bfail(b, SBPE_ENOMEM, "descriptor table");
+        b->desc_cap = cap;
+    }
+    BHIPCHECK(b, hipMemcpy(b->d_desc, b->desc.data(), b->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
+    b->dirty = false;
+    return SBPE_OK;
+}
+
+static sbpe_status batch_pass(sbpe_batch* b, const PassArgs& a) {
+    BHIPCHECK(b, hipEventRecord(b->ev_main, b->stream));
+    BHIPCHECK(b, hipStreamWaitEvent(b->side, b->ev_main, 0));
+    BHIPCHECK(b, hipEventRecord(b->ev_side, b->side));
+    BHIPCHECK(b, hipStreamWaitEvent(b->stream, b->ev_side, 0));
+    int e = launch_interior(b->dtype, b->order, a, b->total_tiles, b->stream);
+    if (e == 0) e = launch_frame(b->dtype, b->order, a, b->total_frame_wg, b->side);
+    if (e != 0) return bfail(b, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+extern "C" sbpe_status sbpe_batch_advance(sbpe_batch_t b, int nsteps) {
+    if (!b) return bfail(nullptr, SBPE_EINVAL, "NULL batch");
+    if (nsteps < 0) return bfail(b, SBPE_EINVAL, "nsteps < 0");
+    for (auto& m : b->members)
+        if (m.remaining < nsteps) return bfail(b, SBPE_EINVAL, "nsteps exceeds the remaining steps of a member");
+    if (b->members.empty() || nsteps == 0) return SBPE_OK;
+    if (hipSetDevice(b->device) != hipSuccess) return bfail(b, SBPE_EHIP, "hipSetDevice failed");
+    if (b->dirty) {
+        sbpe_status s = batch_rebuild(b);
+        if (s) return s;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        PassArgs p1;
+        std::memset(&p1, 0, sizeof p1);
+        p1.blocks = b->d_desc;
+        p1.nblocks = (int)b->desc.size();
+        p1.pass = PASS_RK1;
+        p1.step = b->step + k;
+        p1.rec_base = 0;
+        p1.wa[0] = 1.0;
+        p1.wb[1] = 1.0;
+        sbpe_status s = batch_pass(b, p1);
+        if (s) return s;
+        PassArgs p2 = p1;
+        p2.pass = PASS_RK2;
+        p2.wa[0] = 0.0;
+        p2.wb[0] = 1.0;
+        p2.wb[1] = -2.0;
+        p2.wb[2] = 1.0;
+        s = batch_pass(b, p2);
+        if (s) return s;
+    }
+    BHIPCHECK(b, hipEventRecord(b->ev_side, b->side));
+    BHIPCHECK(b, hipStreamWaitEvent(b->stream, b->ev_side, 0));
+    b->step += nsteps;
+    for (auto& m : b->members) {
+        m.remaining -= nsteps;
+        m.ctx->t += nsteps * m.dt;
+        m.ctx->rec_steps += nsteps;
+    }
+    return SBPE_OK;
+}
+
+extern "C" sbpe_status sbpe_batch_synchronize(sbpe_batch_t b) {
+    if (!b) return bfail(nullptr, SBPE_EINVAL, "NULL batch");
+    BHIPCHECK(b, hipStreamSynchronize(b->side));
+    BHIPCHECK(b, hipStreamSynchronize(b->stream));
+    return SBPE_OK;
+}

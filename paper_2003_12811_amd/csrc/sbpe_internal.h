@@ -55,6 +55,9 @@ struct FaceDesc {
     const void* Th;    // [2][nf] Jhat Theta / (2 w) in this face's order (interface), or null
 };
 
+struct Entry;
+struct Range;
+
 struct BlockDesc {
     int n1, n2;
     double h1, h2;
@@ -70,6 +73,17 @@ struct BlockDesc {
     int tiles_x, tiles_y, tile_beg;     // interior launch geometry
     int tile_y, pad_t;                  // output rows per interior tile
     int frame_n, frame_wg, frame_beg;   // frame launch geometry (points, workgroups, first workgroup)
+    // per-context data of a sweep (a launch may cover blocks of several contexts)
+    double dt;                // RK time step
+    double beta;              // penalty factor
+    const double* tau;        // tabulated time functions [steps][nitems][3]
+    int nitems;               // items per tabulated step
+    int step0;                // launch step index at which tau row 0 (and receiver row 0) applies
+    const Entry* entries;     // point entries of the context
+    const Range* tile_rng;    // entry ranges of this block's interior tiles (index wg - tile_beg)
+    const Range* frame_rng;   // entry ranges of this block's frame workgroups (index wg - frame_beg)
+    double* rec;              // receiver slots [steps][nrec*16][2], or null
+    long rec_stride;          // doubles per step in rec
 };
 
 // point entries: sources add to the right-hand side, receivers record u
@@ -98,15 +112,12 @@ struct PassArgs {
     int pass;
     int homogeneous;
     int total_tiles;                    // interior workgroups over all blocks
-    double t, dt, beta;
-    const double* tau;                  // time-function values of this step [nitems][3]
+    int step;                           // launch step index (time-function row step - step0)
+    int rec_base;                       // receiver row of launch step index 0
     double wa[3], wb[3];                // weights of the tabulated values: first / second evaluation
+                                        // (second sweep: wb multiplies 2/dt^2 of each block)
     const void* in[MAX_APPLY_BLOCKS];   // sbpe_apply operands per block
     void* out[MAX_APPLY_BLOCKS];
-    const Entry* entries;
-    const Range* tile_ranges;    // per interior workgroup
-    const Range* frame_ranges;   // per frame workgroup
-    double* rec_out;             // receiver slots of the current step [nrec*16][2], or null
 };
 
 // interior tile: one wave spanning 64 columns writes the central

@@ -45,7 +45,7 @@ template <typename T>
 __device__ __forceinline__ gp<T> gm(void* p) { return (gp<T>)p; }
 using BlockRef = const GLB BlockDesc&;
 __device__ __forceinline__ BlockRef blk(const PassArgs& A, int b) { return ((const GLB BlockDesc*)A.blocks)[b]; }
-__device__ __forceinline__ const GLB Entry& entry(const PassArgs& A, int e) { return ((const GLB Entry*)A.entries)[e]; }
+__device__ __forceinline__ const GLB Entry& entry(BlockRef B, int e) { return ((const GLB Entry*)B.entries)[e]; }
 __device__ __forceinline__ Range load_range(const Range* base, int k) {
     const GLB Range& r = ((const GLB Range*)base)[k];
     Range o;
@@ -104,14 +104,23 @@ struct W3 {
     __device__ bool any() const { return w0 != 0.0 || w1 != 0.0 || w2 != 0.0; }
 };
 __device__ __forceinline__ W3 weights_a(const PassArgs& A) { return W3{A.wa[0], A.wa[1], A.wa[2]}; }
-__device__ __forceinline__ W3 weights_b(const PassArgs& A) { return W3{A.wb[0], A.wb[1], A.wb[2]}; }
+// second-evaluation weights; in the second RK sweep they multiply 2/dt^2 of the block
+__device__ __forceinline__ W3 weights_b(const PassArgs& A, BlockRef B) {
+    const double s = A.pass == PASS_RK2 ? 2.0 / (B.dt * B.dt) : 1.0;
+    return W3{s * A.wb[0], s * A.wb[1], s * A.wb[2]};
+}
 
 // weighted time-function value of an item in this step
-__device__ __forceinline__ double tval(const PassArgs& A, int item, const W3& w) {
-    const GLB double* t = (const GLB double*)A.tau + 3 * item;
+__device__ __forceinline__ double tval(BlockRef B, const PassArgs& A, int item, const W3& w) {
+    const GLB double* t = (const GLB double*)B.tau + ((long)(A.step - B.step0) * B.nitems + item) * 3;
     return w.w0 * t[0] + w.w1 * t[1] + w.w2 * t[2];
 }
 
+// receiver slots of the current step, or null
+__device__ __forceinline__ gp<double> rec_slots(BlockRef B, const PassArgs& A) {
+    if (!B.rec) return nullptr;
+    return (gp<double>)B.rec + (long)(A.rec_base + A.step - B.step0) * B.rec_stride;
+}
 // sbpe_apply operand of block b.  The kernel argument is read through an
 // unrolled select: indexing it with a runtime block number would make the
 // compiler copy the whole argument block into per-lane scratch memory.
@@ -421,12 +430,12 @@ __device__ __forceinline__ void face_delta(const PassArgs& A, int b, int f, int 
         d0 = 0;
         d1 = 0;
         if (F.kind == BC_DISPLACEMENT && F.g) {
-            const T tau = static_cast<T>(tval(A, F.item_g, tc));
+            const T tau = static_cast<T>(tval(B, A, F.item_g, tc));
             gcp<T> g = gc<T>(F.g);
             d0 = -tau * g[t];
             d1 = -tau * g[F.nf + t];
         } else if (F.kind == BC_INTERFACE && F.V) {
-            const T tau = static_cast<T>(F.vsign * tval(A, F.item_v, tc));
+            const T tau = static_cast<T>(F.vsign * tval(B, A, F.item_v, tc));
             gcp<T> V = gc<T>(F.V);
             d0 = -tau * V[t];
             d1 = -tau * V[F.nf + t];
@@ -441,7 +450,7 @@ template <typename T, int ORD, bool DATA>
 __device__ __forceinline__ void face_sat(const PassArgs& A, int b, int f, int dn, int t, int fld, const W3& tc, T& r0, T& r1) {
     using O = Op<ORD>;
     BlockRef B = blk(A, b);
-    const double beta = A.beta;
+    const double beta = B.beta;
     const GLB FaceDesc& F = B.face[f];
     const int a = f >> 1;
     const long np = (long)B.n1 * B.n2;
@@ -470,7 +479,7 @@ __device__ __forceinline__ void face_sat(const PassArgs& A, int b, int f, int dn
                 r1 -= U[2 * F.nf + t] * x0 + U[3 * F.nf + t] * x1;
             }
         } else if (F.g) {
-            const T tau = static_cast<T>(tval(A, F.item_g, tc));
+            const T tau = static_cast<T>(tval(B, A, F.item_g, tc));
             gcp<T> g = gc<T>(F.g);
             r0 += tau * g[t];
             r1 += tau * g[F.nf + t];
@@ -561,7 +570,7 @@ __device__ __forceinline__ void face_sat(const PassArgs& A, int b, int f, int dn
             r0 -= T(0.5) * iw * (tu0 + tv0);
             r1 -= T(0.5) * iw * (tu1 + tv1);
         } else if (F.Th) {
-            const T tau = static_cast<T>(tval(A, F.item_v, tc));
+            const T tau = static_cast<T>(tval(B, A, F.item_v, tc));
             gcp<T> Th = gc<T>(F.Th);
             r0 += tau * Th[t];
             r1 += tau * Th[F.nf + t];
@@ -583,11 +592,12 @@ __device__ __forceinline__ void sat_point(const PassArgs& A, int b, int i, int j
 
 // sources (and, in the frame, the forcing) at flat point p
 template <typename T>
-__device__ __forceinline__ void point_sources(const PassArgs& A, const Range& rg, long p, const W3& tc, T& r0, T& r1) {
+__device__ __forceinline__ void point_sources(BlockRef B, const PassArgs& A, const Range& rg, long p, const W3& tc, T& r0,
+                                              T& r1) {
     for (int e = rg.beg; e < rg.end; ++e) {
-        const GLB Entry& E = entry(A, e);
+        const GLB Entry& E = entry(B, e);
         if (E.kind == 0 && E.p == p) {
-            const double tau = tval(A, E.id, tc);
+            const double tau = tval(B, A, E.id, tc);
             r0 += static_cast<T>(E.c0 * tau);
             r1 += static_cast<T>(E.c1 * tau);
         }
@@ -599,11 +609,11 @@ __device__ __forceinline__ void point_data(BlockRef B, long p, const PassArgs& A
                                            T& r0, T& r1) {
     if (B.force) {
         gcp<T> F = gc<T>(B.force);
-        const T tau = static_cast<T>(tval(A, B.item_f, tc));
+        const T tau = static_cast<T>(tval(B, A, B.item_f, tc));
         r0 += tau * F[p];
         r1 += tau * F[(long)B.n1 * B.n2 + p];
     }
-    point_sources<T>(A, rg, p, tc, r0, r1);
+    point_sources<T>(B, A, rg, p, tc, r0, r1);
 }
 
 __device__ __forceinline__ int find_block(const PassArgs& A, int wg, bool frame) {
@@ -638,7 +648,7 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     const int lane = threadIdx.x & 63;
     const int sub = lane & 1;
     const int k = (wg - B.frame_beg) * FRAME_PTS + (lane >> 1);
-    const Range rg = load_range(A.frame_ranges, wg);
+    const Range rg = load_range(B.frame_rng, wg - B.frame_beg);
     const int n1 = B.n1, n2 = B.n2;
     const long np = (long)n1 * n2;
     const bool valid = k < B.frame_n;
@@ -660,7 +670,7 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     }
     const long p = (long)j * n1 + i;
     const W3 none{0.0, 0.0, 0.0};
-    const W3 ca = weights_a(A), cb = weights_b(A);
+    const W3 ca = weights_a(A), cb = weights_b(A, B);
     T l0 = 0, l1 = 0, d0 = 0, d1 = 0;
     if (valid) {
         const bool apply = A.pass == PASS_APPLY;
@@ -721,7 +731,7 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     const T Lb = sub ? l1 : ol0;     // L f1, component sub
     const T Da = sub ? od1 : d0;
     const T Db = sub ? d1 : od0;
-    const T dt = static_cast<T>(A.dt);
+    const T dt = static_cast<T>(B.dt);
     if (A.pass == PASS_RK1) {
         gm<T>(B.a1)[q] = irho * (La + Da);
         gm<T>(B.a2)[q] = irho * (La + T(0.5) * dt * Lb + Db);
@@ -737,10 +747,9 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
     uu[q] = un;
     vv[q] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
-    if (A.rec_out) {
-        gp<double> ro = gm<double>(A.rec_out);
+    if (gp<double> ro = rec_slots(B, A)) {
         for (int e = rg.beg; e < rg.end; ++e) {
-            const GLB Entry& E = entry(A, e);
+            const GLB Entry& E = entry(B, e);
             if (E.kind == 1 && E.p == p) ro[2 * E.id + sub] = E.c0 * static_cast<double>(un);
         }
     }
@@ -832,16 +841,16 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
     const bool force = B.force != nullptr;
     const char* frc = force ? (const char*)B.force : cbase + (size_t)K_IRHO * fb;
     const unsigned frc1 = force ? fb : 0u;
-    const Range rg = load_range(A.tile_ranges, wg);
-    const W3 ca = weights_a(A), cb = weights_b(A);
+    const Range rg = load_range(B.tile_rng, wg - B.tile_beg);
+    const W3 ca = weights_a(A), cb = weights_b(A, B);
     T tauf_a = 0, tauf_b = 0;
     if (force) {
-        tauf_a = static_cast<T>(tval(A, B.item_f, ca));
-        tauf_b = static_cast<T>(tval(A, B.item_f, cb));
+        tauf_a = static_cast<T>(tval(B, A, B.item_f, ca));
+        tauf_b = static_cast<T>(tval(B, A, B.item_f, cb));
     }
     const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
     const T i11 = ih1 * ih1, i22 = ih2 * ih2, i12 = ih1 * ih2;
-    const T dt = static_cast<T>(A.dt);
+    const T dt = static_cast<T>(B.dt);
 
     // interior first derivative (times h) from the four neighbours
     auto d1 = [&](T um2, T um1, T up1, T up2) -> T {
@@ -1030,8 +1039,8 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
             const long po = (long)j * n1 + i;
             T da0 = tauf_a * f0, da1 = tauf_a * f1, db0 = tauf_b * f0, db1 = tauf_b * f1;
             if (rg.end > rg.beg) {
-                if (ca.any()) point_sources<T>(A, rg, po, ca, da0, da1);
-                if (NF == 2 && cb.any()) point_sources<T>(A, rg, po, cb, db0, db1);
+                if (ca.any()) point_sources<T>(B, A, rg, po, ca, da0, da1);
+                if (NF == 2 && cb.any()) point_sources<T>(B, A, rg, po, cb, db0, db1);
             }
             if constexpr (PASS == PASS_APPLY) {
                 char* o = (char*)apply_out(A, b);
@@ -1061,10 +1070,10 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
                     sto<T>(u + q * fb, p, un[q]);
                     sto<T>(v + q * fb, p, xo[2 + q] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4));
                 }
-                if (A.rec_out && rg.end > rg.beg) {
-                    gp<double> ro = gm<double>(A.rec_out);
+                gp<double> ro = rec_slots(B, A);
+                if (ro && rg.end > rg.beg) {
                     for (int e = rg.beg; e < rg.end; ++e) {
-                        const GLB Entry& E = entry(A, e);
+                        const GLB Entry& E = entry(B, e);
                         if (E.kind == 1 && E.p == po) {
                             ro[2 * E.id] = E.c0 * static_cast<double>(un[0]);
                             ro[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);

@@ -62,6 +62,14 @@ _PROTOS = {
     'sbpe_set_kernel_timing': [_P, _I],
     'sbpe_get_kernel_timing': [_P, _DP, _IP],
     'sbpe_plan_info': [_P, ctypes.POINTER(ctypes.c_longlong)],
+    'sbpe_batch_create': [_I, _P, _I, _I, ctypes.POINTER(_P)],
+    'sbpe_batch_destroy': [_P],
+    'sbpe_batch_add': [_P, _P, _I, _D],
+    'sbpe_batch_remove': [_P, _P],
+    'sbpe_batch_advance': [_P, _I],
+    'sbpe_batch_remaining': [_P, _P, _IP],
+    'sbpe_batch_info': [_P, _IP, _IP, ctypes.POINTER(ctypes.c_longlong)],
+    'sbpe_batch_synchronize': [_P],
 }
 
 
@@ -79,6 +87,8 @@ def lib():
             fn.restype = ctypes.c_int32
         L.sbpe_last_error.argtypes = [_P]
         L.sbpe_last_error.restype = ctypes.c_char_p
+        L.sbpe_batch_last_error.argtypes = [_P]
+        L.sbpe_batch_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -273,3 +283,48 @@ def sbpe_plan_info(ctx):
     _check(ctx, lib().sbpe_plan_info(ctx, info))
     return dict(interior_points=info[0], frame_points=info[1], interior_workgroups=info[2],
                 frame_workgroups=info[3], frame_width=info[4])
+
+
+# ------------------------------------------------------------------ batches
+def _bcheck(batch, code):
+    if code != OK:
+        msg = lib().sbpe_batch_last_error(batch)
+        raise SbpeError(code, msg.decode() if msg else '')
+
+
+def sbpe_batch_create(device, stream, dtype, order):
+    h = _P()
+    _bcheck(None, lib().sbpe_batch_create(device, _P(stream or 0), dtype, order, ctypes.byref(h)))
+    return h
+
+
+def sbpe_batch_destroy(batch):
+    _bcheck(None, lib().sbpe_batch_destroy(batch))
+
+
+def sbpe_batch_add(batch, ctx, nsteps, dt):
+    _bcheck(batch, lib().sbpe_batch_add(batch, ctx, nsteps, dt))
+
+
+def sbpe_batch_remove(batch, ctx):
+    _bcheck(batch, lib().sbpe_batch_remove(batch, ctx))
+
+
+def sbpe_batch_advance(batch, nsteps):
+    _bcheck(batch, lib().sbpe_batch_advance(batch, nsteps))
+
+
+def sbpe_batch_remaining(batch, ctx):
+    r = _I()
+    _bcheck(batch, lib().sbpe_batch_remaining(batch, ctx, ctypes.byref(r)))
+    return r.value
+
+
+def sbpe_batch_info(batch):
+    m, r, p = _I(), _I(), ctypes.c_longlong()
+    _bcheck(batch, lib().sbpe_batch_info(batch, ctypes.byref(m), ctypes.byref(r), ctypes.byref(p)))
+    return dict(members=m.value, min_remaining=r.value, points=p.value)
+
+
+def sbpe_batch_synchronize(batch):
+    _bcheck(batch, lib().sbpe_batch_synchronize(batch))

@@ -1,0 +1,254 @@
+"""Served forward solves with continuous batching.
+
+A stream of independent shots arrives over time.  Each shot is one
+curvilinear block with its own material, a Ricker point source and surface
+receivers, run for a fixed number of RK4 steps.  The server keeps every
+admitted shot's fields and wavefield resident in HBM and advances all of them
+together through a library batch (``sbpe_batch_*``): one kernel launch per RK4
+sweep covers the blocks of every admitted shot.
+
+* Admission: a shot is set up (library context, coefficient fields, state)
+  as soon as it has arrived and its device memory fits in the HBM budget next
+  to the shots already admitted (first come, first served); setup runs on
+  worker threads while the GPU advances the batch.
+* Between chunks of steps, set-up shots join the batch and finished shots
+  leave it, their receiver traces are read back and their memory is freed.
+* Latency of a shot = completion time - arrival time; the server reports
+  p50/p99 latency, shots/s and grid-point updates/s.
+
+``run_sequential`` runs the same shots one after another with the plain
+per-context ``sbpe_advance`` (the comparison for the batched form).
+"""
+import collections
+import queue
+import threading
+import time
+
+import numpy as np
+
+from . import sbpe as S
+from . import workloads as W
+
+WORDS_RESIDENT = 11 + 4 + 4   # coefficients, RK workspace (a1, a2), state (u, v) per point
+
+
+def shot_bytes(n, nrec, steps, dtype):
+    """Device memory of one admitted shot (fields, state, receiver rows)."""
+    w = 8 if dtype == 'f64' else 4
+    return WORDS_RESIDENT * n * n * w + steps * nrec * 16 * 2 * 8 + 64 * n * 8
+
+
+def make_requests(nshots, rate, sizes, steps, seed=0, nrec=64):
+    """Poisson arrivals (mean rate per second) with sizes drawn uniformly."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, nshots)) if rate > 0 else np.zeros(nshots)
+    n = rng.choice(np.asarray(sizes), nshots)
+    return [dict(id=k, arrival=float(t[k]), n=int(n[k]), seed=k, steps=steps, nrec=nrec) for k in range(nshots)]
+
+
+class Shot:
+    """A library context for one shot, with its state tensors on the device."""
+
+    def __init__(self, req, spec, dtype, device, stream):
+        import torch
+        self.req = req
+        self.ctx = S.sbpe_create(device, stream.cuda_stream, S.F64 if dtype == 'f64' else S.F32,
+                                 spec['order'], 1.0)
+        try:
+            for b in spec['blocks']:
+                bid = S.sbpe_add_block(self.ctx, b['X1'], b['X2'], b['rho'], b['C10'])
+                for f, (kind, g, tfn, tp, U) in enumerate(b['bc']):
+                    if kind != S.BC_TRACTION:
+                        S.sbpe_set_bc(self.ctx, bid, f, kind, U)
+                    if g is not None:
+                        S.sbpe_set_bc_data(self.ctx, bid, f, g, tfn, tp)
+            for (bid, x1, x2, f1, f2, amp, fp, t0) in spec.get('sources', []):
+                S.sbpe_add_source(self.ctx, bid, x1, x2, f1, f2, amp, fp, t0)
+            for (bid, x1, x2) in spec.get('receivers', []):
+                S.sbpe_add_receivers(self.ctx, bid, x1, x2)
+            S.sbpe_finalize(self.ctx)
+            self.dt = S.sbpe_dt_cfl(self.ctx, spec.get('cfl', 0.5))
+            tdt = torch.float64 if dtype == 'f64' else torch.float32
+            shape = (2,) + spec['blocks'][0]['X1'].shape
+            with torch.cuda.stream(stream):
+                self.u = torch.zeros(shape, dtype=tdt, device=device)
+                self.v = torch.zeros(shape, dtype=tdt, device=device)
+            stream.synchronize()
+            S.sbpe_bind_state(self.ctx, [self.u.data_ptr()], [self.v.data_ptr()], 0.0)
+        except Exception:
+            S.sbpe_destroy(self.ctx)
+            raise
+        self.nrec = sum(len(r[1]) for r in spec.get('receivers', []))
+        self.points = sum(b['X1'].size for b in spec['blocks'])
+
+    def receivers(self):
+        return S.sbpe_read_receivers(self.ctx, self.nrec)
+
+    def close(self):
+        if self.ctx is not None:
+            S.sbpe_destroy(self.ctx)
+            self.ctx = None
+
+
+def default_spec(req, device='cuda'):
+    """Client-side inputs of a shot (material sums evaluated with torch on the GPU)."""
+    return W.spec_shot(req['n'], req['seed'], nrec=req['nrec'], device=device)
+
+
+class Server:
+    """Continuous-batching server over one GPU.
+
+    hbm_budget: bytes of device memory the admitted shots may hold together.
+    chunk: RK4 steps advanced between admission / retirement points.
+    """
+
+    def __init__(self, dtype='f32', order=4, device=0, hbm_budget=8 << 30, chunk=50, workers=2,
+                 spec_fn=default_spec):
+        import torch
+        self.torch = torch
+        self.dtype, self.order, self.device = dtype, order, device
+        self.budget, self.chunk, self.workers = hbm_budget, chunk, workers
+        self.spec_fn = spec_fn
+        self.stream = torch.cuda.Stream(device=device)       # batch launches
+        self.aux = torch.cuda.Stream(device=device)          # per-shot setup and read-back
+        self.batch = S.sbpe_batch_create(device, self.stream.cuda_stream, S.F64 if dtype == 'f64' else S.F32,
+                                         order)
+
+    def close(self):
+        if self.batch is not None:
+            S.sbpe_batch_destroy(self.batch)
+            self.batch = None
+
+    def run(self, requests, keep_receivers=True, log=None):
+        """Serve the requests (arrival times in seconds from the start of the
+        call); returns per-shot records and summary statistics."""
+        reqs = sorted(requests, key=lambda r: r['arrival'])
+        lock = threading.Lock()
+        used = [0]
+        todo = queue.Queue()          # arrived requests, in arrival order
+        ready = queue.Queue()         # set-up shots waiting to join the batch
+        retired = queue.Queue()       # shots that left the batch
+        done, failed = [], []
+        start = time.perf_counter()
+        now = lambda: time.perf_counter() - start
+
+        def setup_worker():
+            while True:
+                req = todo.get()
+                if req is None:
+                    return
+                need = shot_bytes(req['n'], req['nrec'], req['steps'], self.dtype)
+                while True:           # wait for HBM budget
+                    with lock:
+                        if used[0] + need <= self.budget or used[0] == 0:
+                            used[0] += need
+                            break
+                    time.sleep(0.002)
+                try:
+                    req['t_setup'] = now()
+                    shot = Shot(req, self.spec_fn(req), self.dtype, self.device, self.aux)
+                    shot.need = need
+                    ready.put(shot)
+                except Exception as e:     # reported, never silently dropped
+                    with lock:
+                        used[0] -= need
+                    failed.append((req['id'], repr(e)))
+                    ready.put(None)
+
+        def reaper():
+            # read back and free retired shots off the launch thread (freeing
+            # device memory may wait for the device)
+            while True:
+                s = retired.get()
+                if s is None:
+                    return
+                rec = s.receivers()       # ordered after the shot's last batched step
+                s.req['t_done'] = now()
+                s.req['latency'] = s.req['t_done'] - s.req['arrival']
+                if keep_receivers:
+                    s.req['receivers'] = rec
+                s.req['points'] = s.points
+                s.close()
+                del s.u, s.v
+                with lock:
+                    used[0] -= s.need
+                    done.append(s.req)
+                if log:
+                    log('shot %d (%d^2) done: latency %.3f s' % (s.req['id'], s.req['n'], s.req['latency']))
+
+        threads = [threading.Thread(target=setup_worker, daemon=True) for _ in range(self.workers)]
+        threads.append(threading.Thread(target=reaper, daemon=True))
+        for t in threads:
+            t.start()
+        pending = collections.deque(reqs)
+        members = {}
+        n_left = len(reqs)            # shots not yet handed to the reaper or failed
+        self.launched_points_steps = 0
+        while n_left > 0:
+            t = now()
+            while pending and pending[0]['arrival'] <= t:
+                todo.put(pending.popleft())
+            while True:               # admit everything that is set up
+                try:
+                    shot = ready.get_nowait()
+                except queue.Empty:
+                    break
+                if shot is None:
+                    n_left -= 1
+                    continue
+                S.sbpe_batch_add(self.batch, shot.ctx, shot.req['steps'], shot.dt)
+                shot.req['t_admit'] = now()
+                members[id(shot)] = shot
+            if not members:
+                wait = pending[0]['arrival'] - now() if pending else 0.0
+                time.sleep(min(max(wait, 0.0005), 0.02))
+                continue
+            info = S.sbpe_batch_info(self.batch)
+            k = min(self.chunk, info['min_remaining'])
+            S.sbpe_batch_advance(self.batch, k)
+            self.launched_points_steps += info['points'] * k
+            for s in [s for s in members.values() if S.sbpe_batch_remaining(self.batch, s.ctx) == 0]:
+                S.sbpe_batch_remove(self.batch, s.ctx)
+                del members[id(s)]
+                retired.put(s)
+                n_left -= 1
+        for _ in range(self.workers):
+            todo.put(None)
+        retired.put(None)
+        for t in threads:
+            t.join()
+        S.sbpe_batch_synchronize(self.batch)
+        wall = now()
+        lat = np.array([r['latency'] for r in done]) if done else np.zeros(1)
+        total_pts = sum(r['points'] * r['steps'] for r in done)
+        return dict(shots=done, failed=failed, wall_s=wall,
+                    p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    shots_per_s=len(done) / wall, updates_per_s=total_pts / wall)
+
+
+def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_receivers=True):
+    """The same shots, in arrival order, one at a time with sbpe_advance
+    (each starts when it has arrived and the previous one has finished)."""
+    import torch
+    stream = torch.cuda.Stream(device=device)
+    reqs = [dict(r) for r in sorted(requests, key=lambda r: r['arrival'])]
+    start = time.perf_counter()
+    now = lambda: time.perf_counter() - start
+    for r in reqs:
+        wait = r['arrival'] - now()
+        if wait > 0:
+            time.sleep(wait)
+        shot = Shot(r, spec_fn(r), dtype, device, stream)
+        S.sbpe_advance(shot.ctx, r['steps'], shot.dt)
+        rec = shot.receivers()
+        r['t_done'] = now()
+        r['latency'] = r['t_done'] - r['arrival']
+        r['points'] = shot.points
+        if keep_receivers:
+            r['receivers'] = rec
+        shot.close()
+    wall = now()
+    lat = np.array([r['latency'] for r in reqs])
+    total_pts = sum(r['points'] * r['steps'] for r in reqs)
+    return dict(shots=reqs, wall_s=wall, p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                shots_per_s=len(reqs) / wall, updates_per_s=total_pts / wall)

@@ -123,26 +123,51 @@ def voigt_to_c10(V):
 
 
 def smooth_random_material(X1, X2, seed, rho_mean=1.0, voigt_mean=VOIGT_C1,
-                           nmodes=8, kmax=4, rel_amp=0.3, min_eig=0.2):
+                           nmodes=8, kmax=4, rel_amp=0.3, min_eig=0.2, device=None):
+    """device (a torch device, e.g. 'cuda') evaluates the Fourier sums with
+    torch there: same draws and formula, different rounding of cos."""
     rng = np.random.default_rng(seed)
     fields = []
+    if device is not None:
+        import torch
+        tX1 = torch.as_tensor(np.ascontiguousarray(X1), device=device)
+        tX2 = torch.as_tensor(np.ascontiguousarray(X2), device=device)
+        tt = torch.empty_like(tX1)
     for mean in (rho_mean,) + tuple(voigt_mean):
         kx = rng.integers(-kmax, kmax + 1, nmodes)
         ky = rng.integers(-kmax, kmax + 1, nmodes)
         ph = rng.uniform(0.0, 2.0 * np.pi, nmodes)
         a = rng.uniform(-1.0, 1.0, nmodes)
-        s = np.zeros_like(X1)
-        for m in range(nmodes):
-            s += a[m] * np.cos(2.0 * np.pi * (kx[m] * X1 + ky[m] * X2) + ph[m])
+        if device is not None:
+            ts = torch.zeros_like(tX1)
+            for m in range(nmodes):
+                torch.mul(tX1, 2.0 * np.pi * float(kx[m]), out=tt)
+                tt.add_(tX2, alpha=2.0 * np.pi * float(ky[m])).add_(float(ph[m])).cos_()
+                ts.add_(tt, alpha=float(a[m]))
+            s = ts.cpu().numpy()
+        else:
+            s = np.zeros_like(X1)
+            for m in range(nmodes):
+                s += a[m] * np.cos(2.0 * np.pi * (kx[m] * X1 + ky[m] * X2) + ph[m])
         fields.append(mean * (1.0 + rel_amp * s / nmodes))
     rho = np.maximum(fields[0], min_eig)
-    c11, c12, c16, c22, c26, c66 = fields[1:]
-    M = np.stack([np.stack([c11, c12, c16], -1), np.stack([c12, c22, c26], -1),
-                  np.stack([c16, c26, c66], -1)], -2)
-    lam, Q = np.linalg.eigh(M)
-    lam = np.maximum(lam, min_eig)
-    M = np.einsum('...ik,...k,...jk->...ij', Q, lam, Q)
-    V = np.stack([M[..., 0, 0], M[..., 0, 1], M[..., 0, 2], M[..., 1, 1], M[..., 1, 2], M[..., 2, 2]])
+    V = np.stack(fields[1:])
+    # eigen-clip the Voigt matrix where M - min_eig I is not positive definite
+    # (leading principal minors), leaving every other point unchanged
+    c11, c12, c16, c22, c26, c66 = V - min_eig * np.array([1, 0, 0, 1, 0, 1.0]).reshape(6, *([1] * X1.ndim))
+    d1 = c11
+    d2 = c11 * c22 - c12 * c12
+    d3 = c11 * (c22 * c66 - c26 * c26) - c12 * (c12 * c66 - c26 * c16) + c16 * (c12 * c26 - c22 * c16)
+    bad = ~((d1 > 0) & (d2 > 0) & (d3 > 0))
+    if bad.any():
+        Vb = V[:, bad]
+        b11, b12, b16, b22, b26, b66 = Vb
+        M = np.stack([np.stack([b11, b12, b16], -1), np.stack([b12, b22, b26], -1),
+                      np.stack([b16, b26, b66], -1)], -2)
+        lam, Q = np.linalg.eigh(M)
+        lam = np.maximum(lam, min_eig)
+        M = np.einsum('...ik,...k,...jk->...ij', Q, lam, Q)
+        V[:, bad] = np.stack([M[..., 0, 0], M[..., 0, 1], M[..., 0, 2], M[..., 1, 1], M[..., 1, 2], M[..., 2, 2]])
     return np.ascontiguousarray(rho), np.ascontiguousarray(V)
 
 
@@ -283,12 +308,12 @@ def spec_c3(n=2049, seed=0, order=4, nrec=16):
                 receivers=recs, steps=1000, cfl=0.5)
 
 
-def spec_shot(n, seed, order=4, nrec=64):
+def spec_shot(n, seed, order=4, nrec=64, device=None):
     """One served shot: Gaussian-topography block of n^2 points, its own random
     material (seed), Ricker source at a random interior point, receivers on x2 = 1."""
     rng = np.random.default_rng(10_000 + seed)
     X1, X2 = grid(GaussianTopography(), n, n)
-    rho, V = smooth_random_material(X1, X2, seed)
+    rho, V = smooth_random_material(X1, X2, seed, device=device)
     bc = _free_faces()
     bc[2] = (DISPLACEMENT, None, T_ZERO, None, None)
     xs = rng.uniform(0.1, 0.9, 2)

@@ -1,0 +1,187 @@
+"""Continuous batching: a shot's result is the same alone and in a mix.
+
+Every block in a batched launch is evaluated with exactly the arithmetic of
+a single-context sbpe_advance, so the comparisons between batched and
+single-context runs are bitwise.  One case also checks a batched shot
+against the FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2003_12811_amd import sbpe as S
+from paper_2003_12811_amd import serve
+from paper_2003_12811_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _stream():
+    import torch
+    return torch.cuda.Stream()
+
+
+def _shot(n, seed, dtype, stream, steps=30, nrec=8):
+    req = dict(id=seed, arrival=0.0, n=n, seed=seed, steps=steps, nrec=nrec)
+    return serve.Shot(req, W.spec_shot(n, seed, nrec=nrec), dtype, 0, stream)
+
+
+def _state(shot):
+    import torch
+    torch.cuda.synchronize()
+    return shot.u.cpu().numpy().copy(), shot.v.cpu().numpy().copy()
+
+
+def _batch(dtype, stream):
+    return S.sbpe_batch_create(0, stream.cuda_stream, S.F64 if dtype == 'f64' else S.F32, 4)
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_batch_alone_equals_plain_advance(dtype):
+    say('batch alone vs sbpe_advance', dtype)
+    st = _stream()
+    a = _shot(45, 1, dtype, st)
+    b = _shot(45, 1, dtype, st)
+    S.sbpe_advance(a.ctx, 30, a.dt)
+    bt = _batch(dtype, st)
+    try:
+        S.sbpe_batch_add(bt, b.ctx, 30, b.dt)
+        S.sbpe_batch_advance(bt, 30)
+        assert S.sbpe_batch_remaining(bt, b.ctx) == 0
+        S.sbpe_batch_remove(bt, b.ctx)
+        ua, va = _state(a)
+        ub, vb = _state(b)
+        assert np.array_equal(ua, ub) and np.array_equal(va, vb)
+        assert np.array_equal(a.receivers(), b.receivers())
+        assert S.sbpe_get_time(a.ctx) == pytest.approx(S.sbpe_get_time(b.ctx), rel=1e-12)
+    finally:
+        S.sbpe_batch_destroy(bt)
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_batch_alone_equals_mix(dtype):
+    """Shot A runs 40 steps alone, then again while other shots of other sizes
+    and time steps join and leave around it."""
+    say('batch alone vs mix', dtype)
+    st = _stream()
+    steps = 40
+    a1 = _shot(61, 7, dtype, st, steps=steps)
+    bt = _batch(dtype, st)
+    try:
+        S.sbpe_batch_add(bt, a1.ctx, steps, a1.dt)
+        S.sbpe_batch_advance(bt, steps)
+        S.sbpe_batch_remove(bt, a1.ctx)
+        ref_u, ref_v = _state(a1)
+        ref_r = a1.receivers()
+        a1.close()
+
+        a2 = _shot(61, 7, dtype, st, steps=steps)
+        o1 = _shot(33, 8, dtype, st, steps=25)
+        o2 = _shot(97, 9, dtype, st, steps=60)
+        o3 = _shot(45, 10, dtype, st, steps=10)
+        S.sbpe_batch_add(bt, o1.ctx, 25, o1.dt)
+        S.sbpe_batch_advance(bt, 5)                 # o1 alone for 5 steps
+        S.sbpe_batch_add(bt, a2.ctx, steps, a2.dt)
+        S.sbpe_batch_add(bt, o2.ctx, 60, o2.dt)
+        S.sbpe_batch_advance(bt, 20)                # o1 finishes
+        S.sbpe_batch_remove(bt, o1.ctx)
+        S.sbpe_batch_add(bt, o3.ctx, 10, o3.dt)
+        S.sbpe_batch_advance(bt, 10)                # o3 done
+        S.sbpe_batch_remove(bt, o3.ctx)
+        info = S.sbpe_batch_info(bt)
+        assert info['members'] == 2 and info['min_remaining'] == 10
+        S.sbpe_batch_advance(bt, 10)                # a2 done
+        S.sbpe_batch_remove(bt, a2.ctx)
+        u, v = _state(a2)
+        assert np.array_equal(u, ref_u) and np.array_equal(v, ref_v)
+        assert np.array_equal(a2.receivers(), ref_r)
+        assert np.abs(ref_u).max() > 0
+        for s in (a2, o1, o2, o3):
+            s.close()
+    finally:
+        S.sbpe_batch_destroy(bt)
+
+
+def test_batch_member_rules():
+    st = _stream()
+    a = _shot(33, 2, 'f64', st)
+    bt = _batch('f64', st)
+    bt32 = _batch('f32', st)
+    try:
+        S.sbpe_batch_add(bt, a.ctx, 10, a.dt)
+        with pytest.raises(S.SbpeError):
+            S.sbpe_advance(a.ctx, 1, a.dt)           # owned by the batch
+        with pytest.raises(S.SbpeError):
+            S.sbpe_batch_add(bt, a.ctx, 10, a.dt)    # already a member
+        with pytest.raises(S.SbpeError):
+            S.sbpe_batch_advance(bt, 11)             # beyond its remaining steps
+        S.sbpe_batch_remove(bt, a.ctx)
+        with pytest.raises(S.SbpeError):
+            S.sbpe_batch_add(bt32, a.ctx, 10, a.dt)  # dtype differs
+    finally:
+        S.sbpe_batch_destroy(bt)
+        S.sbpe_batch_destroy(bt32)
+        a.close()
+
+
+def test_batched_shot_matches_oracle():
+    from oracle import timestep as T
+    from oracle.spec import build, receivers
+    say('batched shot vs oracle')
+    st = _stream()
+    n, steps = 33, 25
+    spec = W.spec_shot(n, 4, nrec=6)
+    req = dict(id=0, arrival=0.0, n=n, seed=4, steps=steps, nrec=6)
+    other = _shot(45, 5, 'f64', st, steps=steps)
+    shot = serve.Shot(req, spec, 'f64', 0, st)
+    bt = _batch('f64', st)
+    try:
+        S.sbpe_batch_add(bt, other.ctx, steps, other.dt)
+        S.sbpe_batch_add(bt, shot.ctx, steps, shot.dt)
+        S.sbpe_batch_advance(bt, steps)
+        S.sbpe_batch_remove(bt, shot.ctx)
+        got = shot.receivers()
+        P = build(spec)
+        u = [np.zeros((2, n, n))]
+        v = [np.zeros((2, n, n))]
+        t = 0.0
+        ref = []
+        for _ in range(steps):
+            u, v = T.rk4_step(P, u, v, t, shot.dt)
+            t += shot.dt
+            ref.append(receivers(spec, u))
+        ref = np.array(ref)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        say('  receivers rel err %.3e' % err)
+        assert err < 1e-11
+    finally:
+        S.sbpe_batch_destroy(bt)
+        shot.close()
+        other.close()
+
+
+def test_server_results_equal_standalone_runs():
+    """Small served stream: every shot's receivers equal its standalone run."""
+    say('server stream')
+    reqs = serve.make_requests(6, rate=200.0, sizes=[33, 49, 65], steps=30, seed=3, nrec=8)
+    spec_fn = lambda r: W.spec_shot(r['n'], r['seed'], nrec=r['nrec'])
+    srv = serve.Server(dtype='f32', hbm_budget=3 * serve.shot_bytes(65, 8, 30, 'f32'), chunk=7, workers=2,
+                       spec_fn=spec_fn)
+    try:
+        res = srv.run(reqs)
+    finally:
+        srv.close()
+    assert not res['failed'] and len(res['shots']) == 6
+    seq = serve.run_sequential([dict(r, arrival=0.0) for r in reqs], dtype='f32', spec_fn=spec_fn)
+    by_id = {r['id']: r for r in seq['shots']}
+    for r in res['shots']:
+        assert np.array_equal(r['receivers'], by_id[r['id']]['receivers']), r['id']
+        assert r['latency'] > 0
+    assert res['p99_s'] >= res['p50_s'] > 0

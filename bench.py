@@ -10,8 +10,10 @@ on the bottom face and traction SATs elsewhere, a 10 Hz Ricker point force and
 sources, receivers).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.  The primary result is
-FP64; the FP32 variant, the plain operator apply and a working set larger than
-the MALL (2x2 blocks of 2049^2, FP32) are reported beside it.
+FP64; the FP32 variant, the plain operator apply, a working set larger than
+the MALL (2x2 blocks of 2049^2, FP32) and a served stream of shots
+(continuous batching against sequential plain solves, p50/p99 latency) are
+reported beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -158,6 +160,9 @@ def main():
     ap.add_argument('--no-large', action='store_true')
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
+    ap.add_argument('--no-serve', action='store_true')
+    ap.add_argument('--serve-shots', type=int, default=32)
+    ap.add_argument('--serve-steps', type=int, default=300)
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='first run a plain device-to-device copy of this many MiB (calibrates '
                          'the HBM byte counters of a profiler)')
@@ -212,6 +217,10 @@ def main():
                          "roofline": roofline(k3, r3['kernels'][k3][0], r3['plan']['interior_points'], 4),
                          "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]}}
         log('  %.3f ms/step, %.3e updates/s' % (r3['ms_per_step'], r3['updates_per_s']))
+    if not args.no_serve:
+        from paper_2003_12811_amd import serve
+        log('served stream vs sequential plain solves')
+        line["serving"] = serve.serve_and_compare(args.serve_shots, 20.0, [257, 513, 1025], args.serve_steps)
     if not args.no_cpu_baseline:
         log('cpu baseline (oracle, 1 thread, %d steps)' % args.cpu_steps)
         line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)

@@ -226,7 +226,7 @@ class Server:
                     shots_per_s=len(done) / wall, updates_per_s=total_pts / wall)
 
 
-def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_receivers=True):
+def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_receivers=True, log=None):
     """The same shots, in arrival order, one at a time with sbpe_advance
     (each starts when it has arrived and the previous one has finished)."""
     import torch
@@ -247,8 +247,82 @@ def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_r
         if keep_receivers:
             r['receivers'] = rec
         shot.close()
+        if log and r['id'] % 16 == 0:
+            log('sequential: shot %d done at %.2f s' % (r['id'], r['t_done']))
     wall = now()
     lat = np.array([r['latency'] for r in reqs])
     total_pts = sum(r['points'] * r['steps'] for r in reqs)
     return dict(shots=reqs, wall_s=wall, p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 shots_per_s=len(reqs) / wall, updates_per_s=total_pts / wall)
+
+
+def summarize(res):
+    keys = ('wall_s', 'p50_s', 'p99_s', 'shots_per_s', 'updates_per_s')
+    return {k: res[k] for k in keys} | {'shots': len(res['shots'])}
+
+
+def main(argv=None):
+    """Serve a Poisson stream of shots and compare with sequential plain solves.
+
+      python -m paper_2003_12811_amd.serve [--shots 256] [--rate 20] [--sizes 257,513,1025,2049]
+          [--steps 1500] [--dtype f32] [--budget-gb 32] [--chunk 50] [--no-sequential]
+    Prints one JSON line.
+    """
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--shots', type=int, default=256)
+    ap.add_argument('--rate', type=float, default=20.0)
+    ap.add_argument('--sizes', default='257,513,1025,2049')
+    ap.add_argument('--steps', type=int, default=1500)
+    ap.add_argument('--nrec', type=int, default=64)
+    ap.add_argument('--dtype', default='f32')
+    ap.add_argument('--budget-gb', type=float, default=32.0)
+    ap.add_argument('--chunk', type=int, default=50)
+    ap.add_argument('--workers', type=int, default=4)
+    ap.add_argument('--seed', type=int, default=0)
+    ap.add_argument('--no-sequential', action='store_true')
+    args = ap.parse_args(argv)
+    out = serve_and_compare(args.shots, args.rate, [int(x) for x in args.sizes.split(',')], args.steps,
+                            args.nrec, args.dtype, args.budget_gb, args.chunk, args.workers, args.seed,
+                            not args.no_sequential)
+    print(json.dumps(out), flush=True)
+
+
+def serve_and_compare(shots, rate, sizes, steps, nrec=64, dtype='f32', budget_gb=32.0, chunk=50, workers=2,
+                      seed=0, sequential=True):
+    """Served run of a Poisson stream, then (optionally) the same shots as
+    sequential plain solves; returns the summary dictionary."""
+    import json
+    import sys
+    from types import SimpleNamespace
+    args = SimpleNamespace(shots=shots, rate=rate, steps=steps, nrec=nrec, dtype=dtype, budget_gb=budget_gb,
+                           chunk=chunk, workers=workers, seed=seed, no_sequential=not sequential)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    reqs = make_requests(args.shots, args.rate, sizes, args.steps, seed=args.seed, nrec=args.nrec)
+    srv = Server(dtype=args.dtype, hbm_budget=int(args.budget_gb * (1 << 30)), chunk=args.chunk,
+                 workers=args.workers)
+    try:
+        log('served: %d shots, sizes %s, %d steps, %.1f/s' % (args.shots, sizes, args.steps, args.rate))
+        res = srv.run([dict(r) for r in reqs], log=log if shots > 64 else None)
+    finally:
+        srv.close()
+    out = dict(workload='Poisson stream (%.1f/s, seed %d) of %d shots, n^2 with n uniform in %s, %d RK4 steps, '
+                        '%d receivers, %s' % (args.rate, args.seed, args.shots, sizes, args.steps, args.nrec,
+                                              args.dtype),
+               served=summarize(res), failed=res['failed'])
+    log('  served:', json.dumps(out['served']))
+    if not args.no_sequential:
+        log('sequential plain solves')
+        seq = run_sequential([dict(r) for r in reqs], dtype=args.dtype, log=log if shots > 64 else None)
+        out['sequential'] = summarize(seq)
+        log('  sequential:', json.dumps(out['sequential']))
+        by_id = {r['id']: r['receivers'] for r in seq['shots']}
+        out['bitwise_equal_to_sequential'] = all(np.array_equal(r['receivers'], by_id[r['id']])
+                                                 for r in res['shots'])
+        out['throughput_ratio'] = res['updates_per_s'] / seq['updates_per_s']
+    return out
+
+
+if __name__ == '__main__':
+    main()

@@ -26,6 +26,7 @@
 // D2^FC and D1 sums to zero), which keeps FP32 cancellation small.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "sbpe_internal.h"
@@ -790,19 +791,29 @@ struct Lead {
     T b1[3];   // x1-narrow coefficients at (i, j)
 };
 
-template <typename T, int ORD, int PASS>
-__global__ void __launch_bounds__(64) k_march(PassArgs A) {
+// SPLIT (RK sweeps): a workgroup of two waves shares the tile; wave w applies
+// L to field w only, which halves the registers of a wave, and the two meet
+// in LDS for the pass arithmetic (RK1: wave w writes a_{w+1}; RK2: wave q
+// writes component q of u and v).
+template <typename T, int ORD, int PASS, bool SPLIT>
+__global__ void __launch_bounds__(SPLIT ? 128 : 64) k_march(PassArgs A) {
     using O = Op<ORD>;
     constexpr int HF = O::HALF;
     constexpr int NW = 2 * HF + 1;
-    constexpr int NF = PASS == PASS_APPLY ? 1 : 2;
+    constexpr int NF = (PASS == PASS_APPLY || SPLIT) ? 1 : 2;
     constexpr int NS = 2 * NF;
+    constexpr int NWAVE = SPLIT ? 2 : 1;
     constexpr int R = Frame<ORD>::R;
     constexpr T C1 = static_cast<T>(O::d1i(HF + 1));
     constexpr T C2 = static_cast<T>(d1_outer<ORD>());
-    __shared__ T s_x[NW][NS][64];
-    __shared__ T s_b[3][64];
-    __shared__ T s_g[NS][64];
+    __shared__ T s_xw[NWAVE][NW][NS][64];
+    __shared__ T s_bw[NWAVE][3][64];
+    __shared__ T s_gw[NWAVE][NS][64];
+    __shared__ T s_l[SPLIT ? 2 : 1][4][64];   // exchange: L (2 components) and centre values of each field
+    const int wv = SPLIT ? (int)(threadIdx.x >> 6) : 0;
+    T(&s_x)[NW][NS][64] = s_xw[wv];
+    T(&s_b)[3][64] = s_bw[wv];
+    T(&s_g)[NS][64] = s_gw[wv];
 
     // workgroup order: consecutive tiles on the same XCD (ids are dealt round-robin to 8 XCDs)
     const int total = A.total_tiles;
@@ -815,7 +826,7 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
     const long np = (long)n1 * n2;
     const int tl = wg - B.tile_beg;
     const int ty = tl / B.tiles_x, tx = tl - ty * B.tiles_x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int i = R - HF + tx * (64 - 2 * HF) + lane;
     const bool act = lane >= HF && lane < 64 - HF && i <= n1 - 1 - R;
     const int ic = i < n1 - 1 ? i : n1 - 1;
@@ -833,6 +844,7 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
     {
         const void* f0p = PASS == PASS_APPLY ? apply_in(A, b) : (PASS == PASS_RK1 ? B.u : B.a1);
         const void* f1p = PASS == PASS_RK1 ? B.v : B.a2;
+        if (SPLIT && wv == 1) f0p = f1p;
 #pragma unroll
         for (int s = 0; s < NS; ++s) fin[s] = (const char*)(s < 2 ? f0p : f1p) + (s & 1) * (size_t)fb;
     }
@@ -944,7 +956,10 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
         const T f0 = ldo<T>(frc, p);
         const T f1 = ldo<T>(frc + frc1, p);
         T xo[4];
-        if constexpr (PASS == PASS_RK2) {
+        if constexpr (PASS == PASS_RK2 && SPLIT) {
+            xo[0] = ldo<T>((const char*)B.u + wv * fb, p);
+            xo[2] = ldo<T>((const char*)B.v + wv * fb, p);
+        } else if constexpr (PASS == PASS_RK2) {
             xo[0] = ldo<T>((const char*)B.u, p);
             xo[1] = ldo<T>((const char*)B.u + fb, p);
             xo[2] = ldo<T>((const char*)B.v, p);
@@ -1035,7 +1050,50 @@ __global__ void __launch_bounds__(64) k_march(PassArgs A) {
             L[x >> 1][x & 1] = lx[x >> 1][x & 1] + (ag + ae) * i12;
         }
         // (6) data, pass arithmetic, stores
-        if (act && live) {
+        if constexpr (SPLIT) {
+            // exchange L and the centre values of both fields
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                s_l[wv][q][lane] = L[0][q];
+                s_l[wv][2 + q][lane] = wc[q];
+            }
+            __syncthreads();
+            if (act && live) {
+                const long po = (long)j * n1 + i;
+                if constexpr (PASS == PASS_RK1) {
+                    // wave 0: a1 = irho (L u + d(t)); wave 1: a2 = irho (L u + dt/2 L v + d(t + dt/2))
+                    const W3 cw{wv ? cb.w0 : ca.w0, wv ? cb.w1 : ca.w1, wv ? cb.w2 : ca.w2};
+                    const T tf = wv ? tauf_b : tauf_a;
+                    T d0 = tf * f0, d1v = tf * f1;
+                    if (rg.end > rg.beg && cw.any()) point_sources<T>(B, A, rg, po, cw, d0, d1v);
+                    const T hdt = wv ? T(0.5) * dt : T(0);
+                    char* o = (char*)(wv ? B.a2 : B.a1);
+                    sto<T>(o, p, irho * (s_l[0][0][lane] + hdt * L[0][0] + d0));
+                    sto<T>(o + fb, p, irho * (s_l[0][1][lane] + hdt * L[0][1] + d1v));
+                } else {
+                    // component q = wv of the RK4 update
+                    const int q = wv;
+                    T db0 = tauf_b * f0, db1 = tauf_b * f1;
+                    if (rg.end > rg.beg && cb.any()) point_sources<T>(B, A, rg, po, cb, db0, db1);
+                    const T dt2 = dt * dt;
+                    const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
+                    const T A1 = s_l[0][2 + q][lane];
+                    const T A2 = s_l[1][2 + q][lane];
+                    const T A3 = A2 + q4 * irho * s_l[0][q][lane];
+                    const T A4 = T(2) * A2 - A1 + q2 * irho * (s_l[1][q][lane] + (q ? db1 : db0));
+                    const T un = xo[0] + dt * xo[2] + s6 * (A1 + A2 + A3);
+                    sto<T>((char*)B.u + q * fb, p, un);
+                    sto<T>((char*)B.v + q * fb, p, xo[2] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4));
+                    gp<double> ro = rec_slots(B, A);
+                    if (ro && rg.end > rg.beg) {
+                        for (int e = rg.beg; e < rg.end; ++e) {
+                            const GLB Entry& E = entry(B, e);
+                            if (E.kind == 1 && E.p == po) ro[2 * E.id + q] = E.c0 * static_cast<double>(un);
+                        }
+                    }
+                }
+            }
+        } else if (act && live) {
             const long po = (long)j * n1 + i;
             T da0 = tauf_a * f0, da1 = tauf_a * f1, db0 = tauf_b * f0, db1 = tauf_b * f1;
             if (rg.end > rg.beg) {
@@ -1168,10 +1226,19 @@ __global__ void __launch_bounds__(256) k_energy_final(const double* partial, int
 // ---------------------------------------------------------- launchers
 template <typename T, int ORD>
 static void launch_march_t(const PassArgs& a, int total_tiles, hipStream_t s) {
-    const dim3 g(((total_tiles + 7) / 8) * 8), bl(64);
-    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_march<T, ORD, PASS_APPLY>), g, bl, 0, s, a);
-    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK1>), g, bl, 0, s, a);
-    else hipLaunchKernelGGL((k_march<T, ORD, PASS_RK2>), g, bl, 0, s, a);
+    const dim3 g(((total_tiles + 7) / 8) * 8), bl(64), bl2(128);
+    // two waves per tile when there are few tiles (the single-wave kernel
+    // needs more registers and fills fewer slots); SBPE_SPLIT=0/1 overrides
+    static const int split_env = [] {
+        const char* e = std::getenv("SBPE_SPLIT");
+        return e ? std::atoi(e) : -1;
+    }();
+    const bool split = split_env >= 0 ? split_env != 0 : total_tiles < 4096;
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_march<T, ORD, PASS_APPLY, false>), g, bl, 0, s, a);
+    else if (a.pass == PASS_RK1 && split) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK1, true>), g, bl2, 0, s, a);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK1, false>), g, bl, 0, s, a);
+    else if (split) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK2, true>), g, bl2, 0, s, a);
+    else hipLaunchKernelGGL((k_march<T, ORD, PASS_RK2, false>), g, bl, 0, s, a);
 }
 
 int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream) {

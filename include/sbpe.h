@@ -185,6 +185,44 @@ sbpe_status sbpe_get_kernel_timing(sbpe_ctx_t ctx, double* ms_avg, int* count);
  * workgroups, info[4] = frame width in points. */
 sbpe_status sbpe_plan_info(sbpe_ctx_t ctx, long long* info);
 
+/* ---------------------------------------------------------------- gradients
+ * Building blocks of the discrete adjoint of a receiver misfit with respect
+ * to rho and C.  H L is symmetric (the energy analysis of Sec. 5 and 6), so
+ * with the adjoint variables scaled as zhat = z / (H rho~) the adjoint state
+ * is advanced with the forward operator itself (sbpe_apply, homogeneous).
+ * Blocks with interface faces are not supported (SBPE_EINVAL). */
+
+/* For every block b, accumulate the gradient of one RK4 stage:
+ *   gc[b]  += alpha * d/dc (z^T H L(c) y)   (10 stored transformed-stiffness
+ *             fields, FP64 device [10][n2][n1], order c1111, c1112, c1212,
+ *             c2121, c2122, c2222, c1121, c1122, c1221, c1222; Sec. 4.7, 5),
+ *   grt[b] += -alpha * H * (z . a)          (FP64 device [n2][n1], gradient
+ *             with respect to rho~ = J rho).
+ * z, y, a are device fields of the context dtype, [2][n2][n1]: the scaled
+ * stage adjoint, the stage displacement and the stage value
+ * a = rho~^{-1} (L y + data(t)).  Unless homogeneous, displacement data at
+ * time t enter delta = y - g(t).  H holds the quadrature weights
+ * h1 h2 H1_i H2_j.  Enqueued on the context stream. */
+sbpe_status sbpe_grad_accumulate(sbpe_ctx_t ctx, const void* const* z, const void* const* y, const void* const* a,
+                                 double alpha, double t, int homogeneous, void* const* gc, void* const* grt);
+
+/* Chain rule of one block to the physical parameters, c = F J C F and
+ * rho~ = J rho (Sec. 3.2.1): gc, grt device arrays as above; g_c10 host
+ * [10][n2][n1] in the C10 order of sbpe_add_block (C treated as major
+ * symmetric), g_rho host [n2][n1].  Synchronises. */
+sbpe_status sbpe_grad_to_physical(sbpe_ctx_t ctx, int block, const void* gc, const void* grt, double* g_c10,
+                                  double* g_rho);
+
+/* y = sum_k coefs[k] x[k] elementwise over count values of the context dtype
+ * (device pointers, 1 <= nterms <= 4, y may be one of the x[k]). */
+sbpe_status sbpe_lincomb(sbpe_ctx_t ctx, int nterms, const double* coefs, const void* const* x, void* y,
+                         long long count);
+
+/* u[b] += scale * (H rho~)^{-1} S^T r, the adjoint of the receiver sampling
+ * (Sec. 7.3) in the scaled variables: r is FP64 device [nrec][2] in the order
+ * of sbpe_add_receivers, u the device displacement fields of every block. */
+sbpe_status sbpe_receiver_adjoint(sbpe_ctx_t ctx, const void* r, void* const* u, double scale);
+
 /* ------------------------------------------------------------------ batches
  * Continuous batching of independent solves (many contexts, e.g. one shot
  * each).  A batch advances the bound states of its members with one kernel

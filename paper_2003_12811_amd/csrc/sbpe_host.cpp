@@ -111,6 +111,7 @@ struct HostBlock {
     // computed at finalize
     std::vector<double> coef;   // [NCOEF][np]
     std::vector<double> J;
+    std::vector<double> Fm;     // F[I][i] = dx_i/dX_I per point, [4][np] (gradients)
     std::vector<double> c10t;   // transformed stiffness, C10 layout
     // device memory owned by the context
     void* d_coef = nullptr;
@@ -160,6 +161,8 @@ struct sbpe_ctx {
     Range* d_tile_ranges = nullptr;
     Range* d_frame_ranges = nullptr;
     TimeFn* d_items = nullptr;      // time functions of the data items (k_tau)
+    RecAdj* d_recadj = nullptr;     // receiver interpolation points for sbpe_receiver_adjoint
+    int nrecadj = 0;
     int nitems = 0;
     double* d_tau = nullptr;        // tabulated time functions [steps][nitems][3]
     long tau_cap = 0;               // steps of capacity
@@ -283,6 +286,7 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
         d1_apply(o, n2, B.h2, &B.X2[i], n1, &A11[i], n1);
     }
     B.J.assign(np, 0.0);
+    B.Fm.assign((size_t)4 * np, 0.0);
     B.coef.assign((size_t)NCOEF * np, 0.0);
     B.c10t.assign((size_t)10 * np, 0.0);
     long bad_j = -1, bad_c = -1;
@@ -297,6 +301,7 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
         B.J[p] = J;
         // F[I][i] = dx_i / dX_I
         const double F[2][2] = {{A11[p] / J, -A01[p] / J}, {-A10[p] / J, A00[p] / J}};
+        for (int q = 0; q < 4; ++q) B.Fm[(size_t)q * np + p] = F[q >> 1][q & 1];
         double Cm[16];
         c10_to_mat(B.C10.data(), np, p, Cm);
         double lmin, lmax;
@@ -574,6 +579,24 @@ static sbpe_status build_plan(sbpe_ctx* c) {
                 add_point(Rv.block, i0 + d, j0 + a, e);
             }
     }
+    // receiver interpolation points with weight / (H rho~) (adjoint of the sampling)
+    std::vector<RecAdj> radj;
+    for (size_t r = 0; r < c->receivers.size(); ++r) {
+        const Receiver& Rv = c->receivers[r];
+        const HostBlock& H = c->blocks[Rv.block];
+        int i0, j0;
+        double wi[4], wj[4];
+        weights_1d(Rv.x1, H.n1, i0, wi);
+        weights_1d(Rv.x2, H.n2, j0, wj);
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 4; ++d) {
+                const int i = i0 + d, j = j0 + a;
+                const long p = (long)j * H.n1 + i;
+                const double Hp = H.h1 * H.h2 * norm_weight(c->order, H.n1, i) * norm_weight(c->order, H.n2, j);
+                const double rt = H.J[p] * H.rho[p];
+                radj.push_back(RecAdj{(int)r, Rv.block, p, wi[d] * wj[a] / (Hp * rt)});
+            }
+    }
     std::stable_sort(ents.begin(), ents.end(), [](const E2& x, const E2& y) {
         return x.frame != y.frame ? x.frame < y.frame : x.wg < y.wg;
     });
@@ -589,6 +612,11 @@ static sbpe_status build_plan(sbpe_ctx* c) {
     if (c->host_only) return SBPE_OK;
     if (flat.empty()) flat.push_back(Entry{-1, -1, 0, 0, 0.0, 0.0});
     c->nitems = (int)items.size();
+    c->nrecadj = (int)radj.size();
+    if (!radj.empty()) {
+        HIPCHECK(c, hipMalloc(&c->d_recadj, radj.size() * sizeof(RecAdj)));
+        HIPCHECK(c, hipMemcpy(c->d_recadj, radj.data(), radj.size() * sizeof(RecAdj), hipMemcpyHostToDevice));
+    }
     HIPCHECK(c, hipMalloc(&c->d_entries, flat.size() * sizeof(Entry)));
     HIPCHECK(c, hipMemcpy(c->d_entries, flat.data(), flat.size() * sizeof(Entry), hipMemcpyHostToDevice));
     HIPCHECK(c, hipMalloc(&c->d_tile_ranges, tr.size() * sizeof(Range)));
@@ -813,6 +841,7 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
         (void)hipFree(c->d_tile_ranges);
         (void)hipFree(c->d_frame_ranges);
         (void)hipFree(c->d_items);
+        (void)hipFree(c->d_recadj);
         (void)hipFree(c->d_tau);
         (void)hipFree(c->d_rec);
         (void)hipFree(c->d_epart);
@@ -1606,5 +1635,122 @@ extern "C" sbpe_status sbpe_batch_synchronize(sbpe_batch_t b) {
     if (!b) return bfail(nullptr, SBPE_EINVAL, "NULL batch");
     BHIPCHECK(b, hipStreamSynchronize(b->side));
     BHIPCHECK(b, hipStreamSynchronize(b->stream));
+    return SBPE_OK;
+}
+
+// -------------------------------------------------------------- gradients
+extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, const void* const* y,
+                                            const void* const* a, double alpha, double t, int homogeneous,
+                                            void* const* gc, void* const* grt) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    const int nb = (int)c->blocks.size();
+    if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "at most 16 blocks");
+    if (!z || !y || !a || !gc || !grt) return fail(c, SBPE_EINVAL, "NULL pointer array");
+    for (int b = 0; b < nb; ++b) {
+        if (!z[b] || !y[b] || !a[b] || !gc[b] || !grt[b]) return fail(c, SBPE_EINVAL, "NULL block pointer");
+        for (int f = 0; f < 4; ++f)
+            if (c->blocks[b].face[f].kind == BC_INTERFACE)
+                return fail(c, SBPE_EINVAL, "coefficient gradients across interfaces are not supported");
+    }
+    if (!homogeneous) {
+        s = fill_tau(c, 1, t, 0.0);
+        if (s) return s;
+    }
+    GradArgs g;
+    std::memset(&g, 0, sizeof g);
+    g.blocks = c->d_desc;
+    g.nblocks = nb;
+    g.homogeneous = homogeneous ? 1 : 0;
+    g.alpha = alpha;
+    g.tau = c->d_tau;
+    long off = 0;
+    for (int b = 0; b < nb; ++b) {
+        g.off[b] = off;
+        off += c->blocks[b].np();
+        g.z[b] = z[b];
+        g.y[b] = y[b];
+        g.a[b] = a[b];
+        g.gc[b] = static_cast<double*>(gc[b]);
+        g.grt[b] = static_cast<double*>(grt[b]);
+    }
+    g.off[nb] = off;
+    const int e = launch_grad(c->dtype, c->order, g, c->stream);
+    if (e != 0) return fail(c, SBPE_EHIP, std::string("gradient launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+extern "C" sbpe_status sbpe_grad_to_physical(sbpe_ctx_t c, int block, const void* gc, const void* grt,
+                                             double* g_c10, double* g_rho) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (block < 0 || block >= (int)c->blocks.size()) return fail(c, SBPE_EINVAL, "no such block");
+    if (!gc || !grt || !g_c10 || !g_rho) return fail(c, SBPE_EINVAL, "NULL pointer");
+    const HostBlock& B = c->blocks[block];
+    const long np = B.np();
+    std::vector<double> hg((size_t)10 * np), hr(np);
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipMemcpy(hg.data(), gc, hg.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(hr.data(), grt, hr.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // stored coefficient k = c_{ijkl} with these representative indices
+    static const int REP[10][4] = {{0, 0, 0, 0}, {0, 0, 0, 1}, {0, 1, 0, 1}, {1, 0, 1, 0}, {1, 0, 1, 1},
+                                   {1, 1, 1, 1}, {0, 0, 1, 0}, {0, 0, 1, 1}, {0, 1, 1, 0}, {0, 1, 1, 1}};
+    int m_of[4][4];
+    for (int m = 0; m < 10; ++m) {
+        m_of[C10P[m][0]][C10P[m][1]] = m;
+        m_of[C10P[m][1]][C10P[m][0]] = m;
+    }
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < np; ++p) {
+        double out[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const double J = B.J[p];
+        double F[2][2];
+        for (int q = 0; q < 4; ++q) F[q >> 1][q & 1] = B.Fm[(size_t)q * np + p];
+        // c_ijkl = J F_Ii C_IjKl F_Kk: d c_ijkl / d C_(Ij)(Kl) = J F_Ii F_Kk
+        for (int k = 0; k < 10; ++k) {
+            const double gk = hg[(size_t)k * np + p];
+            const int i = REP[k][0], j = REP[k][1], kk = REP[k][2], l = REP[k][3];
+            for (int I = 0; I < 2; ++I)
+                for (int K = 0; K < 2; ++K) out[m_of[2 * I + j][2 * K + l]] += gk * J * F[I][i] * F[K][kk];
+        }
+        for (int m = 0; m < 10; ++m) g_c10[(size_t)m * np + p] = out[m];
+        g_rho[p] = J * hr[p];     // rho~ = J rho
+    }
+    return SBPE_OK;
+}
+
+extern "C" sbpe_status sbpe_lincomb(sbpe_ctx_t c, int nterms, const double* coefs, const void* const* x, void* y,
+                                    long long count) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (nterms < 1 || nterms > 4 || !coefs || !x || !y || count < 0) return fail(c, SBPE_EINVAL, "bad arguments");
+    for (int k = 0; k < nterms; ++k)
+        if (!x[k]) return fail(c, SBPE_EINVAL, "NULL input");
+    const int e = launch_lincomb(c->dtype, nterms, coefs, x, y, (long)count, c->stream);
+    if (e != 0) return fail(c, SBPE_EHIP, std::string("lincomb launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+extern "C" sbpe_status sbpe_receiver_adjoint(sbpe_ctx_t c, const void* r, void* const* u, double scale) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    const int nb = (int)c->blocks.size();
+    if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "at most 16 blocks");
+    if (!r || !u) return fail(c, SBPE_EINVAL, "NULL pointer");
+    RecAdjArgs a;
+    std::memset(&a, 0, sizeof a);
+    for (int b = 0; b < nb; ++b) {
+        if (!u[b]) return fail(c, SBPE_EINVAL, "NULL block pointer");
+        a.u[b] = u[b];
+        a.np[b] = c->blocks[b].np();
+    }
+    a.scale = scale;
+    const int e = launch_rec_adjoint(c->dtype, c->d_recadj, c->nrecadj, static_cast<const double*>(r), a, c->stream);
+    if (e != 0) return fail(c, SBPE_EHIP, std::string("receiver adjoint launch: ") + hip_error_string(e));
     return SBPE_OK;
 }

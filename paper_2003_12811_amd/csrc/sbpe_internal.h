@@ -127,12 +127,44 @@ constexpr int TILE_Y_DEFAULT = 10;
 constexpr int FRAME_WG = 256;
 constexpr int FRAME_PTS = 32;   // frame points per workgroup: four waves, two lanes per point in each
 
+// Coefficient gradient of one RK4 stage (sbpe_grad_accumulate): for every block,
+// gc[b][k] += alpha d/dc_k (z^T H L(c) y) and grt[b] += -alpha H (z . a).
+struct GradArgs {
+    const BlockDesc* blocks;
+    int nblocks;
+    int homogeneous;      // displacement data left out of delta = y - g(t)
+    long off[MAX_APPLY_BLOCKS + 1];   // first flat point of each block in the launch
+    double alpha;
+    const double* tau;    // tabulated time functions at t (row 0)
+    const void* z[MAX_APPLY_BLOCKS];
+    const void* y[MAX_APPLY_BLOCKS];
+    const void* a[MAX_APPLY_BLOCKS];
+    double* gc[MAX_APPLY_BLOCKS];     // [10][n2][n1], the stored coefficient order K_C1111 .. K_C1222
+    double* grt[MAX_APPLY_BLOCKS];    // [n2][n1], gradient with respect to rho~ = J rho
+};
+
 // host-side launchers (sbpe_kernels.hip)
 int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream);
 int launch_frame(int dtype, int order, const PassArgs& a, int total_frame_wg, void* stream);
 int launch_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt, double* tau, void* stream);
 int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
                   int npartial, double* result_dev, void* stream);
+int launch_grad(int dtype, int order, const GradArgs& g, void* stream);
+int launch_lincomb(int dtype, int nterms, const double* coefs, const void* const* x, void* y, long count,
+                   void* stream);
+// one interpolation point of one receiver: u[block][c][p] += scale * w * r[rec][c]
+struct RecAdj {
+    int rec;
+    int block;
+    long p;
+    double w;       // interpolation weight / (H_p rho~_p)
+};
+struct RecAdjArgs {
+    void* u[MAX_APPLY_BLOCKS];
+    long np[MAX_APPLY_BLOCKS];
+    double scale;
+};
+int launch_rec_adjoint(int dtype, const RecAdj* ent, int nent, const double* r, const RecAdjArgs& a, void* stream);
 const char* hip_error_string(int code);
 
 }  // namespace sbpe

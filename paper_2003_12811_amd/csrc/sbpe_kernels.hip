@@ -78,6 +78,18 @@ __host__ __device__ constexpr double d1_outer() {
     else return 0.0;
 }
 
+// closure table entries with runtime indices
+template <int ORD>
+__device__ __forceinline__ double table_d2c(int r, int m, int s) {
+    if constexpr (ORD == 4) return D2T4.t[r][m][s];
+    else return D2T2.t[r][m][s];
+}
+template <int ORD>
+__device__ __forceinline__ double table_d1b(int r, int c) {
+    if constexpr (ORD == 4) return O4_D1B[r][c];
+    else return O2_D1B[r][c];
+}
+
 // dimensionless norm weight of point k on a line of n points
 template <int ORD>
 __device__ __forceinline__ double hnorm(int k, int n) {
@@ -1176,6 +1188,301 @@ __global__ void __launch_bounds__(256) k_tau(const TimeFn* items, int nitems, in
     o[2] = tfun(f, t + dt);
 }
 
+// ------------------------------------------------------------ gradients
+// Coefficient gradient of the bilinear form B(c) = z^T H L(c) y of one block
+// (H = h1 h2 H^1 (x) H^2, L the reference-frame operator of the kernels
+// above), accumulated per point.  Each thread owns one grid point and gathers
+// every term in which the coefficients of that point appear:
+//   * narrow terms: h^2 (D2^FC(b) y)_r = sum_m k_rm(b) (y_m - y_r) with k_rm
+//     linear in b (interior edge weights, closure tables), so
+//     dB/db_p = sum_r H_r z_r sum_m dk_rm/db_p (y_m - y_r) / h^2;
+//   * mixed terms D_1 (M D_2 y) and D_2 (M^T D_1 y): dB/dM_ab(p) =
+//     (D_1^T H z_a)(p) (D_2 y_b)(p) + (D_2^T H z_b)(p) (D_1 y_a)(p);
+//   * traction SAT -(1/w) nu c_ajkl D_k y_l at the face points, and the
+//     displacement SAT (normal part on the REACH points next to the face,
+//     tangential part (D_t z)^T H_t q and penalty at the face points);
+//   * rho~ (1/rho~ scales every stage): dB/drho~ = -H (z . a), a the stage value.
+
+// weight of b_{r+o} in the interior edge weight of u_{r+e} - u_r (order 4:
+// e = -2, -1, 1, 2 and o = -2..2; order 2: e = -1, 1 and o = -1..1)
+template <int ORD>
+__device__ __forceinline__ double d2_edge_dw(int e, int o) {
+    if constexpr (ORD == 4) {
+        constexpr double s6 = 1.0 / 6.0, e8 = 0.125, hf = 0.5;
+        switch (e) {
+            case -2: return o == -1 ? s6 : (o == -2 || o == 0) ? -e8 : 0.0;
+            case -1: return (o == -2 || o == 1) ? s6 : (o == -1 || o == 0) ? hf : 0.0;
+            case 1: return (o == -1 || o == 2) ? s6 : (o == 0 || o == 1) ? hf : 0.0;
+            case 2: return o == 1 ? s6 : (o == 0 || o == 2) ? -e8 : 0.0;
+            default: return 0.0;
+        }
+    } else {
+        return (e == -1 && (o == -1 || o == 0)) || (e == 1 && (o == 0 || o == 1)) ? 0.5 : 0.0;
+    }
+}
+
+// sum_r H^_r z_r sum_m dk_rm/db_p (y_m - y_r) along a line (stride st, n points)
+template <typename T, int ORD>
+__device__ double d2_coef_grad(gcp<T> z, gcp<T> y, long st, int p, int n) {
+    using O = Op<ORD>;
+    constexpr int HF = O::HALF;
+    double acc = 0.0;
+    // interior rows r = p - o
+#pragma unroll
+    for (int o = -HF; o <= HF; ++o) {
+        const int r = p - o;
+        if (r < O::R0 || r > n - 1 - O::R0) continue;
+        const double yr = (double)y[(long)r * st];
+        double sum = 0.0;
+#pragma unroll
+        for (int e = -HF; e <= HF; ++e) {
+            if (e == 0) continue;
+            const double w = d2_edge_dw<ORD>(e, o);
+            if (w != 0.0) sum += w * ((double)y[(long)(r + e) * st] - yr);
+        }
+        acc += hnorm<ORD>(r, n) * (double)z[(long)r * st] * sum;
+    }
+    // closure rows at the lower end (coefficient index p) and the upper end (n-1-p)
+    if (p < O::W) {
+#pragma unroll
+        for (int r = 0; r < O::R0; ++r) {
+            const double yr = (double)y[(long)r * st];
+            double sum = 0.0;
+#pragma unroll
+            for (int m = 0; m < O::W; ++m) {
+                if (m == r) continue;
+                const double w = table_d2c<ORD>(r, m, p);
+                if (w != 0.0) sum += w * ((double)y[(long)m * st] - yr);
+            }
+            acc += hnorm<ORD>(r, n) * (double)z[(long)r * st] * sum;
+        }
+    }
+    if (n - 1 - p < O::W) {
+        const int pp = n - 1 - p;
+#pragma unroll
+        for (int r = 0; r < O::R0; ++r) {
+            const int rr = n - 1 - r;
+            const double yr = (double)y[(long)rr * st];
+            double sum = 0.0;
+#pragma unroll
+            for (int m = 0; m < O::W; ++m) {
+                if (m == r) continue;
+                const double w = table_d2c<ORD>(r, m, pp);
+                if (w != 0.0) sum += w * ((double)y[(long)(n - 1 - m) * st] - yr);
+            }
+            acc += hnorm<ORD>(rr, n) * (double)z[(long)rr * st] * sum;
+        }
+    }
+    return acc;
+}
+
+// (D1^ T (H^ z))_p = sum_r D1^[r][p] H^_r z_r along a line (D1^ = h D1)
+template <typename T, int ORD>
+__device__ double d1t_weighted(gcp<T> z, long st, int p, int n) {
+    using O = Op<ORD>;
+    constexpr int HF = O::HALF;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = -HF; k <= HF; ++k) {
+        const int r = p + k;
+        if (k == 0 || r < O::NB || r > n - 1 - O::NB) continue;
+        acc += O::d1i(-k + HF) * hnorm<ORD>(r, n) * (double)z[(long)r * st];
+    }
+    if (p < 6) {
+#pragma unroll
+        for (int r = 0; r < O::NB; ++r) {
+            const double w = table_d1b<ORD>(r, p);
+            if (w != 0.0) acc += w * hnorm<ORD>(r, n) * (double)z[(long)r * st];
+        }
+    }
+    if (n - 1 - p < 6) {
+#pragma unroll
+        for (int r = 0; r < O::NB; ++r) {
+            const double w = -table_d1b<ORD>(r, n - 1 - p);
+            if (w != 0.0) acc += w * hnorm<ORD>(n - 1 - r, n) * (double)z[(long)(n - 1 - r) * st];
+        }
+    }
+    return acc;
+}
+
+template <typename T, int ORD>
+__global__ void __launch_bounds__(256) k_grad(GradArgs G) {
+    using O = Op<ORD>;
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    // block of this point and its operands, read from the kernel argument
+    // with static indices only (a runtime index would copy the argument to
+    // per-lane scratch memory)
+    int b = 0;
+    long end = G.off[1];
+    gcp<T> z = gc<T>(G.z[0]);
+    gcp<T> y = gc<T>(G.y[0]);
+    gcp<T> a = gc<T>(G.a[0]);
+    double* gcb = G.gc[0];
+    double* grb = G.grt[0];
+    long base = 0;
+#pragma unroll
+    for (int k = 1; k < MAX_APPLY_BLOCKS; ++k)
+        if (k < G.nblocks && gid >= G.off[k]) {
+            b = k;
+            base = G.off[k];
+            end = G.off[k + 1];
+            z = gc<T>(G.z[k]);
+            y = gc<T>(G.y[k]);
+            a = gc<T>(G.a[k]);
+            gcb = G.gc[k];
+            grb = G.grt[k];
+        }
+    if (gid >= end) return;
+    BlockRef B = ((const GLB BlockDesc*)G.blocks)[b];
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const long p = gid - base;
+    const int j = (int)(p / n1), i = (int)(p - (long)j * n1);
+    const double h1 = B.h1, h2 = B.h2;
+    const double hn1 = hnorm<ORD>(i, n1), hn2 = hnorm<ORD>(j, n2);
+    const long row = (long)j * n1;
+    double g[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // narrow terms (stored fields: x1 C1111, C1112, C1212; x2 C2121, C2122, C2222)
+    {
+        const double fx = h2 * hn2 / h1, fy = h1 * hn1 / h2;
+        gcp<T> zr0 = z + row, zr1 = z + np + row, yr0 = y + row, yr1 = y + np + row;
+        g[K_C1111] += fx * d2_coef_grad<T, ORD>(zr0, yr0, 1, i, n1);
+        g[K_C1112] += fx * (d2_coef_grad<T, ORD>(zr0, yr1, 1, i, n1) + d2_coef_grad<T, ORD>(zr1, yr0, 1, i, n1));
+        g[K_C1212] += fx * d2_coef_grad<T, ORD>(zr1, yr1, 1, i, n1);
+        gcp<T> zc0 = z + i, zc1 = z + np + i, yc0 = y + i, yc1 = y + np + i;
+        g[K_C2121] += fy * d2_coef_grad<T, ORD>(zc0, yc0, n1, j, n2);
+        g[K_C2122] += fy * (d2_coef_grad<T, ORD>(zc0, yc1, n1, j, n2) + d2_coef_grad<T, ORD>(zc1, yc0, n1, j, n2));
+        g[K_C2222] += fy * d2_coef_grad<T, ORD>(zc1, yc1, n1, j, n2);
+    }
+    // mixed terms: M_ab = c_1a2b (C1121, C1122, C1221, C1222)
+    {
+        double tzx[2], tzy[2], dyx[2], dyy[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            tzx[c] = d1t_weighted<T, ORD>(z + c * np + row, 1, i, n1);
+            tzy[c] = d1t_weighted<T, ORD>(z + c * np + i, n1, j, n2);
+            dyx[c] = (double)d1_line<T, ORD>(y + c * np + row, 1, i, n1);
+            dyy[c] = (double)d1_line<T, ORD>(y + c * np + i, n1, j, n2);
+        }
+        const int km[2][2] = {{K_C1121, K_C1122}, {K_C1221, K_C1222}};
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) g[km[aa][bb]] += hn2 * tzx[aa] * dyy[bb] + hn1 * tzy[bb] * dyx[aa];
+    }
+    // faces through this point
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+        const int ax = f >> 1, sd = f & 1;
+        const bool on = ax == 0 ? (i == (sd ? n1 - 1 : 0)) : (j == (sd ? n2 - 1 : 0));
+        if (!on) continue;
+        const GLB FaceDesc& F = B.face[f];
+        const int t = ax == 0 ? j : i;
+        const int nt = ax == 0 ? n2 : n1;
+        const int na = ax == 0 ? n1 : n2;
+        const double ht = ax == 0 ? h2 : h1, ha = ax == 0 ? h1 : h2;
+        const double wq = ht * hnorm<ORD>(t, nt);      // face quadrature weight
+        const double iw = 1.0 / F.w;
+        const double nu = sd ? 1.0 : -1.0;
+        // N_jl (face-normal narrow) and M_jl fields as stored indices
+        const int kn[2][2] = {{ax == 0 ? K_C1111 : K_C2121, ax == 0 ? K_C1112 : K_C2122},
+                              {ax == 0 ? K_C1112 : K_C2122, ax == 0 ? K_C1212 : K_C2222}};
+        const int km[2][2] = {{K_C1121, K_C1122}, {K_C1221, K_C1222}};
+        const long st_n = ax == 0 ? 1 : n1;      // stride along the normal
+        const long st_t = ax == 0 ? n1 : 1;      // stride along the face
+        const long p_line_n = ax == 0 ? row : i; // start of the normal line through p
+        const long p_line_t = ax == 0 ? i : row; // start of the face line through p
+        const int pn = ax == 0 ? i : j;          // index along the normal line
+        if (F.kind == BC_TRACTION || F.kind == BC_ROBIN) {
+            double dn_y[2], dt_y[2];
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                dn_y[l] = (double)d1_line<T, ORD>(y + l * np + p_line_n, st_n, pn, na) / ha;
+                dt_y[l] = (double)d1_line<T, ORD>(y + l * np + p_line_t, st_t, t, nt) / ht;
+            }
+            const double zc[2] = {(double)z[p], (double)z[np + p]};
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    g[kn[jj][l]] += -wq * nu * zc[jj] * dn_y[l];
+                    if (ax == 0) g[km[jj][l]] += -wq * nu * zc[jj] * dt_y[l];    // c_1j2l D_2
+                    else g[km[l][jj]] += -wq * nu * zc[jj] * dt_y[l];            // c_2j1l = M_lj, D_1
+                }
+        } else if (F.kind == BC_DISPLACEMENT) {
+            double del[2] = {(double)y[p], (double)y[np + p]};
+            if (!G.homogeneous && F.g) {
+                const double tau = ((const GLB double*)G.tau)[3 * F.item_g];
+                gcp<T> gg = gc<T>(F.g);
+                del[0] -= tau * (double)gg[t];
+                del[1] -= tau * (double)gg[F.nf + t];
+            }
+            // normal part: sum over the REACH points along the normal
+            double zn[2] = {0.0, 0.0};
+#pragma unroll
+            for (int dn = 0; dn < O::REACH; ++dn) {
+                const int q = sd ? na - 1 - dn : dn;
+                const double cfq = -O::d1b(0, dn) * wq / ha;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) zn[c] += cfq * (double)z[c * np + p_line_n + (long)q * st_n];
+            }
+            // tangential part: (D_t z)(t)
+            double dtz[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) dtz[c] = (double)d1_line<T, ORD>(z + c * np + p_line_t, st_t, t, nt) / ht;
+            const double pen = 2.0 * B.beta * iw * wq;
+            const double zc[2] = {(double)z[p], (double)z[np + p]};
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    g[kn[jj][l]] += (zn[jj] - pen * zc[jj]) * del[l];
+                    if (ax == 0) g[km[l][jj]] += wq * dtz[jj] * nu * del[l];     // q_j = nu M_lj delta_l
+                    else g[km[jj][l]] += wq * dtz[jj] * nu * del[l];             // q_j = nu M_jl delta_l
+                }
+        }
+    }
+    const double Hp = h1 * h2 * hn1 * hn2;
+    const double al = G.alpha;
+    gp<double> gq = (gp<double>)gcb;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gq[(long)k * np + p] += al * g[k];
+    ((gp<double>)grb)[p] += -al * Hp * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
+}
+
+// y = sum_k c_k x_k (elementwise; y may be one of the x_k)
+template <typename T>
+__global__ void __launch_bounds__(256) k_lincomb(int nterms, double c0, double c1, double c2, double c3,
+                                                 const T* x0, const T* x1, const T* x2, const T* x3, T* y,
+                                                 long count) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    double acc = c0 * (double)x0[i];
+    if (nterms > 1) acc += c1 * (double)x1[i];
+    if (nterms > 2) acc += c2 * (double)x2[i];
+    if (nterms > 3) acc += c3 * (double)x3[i];
+    y[i] = static_cast<T>(acc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_rec_adjoint(const RecAdj* ent, int nent, const double* r, RecAdjArgs A) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= nent) return;
+    const GLB RecAdj& e = ((const GLB RecAdj*)ent)[k];
+    const int b = e.block;
+    T* u = nullptr;
+    long np = 0;
+#pragma unroll
+    for (int q = 0; q < MAX_APPLY_BLOCKS; ++q)
+        if (q == b) {
+            u = (T*)A.u[q];
+            np = A.np[q];
+        }
+    const GLB double* rr = (const GLB double*)r + 2 * e.rec;
+    atomicAdd(&u[e.p], static_cast<T>(A.scale * e.w * rr[0]));
+    atomicAdd(&u[np + e.p], static_cast<T>(A.scale * e.w * rr[1]));
+}
+
 // -------------------------------------------------------------- energy
 // per point H_p rho~_p (|v|^2 - u . a) with a = rho~^{-1} D^tot u already in a1;
 // partial sums per workgroup in FP64, then one workgroup sums them in order.
@@ -1290,6 +1597,45 @@ int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks
     }
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, partial_dev, npartial, result_dev);
     return static_cast<int>(hipGetLastError());
+}
+
+int launch_grad(int dtype, int order, const GradArgs& g, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long n = g.off[g.nblocks];
+    if (n <= 0) return 0;
+    const dim3 grid((unsigned)((n + 255) / 256)), bl(256);
+    if (dtype == 0) {
+        if (order == 4) hipLaunchKernelGGL((k_grad<double, 4>), grid, bl, 0, s, g);
+        else hipLaunchKernelGGL((k_grad<double, 2>), grid, bl, 0, s, g);
+    } else {
+        if (order == 4) hipLaunchKernelGGL((k_grad<float, 4>), grid, bl, 0, s, g);
+        else hipLaunchKernelGGL((k_grad<float, 2>), grid, bl, 0, s, g);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_lincomb(int dtype, int nterms, const double* c, const void* const* x, void* y, long count, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (count <= 0) return 0;
+    const dim3 grid((unsigned)((count + 255) / 256)), bl(256);
+    const void* xs[4] = {x[0], nterms > 1 ? x[1] : x[0], nterms > 2 ? x[2] : x[0], nterms > 3 ? x[3] : x[0]};
+    const double cs[4] = {c[0], nterms > 1 ? c[1] : 0.0, nterms > 2 ? c[2] : 0.0, nterms > 3 ? c[3] : 0.0};
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_lincomb<double>, grid, bl, 0, s, nterms, cs[0], cs[1], cs[2], cs[3], (const double*)xs[0],
+                           (const double*)xs[1], (const double*)xs[2], (const double*)xs[3], (double*)y, count);
+    else
+        hipLaunchKernelGGL(k_lincomb<float>, grid, bl, 0, s, nterms, cs[0], cs[1], cs[2], cs[3], (const float*)xs[0],
+                           (const float*)xs[1], (const float*)xs[2], (const float*)xs[3], (float*)y, count);
+    return (int)hipGetLastError();
+}
+
+int launch_rec_adjoint(int dtype, const RecAdj* ent, int nent, const double* r, const RecAdjArgs& a, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nent <= 0) return 0;
+    const dim3 grid((unsigned)((nent + 255) / 256)), bl(256);
+    if (dtype == 0) hipLaunchKernelGGL(k_rec_adjoint<double>, grid, bl, 0, s, ent, nent, r, a);
+    else hipLaunchKernelGGL(k_rec_adjoint<float>, grid, bl, 0, s, ent, nent, r, a);
+    return (int)hipGetLastError();
 }
 
 const char* hip_error_string(int code) { return hipGetErrorString(static_cast<hipError_t>(code)); }

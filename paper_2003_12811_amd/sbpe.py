@@ -62,6 +62,11 @@ _PROTOS = {
     'sbpe_set_kernel_timing': [_P, _I],
     'sbpe_get_kernel_timing': [_P, _DP, _IP],
     'sbpe_plan_info': [_P, ctypes.POINTER(ctypes.c_longlong)],
+    'sbpe_grad_accumulate': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, _I,
+                             ctypes.POINTER(_P), ctypes.POINTER(_P)],
+    'sbpe_grad_to_physical': [_P, _I, _P, _P, _DP, _DP],
+    'sbpe_lincomb': [_P, _I, _DP, ctypes.POINTER(_P), _P, ctypes.c_longlong],
+    'sbpe_receiver_adjoint': [_P, _P, ctypes.POINTER(_P), _D],
     'sbpe_batch_create': [_I, _P, _I, _I, ctypes.POINTER(_P)],
     'sbpe_batch_destroy': [_P],
     'sbpe_batch_add': [_P, _P, _I, _D],
@@ -262,6 +267,28 @@ def sbpe_get_block_fields(ctx, block):
     _check(ctx, lib().sbpe_get_block_fields(ctx, block, _dp(c10), _dp(J), _dp(jh)))
     jhat = [jh[f, :(n2 if f < 2 else n1)].copy() for f in range(4)]
     return c10, J, jhat
+
+
+def sbpe_grad_accumulate(ctx, z_ptrs, y_ptrs, a_ptrs, alpha, t, homogeneous, gc_ptrs, grt_ptrs):
+    _check(ctx, lib().sbpe_grad_accumulate(ctx, _ptrs(z_ptrs), _ptrs(y_ptrs), _ptrs(a_ptrs), alpha, t,
+                                           1 if homogeneous else 0, _ptrs(gc_ptrs), _ptrs(grt_ptrs)))
+
+
+def sbpe_grad_to_physical(ctx, block, gc_ptr, grt_ptr):
+    n1, n2 = sbpe_block_size(ctx, block)
+    g10 = np.empty((10, n2, n1))
+    gr = np.empty((n2, n1))
+    _check(ctx, lib().sbpe_grad_to_physical(ctx, block, _P(int(gc_ptr)), _P(int(grt_ptr)), _dp(g10), _dp(gr)))
+    return g10, gr
+
+
+def sbpe_lincomb(ctx, coefs, x_ptrs, y_ptr, count):
+    c = np.ascontiguousarray(coefs, dtype=np.float64)
+    _check(ctx, lib().sbpe_lincomb(ctx, len(c), _dp(c), _ptrs(x_ptrs), _P(int(y_ptr)), int(count)))
+
+
+def sbpe_receiver_adjoint(ctx, r_ptr, u_ptrs, scale=1.0):
+    _check(ctx, lib().sbpe_receiver_adjoint(ctx, _P(int(r_ptr)), _ptrs(u_ptrs), scale))
 
 
 KERNEL_KINDS = ('interior_rk1', 'frame_rk1', 'interior_rk2', 'frame_rk2', 'interior_apply', 'frame_apply')

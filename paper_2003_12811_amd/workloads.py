@@ -322,3 +322,46 @@ def spec_shot(n, seed, order=4, nrec=64, device=None):
                 blocks=[dict(X1=X1, X2=X2, rho=rho, C10=voigt_to_c10(V), bc=bc, forcing=None)],
                 interfaces=[], sources=[(0, xs[0], xs[1], 0.0, -1.0, 1.0, 10.0, 0.1)],
                 receivers=[(0, xr, np.ones(nrec))], steps=1500, cfl=0.5)
+
+
+def blob(X1, X2, center=(0.5, 0.5), width=0.1):
+    """Gaussian blob exp(-|X - center|^2 / (2 width^2)) on the physical grid."""
+    return np.exp(-((X1 - center[0]) ** 2 + (X2 - center[1]) ** 2) / (2.0 * width ** 2))
+
+
+def spec_c5(n=513, seed=0, order=4, nrec=100, perturbed=False):
+    """Differentiation workload: Gaussian-topography block of n^2 points with its
+    random smooth material (seed), displacement bottom and traction elsewhere,
+    a 10 Hz vertical Ricker force at (0.5, 0.75) and nrec receivers on x2 = 1.
+    perturbed=True multiplies rho and every stiffness field by (1 + 0.05 blob),
+    the model of the observed data."""
+    X1, X2 = grid(GaussianTopography(), n, n)
+    rho, V = smooth_random_material(X1, X2, seed)
+    C10 = voigt_to_c10(V)
+    if perturbed:
+        s = 1.0 + 0.05 * blob(X1, X2)
+        rho, C10 = rho * s, C10 * s
+    bc = _free_faces()
+    bc[2] = (DISPLACEMENT, None, T_ZERO, None, None)
+    xr = np.linspace(0.02, 0.98, nrec)
+    return dict(order=order,
+                blocks=[dict(X1=X1, X2=X2, rho=rho, C10=C10, bc=bc, forcing=None)],
+                interfaces=[], sources=[(0, 0.5, 0.75, 0.0, -1.0, 1.0, 10.0, 0.1)],
+                receivers=[(0, xr, np.ones(nrec))], steps=2000, cfl=0.5)
+
+
+def smooth_direction(X1, X2, seed, nmodes=4, kmax=3):
+    """A random smooth perturbation direction (rho (n2, n1), Voigt (6, n2, n1))
+    for finite-difference checks: low Fourier modes per field."""
+    rng = np.random.default_rng(50_000 + seed)
+    out = []
+    for _ in range(7):
+        kx = rng.integers(-kmax, kmax + 1, nmodes)
+        ky = rng.integers(-kmax, kmax + 1, nmodes)
+        ph = rng.uniform(0.0, 2.0 * np.pi, nmodes)
+        a = rng.normal(size=nmodes)
+        s = np.zeros_like(X1)
+        for m in range(nmodes):
+            s += a[m] * np.cos(2.0 * np.pi * (kx[m] * X1 + ky[m] * X2) + ph[m])
+        out.append(s / nmodes)
+    return out[0], np.stack(out[1:])

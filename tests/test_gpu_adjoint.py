@@ -1,0 +1,167 @@
+"""Gradients of the receiver misfit by the library's discrete adjoint.
+
+* Against the oracle's discrete adjoint (oracle/adjoint.py) element by element
+  on a small block, with checkpoint segments that do not divide the run.
+* Against central finite differences of J along random smooth directions in
+  (rho, C10): on a small block, and on the 513^2 differentiation workload
+  (2000 steps, 100 receivers, checkpoints every 100 steps, 20 directions).
+* The torch.autograd.Function returns the same gradient.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2003_12811_amd import adjoint as ADJ
+from paper_2003_12811_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _observed(spec_obs, nsteps, dt):
+    mg = ADJ.MisfitGradient(spec_obs, nsteps, dt)
+    try:
+        mg.forward()
+        return mg.traces.copy()
+    finally:
+        mg.close()
+
+
+def _dt(spec, cfl=0.5):
+    from paper_2003_12811_amd.solver import Solver
+    s = Solver(spec, 'f64')
+    try:
+        return s.dt_cfl(cfl)
+    finally:
+        s.close()
+
+
+def _c10_from_full(gC):
+    """dJ/dC10 from dJ/dC with independent entries (pairs 11, 12, 21, 22)."""
+    from oracle.material import C10_ORDER, PAIRS
+    out = []
+    for p, q in C10_ORDER:
+        a = gC[PAIRS[p] + PAIRS[q]]
+        out.append(a if p == q else a + gC[PAIRS[q] + PAIRS[p]])
+    return np.stack(out)
+
+
+def test_gradient_matches_oracle_adjoint():
+    from oracle import adjoint as OA
+    from oracle.spec import build
+    n, nsteps = 21, 23
+    spec = W.spec_c5(n=n, nrec=5)
+    spec_obs = W.spec_c5(n=n, nrec=5, perturbed=True)
+    dt = _dt(spec)
+    say('gradient vs oracle adjoint: n=%d steps=%d dt=%.3e' % (n, nsteps, dt))
+    P_obs = build(spec_obs)
+    d_obs = OA.forward_receivers(P_obs, spec_obs, nsteps, dt)
+    P = build(spec)
+    Jo, go_rho, go_C = OA.misfit_gradient(P, spec, nsteps, dt, d_obs)
+    mg = ADJ.MisfitGradient(spec, nsteps, dt, d_obs=d_obs, checkpoint_every=7)
+    try:
+        J = mg.forward()
+        g_rho, g_c10 = mg.gradient()
+    finally:
+        mg.close()
+    go_c10 = _c10_from_full(go_C)
+    er, ec, eJ = rel(g_rho, go_rho), rel(g_c10, go_c10), abs(J - Jo) / Jo
+    say('  J %.6e (oracle %.6e)  rel err J %.2e  rho %.2e  C10 %.2e' % (J, Jo, eJ, er, ec))
+    assert eJ < 1e-9 and er < 1e-8 and ec < 1e-8
+
+
+def _fd_check(spec, spec_obs, nsteps, dt, ndir, ckpt, tol, eps=1e-5):
+    d_obs = _observed(spec_obs, nsteps, dt)
+    mg = ADJ.MisfitGradient(spec, nsteps, dt, d_obs=d_obs, checkpoint_every=ckpt)
+    try:
+        J0 = mg.forward()
+        g_rho, g_c10 = mg.gradient()
+    finally:
+        mg.close()
+    blk = spec['blocks'][0]
+    X1, X2 = blk['X1'], blk['X2']
+
+    def J_at(rho, C10):
+        sp = dict(spec)
+        b = dict(blk)
+        b['rho'], b['C10'] = rho, C10
+        sp['blocks'] = [b]
+        m = ADJ.MisfitGradient(sp, nsteps, dt, d_obs=d_obs, checkpoint_every=nsteps)
+        try:
+            return m.forward()
+        finally:
+            m.close()
+
+    worst = 0.0
+    for k in range(ndir):
+        drho, dV = W.smooth_direction(X1, X2, k)
+        drho = drho * blk['rho']
+        # Voigt directions keep the minor symmetry (and semidefiniteness) of C
+        dC = W.voigt_to_c10(dV) * np.abs(blk['C10']).max(axis=0, keepdims=True)
+        # central differences at eps and eps/2, Richardson-extrapolated: the
+        # misfit of nearly equal traces is strongly curved, so the plain
+        # central difference has an O(eps^2) error well above rounding
+        def cd(e):
+            return (J_at(blk['rho'] + e * drho, blk['C10'] + e * dC)
+                    - J_at(blk['rho'] - e * drho, blk['C10'] - e * dC)) / (2 * e)
+        fd = (4.0 * cd(0.5 * eps) - cd(eps)) / 3.0
+        ad = float(np.sum(g_rho * drho) + np.sum(g_c10 * dC))
+        if k == 0:   # the Voigt gradient gives the same directional derivative
+            gV = ADJ.c10_grad_to_voigt(g_c10)
+            dVs = dV * np.abs(blk['C10']).max(axis=0, keepdims=True)
+            assert float(np.sum(g_rho * drho) + np.sum(gV * dVs)) == pytest.approx(ad, rel=1e-12)
+        e = abs(ad - fd) / max(abs(fd), 1e-300)
+        worst = max(worst, e)
+        say('  direction %2d: adjoint %.9e  finite difference %.9e  rel %.2e' % (k, ad, fd, e))
+    assert worst < tol, worst
+    return J0
+
+
+def test_gradient_matches_finite_differences_small():
+    n, nsteps = 65, 150
+    spec = W.spec_c5(n=n, nrec=12)
+    spec_obs = W.spec_c5(n=n, nrec=12, perturbed=True)
+    dt = _dt(spec)
+    say('finite differences, n=%d steps=%d' % (n, nsteps))
+    _fd_check(spec, spec_obs, nsteps, dt, ndir=3, ckpt=40, tol=1e-8)
+
+
+def test_c5_gradient_finite_differences():
+    """The differentiation workload: 513^2, 2000 steps, 100 receivers,
+    checkpoints every 100 steps, 20 random smooth directions."""
+    spec = W.spec_c5()
+    spec_obs = W.spec_c5(perturbed=True)
+    dt = _dt(spec)
+    say('C5: 513^2, 2000 steps, dt %.4e' % dt)
+    J0 = _fd_check(spec, spec_obs, 2000, dt, ndir=20, ckpt=100, tol=1e-8)
+    assert J0 > 0
+
+
+def test_autograd_function_matches():
+    import torch
+    n, nsteps = 33, 40
+    spec = W.spec_c5(n=n, nrec=6)
+    spec_obs = W.spec_c5(n=n, nrec=6, perturbed=True)
+    dt = _dt(spec)
+    d_obs = _observed(spec_obs, nsteps, dt)
+    rho = torch.tensor(spec['blocks'][0]['rho'], requires_grad=True)
+    C10 = torch.tensor(spec['blocks'][0]['C10'], requires_grad=True)
+    J = ADJ.seismic_misfit(rho, C10, spec, nsteps, dt, d_obs, 10)
+    J.backward()
+    mg = ADJ.MisfitGradient(spec, nsteps, dt, d_obs=d_obs, checkpoint_every=10)
+    try:
+        J2 = mg.forward()
+        g_rho, g_c10 = mg.gradient()
+    finally:
+        mg.close()
+    assert float(J) == pytest.approx(J2, rel=1e-12)
+    assert np.allclose(rho.grad.numpy(), g_rho, rtol=0, atol=1e-14 * np.abs(g_rho).max())
+    assert np.allclose(C10.grad.numpy(), g_c10, rtol=0, atol=1e-14 * np.abs(g_c10).max())

@@ -95,6 +95,36 @@ def run_gpu(spec, dtype, steps, warmup, apply_reps=0):
     return res
 
 
+def gradient_timing(n=513, nsteps=2000, ckpt=100):
+    """Wall time of the forward run and of the adjoint gradient on the
+    differentiation workload (FP64)."""
+    import torch
+    from paper_2003_12811_amd import adjoint as ADJ
+    from paper_2003_12811_amd import workloads as W
+    from paper_2003_12811_amd.solver import Solver
+    spec, spec_obs = W.spec_c5(n=n), W.spec_c5(n=n, perturbed=True)
+    s = Solver(spec, 'f64')
+    dt = s.dt_cfl(0.5)
+    s.close()
+    obs = ADJ.MisfitGradient(spec_obs, nsteps, dt)
+    obs.forward()
+    d_obs = obs.traces.copy()
+    obs.close()
+    mg = ADJ.MisfitGradient(spec, nsteps, dt, d_obs=d_obs, checkpoint_every=ckpt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = mg.forward()
+    t1 = time.perf_counter()
+    g_rho, g_c10 = mg.gradient()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    mg.close()
+    return {"workload": "%dx%d block, %d RK4 steps, 100 receivers, misfit against the +5%% blob model, "
+                        "checkpoints every %d steps, FP64" % (n, n, nsteps, ckpt),
+            "J": J, "forward_s": t1 - t0, "gradient_s": t2 - t1, "gradient_over_forward": (t2 - t1) / (t1 - t0),
+            "forward_updates_per_s": n * n * nsteps / (t1 - t0)}
+
+
 def copy_probe(mib):
     import torch
     n = mib * (1 << 20) // 4
@@ -161,6 +191,7 @@ def main():
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
+    ap.add_argument('--no-gradient', action='store_true')
     ap.add_argument('--serve-shots', type=int, default=32)
     ap.add_argument('--serve-steps', type=int, default=300)
     ap.add_argument('--copy-probe-mib', type=int, default=0,
@@ -221,6 +252,9 @@ def main():
         from paper_2003_12811_amd import serve
         log('served stream vs sequential plain solves')
         line["serving"] = serve.serve_and_compare(args.serve_shots, 20.0, [257, 513, 1025], args.serve_steps)
+    if not args.no_gradient:
+        log('misfit gradient (513^2, 2000 steps, checkpoints every 100)')
+        line["gradient"] = gradient_timing()
     if not args.no_cpu_baseline:
         log('cpu baseline (oracle, 1 thread, %d steps)' % args.cpu_steps)
         line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)

@@ -119,6 +119,11 @@ struct HostBlock {
     void* d_a1 = nullptr;
     void* d_a2 = nullptr;
     void* d_face[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    // assembled frame operator (CSR over the frame rows)
+    int* d_fr_rowptr = nullptr;
+    int* d_fr_col = nullptr;
+    void* d_fr_val = nullptr;
+    void* d_fr_rsum = nullptr;
     void* u = nullptr;
     void* v = nullptr;
     long np() const { return (long)n1 * n2; }
@@ -181,6 +186,7 @@ struct sbpe_ctx {
     // member of a batch (sbpe_batch_add): the batch owns the stepping
     void* batch = nullptr;
     // kernel timing: pending (kind, start, stop) event records and sums
+    bool frame_sp = false;          // frame rows run from the assembled operator
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -725,7 +731,29 @@ static sbpe_status join_streams(sbpe_ctx* c) {
 static sbpe_status run_pass(sbpe_ctx* c, const PassArgs& a) {
     // launch kinds: 2 * pass index (RK1 = 0, RK2 = 1, APPLY = 2) + (0 interior, 1 frame)
     const int pk = a.pass == PASS_RK1 ? 0 : a.pass == PASS_RK2 ? 1 : 2;
-    sbpe_status s = join_streams(c);
+    sbpe_status s;
+    if (c->frame_sp && sweep_fused(c->total_tiles)) {
+        // assembled frame operator: frame and interior in one launch on the context stream
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            if (c->ev_kind.size() >= 4096) {
+                s = collect_timing(c);
+                if (s) return s;
+            }
+            e0 = next_event(c);
+            e1 = next_event(c);
+            if (!e0 || !e1) return fail(c, SBPE_EHIP, "hipEventCreate failed");
+            HIPCHECK(c, hipEventRecord(e0, c->stream));
+        }
+        const int e = launch_pass(c->dtype, c->order, a, c->total_tiles, c->total_frame_wg, c->stream);
+        if (e != 0) return fail(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+        if (c->timing) {
+            HIPCHECK(c, hipEventRecord(e1, c->stream));
+            c->ev_kind.push_back(2 * pk);
+        }
+        return SBPE_OK;
+    }
+    s = join_streams(c);
     if (s) return s;
     for (int part = 0; part < 2; ++part) {
         hipStream_t st = part == 0 ? c->stream : c->side;
@@ -740,8 +768,9 @@ static sbpe_status run_pass(sbpe_ctx* c, const PassArgs& a) {
             if (!e0 || !e1) return fail(c, SBPE_EHIP, "hipEventCreate failed");
             HIPCHECK(c, hipEventRecord(e0, st));
         }
-        const int e = part == 0 ? launch_interior(c->dtype, c->order, a, c->total_tiles, st)
-                                : launch_frame(c->dtype, c->order, a, c->total_frame_wg, st);
+        const int e = part == 0  ? launch_interior(c->dtype, c->order, a, c->total_tiles, st)
+                      : c->frame_sp ? launch_frame_sp(c->dtype, c->order, a, c->total_frame_wg, st)
+                                    : launch_frame(c->dtype, c->order, a, c->total_frame_wg, st);
         if (e != 0) return fail(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
         if (c->timing) {
             HIPCHECK(c, hipEventRecord(e1, st));
@@ -835,6 +864,10 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
             (void)hipFree(B.d_a2);
             for (int f = 0; f < 4; ++f)
                 for (int k = 0; k < 2; ++k) (void)hipFree(B.d_face[f][k]);
+            (void)hipFree(B.d_fr_rowptr);
+            (void)hipFree(B.d_fr_col);
+            (void)hipFree(B.d_fr_val);
+            (void)hipFree(B.d_fr_rsum);
         }
         (void)hipFree(c->d_desc);
         (void)hipFree(c->d_entries);
@@ -988,6 +1021,270 @@ sbpe_status sbpe_add_receivers(sbpe_ctx_t c, int block, int n, const double* x1,
     return SBPE_OK;
 }
 
+// ------------------------------------------------- assembled frame operator
+// Probe the frame kernel (the definition of the frame rows) with coloured unit
+// fields: colour (i mod 9, j mod 9) per block and component, so that every
+// frame row sees at most one probed point of each colour (no frame stencil,
+// including the interface terms that reach the partner block, spans 9 points
+// in either direction).  Two probes with constant fields give the row sums.
+// The result is checked against the frame kernel on a random field.
+static int probe_window(int i, int n, int color) {
+    int lo = i < 6 ? 0 : (i > n - 7 ? n - 9 : i - 4);
+    lo = std::max(0, std::min(lo, std::max(0, n - 9)));
+    const int p = lo + ((color - lo % 9) % 9 + 9) % 9;
+    return p < n ? p : -1;
+}
+
+static sbpe_status assemble_frame(sbpe_ctx* c) {
+    constexpr int P = 9;
+    const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
+    const int reach = c->order == 4 ? 4 : 2;
+    const int nb = (int)c->blocks.size();
+    if (nb > MAX_APPLY_BLOCKS) return SBPE_OK;     // general frame kernel
+    const size_t es = esize(c);
+    std::vector<void*> X(nb, nullptr), Y(nb, nullptr), G(nb, nullptr), Hh(nb, nullptr);
+    sbpe_status st = SBPE_OK;
+    auto cleanup = [&]() {
+        for (int b = 0; b < nb; ++b) {
+            (void)hipFree(X[b]);
+            (void)hipFree(Y[b]);
+            (void)hipFree(G[b]);
+            (void)hipHostFree(Hh[b]);
+        }
+    };
+    for (int b = 0; b < nb; ++b) {
+        const long np = c->blocks[b].np();
+        const int fn = c->desc[b].frame_n;
+        if (hipMalloc(&X[b], 2 * np * es) != hipSuccess || hipMalloc(&Y[b], 2 * np * es) != hipSuccess ||
+            hipMalloc(&G[b], 2 * (size_t)std::max(fn, 1) * es) != hipSuccess ||
+            hipHostMalloc(&Hh[b], 2 * (size_t)std::max(fn, 1) * es) != hipSuccess) {
+            cleanup();
+            return fail(c, SBPE_ENOMEM, "frame operator assembly buffers");
+        }
+    }
+    PassArgs pa = base_args(c);
+    pa.pass = PASS_APPLY;
+    pa.homogeneous = 1;
+    for (int b = 0; b < nb; ++b) {
+        pa.in[b] = X[b];
+        pa.out[b] = Y[b];
+    }
+    auto val = [&](int b, long idx) -> double {
+        return c->dtype == SBPE_F64 ? static_cast<double*>(Hh[b])[idx] : (double)static_cast<float*>(Hh[b])[idx];
+    };
+    // one probe: fill (bp = -1: every block), frame kernel, gather to the host
+    auto probe = [&](int bp, int comp, int cx, int cy, int period) -> sbpe_status {
+        for (int b = 0; b < nb; ++b) {
+            const HostBlock& H = c->blocks[b];
+            const int e = launch_probe_fill(c->dtype, X[b], H.n1, H.n2, (bp < 0 || bp == b) ? comp : -1, cx, cy,
+                                            period, c->stream);
+            if (e) return fail(c, SBPE_EHIP, std::string("probe fill: ") + hip_error_string(e));
+        }
+        int e = launch_frame(c->dtype, c->order, pa, c->total_frame_wg, c->stream);
+        if (e) return fail(c, SBPE_EHIP, std::string("probe frame: ") + hip_error_string(e));
+        for (int b = 0; b < nb; ++b) {
+            const HostBlock& H = c->blocks[b];
+            const int fn = c->desc[b].frame_n;
+            e = launch_frame_gather(c->dtype, Y[b], H.n1, H.n2, R, fn, G[b], c->stream);
+            if (e) return fail(c, SBPE_EHIP, std::string("probe gather: ") + hip_error_string(e));
+            HIPCHECK(c, hipMemcpyAsync(Hh[b], G[b], 2 * (size_t)fn * es, hipMemcpyDeviceToHost, c->stream));
+        }
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        return SBPE_OK;
+    };
+    // per block: row entries and row sums
+    std::vector<std::vector<std::vector<std::pair<int, double>>>> rows(nb);
+    std::vector<std::vector<double>> rsum(nb);
+    for (int b = 0; b < nb; ++b) {
+        rows[b].resize(2 * (size_t)c->desc[b].frame_n);
+        rsum[b].assign(4 * (size_t)c->desc[b].frame_n, 0.0);
+    }
+    bool bad = false;
+    for (int bp = 0; bp < nb && !bad; ++bp)
+        for (int comp = 0; comp < 2 && !bad; ++comp)
+            for (int cy = 0; cy < P && !bad; ++cy)
+                for (int cx = 0; cx < P && !bad; ++cx) {
+                    st = probe(bp, comp, cx, cy, P);
+                    if (st) {
+                        cleanup();
+                        return st;
+                    }
+                    for (int b = 0; b < nb; ++b) {
+                        const HostBlock& H = c->blocks[b];
+                        // faces of b across which block bp is the partner
+                        int pf_of[4] = {-1, -1, -1, -1};
+                        bool any = b == bp;
+                        for (int f = 0; f < 4; ++f)
+                            if (H.face[f].kind == BC_INTERFACE && H.face[f].partner == bp) {
+                                pf_of[f] = 1;
+                                any = true;
+                            }
+                        if (!any) continue;
+                        const int fn = c->desc[b].frame_n;
+                        const HostBlock& Pb = c->blocks[bp];
+#pragma omp parallel for schedule(static)
+                        for (int k = 0; k < fn; ++k) {
+                            int i, j;
+                            frame_ij(k, H.n1, H.n2, R, i, j);
+                            for (int q = 0; q < 2; ++q) {
+                                const double v = val(b, 2L * k + q);
+                                if (v == 0.0) continue;
+                                int col = 0;
+                                bool ok = false;
+                                if (b == bp) {
+                                    const int ii = probe_window(i, H.n1, cx), jj = probe_window(j, H.n2, cy);
+                                    if (ii >= 0 && jj >= 0) {
+                                        col = 2 * (jj * H.n1 + ii) + comp;
+                                        ok = true;
+                                    }
+                                } else {
+                                    for (int f = 0; f < 4 && !ok; ++f) {
+                                        if (pf_of[f] < 0) continue;
+                                        const int dn = f == 0 ? i : f == 1 ? H.n1 - 1 - i : f == 2 ? j : H.n2 - 1 - j;
+                                        if (dn >= reach) continue;
+                                        const HostFace& F = H.face[f];
+                                        const int t = f < 2 ? j : i;
+                                        const int nf = f < 2 ? H.n2 : H.n1;
+                                        const int tp = F.reversed ? nf - 1 - t : t;
+                                        int ip, jp;
+                                        if (F.pface < 2) {
+                                            ip = F.pface == 0 ? 0 : Pb.n1 - 1;
+                                            jp = tp;
+                                        } else {
+                                            ip = tp;
+                                            jp = F.pface == 2 ? 0 : Pb.n2 - 1;
+                                        }
+                                        const int ii = probe_window(ip, Pb.n1, cx), jj = probe_window(jp, Pb.n2, cy);
+                                        if (ii >= 0 && jj >= 0) {
+                                            col = -1 - ((f << 29) | (comp << 28) | (jj * Pb.n1 + ii));
+                                            ok = true;
+                                        }
+                                    }
+                                }
+                                if (!ok) {
+#pragma omp critical
+                                    bad = true;
+                                    continue;
+                                }
+                                rows[b][2 * (size_t)k + q].emplace_back(col, v);
+                            }
+                        }
+                    }
+                }
+    if (bad) {
+        cleanup();
+        return fail(c, SBPE_EHIP, "frame operator assembly: a frame row reaches beyond the probe window");
+    }
+    for (int comp = 0; comp < 2; ++comp) {
+        st = probe(-1, comp, 0, 0, 0);
+        if (st) {
+            cleanup();
+            return st;
+        }
+        for (int b = 0; b < nb; ++b)
+            for (int k = 0; k < c->desc[b].frame_n; ++k)
+                for (int q = 0; q < 2; ++q) rsum[b][2 * (2 * (size_t)k + q) + comp] = val(b, 2L * k + q);
+    }
+    // CSR upload
+    for (int b = 0; b < nb; ++b) {
+        HostBlock& H = c->blocks[b];
+        const size_t nr = rows[b].size();
+        std::vector<int> rp(nr + 1, 0), cl;
+        std::vector<double> vv;
+        for (size_t r = 0; r < nr; ++r) {
+            std::sort(rows[b][r].begin(), rows[b][r].end());
+            rp[r + 1] = rp[r] + (int)rows[b][r].size();
+            for (auto& e : rows[b][r]) {
+                cl.push_back(e.first);
+                vv.push_back(e.second);
+            }
+        }
+        if (cl.empty()) {
+            cl.push_back(0);
+            vv.push_back(0.0);
+        }
+        if (hipMalloc(&H.d_fr_rowptr, rp.size() * sizeof(int)) != hipSuccess ||
+            hipMalloc(&H.d_fr_col, cl.size() * sizeof(int)) != hipSuccess) {
+            cleanup();
+            return fail(c, SBPE_ENOMEM, "frame operator");
+        }
+        HIPCHECK(c, hipMemcpy(H.d_fr_rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHECK(c, hipMemcpy(H.d_fr_col, cl.data(), cl.size() * sizeof(int), hipMemcpyHostToDevice));
+        st = upload(c, vv, &H.d_fr_val);
+        if (!st) st = upload(c, rsum[b], &H.d_fr_rsum);
+        if (st) {
+            cleanup();
+            return st;
+        }
+        BlockDesc& D = c->desc[b];
+        D.fr_rowptr = H.d_fr_rowptr;
+        D.fr_col = H.d_fr_col;
+        D.fr_val = H.d_fr_val;
+        D.fr_rsum = H.d_fr_rsum;
+    }
+    HIPCHECK(c, hipMemcpy(c->d_desc, c->desc.data(), c->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
+    // check against the frame kernel on a random field
+    {
+        std::vector<std::vector<double>> ref(nb), got(nb);
+        unsigned long long sd = 0x9E3779B97F4A7C15ull;
+        for (int b = 0; b < nb; ++b) {
+            const long np = c->blocks[b].np();
+            std::vector<double> r(2 * np);
+            for (auto& x : r) {
+                sd ^= sd << 13;
+                sd ^= sd >> 7;
+                sd ^= sd << 17;
+                x = (double)(sd >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+            }
+            void* tmp = nullptr;
+            st = upload(c, r, &tmp);
+            if (st) {
+                cleanup();
+                return st;
+            }
+            HIPCHECK(c, hipMemcpy(X[b], tmp, 2 * np * es, hipMemcpyDeviceToDevice));
+            (void)hipFree(tmp);
+        }
+        double scale = 0.0, err = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int e = pass == 0 ? launch_frame(c->dtype, c->order, pa, c->total_frame_wg, c->stream)
+                                    : launch_frame_sp(c->dtype, c->order, pa, c->total_frame_wg, c->stream);
+            if (e) {
+                cleanup();
+                return fail(c, SBPE_EHIP, std::string("frame operator check: ") + hip_error_string(e));
+            }
+            for (int b = 0; b < nb; ++b) {
+                const HostBlock& H = c->blocks[b];
+                const int fn = c->desc[b].frame_n;
+                if (launch_frame_gather(c->dtype, Y[b], H.n1, H.n2, R, fn, G[b], c->stream)) {
+                    cleanup();
+                    return fail(c, SBPE_EHIP, "frame operator check gather");
+                }
+                HIPCHECK(c, hipMemcpyAsync(Hh[b], G[b], 2 * (size_t)fn * es, hipMemcpyDeviceToHost, c->stream));
+                HIPCHECK(c, hipStreamSynchronize(c->stream));
+                auto& dst = pass == 0 ? ref[b] : got[b];
+                dst.resize(2 * (size_t)fn);
+                for (size_t k = 0; k < dst.size(); ++k) dst[k] = val(b, (long)k);
+            }
+        }
+        for (int b = 0; b < nb; ++b)
+            for (size_t k = 0; k < ref[b].size(); ++k) {
+                scale = std::max(scale, std::fabs(ref[b][k]));
+                err = std::max(err, std::fabs(ref[b][k] - got[b][k]));
+            }
+        const double tol = c->dtype == SBPE_F64 ? 1e-11 : 1e-4;
+        if (err > tol * std::max(scale, 1e-300)) {
+            cleanup();
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "frame operator assembly check failed: %.3e relative", err / scale);
+            return fail(c, SBPE_EHIP, buf);
+        }
+    }
+    cleanup();
+    c->frame_sp = true;
+    return SBPE_OK;
+}
+
 sbpe_status sbpe_finalize(sbpe_ctx_t c) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
@@ -1054,6 +1351,10 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
     }
     sbpe_status s = build_plan(c);
     if (s) return s;
+    if (!c->host_only) {
+        s = assemble_frame(c);
+        if (s) return s;
+    }
     c->finalized = true;
     return SBPE_OK;
 }
@@ -1578,12 +1879,7 @@ static sbpe_status batch_rebuild(sbpe_batch* b) {
 }
 
 static sbpe_status batch_pass(sbpe_batch* b, const PassArgs& a) {
-    BHIPCHECK(b, hipEventRecord(b->ev_main, b->stream));
-    BHIPCHECK(b, hipStreamWaitEvent(b->side, b->ev_main, 0));
-    BHIPCHECK(b, hipEventRecord(b->ev_side, b->side));
-    BHIPCHECK(b, hipStreamWaitEvent(b->stream, b->ev_side, 0));
-    int e = launch_interior(b->dtype, b->order, a, b->total_tiles, b->stream);
-    if (e == 0) e = launch_frame(b->dtype, b->order, a, b->total_frame_wg, b->side);
+    const int e = launch_pass(b->dtype, b->order, a, b->total_tiles, b->total_frame_wg, b->stream);
     if (e != 0) return bfail(b, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
     return SBPE_OK;
 }

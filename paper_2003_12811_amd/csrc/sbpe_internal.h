@@ -3,6 +3,8 @@
 // pointer is device memory owned by the context (coefficients, workspace) or
 // by the caller (bound state, sbpe_apply operands).
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace sbpe {
@@ -84,7 +86,34 @@ struct BlockDesc {
     const Range* frame_rng;   // entry ranges of this block's frame workgroups (index wg - frame_beg)
     double* rec;              // receiver slots [steps][nrec*16][2], or null
     long rec_stride;          // doubles per step in rec
+    // assembled frame operator rho~^{-1} L restricted to the frame rows (null
+    // until assembled): CSR over rows 2k + q (frame point k, component q);
+    // col >= 0: own block, 2 p + q'; col < 0: -1 - ((f << 29) | (q' << 28) | p)
+    // for point p of the interface partner across face f
+    const int* fr_rowptr;
+    const int* fr_col;
+    const void* fr_val;       // [nnz] in the context dtype
+    const void* fr_rsum;      // [2 frame_n][2] row sums per input component
 };
+
+// frame point k of a block -> grid point (i, j): the R rows along x2 = 0, the
+// R rows along x2 = 1 (row by row), then the side bands column by column
+// (R columns at each x1 face, rows R .. n2-1-R)
+inline __host__ __device__ void frame_ij(int k, int n1, int n2, int R, int& i, int& j) {
+    if (k < R * n1) {
+        j = k / n1;
+        i = k - j * n1;
+    } else if (k < 2 * R * n1) {
+        const int kk = k - R * n1;
+        j = n2 - R + kk / n1;
+        i = kk % n1;
+    } else {
+        const int kk = k - 2 * R * n1;
+        const int cc = kk / (n2 - 2 * R), row = kk - cc * (n2 - 2 * R);
+        j = R + row;
+        i = cc < R ? cc : n1 - 2 * R + cc;
+    }
+}
 
 // point entries: sources add to the right-hand side, receivers record u
 struct Entry {
@@ -112,6 +141,7 @@ struct PassArgs {
     int pass;
     int homogeneous;
     int total_tiles;                    // interior workgroups over all blocks
+    int total_frame_wg;                 // frame point groups (FRAME_PTS points each) over all blocks
     int step;                           // launch step index (time-function row step - step0)
     int rec_base;                       // receiver row of launch step index 0
     double wa[3], wb[3];                // weights of the tabulated values: first / second evaluation
@@ -150,6 +180,14 @@ int launch_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt
 int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
                   int npartial, double* result_dev, void* stream);
 int launch_grad(int dtype, int order, const GradArgs& g, void* stream);
+// frame operator assembly: probe fill, compaction of frame outputs, sparse frame kernel
+int launch_probe_fill(int dtype, void* x, int n1, int n2, int comp, int cx, int cy, int period, void* stream);
+int launch_frame_gather(int dtype, const void* y, int n1, int n2, int R, int frame_n, void* out, void* stream);
+int launch_frame_sp(int dtype, int order, const PassArgs& a, int total_frame_wg, void* stream);
+// one sweep (frame operator and interior tiles) in one launch; sweep_fused
+// says whether a grid of that many tiles is swept that way
+bool sweep_fused(int total_tiles);
+int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg, void* stream);
 int launch_lincomb(int dtype, int nterms, const double* coefs, const void* const* x, void* y, long count,
                    void* stream);
 // one interpolation point of one receiver: u[block][c][p] += scale * w * r[rec][c]

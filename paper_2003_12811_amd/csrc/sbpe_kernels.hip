@@ -667,20 +667,7 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     const bool valid = k < B.frame_n;
     const int kk0 = valid ? k : 0;
     int i, j;
-    if (kk0 < R * n1) {
-        j = kk0 / n1;
-        i = kk0 - j * n1;
-    } else if (kk0 < 2 * R * n1) {
-        const int kk = kk0 - R * n1;
-        j = n2 - R + kk / n1;
-        i = kk % n1;
-    } else {
-        // side bands column by column: the points of a wave share their x1 closure row
-        const int kk = kk0 - 2 * R * n1;
-        const int cc = kk / (n2 - 2 * R), row = kk - cc * (n2 - 2 * R);
-        j = R + row;
-        i = cc < R ? cc : n1 - 2 * R + cc;
-    }
+    frame_ij(kk0, n1, n2, R, i, j);
     const long p = (long)j * n1 + i;
     const W3 none{0.0, 0.0, 0.0};
     const W3 ca = weights_a(A), cb = weights_b(A, B);
@@ -768,6 +755,193 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     }
 }
 
+// ------------------------------------------------- assembled frame operator
+// The frame rows of rho~^{-1} L are assembled once at setup by probing
+// k_frame with coloured unit vectors (colour (i mod 9, j mod 9): no stencil of
+// a frame row spans 9 points in either direction) and applied by k_frame_sp
+// in difference form,
+//   (rho~^{-1} L x)_{k,q} = sum_(p',q') K (x_q'(p') - x_q'(p_k)) + sum_q' S_q' x_q'(p_k),
+// with the row sums S from probes with constant fields, so that FP32 sums of
+// the O(1/h^2) entries cancel like the stencil kernels' differences.
+template <typename T>
+__global__ void __launch_bounds__(256) k_probe_fill(T* x, int n1, int n2, int comp, int cx, int cy, int period) {
+    const long np = (long)n1 * n2;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= 2 * np) return;
+    const int q = (int)(idx / np);
+    const long p = idx - q * np;
+    const int j = (int)(p / n1), i = (int)(p - (long)j * n1);
+    bool one = q == comp;
+    if (one && period > 0) one = (i % period) == cx && (j % period) == cy;
+    ((gp<T>)x)[idx] = one ? T(1) : T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_frame_gather(const T* y, int n1, int n2, int R, int frame_n, T* out) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= frame_n) return;
+    int i, j;
+    frame_ij(k, n1, n2, R, i, j);
+    const long np = (long)n1 * n2;
+    const long p = (long)j * n1 + i;
+    ((gp<T>)out)[2 * k] = ((gcp<T>)y)[p];
+    ((gp<T>)out)[2 * k + 1] = ((gcp<T>)y)[np + p];
+}
+
+// Eight lanes per frame point (four per component row).  Frame points are
+// numbered globally in groups of FRAME_PTS per block (the k_frame workgroup
+// layout, so the point-entry ranges carry over); a workgroup of nt threads
+// takes points fwg * nt / 8 .. (fwg + 1) * nt / 8 - 1.
+template <typename T, int ORD>
+__device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt) {
+    constexpr int R = Frame<ORD>::R;
+    const int g = fwg * (nt >> 3) + (int)(threadIdx.x >> 3);
+    const int wg = g / FRAME_PTS;
+    if (wg >= A.total_frame_wg) return;        // whole 8-lane groups leave together
+    const int b = find_block(A, wg, true);
+    BlockRef B = blk(A, b);
+    const int lane = threadIdx.x & 7;          // lane within the point
+    const int q = lane >> 2;                   // component row
+    const int sl = lane & 3;                   // lane within the row
+    const int k = (wg - B.frame_beg) * FRAME_PTS + g % FRAME_PTS;
+    const Range rg = load_range(B.frame_rng, wg - B.frame_beg);
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const bool valid = k < B.frame_n;
+    int i, j;
+    frame_ij(valid ? k : 0, n1, n2, R, i, j);
+    const long p = (long)j * n1 + i;
+    const bool apply = A.pass == PASS_APPLY;
+    constexpr int NFMAX = 2;
+    const int nf = apply ? 1 : 2;
+    // input fields of the sweep (own block) and their values at the point
+    gcp<T> xf[NFMAX];
+    if (apply) {
+        xf[0] = gc<T>(apply_in(A, b));
+        xf[1] = xf[0];
+    } else if (A.pass == PASS_RK1) {
+        xf[0] = gc<T>(B.u);
+        xf[1] = gc<T>(B.v);
+    } else {
+        xf[0] = gc<T>(B.a1);
+        xf[1] = gc<T>(B.a2);
+    }
+    T acc[NFMAX] = {T(0), T(0)};
+    T xp[NFMAX][2];
+#pragma unroll
+    for (int f = 0; f < NFMAX; ++f) {
+        xp[f][0] = valid ? xf[f][p] : T(0);
+        xp[f][1] = valid ? xf[f][np + p] : T(0);
+    }
+    if (valid) {
+        const int row = 2 * k + q;
+        const GLB int* rp = (const GLB int*)B.fr_rowptr;
+        const GLB int* cl = (const GLB int*)B.fr_col;
+        gcp<T> vl = gc<T>(B.fr_val);
+        const int e0 = rp[row], e1 = rp[row + 1];
+        for (int e = e0 + sl; e < e1; e += 4) {
+            const int c = cl[e];
+            const T w = vl[e];
+            if (c >= 0) {
+                const int qq = c & 1;
+                const long pp = c >> 1;
+#pragma unroll
+                for (int f = 0; f < NFMAX; ++f)
+                    if (f < nf) acc[f] += w * (xf[f][qq * np + pp] - xp[f][qq]);
+            } else {
+                const int v = -1 - c;
+                const int ff = v >> 29, qq = (v >> 28) & 1;
+                const long pp = v & ((1 << 28) - 1);
+                const GLB FaceDesc& F = B.face[ff];
+                const int pb = F.partner;
+                BlockRef P = blk(A, pb);
+                const long npp = (long)P.n1 * P.n2;
+                gcp<T> pf[NFMAX];
+                if (apply) {
+                    pf[0] = gc<T>(apply_in(A, pb));
+                    pf[1] = pf[0];
+                } else if (A.pass == PASS_RK1) {
+                    pf[0] = gc<T>(P.u);
+                    pf[1] = gc<T>(P.v);
+                } else {
+                    pf[0] = gc<T>(P.a1);
+                    pf[1] = gc<T>(P.a2);
+                }
+#pragma unroll
+                for (int f = 0; f < NFMAX; ++f)
+                    if (f < nf) acc[f] += w * (pf[f][qq * npp + pp] - xp[f][qq]);
+            }
+        }
+    }
+    // reduce the four lanes of the row
+#pragma unroll
+    for (int f = 0; f < NFMAX; ++f) {
+        acc[f] += __shfl_xor(acc[f], 1);
+        acc[f] += __shfl_xor(acc[f], 2);
+    }
+    if (valid) {
+        gcp<T> rs = gc<T>(B.fr_rsum);
+        const T s0 = rs[2 * (2 * k + q)], s1 = rs[2 * (2 * k + q) + 1];
+#pragma unroll
+        for (int f = 0; f < NFMAX; ++f) acc[f] += s0 * xp[f][0] + s1 * xp[f][1];
+    }
+    // data: lane 0 of the point with the first weights, lane 4 with the second
+    const W3 ca = weights_a(A), cb = weights_b(A, B);
+    T d0 = 0, d1 = 0;
+    if (valid && (lane == 0 || (lane == 4 && !apply))) {
+        const W3 cw{lane ? cb.w0 : ca.w0, lane ? cb.w1 : ca.w1, lane ? cb.w2 : ca.w2};
+        if (cw.any()) {
+            const int fld = apply ? FLD_IN : (A.pass == PASS_RK1 ? FLD_U : FLD_A1);
+            sat_point<T, ORD, true>(A, b, i, j, fld, cw, d0, d1);
+            point_data<T>(B, p, A, rg, cw, d0, d1);
+        }
+    }
+    // broadcast the data of lanes 0 and 4 to the point's lanes
+    const int base = threadIdx.x & ~7;
+    const T da0 = __shfl(d0, base), da1 = __shfl(d1, base);
+    const T db0 = __shfl(d0, base + 4), db1 = __shfl(d1, base + 4);
+    // the other row's results (component 1 - q)
+    T oth[NFMAX];
+#pragma unroll
+    for (int f = 0; f < NFMAX; ++f) oth[f] = __shfl_xor(acc[f], 4);
+    if (!valid || sl != 0) return;
+    const T irho = gc<T>(B.coef)[(long)K_IRHO * np + p];
+    const long qp = (long)q * np + p;
+    const T da = q ? da1 : da0, db = q ? db1 : db0;
+    (void)oth;
+    if (apply) {
+        gm<T>(apply_out(A, b))[qp] = acc[0] + irho * da;
+        return;
+    }
+    const T dt = static_cast<T>(B.dt);
+    if (A.pass == PASS_RK1) {
+        gm<T>(B.a1)[qp] = acc[0] + irho * da;
+        gm<T>(B.a2)[qp] = acc[0] + T(0.5) * dt * acc[1] + irho * db;
+        return;
+    }
+    const T A1 = gc<T>(B.a1)[qp], A2 = gc<T>(B.a2)[qp];
+    gp<T> uu = gm<T>(B.u);
+    gp<T> vv = gm<T>(B.v);
+    const T dt2 = dt * dt;
+    const T A3 = A2 + T(0.25) * dt2 * acc[0];
+    const T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * (acc[1] + irho * db);
+    const T uo = uu[qp], vo = vv[qp];
+    const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
+    uu[qp] = un;
+    vv[qp] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
+    if (gp<double> ro = rec_slots(B, A)) {
+        for (int e = rg.beg; e < rg.end; ++e) {
+            const GLB Entry& E = entry(B, e);
+            if (E.kind == 1 && E.p == p) ro[2 * E.id + q] = E.c0 * static_cast<double>(un);
+        }
+    }
+}
+
+template <typename T, int ORD>
+__global__ void __launch_bounds__(FRAME_WG) k_frame_sp(PassArgs A) {
+    frame_sp_body<T, ORD>(A, blockIdx.x, FRAME_WG);
+}
+
 // ------------------------------------------------------------- interior
 // Marching kernel: one wave covers the 64 columns i0 .. i0+63 and writes the
 // OUTW = 64 - 2H central ones (H = half width of the interior stencils), so
@@ -808,7 +982,7 @@ struct Lead {
 // in LDS for the pass arithmetic (RK1: wave w writes a_{w+1}; RK2: wave q
 // writes component q of u and v).
 template <typename T, int ORD, int PASS, bool SPLIT>
-__global__ void __launch_bounds__(SPLIT ? 128 : 64) k_march(PassArgs A) {
+__device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
     using O = Op<ORD>;
     constexpr int HF = O::HALF;
     constexpr int NW = 2 * HF + 1;
@@ -830,7 +1004,7 @@ __global__ void __launch_bounds__(SPLIT ? 128 : 64) k_march(PassArgs A) {
     // workgroup order: consecutive tiles on the same XCD (ids are dealt round-robin to 8 XCDs)
     const int total = A.total_tiles;
     const int per = (total + 7) / 8;
-    const int wg = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    const int wg = (bid % 8) * per + bid / 8;
     if (wg >= total) return;
     const int b = find_block(A, wg, false);
     BlockRef B = blk(A, b);
@@ -1166,6 +1340,23 @@ __global__ void __launch_bounds__(SPLIT ? 128 : 64) k_march(PassArgs A) {
             step(std::integral_constant<int, 4 % NW>{}, j0 + 4);
         }
     }
+}
+
+// One sweep in one launch: the first nframe workgroups (a multiple of 8, so
+// that the interior workgroups keep their position among the 8 XCDs) apply the
+// assembled frame operator, the others march over interior tiles.
+template <typename T, int ORD, int PASS, bool SPLIT>
+__global__ void __launch_bounds__(SPLIT ? 128 : 64) k_pass(PassArgs A, int nframe) {
+    // frame workgroups first: they are few and slower per point, so they start
+    // before the interior tiles fill the machine
+    const int bid = (int)blockIdx.x;
+    if (bid < nframe) frame_sp_body<T, ORD>(A, bid, SPLIT ? 128 : 64);
+    else march_body<T, ORD, PASS, SPLIT>(A, bid - nframe);
+}
+
+template <typename T, int ORD, int PASS, bool SPLIT>
+__global__ void __launch_bounds__(SPLIT ? 128 : 64) k_march(PassArgs A) {
+    march_body<T, ORD, PASS, SPLIT>(A, blockIdx.x);
 }
 
 // ---------------------------------------------------------- tau table
@@ -1531,21 +1722,66 @@ __global__ void __launch_bounds__(256) k_energy_final(const double* partial, int
 }
 
 // ---------------------------------------------------------- launchers
-template <typename T, int ORD>
-static void launch_march_t(const PassArgs& a, int total_tiles, hipStream_t s) {
-    const dim3 g(((total_tiles + 7) / 8) * 8), bl(64), bl2(128);
-    // two waves per tile when there are few tiles (the single-wave kernel
-    // needs more registers and fills fewer slots); SBPE_SPLIT=0/1 overrides
+// Two waves per tile when there are few tiles (the single-wave kernel needs
+// more registers and fills fewer slots); SBPE_SPLIT=0/1 overrides.
+static bool split_tiles(int total_tiles) {
     static const int split_env = [] {
         const char* e = std::getenv("SBPE_SPLIT");
         return e ? std::atoi(e) : -1;
     }();
-    const bool split = split_env >= 0 ? split_env != 0 : total_tiles < 4096;
+    return split_env >= 0 ? split_env != 0 : total_tiles < 4096;
+}
+
+bool sweep_fused(int total_tiles) {
+    // one launch for frame and interior pays while the tiles alone do not
+    // fill the machine; on larger grids the frame overlaps better from a
+    // second stream.  SBPE_FUSED=0/1 overrides.
+    static const int env = [] {
+        const char* e = std::getenv("SBPE_FUSED");
+        return e ? std::atoi(e) : -1;
+    }();
+    return env >= 0 ? env != 0 : split_tiles(total_tiles);
+}
+
+template <typename T, int ORD>
+static void launch_march_t(const PassArgs& a, int total_tiles, hipStream_t s) {
+    const dim3 g(((total_tiles + 7) / 8) * 8), bl(64), bl2(128);
+    const bool split = split_tiles(total_tiles);
     if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_march<T, ORD, PASS_APPLY, false>), g, bl, 0, s, a);
     else if (a.pass == PASS_RK1 && split) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK1, true>), g, bl2, 0, s, a);
     else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK1, false>), g, bl, 0, s, a);
     else if (split) hipLaunchKernelGGL((k_march<T, ORD, PASS_RK2, true>), g, bl2, 0, s, a);
     else hipLaunchKernelGGL((k_march<T, ORD, PASS_RK2, false>), g, bl, 0, s, a);
+}
+
+template <typename T, int ORD>
+static void launch_pass_t(const PassArgs& a, int total_tiles, int total_frame_wg, hipStream_t s) {
+    const bool split = a.pass != PASS_APPLY && split_tiles(total_tiles);
+    const int nt = split ? 128 : 64;
+    // frame workgroups (nt / 8 points each), rounded to whole XCD rounds
+    const long fpts = (long)total_frame_wg * FRAME_PTS;
+    const int nframe = (int)(((fpts + nt / 8 - 1) / (nt / 8) + 7) / 8 * 8);
+    const dim3 g(nframe + ((total_tiles + 7) / 8) * 8), bl(nt);
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_pass<T, ORD, PASS_APPLY, false>), g, bl, 0, s, a, nframe);
+    else if (a.pass == PASS_RK1 && split) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK1, true>), g, bl, 0, s, a, nframe);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK1, false>), g, bl, 0, s, a, nframe);
+    else if (split) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK2, true>), g, bl, 0, s, a, nframe);
+    else hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK2, false>), g, bl, 0, s, a, nframe);
+}
+
+int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PassArgs b = a;
+    b.total_tiles = total_tiles;
+    b.total_frame_wg = total_frame_wg;
+    if (dtype == 0) {
+        if (order == 4) launch_pass_t<double, 4>(b, total_tiles, total_frame_wg, s);
+        else launch_pass_t<double, 2>(b, total_tiles, total_frame_wg, s);
+    } else {
+        if (order == 4) launch_pass_t<float, 4>(b, total_tiles, total_frame_wg, s);
+        else launch_pass_t<float, 2>(b, total_tiles, total_frame_wg, s);
+    }
+    return (int)hipGetLastError();
 }
 
 int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream) {
@@ -1635,6 +1871,41 @@ int launch_rec_adjoint(int dtype, const RecAdj* ent, int nent, const double* r, 
     const dim3 grid((unsigned)((nent + 255) / 256)), bl(256);
     if (dtype == 0) hipLaunchKernelGGL(k_rec_adjoint<double>, grid, bl, 0, s, ent, nent, r, a);
     else hipLaunchKernelGGL(k_rec_adjoint<float>, grid, bl, 0, s, ent, nent, r, a);
+    return (int)hipGetLastError();
+}
+
+int launch_probe_fill(int dtype, void* x, int n1, int n2, int comp, int cx, int cy, int period, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long n = 2L * n1 * n2;
+    const dim3 grid((unsigned)((n + 255) / 256)), bl(256);
+    if (dtype == 0) hipLaunchKernelGGL(k_probe_fill<double>, grid, bl, 0, s, (double*)x, n1, n2, comp, cx, cy, period);
+    else hipLaunchKernelGGL(k_probe_fill<float>, grid, bl, 0, s, (float*)x, n1, n2, comp, cx, cy, period);
+    return (int)hipGetLastError();
+}
+
+int launch_frame_gather(int dtype, const void* y, int n1, int n2, int R, int frame_n, void* out, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (frame_n <= 0) return 0;
+    const dim3 grid((unsigned)((frame_n + 255) / 256)), bl(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_frame_gather<double>, grid, bl, 0, s, (const double*)y, n1, n2, R, frame_n, (double*)out);
+    else hipLaunchKernelGGL(k_frame_gather<float>, grid, bl, 0, s, (const float*)y, n1, n2, R, frame_n, (float*)out);
+    return (int)hipGetLastError();
+}
+
+int launch_frame_sp(int dtype, int order, const PassArgs& a0, int total_frame_wg, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (total_frame_wg <= 0) return 0;
+    PassArgs a = a0;
+    a.total_frame_wg = total_frame_wg;
+    const dim3 g(total_frame_wg), b(FRAME_WG);
+    if (dtype == 0) {
+        if (order == 4) hipLaunchKernelGGL((k_frame_sp<double, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_frame_sp<double, 2>), g, b, 0, s, a);
+    } else {
+        if (order == 4) hipLaunchKernelGGL((k_frame_sp<float, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_frame_sp<float, 2>), g, b, 0, s, a);
+    }
     return (int)hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# algorithmic words per interior point of each kernel launch:
+# algorithmic words per updated point of each kernel launch (each field read or
+# written once per sweep):
 #   first sweep : u, v in (4) + 11 coefficient fields + a1, a2 out (4)
 #   second sweep: a1, a2 in (4) + 11 coefficients + u, v in (4) + u, v out (4)
 #   apply       : u in (2) + 11 coefficients + a out (2)
@@ -137,6 +138,12 @@ def copy_probe(mib):
     del src, dst
 
 
+def swept_points(plan):
+    """Points whose update the timed 'interior' launch performs: a one-launch
+    sweep also updates the frame points."""
+    return plan['interior_points'] + (plan['frame_points'] if plan['fused_sweep'] else 0)
+
+
 def dominant(res):
     best, kind = -1.0, None
     for k, (ms, cnt) in res['kernels'].items():
@@ -203,8 +210,8 @@ def main():
         return
     world = int(os.environ.get('WORLD_SIZE', '1'))
     if args.gpus != 1 or world != 1:
-        print('this build measures one GPU only: run bench.py with --gpus 1 (the multi-GPU '
-              'sharding by blocks is described in DESIGN.md, not implemented)', file=sys.stderr)
+        print('bench.py measures one GPU only: run it with --gpus 1 (sharding the blocks over '
+              'several GPUs is not implemented)', file=sys.stderr)
         sys.exit(2)
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
@@ -217,7 +224,7 @@ def main():
     log('fp32 run')
     r32 = run_gpu(spec, 'f32', args.steps, args.warmup, apply_reps=50)
     log('  %.3f ms/step, %.3e updates/s' % (r32['ms_per_step'], r32['updates_per_s']))
-    pts = r64['plan']['interior_points']
+    pts = swept_points(r64['plan'])
     k = dominant(r64)
     line = {
         "metric": "grid-point updates/s", "value": r64['updates_per_s'], "unit": "grid-point updates/s",
@@ -245,7 +252,7 @@ def main():
         k3 = dominant(r3)
         line["large"] = {"workload": "2x2 blocks of %d^2 with interfaces, FP32" % args.large_n,
                          "value": r3['updates_per_s'], "ms_per_step": r3['ms_per_step'],
-                         "roofline": roofline(k3, r3['kernels'][k3][0], r3['plan']['interior_points'], 4),
+                         "roofline": roofline(k3, r3['kernels'][k3][0], swept_points(r3['plan']), 4),
                          "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]}}
         log('  %.3f ms/step, %.3e updates/s' % (r3['ms_per_step'], r3['updates_per_s']))
     if not args.no_serve:

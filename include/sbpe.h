@@ -180,9 +180,12 @@ sbpe_status sbpe_synchronize(sbpe_ctx_t ctx);
 sbpe_status sbpe_set_kernel_timing(sbpe_ctx_t ctx, int enable);
 sbpe_status sbpe_get_kernel_timing(sbpe_ctx_t ctx, double* ms_avg, int* count);
 
-/* Launch plan after sbpe_finalize: info[0] = interior points, info[1] = frame
- * points (summed over blocks), info[2] = interior workgroups, info[3] = frame
- * workgroups, info[4] = frame width in points. */
+/* Launch plan after sbpe_finalize (info holds 6 entries): info[0] = interior
+ * points, info[1] = frame points (summed over blocks), info[2] = interior
+ * workgroups, info[3] = frame workgroups, info[4] = frame width in points,
+ * info[5] = 1 when each sweep is a single launch that also updates the frame
+ * points (then the kernel timing reports it as the interior kind and the frame
+ * kinds stay empty), 0 when frame and interior are separate launches. */
 sbpe_status sbpe_plan_info(sbpe_ctx_t ctx, long long* info);
 
 /* ---------------------------------------------------------------- gradients

@@ -603,8 +603,12 @@ static sbpe_status build_plan(sbpe_ctx* c) {
                 radj.push_back(RecAdj{(int)r, Rv.block, p, wi[d] * wj[a] / (Hp * rt)});
             }
     }
+    // by workgroup, then by point (the interior kernel walks a tile's entries
+    // row by row); entries of one point keep their order
     std::stable_sort(ents.begin(), ents.end(), [](const E2& x, const E2& y) {
-        return x.frame != y.frame ? x.frame < y.frame : x.wg < y.wg;
+        if (x.frame != y.frame) return x.frame < y.frame;
+        if (x.wg != y.wg) return x.wg < y.wg;
+        return x.e.p < y.e.p;
     });
     std::vector<Entry> flat;
     std::vector<Range> tr(std::max(tiles, 1), Range{0, 0}), fr(std::max(fwg, 1), Range{0, 0});
@@ -1618,6 +1622,7 @@ sbpe_status sbpe_plan_info(sbpe_ctx_t c, long long* info) {
     info[2] = c->total_tiles;
     info[3] = c->total_frame_wg;
     info[4] = R;
+    info[5] = (c->frame_sp && sweep_fused(c->total_tiles)) ? 1 : 0;
     return SBPE_OK;
 }
 

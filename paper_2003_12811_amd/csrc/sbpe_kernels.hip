@@ -969,12 +969,23 @@ __device__ __forceinline__ void sto(char* base, unsigned off, T v) {
     *(GLB T*)((GLB char*)base + off) = v;
 }
 
-template <typename T, int NS>
+// Orders the LDS accesses of one wave (the other lanes' writes before the
+// reads that follow) without a workgroup barrier: LDS operations of a wave
+// complete in issue order, so only compiler reordering has to be prevented.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int NS, int NX>
 struct Lead {
     T w[NS];   // input fields at (i, j + H)
     T b2[3];   // x2-narrow coefficients at (i, j + H)
     T m[4];    // mixed coefficients at (i, j + H)
     T b1[3];   // x1-narrow coefficients at (i, j)
+    T pt[3];   // 1/rho~ and the two forcing components at (i, j)
+    T xo[NX > 0 ? NX : 1];   // RK2: the state read back at (i, j)
 };
 
 // SPLIT (RK sweeps): a workgroup of two waves shares the tile; wave w applies
@@ -988,6 +999,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
     constexpr int NW = 2 * HF + 1;
     constexpr int NF = (PASS == PASS_APPLY || SPLIT) ? 1 : 2;
     constexpr int NS = 2 * NF;
+    constexpr int NX = PASS == PASS_RK2 ? (SPLIT ? 2 : 4) : 0;   // state words read back per point
     constexpr int NWAVE = SPLIT ? 2 : 1;
     constexpr int R = Frame<ORD>::R;
     constexpr T C1 = static_cast<T>(O::d1i(HF + 1));
@@ -995,7 +1007,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
     __shared__ T s_xw[NWAVE][NW][NS][64];
     __shared__ T s_bw[NWAVE][3][64];
     __shared__ T s_gw[NWAVE][NS][64];
-    __shared__ T s_l[SPLIT ? 2 : 1][4][64];   // exchange: L (2 components) and centre values of each field
+    __shared__ T s_lb[SPLIT ? 2 : 1][SPLIT ? 2 : 1][4][64];   // exchange (by row parity): L and centre values
     const int wv = SPLIT ? (int)(threadIdx.x >> 6) : 0;
     T(&s_x)[NW][NS][64] = s_xw[wv];
     T(&s_b)[3][64] = s_bw[wv];
@@ -1046,6 +1058,71 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
         tauf_a = static_cast<T>(tval(B, A, B.item_f, ca));
         tauf_b = static_cast<T>(tval(B, A, B.item_f, cb));
     }
+    // Point sources and receivers of the tile, staged once per workgroup (a
+    // source with its amplitudes times the time functions of both weight
+    // sets, a receiver with its interpolation weight), so that the per-row
+    // matching reads LDS instead of a chain of dependent global loads.  A
+    // tile with more entries than fit keeps the global loop.
+    constexpr int MAXE = 32;
+    __shared__ int s_ep[MAXE];
+    __shared__ int s_eid[MAXE];        // receiver slot, or -1 for a source
+    __shared__ double s_ev[MAXE][4];
+    const int ne = rg.end - rg.beg;
+    const bool staged = ne <= MAXE;
+    if (ne > 0 && staged) {
+        for (int k = threadIdx.x; k < ne; k += NWAVE * 64) {
+            const GLB Entry& E = entry(B, rg.beg + k);
+            s_ep[k] = E.p;
+            if (E.kind == 0) {
+                const double ta = tval(B, A, E.id, ca), tb = tval(B, A, E.id, cb);
+                s_eid[k] = -1;
+                s_ev[k][0] = E.c0 * ta;
+                s_ev[k][1] = E.c1 * ta;
+                s_ev[k][2] = E.c0 * tb;
+                s_ev[k][3] = E.c1 * tb;
+            } else {
+                s_eid[k] = E.id;
+                s_ev[k][0] = E.c0;
+            }
+        }
+        __syncthreads();
+    }
+    // The staged entries are sorted by point, so the entries of row j are
+    // the range [e_lo, e_hi), found by a cursor that only moves forward.
+    int e_cur = 0, e_lo = 0, e_hi = 0;
+    auto entry_rows = [&](int j) {
+        if (ne == 0 || !staged) return;
+        const long rs = (long)j * n1, re = rs + n1;
+        while (e_cur < ne && (long)s_ep[e_cur] < rs) ++e_cur;
+        e_lo = e_cur;
+        e_hi = e_cur;
+        while (e_hi < ne && (long)s_ep[e_hi] < re) ++e_hi;
+    };
+    // add the sources at point po with the first (ca) or second (cb) weights
+    auto sources = [&](long po, bool second, T& r0, T& r1) {
+        if (staged) {
+            const int o = second ? 2 : 0;
+            for (int k = e_lo; k < e_hi; ++k)
+                if (s_eid[k] < 0 && (long)s_ep[k] == po) {
+                    r0 += static_cast<T>(s_ev[k][o]);
+                    r1 += static_cast<T>(s_ev[k][o + 1]);
+                }
+        } else {
+            point_sources<T>(B, A, rg, po, second ? cb : ca, r0, r1);
+        }
+    };
+    // receiver slots of point po, component q
+    auto record = [&](gp<double> ro, long po, int q, double un) {
+        if (staged) {
+            for (int k = e_lo; k < e_hi; ++k)
+                if (s_eid[k] >= 0 && (long)s_ep[k] == po) ro[2 * s_eid[k] + q] = s_ev[k][0] * un;
+        } else {
+            for (int e = rg.beg; e < rg.end; ++e) {
+                const GLB Entry& E = entry(B, e);
+                if (E.kind == 1 && E.p == po) ro[2 * E.id + q] = E.c0 * un;
+            }
+        }
+    };
     const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
     const T i11 = ih1 * ih1, i22 = ih2 * ih2, i12 = ih1 * ih2;
     const T dt = static_cast<T>(B.dt);
@@ -1055,8 +1132,9 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
         if constexpr (HF == 2) return C1 * (up1 - um1) + C2 * (up2 - um2);
         else return C1 * (up1 - um1);
     };
-    // leading-row loads for output row j
-    auto load_lead = [&](int j, Lead<T, NS>& L) {
+    // loads for output row j: the leading row j + H of the windows and the
+    // per-point operands of row j, issued one row ahead of their use
+    auto load_lead = [&](int j, Lead<T, NS, NX>& L) {
         const int jj = j < je ? j : je;
         const unsigned qn = (unsigned)(jj + HF) * rowb + lo;
         const unsigned qj = (unsigned)jj * rowb + lo;
@@ -1072,6 +1150,18 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
         L.b1[0] = ldo<T>(cf(K_C1111), qj);
         L.b1[1] = ldo<T>(cf(K_C1112), qj);
         L.b1[2] = ldo<T>(cf(K_C1212), qj);
+        L.pt[0] = ldo<T>(cf(K_IRHO), qj);
+        L.pt[1] = ldo<T>(frc, qj);
+        L.pt[2] = ldo<T>(frc + frc1, qj);
+        if constexpr (PASS == PASS_RK2 && SPLIT) {
+            L.xo[0] = ldo<T>((const char*)B.u + wv * fb, qj);
+            L.xo[1] = ldo<T>((const char*)B.v + wv * fb, qj);
+        } else if constexpr (PASS == PASS_RK2) {
+            L.xo[0] = ldo<T>((const char*)B.u, qj);
+            L.xo[1] = ldo<T>((const char*)B.u + fb, qj);
+            L.xo[2] = ldo<T>((const char*)B.v, qj);
+            L.xo[3] = ldo<T>((const char*)B.v + fb, qj);
+        }
     };
 
     // register windows indexed by ring slot: slot(r) = (r - jb + HF) mod NW
@@ -1111,12 +1201,12 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
             mw[2][r] = ldo<T>(cf(K_C1221), q);
             mw[3][r] = ldo<T>(cf(K_C1222), q);
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int r = 0; r < 2 * HF; ++r) e_row(r);
     }
 
-    Lead<T, NS> P;
+    Lead<T, NS, NX> P;
     load_lead(jb, P);
 
     // one output row; K is the position in the unrolled group (slot of row j is K + HF)
@@ -1135,24 +1225,21 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) mw[m][sn] = P.m[m];
         const T b1c[3] = {P.b1[0], P.b1[1], P.b1[2]};
-        // (2) per-point operands of row j, then the leading row of j + 1
+        // (2) per-point operands of row j, then the loads for row j + 1
         const bool live = j <= je;
+        if (live) entry_rows(j);
         const unsigned p = (unsigned)(live ? j : je) * rowb + lo;
-        const T irho = ldo<T>(cf(K_IRHO), p);
-        const T f0 = ldo<T>(frc, p);
-        const T f1 = ldo<T>(frc + frc1, p);
+        const T irho = P.pt[0], f0 = P.pt[1], f1 = P.pt[2];
         T xo[4];
         if constexpr (PASS == PASS_RK2 && SPLIT) {
-            xo[0] = ldo<T>((const char*)B.u + wv * fb, p);
-            xo[2] = ldo<T>((const char*)B.v + wv * fb, p);
+            xo[0] = P.xo[0];
+            xo[2] = P.xo[1];
         } else if constexpr (PASS == PASS_RK2) {
-            xo[0] = ldo<T>((const char*)B.u, p);
-            xo[1] = ldo<T>((const char*)B.u + fb, p);
-            xo[2] = ldo<T>((const char*)B.v, p);
-            xo[3] = ldo<T>((const char*)B.v + fb, p);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xo[k] = P.xo[k];
         }
         load_lead(j + 1, P);
-        __syncthreads();
+        wave_sync();
         // (3) E at the leading row
         e_row(sn);
         // (4) G at row j (all 64 columns) and the narrow x2 term, then the
@@ -1223,7 +1310,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
                 lx[f][1] += (ax2 + ax3) * i11;
             }
         }
-        __syncthreads();
+        wave_sync();
         // (5) D_1 G and D_2 E
         T L[NF][2];
 #pragma unroll
@@ -1237,7 +1324,10 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
         }
         // (6) data, pass arithmetic, stores
         if constexpr (SPLIT) {
-            // exchange L and the centre values of both fields
+            // exchange L and the centre values of both fields; the buffer
+            // alternates with the row, so the next row's writes never meet
+            // this row's reads and one barrier per row suffices
+            T(&s_l)[2][4][64] = s_lb[j & 1];
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 s_l[wv][q][lane] = L[0][q];
@@ -1251,7 +1341,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
                     const W3 cw{wv ? cb.w0 : ca.w0, wv ? cb.w1 : ca.w1, wv ? cb.w2 : ca.w2};
                     const T tf = wv ? tauf_b : tauf_a;
                     T d0 = tf * f0, d1v = tf * f1;
-                    if (rg.end > rg.beg && cw.any()) point_sources<T>(B, A, rg, po, cw, d0, d1v);
+                    if (ne > 0 && cw.any()) sources(po, wv != 0, d0, d1v);
                     const T hdt = wv ? T(0.5) * dt : T(0);
                     char* o = (char*)(wv ? B.a2 : B.a1);
                     sto<T>(o, p, irho * (s_l[0][0][lane] + hdt * L[0][0] + d0));
@@ -1260,7 +1350,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
                     // component q = wv of the RK4 update
                     const int q = wv;
                     T db0 = tauf_b * f0, db1 = tauf_b * f1;
-                    if (rg.end > rg.beg && cb.any()) point_sources<T>(B, A, rg, po, cb, db0, db1);
+                    if (ne > 0 && cb.any()) sources(po, true, db0, db1);
                     const T dt2 = dt * dt;
                     const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
                     const T A1 = s_l[0][2 + q][lane];
@@ -1271,20 +1361,15 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
                     sto<T>((char*)B.u + q * fb, p, un);
                     sto<T>((char*)B.v + q * fb, p, xo[2] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4));
                     gp<double> ro = rec_slots(B, A);
-                    if (ro && rg.end > rg.beg) {
-                        for (int e = rg.beg; e < rg.end; ++e) {
-                            const GLB Entry& E = entry(B, e);
-                            if (E.kind == 1 && E.p == po) ro[2 * E.id + q] = E.c0 * static_cast<double>(un);
-                        }
-                    }
+                    if (ro && ne > 0) record(ro, po, q, static_cast<double>(un));
                 }
             }
         } else if (act && live) {
             const long po = (long)j * n1 + i;
             T da0 = tauf_a * f0, da1 = tauf_a * f1, db0 = tauf_b * f0, db1 = tauf_b * f1;
-            if (rg.end > rg.beg) {
-                if (ca.any()) point_sources<T>(B, A, rg, po, ca, da0, da1);
-                if (NF == 2 && cb.any()) point_sources<T>(B, A, rg, po, cb, db0, db1);
+            if (ne > 0) {
+                if (ca.any()) sources(po, false, da0, da1);
+                if (NF == 2 && cb.any()) sources(po, true, db0, db1);
             }
             if constexpr (PASS == PASS_APPLY) {
                 char* o = (char*)apply_out(A, b);
@@ -1315,18 +1400,13 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
                     sto<T>(v + q * fb, p, xo[2 + q] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4));
                 }
                 gp<double> ro = rec_slots(B, A);
-                if (ro && rg.end > rg.beg) {
-                    for (int e = rg.beg; e < rg.end; ++e) {
-                        const GLB Entry& E = entry(B, e);
-                        if (E.kind == 1 && E.p == po) {
-                            ro[2 * E.id] = E.c0 * static_cast<double>(un[0]);
-                            ro[2 * E.id + 1] = E.c0 * static_cast<double>(un[1]);
-                        }
-                    }
+                if (ro && ne > 0) {
+                    record(ro, po, 0, static_cast<double>(un[0]));
+                    record(ro, po, 1, static_cast<double>(un[1]));
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
     };
 
     // rows past je (at most NW - 1 in the last group) are evaluated on

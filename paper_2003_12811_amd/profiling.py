@@ -35,12 +35,13 @@ def source_hash(path=KERNEL_SOURCE):
 
 def kernel_kind(name):
     """'interior_rk1/f64' style label of a library kernel name, or None."""
-    m = re.search(r'sbpe::k_(march|frame)<(double|float), (\d)(?:, (\d))?>', name)
+    m = re.search(r'sbpe::k_(march|pass|frame_sp|frame)<(double|float), (\d)(?:, (\d))?', name)
     if not m:
         return None
     part, ty, order, p = m.group(1), m.group(2), m.group(3), m.group(4)
     dt = 'f64' if ty == 'double' else 'f32'
-    if part == 'march':
+    if part in ('march', 'pass'):
+        # a one-launch sweep (k_pass) also updates the frame points
         return 'interior_%s/%s/o%s' % (('apply', 'rk1', 'rk2')[int(p)], dt, order)
     return 'frame/%s/o%s' % (dt, order)
 

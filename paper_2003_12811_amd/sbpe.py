@@ -306,10 +306,10 @@ def sbpe_get_kernel_timing(ctx):
 
 
 def sbpe_plan_info(ctx):
-    info = (ctypes.c_longlong * 5)()
+    info = (ctypes.c_longlong * 6)()
     _check(ctx, lib().sbpe_plan_info(ctx, info))
     return dict(interior_points=info[0], frame_points=info[1], interior_workgroups=info[2],
-                frame_workgroups=info[3], frame_width=info[4])
+                frame_workgroups=info[3], frame_width=info[4], fused_sweep=bool(info[5]))
 
 
 # ------------------------------------------------------------------ batches

@@ -603,21 +603,27 @@ static sbpe_status build_plan(sbpe_ctx* c) {
                 radj.push_back(RecAdj{(int)r, Rv.block, p, wi[d] * wj[a] / (Hp * rt)});
             }
     }
-    // by workgroup, then by point (the interior kernel walks a tile's entries
-    // row by row); entries of one point keep their order
+    // by workgroup, then sources before receivers, then by point (the
+    // interior kernel walks a tile's entries row by row); entries of one
+    // point keep their order
     std::stable_sort(ents.begin(), ents.end(), [](const E2& x, const E2& y) {
         if (x.frame != y.frame) return x.frame < y.frame;
         if (x.wg != y.wg) return x.wg < y.wg;
+        if (x.e.kind != y.e.kind) return x.e.kind < y.e.kind;
         return x.e.p < y.e.p;
     });
     std::vector<Entry> flat;
-    std::vector<Range> tr(std::max(tiles, 1), Range{0, 0}), fr(std::max(fwg, 1), Range{0, 0});
+    std::vector<Range> tr(std::max(tiles, 1), Range{0, 0, 0, 0}), fr(std::max(fwg, 1), Range{0, 0, 0, 0});
     for (size_t k = 0; k < ents.size(); ++k) {
         const int idx = (int)flat.size();
         flat.push_back(ents[k].e);
         Range& rg = ents[k].frame ? fr[ents[k].wg] : tr[ents[k].wg];
-        if (rg.end == rg.beg) rg.beg = idx;
+        if (rg.end == rg.beg) {
+            rg.beg = idx;
+            rg.mid = idx;
+        }
         rg.end = idx + 1;
+        if (ents[k].e.kind == 0) rg.mid = idx + 1;
     }
     if (c->host_only) return SBPE_OK;
     if (flat.empty()) flat.push_back(Entry{-1, -1, 0, 0, 0.0, 0.0});

@@ -124,8 +124,10 @@ struct Entry {
     double c0, c1;  // source: amp dir_J w / H (J f contribution); receiver: weight, unused
 };
 
+// Point entries of one workgroup: sources in [beg, mid), receivers in
+// [mid, end), each run sorted by point.
 struct Range {
-    int beg, end;
+    int beg, mid, end, pad;
 };
 
 // Time functions are tabulated per RK4 step by k_tau: tau[(step * nitems + item) * 3 + k]
@@ -155,7 +157,7 @@ struct PassArgs {
 constexpr int TILE_LANES = 64;
 constexpr int TILE_Y_DEFAULT = 10;
 constexpr int FRAME_WG = 256;
-constexpr int FRAME_PTS = 32;   // frame points per workgroup: four waves, two lanes per point in each
+constexpr int FRAME_PTS = 32;   // frame points per group (the unit of the point-entry ranges)
 
 // Coefficient gradient of one RK4 stage (sbpe_grad_accumulate): for every block,
 // gc[b][k] += alpha d/dc_k (z^T H L(c) y) and grt[b] += -alpha H (z . a).

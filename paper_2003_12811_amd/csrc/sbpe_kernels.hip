@@ -51,8 +51,23 @@ __device__ __forceinline__ Range load_range(const Range* base, int k) {
     const GLB Range& r = ((const GLB Range*)base)[k];
     Range o;
     o.beg = r.beg;
+    o.mid = r.mid;
     o.end = r.end;
+    o.pad = 0;
     return o;
+}
+// calls fn(E) for every entry in [beg, end) at point p; the point indices
+// are loaded four at a time so that a long range costs few round trips
+template <typename F>
+__device__ __forceinline__ void entries_at(BlockRef B, int beg, int end, long p, F&& fn) {
+    for (int e = beg; e < end; e += 4) {
+        int pe[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pe[u] = e + u < end ? entry(B, e + u).p : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if ((long)pe[u] == p) fn(entry(B, e + u));
+    }
 }
 
 template <int ORD> struct Op;
@@ -474,6 +489,11 @@ __device__ __forceinline__ void face_sat(const PassArgs& A, int b, int f, int dn
     const int nt = a == 0 ? B.n2 : B.n1;
     const double ht = a == 0 ? B.h2 : B.h1;
     const T iw = T(1.0 / F.w);
+    // the data part of a face without data is zero
+    if (DATA && !(F.kind == BC_DISPLACEMENT ? F.g != nullptr
+                  : F.kind == BC_INTERFACE  ? (F.V != nullptr || F.Th != nullptr)
+                                            : F.g != nullptr))
+        return;
 
     if (F.kind == BC_TRACTION || F.kind == BC_ROBIN) {
         if (dn != 0) return;
@@ -607,14 +627,11 @@ __device__ __forceinline__ void sat_point(const PassArgs& A, int b, int i, int j
 template <typename T>
 __device__ __forceinline__ void point_sources(BlockRef B, const PassArgs& A, const Range& rg, long p, const W3& tc, T& r0,
                                               T& r1) {
-    for (int e = rg.beg; e < rg.end; ++e) {
-        const GLB Entry& E = entry(B, e);
-        if (E.kind == 0 && E.p == p) {
-            const double tau = tval(B, A, E.id, tc);
-            r0 += static_cast<T>(E.c0 * tau);
-            r1 += static_cast<T>(E.c1 * tau);
-        }
-    }
+    entries_at(B, rg.beg, rg.mid, p, [&](const GLB Entry& E) {
+        const double tau = tval(B, A, E.id, tc);
+        r0 += static_cast<T>(E.c0 * tau);
+        r1 += static_cast<T>(E.c1 * tau);
+    });
 }
 
 template <typename T>
@@ -747,12 +764,9 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
     const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
     uu[q] = un;
     vv[q] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
-    if (gp<double> ro = rec_slots(B, A)) {
-        for (int e = rg.beg; e < rg.end; ++e) {
-            const GLB Entry& E = entry(B, e);
-            if (E.kind == 1 && E.p == p) ro[2 * E.id + sub] = E.c0 * static_cast<double>(un);
-        }
-    }
+    if (gp<double> ro = rec_slots(B, A))
+        entries_at(B, rg.mid, rg.end, p,
+                   [&](const GLB Entry& E) { ro[2 * E.id + sub] = E.c0 * static_cast<double>(un); });
 }
 
 // ------------------------------------------------- assembled frame operator
@@ -788,21 +802,29 @@ __global__ void __launch_bounds__(256) k_frame_gather(const T* y, int n1, int n2
     ((gp<T>)out)[2 * k + 1] = ((gcp<T>)y)[np + p];
 }
 
-// Eight lanes per frame point (four per component row).  Frame points are
+// FRAME_LANES lanes per frame point, half per component row.  Frame points are
 // numbered globally in groups of FRAME_PTS per block (the k_frame workgroup
 // layout, so the point-entry ranges carry over); a workgroup of nt threads
-// takes points fwg * nt / 8 .. (fwg + 1) * nt / 8 - 1.
-template <typename T, int ORD>
+// takes points fwg * nt / FRAME_LANES .. (fwg + 1) * nt / FRAME_LANES - 1.
+// Every load that does not depend on the row's entries is issued first, and
+// the row is gathered FRAME_UNROLL entries per lane at a time (all column and
+// weight loads, then all gathers), so a row costs few round trips to memory.
+constexpr int FRAME_LANES = 8;
+constexpr int FRAME_UNROLL = 8;
+
+template <typename T, int ORD, int PASS>
 __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt) {
     constexpr int R = Frame<ORD>::R;
-    const int g = fwg * (nt >> 3) + (int)(threadIdx.x >> 3);
+    constexpr int RL = FRAME_LANES / 2;        // lanes per component row
+    constexpr int U = FRAME_UNROLL;
+    const int g = fwg * (nt / FRAME_LANES) + (int)(threadIdx.x / FRAME_LANES);
     const int wg = g / FRAME_PTS;
-    if (wg >= A.total_frame_wg) return;        // whole 8-lane groups leave together
+    if (wg >= A.total_frame_wg) return;        // whole point groups leave together
     const int b = find_block(A, wg, true);
     BlockRef B = blk(A, b);
-    const int lane = threadIdx.x & 7;          // lane within the point
-    const int q = lane >> 2;                   // component row
-    const int sl = lane & 3;                   // lane within the row
+    const int lane = threadIdx.x & (FRAME_LANES - 1);   // lane within the point
+    const int q = lane / RL;                   // component row
+    const int sl = lane & (RL - 1);            // lane within the row
     const int k = (wg - B.frame_beg) * FRAME_PTS + g % FRAME_PTS;
     const Range rg = load_range(B.frame_rng, wg - B.frame_beg);
     const int n1 = B.n1, n2 = B.n2;
@@ -811,44 +833,82 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
     int i, j;
     frame_ij(valid ? k : 0, n1, n2, R, i, j);
     const long p = (long)j * n1 + i;
-    const bool apply = A.pass == PASS_APPLY;
-    constexpr int NFMAX = 2;
-    const int nf = apply ? 1 : 2;
+    constexpr bool apply = PASS == PASS_APPLY;
+    constexpr int NF = apply ? 1 : 2;
     // input fields of the sweep (own block) and their values at the point
-    gcp<T> xf[NFMAX];
-    if (apply) {
+    gcp<T> xf[NF];
+    if constexpr (apply) {
         xf[0] = gc<T>(apply_in(A, b));
-        xf[1] = xf[0];
-    } else if (A.pass == PASS_RK1) {
+    } else if constexpr (PASS == PASS_RK1) {
         xf[0] = gc<T>(B.u);
         xf[1] = gc<T>(B.v);
     } else {
         xf[0] = gc<T>(B.a1);
         xf[1] = gc<T>(B.a2);
     }
-    T acc[NFMAX] = {T(0), T(0)};
-    T xp[NFMAX][2];
+    T xp[NF][2];
 #pragma unroll
-    for (int f = 0; f < NFMAX; ++f) {
-        xp[f][0] = valid ? xf[f][p] : T(0);
-        xp[f][1] = valid ? xf[f][np + p] : T(0);
+    for (int f = 0; f < NF; ++f) {
+        xp[f][0] = xf[f][p];
+        xp[f][1] = xf[f][np + p];
     }
+    // per-point operands of the pass arithmetic, issued before the row
+    const long qp = (long)q * np + p;
+    const T irho = gc<T>(B.coef)[(long)K_IRHO * np + p];
+    gcp<T> rs = gc<T>(B.fr_rsum);
+    const long ridx = valid ? 2 * (2 * (long)k + q) : 0;
+    const T s0 = rs[ridx], s1 = rs[ridx + 1];
+    T A1 = 0, A2 = 0, uo = 0, vo = 0;
+    if constexpr (PASS == PASS_RK2) {
+        A1 = gc<T>(B.a1)[qp];
+        A2 = gc<T>(B.a2)[qp];
+        uo = gc<T>(B.u)[qp];
+        vo = gc<T>(B.v)[qp];
+    }
+    T acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = T(0);
     if (valid) {
         const int row = 2 * k + q;
         const GLB int* rp = (const GLB int*)B.fr_rowptr;
         const GLB int* cl = (const GLB int*)B.fr_col;
         gcp<T> vl = gc<T>(B.fr_val);
         const int e0 = rp[row], e1 = rp[row + 1];
-        for (int e = e0 + sl; e < e1; e += 4) {
-            const int c = cl[e];
-            const T w = vl[e];
-            if (c >= 0) {
-                const int qq = c & 1;
-                const long pp = c >> 1;
+        bool partner = false;
+        for (int e = e0 + sl; e < e1; e += RL * U) {
+            int cc[U];
+            T ww[U];
 #pragma unroll
-                for (int f = 0; f < NFMAX; ++f)
-                    if (f < nf) acc[f] += w * (xf[f][qq * np + pp] - xp[f][qq]);
-            } else {
+            for (int u = 0; u < U; ++u) {
+                const int ee = e + RL * u;
+                const int ec = ee < e1 ? ee : e0;          // e0 < e1 here: a valid entry
+                cc[u] = cl[ec];
+                ww[u] = vl[ec];
+            }
+            T xv[U][NF];
+            int qq[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = e + RL * u < e1;
+                const int c = cc[u];
+                partner |= in && c < 0;
+                if (!(in && c >= 0)) ww[u] = T(0);
+                qq[u] = c >= 0 ? (c & 1) : 0;
+                const long ix = c >= 0 ? (long)qq[u] * np + (c >> 1) : p;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) xv[u][f] = xf[f][ix];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int f = 0; f < NF; ++f) acc[f] += ww[u] * (xv[u][f] - (qq[u] ? xp[f][1] : xp[f][0]));
+        }
+        if (partner) {
+            // columns in a partner block across an interface
+            for (int e = e0 + sl; e < e1; e += RL) {
+                const int c = cl[e];
+                if (c >= 0) continue;
+                const T w = vl[e];
                 const int v = -1 - c;
                 const int ff = v >> 29, qq = (v >> 28) & 1;
                 const long pp = v & ((1 << 28) - 1);
@@ -856,11 +916,10 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
                 const int pb = F.partner;
                 BlockRef P = blk(A, pb);
                 const long npp = (long)P.n1 * P.n2;
-                gcp<T> pf[NFMAX];
-                if (apply) {
+                gcp<T> pf[NF];
+                if constexpr (apply) {
                     pf[0] = gc<T>(apply_in(A, pb));
-                    pf[1] = pf[0];
-                } else if (A.pass == PASS_RK1) {
+                } else if constexpr (PASS == PASS_RK1) {
                     pf[0] = gc<T>(P.u);
                     pf[1] = gc<T>(P.v);
                 } else {
@@ -868,78 +927,62 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
                     pf[1] = gc<T>(P.a2);
                 }
 #pragma unroll
-                for (int f = 0; f < NFMAX; ++f)
-                    if (f < nf) acc[f] += w * (pf[f][qq * npp + pp] - xp[f][qq]);
+                for (int f = 0; f < NF; ++f) acc[f] += w * (pf[f][qq * npp + pp] - xp[f][qq]);
             }
         }
     }
-    // reduce the four lanes of the row
+    // reduce the lanes of the row
 #pragma unroll
-    for (int f = 0; f < NFMAX; ++f) {
-        acc[f] += __shfl_xor(acc[f], 1);
-        acc[f] += __shfl_xor(acc[f], 2);
-    }
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int m = 1; m < RL; m <<= 1) acc[f] += __shfl_xor(acc[f], m);
     if (valid) {
-        gcp<T> rs = gc<T>(B.fr_rsum);
-        const T s0 = rs[2 * (2 * k + q)], s1 = rs[2 * (2 * k + q) + 1];
 #pragma unroll
-        for (int f = 0; f < NFMAX; ++f) acc[f] += s0 * xp[f][0] + s1 * xp[f][1];
+        for (int f = 0; f < NF; ++f) acc[f] += s0 * xp[f][0] + s1 * xp[f][1];
     }
-    // data: lane 0 of the point with the first weights, lane 4 with the second
+    // data: lane 0 of the point with the first weights, lane RL with the second
     const W3 ca = weights_a(A), cb = weights_b(A, B);
     T d0 = 0, d1 = 0;
-    if (valid && (lane == 0 || (lane == 4 && !apply))) {
+    if (valid && (lane == 0 || (lane == RL && !apply))) {
         const W3 cw{lane ? cb.w0 : ca.w0, lane ? cb.w1 : ca.w1, lane ? cb.w2 : ca.w2};
         if (cw.any()) {
-            const int fld = apply ? FLD_IN : (A.pass == PASS_RK1 ? FLD_U : FLD_A1);
+            const int fld = apply ? FLD_IN : (PASS == PASS_RK1 ? FLD_U : FLD_A1);
             sat_point<T, ORD, true>(A, b, i, j, fld, cw, d0, d1);
             point_data<T>(B, p, A, rg, cw, d0, d1);
         }
     }
-    // broadcast the data of lanes 0 and 4 to the point's lanes
-    const int base = threadIdx.x & ~7;
+    // broadcast the data of lanes 0 and RL to the point's lanes
+    const int base = threadIdx.x & ~(FRAME_LANES - 1);
     const T da0 = __shfl(d0, base), da1 = __shfl(d1, base);
-    const T db0 = __shfl(d0, base + 4), db1 = __shfl(d1, base + 4);
-    // the other row's results (component 1 - q)
-    T oth[NFMAX];
-#pragma unroll
-    for (int f = 0; f < NFMAX; ++f) oth[f] = __shfl_xor(acc[f], 4);
+    const T db0 = __shfl(d0, base + RL), db1 = __shfl(d1, base + RL);
     if (!valid || sl != 0) return;
-    const T irho = gc<T>(B.coef)[(long)K_IRHO * np + p];
-    const long qp = (long)q * np + p;
     const T da = q ? da1 : da0, db = q ? db1 : db0;
-    (void)oth;
-    if (apply) {
+    if constexpr (apply) {
         gm<T>(apply_out(A, b))[qp] = acc[0] + irho * da;
         return;
     }
     const T dt = static_cast<T>(B.dt);
-    if (A.pass == PASS_RK1) {
+    if constexpr (PASS == PASS_RK1) {
         gm<T>(B.a1)[qp] = acc[0] + irho * da;
-        gm<T>(B.a2)[qp] = acc[0] + T(0.5) * dt * acc[1] + irho * db;
+        gm<T>(B.a2)[qp] = acc[0] + T(0.5) * dt * acc[NF - 1] + irho * db;
         return;
     }
-    const T A1 = gc<T>(B.a1)[qp], A2 = gc<T>(B.a2)[qp];
     gp<T> uu = gm<T>(B.u);
     gp<T> vv = gm<T>(B.v);
     const T dt2 = dt * dt;
     const T A3 = A2 + T(0.25) * dt2 * acc[0];
-    const T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * (acc[1] + irho * db);
-    const T uo = uu[qp], vo = vv[qp];
+    const T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * (acc[NF - 1] + irho * db);
     const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
     uu[qp] = un;
     vv[qp] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);
-    if (gp<double> ro = rec_slots(B, A)) {
-        for (int e = rg.beg; e < rg.end; ++e) {
-            const GLB Entry& E = entry(B, e);
-            if (E.kind == 1 && E.p == p) ro[2 * E.id + q] = E.c0 * static_cast<double>(un);
-        }
-    }
+    if (gp<double> ro = rec_slots(B, A))
+        entries_at(B, rg.mid, rg.end, p,
+                   [&](const GLB Entry& E) { ro[2 * E.id + q] = E.c0 * static_cast<double>(un); });
 }
 
-template <typename T, int ORD>
+template <typename T, int ORD, int PASS>
 __global__ void __launch_bounds__(FRAME_WG) k_frame_sp(PassArgs A) {
-    frame_sp_body<T, ORD>(A, blockIdx.x, FRAME_WG);
+    frame_sp_body<T, ORD, PASS>(A, blockIdx.x, FRAME_WG);
 }
 
 // ------------------------------------------------------------- interior
@@ -1068,6 +1111,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
     __shared__ int s_eid[MAXE];        // receiver slot, or -1 for a source
     __shared__ double s_ev[MAXE][4];
     const int ne = rg.end - rg.beg;
+    const int ns = rg.mid - rg.beg;      // sources first, then receivers
     const bool staged = ne <= MAXE;
     if (ne > 0 && staged) {
         for (int k = threadIdx.x; k < ne; k += NWAVE * 64) {
@@ -1087,23 +1131,26 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
         }
         __syncthreads();
     }
-    // The staged entries are sorted by point, so the entries of row j are
-    // the range [e_lo, e_hi), found by a cursor that only moves forward.
-    int e_cur = 0, e_lo = 0, e_hi = 0;
+    // Both staged runs are sorted by point, so the sources of row j are
+    // [s_lo, s_hi) and its receivers [r_lo, r_hi), found by cursors that only
+    // move forward.
+    int s_lo = 0, s_hi = 0, r_lo = ns, r_hi = ns;
     auto entry_rows = [&](int j) {
         if (ne == 0 || !staged) return;
         const long rs = (long)j * n1, re = rs + n1;
-        while (e_cur < ne && (long)s_ep[e_cur] < rs) ++e_cur;
-        e_lo = e_cur;
-        e_hi = e_cur;
-        while (e_hi < ne && (long)s_ep[e_hi] < re) ++e_hi;
+        while (s_lo < ns && (long)s_ep[s_lo] < rs) ++s_lo;
+        s_hi = s_lo;
+        while (s_hi < ns && (long)s_ep[s_hi] < re) ++s_hi;
+        while (r_lo < ne && (long)s_ep[r_lo] < rs) ++r_lo;
+        r_hi = r_lo;
+        while (r_hi < ne && (long)s_ep[r_hi] < re) ++r_hi;
     };
     // add the sources at point po with the first (ca) or second (cb) weights
     auto sources = [&](long po, bool second, T& r0, T& r1) {
         if (staged) {
             const int o = second ? 2 : 0;
-            for (int k = e_lo; k < e_hi; ++k)
-                if (s_eid[k] < 0 && (long)s_ep[k] == po) {
+            for (int k = s_lo; k < s_hi; ++k)
+                if ((long)s_ep[k] == po) {
                     r0 += static_cast<T>(s_ev[k][o]);
                     r1 += static_cast<T>(s_ev[k][o + 1]);
                 }
@@ -1114,13 +1161,10 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
     // receiver slots of point po, component q
     auto record = [&](gp<double> ro, long po, int q, double un) {
         if (staged) {
-            for (int k = e_lo; k < e_hi; ++k)
-                if (s_eid[k] >= 0 && (long)s_ep[k] == po) ro[2 * s_eid[k] + q] = s_ev[k][0] * un;
+            for (int k = r_lo; k < r_hi; ++k)
+                if ((long)s_ep[k] == po) ro[2 * s_eid[k] + q] = s_ev[k][0] * un;
         } else {
-            for (int e = rg.beg; e < rg.end; ++e) {
-                const GLB Entry& E = entry(B, e);
-                if (E.kind == 1 && E.p == po) ro[2 * E.id + q] = E.c0 * un;
-            }
+            entries_at(B, rg.mid, rg.end, po, [&](const GLB Entry& E) { ro[2 * E.id + q] = E.c0 * un; });
         }
     };
     const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
@@ -1424,13 +1468,14 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
 
 // One sweep in one launch: the first nframe workgroups (a multiple of 8, so
 // that the interior workgroups keep their position among the 8 XCDs) apply the
-// assembled frame operator, the others march over interior tiles.
+// assembled frame operator, the others march over interior tiles.  The frame
+// workgroups go first: their chains of dependent loads are long, and started
+// last they would set the end of the launch (spreading them evenly among the
+// tiles measured slower).
 template <typename T, int ORD, int PASS, bool SPLIT>
 __global__ void __launch_bounds__(SPLIT ? 128 : 64) k_pass(PassArgs A, int nframe) {
-    // frame workgroups first: they are few and slower per point, so they start
-    // before the interior tiles fill the machine
     const int bid = (int)blockIdx.x;
-    if (bid < nframe) frame_sp_body<T, ORD>(A, bid, SPLIT ? 128 : 64);
+    if (bid < nframe) frame_sp_body<T, ORD, PASS>(A, bid, SPLIT ? 128 : 64);
     else march_body<T, ORD, PASS, SPLIT>(A, bid - nframe);
 }
 
@@ -1838,9 +1883,10 @@ template <typename T, int ORD>
 static void launch_pass_t(const PassArgs& a, int total_tiles, int total_frame_wg, hipStream_t s) {
     const bool split = a.pass != PASS_APPLY && split_tiles(total_tiles);
     const int nt = split ? 128 : 64;
-    // frame workgroups (nt / 8 points each), rounded to whole XCD rounds
+    // frame workgroups (nt / FRAME_LANES points each), rounded to whole XCD rounds
     const long fpts = (long)total_frame_wg * FRAME_PTS;
-    const int nframe = (int)(((fpts + nt / 8 - 1) / (nt / 8) + 7) / 8 * 8);
+    const int ppw = nt / FRAME_LANES;
+    const int nframe = (int)(((fpts + ppw - 1) / ppw + 7) / 8 * 8);
     const dim3 g(nframe + ((total_tiles + 7) / 8) * 8), bl(nt);
     if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_pass<T, ORD, PASS_APPLY, false>), g, bl, 0, s, a, nframe);
     else if (a.pass == PASS_RK1 && split) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK1, true>), g, bl, 0, s, a, nframe);
@@ -1973,18 +2019,26 @@ int launch_frame_gather(int dtype, const void* y, int n1, int n2, int R, int fra
     return (int)hipGetLastError();
 }
 
+template <typename T, int ORD>
+static void launch_frame_sp_t(const PassArgs& a, dim3 g, dim3 b, hipStream_t s) {
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_frame_sp<T, ORD, PASS_APPLY>), g, b, 0, s, a);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_frame_sp<T, ORD, PASS_RK1>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_frame_sp<T, ORD, PASS_RK2>), g, b, 0, s, a);
+}
+
 int launch_frame_sp(int dtype, int order, const PassArgs& a0, int total_frame_wg, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (total_frame_wg <= 0) return 0;
     PassArgs a = a0;
     a.total_frame_wg = total_frame_wg;
-    const dim3 g(total_frame_wg), b(FRAME_WG);
+    const long pts = (long)total_frame_wg * FRAME_PTS;
+    const dim3 g((unsigned)((pts + FRAME_WG / FRAME_LANES - 1) / (FRAME_WG / FRAME_LANES))), b(FRAME_WG);
     if (dtype == 0) {
-        if (order == 4) hipLaunchKernelGGL((k_frame_sp<double, 4>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_frame_sp<double, 2>), g, b, 0, s, a);
+        if (order == 4) launch_frame_sp_t<double, 4>(a, g, b, s);
+        else launch_frame_sp_t<double, 2>(a, g, b, s);
     } else {
-        if (order == 4) hipLaunchKernelGGL((k_frame_sp<float, 4>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_frame_sp<float, 2>), g, b, 0, s, a);
+        if (order == 4) launch_frame_sp_t<float, 4>(a, g, b, s);
+        else launch_frame_sp_t<float, 2>(a, g, b, s);
     }
     return (int)hipGetLastError();
 }

@@ -199,7 +199,9 @@ def main():
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
     ap.add_argument('--no-gradient', action='store_true')
-    ap.add_argument('--serve-shots', type=int, default=32)
+    ap.add_argument('--serve-shots', type=int, default=48)
+    ap.add_argument('--serve-rate', type=float, default=200.0,
+                    help='mean arrival rate of the served stream (shots/s); the default saturates the GPU')
     ap.add_argument('--serve-steps', type=int, default=300)
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='first run a plain device-to-device copy of this many MiB (calibrates '
@@ -258,7 +260,8 @@ def main():
     if not args.no_serve:
         from paper_2003_12811_amd import serve
         log('served stream vs sequential plain solves')
-        line["serving"] = serve.serve_and_compare(args.serve_shots, 20.0, [257, 513, 1025], args.serve_steps)
+        line["serving"] = serve.serve_and_compare(args.serve_shots, args.serve_rate, [257, 513, 1025],
+                                                  args.serve_steps)
     if not args.no_gradient:
         log('misfit gradient (513^2, 2000 steps, checkpoints every 100)')
         line["gradient"] = gradient_timing()

@@ -1082,8 +1082,28 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
     auto val = [&](int b, long idx) -> double {
         return c->dtype == SBPE_F64 ? static_cast<double*>(Hh[b])[idx] : (double)static_cast<float*>(Hh[b])[idx];
     };
-    // one probe: fill (bp = -1: every block), frame kernel, gather to the host
-    auto probe = [&](int bp, int comp, int cx, int cy, int period) -> sbpe_status {
+    // Probes: for every block bp, component and colour (cx, cy), unit vectors
+    // of that colour in block bp (zero elsewhere), the frame kernel, and the
+    // frame outputs of every block gathered into slice pi of one device
+    // buffer; then the two constant probes (row sums).  Everything is
+    // enqueued first and copied to the host once.
+    const int NPC = nb * 2 * P * P;
+    const int NPR = NPC + 2;
+    std::vector<void*> Ga(nb, nullptr);
+    std::vector<std::vector<char>> Ha(nb);
+    auto cleanup_all = [&]() {
+        for (int b = 0; b < nb; ++b) (void)hipFree(Ga[b]);
+        cleanup();
+    };
+    for (int b = 0; b < nb; ++b) {
+        const size_t bytes = (size_t)NPR * 2 * (size_t)std::max(c->desc[b].frame_n, 1) * es;
+        if (hipMalloc(&Ga[b], bytes) != hipSuccess) {
+            cleanup_all();
+            return fail(c, SBPE_ENOMEM, "frame operator assembly buffers");
+        }
+        Ha[b].resize(bytes);
+    }
+    auto probe = [&](int pi, int bp, int comp, int cx, int cy, int period) -> sbpe_status {
         for (int b = 0; b < nb; ++b) {
             const HostBlock& H = c->blocks[b];
             const int e = launch_probe_fill(c->dtype, X[b], H.n1, H.n2, (bp < 0 || bp == b) ? comp : -1, cx, cy,
@@ -1095,135 +1115,133 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
         for (int b = 0; b < nb; ++b) {
             const HostBlock& H = c->blocks[b];
             const int fn = c->desc[b].frame_n;
-            e = launch_frame_gather(c->dtype, Y[b], H.n1, H.n2, R, fn, G[b], c->stream);
+            char* dst = static_cast<char*>(Ga[b]) + (size_t)pi * 2 * (size_t)fn * es;
+            e = launch_frame_gather(c->dtype, Y[b], H.n1, H.n2, R, fn, dst, c->stream);
             if (e) return fail(c, SBPE_EHIP, std::string("probe gather: ") + hip_error_string(e));
-            HIPCHECK(c, hipMemcpyAsync(Hh[b], G[b], 2 * (size_t)fn * es, hipMemcpyDeviceToHost, c->stream));
         }
-        HIPCHECK(c, hipStreamSynchronize(c->stream));
         return SBPE_OK;
     };
-    // per block: row entries and row sums
-    std::vector<std::vector<std::vector<std::pair<int, double>>>> rows(nb);
-    std::vector<std::vector<double>> rsum(nb);
-    for (int b = 0; b < nb; ++b) {
-        rows[b].resize(2 * (size_t)c->desc[b].frame_n);
-        rsum[b].assign(4 * (size_t)c->desc[b].frame_n, 0.0);
-    }
-    bool bad = false;
-    for (int bp = 0; bp < nb && !bad; ++bp)
-        for (int comp = 0; comp < 2 && !bad; ++comp)
-            for (int cy = 0; cy < P && !bad; ++cy)
-                for (int cx = 0; cx < P && !bad; ++cx) {
-                    st = probe(bp, comp, cx, cy, P);
-                    if (st) {
-                        cleanup();
-                        return st;
-                    }
-                    for (int b = 0; b < nb; ++b) {
-                        const HostBlock& H = c->blocks[b];
-                        // faces of b across which block bp is the partner
-                        int pf_of[4] = {-1, -1, -1, -1};
-                        bool any = b == bp;
-                        for (int f = 0; f < 4; ++f)
-                            if (H.face[f].kind == BC_INTERFACE && H.face[f].partner == bp) {
-                                pf_of[f] = 1;
-                                any = true;
-                            }
-                        if (!any) continue;
-                        const int fn = c->desc[b].frame_n;
-                        const HostBlock& Pb = c->blocks[bp];
-#pragma omp parallel for schedule(static)
-                        for (int k = 0; k < fn; ++k) {
-                            int i, j;
-                            frame_ij(k, H.n1, H.n2, R, i, j);
-                            for (int q = 0; q < 2; ++q) {
-                                const double v = val(b, 2L * k + q);
-                                if (v == 0.0) continue;
-                                int col = 0;
-                                bool ok = false;
-                                if (b == bp) {
-                                    const int ii = probe_window(i, H.n1, cx), jj = probe_window(j, H.n2, cy);
-                                    if (ii >= 0 && jj >= 0) {
-                                        col = 2 * (jj * H.n1 + ii) + comp;
-                                        ok = true;
-                                    }
-                                } else {
-                                    for (int f = 0; f < 4 && !ok; ++f) {
-                                        if (pf_of[f] < 0) continue;
-                                        const int dn = f == 0 ? i : f == 1 ? H.n1 - 1 - i : f == 2 ? j : H.n2 - 1 - j;
-                                        if (dn >= reach) continue;
-                                        const HostFace& F = H.face[f];
-                                        const int t = f < 2 ? j : i;
-                                        const int nf = f < 2 ? H.n2 : H.n1;
-                                        const int tp = F.reversed ? nf - 1 - t : t;
-                                        int ip, jp;
-                                        if (F.pface < 2) {
-                                            ip = F.pface == 0 ? 0 : Pb.n1 - 1;
-                                            jp = tp;
-                                        } else {
-                                            ip = tp;
-                                            jp = F.pface == 2 ? 0 : Pb.n2 - 1;
-                                        }
-                                        const int ii = probe_window(ip, Pb.n1, cx), jj = probe_window(jp, Pb.n2, cy);
-                                        if (ii >= 0 && jj >= 0) {
-                                            col = -1 - ((f << 29) | (comp << 28) | (jj * Pb.n1 + ii));
-                                            ok = true;
-                                        }
-                                    }
-                                }
-                                if (!ok) {
-#pragma omp critical
-                                    bad = true;
-                                    continue;
-                                }
-                                rows[b][2 * (size_t)k + q].emplace_back(col, v);
-                            }
-                        }
-                    }
-                }
-    if (bad) {
-        cleanup();
-        return fail(c, SBPE_EHIP, "frame operator assembly: a frame row reaches beyond the probe window");
-    }
-    for (int comp = 0; comp < 2; ++comp) {
-        st = probe(-1, comp, 0, 0, 0);
+    {
+        int pi = 0;
+        for (int bp = 0; bp < nb && !st; ++bp)
+            for (int comp = 0; comp < 2 && !st; ++comp)
+                for (int cy = 0; cy < P && !st; ++cy)
+                    for (int cx = 0; cx < P && !st; ++cx) st = probe(pi++, bp, comp, cx, cy, P);
+        for (int comp = 0; comp < 2 && !st; ++comp) st = probe(NPC + comp, -1, comp, 0, 0, 0);
         if (st) {
-            cleanup();
+            cleanup_all();
             return st;
         }
         for (int b = 0; b < nb; ++b)
-            for (int k = 0; k < c->desc[b].frame_n; ++k)
-                for (int q = 0; q < 2; ++q) rsum[b][2 * (2 * (size_t)k + q) + comp] = val(b, 2L * k + q);
+            if (hipMemcpyAsync(Ha[b].data(), Ga[b], Ha[b].size(), hipMemcpyDeviceToHost, c->stream) != hipSuccess) {
+                cleanup_all();
+                return fail(c, SBPE_EHIP, "frame operator probe copy");
+            }
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            cleanup_all();
+            return fail(c, SBPE_EHIP, "frame operator probes");
+        }
     }
-    // CSR upload
-    for (int b = 0; b < nb; ++b) {
-        HostBlock& H = c->blocks[b];
-        const size_t nr = rows[b].size();
-        std::vector<int> rp(nr + 1, 0), cl;
-        std::vector<double> vv;
-        for (size_t r = 0; r < nr; ++r) {
-            std::sort(rows[b][r].begin(), rows[b][r].end());
-            rp[r + 1] = rp[r] + (int)rows[b][r].size();
-            for (auto& e : rows[b][r]) {
-                cl.push_back(e.first);
-                vv.push_back(e.second);
+    // value of frame row r (2 k + q) of block b in probe pi
+    auto hv = [&](int b, int pi, long r) -> double {
+        const size_t idx = (size_t)pi * 2 * (size_t)c->desc[b].frame_n + (size_t)r;
+        return c->dtype == SBPE_F64 ? reinterpret_cast<const double*>(Ha[b].data())[idx]
+                                    : (double)reinterpret_cast<const float*>(Ha[b].data())[idx];
+    };
+    // column of the unit vector of probe pi that row (b; i, j) sees, or false
+    // if none of its window does (a row reaching beyond the probing period)
+    auto column = [&](int b, int i, int j, int pi, int& col) -> bool {
+        const int bp = pi / (2 * P * P), comp = (pi / (P * P)) % 2, cy = (pi / P) % P, cx = pi % P;
+        const HostBlock& H = c->blocks[b];
+        if (b == bp) {
+            const int ii = probe_window(i, H.n1, cx), jj = probe_window(j, H.n2, cy);
+            if (ii < 0 || jj < 0) return false;
+            col = 2 * (jj * H.n1 + ii) + comp;
+            return true;
+        }
+        const HostBlock& Pb = c->blocks[bp];
+        for (int f = 0; f < 4; ++f) {
+            const HostFace& F = H.face[f];
+            if (F.kind != BC_INTERFACE || F.partner != bp) continue;
+            const int dn = f == 0 ? i : f == 1 ? H.n1 - 1 - i : f == 2 ? j : H.n2 - 1 - j;
+            if (dn >= reach) continue;
+            const int t = f < 2 ? j : i;
+            const int nf = f < 2 ? H.n2 : H.n1;
+            const int tp = F.reversed ? nf - 1 - t : t;
+            int ip, jp;
+            if (F.pface < 2) {
+                ip = F.pface == 0 ? 0 : Pb.n1 - 1;
+                jp = tp;
+            } else {
+                ip = tp;
+                jp = F.pface == 2 ? 0 : Pb.n2 - 1;
+            }
+            const int ii = probe_window(ip, Pb.n1, cx), jj = probe_window(jp, Pb.n2, cy);
+            if (ii >= 0 && jj >= 0) {
+                col = -1 - ((f << 29) | (comp << 28) | (jj * Pb.n1 + ii));
+                return true;
             }
         }
-        if (cl.empty()) {
-            cl.push_back(0);
-            vv.push_back(0.0);
+        return false;
+    };
+    // CSR per block: count the nonzeros of each row, then fill each row in
+    // probe order and sort it by column
+    bool bad = false;
+    for (int b = 0; b < nb && !bad; ++b) {
+        HostBlock& H = c->blocks[b];
+        const int fn = c->desc[b].frame_n;
+        const long nr = 2L * fn;
+        std::vector<int> rp(nr + 1, 0);
+#pragma omp parallel for schedule(static)
+        for (long r = 0; r < nr; ++r) {
+            int cnt = 0;
+            for (int pi = 0; pi < NPC; ++pi) cnt += hv(b, pi, r) != 0.0;
+            rp[r + 1] = cnt;
         }
+        for (long r = 0; r < nr; ++r) rp[r + 1] += rp[r];
+        std::vector<int> cl(std::max(rp[nr], 1), 0);
+        std::vector<double> vv(std::max(rp[nr], 1), 0.0);
+        std::vector<double> rs(4 * (size_t)std::max(fn, 1), 0.0);
+#pragma omp parallel
+        {
+            std::vector<std::pair<int, double>> row;
+#pragma omp for schedule(static)
+            for (long r = 0; r < nr; ++r) {
+                const int k = (int)(r / 2);
+                int i, j;
+                frame_ij(k, H.n1, H.n2, R, i, j);
+                row.clear();
+                for (int pi = 0; pi < NPC; ++pi) {
+                    const double v = hv(b, pi, r);
+                    if (v == 0.0) continue;
+                    int col = 0;
+                    if (!column(b, i, j, pi, col)) {
+#pragma omp critical
+                        bad = true;
+                        continue;
+                    }
+                    row.emplace_back(col, v);
+                }
+                std::sort(row.begin(), row.end());
+                for (size_t e = 0; e < row.size(); ++e) {
+                    cl[rp[r] + e] = row[e].first;
+                    vv[rp[r] + e] = row[e].second;
+                }
+                for (int comp = 0; comp < 2; ++comp) rs[2 * r + comp] = hv(b, NPC + comp, r);
+            }
+        }
+        if (bad) break;
         if (hipMalloc(&H.d_fr_rowptr, rp.size() * sizeof(int)) != hipSuccess ||
             hipMalloc(&H.d_fr_col, cl.size() * sizeof(int)) != hipSuccess) {
-            cleanup();
+            cleanup_all();
             return fail(c, SBPE_ENOMEM, "frame operator");
         }
         HIPCHECK(c, hipMemcpy(H.d_fr_rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
         HIPCHECK(c, hipMemcpy(H.d_fr_col, cl.data(), cl.size() * sizeof(int), hipMemcpyHostToDevice));
         st = upload(c, vv, &H.d_fr_val);
-        if (!st) st = upload(c, rsum[b], &H.d_fr_rsum);
+        if (!st) st = upload(c, rs, &H.d_fr_rsum);
         if (st) {
-            cleanup();
+            cleanup_all();
             return st;
         }
         BlockDesc& D = c->desc[b];
@@ -1231,6 +1249,12 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
         D.fr_col = H.d_fr_col;
         D.fr_val = H.d_fr_val;
         D.fr_rsum = H.d_fr_rsum;
+    }
+    for (int b = 0; b < nb; ++b) (void)hipFree(Ga[b]);
+    Ga.assign(nb, nullptr);
+    if (bad) {
+        cleanup();
+        return fail(c, SBPE_EHIP, "frame operator assembly: a frame row reaches beyond the probe window");
     }
     HIPCHECK(c, hipMemcpy(c->d_desc, c->desc.data(), c->desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
     // check against the frame kernel on a random field
@@ -1889,8 +1913,22 @@ static sbpe_status batch_rebuild(sbpe_batch* b) {
     return SBPE_OK;
 }
 
+// One sweep over every member: a single launch while the tiles are few,
+// otherwise the interior tiles on the batch stream and the frame operator on
+// the side stream (each waits for the other's previous sweep).  Either way
+// every point is evaluated with the arithmetic of a single-context sweep.
 static sbpe_status batch_pass(sbpe_batch* b, const PassArgs& a) {
-    const int e = launch_pass(b->dtype, b->order, a, b->total_tiles, b->total_frame_wg, b->stream);
+    int e;
+    if (sweep_fused(b->total_tiles)) {
+        e = launch_pass(b->dtype, b->order, a, b->total_tiles, b->total_frame_wg, b->stream);
+    } else {
+        BHIPCHECK(b, hipEventRecord(b->ev_main, b->stream));
+        BHIPCHECK(b, hipStreamWaitEvent(b->side, b->ev_main, 0));
+        BHIPCHECK(b, hipEventRecord(b->ev_side, b->side));
+        BHIPCHECK(b, hipStreamWaitEvent(b->stream, b->ev_side, 0));
+        e = launch_interior(b->dtype, b->order, a, b->total_tiles, b->stream);
+        if (e == 0) e = launch_frame_sp(b->dtype, b->order, a, b->total_frame_wg, b->side);
+    }
     if (e != 0) return bfail(b, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
     return SBPE_OK;
 }

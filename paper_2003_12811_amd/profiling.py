@@ -43,7 +43,10 @@ def kernel_kind(name):
     if part in ('march', 'pass'):
         # a one-launch sweep (k_pass) also updates the frame points
         return 'interior_%s/%s/o%s' % (('apply', 'rk1', 'rk2')[int(p)], dt, order)
-    return 'frame/%s/o%s' % (dt, order)
+    if part == 'frame_sp':
+        return 'frame_%s/%s/o%s' % (('apply', 'rk1', 'rk2')[int(p)], dt, order)
+    # the stencil form of the frame rows, run at setup to assemble the operator
+    return 'frame_stencil/%s/o%s' % (dt, order)
 
 
 def summarize_stats(stats_csv, out_md, command):

@@ -4,8 +4,9 @@ A stream of independent shots arrives over time.  Each shot is one
 curvilinear block with its own material, a Ricker point source and surface
 receivers, run for a fixed number of RK4 steps.  The server keeps every
 admitted shot's fields and wavefield resident in HBM and advances all of them
-together through a library batch (``sbpe_batch_*``): one kernel launch per RK4
-sweep covers the blocks of every admitted shot.
+together through a library batch (``sbpe_batch_*``): each RK4 sweep covers the
+blocks of every admitted shot in one launch (two, on two streams, when the
+batch's tiles alone fill the GPU).
 
 * Admission: a shot is set up (library context, coefficient fields, state)
   as soon as it has arrived and its device memory fits in the HBM budget next

@@ -156,14 +156,16 @@ class Interface:
 
     ``reversed`` is True when the two faces are traversed in opposite
     directions.  V and Theta are optional jump data (2, nf) for displacement
-    and traction (Sec. 6, eq. interface_phys), as seen from side a.
+    and traction (Sec. 6, eq. interface_phys): u^a - u^b = V tfun(t) and
+    tau^a + tau^b = Theta tfun(t), in side a's point order (tfun None: 1).
     """
 
-    def __init__(self, a, fa, b, fb, reversed=False, V=None, Theta=None):
+    def __init__(self, a, fa, b, fb, reversed=False, V=None, Theta=None, tfun=None):
         self.a, self.fa, self.b, self.fb = a, fa, b, fb
         self.reversed = reversed
         self.V = V
         self.Theta = Theta
+        self.tfun = tfun
 
 
 class Problem:
@@ -241,10 +243,11 @@ class Problem:
         th = np.zeros_like(jump)
         own = slice(None) if sgn > 0 else perm      # V, Theta are stored in side a's order
         if not homogeneous:
+            tv = 1.0 if itf.tfun is None else itf.tfun(t)
             if itf.V is not None:
-                jump = jump - sgn * itf.V[:, own]
+                jump = jump - sgn * tv * itf.V[:, own]
             if itf.Theta is not None:
-                th = itf.Theta[:, own]
+                th = tv * itf.Theta[:, own]
         Jhat = fo['Jhat']
         Z = self.beta * DIM * Jhat / 4.0 * (
             B.nCn(f) / (fo['h_1'] * fo['Jf'])

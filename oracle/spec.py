@@ -29,6 +29,11 @@ def build(spec, beta=1.0):
         blocks.append(E.Block(b['X1'], b['X2'], b['rho'], M.full_from_c10(b['C10']),
                               order=spec['order'], beta=beta))
     itfs = [E.Interface(a, fa, bb, fb, reversed=bool(rev)) for (a, fa, bb, fb, rev) in spec.get('interfaces', [])]
+    # jump data (Sec. 6): (interface index, V, Theta, time_fn, params), side a's order
+    for (k, V, Th, tk, tp) in spec.get('interface_data', []):
+        itfs[k].V = None if V is None else np.asarray(V, dtype=float)
+        itfs[k].Theta = None if Th is None else np.asarray(Th, dtype=float)
+        itfs[k].tfun = tfun(tk, tp)
     P = E.Problem(blocks, itfs, beta=beta)
     for k, b in enumerate(spec['blocks']):
         for f, (kind, g, tk, tp, U) in enumerate(b['bc']):

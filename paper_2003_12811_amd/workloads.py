@@ -221,6 +221,29 @@ def mms_c1(X1, X2, C10, rho=1.0):
     return dict(u=u, f=f, grad=grad, C=C, omega=OMEGA_C1)
 
 
+def mms_wave(X1, X2, C10, rho=1.0, amp=1.0, phase=0.0, omega=OMEGA_C1):
+    """The C1 manufactured solution with an amplitude and a phase,
+    u_L = amp sin(2 pi X1 + L + phase) cos(2 pi X2) cos(omega t), for constant
+    C10 (10,) and rho; same fields as ``mms_c1``."""
+    C = c10_to_full(np.asarray(C10, dtype=float))
+    tp = 2.0 * np.pi
+    ph = [L + phase for L in (1, 2)]
+    u = np.stack([amp * np.sin(tp * X1 + q) * np.cos(tp * X2) for q in ph])
+    grad = np.stack([np.stack([amp * tp * np.cos(tp * X1 + q) * np.cos(tp * X2),
+                               -amp * tp * np.sin(tp * X1 + q) * np.sin(tp * X2)]) for q in ph])
+    hess = np.empty((2, 2, 2) + X1.shape)        # [L, I, K]
+    for Li, q in enumerate(ph):
+        sv = amp * np.sin(tp * X1 + q) * np.cos(tp * X2)
+        m = amp * np.cos(tp * X1 + q) * np.sin(tp * X2)
+        hess[Li, 0, 0] = -tp ** 2 * sv
+        hess[Li, 1, 1] = -tp ** 2 * sv
+        hess[Li, 0, 1] = -tp ** 2 * m
+        hess[Li, 1, 0] = -tp ** 2 * m
+    div = np.einsum('IJKL,LIK...->J...', C, hess)
+    f = -rho * omega ** 2 * u - div
+    return dict(u=u, f=f, grad=grad, C=C, omega=omega)
+
+
 def traction_data(mms, face_idx, normal):
     """n_I C_IJKL d_K u_L at the face points (flat indices), shape (2, nf)."""
     g = mms['grad'].reshape(2, 2, -1)[..., face_idx]
@@ -263,6 +286,42 @@ def spec_c1(n=65, order=4):
                forcing=(mm['f'], T_COS, (mm['omega'], 0.0)))
     return dict(order=order, blocks=[blk], interfaces=[], sources=[], receivers=[],
                 mms=mm, T=0.5, cfl=0.5)
+
+
+def spec_fault(n=33, order=4, jump_data=True):
+    """Two Cartesian blocks [0, 1/2] x [0, 1] and [1/2, 1] x [0, 1] of n^2
+    points each, joined along x1 = 1/2, with different constant materials and a
+    manufactured solution that jumps across the interface; the jumps in
+    displacement and traction enter as interface data (Sec. 6,
+    eq. interface_phys), the outer faces carry the exact tractions.
+    jump_data=False drops the interface data (the solution then does not
+    satisfy the discrete problem)."""
+    voigt = np.array(VOIGT_C1)
+    parts = [dict(lim=(0.0, 0.5), scale=1.0, rho=1.0, amp=1.0, phase=0.0),
+             dict(lim=(0.5, 1.0), scale=2.5, rho=1.5, amp=0.6, phase=0.9)]
+    blocks, mms = [], []
+    for P in parts:
+        X1, X2 = grid(Identity(), n, n, P['lim'])
+        C10c = voigt_to_c10(P['scale'] * voigt)
+        mm = mms_wave(X1, X2, C10c, rho=P['rho'], amp=P['amp'], phase=P['phase'])
+        bc = []
+        for f in range(4):
+            g = traction_data(mm, face_flat_index(f, n, n), outward_normal(Identity(), f, n, n, P['lim']))
+            bc.append((TRACTION, g, T_COS, (mm['omega'], 0.0), None))
+        blocks.append(dict(X1=X1, X2=X2, rho=P['rho'] * np.ones((n, n)), C10=C10c[:, None, None] * np.ones((1, n, n)),
+                           bc=bc, forcing=(mm['f'], T_COS, (mm['omega'], 0.0))))
+        mms.append(mm)
+    # face 1 (x1 = 1/2) of block 0 meets face 0 of block 1, same point order
+    ia, ib = face_flat_index(1, n, n), face_flat_index(0, n, n)
+    V = mms[0]['u'].reshape(2, -1)[:, ia] - mms[1]['u'].reshape(2, -1)[:, ib]
+    Th = (traction_data(mms[0], ia, outward_normal(Identity(), 1, n, n, parts[0]['lim']))
+          + traction_data(mms[1], ib, outward_normal(Identity(), 0, n, n, parts[1]['lim'])))
+    # the interface faces are not traction faces: their bc entries are ignored
+    spec = dict(order=order, blocks=blocks, interfaces=[(0, 1, 1, 0, False)], sources=[], receivers=[],
+                mms=mms, T=0.5, cfl=0.5)
+    if jump_data:
+        spec['interface_data'] = [(0, V, Th, T_COS, (mms[0]['omega'], 0.0))]
+    return spec
 
 
 def spec_c2(n=1025, seed=0, order=4, nrec=16):

@@ -107,6 +107,17 @@ sbpe_status sbpe_set_bc_data(sbpe_ctx_t ctx, int block, int face, const double* 
  * opposite directions.  Both faces need the same number of points. */
 sbpe_status sbpe_connect(sbpe_ctx_t ctx, int blkA, int faceA, int blkB, int faceB, int reversed);
 
+/* Separable jump data of an interface (Sec. 6, eq. interface_phys and
+ * eq. scheme_interface): across the interface at face `face` of `block`,
+ *   u(this block) - u(partner) = V_J(x) tau(t)   (displacement jump),
+ *   tau(this block) + tau(partner) = Theta_J(x) tau(t)   (traction jump),
+ * with V, Theta [2][nf] in this face's point order (either may be NULL for
+ * zero) and one time function for both (SBPE_TIME_*).  The data are copied and
+ * apply to both sides of the interface; call after sbpe_connect and before
+ * sbpe_finalize.  Returns SBPE_ESTATE if the face is not an interface. */
+sbpe_status sbpe_set_interface_data(sbpe_ctx_t ctx, int block, int face, const double* V, const double* Theta,
+                                    int time_fn, const double* time_params);
+
 /* Separable body force f_J(x) tau(t) of a block: F [2][n2][n1], copied. */
 sbpe_status sbpe_set_forcing(sbpe_ctx_t ctx, int block, const double* F, int time_fn,
                              const double* time_params);

@@ -97,6 +97,9 @@ struct HostFace {
     std::vector<double> U;      // [4][nf] physical U_JL
     std::vector<double> g;      // [2][nf]
     TimeFn tf{TF_ZERO, 0, {0.0, 0.0}};
+    // interface jump data in this face's order: V = u(side 0) - u(side 1), Th = tau + tau'
+    std::vector<double> V, Th;
+    TimeFn jtf{TF_ZERO, 0, {0.0, 0.0}};
     int partner = -1, pface = -1, reversed = 0, side = 0;
     std::vector<double> jhat;   // computed
 };
@@ -118,7 +121,7 @@ struct HostBlock {
     void* d_force = nullptr;
     void* d_a1 = nullptr;
     void* d_a2 = nullptr;
-    void* d_face[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    void* d_face[4][4] = {};    // per face: g, U, V, Theta (device, scaled for the kernels)
     // assembled frame operator (CSR over the frame rows)
     int* d_fr_rowptr = nullptr;
     int* d_fr_col = nullptr;
@@ -516,8 +519,8 @@ static sbpe_status build_plan(sbpe_ctx* c) {
             F.pface = HF.pface;
             F.reversed = HF.reversed;
             F.vsign = HF.side == 0 ? 1.0 : -1.0;
-            F.V = nullptr;
-            F.Th = nullptr;
+            F.V = H.d_face[f][2];
+            F.Th = H.d_face[f][3];
             if (HF.kind == BC_INTERFACE) {
                 const HostBlock& P = c->blocks[HF.partner];
                 const int pa = HF.pface >> 1;
@@ -552,7 +555,10 @@ static sbpe_status build_plan(sbpe_ctx* c) {
     // time-function items: per block 4 faces (g), 4 faces (jump data), forcing; then sources
     std::vector<TimeFn> items((size_t)nb * ITEMS_PER_BLOCK + c->sources.size(), TimeFn{TF_ZERO, 0, {0.0, 0.0}});
     for (int b = 0; b < nb; ++b) {
-        for (int f = 0; f < 4; ++f) items[(size_t)b * ITEMS_PER_BLOCK + f] = c->blocks[b].face[f].tf;
+        for (int f = 0; f < 4; ++f) {
+            items[(size_t)b * ITEMS_PER_BLOCK + f] = c->blocks[b].face[f].tf;
+            items[(size_t)b * ITEMS_PER_BLOCK + 4 + f] = c->blocks[b].face[f].jtf;
+        }
         items[(size_t)b * ITEMS_PER_BLOCK + 8] = c->blocks[b].ftf;
     }
     for (size_t s = 0; s < c->sources.size(); ++s) {
@@ -873,7 +879,7 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
             (void)hipFree(B.d_a1);
             (void)hipFree(B.d_a2);
             for (int f = 0; f < 4; ++f)
-                for (int k = 0; k < 2; ++k) (void)hipFree(B.d_face[f][k]);
+                for (int k = 0; k < 4; ++k) (void)hipFree(B.d_face[f][k]);
             (void)hipFree(B.d_fr_rowptr);
             (void)hipFree(B.d_fr_col);
             (void)hipFree(B.d_fr_val);
@@ -997,6 +1003,42 @@ sbpe_status sbpe_connect(sbpe_ctx_t c, int bA, int fA, int bB, int fB, int rever
     A.reversed = B.reversed = reversed ? 1 : 0;
     A.side = 0;
     B.side = 1;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_set_interface_data(sbpe_ctx_t c, int block, int face, const double* V, const double* Th,
+                                    int time_fn, const double* tp) {
+    sbpe_status s = check_face(c, block, face);
+    if (s) return s;
+    if (time_fn < SBPE_TIME_ZERO || time_fn > SBPE_TIME_RICKER) return fail(c, SBPE_EINVAL, "bad time function");
+    HostFace& A = c->blocks[block].face[face];
+    if (A.kind != BC_INTERFACE) return fail(c, SBPE_ESTATE, "face is not an interface");
+    HostFace& B = c->blocks[A.partner].face[A.pface];
+    const int nf = c->blocks[block].nf(face);
+    // both faces keep V as u(side 0) - u(side 1) and Theta, each in its own order
+    const double sv = A.side == 0 ? 1.0 : -1.0;
+    auto other = [&](int t) { return A.reversed ? nf - 1 - t : t; };
+    A.V.clear();
+    B.V.clear();
+    A.Th.clear();
+    B.Th.clear();
+    if (V) {
+        A.V.assign(2 * nf, 0.0);
+        B.V.assign(2 * nf, 0.0);
+        for (int q = 0; q < 2; ++q)
+            for (int t = 0; t < nf; ++t) {
+                A.V[q * nf + t] = sv * V[q * nf + t];
+                B.V[q * nf + other(t)] = sv * V[q * nf + t];
+            }
+    }
+    if (Th) {
+        A.Th.assign(Th, Th + 2 * nf);
+        B.Th.assign(2 * nf, 0.0);
+        for (int q = 0; q < 2; ++q)
+            for (int t = 0; t < nf; ++t) B.Th[q * nf + other(t)] = Th[q * nf + t];
+    }
+    set_time_fn(time_fn, tp, A.jtf);
+    B.jtf = A.jtf;
     return SBPE_OK;
 }
 
@@ -1378,6 +1420,20 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
                     for (int k = 0; k < 4; ++k)
                         for (int t = 0; t < nf; ++t) U[k * nf + t] *= F.jhat[t] / w;
                     s = upload(c, U, &B.d_face[f][1]);
+                    if (s) return s;
+                }
+                if (F.kind == BC_INTERFACE && !F.V.empty()) {
+                    s = upload(c, F.V, &B.d_face[f][2]);
+                    if (s) return s;
+                }
+                if (F.kind == BC_INTERFACE && !F.Th.empty()) {
+                    // the traction-jump SAT adds Jhat H_f Theta / 2 at the face row: Jhat Theta / (2 w)
+                    std::vector<double> th(F.Th);
+                    for (int t = 0; t < nf; ++t) {
+                        th[t] *= 0.5 * F.jhat[t] / w;
+                        th[nf + t] *= 0.5 * F.jhat[t] / w;
+                    }
+                    s = upload(c, th, &B.d_face[f][3]);
                     if (s) return s;
                 }
             }

@@ -43,6 +43,7 @@ _PROTOS = {
     'sbpe_set_bc_data': [_P, _I, _I, _DP, _I, _DP],
     'sbpe_connect': [_P, _I, _I, _I, _I, _I],
     'sbpe_set_forcing': [_P, _I, _DP, _I, _DP],
+    'sbpe_set_interface_data': [_P, _I, _I, _DP, _DP, _I, _DP],
     'sbpe_add_source': [_P, _I, _D, _D, _D, _D, _D, _D, _D],
     'sbpe_add_receivers': [_P, _I, _I, _DP, _DP],
     'sbpe_finalize': [_P],
@@ -171,6 +172,16 @@ def sbpe_set_bc_data(ctx, block, face, g, time_fn, time_params=None):
 
 def sbpe_connect(ctx, blkA, faceA, blkB, faceB, reversed=False):
     _check(ctx, lib().sbpe_connect(ctx, blkA, faceA, blkB, faceB, 1 if reversed else 0))
+
+
+def sbpe_set_interface_data(ctx, block, face, V, Theta, time_fn, time_params=None):
+    """Jump data across the interface at (block, face): V = u(this) - u(partner),
+    Theta = tau(this) + tau(partner), each (2, nf) in this face's order or None."""
+    V = None if V is None else _f64(V)
+    Th = None if Theta is None else _f64(Theta)
+    tp = _tparams(time_params)
+    _check(ctx, lib().sbpe_set_interface_data(ctx, block, face, None if V is None else _dp(V),
+                                               None if Th is None else _dp(Th), time_fn, _dp(tp)))
 
 
 def sbpe_set_forcing(ctx, block, F, time_fn, time_params=None):

@@ -53,8 +53,12 @@ class Solver:
             if b.get('forcing') is not None:
                 F, tfn, tp = b['forcing']
                 S.sbpe_set_forcing(ctx, bid, F, tfn, tp)
-        for (a, fa, bb, fb, rev) in spec.get('interfaces', []):
+        itfs = spec.get('interfaces', [])
+        for (a, fa, bb, fb, rev) in itfs:
             S.sbpe_connect(ctx, a, fa, bb, fb, rev)
+        # jump data, given on side a of each interface: V = u_a - u_b, Theta = tau_a + tau_b
+        for (k, V, Th, tfn, tp) in spec.get('interface_data', []):
+            S.sbpe_set_interface_data(ctx, itfs[k][0], itfs[k][1], V, Th, tfn, tp)
         for (bid, x1, x2, f1, f2, amp, fp, t0) in spec.get('sources', []):
             S.sbpe_add_source(ctx, bid, x1, x2, f1, f2, amp, fp, t0)
         for (bid, x1, x2) in spec.get('receivers', []):

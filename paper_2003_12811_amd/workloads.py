@@ -300,12 +300,15 @@ def spec_fault(n=33, order=4, jump_data=True):
     parts = [dict(lim=(0.0, 0.5), scale=1.0, rho=1.0, amp=1.0, phase=0.0),
              dict(lim=(0.5, 1.0), scale=2.5, rho=1.5, amp=0.6, phase=0.9)]
     blocks, mms = [], []
-    for P in parts:
+    for k, P in enumerate(parts):
         X1, X2 = grid(Identity(), n, n, P['lim'])
         C10c = voigt_to_c10(P['scale'] * voigt)
         mm = mms_wave(X1, X2, C10c, rho=P['rho'], amp=P['amp'], phase=P['phase'])
         bc = []
         for f in range(4):
+            if f == 1 - k:          # the interface face
+                bc.append((TRACTION, None, T_ZERO, None, None))
+                continue
             g = traction_data(mm, face_flat_index(f, n, n), outward_normal(Identity(), f, n, n, P['lim']))
             bc.append((TRACTION, g, T_COS, (mm['omega'], 0.0), None))
         blocks.append(dict(X1=X1, X2=X2, rho=P['rho'] * np.ones((n, n)), C10=C10c[:, None, None] * np.ones((1, n, n)),
@@ -316,7 +319,6 @@ def spec_fault(n=33, order=4, jump_data=True):
     V = mms[0]['u'].reshape(2, -1)[:, ia] - mms[1]['u'].reshape(2, -1)[:, ib]
     Th = (traction_data(mms[0], ia, outward_normal(Identity(), 1, n, n, parts[0]['lim']))
           + traction_data(mms[1], ib, outward_normal(Identity(), 0, n, n, parts[1]['lim'])))
-    # the interface faces are not traction faces: their bc entries are ignored
     spec = dict(order=order, blocks=blocks, interfaces=[(0, 1, 1, 0, False)], sources=[], receivers=[],
                 mms=mms, T=0.5, cfl=0.5)
     if jump_data:

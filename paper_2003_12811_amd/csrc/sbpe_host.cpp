@@ -228,40 +228,40 @@ static sbpe_status upload(sbpe_ctx* c, const std::vector<double>& h, void** d) {
     return SBPE_OK;
 }
 
-// ---------------------------------------------------------- eigen helpers
-// smallest and largest eigenvalue of a symmetric 4x4 matrix (cyclic Jacobi)
-static void eig4(const double Ain[16], double& lmin, double& lmax) {
+// Whether the symmetric 4x4 matrix A is positive semidefinite up to
+// -tol_rel * max(1, largest diagonal entry): LDL^T with diagonal pivoting.  Once
+// the largest remaining pivot is at or below the tolerance, the remaining block
+// must vanish (a zero diagonal with a nonzero off-diagonal entry, or a negative
+// diagonal, means a negative eigenvalue).
+static bool psd4(const double Ain[16], double tol_rel) {
     double a[4][4];
-    for (int i = 0; i < 4; ++i)
+    double dmax = 0.0;
+    for (int i = 0; i < 4; ++i) {
         for (int j = 0; j < 4; ++j) a[i][j] = Ain[4 * i + j];
-    for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < 4; ++p)
-            for (int q = p + 1; q < 4; ++q) off += a[p][q] * a[p][q];
-        if (off < 1e-30) break;
-        for (int p = 0; p < 4; ++p)
-            for (int q = p + 1; q < 4; ++q) {
-                if (std::fabs(a[p][q]) < 1e-300) continue;
-                const double th = 0.5 * (a[q][q] - a[p][p]) / a[p][q];
-                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-                for (int k = 0; k < 4; ++k) {
-                    const double akp = a[k][p], akq = a[k][q];
-                    a[k][p] = cs * akp - sn * akq;
-                    a[k][q] = sn * akp + cs * akq;
-                }
-                for (int k = 0; k < 4; ++k) {
-                    const double apk = a[p][k], aqk = a[q][k];
-                    a[p][k] = cs * apk - sn * aqk;
-                    a[q][k] = sn * apk + cs * aqk;
-                }
-            }
+        dmax = std::max(dmax, a[i][i]);
     }
-    lmin = lmax = a[0][0];
-    for (int i = 1; i < 4; ++i) {
-        lmin = std::min(lmin, a[i][i]);
-        lmax = std::max(lmax, a[i][i]);
+    const double tol = tol_rel * std::max(1.0, dmax);
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+        for (int i = k + 1; i < 4; ++i)
+            if (a[i][i] > a[p][p]) p = i;
+        if (p != k) {
+            for (int j = 0; j < 4; ++j) std::swap(a[k][j], a[p][j]);
+            for (int i = 0; i < 4; ++i) std::swap(a[i][k], a[i][p]);
+        }
+        const double d = a[k][k];
+        if (d <= tol) {
+            for (int i = k; i < 4; ++i)
+                for (int j = k; j < 4; ++j)
+                    if (std::fabs(a[i][j]) > tol) return false;
+            return true;
+        }
+        for (int i = k + 1; i < 4; ++i) {
+            const double l = a[i][k] / d;
+            for (int j = k + 1; j < 4; ++j) a[i][j] -= l * a[k][j];
+        }
     }
+    return true;
 }
 
 // pair index (IJ) -> 0..3 with 11, 12, 21, 22; C10 upper triangle order
@@ -313,9 +313,7 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
         for (int q = 0; q < 4; ++q) B.Fm[(size_t)q * np + p] = F[q >> 1][q & 1];
         double Cm[16];
         c10_to_mat(B.C10.data(), np, p, Cm);
-        double lmin, lmax;
-        eig4(Cm, lmin, lmax);
-        if (lmin < -1e-10 * std::max(1.0, std::fabs(lmax))) {
+        if (!psd4(Cm, 1e-10)) {
 #pragma omp critical
             bad_c = (bad_c < 0 || p < bad_c) ? p : bad_c;
             continue;

@@ -131,3 +131,46 @@ def test_error_codes():
         S.sbpe_create(-1, None, S.F64, 6, 1.0)
     with pytest.raises(S.SbpeError):
         S.sbpe_create(-1, None, S.F64, 4, 0.5)
+
+
+def _finalize_status(M4):
+    """sbpe_finalize on a small host-only block whose stiffness, as the 4x4
+    matrix over the pairs (11, 12, 21, 22), is M4 at every point."""
+    n = 15
+    X1, X2 = W.grid(W.Identity(), n, n)
+    iu = np.triu_indices(4)
+    C10 = np.asarray(M4)[iu][:, None, None] * np.ones((1, n, n))
+    ctx = _host_ctx()
+    try:
+        S.sbpe_add_block(ctx, X1, X2, np.ones((n, n)), C10)
+        S.sbpe_finalize(ctx)
+        return 0
+    except S.SbpeError as e:
+        return e.code
+    finally:
+        S.sbpe_destroy(ctx)
+
+
+def test_stiffness_psd_check_against_eigenvalues():
+    """The finalize check accepts exactly the semidefinite stiffnesses (up to a
+    relative 1e-10), judged here by numpy's eigenvalues: full-rank and
+    minor-symmetric (rank 3) media, and matrices with one eigenvalue moved to
+    -1e-13 (accepted) or -1e-6 (rejected) of the scale."""
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        Q, _ = np.linalg.qr(rng.normal(size=(4, 4)))
+        lam = rng.uniform(0.5, 3.0, 4)
+        if trial % 4 == 1:
+            lam[rng.integers(4)] = 0.0                  # semidefinite
+        if trial % 4 == 2:
+            lam[rng.integers(4)] = -1e-13 * lam.max()   # within the tolerance
+        if trial % 4 == 3:
+            lam[rng.integers(4)] = -1e-6 * lam.max()    # clearly indefinite
+        A = (Q * lam) @ Q.T
+        A = 0.5 * (A + A.T)
+        want_ok = np.linalg.eigvalsh(A).min() >= -1e-10 * max(1.0, np.abs(A).max())
+        assert (_finalize_status(A) == 0) == want_ok, (trial, np.linalg.eigvalsh(A))
+    # minor-symmetric media from Voigt (rank 3) are accepted
+    V = np.array(W.VOIGT_C1)
+    A = M.full_from_c10(W.voigt_to_c10(V)).reshape(4, 4)
+    assert _finalize_status(A) == 0

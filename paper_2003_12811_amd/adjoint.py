@@ -8,9 +8,9 @@ gradient is the exact derivative of the discrete map (up to rounding):
 * Forward: ``sbpe_advance`` with a checkpoint of (u, v, t) every
   ``checkpoint_every`` steps; J from the recorded receiver traces.
 * Reverse, segment by segment from the last checkpoint: the segment's states
-  are recomputed with the stage form of RK4 (``sbpe_apply`` with the data at
-  the stage times, ``sbpe_lincomb`` for the stage combinations), then each
-  step is reversed: with b = (1/6, 1/3, 1/3, 1/6), c = (0, 1/2, 1/2, 1), the
+  are recomputed with ``sbpe_advance``, each step's stages with the stage form
+  of RK4 (``sbpe_apply`` with the data at the stage times, ``sbpe_lincomb``
+  for the stage combinations), then each step is reversed: with b = (1/6, 1/3, 1/3, 1/6), c = (0, 1/2, 1/2, 1), the
   stage-slope adjoints k_i = dt b_i y^ are propagated from the last stage to
   the first through (u, v) -> (L^T v, u).  Because H L is symmetric (the energy
   analysis of Sec. 5), in the variables y^ = y / (H rho~) the transpose is the
@@ -70,32 +70,6 @@ class MisfitGradient:
     def _apply(self, x, t, homogeneous, out):
         S.sbpe_apply(self.sol.ctx, [x.data_ptr()], [out.data_ptr()], t, homogeneous)
 
-    def _stages(self, u, v, t):
-        """Stage displacements U_i, velocities V_i and values a_i of one step."""
-        h = self.dt
-        U, V, A = [u], [v], []
-        for i in range(4):
-            a = self._new()
-            self._apply(U[i], t + C_RK[i] * h, False, a)
-            A.append(a)
-            if i < 3:
-                Un, Vn = self._new(), self._new()
-                self._lin([1.0, C_RK[i + 1] * h], [u, V[i]], Un)
-                self._lin([1.0, C_RK[i + 1] * h], [v, A[i]], Vn)
-                U.append(Un)
-                V.append(Vn)
-        return U, V, A
-
-    def _step(self, u, v, t):
-        h = self.dt
-        U, V, A = self._stages(u, v, t)
-        un, vn = self._new(), self._new()
-        self._lin([1.0, h * B_RK[0], h * B_RK[1], h * B_RK[2]], [u, V[0], V[1], V[2]], un)
-        self._lin([1.0, h * B_RK[3]], [un, V[3]], un)
-        self._lin([1.0, h * B_RK[0], h * B_RK[1], h * B_RK[2]], [v, A[0], A[1], A[2]], vn)
-        self._lin([1.0, h * B_RK[3]], [vn, A[3]], vn)
-        return un, vn
-
     # ------------------------------------------------------------ forward
     def forward(self):
         """Run from rest with checkpoints; returns J (and keeps the traces)."""
@@ -117,56 +91,78 @@ class MisfitGradient:
 
     # ------------------------------------------------------------ reverse
     def gradient(self):
-        """(dJ/drho (n2, n1), dJ/dC10 (10, n2, n1)) after ``forward``."""
+        """(dJ/drho (n2, n1), dJ/dC10 (10, n2, n1)) after ``forward``.
+
+        Per step, with stage slopes k_i = (V_i, A_i) and their adjoints
+        (ku_i, kv_i), from the last stage to the first:
+            ku_i = dt b_i uh + dt c_{i+1} Yu_{i+1},  kv_i = dt b_i vh + dt c_{i+1} ku_{i+1},
+            Yu_i = L kv_i (scaled variables),
+        then uh <- uh + sum_i Yu_i and vh <- vh + sum_i ku_i.  The states of a
+        checkpoint segment are recomputed with ``sbpe_advance``; every work
+        buffer is allocated once.
+        """
         torch = self.torch
-        ctx = self.sol.ctx
+        sol = self.sol
+        ctx = sol.ctx
         h = self.dt
         n2, n1 = self.shape[1:]
         gc = torch.zeros((10, n2, n1), dtype=torch.float64, device=self.dev)
         grt = torch.zeros((n2, n1), dtype=torch.float64, device=self.dev)
         res = torch.as_tensor(np.ascontiguousarray(self.residuals), dtype=torch.float64, device=self.dev)
         rstride = self.nrec * 2 * 8
-        uh, vh = self._new().zero_(), self._new().zero_()
         N = self.nsteps
+        new = self._new
+        uh, vh, yu, yv = new().zero_(), new().zero_(), new(), new()
+        U = [None] + [new() for _ in range(3)]
+        V = [None] + [new() for _ in range(3)]
+        A = [new() for _ in range(4)]
+        ku = [new() for _ in range(4)]
+        kv = [new() for _ in range(4)]
+        Yu = [new() for _ in range(4)]
+        seg_u = [new() for _ in range(self.K)]
+        seg_v = [new() for _ in range(self.K)]
+        lin = self._lin
         if self.nrec:
             S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (N - 1) * rstride, [uh.data_ptr()], 1.0)
         for (cu, cv, ct, c0) in reversed(self.checkpoints):
-            # recompute the segment's states
             k = min(self.K, N - c0)
-            states = [(cu, cv, ct)]
-            u, v, t = cu, cv, ct
-            for s in range(k - 1):
-                u, v = self._step(u, v, t)
-                t = ct + (s + 1) * h
-                states.append((u, v, t))
-            for s in range(k - 1, -1, -1):
-                n = c0 + s                      # reversing the step from y_n to y_{n+1}
-                u, v, t = states[s]
-                U, V, A = self._stages(u, v, t)
-                ku = []
-                kv = []
+            # the segment's states
+            sol.set_state([cu], [cv], ct)
+            seg_u[0].copy_(cu)
+            seg_v[0].copy_(cv)
+            for s_ in range(1, k):
+                sol.advance(1, h)
+                seg_u[s_].copy_(sol.u[0])
+                seg_v[s_].copy_(sol.v[0])
+            for s_ in range(k - 1, -1, -1):
+                n = c0 + s_                     # reversing the step from y_n to y_{n+1}
+                u, v, t = seg_u[s_], seg_v[s_], ct + s_ * h
+                # stages of the step
+                U[0], V[0] = u, v
                 for i in range(4):
-                    a, b = self._new(), self._new()
-                    self._lin([h * B_RK[i]], [uh], a)
-                    self._lin([h * B_RK[i]], [vh], b)
-                    ku.append(a)
-                    kv.append(b)
-                yu, yv = uh, vh               # y^_{n+1} carried into y^_n
+                    self._apply(U[i], t + C_RK[i] * h, False, A[i])
+                    if i < 3:
+                        lin([1.0, C_RK[i + 1] * h], [u, V[i]], U[i + 1])
+                        lin([1.0, C_RK[i + 1] * h], [v, A[i]], V[i + 1])
+                # stage adjoints, last stage first
                 for i in range(3, -1, -1):
-                    Yu = self._new()
-                    self._apply(kv[i], 0.0, True, Yu)
-                    Yv = ku[i]
+                    if i == 3:
+                        lin([h * B_RK[3]], [uh], ku[3])
+                        lin([h * B_RK[3]], [vh], kv[3])
+                    else:
+                        lin([h * B_RK[i], h * C_RK[i + 1]], [uh, Yu[i + 1]], ku[i])
+                        lin([h * B_RK[i], h * C_RK[i + 1]], [vh, ku[i + 1]], kv[i])
+                    self._apply(kv[i], 0.0, True, Yu[i])
                     S.sbpe_grad_accumulate(ctx, [kv[i].data_ptr()], [U[i].data_ptr()], [A[i].data_ptr()], 1.0,
                                            t + C_RK[i] * h, False, [gc.data_ptr()], [grt.data_ptr()])
-                    if i > 0:
-                        self._lin([1.0, h * C_RK[i]], [ku[i - 1], Yu], ku[i - 1])
-                        self._lin([1.0, h * C_RK[i]], [kv[i - 1], Yv], kv[i - 1])
-                    self._lin([1.0, 1.0], [yu, Yu], yu)
-                    self._lin([1.0, 1.0], [yv, Yv], yv)
-                uh, vh = yu, yv
+                lin([1.0, 1.0, 1.0, 1.0], [uh, Yu[3], Yu[2], Yu[1]], yu)
+                lin([1.0, 1.0], [yu, Yu[0]], yu)
+                lin([1.0, 1.0, 1.0, 1.0], [vh, ku[3], ku[2], ku[1]], yv)
+                lin([1.0, 1.0], [yv, ku[0]], yv)
+                uh, yu = yu, uh
+                vh, yv = yv, vh
                 if n > 0 and self.nrec:
                     S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (n - 1) * rstride, [uh.data_ptr()], 1.0)
-            states = None
         g10, grho = S.sbpe_grad_to_physical(ctx, 0, gc.data_ptr(), grt.data_ptr())
         return grho, g10
 

@@ -1592,6 +1592,58 @@ __device__ double d2_coef_grad(gcp<T> z, gcp<T> y, long st, int p, int n) {
     return acc;
 }
 
+// d2_coef_grad away from the closures (every row r = p - o an interior row,
+// H^_r = 1), from register windows zw[k] = z_{p-H+k} and yw[k] = y_{p-2H+k};
+// the same operations in the same order as d2_coef_grad
+template <int ORD>
+__device__ __forceinline__ double d2_coef_grad_win(const double* zw, const double* yw) {
+    constexpr int HF = Op<ORD>::HALF;
+    double acc = 0.0;
+#pragma unroll
+    for (int o = -HF; o <= HF; ++o) {
+        const double yr = yw[2 * HF - o];
+        double sum = 0.0;
+#pragma unroll
+        for (int e = -HF; e <= HF; ++e) {
+            if (e == 0) continue;
+            const double w = d2_edge_dw<ORD>(e, o);
+            if (w != 0.0) sum += w * (yw[2 * HF - o + e] - yr);
+        }
+        acc += 1.0 * zw[HF - o] * sum;
+    }
+    return acc;
+}
+
+// the narrow coefficient gradients of one line direction at index p: the
+// window path where no closure row is involved, else the general one
+template <typename T, int ORD>
+__device__ __forceinline__ void d2_coef_grad_pairs(gcp<T> z0, gcp<T> z1, gcp<T> y0, gcp<T> y1, long st, int p, int n,
+                                                   double& g00, double& g01, double& g11) {
+    using O = Op<ORD>;
+    constexpr int HF = O::HALF;
+    constexpr int LO = (O::R0 + HF > O::W) ? O::R0 + HF : O::W;
+    if (p >= LO && p <= n - 1 - LO) {
+        double zw[2][2 * HF + 1], yw[2][4 * HF + 1];
+#pragma unroll
+        for (int k = 0; k <= 2 * HF; ++k) {
+            zw[0][k] = (double)z0[(long)(p - HF + k) * st];
+            zw[1][k] = (double)z1[(long)(p - HF + k) * st];
+        }
+#pragma unroll
+        for (int k = 0; k <= 4 * HF; ++k) {
+            yw[0][k] = (double)y0[(long)(p - 2 * HF + k) * st];
+            yw[1][k] = (double)y1[(long)(p - 2 * HF + k) * st];
+        }
+        g00 = d2_coef_grad_win<ORD>(zw[0], yw[0]);
+        g01 = d2_coef_grad_win<ORD>(zw[0], yw[1]) + d2_coef_grad_win<ORD>(zw[1], yw[0]);
+        g11 = d2_coef_grad_win<ORD>(zw[1], yw[1]);
+    } else {
+        g00 = d2_coef_grad<T, ORD>(z0, y0, st, p, n);
+        g01 = d2_coef_grad<T, ORD>(z0, y1, st, p, n) + d2_coef_grad<T, ORD>(z1, y0, st, p, n);
+        g11 = d2_coef_grad<T, ORD>(z1, y1, st, p, n);
+    }
+}
+
 // (D1^ T (H^ z))_p = sum_r D1^[r][p] H^_r z_r along a line (D1^ = h D1)
 template <typename T, int ORD>
 __device__ double d1t_weighted(gcp<T> z, long st, int p, int n) {
@@ -1661,14 +1713,15 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     // narrow terms (stored fields: x1 C1111, C1112, C1212; x2 C2121, C2122, C2222)
     {
         const double fx = h2 * hn2 / h1, fy = h1 * hn1 / h2;
-        gcp<T> zr0 = z + row, zr1 = z + np + row, yr0 = y + row, yr1 = y + np + row;
-        g[K_C1111] += fx * d2_coef_grad<T, ORD>(zr0, yr0, 1, i, n1);
-        g[K_C1112] += fx * (d2_coef_grad<T, ORD>(zr0, yr1, 1, i, n1) + d2_coef_grad<T, ORD>(zr1, yr0, 1, i, n1));
-        g[K_C1212] += fx * d2_coef_grad<T, ORD>(zr1, yr1, 1, i, n1);
-        gcp<T> zc0 = z + i, zc1 = z + np + i, yc0 = y + i, yc1 = y + np + i;
-        g[K_C2121] += fy * d2_coef_grad<T, ORD>(zc0, yc0, n1, j, n2);
-        g[K_C2122] += fy * (d2_coef_grad<T, ORD>(zc0, yc1, n1, j, n2) + d2_coef_grad<T, ORD>(zc1, yc0, n1, j, n2));
-        g[K_C2222] += fy * d2_coef_grad<T, ORD>(zc1, yc1, n1, j, n2);
+        double a00, a01, a11;
+        d2_coef_grad_pairs<T, ORD>(z + row, z + np + row, y + row, y + np + row, 1, i, n1, a00, a01, a11);
+        g[K_C1111] += fx * a00;
+        g[K_C1112] += fx * a01;
+        g[K_C1212] += fx * a11;
+        d2_coef_grad_pairs<T, ORD>(z + i, z + np + i, y + i, y + np + i, n1, j, n2, a00, a01, a11);
+        g[K_C2121] += fy * a00;
+        g[K_C2122] += fy * a01;
+        g[K_C2222] += fy * a11;
     }
     // mixed terms: M_ab = c_1a2b (C1121, C1122, C1221, C1222)
     {

@@ -185,3 +185,32 @@ def test_server_results_equal_standalone_runs():
         assert np.array_equal(r['receivers'], by_id[r['id']]['receivers']), r['id']
         assert r['latency'] > 0
     assert res['p99_s'] >= res['p50_s'] > 0
+
+
+def test_large_batch_two_stream_sweeps_equal_plain_advance():
+    """A batch whose tiles fill the GPU (three 1025^2 shots, over 4096 tiles)
+    sweeps the interior and the frame operator as two launches on two
+    streams; each member still equals its own sbpe_advance bitwise."""
+    say('large batch (two-stream sweeps)')
+    st = _stream()
+    steps = 12
+    plain = [_shot(1025, 30 + k, 'f32', st, steps=steps) for k in range(3)]
+    batched = [_shot(1025, 30 + k, 'f32', st, steps=steps) for k in range(3)]
+    bt = _batch('f32', st)
+    try:
+        for s in plain:
+            S.sbpe_advance(s.ctx, steps, s.dt)
+        for s in batched:
+            S.sbpe_batch_add(bt, s.ctx, steps, s.dt)
+        assert S.sbpe_batch_info(bt)['members'] == 3
+        S.sbpe_batch_advance(bt, steps)
+        for a, b in zip(plain, batched):
+            S.sbpe_batch_remove(bt, b.ctx)
+            ua, va = _state(a)
+            ub, vb = _state(b)
+            assert np.array_equal(ua, ub) and np.array_equal(va, vb)
+            assert np.array_equal(a.receivers(), b.receivers())
+    finally:
+        S.sbpe_batch_destroy(bt)
+        for s in plain + batched:
+            s.close()

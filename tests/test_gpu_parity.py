@@ -253,3 +253,36 @@ def test_full_size_c2_apply(dtype):
     say('  rel L2', err)
     assert err < TOL[dtype]
     sol.close()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_full_size_c2_advance(dtype):
+    """Config 2 at its full size (1025^2, source, receivers), advanced by the
+    one-launch RK sweeps the benchmark times, against the oracle's literal RK4:
+    the whole state after 3 steps from a smooth nonzero state."""
+    n, nsteps = 1025, 3
+    say('full size C2 advance', dtype)
+    spec = W.spec_c2(n=n, nrec=16)
+    P = build(spec)
+    sol = solver(spec, dtype)
+    try:
+        plan = S.sbpe_plan_info(sol.ctx)
+        assert plan['fused_sweep']
+        dt = sol.dt_cfl(0.5)
+        x1, x2 = W.reference_grid(n, n)
+        u0 = rounded(np.stack([np.sin(7 * x1) * np.cos(5 * x2), np.cos(3 * x1 + 2 * x2)]), dtype)
+        v0 = rounded(np.stack([np.cos(4 * x1) * np.sin(3 * x2), np.sin(2 * x1 - x2)]), dtype)
+        t0 = 0.09          # inside the Ricker pulse
+        sol.set_state([u0], [v0], t0)
+        sol.advance(nsteps, dt)
+        ug, vg = sol.state_numpy()
+        u, v, t = [u0.copy()], [v0.copy()], t0
+        for _ in range(nsteps):
+            u, v = T.rk4_step(P, u, v, t, dt)
+            t += dt
+        eu, ev = rel(ug[0], u[0]), rel(vg[0], v[0])
+        say('  rel L2 u %.3e v %.3e' % (eu, ev))
+        tol = {'f64': 1e-11, 'f32': 1e-5}[dtype]
+        assert eu < tol and ev < tol
+    finally:
+        sol.close()

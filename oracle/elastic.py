@@ -6,7 +6,8 @@ Semidiscrete scheme (Sec. 5, eq. semidiscrete_general):
 
 * DD_ik(b) = D_ii^FC(b) for i = k, D_i b D_k for i != k (Sec. 4.6, eq. def_cd);
   the elastic operator is DD_ik(c_ijkl) u_l (Sec. 4.7) and the physical one is
-  scaled by J^{-1} (Theorem 1).
+  scaled by J^{-1} (Theorem 1).  Block(operator='wide') replaces D_ii^FC(b) by
+  D_i b D_i, the wide-stencil operator compared in Sec. 7.1 with the same SATs.
 * Discrete traction T_JL = n_I C_IJKL D_K with D_K = F_Kk D_k
   (eq. discr_traction_op, eq. chain_discrete).
 * Robin / traction SAT (Sec. 5.1, eq. sat_traction):
@@ -28,7 +29,10 @@ Parity status: pinned (tests/test_oracle_2d.py: brute-force symmetry of
 A = diag(JH, JH) D^tot and negative semidefiniteness for every boundary type and
 for a two-block interface, translation null space for traction-only blocks,
 constant-coefficient textbook reduction, isotropic reduction;
-tests/test_oracle_time.py: manufactured-solution convergence, energy).
+tests/test_oracle_time.py: manufactured-solution convergence, energy;
+tests/test_oracle_wide.py: the wide operator's squared-stencil rows, its PSD
+difference from the narrow one, symmetry, convergence and the accuracy and
+spectral-radius comparisons of Sec. 7.1).
 """
 import numpy as np
 import scipy.sparse as sps
@@ -44,9 +48,15 @@ DIM = 2
 class Block:
     """One curvilinear block: grid, density, stiffness, boundary conditions."""
 
-    def __init__(self, X1, X2, rho, C, order=4, beta=1.0):
+    def __init__(self, X1, X2, rho, C, order=4, beta=1.0, operator='narrow'):
+        if operator not in ('narrow', 'wide'):
+            raise ValueError(operator)
         self.order = order
         self.beta = beta
+        # 'narrow': D_ii^FC(c) (Sec. 4.1); 'wide': D_i c D_i with the first
+        # derivative applied twice (the wide-stencil operator the narrow one is
+        # compared with in Sec. 7.1; fully compatible in the sense of Sec. 4.7)
+        self.operator = operator
         self.X1 = np.asarray(X1, dtype=float)
         self.X2 = np.asarray(X2, dtype=float)
         self.n2, self.n1 = self.X1.shape
@@ -144,8 +154,12 @@ class Block:
         r = np.zeros((2, self.n2, self.n1))
         for j in range(2):
             for l in range(2):
-                r[j] += sbp.apply_d2fc(u[l], c[0, j, 0, l], h1, o, axis=1)
-                r[j] += sbp.apply_d2fc(u[l], c[1, j, 1, l], h2, o, axis=0)
+                if self.operator == 'wide':
+                    r[j] += sbp.apply_d1(c[0, j, 0, l] * sbp.apply_d1(u[l], h1, o, axis=1), h1, o, axis=1)
+                    r[j] += sbp.apply_d1(c[1, j, 1, l] * sbp.apply_d1(u[l], h2, o, axis=0), h2, o, axis=0)
+                else:
+                    r[j] += sbp.apply_d2fc(u[l], c[0, j, 0, l], h1, o, axis=1)
+                    r[j] += sbp.apply_d2fc(u[l], c[1, j, 1, l], h2, o, axis=0)
                 r[j] += sbp.apply_d1(c[0, j, 1, l] * sbp.apply_d1(u[l], h2, o, axis=0), h1, o, axis=1)
                 r[j] += sbp.apply_d1(c[1, j, 0, l] * sbp.apply_d1(u[l], h1, o, axis=1), h2, o, axis=0)
         return r

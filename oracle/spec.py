@@ -27,7 +27,7 @@ def build(spec, beta=1.0):
     blocks = []
     for b in spec['blocks']:
         blocks.append(E.Block(b['X1'], b['X2'], b['rho'], M.full_from_c10(b['C10']),
-                              order=spec['order'], beta=beta))
+                              order=spec['order'], beta=beta, operator=spec.get('operator', 'narrow')))
     itfs = [E.Interface(a, fa, bb, fb, reversed=bool(rev)) for (a, fa, bb, fb, rev) in spec.get('interfaces', [])]
     # jump data (Sec. 6): (interface index, V, Theta, time_fn, params), side a's order
     for (k, V, Th, tk, tp) in spec.get('interface_data', []):

@@ -91,6 +91,17 @@ sbpe_status sbpe_add_block(sbpe_ctx_t ctx, int n1, int n2, const double* X1, con
  * no factor 2, index 6 <-> 12) of a normal material to the C10 layout. */
 sbpe_status sbpe_voigt_to_c10(const double* voigt, size_t npts, double* C10);
 
+/* Second-derivative operator of the i = k terms DD_ii(c) of the elastic
+ * operator (Sec. 4.6): SBPE_OP_NARROW (default) the adapted fully compatible
+ * narrow-stencil D2^FC(c) of Sec. 4.1; SBPE_OP_WIDE the wide-stencil D_i c D_i
+ * (the first derivative applied twice), the operator the narrow one is
+ * compared with in Sec. 7.1, with the same SATs.  Call before sbpe_finalize
+ * (SBPE_ESTATE after it; SBPE_EINVAL for another value).  A wide context
+ * supports sbpe_apply, sbpe_advance and the energy; it cannot join a batch
+ * and sbpe_grad_accumulate rejects it (SBPE_EINVAL). */
+enum { SBPE_OP_NARROW = 0, SBPE_OP_WIDE = 1 };
+sbpe_status sbpe_set_operator(sbpe_ctx_t ctx, int op);
+
 /* Boundary condition of a face (Sec. 5): traction, Robin (U: [2][2][nf]
  * symmetric positive semidefinite U_JL at the face points, row-major JL;
  * required for Robin, ignored otherwise) or displacement.  Interfaces are made

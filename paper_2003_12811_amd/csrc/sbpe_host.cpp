@@ -155,6 +155,7 @@ struct sbpe_ctx {
     hipEvent_t ev_main = nullptr, ev_side = nullptr;
     int dtype = SBPE_F64;
     int order = 4;
+    int op = SBPE_OP_NARROW;        // second-derivative operator of the i = k terms
     double beta = 1.0;
     bool host_only = false;
     std::string err;
@@ -685,6 +686,7 @@ static PassArgs base_args(const sbpe_ctx* c) {
     std::memset(&a, 0, sizeof a);
     a.blocks = c->d_desc;
     a.nblocks = (int)c->blocks.size();
+    a.wide = c->op == SBPE_OP_WIDE ? 1 : 0;
     return a;
 }
 
@@ -746,7 +748,7 @@ static sbpe_status run_pass(sbpe_ctx* c, const PassArgs& a) {
     // launch kinds: 2 * pass index (RK1 = 0, RK2 = 1, APPLY = 2) + (0 interior, 1 frame)
     const int pk = a.pass == PASS_RK1 ? 0 : a.pass == PASS_RK2 ? 1 : 2;
     sbpe_status s;
-    if (c->frame_sp && sweep_fused(c->total_tiles)) {
+    if (c->frame_sp && c->op == SBPE_OP_NARROW && sweep_fused(c->total_tiles)) {
         // assembled frame operator: frame and interior in one launch on the context stream
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
@@ -947,6 +949,14 @@ static sbpe_status check_face(sbpe_ctx* c, int block, int face) {
     return SBPE_OK;
 }
 
+sbpe_status sbpe_set_operator(sbpe_ctx_t c, int op) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
+    if (op != SBPE_OP_NARROW && op != SBPE_OP_WIDE) return fail(c, SBPE_EINVAL, "operator must be narrow or wide");
+    c->op = op;
+    return SBPE_OK;
+}
+
 sbpe_status sbpe_set_bc(sbpe_ctx_t c, int block, int face, int bc, const double* U) {
     sbpe_status s = check_face(c, block, face);
     if (s) return s;
@@ -1073,20 +1083,25 @@ sbpe_status sbpe_add_receivers(sbpe_ctx_t c, int block, int n, const double* x1,
 
 // ------------------------------------------------- assembled frame operator
 // Probe the frame kernel (the definition of the frame rows) with coloured unit
-// fields: colour (i mod 9, j mod 9) per block and component, so that every
-// frame row sees at most one probed point of each colour (no frame stencil,
-// including the interface terms that reach the partner block, spans 9 points
-// in either direction).  Two probes with constant fields give the row sums.
-// The result is checked against the frame kernel on a random field.
-static int probe_window(int i, int n, int color) {
-    int lo = i < 6 ? 0 : (i > n - 7 ? n - 9 : i - 4);
-    lo = std::max(0, std::min(lo, std::max(0, n - 9)));
-    const int p = lo + ((color - lo % 9) % 9 + 9) % 9;
+// fields: colour (i mod P, j mod P) per block and component, so that every
+// frame row sees at most one probed point of each colour.  No frame stencil
+// of the narrow operator, including the interface terms that reach the
+// partner block, spans more than 9 points in either direction (P = 9).  The
+// wide operator's closure rows reach one point further (row 5 of order 4
+// couples points 0 .. 9 through D_1 b D_1), so it is probed with P = 11,
+// whose window (offsets -5 .. 5) holds every row.  Two probes with constant
+// fields give the row sums.  The result is checked against the frame kernel
+// on a random field.
+static int probe_window(int i, int n, int color, int P) {
+    const int back = (P - 1) / 2;
+    int lo = i < 6 ? 0 : (i > n - 7 ? n - P : i - back);
+    lo = std::max(0, std::min(lo, std::max(0, n - P)));
+    const int p = lo + ((color - lo % P) % P + P) % P;
     return p < n ? p : -1;
 }
 
 static sbpe_status assemble_frame(sbpe_ctx* c) {
-    constexpr int P = 9;
+    const int P = (c->op == SBPE_OP_WIDE && c->order == 4) ? 11 : 9;
     const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
     const int reach = c->order == 4 ? 4 : 2;
     const int nb = (int)c->blocks.size();
@@ -1194,7 +1209,7 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
         const int bp = pi / (2 * P * P), comp = (pi / (P * P)) % 2, cy = (pi / P) % P, cx = pi % P;
         const HostBlock& H = c->blocks[b];
         if (b == bp) {
-            const int ii = probe_window(i, H.n1, cx), jj = probe_window(j, H.n2, cy);
+            const int ii = probe_window(i, H.n1, cx, P), jj = probe_window(j, H.n2, cy, P);
             if (ii < 0 || jj < 0) return false;
             col = 2 * (jj * H.n1 + ii) + comp;
             return true;
@@ -1216,7 +1231,7 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
                 ip = tp;
                 jp = F.pface == 2 ? 0 : Pb.n2 - 1;
             }
-            const int ii = probe_window(ip, Pb.n1, cx), jj = probe_window(jp, Pb.n2, cy);
+            const int ii = probe_window(ip, Pb.n1, cx, P), jj = probe_window(jp, Pb.n2, cy, P);
             if (ii >= 0 && jj >= 0) {
                 col = -1 - ((f << 29) | (comp << 28) | (jj * Pb.n1 + ii));
                 return true;
@@ -1706,7 +1721,7 @@ sbpe_status sbpe_plan_info(sbpe_ctx_t c, long long* info) {
     info[2] = c->total_tiles;
     info[3] = c->total_frame_wg;
     info[4] = R;
-    info[5] = (c->frame_sp && sweep_fused(c->total_tiles)) ? 1 : 0;
+    info[5] = (c->frame_sp && c->op == SBPE_OP_NARROW && sweep_fused(c->total_tiles)) ? 1 : 0;
     return SBPE_OK;
 }
 
@@ -1854,6 +1869,7 @@ sbpe_status sbpe_batch_add(sbpe_batch_t b, sbpe_ctx_t c, int nsteps, double dt) 
     if (c->batch) return bfail(b, SBPE_ESTATE, "context already belongs to a batch");
     if (c->device != b->device || c->dtype != b->dtype || c->order != b->order)
         return bfail(b, SBPE_EINVAL, "context device, dtype or order differs from the batch");
+    if (c->op != SBPE_OP_NARROW) return bfail(b, SBPE_EINVAL, "batches take narrow-operator contexts only");
     if (nsteps <= 0 || !(dt > 0) || !std::isfinite(dt)) return bfail(b, SBPE_EINVAL, "bad nsteps or dt");
     // time functions for all its steps, receiver rows for all its steps
     sbpe_status s = fill_tau(c, nsteps, c->t, dt);
@@ -2045,6 +2061,7 @@ extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, 
     if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
     sbpe_status s = need_gpu(c);
     if (s) return s;
+    if (c->op != SBPE_OP_NARROW) return fail(c, SBPE_EINVAL, "coefficient gradients of the wide-stencil operator are not supported");
     const int nb = (int)c->blocks.size();
     if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "at most 16 blocks");
     if (!z || !y || !a || !gc || !grt) return fail(c, SBPE_EINVAL, "NULL pointer array");

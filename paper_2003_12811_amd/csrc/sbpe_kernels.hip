@@ -307,13 +307,28 @@ __device__ __forceinline__ T d2_line(gcp<T> b, gcp<T> u, long st, int r, int n) 
     return d2_dispatch<T, ORD, 0>(lo ? r : n - 1 - r, b, u, st, lo, n);
 }
 
+// h^2 (D1 b D1 u)_r on a line of n points (the wide-stencil second
+// derivative); b, u point at index 0 of the line.
+template <typename T, int ORD>
+__device__ __forceinline__ T wide_line(gcp<T> b, gcp<T> u, long st, int r, int n) {
+    T acc = 0;
+    d1_foreach<ORD>(r, n, [&](int k, double w) { acc += static_cast<T>(w) * b[(long)k * st] * d1_line<T, ORD>(u, st, k, n); });
+    return acc;
+}
+
+template <typename T, int ORD>
+__device__ __forceinline__ T second_line(bool wide, gcp<T> b, gcp<T> u, long st, int r, int n) {
+    return wide ? wide_line<T, ORD>(b, u, st, r, n) : d2_line<T, ORD>(b, u, st, r, n);
+}
+
 // -------------------------------------------------- volume at one point
 // One of the four term groups of DD_ik(c_ijkl) u_l at (i, j) with
 // boundary-aware 1-D rows (frame points):
 //   PART 0: D_11^FC(c_1j1l) u_l        PART 1: D_22^FC(c_2j2l) u_l
 //   PART 2: D_1 (c_1j2l D_2 u_l)       PART 3: D_2 (c_2j1l D_1 u_l)
+// With wide set, parts 0 and 1 take D_i c D_i instead of D_ii^FC(c).
 template <typename T, int ORD, int PART>
-__device__ __forceinline__ void volume_part(BlockRef B, gcp<T> u, int i, int j, T& r0, T& r1) {
+__device__ __forceinline__ void volume_part(BlockRef B, gcp<T> u, int i, int j, T& r0, T& r1, bool wide) {
     const int n1 = B.n1, n2 = B.n2;
     const long np = (long)n1 * n2;
     gcp<T> c = gc<T>(B.coef);
@@ -322,17 +337,17 @@ __device__ __forceinline__ void volume_part(BlockRef B, gcp<T> u, int i, int j, 
     const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
     const long rj = (long)j * n1;
     if constexpr (PART == 0) {
-        const T a00 = d2_line<T, ORD>(c + K_C1111 * np + rj, u0 + rj, 1, i, n1);
-        const T a01 = d2_line<T, ORD>(c + K_C1112 * np + rj, u1 + rj, 1, i, n1);
-        const T a10 = d2_line<T, ORD>(c + K_C1112 * np + rj, u0 + rj, 1, i, n1);
-        const T a11 = d2_line<T, ORD>(c + K_C1212 * np + rj, u1 + rj, 1, i, n1);
+        const T a00 = second_line<T, ORD>(wide, c + K_C1111 * np + rj, u0 + rj, 1, i, n1);
+        const T a01 = second_line<T, ORD>(wide, c + K_C1112 * np + rj, u1 + rj, 1, i, n1);
+        const T a10 = second_line<T, ORD>(wide, c + K_C1112 * np + rj, u0 + rj, 1, i, n1);
+        const T a11 = second_line<T, ORD>(wide, c + K_C1212 * np + rj, u1 + rj, 1, i, n1);
         r0 += (a00 + a01) * ih1 * ih1;
         r1 += (a10 + a11) * ih1 * ih1;
     } else if constexpr (PART == 1) {
-        const T b00 = d2_line<T, ORD>(c + K_C2121 * np + i, u0 + i, n1, j, n2);
-        const T b01 = d2_line<T, ORD>(c + K_C2122 * np + i, u1 + i, n1, j, n2);
-        const T b10 = d2_line<T, ORD>(c + K_C2122 * np + i, u0 + i, n1, j, n2);
-        const T b11 = d2_line<T, ORD>(c + K_C2222 * np + i, u1 + i, n1, j, n2);
+        const T b00 = second_line<T, ORD>(wide, c + K_C2121 * np + i, u0 + i, n1, j, n2);
+        const T b01 = second_line<T, ORD>(wide, c + K_C2122 * np + i, u1 + i, n1, j, n2);
+        const T b10 = second_line<T, ORD>(wide, c + K_C2122 * np + i, u0 + i, n1, j, n2);
+        const T b11 = second_line<T, ORD>(wide, c + K_C2222 * np + i, u1 + i, n1, j, n2);
         r0 += (b00 + b01) * ih2 * ih2;
         r1 += (b10 + b11) * ih2 * ih2;
     } else if constexpr (PART == 2) {
@@ -696,18 +711,18 @@ __global__ void __launch_bounds__(FRAME_WG) k_frame(PassArgs A) {
         gcp<T> u = field_ptr<T>(A, b, fld);
         if (part == 0) {
             if (hom) {
-                volume_part<T, ORD, 0>(B, u, i, j, l0, l1);
+                volume_part<T, ORD, 0>(B, u, i, j, l0, l1, A.wide != 0);
                 sat_point<T, ORD, false, 0, 2>(A, b, i, j, fld, none, l0, l1);
             }
         } else if (part == 1) {
             if (hom) {
-                volume_part<T, ORD, 1>(B, u, i, j, l0, l1);
+                volume_part<T, ORD, 1>(B, u, i, j, l0, l1, A.wide != 0);
                 sat_point<T, ORD, false, 2, 4>(A, b, i, j, fld, none, l0, l1);
             }
         } else if (part == 2) {
-            if (hom) volume_part<T, ORD, 2>(B, u, i, j, l0, l1);
+            if (hom) volume_part<T, ORD, 2>(B, u, i, j, l0, l1, A.wide != 0);
         } else {
-            if (hom) volume_part<T, ORD, 3>(B, u, i, j, l0, l1);
+            if (hom) volume_part<T, ORD, 3>(B, u, i, j, l0, l1, A.wide != 0);
             // member-wise select (a runtime choice between two structs goes through scratch memory)
             const bool second = !apply && sub;
             const W3 cw{second ? cb.w0 : ca.w0, second ? cb.w1 : ca.w1, second ? cb.w2 : ca.w2};
@@ -1484,6 +1499,230 @@ __global__ void __launch_bounds__(SPLIT ? 128 : 64) k_march(PassArgs A) {
     march_body<T, ORD, PASS, SPLIT>(A, blockIdx.x);
 }
 
+// ------------------------------------------------ wide-stencil interior
+// With the wide-stencil operator (D_ii^FC(c) replaced by D_i c D_i, the
+// operator the narrow one is compared with in Sec. 7.1) every interior term
+// is a first derivative of a first derivative, so the operator is the
+// divergence of a discrete stress:
+//   s1_j = c_1j1l D_1 u_l + c_1j2l D_2 u_l,   s2_j = c_2j1l D_1 u_l + c_2j2l D_2 u_l,
+//   (L u)_j = D_1 s1_j + D_2 s2_j.
+// At points >= R from every face all first derivatives are interior rows.
+// One wave per tile of the narrow march (same geometry and point-entry
+// ranges).  For output row j the input row j + 2H enters an LDS ring of
+// 2H + 1 rows (with H halo columns on each side); the stress is formed at the
+// middle row m = j + H from the ring, s1 into an LDS ring (D_1 s1 needs the
+// neighbouring lanes), s2 into a register window (D_2 s2 needs rows j +- H).
+// The row loop is unrolled by 2H + 1, so all slots are compile-time constants.
+template <typename T, int ORD, int PASS>
+__device__ __forceinline__ void wide_body(const PassArgs& A, int bid) {
+    using O = Op<ORD>;
+    constexpr int HF = O::HALF;
+    constexpr int NW = 2 * HF + 1;
+    constexpr int NF = PASS == PASS_APPLY ? 1 : 2;
+    constexpr int NS = 2 * NF;
+    constexpr int XW = 64 + 2 * HF;
+    constexpr int R = Frame<ORD>::R;
+    static_assert(R >= 2 * HF, "the wide interior reaches 2H rows beyond a tile");
+    constexpr T C1 = static_cast<T>(O::d1i(HF + 1));
+    constexpr T C2 = static_cast<T>(d1_outer<ORD>());
+    __shared__ T s_u[NW][NS][XW];   // input rows; column of lane l at index l + H
+    __shared__ T s_s[NW][NS][64];   // s1 rows
+
+    const int total = A.total_tiles;
+    const int per = (total + 7) / 8;
+    const int wg = (bid % 8) * per + bid / 8;
+    if (wg >= total) return;
+    const int b = find_block(A, wg, false);
+    BlockRef B = blk(A, b);
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const int tl = wg - B.tile_beg;
+    const int ty = tl / B.tiles_x, tx = tl - ty * B.tiles_x;
+    const int lane = threadIdx.x & 63;
+    const int i0 = R - HF + tx * (64 - 2 * HF);     // column of lane 0
+    const int i = i0 + lane;
+    const bool act = lane >= HF && lane < 64 - HF && i <= n1 - 1 - R;
+    const int ic = i < n1 - 1 ? i : n1 - 1;
+    // lanes 0 .. 2H-1 also load a halo column: the H columns left of lane 0
+    // (i0 - H >= R - 2H >= 0), then the H columns right of lane 63
+    const bool halo = lane < 2 * HF;
+    int ix = lane < HF ? i0 - HF + lane : i0 + 64 + (lane - HF);
+    ix = ix < n1 - 1 ? ix : n1 - 1;
+    const int xs = lane < HF ? lane : 64 + lane;
+    const int jb = R + ty * B.tile_y;
+    const int je = (jb + B.tile_y < n2 - R ? jb + B.tile_y : n2 - R) - 1;
+    const unsigned fb = (unsigned)np * (unsigned)sizeof(T);
+    const unsigned rowb = (unsigned)n1 * (unsigned)sizeof(T);
+    const unsigned lo = (unsigned)ic * (unsigned)sizeof(T);
+    const unsigned lx = (unsigned)ix * (unsigned)sizeof(T);
+    const char* cbase = (const char*)B.coef;
+    auto cf = [&](int k) { return cbase + (size_t)k * fb; };
+    const char* fin[NS];
+    {
+        const void* f0p = PASS == PASS_APPLY ? apply_in(A, b) : (PASS == PASS_RK1 ? B.u : B.a1);
+        const void* f1p = PASS == PASS_RK1 ? B.v : B.a2;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) fin[s] = (const char*)(s < 2 ? f0p : f1p) + (s & 1) * (size_t)fb;
+    }
+    const Range rg = load_range(B.tile_rng, wg - B.tile_beg);
+    const W3 ca = weights_a(A), cb = weights_b(A, B);
+    const bool force = B.force != nullptr;
+    T tauf_a = 0, tauf_b = 0;
+    if (force) {
+        tauf_a = static_cast<T>(tval(B, A, B.item_f, ca));
+        tauf_b = static_cast<T>(tval(B, A, B.item_f, cb));
+    }
+    const bool ents = rg.end > rg.beg;
+    const T ih1 = T(1.0 / B.h1), ih2 = T(1.0 / B.h2);
+    const T dt = static_cast<T>(B.dt);
+    auto d1 = [&](T um2, T um1, T up1, T up2) -> T {
+        if constexpr (HF == 2) return C1 * (up1 - um1) + C2 * (up2 - um2);
+        else return C1 * (up1 - um1);
+    };
+    // input row r into ring slot sl
+    auto stage = [&](const int sl, const int r) {
+        const unsigned q = (unsigned)r * rowb;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) s_u[sl][s][lane + HF] = ldo<T>(fin[s], q + lo);
+        if (halo) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) s_u[sl][s][xs] = ldo<T>(fin[s], q + lx);
+        }
+    };
+
+    T s2w[NS][NW];   // s2 by ring slot
+
+    // the stress at middle row m (ring slot sm; the ring holds rows m - H .. m + H)
+    auto stress = [&](auto KC, const int m) {
+        constexpr int K = decltype(KC)::value;
+        constexpr int sm = (K + HF) % NW;
+        const unsigned q = (unsigned)m * rowb + lo;
+        const T n11 = ldo<T>(cf(K_C1111), q), n12 = ldo<T>(cf(K_C1112), q), n22 = ldo<T>(cf(K_C1212), q);
+        const T p11 = ldo<T>(cf(K_C2121), q), p12 = ldo<T>(cf(K_C2122), q), p22 = ldo<T>(cf(K_C2222), q);
+        const T m00 = ldo<T>(cf(K_C1121), q), m01 = ldo<T>(cf(K_C1122), q);
+        const T m10 = ldo<T>(cf(K_C1221), q), m11 = ldo<T>(cf(K_C1222), q);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            T a[2], g[2];   // h1 D_1 u_l and h2 D_2 u_l at (i, m)
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const int x = 2 * f + l;
+                a[l] = d1(HF > 1 ? s_u[sm][x][lane] : T(0), s_u[sm][x][lane + HF - 1], s_u[sm][x][lane + HF + 1],
+                          HF > 1 ? s_u[sm][x][lane + 2 * HF] : T(0));
+                g[l] = d1(HF > 1 ? s_u[K % NW][x][lane + HF] : T(0), s_u[(K + HF - 1) % NW][x][lane + HF],
+                          s_u[(K + HF + 1) % NW][x][lane + HF], HF > 1 ? s_u[(K + 2 * HF) % NW][x][lane + HF] : T(0));
+            }
+            s_s[sm][2 * f][lane] = ih1 * (n11 * a[0] + n12 * a[1]) + ih2 * (m00 * g[0] + m01 * g[1]);
+            s_s[sm][2 * f + 1][lane] = ih1 * (n12 * a[0] + n22 * a[1]) + ih2 * (m10 * g[0] + m11 * g[1]);
+            s2w[2 * f][sm] = ih1 * (m00 * a[0] + m10 * a[1]) + ih2 * (p11 * g[0] + p12 * g[1]);
+            s2w[2 * f + 1][sm] = ih1 * (m01 * a[0] + m11 * a[1]) + ih2 * (p12 * g[0] + p22 * g[1]);
+        }
+    };
+
+    // prologue: rows jb - 2H .. jb - 1 staged (slots 1 .. 2H)
+#pragma unroll
+    for (int r = 0; r < 2 * HF; ++r) stage(r + 1, jb - 2 * HF + r);
+
+    // one row: stage row j + 2H, the stress at j + H, and (OUT) output row j
+    auto step = [&](auto KC, auto OUTC, const int j) {
+        constexpr int K = decltype(KC)::value;
+        constexpr bool OUT = decltype(OUTC)::value;
+        constexpr int sj = K % NW;
+        const int jj = j < je ? j : je;     // rows past the tile end are clamped and not stored
+        wave_sync();
+        stage((K + 2 * HF) % NW, jj + 2 * HF);
+        wave_sync();
+        stress(KC, jj + HF);
+        if constexpr (OUT) {
+            const unsigned p = (unsigned)jj * rowb + lo;
+            const T irho = ldo<T>(cf(K_IRHO), p);
+            T f0 = 0, f1 = 0;
+            if (force) {
+                f0 = ldo<T>((const char*)B.force, p);
+                f1 = ldo<T>((const char*)B.force + fb, p);
+            }
+            T xo[4] = {0, 0, 0, 0};
+            if constexpr (PASS == PASS_RK2) {
+                xo[0] = ldo<T>((const char*)B.u, p);
+                xo[1] = ldo<T>((const char*)B.u + fb, p);
+                xo[2] = ldo<T>((const char*)B.v, p);
+                xo[3] = ldo<T>((const char*)B.v + fb, p);
+            }
+            wave_sync();
+            T L[NF][2], wc[NS];
+            const int lm2 = lane - 2 < 0 ? 0 : lane - 2, lm1 = lane - 1 < 0 ? 0 : lane - 1;
+            const int lp1 = lane + 1 > 63 ? 63 : lane + 1, lp2 = lane + 2 > 63 ? 63 : lane + 2;
+#pragma unroll
+            for (int x = 0; x < NS; ++x) {
+                const T a1 = d1(HF > 1 ? s_s[sj][x][lm2] : T(0), s_s[sj][x][lm1], s_s[sj][x][lp1],
+                                HF > 1 ? s_s[sj][x][lp2] : T(0));
+                const T a2 = d1(HF > 1 ? s2w[x][(K + NW - 2) % NW] : T(0), s2w[x][(K + NW - 1) % NW],
+                                s2w[x][(K + 1) % NW], HF > 1 ? s2w[x][(K + 2) % NW] : T(0));
+                L[x >> 1][x & 1] = ih1 * a1 + ih2 * a2;
+                wc[x] = s_u[sj][x][lane + HF];
+            }
+            if (act && j <= je) {
+                const long po = (long)j * n1 + i;
+                T da0 = tauf_a * f0, da1 = tauf_a * f1, db0 = tauf_b * f0, db1 = tauf_b * f1;
+                if (ents) {
+                    if (ca.any()) point_sources<T>(B, A, rg, po, ca, da0, da1);
+                    if (NF == 2 && cb.any()) point_sources<T>(B, A, rg, po, cb, db0, db1);
+                }
+                if constexpr (PASS == PASS_APPLY) {
+                    char* o = (char*)apply_out(A, b);
+                    sto<T>(o, p, irho * (L[0][0] + da0));
+                    sto<T>(o + fb, p, irho * (L[0][1] + da1));
+                } else if constexpr (PASS == PASS_RK1) {
+                    const T hdt = T(0.5) * dt;
+                    sto<T>((char*)B.a1, p, irho * (L[0][0] + da0));
+                    sto<T>((char*)B.a1 + fb, p, irho * (L[0][1] + da1));
+                    sto<T>((char*)B.a2, p, irho * (L[0][0] + hdt * L[NF - 1][0] + db0));
+                    sto<T>((char*)B.a2 + fb, p, irho * (L[0][1] + hdt * L[NF - 1][1] + db1));
+                } else {
+                    const T dt2 = dt * dt;
+                    const T q4 = T(0.25) * dt2, q2 = T(0.5) * dt2, s6 = dt2 / T(6), d6 = dt / T(6);
+                    gp<double> ro = rec_slots(B, A);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const T A1 = wc[q];
+                        const T A2 = wc[2 + q];
+                        const T A3 = A2 + q4 * irho * L[0][q];
+                        const T A4 = T(2) * A2 - A1 + q2 * irho * (L[NF - 1][q] + (q ? db1 : db0));
+                        const T un = xo[q] + dt * xo[2 + q] + s6 * (A1 + A2 + A3);
+                        sto<T>((char*)B.u + q * fb, p, un);
+                        sto<T>((char*)B.v + q * fb, p, xo[2 + q] + d6 * (A1 + T(2) * A2 + T(2) * A3 + A4));
+                        if (ro && ents)
+                            entries_at(B, rg.mid, rg.end, po, [&](const GLB Entry& E) {
+                                ro[2 * E.id + q] = E.c0 * static_cast<double>(un);
+                            });
+                    }
+                }
+            }
+        }
+    };
+    // rows jb - 2H .. jb - 1 as middle-row producers only (their slots are 1 .. 2H)
+    step(std::integral_constant<int, 1>{}, std::false_type{}, jb - 2 * HF);
+    step(std::integral_constant<int, 2>{}, std::false_type{}, jb - 2 * HF + 1);
+    if constexpr (HF > 1) {
+        step(std::integral_constant<int, 3 % NW>{}, std::false_type{}, jb - 2);
+        step(std::integral_constant<int, 4 % NW>{}, std::false_type{}, jb - 1);
+    }
+    for (int j0 = jb; j0 <= je; j0 += NW) {
+        step(std::integral_constant<int, 0>{}, std::true_type{}, j0);
+        step(std::integral_constant<int, 1>{}, std::true_type{}, j0 + 1);
+        step(std::integral_constant<int, 2>{}, std::true_type{}, j0 + 2);
+        if constexpr (NW > 3) {
+            step(std::integral_constant<int, 3 % NW>{}, std::true_type{}, j0 + 3);
+            step(std::integral_constant<int, 4 % NW>{}, std::true_type{}, j0 + 4);
+        }
+    }
+}
+
+template <typename T, int ORD, int PASS>
+__global__ void __launch_bounds__(64) k_wide(PassArgs A) {
+    wide_body<T, ORD, PASS>(A, blockIdx.x);
+}
+
 // ---------------------------------------------------------- tau table
 // tau[(s * nitems + it) * 3 + k] = tau_it(t0 + s dt + c_k dt), c = (0, 1/2, 1)
 __global__ void __launch_bounds__(256) k_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt,
@@ -1963,11 +2202,29 @@ int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int to
     return (int)hipGetLastError();
 }
 
+template <typename T, int ORD>
+static void launch_wide_t(const PassArgs& a, int total_tiles, hipStream_t s) {
+    const dim3 g(((total_tiles + 7) / 8) * 8), bl(64);
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_wide<T, ORD, PASS_APPLY>), g, bl, 0, s, a);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_wide<T, ORD, PASS_RK1>), g, bl, 0, s, a);
+    else hipLaunchKernelGGL((k_wide<T, ORD, PASS_RK2>), g, bl, 0, s, a);
+}
+
 int launch_interior(int dtype, int order, const PassArgs& a, int total_tiles, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (total_tiles <= 0) return 0;
     PassArgs b = a;
     b.total_tiles = total_tiles;
+    if (a.wide) {
+        if (dtype == 0) {
+            if (order == 4) launch_wide_t<double, 4>(b, total_tiles, s);
+            else launch_wide_t<double, 2>(b, total_tiles, s);
+        } else {
+            if (order == 4) launch_wide_t<float, 4>(b, total_tiles, s);
+            else launch_wide_t<float, 2>(b, total_tiles, s);
+        }
+        return static_cast<int>(hipGetLastError());
+    }
     if (dtype == 0) {
         if (order == 4) launch_march_t<double, 4>(b, total_tiles, s);
         else launch_march_t<double, 2>(b, total_tiles, s);

@@ -19,6 +19,7 @@ F64, F32 = 0, 1
 FACE_X1LO, FACE_X1HI, FACE_X2LO, FACE_X2HI = 0, 1, 2, 3
 BC_TRACTION, BC_ROBIN, BC_DISPLACEMENT, BC_INTERFACE = 0, 1, 2, 3
 TIME_ZERO, TIME_ONE, TIME_COS, TIME_RICKER = 0, 1, 2, 3
+OP_NARROW, OP_WIDE = 0, 1
 
 
 class SbpeError(RuntimeError):
@@ -39,6 +40,7 @@ _PROTOS = {
     'sbpe_destroy': [_P],
     'sbpe_add_block': [_P, _I, _I, _DP, _DP, _DP, _DP, _IP],
     'sbpe_voigt_to_c10': [_DP, ctypes.c_size_t, _DP],
+    'sbpe_set_operator': [_P, _I],
     'sbpe_set_bc': [_P, _I, _I, _I, _DP],
     'sbpe_set_bc_data': [_P, _I, _I, _DP, _I, _DP],
     'sbpe_connect': [_P, _I, _I, _I, _I, _I],
@@ -157,6 +159,10 @@ def sbpe_voigt_to_c10(voigt):
     out = np.empty((10,) + shp)
     _check(None, lib().sbpe_voigt_to_c10(_dp(V), int(np.prod(shp)), _dp(out)))
     return out
+
+
+def sbpe_set_operator(ctx, op):
+    _check(ctx, lib().sbpe_set_operator(ctx, op))
 
 
 def sbpe_set_bc(ctx, block, face, bc, U=None):

@@ -43,6 +43,9 @@ class Solver:
 
     def _setup(self, spec):
         ctx = self.ctx
+        op = spec.get('operator', 'narrow')
+        if op != 'narrow':
+            S.sbpe_set_operator(ctx, {'wide': S.OP_WIDE}[op])
         for b in spec['blocks']:
             bid = S.sbpe_add_block(ctx, b['X1'], b['X2'], b['rho'], b['C10'])
             for f, (kind, g, tfn, tp, U) in enumerate(b['bc']):

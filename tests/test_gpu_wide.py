@@ -1,0 +1,233 @@
+"""The wide-stencil operator variant (D_ii^FC(c) replaced by D_i c D_i with
+the same SATs, the comparison of Sec. 7.1) through the C ABI, against the
+oracle's wide operator.
+
+* sbpe_apply on a curvilinear block with every boundary kind, data, forcing
+  and point sources (orders 4 and 2, FP64 and FP32; several interior tiles
+  with a ragged tail in both directions), and on 2x2 blocks with interfaces.
+* sbpe_advance with sources and receivers, FP64 and FP32.
+* The energy of the wide scheme, equal to the oracle's, does not grow.
+* The C1 manufactured solution: the library's wide run equals the oracle's,
+  and its error is an order of magnitude above the narrow run's.
+* A wide context cannot join a batch and has no coefficient gradient.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import timestep as T
+from oracle.spec import build, receivers
+from paper_2003_12811_amd import sbpe as S
+from paper_2003_12811_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = {'f64': 1e-11, 'f32': 1e-5}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def cat(xs):
+    return np.concatenate([np.asarray(x, dtype=float).ravel() for x in xs])
+
+
+def solver(spec, dtype='f64'):
+    from paper_2003_12811_amd.solver import Solver
+    return Solver(spec, dtype=dtype)
+
+
+def rounded(x, dtype):
+    return x.astype(np.float32).astype(np.float64) if dtype == 'f32' else x
+
+
+def wide(spec):
+    spec = dict(spec)
+    spec['operator'] = 'wide'
+    return spec
+
+
+def mixed_spec(n1, n2, order, seed=7):
+    X1, X2 = W.grid(W.GaussianTopography(0.15, 0.2), n1, n2)
+    rho, C10 = W.paper_random_material((n2, n1), seed)
+    rng = np.random.default_rng(seed)
+    nf = [n2, n2, n1, n1]
+    Q = rng.uniform(0, 1, (2, 2, n2))
+    U = np.einsum('ikf,jkf->ijf', Q, Q)
+    bc = [(W.DISPLACEMENT, rng.normal(size=(2, nf[0])), W.T_COS, (3.0, 0.2), None),
+          (W.ROBIN, rng.normal(size=(2, nf[1])), W.T_RICKER, (5.0, 0.1), U),
+          (W.TRACTION, rng.normal(size=(2, nf[2])), W.T_COS, (2.0, -0.4), None),
+          (W.DISPLACEMENT, None, W.T_ZERO, None, None)]
+    F = rng.normal(size=(2, n2, n1))
+    blk = dict(X1=X1, X2=X2, rho=rho, C10=C10, bc=bc, forcing=(F, W.T_COS, (1.5, 0.3)))
+    return dict(order=order, blocks=[blk], interfaces=[], operator='wide',
+                sources=[(0, 0.37, 0.61, 0.3, -1.0, 2.0, 8.0, 0.05), (0, 0.52, 0.5, 1.0, 0.0, 1.0, 6.0, 0.02)],
+                receivers=[])
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+@pytest.mark.parametrize("order", [4, 2])
+def test_wide_apply_single_block_all_bcs(dtype, order):
+    n1, n2 = (150, 47) if order == 4 else (131, 36)
+    say('wide apply single block', dtype, order, n1, n2)
+    spec = mixed_spec(n1, n2, order)
+    P = build(spec)
+    sol = solver(spec, dtype)
+    try:
+        rng = np.random.default_rng(11)
+        u = rounded(rng.normal(size=(2, n2, n1)), dtype)
+        for t, hom in ((0.13, False), (0.0, True)):
+            got = sol.apply([u], t=t, homogeneous=hom)[0].double().cpu().numpy()
+            if hom:
+                B = P.blocks[0]
+                ref = (P.total_operator([u], t, homogeneous=True)[0] / B.rho.ravel()).reshape(2, n2, n1)
+            else:
+                ref = P.rhs([u], t)[0]
+            err = rel(got, ref)
+            say('  t', t, 'hom', hom, 'rel L2', err)
+            assert err < TOL[dtype]
+        # the wide operator is not the narrow one
+        nspec = dict(spec)
+        nspec['operator'] = 'narrow'
+        narrow = build(nspec).rhs([u], 0.13)[0]
+        assert rel(narrow, P.rhs([u], 0.13)[0]) > 1e-3
+    finally:
+        sol.close()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_wide_apply_multiblock(dtype):
+    n = 45
+    say('wide apply 2x2 blocks', dtype, n)
+    spec = wide(W.spec_c3(n=n))
+    P = build(spec)
+    sol = solver(spec, dtype)
+    try:
+        rng = np.random.default_rng(5)
+        us = [rounded(rng.normal(size=(2, n, n)), dtype) for _ in range(4)]
+        got = [x.double().cpu().numpy() for x in sol.apply(us, t=0.11)]
+        err = rel(cat(got), cat(P.rhs(us, 0.11)))
+        say('  rel L2', err)
+        assert err < TOL[dtype]
+    finally:
+        sol.close()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_wide_advance_source_receivers(dtype):
+    n, nsteps = 97, 60
+    say('wide advance C2 geometry', n, dtype)
+    spec = wide(W.spec_c2(n=n, nrec=8))
+    # receivers inside the interior tiles as well as on the surface
+    spec['receivers'] = list(spec['receivers']) + [(0, np.array([0.43, 0.61]), np.array([0.55, 0.38]))]
+    P = build(spec)
+    sol = solver(spec, dtype)
+    try:
+        dt = T.dt_cfl(P, 0.5)
+        sol.set_state(None, None, 0.0)
+        sol.advance(nsteps, dt)
+        ug, vg = sol.state_numpy()
+        rg = sol.receivers()
+        u, v, t = [np.zeros((2, n, n))], [np.zeros((2, n, n))], 0.0
+        rec = []
+        for _ in range(nsteps):
+            u, v = T.rk4_step(P, u, v, t, dt)
+            t += dt
+            rec.append(receivers(spec, u))
+        rec = np.array(rec)
+        eu, ev, er = rel(ug[0], u[0]), rel(vg[0], v[0]), rel(rg, rec)
+        say('  rel L2 u', eu, 'v', ev, 'receivers', er)
+        assert np.abs(u[0]).max() > 0
+        assert max(eu, ev, er) < TOL[dtype]
+    finally:
+        sol.close()
+
+
+def test_wide_energy():
+    n = 61
+    say('wide energy', n)
+    spec = wide(W.spec_c2(n=n, nrec=0))
+    spec['sources'] = []
+    P = build(spec)
+    sol = solver(spec, 'f64')
+    try:
+        rng = np.random.default_rng(4)
+        u0, v0 = rng.normal(size=(2, n, n)), rng.normal(size=(2, n, n))
+        sol.set_state([u0], [v0], 0.0)
+        e_lib, e_or = sol.energy(), P.energy([u0], [v0])
+        say('  energy lib', e_lib, 'oracle', e_or)
+        assert abs(e_lib / e_or - 1) < 1e-11
+        dt = T.dt_cfl(P, 0.5)
+        prev = e_lib
+        for _ in range(5):
+            sol.advance(10, dt)
+            e = sol.energy()
+            assert e <= prev * (1 + 1e-12)
+            prev = e
+    finally:
+        sol.close()
+
+
+def test_wide_mms_matches_oracle_and_is_less_accurate():
+    n = 65
+    say('wide and narrow C1 MMS', n)
+    errs = {}
+    for op in ('wide', 'narrow'):
+        spec = W.spec_c1(n)
+        spec['operator'] = op
+        P = build(spec)
+        nst, dt = T.steps_for(0.5, T.dt_cfl(P, 0.5))
+        u0 = spec['mms']['u']
+        sol = solver(spec, 'f64')
+        try:
+            sol.set_state([u0], None, 0.0)
+            sol.advance(nst, dt)
+            ug, vg = sol.state_numpy()
+        finally:
+            sol.close()
+        B = P.blocks[0]
+        exact = u0 * np.cos(spec['mms']['omega'] * 0.5)
+        errs[op] = np.sqrt(np.sum(B.J * B.H * ((ug[0] - exact) ** 2).sum(0)))
+        if op == 'wide':
+            u, v, t = [u0.copy()], [np.zeros_like(u0)], 0.0
+            for _ in range(nst):
+                u, v = T.rk4_step(P, u, v, t, dt)
+                t += dt
+            eu, ev = rel(ug[0], u[0]), rel(vg[0], v[0])
+            say('  wide vs oracle: u', eu, 'v', ev)
+            assert eu < 1e-11 and ev < 1e-11
+    say('  MMS error wide', errs['wide'], 'narrow', errs['narrow'])
+    assert errs['wide'] > 8 * errs['narrow']
+
+
+def test_wide_context_restrictions():
+    import torch
+    n = 41
+    spec = wide(W.spec_c2(n=n, nrec=0))
+    spec['sources'] = []
+    sol = solver(spec, 'f64')
+    b = S.sbpe_batch_create(0, torch.cuda.current_stream().cuda_stream, S.F64, 4)
+    try:
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_set_operator(sol.ctx, S.OP_NARROW)
+        assert e.value.code == S.ESTATE
+        sol.set_state(None, None, 0.0)
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_batch_add(b, sol.ctx, 10, 1e-3)
+        assert e.value.code == S.EINVAL
+        z = [torch.zeros((2, n, n), dtype=torch.float64, device='cuda')]
+        gc = [torch.zeros((10, n, n), dtype=torch.float64, device='cuda')]
+        grt = [torch.zeros((n, n), dtype=torch.float64, device='cuda')]
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_grad_accumulate(sol.ctx, [z[0].data_ptr()], [z[0].data_ptr()], [z[0].data_ptr()], 1.0, 0.0, 1,
+                                   [gc[0].data_ptr()], [grt[0].data_ptr()])
+        assert e.value.code == S.EINVAL
+    finally:
+        S.sbpe_batch_destroy(b)
+        sol.close()

@@ -133,6 +133,27 @@ def test_error_codes():
         S.sbpe_create(-1, None, S.F64, 4, 0.5)
 
 
+def test_set_operator_states():
+    n = 15
+    X1, X2 = W.grid(W.Identity(), n, n)
+    rho, C10 = W.paper_random_material((n, n), 0)
+    ctx = _host_ctx()
+    try:
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_set_operator(ctx, 5)
+        assert e.value.code == S.EINVAL
+        S.sbpe_set_operator(ctx, S.OP_WIDE)
+        S.sbpe_set_operator(ctx, S.OP_NARROW)
+        S.sbpe_set_operator(ctx, S.OP_WIDE)
+        S.sbpe_add_block(ctx, X1, X2, rho, C10)
+        S.sbpe_finalize(ctx)
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_set_operator(ctx, S.OP_NARROW)
+        assert e.value.code == S.ESTATE
+    finally:
+        S.sbpe_destroy(ctx)
+
+
 def _finalize_status(M4):
     """sbpe_finalize on a small host-only block whose stiffness, as the 4x4
     matrix over the pairs (11, 12, 21, 22), is M4 at every point."""

@@ -10,10 +10,10 @@ on the bottom face and traction SATs elsewhere, a 10 Hz Ricker point force and
 sources, receivers).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.  The primary result is
-FP64; the FP32 variant, the plain operator apply, a working set larger than
-the MALL (2x2 blocks of 2049^2, FP32) and a served stream of shots
-(continuous batching against sequential plain solves, p50/p99 latency) are
-reported beside it.
+FP64; the FP32 variant, the plain operator apply, the same workload with the
+wide-stencil operator, a working set larger than the MALL (2x2 blocks of
+2049^2, FP32) and a served stream of shots (continuous batching against
+sequential plain solves, p50/p99 latency) are reported beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -195,6 +195,7 @@ def main():
     ap.add_argument('--cpu-steps', type=int, default=10)
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-large', action='store_true')
+    ap.add_argument('--no-wide', action='store_true')
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
@@ -245,6 +246,20 @@ def main():
                 "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4),
                 "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4)},
     }
+    if not args.no_wide:
+        log('wide-stencil operator, fp64')
+        spw = dict(spec)
+        spw['operator'] = 'wide'
+        rw = run_gpu(spw, 'f64', args.steps, args.warmup, apply_reps=50)
+        kw = dominant(rw)
+        line["wide"] = {"workload": "the same %dx%d workload with the wide-stencil operator D_i c D_i, FP64"
+                                    % (args.n, args.n),
+                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'],
+                        "roofline": roofline(kw, rw['kernels'][kw][0], swept_points(rw['plan']), 8),
+                        "apply_roofline": roofline('interior_apply', rw['apply_kernels']['interior_apply'][0],
+                                                   swept_points(rw['plan']), 8),
+                        "kernels_ms": {kk: v[0] for kk, v in rw['kernels'].items() if v[1]}}
+        log('  %.3f ms/step, %.3e updates/s' % (rw['ms_per_step'], rw['updates_per_s']))
     if not args.no_large:
         log('large working set: 2x2 blocks of %d^2, fp32' % args.large_n)
         t0 = time.time()

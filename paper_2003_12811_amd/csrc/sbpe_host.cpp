@@ -748,7 +748,7 @@ static sbpe_status run_pass(sbpe_ctx* c, const PassArgs& a) {
     // launch kinds: 2 * pass index (RK1 = 0, RK2 = 1, APPLY = 2) + (0 interior, 1 frame)
     const int pk = a.pass == PASS_RK1 ? 0 : a.pass == PASS_RK2 ? 1 : 2;
     sbpe_status s;
-    if (c->frame_sp && c->op == SBPE_OP_NARROW && sweep_fused(c->total_tiles)) {
+    if (c->frame_sp && sweep_fused(c->total_tiles)) {
         // assembled frame operator: frame and interior in one launch on the context stream
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
@@ -1721,7 +1721,7 @@ sbpe_status sbpe_plan_info(sbpe_ctx_t c, long long* info) {
     info[2] = c->total_tiles;
     info[3] = c->total_frame_wg;
     info[4] = R;
-    info[5] = (c->frame_sp && c->op == SBPE_OP_NARROW && sweep_fused(c->total_tiles)) ? 1 : 0;
+    info[5] = (c->frame_sp && sweep_fused(c->total_tiles)) ? 1 : 0;
     return SBPE_OK;
 }
 

@@ -1566,9 +1566,8 @@ __device__ __forceinline__ void wide_body(const PassArgs& A, int bid) {
     }
     const Range rg = load_range(B.tile_rng, wg - B.tile_beg);
     const W3 ca = weights_a(A), cb = weights_b(A, B);
-    const bool force = B.force != nullptr;
     T tauf_a = 0, tauf_b = 0;
-    if (force) {
+    if (B.force != nullptr) {
         tauf_a = static_cast<T>(tval(B, A, B.item_f, ca));
         tauf_b = static_cast<T>(tval(B, A, B.item_f, cb));
     }
@@ -1579,7 +1578,42 @@ __device__ __forceinline__ void wide_body(const PassArgs& A, int bid) {
         if constexpr (HF == 2) return C1 * (up1 - um1) + C2 * (up2 - um2);
         else return C1 * (up1 - um1);
     };
-    // input row r into ring slot sl
+    // global loads of one step, issued one step ahead of their use: the
+    // entering row (and the halo column of lanes 0 .. 2H-1), the ten stiffness
+    // fields at the middle row, and the per-point operands of the output row
+    struct WLead {
+        T w[NS], wx[NS];
+        T c[10];
+        T pt[3];
+        T xo[PASS == PASS_RK2 ? 4 : 1];
+    };
+    const bool force = B.force != nullptr;
+    const char* frc = force ? (const char*)B.force : cbase + (size_t)K_IRHO * fb;
+    const unsigned frc1 = force ? fb : 0u;
+    auto load_lead = [&](int j, WLead& P) {
+        const int jj = j < je ? j : je;
+        const unsigned ql = (unsigned)(jj + 2 * HF) * rowb;
+        const unsigned qm = (unsigned)(jj + HF) * rowb + lo;
+        const unsigned qj = (unsigned)jj * rowb + lo;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) P.w[s] = ldo<T>(fin[s], ql + lo);
+        if (halo) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) P.wx[s] = ldo<T>(fin[s], ql + lx);
+        }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) P.c[k] = ldo<T>(cf(k), qm);
+        P.pt[0] = ldo<T>(cf(K_IRHO), qj);
+        P.pt[1] = ldo<T>(frc, qj);
+        P.pt[2] = ldo<T>(frc + frc1, qj);
+        if constexpr (PASS == PASS_RK2) {
+            P.xo[0] = ldo<T>((const char*)B.u, qj);
+            P.xo[1] = ldo<T>((const char*)B.u + fb, qj);
+            P.xo[2] = ldo<T>((const char*)B.v, qj);
+            P.xo[3] = ldo<T>((const char*)B.v + fb, qj);
+        }
+    };
+    // input row r into ring slot sl (prologue)
     auto stage = [&](const int sl, const int r) {
         const unsigned q = (unsigned)r * rowb;
 #pragma unroll
@@ -1592,15 +1626,13 @@ __device__ __forceinline__ void wide_body(const PassArgs& A, int bid) {
 
     T s2w[NS][NW];   // s2 by ring slot
 
-    // the stress at middle row m (ring slot sm; the ring holds rows m - H .. m + H)
-    auto stress = [&](auto KC, const int m) {
+    // the stress at the middle row (ring slot sm; the ring holds rows m - H .. m + H)
+    auto stress = [&](auto KC, const T (&c)[10]) {
         constexpr int K = decltype(KC)::value;
         constexpr int sm = (K + HF) % NW;
-        const unsigned q = (unsigned)m * rowb + lo;
-        const T n11 = ldo<T>(cf(K_C1111), q), n12 = ldo<T>(cf(K_C1112), q), n22 = ldo<T>(cf(K_C1212), q);
-        const T p11 = ldo<T>(cf(K_C2121), q), p12 = ldo<T>(cf(K_C2122), q), p22 = ldo<T>(cf(K_C2222), q);
-        const T m00 = ldo<T>(cf(K_C1121), q), m01 = ldo<T>(cf(K_C1122), q);
-        const T m10 = ldo<T>(cf(K_C1221), q), m11 = ldo<T>(cf(K_C1222), q);
+        const T n11 = c[K_C1111], n12 = c[K_C1112], n22 = c[K_C1212];
+        const T p11 = c[K_C2121], p12 = c[K_C2122], p22 = c[K_C2222];
+        const T m00 = c[K_C1121], m01 = c[K_C1122], m10 = c[K_C1221], m11 = c[K_C1222];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             T a[2], g[2];   // h1 D_1 u_l and h2 D_2 u_l at (i, m)
@@ -1622,32 +1654,37 @@ __device__ __forceinline__ void wide_body(const PassArgs& A, int bid) {
     // prologue: rows jb - 2H .. jb - 1 staged (slots 1 .. 2H)
 #pragma unroll
     for (int r = 0; r < 2 * HF; ++r) stage(r + 1, jb - 2 * HF + r);
+    WLead P;
+    load_lead(jb - 2 * HF, P);
 
     // one row: stage row j + 2H, the stress at j + H, and (OUT) output row j
     auto step = [&](auto KC, auto OUTC, const int j) {
         constexpr int K = decltype(KC)::value;
         constexpr bool OUT = decltype(OUTC)::value;
         constexpr int sj = K % NW;
+        constexpr int sl = (K + 2 * HF) % NW;
         const int jj = j < je ? j : je;     // rows past the tile end are clamped and not stored
         wave_sync();
-        stage((K + 2 * HF) % NW, jj + 2 * HF);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) s_u[sl][s][lane + HF] = P.w[s];
+        if (halo) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) s_u[sl][s][xs] = P.wx[s];
+        }
+        T c[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) c[k] = P.c[k];
+        const T irho = P.pt[0], f0 = P.pt[1], f1 = P.pt[2];
+        T xo[4] = {0, 0, 0, 0};
+        if constexpr (PASS == PASS_RK2) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xo[k] = P.xo[k];
+        }
+        load_lead(j + 1, P);
         wave_sync();
-        stress(KC, jj + HF);
+        stress(KC, c);
         if constexpr (OUT) {
             const unsigned p = (unsigned)jj * rowb + lo;
-            const T irho = ldo<T>(cf(K_IRHO), p);
-            T f0 = 0, f1 = 0;
-            if (force) {
-                f0 = ldo<T>((const char*)B.force, p);
-                f1 = ldo<T>((const char*)B.force + fb, p);
-            }
-            T xo[4] = {0, 0, 0, 0};
-            if constexpr (PASS == PASS_RK2) {
-                xo[0] = ldo<T>((const char*)B.u, p);
-                xo[1] = ldo<T>((const char*)B.u + fb, p);
-                xo[2] = ldo<T>((const char*)B.v, p);
-                xo[3] = ldo<T>((const char*)B.v + fb, p);
-            }
             wave_sync();
             T L[NF][2], wc[NS];
             const int lm2 = lane - 2 < 0 ? 0 : lane - 2, lm1 = lane - 1 < 0 ? 0 : lane - 1;
@@ -1721,6 +1758,15 @@ __device__ __forceinline__ void wide_body(const PassArgs& A, int bid) {
 template <typename T, int ORD, int PASS>
 __global__ void __launch_bounds__(64) k_wide(PassArgs A) {
     wide_body<T, ORD, PASS>(A, blockIdx.x);
+}
+
+// one sweep of the wide-stencil operator in one launch: frame workgroups
+// first (as k_pass), then the interior tiles
+template <typename T, int ORD, int PASS>
+__global__ void __launch_bounds__(64) k_pass_wide(PassArgs A, int nframe) {
+    const int bid = (int)blockIdx.x;
+    if (bid < nframe) frame_sp_body<T, ORD, PASS>(A, bid, 64);
+    else wide_body<T, ORD, PASS>(A, bid - nframe);
 }
 
 // ---------------------------------------------------------- tau table
@@ -2187,11 +2233,32 @@ static void launch_pass_t(const PassArgs& a, int total_tiles, int total_frame_wg
     else hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK2, false>), g, bl, 0, s, a, nframe);
 }
 
+template <typename T, int ORD>
+static void launch_pass_wide_t(const PassArgs& a, int total_tiles, int total_frame_wg, hipStream_t s) {
+    const long fpts = (long)total_frame_wg * FRAME_PTS;
+    const int ppw = 64 / FRAME_LANES;
+    const int nframe = (int)(((fpts + ppw - 1) / ppw + 7) / 8 * 8);
+    const dim3 g(nframe + ((total_tiles + 7) / 8) * 8), bl(64);
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_APPLY>), g, bl, 0, s, a, nframe);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_RK1>), g, bl, 0, s, a, nframe);
+    else hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_RK2>), g, bl, 0, s, a, nframe);
+}
+
 int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     PassArgs b = a;
     b.total_tiles = total_tiles;
     b.total_frame_wg = total_frame_wg;
+    if (a.wide) {
+        if (dtype == 0) {
+            if (order == 4) launch_pass_wide_t<double, 4>(b, total_tiles, total_frame_wg, s);
+            else launch_pass_wide_t<double, 2>(b, total_tiles, total_frame_wg, s);
+        } else {
+            if (order == 4) launch_pass_wide_t<float, 4>(b, total_tiles, total_frame_wg, s);
+            else launch_pass_wide_t<float, 2>(b, total_tiles, total_frame_wg, s);
+        }
+        return (int)hipGetLastError();
+    }
     if (dtype == 0) {
         if (order == 4) launch_pass_t<double, 4>(b, total_tiles, total_frame_wg, s);
         else launch_pass_t<double, 2>(b, total_tiles, total_frame_wg, s);

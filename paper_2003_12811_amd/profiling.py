@@ -35,7 +35,7 @@ def source_hash(path=KERNEL_SOURCE):
 
 def kernel_kind(name):
     """'interior_rk1/f64' style label of a library kernel name, or None."""
-    m = re.search(r'sbpe::k_(march|pass|frame_sp|frame)<(double|float), (\d)(?:, (\d))?', name)
+    m = re.search(r'sbpe::k_(march|pass_wide|pass|frame_sp|frame|wide)<(double|float), (\d)(?:, (\d))?', name)
     if not m:
         return None
     part, ty, order, p = m.group(1), m.group(2), m.group(3), m.group(4)
@@ -43,6 +43,9 @@ def kernel_kind(name):
     if part in ('march', 'pass'):
         # a one-launch sweep (k_pass) also updates the frame points
         return 'interior_%s/%s/o%s' % (('apply', 'rk1', 'rk2')[int(p)], dt, order)
+    if part in ('wide', 'pass_wide'):
+        # the wide-stencil operator's tiles (a one-launch sweep also updates the frame points)
+        return 'wide_%s/%s/o%s' % (('apply', 'rk1', 'rk2')[int(p)], dt, order)
     if part == 'frame_sp':
         return 'frame_%s/%s/o%s' % (('apply', 'rk1', 'rk2')[int(p)], dt, order)
     # the stencil form of the frame rows, run at setup to assemble the operator

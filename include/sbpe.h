@@ -96,9 +96,8 @@ sbpe_status sbpe_voigt_to_c10(const double* voigt, size_t npts, double* C10);
  * narrow-stencil D2^FC(c) of Sec. 4.1; SBPE_OP_WIDE the wide-stencil D_i c D_i
  * (the first derivative applied twice), the operator the narrow one is
  * compared with in Sec. 7.1, with the same SATs.  Call before sbpe_finalize
- * (SBPE_ESTATE after it; SBPE_EINVAL for another value).  A wide context
- * supports sbpe_apply, sbpe_advance and the energy; it cannot join a batch
- * and sbpe_grad_accumulate rejects it (SBPE_EINVAL). */
+ * (SBPE_ESTATE after it; SBPE_EINVAL for another value).  Every other entry
+ * point works with either operator; the members of one batch share it. */
 enum { SBPE_OP_NARROW = 0, SBPE_OP_WIDE = 1 };
 sbpe_status sbpe_set_operator(sbpe_ctx_t ctx, int op);
 
@@ -272,7 +271,10 @@ const char* sbpe_batch_last_error(sbpe_batch_t batch);
 /* Admit a finalized context with a bound state for nsteps RK4 steps of size
  * dt starting at its current time.  Its time functions for all nsteps steps
  * are tabulated and its receiver buffer is sized here.  While it is a member,
- * sbpe_advance, sbpe_apply and sbpe_bind_state on it fail with SBPE_ESTATE. */
+ * sbpe_advance, sbpe_apply and sbpe_bind_state on it fail with SBPE_ESTATE.
+ * The members of a batch share device, dtype, order and operator
+ * (sbpe_set_operator; the first member of an empty batch sets it): a context
+ * that differs is refused with SBPE_EINVAL. */
 sbpe_status sbpe_batch_add(sbpe_batch_t batch, sbpe_ctx_t ctx, int nsteps, double dt);
 
 /* Remove a member (normally once its remaining step count is 0).  Work later

@@ -25,7 +25,9 @@ The gradient is the exact derivative of the discrete map:
   (z/rho)^T D^tot(C) Y, written out term by term from the definitions:
     - narrow terms: w^T D2^FC(b) y with D2^FC(b) = H^{-1}(-D1^T H b D1 - R(b)
       - e0 b0 e0^T D1 + eN bN eN^T D1) and R(b) = sum_w gamma_w B_w(b) d_w d_w^T / h
-      (Sec. 4, eq. sbp_property_2nd_der, B_structure_1d; Sec. 4.1);
+      (Sec. 4, eq. sbp_property_2nd_der, B_structure_1d; Sec. 4.1); with the
+      wide-stencil operator D_i b D_i (Sec. 7.1) these terms take the form of
+      the mixed ones, (D_i^T w) (D_i y);
     - mixed terms: w^T D_i (c D_k y) -> (D_i^T w) (D_k y) (Sec. 4.6);
     - traction SAT: -(JH)^{-1} e_f Jhat H_f n_I C_IJKL D_K y_L (Sec. 5.1);
     - displacement SAT: (JH)^{-1} (T^T - Z^T) e_f Jhat H_f delta (Sec. 5.2).
@@ -80,12 +82,18 @@ def coef_gradient(P, k, w, Y, t=0.0, homogeneous=True):
     # volume: (w / J)^T DD(c) Y, then c = F J C F
     z = w / B.J
     gc = np.zeros((2, 2, 2, 2, n2, n1))
+    D1x, D1y = sbp._ops(n1, h1, o)[1], sbp._ops(n2, h2, o)[1]
     for j in range(2):
         for l in range(2):
-            gc[0, j, 0, l] += d2fc_coef_grad(z[j], Y[l], h1, o, axis=1)
-            gc[1, j, 1, l] += d2fc_coef_grad(z[j], Y[l], h2, o, axis=0)
-            gc[0, j, 1, l] += sbp._along(sbp._ops(n1, h1, o)[1].T, z[j], 1) * sbp.apply_d1(Y[l], h2, o, axis=0)
-            gc[1, j, 0, l] += sbp._along(sbp._ops(n2, h2, o)[1].T, z[j], 0) * sbp.apply_d1(Y[l], h1, o, axis=1)
+            if B.operator == 'wide':
+                # w^T D_i (b D_i y) -> (D_i^T w) (D_i y), like the mixed terms
+                gc[0, j, 0, l] += sbp._along(D1x.T, z[j], 1) * sbp.apply_d1(Y[l], h1, o, axis=1)
+                gc[1, j, 1, l] += sbp._along(D1y.T, z[j], 0) * sbp.apply_d1(Y[l], h2, o, axis=0)
+            else:
+                gc[0, j, 0, l] += d2fc_coef_grad(z[j], Y[l], h1, o, axis=1)
+                gc[1, j, 1, l] += d2fc_coef_grad(z[j], Y[l], h2, o, axis=0)
+            gc[0, j, 1, l] += sbp._along(D1x.T, z[j], 1) * sbp.apply_d1(Y[l], h2, o, axis=0)
+            gc[1, j, 0, l] += sbp._along(D1y.T, z[j], 0) * sbp.apply_d1(Y[l], h1, o, axis=1)
     gC = np.einsum('Ii...,ijkl...,Kk...->IjKl...', B.F, gc, B.F) * B.J
     gCf = gC.reshape(2, 2, 2, 2, -1)
     JH = (B.J * B.H).ravel()

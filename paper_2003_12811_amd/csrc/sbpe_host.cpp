@@ -1802,6 +1802,7 @@ struct sbpe_batch {
     hipStream_t side = nullptr;
     hipEvent_t ev_main = nullptr, ev_side = nullptr;
     int dtype = SBPE_F64, order = 4;
+    int op = SBPE_OP_NARROW;     // operator of the members (set by the first member of an empty batch)
     std::string err;
     std::vector<BatchMember> members;
     std::vector<BlockDesc> desc;
@@ -1869,7 +1870,8 @@ sbpe_status sbpe_batch_add(sbpe_batch_t b, sbpe_ctx_t c, int nsteps, double dt) 
     if (c->batch) return bfail(b, SBPE_ESTATE, "context already belongs to a batch");
     if (c->device != b->device || c->dtype != b->dtype || c->order != b->order)
         return bfail(b, SBPE_EINVAL, "context device, dtype or order differs from the batch");
-    if (c->op != SBPE_OP_NARROW) return bfail(b, SBPE_EINVAL, "batches take narrow-operator contexts only");
+    if (!b->members.empty() && c->op != b->op)
+        return bfail(b, SBPE_EINVAL, "context operator (narrow or wide) differs from the batch members'");
     if (nsteps <= 0 || !(dt > 0) || !std::isfinite(dt)) return bfail(b, SBPE_EINVAL, "bad nsteps or dt");
     // time functions for all its steps, receiver rows for all its steps
     sbpe_status s = fill_tau(c, nsteps, c->t, dt);
@@ -1893,6 +1895,7 @@ sbpe_status sbpe_batch_add(sbpe_batch_t b, sbpe_ctx_t c, int nsteps, double dt) 
     BHIPCHECK(b, hipStreamWaitEvent(b->stream, c->ev_main, 0));
     BHIPCHECK(b, hipStreamWaitEvent(b->side, c->ev_main, 0));
     c->batch = b;
+    if (b->members.empty()) b->op = c->op;
     b->members.push_back(BatchMember{c, dt, nsteps, b->step, c->rec_steps});
     b->dirty = true;
     return SBPE_OK;
@@ -2020,6 +2023,7 @@ extern "C" sbpe_status sbpe_batch_advance(sbpe_batch_t b, int nsteps) {
         p1.blocks = b->d_desc;
         p1.nblocks = (int)b->desc.size();
         p1.pass = PASS_RK1;
+        p1.wide = b->op == SBPE_OP_WIDE ? 1 : 0;
         p1.step = b->step + k;
         p1.rec_base = 0;
         p1.wa[0] = 1.0;
@@ -2061,7 +2065,6 @@ extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, 
     if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
     sbpe_status s = need_gpu(c);
     if (s) return s;
-    if (c->op != SBPE_OP_NARROW) return fail(c, SBPE_EINVAL, "coefficient gradients of the wide-stencil operator are not supported");
     const int nb = (int)c->blocks.size();
     if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "at most 16 blocks");
     if (!z || !y || !a || !gc || !grt) return fail(c, SBPE_EINVAL, "NULL pointer array");
@@ -2080,6 +2083,7 @@ extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, 
     g.blocks = c->d_desc;
     g.nblocks = nb;
     g.homogeneous = homogeneous ? 1 : 0;
+    g.wide = c->op == SBPE_OP_WIDE ? 1 : 0;
     g.alpha = alpha;
     g.tau = c->d_tau;
     long off = 0;

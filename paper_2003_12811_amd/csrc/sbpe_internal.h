@@ -167,6 +167,7 @@ struct GradArgs {
     const BlockDesc* blocks;
     int nblocks;
     int homogeneous;      // displacement data left out of delta = y - g(t)
+    int wide;             // wide-stencil operator: the i = k terms are D_i c D_i
     long off[MAX_APPLY_BLOCKS + 1];   // first flat point of each block in the launch
     double alpha;
     const double* tau;    // tabulated time functions at t (row 0)

@@ -1995,29 +1995,42 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     const double hn1 = hnorm<ORD>(i, n1), hn2 = hnorm<ORD>(j, n2);
     const long row = (long)j * n1;
     double g[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    // narrow terms (stored fields: x1 C1111, C1112, C1212; x2 C2121, C2122, C2222)
+    double tzx[2], tzy[2], dyx[2], dyy[2];   // (D^T H z) and D y along x1 and x2 at p
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        tzx[c] = d1t_weighted<T, ORD>(z + c * np + row, 1, i, n1);
+        tzy[c] = d1t_weighted<T, ORD>(z + c * np + i, n1, j, n2);
+        dyx[c] = (double)d1_line<T, ORD>(y + c * np + row, 1, i, n1);
+        dyy[c] = (double)d1_line<T, ORD>(y + c * np + i, n1, j, n2);
+    }
+    // i = k terms (stored fields: x1 C1111, C1112, C1212; x2 C2121, C2122, C2222)
     {
         const double fx = h2 * hn2 / h1, fy = h1 * hn1 / h2;
         double a00, a01, a11;
-        d2_coef_grad_pairs<T, ORD>(z + row, z + np + row, y + row, y + np + row, 1, i, n1, a00, a01, a11);
+        if (G.wide) {
+            // z^T H D_1 b D_1 y: dB/db_p = (D_1^T H z)(p) (D_1 y)(p), as for the mixed terms
+            a00 = tzx[0] * dyx[0];
+            a01 = tzx[0] * dyx[1] + tzx[1] * dyx[0];
+            a11 = tzx[1] * dyx[1];
+        } else {
+            d2_coef_grad_pairs<T, ORD>(z + row, z + np + row, y + row, y + np + row, 1, i, n1, a00, a01, a11);
+        }
         g[K_C1111] += fx * a00;
         g[K_C1112] += fx * a01;
         g[K_C1212] += fx * a11;
-        d2_coef_grad_pairs<T, ORD>(z + i, z + np + i, y + i, y + np + i, n1, j, n2, a00, a01, a11);
+        if (G.wide) {
+            a00 = tzy[0] * dyy[0];
+            a01 = tzy[0] * dyy[1] + tzy[1] * dyy[0];
+            a11 = tzy[1] * dyy[1];
+        } else {
+            d2_coef_grad_pairs<T, ORD>(z + i, z + np + i, y + i, y + np + i, n1, j, n2, a00, a01, a11);
+        }
         g[K_C2121] += fy * a00;
         g[K_C2122] += fy * a01;
         g[K_C2222] += fy * a11;
     }
     // mixed terms: M_ab = c_1a2b (C1121, C1122, C1221, C1222)
     {
-        double tzx[2], tzy[2], dyx[2], dyy[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            tzx[c] = d1t_weighted<T, ORD>(z + c * np + row, 1, i, n1);
-            tzy[c] = d1t_weighted<T, ORD>(z + c * np + i, n1, j, n2);
-            dyx[c] = (double)d1_line<T, ORD>(y + c * np + row, 1, i, n1);
-            dyy[c] = (double)d1_line<T, ORD>(y + c * np + i, n1, j, n2);
-        }
         const int km[2][2] = {{K_C1121, K_C1122}, {K_C1221, K_C1222}};
 #pragma unroll
         for (int aa = 0; aa < 2; ++aa)

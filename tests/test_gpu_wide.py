@@ -9,7 +9,8 @@ oracle's wide operator.
 * The energy of the wide scheme, equal to the oracle's, does not grow.
 * The C1 manufactured solution: the library's wide run equals the oracle's,
   and its error is an order of magnitude above the narrow run's.
-* A wide context cannot join a batch and has no coefficient gradient.
+* Wide shots advanced in one batch equal their plain advances bitwise.
+* The misfit gradient of the wide scheme equals the oracle's discrete adjoint.
 """
 import sys
 
@@ -206,28 +207,70 @@ def test_wide_mms_matches_oracle_and_is_less_accurate():
     assert errs['wide'] > 8 * errs['narrow']
 
 
-def test_wide_context_restrictions():
+def test_wide_batch_equals_plain_advance():
+    """Two wide shots of different sizes and steps advanced in one batch equal
+    their sbpe_advance runs bitwise; a narrow context cannot join them, and a
+    finalized context keeps its operator."""
     import torch
-    n = 41
-    spec = wide(W.spec_c2(n=n, nrec=0))
-    spec['sources'] = []
-    sol = solver(spec, 'f64')
+    specs = [wide(W.spec_c2(n=45, nrec=4)), wide(W.spec_c2(n=61, seed=3, nrec=4))]
+    plain = [solver(s) for s in specs]
+    batched = [solver(s) for s in specs]
+    narrow = solver(W.spec_c2(n=45, nrec=0))
     b = S.sbpe_batch_create(0, torch.cuda.current_stream().cuda_stream, S.F64, 4)
     try:
         with pytest.raises(S.SbpeError) as e:
-            S.sbpe_set_operator(sol.ctx, S.OP_NARROW)
+            S.sbpe_set_operator(plain[0].ctx, S.OP_NARROW)
         assert e.value.code == S.ESTATE
-        sol.set_state(None, None, 0.0)
+        dts = [p.dt_cfl(0.5) for p in plain]
+        for x in plain + batched + [narrow]:
+            x.set_state(None, None, 0.0)
+        for p, dt in zip(plain, dts):
+            p.advance(20, dt)
+        for x, dt in zip(batched, dts):
+            S.sbpe_batch_add(b, x.ctx, 20, dt)
         with pytest.raises(S.SbpeError) as e:
-            S.sbpe_batch_add(b, sol.ctx, 10, 1e-3)
+            S.sbpe_batch_add(b, narrow.ctx, 20, dts[0])
         assert e.value.code == S.EINVAL
-        z = [torch.zeros((2, n, n), dtype=torch.float64, device='cuda')]
-        gc = [torch.zeros((10, n, n), dtype=torch.float64, device='cuda')]
-        grt = [torch.zeros((n, n), dtype=torch.float64, device='cuda')]
-        with pytest.raises(S.SbpeError) as e:
-            S.sbpe_grad_accumulate(sol.ctx, [z[0].data_ptr()], [z[0].data_ptr()], [z[0].data_ptr()], 1.0, 0.0, 1,
-                                   [gc[0].data_ptr()], [grt[0].data_ptr()])
-        assert e.value.code == S.EINVAL
+        S.sbpe_batch_advance(b, 20)
+        S.sbpe_batch_synchronize(b)
+        for x in batched:
+            S.sbpe_batch_remove(b, x.ctx)
+        for p, x in zip(plain, batched):
+            up, vp = p.state_numpy()
+            ub, vb = x.state_numpy()
+            assert np.abs(up[0]).max() > 0
+            assert np.array_equal(up[0], ub[0]) and np.array_equal(vp[0], vb[0])
+            assert np.array_equal(p.receivers(), x.receivers())
     finally:
         S.sbpe_batch_destroy(b)
-        sol.close()
+        for x in plain + batched + [narrow]:
+            x.close()
+
+
+def test_wide_gradient_matches_oracle_adjoint():
+    """The misfit gradient with the wide operator (the library's discrete
+    adjoint: sbpe_apply on the adjoint state, sbpe_grad_accumulate with the
+    wide i = k terms) against the oracle's discrete adjoint of the same
+    scheme, with checkpoint segments that do not divide the run."""
+    from oracle import adjoint as OA
+    from paper_2003_12811_amd import adjoint as ADJ
+    from oracle.material import C10_ORDER, PAIRS
+    n, nsteps = 21, 23
+    spec = wide(W.spec_c5(n=n, nrec=5))
+    spec_obs = wide(W.spec_c5(n=n, nrec=5, perturbed=True))
+    P = build(spec)
+    dt = T.dt_cfl(P, 0.5)
+    say('wide gradient vs oracle adjoint: n=%d steps=%d' % (n, nsteps))
+    d_obs = OA.forward_receivers(build(spec_obs), spec_obs, nsteps, dt)
+    Jo, go_rho, go_C = OA.misfit_gradient(P, spec, nsteps, dt, d_obs)
+    mg = ADJ.MisfitGradient(spec, nsteps, dt, d_obs=d_obs, checkpoint_every=7)
+    try:
+        J = mg.forward()
+        g_rho, g_c10 = mg.gradient()
+    finally:
+        mg.close()
+    go_c10 = np.stack([go_C[PAIRS[p] + PAIRS[q]] if p == q else go_C[PAIRS[p] + PAIRS[q]] + go_C[PAIRS[q] + PAIRS[p]]
+                       for p, q in C10_ORDER])
+    er, ec, eJ = rel(g_rho, go_rho), rel(g_c10, go_c10), abs(J - Jo) / Jo
+    say('  J %.6e (oracle %.6e)  rel err J %.2e  rho %.2e  C10 %.2e' % (J, Jo, eJ, er, ec))
+    assert eJ < 1e-9 and er < 1e-8 and ec < 1e-8

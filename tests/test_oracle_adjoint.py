@@ -3,7 +3,8 @@
 * The C-gradient of the bilinear form w^T D^tot(C) Y is compared with unit
   probes of C: the form is linear in C, so B(C + e) - B(C) is the exact
   derivative along e.  Probes cover corners, faces of every covered type,
-  closure rows and interior points, and all 16 tensor entries.
+  closure rows and interior points, and all 16 tensor entries, for the
+  narrow and the wide-stencil operator.
 * The misfit gradient (reverse pass of the RK4 map) is compared with central
   finite differences of J along random directions in rho and C.
 """
@@ -18,12 +19,12 @@ from oracle.geometry import metrics
 from paper_2003_12811_amd import workloads as W
 
 
-def _problem(n1, n2, order, seed, C=None, rho=None):
+def _problem(n1, n2, order, seed, C=None, rho=None, operator='narrow'):
     X1, X2 = W.grid(W.GaussianTopography(0.12, 0.2), n1, n2)
     rho0, C10 = W.paper_random_material((n2, n1), seed)
     Cf = M.full_from_c10(C10) if C is None else C
     rho = rho0 if rho is None else rho
-    B = E.Block(X1, X2, rho, Cf, order=order)
+    B = E.Block(X1, X2, rho, Cf, order=order, operator=operator)
     P = E.Problem([B])
     rng = np.random.default_rng(seed)
     P.set_bc(0, 0, E.DISPLACEMENT, g=rng.normal(size=(2, n2)), tfun=lambda t: np.cos(3 * t + 0.2))
@@ -37,9 +38,10 @@ def _form(P, w, Y, t):
     return float(np.sum(w.reshape(2, -1) * P.total_operator([Y], t, homogeneous=False)[0]))
 
 
-@pytest.mark.parametrize("order,n1,n2", [(4, 13, 14), (2, 7, 8)])
-def test_coef_gradient_matches_unit_probes(order, n1, n2):
-    P, X1, X2, rho, C = _problem(n1, n2, order, 5)
+@pytest.mark.parametrize("order,n1,n2,operator", [(4, 13, 14, 'narrow'), (2, 7, 8, 'narrow'),
+                                                   (4, 14, 15, 'wide'), (2, 7, 8, 'wide')])
+def test_coef_gradient_matches_unit_probes(order, n1, n2, operator):
+    P, X1, X2, rho, C = _problem(n1, n2, order, 5, operator=operator)
     rng = np.random.default_rng(1)
     w = rng.normal(size=(2, n2, n1))
     Y = rng.normal(size=(2, n2, n1))
@@ -55,7 +57,7 @@ def test_coef_gradient_matches_unit_probes(order, n1, n2):
                      (0, 1, 0, 0), (1, 1, 0, 1)]:
             C2 = C.copy()
             C2[comp + (j, i)] += 1.0
-            P2 = _problem(n1, n2, order, 5, C=C2, rho=rho)[0]
+            P2 = _problem(n1, n2, order, 5, C=C2, rho=rho, operator=operator)[0]
             d = _form(P2, w, Y, t) - base
             worst = max(worst, abs(d - g[comp + (j, i)]) / scale)
     assert worst < 1e-10, worst

@@ -138,6 +138,25 @@ def copy_probe(mib):
     del src, dst
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written / time) of a
+    plain torch copy of mib MiB, timed with events on the current stream."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device='cuda')
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def swept_points(plan):
     """Points whose update the timed 'interior' launch performs: a one-launch
     sweep also updates the frame points."""
@@ -246,6 +265,8 @@ def main():
                 "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4),
                 "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4)},
     }
+    cbw = copy_bandwidth()
+    log('copy bandwidth %.1f GB/s' % cbw)
     if not args.no_wide:
         log('wide-stencil operator, fp64')
         spw = dict(spec)
@@ -283,6 +304,12 @@ def main():
     if not args.no_cpu_baseline:
         log('cpu baseline (oracle, 1 thread, %d steps)' % args.cpu_steps)
         line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
+    # every roofline also against the measured copy bandwidth
+    for sec in (line, line["f32"], line.get("wide", {}), line.get("large", {})):
+        for key in ("roofline", "apply_roofline"):
+            if key in sec:
+                sec[key]["copy_gbs"] = round(cbw, 1)
+                sec[key]["frac_of_copy"] = round(sec[key]["achieved"] / cbw, 4)
     print(json.dumps(line), flush=True)
 
 

@@ -12,6 +12,9 @@ Semidiscrete scheme (Sec. 5, eq. semidiscrete_general):
   (eq. discr_traction_op, eq. chain_discrete).
 * Robin / traction SAT (Sec. 5.1, eq. sat_traction):
   SAT_J = -(JH)^{-1} sum_f e_f Jhat H_f ( e_f^T (T_JL u_L + U_JL u_L) - g_J ).
+* Dissipative Robin term (the remark after eq. sat_traction): T u + U u + V u_t = g
+  with V symmetric PSD, imposed by adding -(JH)^{-1} sum_f e_f Jhat H_f V v to the
+  Robin SAT (Problem.dissipation; v = u_t enters the RHS only through it).
 * Displacement SAT (Sec. 5.2, eq. dirichlet_ansatz, Theorem 2):
   SAT_J = (JH)^{-1} sum_f (T_LJ - Z_LJ)^T e_f Jhat H_f (e_f^T u_L - g_L),
   Z_JL = beta d Jhat / (h_1 J) n_I C_IJKL n_K.
@@ -30,6 +33,8 @@ A = diag(JH, JH) D^tot and negative semidefiniteness for every boundary type and
 for a two-block interface, translation null space for traction-only blocks,
 constant-coefficient textbook reduction, isotropic reduction;
 tests/test_oracle_time.py: manufactured-solution convergence, energy;
+tests/test_oracle_dissipation.py: the energy rate equals the dissipation of the
+V terms, and an impedance face reflects the textbook fraction of a plane wave;
 tests/test_oracle_wide.py: the wide operator's squared-stencil rows, its PSD
 difference from the narrow one, symmetry, convergence and the accuracy and
 spectral-radius comparisons of Sec. 7.1).
@@ -198,8 +203,11 @@ class Problem:
             A.bc[itf.fa] = dict(kind=INTERFACE, itf=itf, side=0)
             B.bc[itf.fb] = dict(kind=INTERFACE, itf=itf, side=1)
 
-    def set_bc(self, blk, face, kind, g=None, tfun=None, U=None):
-        self.blocks[blk].bc[face] = dict(kind=kind, g=g, tfun=tfun, U=U)
+    def set_bc(self, blk, face, kind, g=None, tfun=None, U=None, V=None):
+        """V (traction and Robin faces): the dissipative term V_JL du_L/dt of the
+        generalised Robin condition (the remark after eq. sat_traction, Sec. 5.1),
+        shape (2, 2, nf), symmetric positive semidefinite per face point."""
+        self.blocks[blk].bc[face] = dict(kind=kind, g=g, tfun=tfun, U=U, V=V)
 
     # ------------------------------------------------------------ the SATs
     def _data(self, bc, t, nf):
@@ -283,12 +291,26 @@ class Problem:
             out.append(vol + self.sat(k, us, t, homogeneous))
         return out
 
-    def rhs(self, us, t):
-        """Acceleration u_tt = rho^{-1} (D^Omega u + f + SAT) for every block."""
+    def dissipation(self, k, vs):
+        """SAT of the dissipative Robin term on block k: the Robin SAT with
+        T u + U u - g replaced by V u_t, i.e. -(JH)^{-1} sum_f e_f Jhat H_f V v."""
+        B = self.blocks[k]
+        out = np.zeros((2, B.npts))
+        for f in range(4):
+            bc = B.bc[f]
+            if bc['kind'] in (TRACTION, ROBIN) and bc.get('V') is not None:
+                out -= B.lift(f, np.einsum('JLf,Lf->Jf', bc['V'], B.face_values(f, vs[k])))
+        return out
+
+    def rhs(self, us, t, vs=None):
+        """Acceleration u_tt = rho^{-1} (D^Omega u + f + SAT) for every block;
+        the velocities vs enter the dissipative Robin terms (omitted when None)."""
         L = self.total_operator(us, t, homogeneous=False)
         out = []
         for k, B in enumerate(self.blocks):
             r = L[k]
+            if vs is not None:
+                r = r + self.dissipation(k, vs)
             if self.forcing[k] is not None:
                 Fs, tf = self.forcing[k]
                 r = r + Fs.reshape(2, -1) * tf(t)

@@ -2,7 +2,7 @@
 
 A spec is a dict of NumPy arrays and tuples (the seeded workloads produce them):
 order, blocks [X1, X2, rho, C10, bc = 4 x (kind, g, time_fn, time_params, U),
-forcing], interfaces, sources, receivers.  Time functions: 0 zero, 1 one,
+forcing], interfaces, interface_data, dissipation, sources, receivers.  Time functions: 0 zero, 1 one,
 2 cos(p0 t + p1), 3 Ricker(peak p0, centre p1) (Sec. 7.3).
 """
 import numpy as np
@@ -43,6 +43,9 @@ def build(spec, beta=1.0):
         if b.get('forcing') is not None:
             F, tk, tp = b['forcing']
             P.forcing[k] = (F, tfun(tk, tp))
+    # dissipative Robin terms V u_t (the remark after eq. sat_traction): (block, face, V [2][2][nf])
+    for (k, f, V) in spec.get('dissipation', []):
+        P.blocks[k].bc[f]['V'] = np.asarray(V, dtype=float)
     for (bid, x1, x2, f1, f2, amp, fp, t0) in spec.get('sources', []):
         P.sources.append(Src.point_source(bid, blocks[bid], x1, x2, (f1, f2), amp, fp, t0))
     return P

@@ -1,8 +1,9 @@
 """Time integration and time-step selection (oracle, test infrastructure only).
 
 * Classical fourth-order Runge-Kutta on the first-order system
-  (u, v = u_t)' = (v, a(u, t)), with forcing and boundary data evaluated at the
-  stage times t, t + dt/2, t + dt/2, t + dt (Sec. 7.1).
+  (u, v = u_t)' = (v, a(u, v, t)), with forcing and boundary data evaluated at
+  the stage times t, t + dt/2, t + dt/2, t + dt (Sec. 7.1); v enters a only
+  through dissipative Robin terms.
 * dt = CFL * min over grid points of h / v_max, with v_max the largest
   quasi-P speed of the transformed material (rho~, c) in the reference domain,
   i.e. the square root of the largest eigenvalue of rho~^{-1} xi_i c_ijkl xi_k
@@ -20,16 +21,16 @@ import numpy as np
 
 def rk4_step(problem, us, vs, t, dt):
     """One classical RK4 step on (u, v); returns (u_new, v_new)."""
-    a1 = problem.rhs(us, t)
+    a1 = problem.rhs(us, t, vs)
     u2 = [u + 0.5 * dt * v for u, v in zip(us, vs)]
     v2 = [v + 0.5 * dt * a for v, a in zip(vs, a1)]
-    a2 = problem.rhs(u2, t + 0.5 * dt)
+    a2 = problem.rhs(u2, t + 0.5 * dt, v2)
     u3 = [u + 0.5 * dt * v for u, v in zip(us, v2)]
     v3 = [v + 0.5 * dt * a for v, a in zip(vs, a2)]
-    a3 = problem.rhs(u3, t + 0.5 * dt)
+    a3 = problem.rhs(u3, t + 0.5 * dt, v3)
     u4 = [u + dt * v for u, v in zip(us, v3)]
     v4 = [v + dt * a for v, a in zip(vs, a3)]
-    a4 = problem.rhs(u4, t + dt)
+    a4 = problem.rhs(u4, t + dt, v4)
     un = [u + dt / 6.0 * (v1 + 2 * vb + 2 * vc + vd)
           for u, v1, vb, vc, vd in zip(us, vs, v2, v3, v4)]
     vn = [v + dt / 6.0 * (p + 2 * q + 2 * r + s)

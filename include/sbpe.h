@@ -107,6 +107,19 @@ sbpe_status sbpe_set_operator(sbpe_ctx_t ctx, int op);
  * with sbpe_connect. */
 sbpe_status sbpe_set_bc(sbpe_ctx_t ctx, int block, int face, int bc, const double* U);
 
+/* Dissipative Robin term (the remark after eq. sat_traction, Sec. 5.1): the
+ * condition of a traction or Robin face becomes T u + U u + V u_t = g, imposed
+ * by adding V u_t to the Robin SAT; the discrete energy then decays at the rate
+ * sum over the face of Jhat H_f u_t.V u_t.  V: [2][2][nf] symmetric positive
+ * semidefinite at the face points (row-major JL), copied; NULL removes it.
+ * SBPE_ESTATE unless the face is traction or Robin; SBPE_EINVAL for a V that
+ * is not PSD.  The term acts on the velocity, so it enters sbpe_advance and
+ * batches (the stage velocities of RK4) but not sbpe_apply, which evaluates
+ * the right-hand side at zero velocity; sbpe_grad_accumulate rejects a context
+ * with dissipative faces (the scheme is no longer self-adjoint); at most 16
+ * blocks (SBPE_EINVAL at finalize otherwise). */
+sbpe_status sbpe_set_bc_dissipation(sbpe_ctx_t ctx, int block, int face, const double* V);
+
 /* Separable boundary data g_J(x) tau(t) of a face: g [2][nf] (traction data for
  * traction/Robin faces, boundary displacement for displacement faces), copied. */
 sbpe_status sbpe_set_bc_data(sbpe_ctx_t ctx, int block, int face, const double* g,

@@ -95,6 +95,7 @@ static void d1_apply(int order, int n, double h, const double* u, long st, doubl
 struct HostFace {
     int kind = BC_TRACTION;
     std::vector<double> U;      // [4][nf] physical U_JL
+    std::vector<double> Dv;     // [4][nf] physical V_JL of a dissipative Robin term V u_t, or empty
     std::vector<double> g;      // [2][nf]
     TimeFn tf{TF_ZERO, 0, {0.0, 0.0}};
     // interface jump data in this face's order: V = u(side 0) - u(side 1), Th = tau + tau'
@@ -121,7 +122,7 @@ struct HostBlock {
     void* d_force = nullptr;
     void* d_a1 = nullptr;
     void* d_a2 = nullptr;
-    void* d_face[4][4] = {};    // per face: g, U, V, Theta (device, scaled for the kernels)
+    void* d_face[4][5] = {};    // per face: g, U, V, Theta, Dv (device, scaled for the kernels)
     // assembled frame operator (CSR over the frame rows)
     int* d_fr_rowptr = nullptr;
     int* d_fr_col = nullptr;
@@ -156,6 +157,7 @@ struct sbpe_ctx {
     int dtype = SBPE_F64;
     int order = 4;
     int op = SBPE_OP_NARROW;        // second-derivative operator of the i = k terms
+    bool dissipative = false;       // some face carries a dissipative Robin term V u_t
     double beta = 1.0;
     bool host_only = false;
     std::string err;
@@ -520,6 +522,7 @@ static sbpe_status build_plan(sbpe_ctx* c) {
             F.vsign = HF.side == 0 ? 1.0 : -1.0;
             F.V = H.d_face[f][2];
             F.Th = H.d_face[f][3];
+            F.Dv = H.d_face[f][4];
             if (HF.kind == BC_INTERFACE) {
                 const HostBlock& P = c->blocks[HF.partner];
                 const int pa = HF.pface >> 1;
@@ -879,7 +882,7 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
             (void)hipFree(B.d_a1);
             (void)hipFree(B.d_a2);
             for (int f = 0; f < 4; ++f)
-                for (int k = 0; k < 4; ++k) (void)hipFree(B.d_face[f][k]);
+                for (int k = 0; k < 5; ++k) (void)hipFree(B.d_face[f][k]);
             (void)hipFree(B.d_fr_rowptr);
             (void)hipFree(B.d_fr_col);
             (void)hipFree(B.d_fr_val);
@@ -978,6 +981,33 @@ sbpe_status sbpe_set_bc(sbpe_ctx_t c, int block, int face, int bc, const double*
         F.U.clear();
     }
     F.kind = bc;
+    return SBPE_OK;
+}
+
+// symmetric positive semidefinite 2x2 matrices M[k * nf + t] (row-major JL) at every face point
+static bool psd2_field(const double* M, int nf) {
+    for (int t = 0; t < nf; ++t) {
+        const double a = M[t], b = M[nf + t], b2 = M[2 * nf + t], d = M[3 * nf + t];
+        if (std::fabs(b - b2) > 1e-12 * (std::fabs(a) + std::fabs(d) + 1e-300) || a < 0 || d < 0 ||
+            a * d - b * b < -1e-12 * (a * d + 1e-300))
+            return false;
+    }
+    return true;
+}
+
+sbpe_status sbpe_set_bc_dissipation(sbpe_ctx_t c, int block, int face, const double* V) {
+    sbpe_status s = check_face(c, block, face);
+    if (s) return s;
+    HostFace& F = c->blocks[block].face[face];
+    if (F.kind != BC_TRACTION && F.kind != BC_ROBIN)
+        return fail(c, SBPE_ESTATE, "a dissipative term needs a traction or Robin face");
+    if (!V) {
+        F.Dv.clear();
+        return SBPE_OK;
+    }
+    const int nf = c->blocks[block].nf(face);
+    if (!psd2_field(V, nf)) return fail(c, SBPE_EINVAL, "V must be symmetric positive semidefinite");
+    F.Dv.assign(V, V + 4 * nf);
     return SBPE_OK;
 }
 
@@ -1378,6 +1408,18 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
     if (c->blocks.empty()) return fail(c, SBPE_ESTATE, "no blocks");
+    // dissipative terms: traction or Robin faces only; they are applied with
+    // the assembled frame operator (at most MAX_APPLY_BLOCKS blocks)
+    c->dissipative = false;
+    for (const auto& B : c->blocks)
+        for (int f = 0; f < 4; ++f) {
+            if (B.face[f].Dv.empty()) continue;
+            if (B.face[f].kind != BC_TRACTION && B.face[f].kind != BC_ROBIN)
+                return fail(c, SBPE_EINVAL, "a dissipative term is set on a face that is no longer traction or Robin");
+            c->dissipative = true;
+        }
+    if (c->dissipative && c->blocks.size() > (size_t)MAX_APPLY_BLOCKS)
+        return fail(c, SBPE_EINVAL, "dissipative faces need at most 16 blocks");
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         sbpe_status s = setup_block(c, (int)b);
         if (s) return s;
@@ -1433,6 +1475,13 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
                     for (int k = 0; k < 4; ++k)
                         for (int t = 0; t < nf; ++t) U[k * nf + t] *= F.jhat[t] / w;
                     s = upload(c, U, &B.d_face[f][1]);
+                    if (s) return s;
+                }
+                if (!F.Dv.empty()) {
+                    std::vector<double> dv(F.Dv);
+                    for (int k = 0; k < 4; ++k)
+                        for (int t = 0; t < nf; ++t) dv[k * nf + t] *= F.jhat[t] / w;
+                    s = upload(c, dv, &B.d_face[f][4]);
                     if (s) return s;
                 }
                 if (F.kind == BC_INTERFACE && !F.V.empty()) {
@@ -2065,6 +2114,8 @@ extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, 
     if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
     sbpe_status s = need_gpu(c);
     if (s) return s;
+    if (c->dissipative)
+        return fail(c, SBPE_EINVAL, "coefficient gradients with dissipative faces are not supported (the scheme is not self-adjoint)");
     const int nb = (int)c->blocks.size();
     if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "at most 16 blocks");
     if (!z || !y || !a || !gc || !grt) return fail(c, SBPE_EINVAL, "NULL pointer array");

@@ -55,6 +55,7 @@ struct FaceDesc {
     const void* U;     // [4][nf]: Robin Jhat U_JL / w (row-major JL), or null
     const void* V;     // [2][nf] displacement jump in this face's order (interface), or null
     const void* Th;    // [2][nf] Jhat Theta / (2 w) in this face's order (interface), or null
+    const void* Dv;    // [4][nf] Jhat V_JL / w of a dissipative Robin term V u_t (row-major JL), or null
 };
 
 struct Entry;

@@ -970,23 +970,67 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
     const int base = threadIdx.x & ~(FRAME_LANES - 1);
     const T da0 = __shfl(d0, base), da1 = __shfl(d1, base);
     const T db0 = __shfl(d0, base + RL), db1 = __shfl(d1, base + RL);
+    // the other component row's rho~^-1 L of the first field
+    const T acc0o = __shfl(acc[0], base + RL * (1 - q));
     if (!valid || sl != 0) return;
     const T da = q ? da1 : da0, db = q ? db1 : db0;
     if constexpr (apply) {
         gm<T>(apply_out(A, b))[qp] = acc[0] + irho * da;
         return;
     }
+    // Dissipative Robin terms V u_t (the remark after eq. sat_traction): at a
+    // face point a = rho~^-1 (L u - S v + d) with S = sum over its faces of
+    // Jhat V / w, so the stage velocities enter pointwise:
+    //   A1 -= rho~^-1 S v,  A2 -= rho~^-1 S (v + dt/2 A1),
+    //   A3 -= rho~^-1 dt/2 S (A2 - A1),  A4 += rho~^-1 dt S (A1 - A3).
+    T Dm[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+    bool dis = false;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const GLB FaceDesc& F = B.face[f];
+        const bool on = f == 0 ? i == 0 : f == 1 ? i == n1 - 1 : f == 2 ? j == 0 : j == n2 - 1;
+        if (on && F.Dv) {
+            gcp<T> dv = gc<T>(F.Dv);
+            const int t = f < 2 ? j : i, nf = F.nf;
+            Dm[0][0] += dv[t];
+            Dm[0][1] += dv[nf + t];
+            Dm[1][0] += dv[2 * nf + t];
+            Dm[1][1] += dv[3 * nf + t];
+            dis = true;
+        }
+    }
+    auto smul = [&](int c, T x0, T x1) { return c ? Dm[1][0] * x0 + Dm[1][1] * x1 : Dm[0][0] * x0 + Dm[0][1] * x1; };
     const T dt = static_cast<T>(B.dt);
     if constexpr (PASS == PASS_RK1) {
-        gm<T>(B.a1)[qp] = acc[0] + irho * da;
-        gm<T>(B.a2)[qp] = acc[0] + T(0.5) * dt * acc[NF - 1] + irho * db;
+        T a1 = acc[0] + irho * da;
+        T a2 = acc[0] + T(0.5) * dt * acc[NF - 1] + irho * db;
+        if (dis) {
+            const T v0 = xp[1][0], v1 = xp[1][1];
+            const T dao = q ? da0 : da1;
+            a1 -= irho * smul(q, v0, v1);
+            const T a1o = acc0o + irho * (dao - smul(1 - q, v0, v1));
+            const T w0 = v0 + T(0.5) * dt * (q ? a1o : a1), w1 = v1 + T(0.5) * dt * (q ? a1 : a1o);
+            a2 -= irho * smul(q, w0, w1);
+        }
+        gm<T>(B.a1)[qp] = a1;
+        gm<T>(B.a2)[qp] = a2;
         return;
     }
     gp<T> uu = gm<T>(B.u);
     gp<T> vv = gm<T>(B.v);
     const T dt2 = dt * dt;
-    const T A3 = A2 + T(0.25) * dt2 * acc[0];
-    const T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * (acc[NF - 1] + irho * db);
+    T A3 = A2 + T(0.25) * dt2 * acc[0];
+    T A4 = T(2) * A2 - A1 + T(0.5) * dt2 * (acc[NF - 1] + irho * db);
+    if (dis) {
+        const long qo = (long)(1 - q) * np + p;
+        const T A1o = gc<T>(B.a1)[qo], A2o = gc<T>(B.a2)[qo];
+        const T e0 = q ? A2o - A1o : A2 - A1, e1 = q ? A2 - A1 : A2o - A1o;
+        const T hdt = T(0.5) * dt;
+        A3 -= irho * hdt * smul(q, e0, e1);
+        const T A3o = A2o + T(0.25) * dt2 * acc0o - irho * hdt * smul(1 - q, e0, e1);
+        const T g0 = q ? A1o - A3o : A1 - A3, g1 = q ? A1 - A3 : A1o - A3o;
+        A4 += irho * dt * smul(q, g0, g1);
+    }
     const T un = uo + dt * vo + dt2 / T(6) * (A1 + A2 + A3);
     uu[qp] = un;
     vv[qp] = vo + dt / T(6) * (A1 + T(2) * A2 + T(2) * A3 + A4);

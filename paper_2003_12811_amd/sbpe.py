@@ -43,6 +43,7 @@ _PROTOS = {
     'sbpe_set_operator': [_P, _I],
     'sbpe_set_bc': [_P, _I, _I, _I, _DP],
     'sbpe_set_bc_data': [_P, _I, _I, _DP, _I, _DP],
+    'sbpe_set_bc_dissipation': [_P, _I, _I, _DP],
     'sbpe_connect': [_P, _I, _I, _I, _I, _I],
     'sbpe_set_forcing': [_P, _I, _DP, _I, _DP],
     'sbpe_set_interface_data': [_P, _I, _I, _DP, _DP, _I, _DP],
@@ -168,6 +169,11 @@ def sbpe_set_operator(ctx, op):
 def sbpe_set_bc(ctx, block, face, bc, U=None):
     U = _f64(U)
     _check(ctx, lib().sbpe_set_bc(ctx, block, face, bc, _dp(U)))
+
+
+def sbpe_set_bc_dissipation(ctx, block, face, V=None):
+    V = _f64(V)
+    _check(ctx, lib().sbpe_set_bc_dissipation(ctx, block, face, _dp(V)))
 
 
 def sbpe_set_bc_data(ctx, block, face, g, time_fn, time_params=None):

@@ -56,6 +56,9 @@ class Solver:
             if b.get('forcing') is not None:
                 F, tfn, tp = b['forcing']
                 S.sbpe_set_forcing(ctx, bid, F, tfn, tp)
+        # dissipative Robin terms V u_t: (block, face, V [2][2][nf])
+        for (bid, f, V) in spec.get('dissipation', []):
+            S.sbpe_set_bc_dissipation(ctx, bid, f, V)
         itfs = spec.get('interfaces', [])
         for (a, fa, bb, fb, rev) in itfs:
             S.sbpe_connect(ctx, a, fa, bb, fb, rev)

@@ -1,0 +1,173 @@
+"""The dissipative Robin term V u_t (the remark after eq. sat_traction in
+Sec. 5.1) through the C ABI, against the oracle.
+
+* sbpe_advance from a nonzero velocity on a curvilinear block with a
+  dissipative Robin face and a dissipative traction face, beside displacement
+  and traction data, forcing, a source and interior receivers (FP64 1e-11,
+  FP32 1e-5), and the same shot advanced in a batch (bitwise).
+* The impedance face: a plane P wave leaves the block through a face with
+  V = 2 Z and leaves 1/9 of its energy, as in the oracle (whose state the
+  library matches to 1e-11).
+* sbpe_apply ignores the term (it evaluates the right-hand side at zero
+  velocity); the gradient entry point refuses a dissipative context; a
+  displacement face cannot carry the term.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import timestep as T
+from oracle.spec import build, receivers
+from paper_2003_12811_amd import sbpe as S
+from paper_2003_12811_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = {'f64': 1e-11, 'f32': 1e-5}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def solver(spec, dtype='f64'):
+    from paper_2003_12811_amd.solver import Solver
+    return Solver(spec, dtype=dtype)
+
+
+def rounded(x, dtype):
+    return x.astype(np.float32).astype(np.float64) if dtype == 'f32' else x
+
+
+def _psd(rng, nf, scale):
+    Q = rng.uniform(-1, 1, (2, 2, nf))
+    return scale * np.einsum('ikf,jkf->ijf', Q, Q)
+
+
+def dissipative_spec(n1, n2, order=4, seed=5):
+    X1, X2 = W.grid(W.GaussianTopography(0.15, 0.2), n1, n2)
+    rho, C10 = W.paper_random_material((n2, n1), seed)
+    rng = np.random.default_rng(seed)
+    nf = [n2, n2, n1, n1]
+    bc = [(W.DISPLACEMENT, rng.normal(size=(2, nf[0])), W.T_COS, (3.0, 0.2), None),
+          (W.ROBIN, rng.normal(size=(2, nf[1])), W.T_RICKER, (5.0, 0.1), _psd(rng, nf[1], 1.0)),
+          (W.TRACTION, rng.normal(size=(2, nf[2])), W.T_COS, (2.0, -0.4), None),
+          (W.TRACTION, None, W.T_ZERO, None, None)]
+    F = rng.normal(size=(2, n2, n1))
+    blk = dict(X1=X1, X2=X2, rho=rho, C10=C10, bc=bc, forcing=(F, W.T_COS, (1.5, 0.3)))
+    return dict(order=order, blocks=[blk], interfaces=[],
+                dissipation=[(0, 1, _psd(rng, nf[1], 2.0)), (0, 3, _psd(rng, nf[3], 2.0))],
+                sources=[(0, 0.37, 0.61, 0.3, -1.0, 2.0, 8.0, 0.05)],
+                receivers=[(0, np.array([0.3, 0.52, 0.99]), np.array([0.4, 0.6, 0.99]))])
+
+
+def _initial(n1, n2, dtype):
+    x = np.linspace(0, 1, n1)[None, :]
+    y = np.linspace(0, 1, n2)[:, None]
+    u0 = np.stack([np.sin(3 * x + 1) * np.cos(2 * y), np.cos(2 * x) * np.sin(3 * y + 0.5)])
+    v0 = np.stack([np.cos(4 * x) * np.sin(2 * y + 0.3), np.sin(3 * x + 0.2) * np.cos(5 * y)])
+    return rounded(u0, dtype), rounded(v0, dtype)
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_dissipative_advance_matches_oracle_and_batch(dtype):
+    import torch
+    n1, n2, nsteps = 150, 47, 40
+    say('dissipative advance', dtype, n1, n2)
+    spec = dissipative_spec(n1, n2)
+    P = build(spec)
+    dt = T.dt_cfl(P, 0.5)
+    u0, v0 = _initial(n1, n2, dtype)
+    sol = solver(spec, dtype)
+    other = solver(spec, dtype)
+    b = S.sbpe_batch_create(0, torch.cuda.current_stream().cuda_stream, S.F64 if dtype == 'f64' else S.F32, 4)
+    try:
+        sol.set_state([u0], [v0], 0.0)
+        sol.advance(nsteps, dt)
+        ug, vg = sol.state_numpy()
+        rg = sol.receivers()
+        u, v, t, rec = [u0.copy()], [v0.copy()], 0.0, []
+        for _ in range(nsteps):
+            u, v = T.rk4_step(P, u, v, t, dt)
+            t += dt
+            rec.append(receivers(spec, u))
+        eu, ev, er = rel(ug[0], u[0]), rel(vg[0], v[0]), rel(rg, np.array(rec))
+        say('  rel L2 u', eu, 'v', ev, 'receivers', er)
+        assert max(eu, ev, er) < TOL[dtype]
+        # the same shot in a batch
+        other.set_state([u0], [v0], 0.0)
+        S.sbpe_batch_add(b, other.ctx, nsteps, dt)
+        S.sbpe_batch_advance(b, nsteps)
+        S.sbpe_batch_synchronize(b)
+        S.sbpe_batch_remove(b, other.ctx)
+        ub, vb = other.state_numpy()
+        assert np.array_equal(ub[0], ug[0]) and np.array_equal(vb[0], vg[0])
+    finally:
+        S.sbpe_batch_destroy(b)
+        sol.close()
+        other.close()
+
+
+def test_impedance_face_leaves_one_ninth():
+    n, sigma, scale = 81, 0.08, 2.0
+    lam, mu, rho = 0.0, 1.0, 1.0
+    cp, cs = np.sqrt((lam + 2 * mu) / rho), np.sqrt(mu / rho)
+    X1, X2 = W.grid(W.Identity(), n, n)
+    C10 = W.voigt_to_c10(np.array([lam + 2 * mu, lam, 0.0, lam + 2 * mu, 0.0, mu]))[:, None, None] * np.ones((1, n, n))
+    V = np.zeros((2, 2, n))
+    V[0, 0], V[1, 1] = scale * rho * cp, scale * rho * cs
+    free = (W.TRACTION, None, W.T_ZERO, None, None)
+    spec = dict(order=4, blocks=[dict(X1=X1, X2=X2, rho=rho * np.ones((n, n)), C10=C10, bc=[free] * 4, forcing=None)],
+                interfaces=[], dissipation=[(0, 1, V)], sources=[], receivers=[])
+    P = build(spec)
+    g = np.exp(-((X1 - 0.5) / sigma) ** 2)
+    u0 = np.stack([g, np.zeros_like(g)])
+    v0 = np.stack([cp * (2 * (X1 - 0.5) / sigma ** 2) * g, np.zeros_like(g)])
+    nst, dt = T.steps_for(0.62, T.dt_cfl(P, 0.5))
+    sol = solver(spec, 'f64')
+    try:
+        sol.set_state([u0], [v0], 0.0)
+        e0 = sol.energy()
+        sol.advance(nst, dt)
+        ratio = sol.energy() / e0
+        ug, vg = sol.state_numpy()
+    finally:
+        sol.close()
+    u, v = [u0], [v0]
+    for k in range(nst):
+        u, v = T.rk4_step(P, u, v, k * dt, dt)
+    eu, ev = rel(ug[0], u[0]), rel(vg[0], v[0])
+    say('  energy ratio', ratio, 'rel L2 u', eu, 'v', ev)
+    assert eu < 1e-11 and ev < 1e-11
+    assert abs(ratio - 1.0 / 9.0) < 2e-3
+
+
+def test_dissipation_rules():
+    import torch
+    n1, n2 = 60, 40
+    spec = dissipative_spec(n1, n2)
+    plain = dict(spec)
+    plain['dissipation'] = []
+    sol = solver(spec)
+    ref = solver(plain)
+    try:
+        rng = np.random.default_rng(3)
+        u = rng.normal(size=(2, n2, n1))
+        a = sol.apply([u], t=0.2)[0].cpu().numpy()
+        r = ref.apply([u], t=0.2)[0].cpu().numpy()
+        assert np.array_equal(a, r)
+        z = torch.zeros((2, n2, n1), dtype=torch.float64, device='cuda')
+        gc = torch.zeros((10, n2, n1), dtype=torch.float64, device='cuda')
+        grt = torch.zeros((n2, n1), dtype=torch.float64, device='cuda')
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_grad_accumulate(sol.ctx, [z.data_ptr()], [z.data_ptr()], [z.data_ptr()], 1.0, 0.0, 1,
+                                   [gc.data_ptr()], [grt.data_ptr()])
+        assert e.value.code == S.EINVAL
+    finally:
+        sol.close()
+        ref.close()

@@ -154,6 +154,34 @@ def test_set_operator_states():
         S.sbpe_destroy(ctx)
 
 
+def test_dissipation_states():
+    n = 15
+    X1, X2 = W.grid(W.Identity(), n, n)
+    rho, C10 = W.paper_random_material((n, n), 0)
+    ctx = _host_ctx()
+    try:
+        S.sbpe_add_block(ctx, X1, X2, rho, C10)
+        S.sbpe_set_bc(ctx, 0, 0, S.BC_DISPLACEMENT)
+        V = np.zeros((2, 2, n))
+        V[0, 0] = V[1, 1] = 1.0
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_set_bc_dissipation(ctx, 0, 0, V)
+        assert e.value.code == S.ESTATE
+        bad = V.copy()
+        bad[0, 1] = 3.0      # not symmetric
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_set_bc_dissipation(ctx, 0, 1, bad)
+        assert e.value.code == S.EINVAL
+        S.sbpe_set_bc_dissipation(ctx, 0, 1, V)
+        # the face may not change kind afterwards
+        S.sbpe_set_bc(ctx, 0, 1, S.BC_DISPLACEMENT)
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_finalize(ctx)
+        assert e.value.code == S.EINVAL
+    finally:
+        S.sbpe_destroy(ctx)
+
+
 def _finalize_status(M4):
     """sbpe_finalize on a small host-only block whose stiffness, as the 4x4
     matrix over the pairs (11, 12, 21, 22), is M4 at every point."""

@@ -11,8 +11,8 @@ sources, receivers).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line on stdout; progress goes to stderr.  The primary result is
 FP64; the FP32 variant, the plain operator apply, the same workload with the
-wide-stencil operator, a working set larger than the MALL (2x2 blocks of
-2049^2, FP32) and a served stream of shots (continuous batching against
+wide-stencil operator, working sets larger than the MALL (one 2049^2 block in
+FP64, 2x2 blocks of 2049^2 in FP32) and a served stream of shots (continuous batching against
 sequential plain solves, p50/p99 latency) are reported beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -215,6 +215,7 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-large', action='store_true')
     ap.add_argument('--no-wide', action='store_true')
+    ap.add_argument('--no-hbm', action='store_true')
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
@@ -265,8 +266,10 @@ def main():
                 "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4),
                 "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4)},
     }
-    cbw = copy_bandwidth()
-    log('copy bandwidth %.1f GB/s' % cbw)
+    # (left out of profiler calibration runs, whose copy probe must stay the largest copy)
+    cbw = None if args.copy_probe_mib else copy_bandwidth()
+    if cbw:
+        log('copy bandwidth %.1f GB/s' % cbw)
     if not args.no_wide:
         log('wide-stencil operator, fp64')
         spw = dict(spec)
@@ -281,6 +284,19 @@ def main():
                                                    swept_points(rw['plan']), 8),
                         "kernels_ms": {kk: v[0] for kk, v in rw['kernels'].items() if v[1]}}
         log('  %.3f ms/step, %.3e updates/s' % (rw['ms_per_step'], rw['updates_per_s']))
+    if not args.no_hbm:
+        # the roofline case beyond the MALL in FP64: one 2049^2 block of the same recipe
+        # (about 0.8 GB per sweep; the 1025^2 working set fits the 256 MB MALL)
+        log('hbm-bound working set: %dx%d, fp64' % (args.large_n, args.large_n))
+        sph = W.spec_c2(n=args.large_n)
+        rh = run_gpu(sph, 'f64', max(args.steps // 4, 20), 10)
+        kh = dominant(rh)
+        line["hbm_bound"] = {"workload": "the same recipe on one %dx%d block, FP64 (working set beyond the MALL)"
+                                         % (args.large_n, args.large_n),
+                             "value": rh['updates_per_s'], "ms_per_step": rh['ms_per_step'],
+                             "roofline": roofline(kh, rh['kernels'][kh][0], swept_points(rh['plan']), 8),
+                             "kernels_ms": {kk: v[0] for kk, v in rh['kernels'].items() if v[1]}}
+        log('  %.3f ms/step, %.3e updates/s' % (rh['ms_per_step'], rh['updates_per_s']))
     if not args.no_large:
         log('large working set: 2x2 blocks of %d^2, fp32' % args.large_n)
         t0 = time.time()
@@ -305,9 +321,9 @@ def main():
         log('cpu baseline (oracle, 1 thread, %d steps)' % args.cpu_steps)
         line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
     # every roofline also against the measured copy bandwidth
-    for sec in (line, line["f32"], line.get("wide", {}), line.get("large", {})):
+    for sec in (line, line["f32"], line.get("wide", {}), line.get("hbm_bound", {}), line.get("large", {})):
         for key in ("roofline", "apply_roofline"):
-            if key in sec:
+            if key in sec and cbw:
                 sec[key]["copy_gbs"] = round(cbw, 1)
                 sec[key]["frac_of_copy"] = round(sec[key]["achieved"] / cbw, 4)
     print(json.dumps(line), flush=True)

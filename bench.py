@@ -7,7 +7,10 @@ SPD stiffness and density (8 Fourier modes per field, seed 0), displacement SAT
 on the bottom face and traction SATs elsewhere, a 10 Hz Ricker point force and
 16 surface receivers; classical RK4 at CFL 0.5.  A step is one full RK4 step
 (four right-hand-side evaluations fused into two sweeps over the grid,
-sources, receivers).  Inputs are resident in HBM before timing starts.
+sources, receivers).  Inputs are resident in HBM before timing starts.  The
+throughput comes from the timed steps alone; the launch durations of the
+roofline come from the same number of steps run again with HIP events around
+every launch (the events lengthen a 1025^2 step by 12-19 %).
 
 Prints one JSON line on stdout; progress goes to stderr.  The primary result is
 FP64; the FP32 variant, the plain operator apply, the same workload with the
@@ -45,41 +48,79 @@ def log(*a):
 TRAFFIC_PROFILE = os.path.join(ROOT, 'profiles', 'hbm_traffic_c2_1025.md')
 
 
-def roofline(kind, ms, points, wbytes, traffic_key=None):
+def roofline(kind, ms, points, wbytes, traffic_key=None, tile_rows=None):
     byts = WORDS[kind] * wbytes * points
     gbs = byts / (ms * 1e-3) / 1e9
     traffic = None
     if traffic_key is not None:
         from paper_2003_12811_amd import profiling
-        t = profiling.read_traffic(TRAFFIC_PROFILE)
+        t = profiling.read_traffic(TRAFFIC_PROFILE, tile_rows=tile_rows or 10)
         traffic = t.get(traffic_key) if t else None
     return {"bound": "hbm", "kernel": kind, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
             "avg_ms": round(ms, 5), "bytes_per_launch": byts}
 
 
-def run_gpu(spec, dtype, steps, warmup, apply_reps=0):
+TILE_CANDIDATES = (10, 14, 16, 18, 20, 24)
+
+
+def tune_tile_rows(spec, dtype, candidates=TILE_CANDIDATES, steps=60):
+    """Tile height with the shortest step on this workload (a launch-shape
+    choice: the results do not depend on it), timed before the benchmark."""
+    import torch
+    from paper_2003_12811_amd.solver import Solver
+    times = {}
+    for rows in candidates:
+        sol = Solver(spec, dtype, tile_rows=rows)
+        dt = sol.dt_cfl(spec.get('cfl', 0.5))
+        sol.set_state(None, None, 0.0)
+        sol.advance(10, dt)
+        sol.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol.advance(steps, dt)
+        sol.synchronize()
+        torch.cuda.synchronize()
+        times[rows] = 1e3 * (time.perf_counter() - t0) / steps
+        sol.close()
+    best = min(times, key=times.get)
+    log('  tile rows %s -> %d' % ({k: round(v, 4) for k, v in times.items()}, best))
+    return best, times
+
+
+def run_gpu(spec, dtype, steps, warmup, apply_reps=0, tile_rows=0):
     import torch
     from paper_2003_12811_amd import sbpe as S
     from paper_2003_12811_amd.solver import Solver
-    sol = Solver(spec, dtype)
+    sol = Solver(spec, dtype, tile_rows=tile_rows)
     dt = sol.dt_cfl(spec.get('cfl', 0.5))
     sol.set_state(None, None, 0.0)
     plan = S.sbpe_plan_info(sol.ctx)
     npts = sum(b['X1'].size for b in spec['blocks'])
     sol.advance(warmup, dt)
     sol.synchronize()
-    S.sbpe_set_kernel_timing(sol.ctx, 1)
-    S.sbpe_get_kernel_timing(sol.ctx)
     torch.cuda.synchronize()
+    # the timed steps, without per-launch events (they cost 12-19 % of a
+    # 1025^2 step), give the throughput ...
     t0 = time.perf_counter()
     sol.advance(steps, dt)
     sol.synchronize()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = S.sbpe_get_kernel_timing(sol.ctx)
     wall = t1 - t0
+    # ... then the same number of steps again with HIP events around every
+    # launch, on the launch's own stream, give the launch durations
+    S.sbpe_set_kernel_timing(sol.ctx, 1)
+    S.sbpe_get_kernel_timing(sol.ctx)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sol.advance(steps, dt)
+    sol.synchronize()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    kt = S.sbpe_get_kernel_timing(sol.ctx)
     res = dict(dtype=dtype, points=npts, steps=steps, wall_s=wall, ms_per_step=1e3 * wall / steps,
+               ms_per_step_with_events=1e3 * (t3 - t2) / steps,
                updates_per_s=npts * steps / wall, dt=dt, kernels=kt, plan=plan)
     if apply_reps:
         u = [torch.zeros((2,) + b['X1'].shape, dtype=sol.tdtype, device=sol.device) for b in spec['blocks']]
@@ -216,6 +257,8 @@ def main():
     ap.add_argument('--no-large', action='store_true')
     ap.add_argument('--no-wide', action='store_true')
     ap.add_argument('--no-hbm', action='store_true')
+    ap.add_argument('--tile-rows', type=int, default=0,
+                    help='interior tile height of the 1025^2 runs (0: pick it by timing a few candidates)')
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
@@ -241,11 +284,17 @@ def main():
     from paper_2003_12811_amd import workloads as W
     log('building workload %dx%d' % (args.n, args.n))
     spec = W.spec_c2(n=args.n)
+    tiles64, tiles32 = (args.tile_rows, {}), (args.tile_rows, {})
+    if not args.tile_rows:
+        log('tile height, fp64')
+        tiles64 = tune_tile_rows(spec, 'f64')
+        log('tile height, fp32')
+        tiles32 = tune_tile_rows(spec, 'f32')
     log('fp64 run')
-    r64 = run_gpu(spec, 'f64', args.steps, args.warmup, apply_reps=50)
+    r64 = run_gpu(spec, 'f64', args.steps, args.warmup, apply_reps=50, tile_rows=tiles64[0])
     log('  %.3f ms/step, %.3e updates/s' % (r64['ms_per_step'], r64['updates_per_s']))
     log('fp32 run')
-    r32 = run_gpu(spec, 'f32', args.steps, args.warmup, apply_reps=50)
+    r32 = run_gpu(spec, 'f32', args.steps, args.warmup, apply_reps=50, tile_rows=tiles32[0])
     log('  %.3f ms/step, %.3e updates/s' % (r32['ms_per_step'], r32['updates_per_s']))
     pts = swept_points(r64['plan'])
     k = dominant(r64)
@@ -257,12 +306,14 @@ def main():
         "config": {"workload": "single curvilinear block %dx%d, Gaussian topography, random smooth SPD C/rho "
                                "(seed 0), displacement bottom + traction SATs, 10 Hz Ricker force, 16 receivers, "
                                "4th-order SBP-SAT, RK4 CFL 0.5" % (args.n, args.n),
-                   "points": r64['points'], "dt": r64['dt'], "parallelism": "1 GPU"},
+                   "points": r64['points'], "dt": r64['dt'], "parallelism": "1 GPU",
+                   "tile_rows": tiles64[0], "tile_rows_ms_per_step": tiles64[1]},
         "roofline": roofline(k, r64['kernels'][k][0], pts, 8,
-                             traffic_key=('%s/f64/o4' % k) if args.n == 1025 else None),
+                             traffic_key=('%s/f64/o4' % k) if args.n == 1025 else None, tile_rows=tiles64[0]),
         "kernels_ms": {kk: v[0] for kk, v in r64['kernels'].items() if v[1]},
+        "ms_per_step_with_events": r64['ms_per_step_with_events'],
         "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8),
-        "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'],
+        "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'], "tile_rows": tiles32[0],
                 "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4),
                 "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4)},
     }

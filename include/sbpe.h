@@ -91,6 +91,14 @@ sbpe_status sbpe_add_block(sbpe_ctx_t ctx, int n1, int n2, const double* X1, con
  * no factor 2, index 6 <-> 12) of a normal material to the C10 layout. */
 sbpe_status sbpe_voigt_to_c10(const double* voigt, size_t npts, double* C10);
 
+/* Output rows per interior tile, a launch-shape parameter (results do not
+ * depend on it): 0 (default) = 10, else 1..256.  Which height runs fastest
+ * depends on the grid and dtype through how the tiles fill the machine; the
+ * benchmark picks it by timing a few candidates.  Call before sbpe_finalize
+ * (SBPE_ESTATE after it; SBPE_EINVAL outside 0..256).  The environment
+ * variable SBPE_TILE_ROWS overrides it. */
+sbpe_status sbpe_set_tile_rows(sbpe_ctx_t ctx, int rows);
+
 /* Second-derivative operator of the i = k terms DD_ii(c) of the elastic
  * operator (Sec. 4.6): SBPE_OP_NARROW (default) the adapted fully compatible
  * narrow-stencil D2^FC(c) of Sec. 4.1; SBPE_OP_WIDE the wide-stencil D_i c D_i

@@ -158,6 +158,7 @@ struct sbpe_ctx {
     int order = 4;
     int op = SBPE_OP_NARROW;        // second-derivative operator of the i = k terms
     bool dissipative = false;       // some face carries a dissipative Robin term V u_t
+    int tile_rows = 0;              // output rows per interior tile (0: the default)
     double beta = 1.0;
     bool host_only = false;
     std::string err;
@@ -477,7 +478,7 @@ static sbpe_status build_plan(sbpe_ctx* c) {
     const int nb = (int)c->blocks.size();
     // interior tiles: 64 lanes, of which the central 64 - 2 * half-width are written
     const int tile_w = TILE_LANES - 2 * (c->order / 2);
-    int tile_y = TILE_Y_DEFAULT;
+    int tile_y = c->tile_rows > 0 ? c->tile_rows : TILE_Y_DEFAULT;
     if (const char* e = std::getenv("SBPE_TILE_ROWS")) tile_y = std::max(1, std::atoi(e));
     c->desc.assign(nb, BlockDesc{});
     int tiles = 0, fwg = 0;
@@ -949,6 +950,14 @@ static sbpe_status check_face(sbpe_ctx* c, int block, int face) {
     if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
     if (block < 0 || block >= (int)c->blocks.size()) return fail(c, SBPE_EINVAL, "no such block");
     if (face < 0 || face > 3) return fail(c, SBPE_EINVAL, "face must be 0..3");
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_set_tile_rows(sbpe_ctx_t c, int rows) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
+    if (rows < 0 || rows > 256) return fail(c, SBPE_EINVAL, "tile rows must be 0 (default) or 1..256");
+    c->tile_rows = rows;
     return SBPE_OK;
 }
 

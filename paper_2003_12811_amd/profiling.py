@@ -83,6 +83,7 @@ def summarize_traffic(fetch_csv, write_csv, copy_mib, out_md, command):
               'so FETCH_SIZE is scaled by %.4f and WRITE_SIZE by %.4f.' % (
                   copy_mib, max(fe[COPY_KERNEL]), max(wr[COPY_KERNEL]), f_scale, w_scale), '',
               'kernel source sha256 = %s' % source_hash(), '',
+              'interior tile rows = %d' % _tile_rows(command), '',
               '| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read MB | written MB |',
               '|---|---|---|---|---|---|']
     machine = []
@@ -99,15 +100,26 @@ def summarize_traffic(fetch_csv, write_csv, copy_mib, out_md, command):
     open(out_md, 'w').write('\n'.join(lines) + '\n')
 
 
-def read_traffic(md_path, source=KERNEL_SOURCE):
+def _tile_rows(command):
+    """Interior tile height of a bench.py command line (10 unless given)."""
+    m = re.search(r'--tile-rows (\d+)', command)
+    return int(m.group(1)) if m else 10
+
+
+def read_traffic(md_path, source=KERNEL_SOURCE, tile_rows=None):
     """{kind: bytes per launch} from a traffic summary, or None if it is
-    missing or was measured on a different kernel source."""
+    missing, was measured on a different kernel source, or (tile_rows given)
+    with another interior tile height."""
     if not os.path.exists(md_path):
         return None
     txt = open(md_path).read()
     m = re.search(r'kernel source sha256 = ([0-9a-f]{64})', txt)
     if not m or m.group(1) != source_hash(source):
         return None
+    if tile_rows is not None:
+        t = re.search(r'interior tile rows = (\d+)', txt)
+        if not t or int(t.group(1)) != tile_rows:
+            return None
     return {k: int(v) for k, v in re.findall(r'traffic_bytes (\S+) = (\d+)', txt)}
 
 

@@ -41,6 +41,7 @@ _PROTOS = {
     'sbpe_add_block': [_P, _I, _I, _DP, _DP, _DP, _DP, _IP],
     'sbpe_voigt_to_c10': [_DP, ctypes.c_size_t, _DP],
     'sbpe_set_operator': [_P, _I],
+    'sbpe_set_tile_rows': [_P, _I],
     'sbpe_set_bc': [_P, _I, _I, _I, _DP],
     'sbpe_set_bc_data': [_P, _I, _I, _DP, _I, _DP],
     'sbpe_set_bc_dissipation': [_P, _I, _I, _DP],
@@ -160,6 +161,10 @@ def sbpe_voigt_to_c10(voigt):
     out = np.empty((10,) + shp)
     _check(None, lib().sbpe_voigt_to_c10(_dp(V), int(np.prod(shp)), _dp(out)))
     return out
+
+
+def sbpe_set_tile_rows(ctx, rows):
+    _check(ctx, lib().sbpe_set_tile_rows(ctx, rows))
 
 
 def sbpe_set_operator(ctx, op):

@@ -18,7 +18,7 @@ def _torch():
 class Solver:
     """One context of the library built from a spec."""
 
-    def __init__(self, spec, dtype='f64', device=0, beta=1.0, stream=None):
+    def __init__(self, spec, dtype='f64', device=0, beta=1.0, stream=None, tile_rows=0):
         torch = _torch()
         self.torch = torch
         self.spec = spec
@@ -30,6 +30,8 @@ class Solver:
         self.ctx = S.sbpe_create(device, stream.cuda_stream, S.F64 if dtype == 'f64' else S.F32,
                                  spec['order'], beta)
         try:
+            if tile_rows:
+                S.sbpe_set_tile_rows(self.ctx, tile_rows)
             self._setup(spec)
         except Exception:
             S.sbpe_destroy(self.ctx)

@@ -154,6 +154,27 @@ def test_set_operator_states():
         S.sbpe_destroy(ctx)
 
 
+def test_tile_rows_states():
+    n = 15
+    X1, X2 = W.grid(W.Identity(), n, n)
+    rho, C10 = W.paper_random_material((n, n), 0)
+    ctx = _host_ctx()
+    try:
+        for bad in (-1, 257):
+            with pytest.raises(S.SbpeError) as e:
+                S.sbpe_set_tile_rows(ctx, bad)
+            assert e.value.code == S.EINVAL
+        S.sbpe_set_tile_rows(ctx, 20)
+        S.sbpe_set_tile_rows(ctx, 0)
+        S.sbpe_add_block(ctx, X1, X2, rho, C10)
+        S.sbpe_finalize(ctx)
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_set_tile_rows(ctx, 12)
+        assert e.value.code == S.ESTATE
+    finally:
+        S.sbpe_destroy(ctx)
+
+
 def test_dissipation_states():
     n = 15
     X1, X2 = W.grid(W.Identity(), n, n)

@@ -325,11 +325,12 @@ def main():
         log('wide-stencil operator, fp64')
         spw = dict(spec)
         spw['operator'] = 'wide'
-        rw = run_gpu(spw, 'f64', args.steps, args.warmup, apply_reps=50)
+        tw = (args.tile_rows, {}) if args.tile_rows else tune_tile_rows(spw, 'f64')
+        rw = run_gpu(spw, 'f64', args.steps, args.warmup, apply_reps=50, tile_rows=tw[0])
         kw = dominant(rw)
         line["wide"] = {"workload": "the same %dx%d workload with the wide-stencil operator D_i c D_i, FP64"
                                     % (args.n, args.n),
-                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'],
+                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'], "tile_rows": tw[0],
                         "roofline": roofline(kw, rw['kernels'][kw][0], swept_points(rw['plan']), 8),
                         "apply_roofline": roofline('interior_apply', rw['apply_kernels']['interior_apply'][0],
                                                    swept_points(rw['plan']), 8),

@@ -8,6 +8,8 @@ on the bottom face and traction SATs elsewhere, a 10 Hz Ricker point force and
 16 surface receivers; classical RK4 at CFL 0.5.  A step is one full RK4 step
 (four right-hand-side evaluations fused into two sweeps over the grid,
 sources, receivers).  Inputs are resident in HBM before timing starts.  The
+launch shape (tile height, frame groups per frame workgroup) is picked by
+timing candidates first; it does not change the results.  The
 throughput comes from the timed steps alone; the launch durations of the
 roofline come from the same number of steps run again with HIP events around
 every launch (the events lengthen a 1025^2 step by 12-19 %).
@@ -62,37 +64,47 @@ def roofline(kind, ms, points, wbytes, traffic_key=None, tile_rows=None):
 
 
 TILE_CANDIDATES = (10, 14, 16, 18, 20, 24)
+FRAME_LOOP_CANDIDATES = (1, 2, 4)
 
 
-def tune_tile_rows(spec, dtype, candidates=TILE_CANDIDATES, steps=60):
-    """Tile height with the shortest step on this workload (a launch-shape
-    choice: the results do not depend on it), timed before the benchmark."""
+def tune_launch(spec, dtype, tiles=TILE_CANDIDATES, loops=FRAME_LOOP_CANDIDATES, steps=60):
+    """Launch shape (interior tile height, frame groups per frame workgroup)
+    with the shortest step on this workload, timed before the benchmark; the
+    results do not depend on it.  The default shape (10, 1) is kept unless
+    another is more than 1 % faster."""
     import torch
     from paper_2003_12811_amd.solver import Solver
     times = {}
-    for rows in candidates:
+    for rows in tiles:
         sol = Solver(spec, dtype, tile_rows=rows)
         dt = sol.dt_cfl(spec.get('cfl', 0.5))
         sol.set_state(None, None, 0.0)
-        sol.advance(10, dt)
-        sol.synchronize()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sol.advance(steps, dt)
-        sol.synchronize()
-        torch.cuda.synchronize()
-        times[rows] = 1e3 * (time.perf_counter() - t0) / steps
+        for fl in loops:
+            sol.set_frame_loop(fl)
+            sol.advance(10, dt)
+            sol.synchronize()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sol.advance(steps, dt)
+            sol.synchronize()
+            torch.cuda.synchronize()
+            times[(rows, fl)] = 1e3 * (time.perf_counter() - t0) / steps
         sol.close()
-    best = min(times, key=times.get)
-    log('  tile rows %s -> %d' % ({k: round(v, 4) for k, v in times.items()}, best))
-    return best, times
+    best = (tiles[0], loops[0])
+    for key, ms in times.items():
+        if ms < 0.99 * times[best]:
+            best = key
+    table = {'%dx%d' % k: round(v, 4) for k, v in times.items()}
+    log('  launch shapes (tile rows x frame groups) %s -> %dx%d' % (table, best[0], best[1]))
+    return best, table
 
 
-def run_gpu(spec, dtype, steps, warmup, apply_reps=0, tile_rows=0):
+def run_gpu(spec, dtype, steps, warmup, apply_reps=0, shape=(0, 1)):
     import torch
     from paper_2003_12811_amd import sbpe as S
     from paper_2003_12811_amd.solver import Solver
-    sol = Solver(spec, dtype, tile_rows=tile_rows)
+    sol = Solver(spec, dtype, tile_rows=shape[0])
+    sol.set_frame_loop(shape[1])
     dt = sol.dt_cfl(spec.get('cfl', 0.5))
     sol.set_state(None, None, 0.0)
     plan = S.sbpe_plan_info(sol.ctx)
@@ -258,7 +270,9 @@ def main():
     ap.add_argument('--no-wide', action='store_true')
     ap.add_argument('--no-hbm', action='store_true')
     ap.add_argument('--tile-rows', type=int, default=0,
-                    help='interior tile height of the 1025^2 runs (0: pick it by timing a few candidates)')
+                    help='interior tile height of the 1025^2 runs (0: pick the launch shape by timing candidates)')
+    ap.add_argument('--frame-loop', type=int, default=1,
+                    help='frame groups per frame workgroup, used with --tile-rows')
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
@@ -284,17 +298,18 @@ def main():
     from paper_2003_12811_amd import workloads as W
     log('building workload %dx%d' % (args.n, args.n))
     spec = W.spec_c2(n=args.n)
-    tiles64, tiles32 = (args.tile_rows, {}), (args.tile_rows, {})
+    fixed = ((args.tile_rows, args.frame_loop), {})
+    tuned64, tuned32 = fixed, fixed
     if not args.tile_rows:
-        log('tile height, fp64')
-        tiles64 = tune_tile_rows(spec, 'f64')
-        log('tile height, fp32')
-        tiles32 = tune_tile_rows(spec, 'f32')
+        log('launch shape, fp64')
+        tuned64 = tune_launch(spec, 'f64')
+        log('launch shape, fp32')
+        tuned32 = tune_launch(spec, 'f32')
     log('fp64 run')
-    r64 = run_gpu(spec, 'f64', args.steps, args.warmup, apply_reps=50, tile_rows=tiles64[0])
+    r64 = run_gpu(spec, 'f64', args.steps, args.warmup, apply_reps=50, shape=tuned64[0])
     log('  %.3f ms/step, %.3e updates/s' % (r64['ms_per_step'], r64['updates_per_s']))
     log('fp32 run')
-    r32 = run_gpu(spec, 'f32', args.steps, args.warmup, apply_reps=50, tile_rows=tiles32[0])
+    r32 = run_gpu(spec, 'f32', args.steps, args.warmup, apply_reps=50, shape=tuned32[0])
     log('  %.3f ms/step, %.3e updates/s' % (r32['ms_per_step'], r32['updates_per_s']))
     pts = swept_points(r64['plan'])
     k = dominant(r64)
@@ -307,13 +322,15 @@ def main():
                                "(seed 0), displacement bottom + traction SATs, 10 Hz Ricker force, 16 receivers, "
                                "4th-order SBP-SAT, RK4 CFL 0.5" % (args.n, args.n),
                    "points": r64['points'], "dt": r64['dt'], "parallelism": "1 GPU",
-                   "tile_rows": tiles64[0], "tile_rows_ms_per_step": tiles64[1]},
+                   "tile_rows": tuned64[0][0], "frame_loop": tuned64[0][1],
+                   "launch_shape_ms_per_step": tuned64[1]},
         "roofline": roofline(k, r64['kernels'][k][0], pts, 8,
-                             traffic_key=('%s/f64/o4' % k) if args.n == 1025 else None, tile_rows=tiles64[0]),
+                             traffic_key=('%s/f64/o4' % k) if args.n == 1025 else None, tile_rows=tuned64[0][0]),
         "kernels_ms": {kk: v[0] for kk, v in r64['kernels'].items() if v[1]},
         "ms_per_step_with_events": r64['ms_per_step_with_events'],
         "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8),
-        "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'], "tile_rows": tiles32[0],
+        "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'],
+                "tile_rows": tuned32[0][0], "frame_loop": tuned32[0][1],
                 "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4),
                 "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4)},
     }
@@ -325,12 +342,12 @@ def main():
         log('wide-stencil operator, fp64')
         spw = dict(spec)
         spw['operator'] = 'wide'
-        tw = (args.tile_rows, {}) if args.tile_rows else tune_tile_rows(spw, 'f64')
-        rw = run_gpu(spw, 'f64', args.steps, args.warmup, apply_reps=50, tile_rows=tw[0])
+        tw = fixed if args.tile_rows else tune_launch(spw, 'f64', loops=(1,))
+        rw = run_gpu(spw, 'f64', args.steps, args.warmup, apply_reps=50, shape=tw[0])
         kw = dominant(rw)
         line["wide"] = {"workload": "the same %dx%d workload with the wide-stencil operator D_i c D_i, FP64"
                                     % (args.n, args.n),
-                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'], "tile_rows": tw[0],
+                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'], "tile_rows": tw[0][0],
                         "roofline": roofline(kw, rw['kernels'][kw][0], swept_points(rw['plan']), 8),
                         "apply_roofline": roofline('interior_apply', rw['apply_kernels']['interior_apply'][0],
                                                    swept_points(rw['plan']), 8),

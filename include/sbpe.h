@@ -99,6 +99,12 @@ sbpe_status sbpe_voigt_to_c10(const double* voigt, size_t npts, double* C10);
  * variable SBPE_TILE_ROWS overrides it. */
 sbpe_status sbpe_set_tile_rows(sbpe_ctx_t ctx, int rows);
 
+/* Frame groups per frame workgroup of a one-launch sweep (another launch-shape
+ * parameter; results do not depend on it): 1 (default) .. 64.  May be called
+ * at any time; it applies to the context's own sweeps (batches use 1).
+ * SBPE_EINVAL outside 1..64. */
+sbpe_status sbpe_set_frame_loop(sbpe_ctx_t ctx, int groups);
+
 /* Second-derivative operator of the i = k terms DD_ii(c) of the elastic
  * operator (Sec. 4.6): SBPE_OP_NARROW (default) the adapted fully compatible
  * narrow-stencil D2^FC(c) of Sec. 4.1; SBPE_OP_WIDE the wide-stencil D_i c D_i

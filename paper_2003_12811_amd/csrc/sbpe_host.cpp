@@ -159,6 +159,7 @@ struct sbpe_ctx {
     int op = SBPE_OP_NARROW;        // second-derivative operator of the i = k terms
     bool dissipative = false;       // some face carries a dissipative Robin term V u_t
     int tile_rows = 0;              // output rows per interior tile (0: the default)
+    int frame_loop = 1;             // one-launch sweeps: frame groups per frame workgroup
     double beta = 1.0;
     bool host_only = false;
     std::string err;
@@ -691,6 +692,7 @@ static PassArgs base_args(const sbpe_ctx* c) {
     a.blocks = c->d_desc;
     a.nblocks = (int)c->blocks.size();
     a.wide = c->op == SBPE_OP_WIDE ? 1 : 0;
+    a.floop = c->frame_loop;
     return a;
 }
 
@@ -958,6 +960,13 @@ sbpe_status sbpe_set_tile_rows(sbpe_ctx_t c, int rows) {
     if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
     if (rows < 0 || rows > 256) return fail(c, SBPE_EINVAL, "tile rows must be 0 (default) or 1..256");
     c->tile_rows = rows;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_set_frame_loop(sbpe_ctx_t c, int groups) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (groups < 1 || groups > 64) return fail(c, SBPE_EINVAL, "frame groups per workgroup must be 1..64");
+    c->frame_loop = groups;
     return SBPE_OK;
 }
 
@@ -2082,6 +2091,7 @@ extern "C" sbpe_status sbpe_batch_advance(sbpe_batch_t b, int nsteps) {
         p1.nblocks = (int)b->desc.size();
         p1.pass = PASS_RK1;
         p1.wide = b->op == SBPE_OP_WIDE ? 1 : 0;
+        p1.floop = 1;
         p1.step = b->step + k;
         p1.rec_base = 0;
         p1.wa[0] = 1.0;

@@ -148,7 +148,7 @@ struct PassArgs {
     int step;                           // launch step index (time-function row step - step0)
     int rec_base;                       // receiver row of launch step index 0
     int wide;                           // 1: wide-stencil operator D_i c D_i for the i = k terms
-    int pad_w;
+    int floop;                          // one-launch sweeps: frame groups per frame workgroup (>= 1)
     double wa[3], wb[3];                // weights of the tabulated values: first / second evaluation
                                         // (second sweep: wb multiplies 2/dt^2 of each block)
     const void* in[MAX_APPLY_BLOCKS];   // sbpe_apply operands per block

@@ -1531,11 +1531,16 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
 // workgroups go first: their chains of dependent loads are long, and started
 // last they would set the end of the launch (spreading them evenly among the
 // tiles measured slower).
+// A frame workgroup takes floop consecutive frame groups (nt / FRAME_LANES
+// points each): fewer, longer frame workgroups in front of the tiles.
 template <typename T, int ORD, int PASS, bool SPLIT>
-__global__ void __launch_bounds__(SPLIT ? 128 : 64) k_pass(PassArgs A, int nframe) {
+__global__ void __launch_bounds__(SPLIT ? 128 : 64) k_pass(PassArgs A, int nframe, int floop) {
     const int bid = (int)blockIdx.x;
-    if (bid < nframe) frame_sp_body<T, ORD, PASS>(A, bid, SPLIT ? 128 : 64);
-    else march_body<T, ORD, PASS, SPLIT>(A, bid - nframe);
+    if (bid < nframe) {
+        for (int r = 0; r < floop; ++r) frame_sp_body<T, ORD, PASS>(A, bid * floop + r, SPLIT ? 128 : 64);
+    } else {
+        march_body<T, ORD, PASS, SPLIT>(A, bid - nframe);
+    }
 }
 
 template <typename T, int ORD, int PASS, bool SPLIT>
@@ -2281,13 +2286,15 @@ static void launch_pass_t(const PassArgs& a, int total_tiles, int total_frame_wg
     // frame workgroups (nt / FRAME_LANES points each), rounded to whole XCD rounds
     const long fpts = (long)total_frame_wg * FRAME_PTS;
     const int ppw = nt / FRAME_LANES;
-    const int nframe = (int)(((fpts + ppw - 1) / ppw + 7) / 8 * 8);
+    const int floop = a.floop > 1 ? a.floop : 1;   // frame groups per frame workgroup
+    const long ngroups = (fpts + ppw - 1) / ppw;
+    const int nframe = (int)(((ngroups + floop - 1) / floop + 7) / 8 * 8);
     const dim3 g(nframe + ((total_tiles + 7) / 8) * 8), bl(nt);
-    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_pass<T, ORD, PASS_APPLY, false>), g, bl, 0, s, a, nframe);
-    else if (a.pass == PASS_RK1 && split) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK1, true>), g, bl, 0, s, a, nframe);
-    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK1, false>), g, bl, 0, s, a, nframe);
-    else if (split) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK2, true>), g, bl, 0, s, a, nframe);
-    else hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK2, false>), g, bl, 0, s, a, nframe);
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_pass<T, ORD, PASS_APPLY, false>), g, bl, 0, s, a, nframe, floop);
+    else if (a.pass == PASS_RK1 && split) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK1, true>), g, bl, 0, s, a, nframe, floop);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK1, false>), g, bl, 0, s, a, nframe, floop);
+    else if (split) hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK2, true>), g, bl, 0, s, a, nframe, floop);
+    else hipLaunchKernelGGL((k_pass<T, ORD, PASS_RK2, false>), g, bl, 0, s, a, nframe, floop);
 }
 
 template <typename T, int ORD>

@@ -42,6 +42,7 @@ _PROTOS = {
     'sbpe_voigt_to_c10': [_DP, ctypes.c_size_t, _DP],
     'sbpe_set_operator': [_P, _I],
     'sbpe_set_tile_rows': [_P, _I],
+    'sbpe_set_frame_loop': [_P, _I],
     'sbpe_set_bc': [_P, _I, _I, _I, _DP],
     'sbpe_set_bc_data': [_P, _I, _I, _DP, _I, _DP],
     'sbpe_set_bc_dissipation': [_P, _I, _I, _DP],
@@ -165,6 +166,10 @@ def sbpe_voigt_to_c10(voigt):
 
 def sbpe_set_tile_rows(ctx, rows):
     _check(ctx, lib().sbpe_set_tile_rows(ctx, rows))
+
+
+def sbpe_set_frame_loop(ctx, groups):
+    _check(ctx, lib().sbpe_set_frame_loop(ctx, groups))
 
 
 def sbpe_set_operator(ctx, op):

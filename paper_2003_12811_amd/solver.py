@@ -74,6 +74,10 @@ class Solver:
         S.sbpe_finalize(ctx)
 
     # ------------------------------------------------------------ calls
+    def set_frame_loop(self, groups):
+        """Frame groups per frame workgroup of a one-launch sweep (launch shape only)."""
+        S.sbpe_set_frame_loop(self.ctx, groups)
+
     def dt_cfl(self, cfl):
         return S.sbpe_dt_cfl(self.ctx, cfl)
 

@@ -289,14 +289,15 @@ def test_full_size_c2_advance(dtype):
 
 
 def test_tile_rows_do_not_change_results():
-    """The interior tile height is a launch-shape choice: a run gives the same
-    bits for any height (the benchmark picks the fastest)."""
+    """The launch shape (interior tile height, frame groups per frame
+    workgroup) does not change a run's bits (the benchmark picks the fastest)."""
     n, nsteps = 97, 20
     spec = W.spec_c2(n=n, nrec=8)
-    say('tile rows', n)
+    say('launch shapes', n)
     out = []
-    for rows in (10, 7, 20):
+    for rows, loop in ((10, 1), (7, 3), (20, 4)):
         sol = solver(spec, 'f64', tile_rows=rows)
+        sol.set_frame_loop(loop)
         try:
             dt = T.dt_cfl(build(spec), 0.5) if not out else out[0][3]
             sol.set_state(None, None, 0.0)

@@ -166,6 +166,11 @@ def test_tile_rows_states():
             assert e.value.code == S.EINVAL
         S.sbpe_set_tile_rows(ctx, 20)
         S.sbpe_set_tile_rows(ctx, 0)
+        for bad in (0, 65):
+            with pytest.raises(S.SbpeError) as e:
+                S.sbpe_set_frame_loop(ctx, bad)
+            assert e.value.code == S.EINVAL
+        S.sbpe_set_frame_loop(ctx, 4)
         S.sbpe_add_block(ctx, X1, X2, rho, C10)
         S.sbpe_finalize(ctx)
         with pytest.raises(S.SbpeError) as e:

@@ -64,7 +64,7 @@ def roofline(kind, ms, points, wbytes, traffic_key=None, tile_rows=None):
 
 
 TILE_CANDIDATES = (10, 14, 16, 18, 20, 24)
-FRAME_LOOP_CANDIDATES = (1, 2, 4)
+FRAME_LOOP_CANDIDATES = (1, 2, 3, 4)
 
 
 def tune_launch(spec, dtype, tiles=TILE_CANDIDATES, loops=FRAME_LOOP_CANDIDATES, steps=60):
@@ -342,12 +342,13 @@ def main():
         log('wide-stencil operator, fp64')
         spw = dict(spec)
         spw['operator'] = 'wide'
-        tw = fixed if args.tile_rows else tune_launch(spw, 'f64', loops=(1,))
+        tw = fixed if args.tile_rows else tune_launch(spw, 'f64', loops=(1, 2, 4, 8))
         rw = run_gpu(spw, 'f64', args.steps, args.warmup, apply_reps=50, shape=tw[0])
         kw = dominant(rw)
         line["wide"] = {"workload": "the same %dx%d workload with the wide-stencil operator D_i c D_i, FP64"
                                     % (args.n, args.n),
-                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'], "tile_rows": tw[0][0],
+                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'],
+                        "tile_rows": tw[0][0], "frame_loop": tw[0][1],
                         "roofline": roofline(kw, rw['kernels'][kw][0], swept_points(rw['plan']), 8),
                         "apply_roofline": roofline('interior_apply', rw['apply_kernels']['interior_apply'][0],
                                                    swept_points(rw['plan']), 8),

@@ -1812,10 +1812,13 @@ __global__ void __launch_bounds__(64) k_wide(PassArgs A) {
 // one sweep of the wide-stencil operator in one launch: frame workgroups
 // first (as k_pass), then the interior tiles
 template <typename T, int ORD, int PASS>
-__global__ void __launch_bounds__(64) k_pass_wide(PassArgs A, int nframe) {
+__global__ void __launch_bounds__(64) k_pass_wide(PassArgs A, int nframe, int floop) {
     const int bid = (int)blockIdx.x;
-    if (bid < nframe) frame_sp_body<T, ORD, PASS>(A, bid, 64);
-    else wide_body<T, ORD, PASS>(A, bid - nframe);
+    if (bid < nframe) {
+        for (int r = 0; r < floop; ++r) frame_sp_body<T, ORD, PASS>(A, bid * floop + r, 64);
+    } else {
+        wide_body<T, ORD, PASS>(A, bid - nframe);
+    }
 }
 
 // ---------------------------------------------------------- tau table
@@ -2301,11 +2304,13 @@ template <typename T, int ORD>
 static void launch_pass_wide_t(const PassArgs& a, int total_tiles, int total_frame_wg, hipStream_t s) {
     const long fpts = (long)total_frame_wg * FRAME_PTS;
     const int ppw = 64 / FRAME_LANES;
-    const int nframe = (int)(((fpts + ppw - 1) / ppw + 7) / 8 * 8);
+    const int floop = a.floop > 1 ? a.floop : 1;
+    const long ngroups = (fpts + ppw - 1) / ppw;
+    const int nframe = (int)(((ngroups + floop - 1) / floop + 7) / 8 * 8);
     const dim3 g(nframe + ((total_tiles + 7) / 8) * 8), bl(64);
-    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_APPLY>), g, bl, 0, s, a, nframe);
-    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_RK1>), g, bl, 0, s, a, nframe);
-    else hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_RK2>), g, bl, 0, s, a, nframe);
+    if (a.pass == PASS_APPLY) hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_APPLY>), g, bl, 0, s, a, nframe, floop);
+    else if (a.pass == PASS_RK1) hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_RK1>), g, bl, 0, s, a, nframe, floop);
+    else hipLaunchKernelGGL((k_pass_wide<T, ORD, PASS_RK2>), g, bl, 0, s, a, nframe, floop);
 }
 
 int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg, void* stream) {

@@ -74,18 +74,18 @@ def _initial(n1, n2, dtype):
     return rounded(u0, dtype), rounded(v0, dtype)
 
 
-@pytest.mark.parametrize("dtype", ['f64', 'f32'])
-def test_dissipative_advance_matches_oracle_and_batch(dtype):
+@pytest.mark.parametrize("dtype,order", [('f64', 4), ('f32', 4), ('f64', 2)])
+def test_dissipative_advance_matches_oracle_and_batch(dtype, order):
     import torch
     n1, n2, nsteps = 150, 47, 40
-    say('dissipative advance', dtype, n1, n2)
-    spec = dissipative_spec(n1, n2)
+    say('dissipative advance', dtype, order, n1, n2)
+    spec = dissipative_spec(n1, n2, order=order)
     P = build(spec)
     dt = T.dt_cfl(P, 0.5)
     u0, v0 = _initial(n1, n2, dtype)
     sol = solver(spec, dtype)
     other = solver(spec, dtype)
-    b = S.sbpe_batch_create(0, torch.cuda.current_stream().cuda_stream, S.F64 if dtype == 'f64' else S.F32, 4)
+    b = S.sbpe_batch_create(0, torch.cuda.current_stream().cuda_stream, S.F64 if dtype == 'f64' else S.F32, order)
     try:
         sol.set_state([u0], [v0], 0.0)
         sol.advance(nsteps, dt)

@@ -258,13 +258,16 @@ def test_full_size_c2_apply(dtype):
 @pytest.mark.parametrize("dtype", ['f64', 'f32'])
 def test_full_size_c2_advance(dtype):
     """Config 2 at its full size (1025^2, source, receivers), advanced by the
-    one-launch RK sweeps the benchmark times, against the oracle's literal RK4:
-    the whole state after 3 steps from a smooth nonzero state."""
+    one-launch RK sweeps the benchmark times (in the launch shapes its tuning
+    picked on the measured machine: 20-row tiles, 2 frame groups per frame
+    workgroup in FP64 and 4 in FP32), against the oracle's literal RK4: the
+    whole state after 3 steps from a smooth nonzero state."""
     n, nsteps = 1025, 3
     say('full size C2 advance', dtype)
     spec = W.spec_c2(n=n, nrec=16)
     P = build(spec)
-    sol = solver(spec, dtype)
+    sol = solver(spec, dtype, tile_rows=20)
+    sol.set_frame_loop(2 if dtype == 'f64' else 4)
     try:
         plan = S.sbpe_plan_info(sol.ctx)
         assert plan['fused_sweep']

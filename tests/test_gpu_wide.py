@@ -120,11 +120,11 @@ def test_wide_apply_multiblock(dtype):
         sol.close()
 
 
-@pytest.mark.parametrize("dtype", ['f64', 'f32'])
-def test_wide_advance_source_receivers(dtype):
+@pytest.mark.parametrize("dtype,order", [('f64', 4), ('f32', 4), ('f64', 2)])
+def test_wide_advance_source_receivers(dtype, order):
     n, nsteps = 97, 60
-    say('wide advance C2 geometry', n, dtype)
-    spec = wide(W.spec_c2(n=n, nrec=8))
+    say('wide advance C2 geometry', n, dtype, order)
+    spec = wide(W.spec_c2(n=n, nrec=8, order=order))
     # receivers inside the interior tiles as well as on the surface
     spec['receivers'] = list(spec['receivers']) + [(0, np.array([0.43, 0.61]), np.array([0.55, 0.38]))]
     P = build(spec)

@@ -359,11 +359,13 @@ def main():
         # (about 0.8 GB per sweep; the 1025^2 working set fits the 256 MB MALL)
         log('hbm-bound working set: %dx%d, fp64' % (args.large_n, args.large_n))
         sph = W.spec_c2(n=args.large_n)
-        rh = run_gpu(sph, 'f64', max(args.steps // 4, 20), 10)
+        th = fixed if args.tile_rows else tune_launch(sph, 'f64', tiles=(10, 20), loops=(1, 2, 4), steps=20)
+        rh = run_gpu(sph, 'f64', max(args.steps // 4, 20), 10, shape=th[0])
         kh = dominant(rh)
         line["hbm_bound"] = {"workload": "the same recipe on one %dx%d block, FP64 (working set beyond the MALL)"
                                          % (args.large_n, args.large_n),
                              "value": rh['updates_per_s'], "ms_per_step": rh['ms_per_step'],
+                             "tile_rows": th[0][0], "frame_loop": th[0][1],
                              "roofline": roofline(kh, rh['kernels'][kh][0], swept_points(rh['plan']), 8),
                              "kernels_ms": {kk: v[0] for kk, v in rh['kernels'].items() if v[1]}}
         log('  %.3f ms/step, %.3e updates/s' % (rh['ms_per_step'], rh['updates_per_s']))

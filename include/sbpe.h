@@ -83,7 +83,8 @@ const char* sbpe_last_error(sbpe_ctx_t ctx);
  * [n2][n1]) and stiffness C10 ([10][n2][n1]: the major-symmetric components
  * C1111, C1112, C1121, C1122, C1212, C1221, C1222, C2121, C2122, C2222; minor
  * symmetry is not assumed, Sec. 3).  Arrays are copied.  All faces start as
- * homogeneous traction.  n1, n2 >= 13 for order 4, >= 6 for order 2. */
+ * homogeneous traction.  n1, n2 >= 13 for order 4, >= 6 for order 2, and
+ * n1 n2 <= 2^28 (SBPE_EINVAL otherwise, before the arrays are read). */
 sbpe_status sbpe_add_block(sbpe_ctx_t ctx, int n1, int n2, const double* X1, const double* X2,
                            const double* rho, const double* C10, int* block_id);
 

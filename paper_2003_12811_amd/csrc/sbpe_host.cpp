@@ -931,6 +931,9 @@ sbpe_status sbpe_add_block(sbpe_ctx_t c, int n1, int n2, const double* X1, const
     if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
     const int nmin = c->order == 4 ? 13 : 6;
     if (n1 < nmin || n2 < nmin) return fail(c, SBPE_EINVAL, "block too small for the operator order");
+    // the kernels address a field with 32-bit byte offsets and the frame operator
+    // encodes a partner point in 28 bits: at most 2^28 points per block
+    if ((long)n1 * n2 > (1L << 28)) return fail(c, SBPE_EINVAL, "block has more than 2^28 points");
     if (!X1 || !X2 || !rho || !C10) return fail(c, SBPE_EINVAL, "NULL array");
     const long np = (long)n1 * n2;
     for (long p = 0; p < np; ++p)

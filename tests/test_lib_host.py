@@ -154,6 +154,24 @@ def test_set_operator_states():
         S.sbpe_destroy(ctx)
 
 
+def test_block_size_limits():
+    """Below the operator's minimum and above 2^28 points a block is refused
+    before its arrays are read (the raw call gets one-element arrays)."""
+    import ctypes
+    lib = S.lib()
+    one = np.ones(1)
+    ptr = one.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    bid = ctypes.c_int(-1)
+    for order, sizes in ((4, [(12, 40), (40, 12), (16385, 16385), (1 << 20, 257)]), (2, [(5, 30)])):
+        ctx = _host_ctx(order)
+        try:
+            for n1, n2 in sizes:
+                st = lib.sbpe_add_block(ctx, n1, n2, ptr, ptr, ptr, ptr, ctypes.byref(bid))
+                assert st == S.EINVAL, (order, n1, n2, st)
+        finally:
+            S.sbpe_destroy(ctx)
+
+
 def test_tile_rows_states():
     n = 15
     X1, X2 = W.grid(W.Identity(), n, n)

@@ -374,10 +374,11 @@ def main():
         t0 = time.time()
         sp3 = W.spec_c3(n=args.large_n)
         log('  workload built in %.1f s' % (time.time() - t0))
-        r3 = run_gpu(sp3, 'f32', max(args.steps // 4, 20), 10)
+        t3 = fixed if args.tile_rows else tune_launch(sp3, 'f32', tiles=(10, 20), loops=(1,), steps=20)
+        r3 = run_gpu(sp3, 'f32', max(args.steps // 4, 20), 10, shape=t3[0])
         k3 = dominant(r3)
         line["large"] = {"workload": "2x2 blocks of %d^2 with interfaces, FP32" % args.large_n,
-                         "value": r3['updates_per_s'], "ms_per_step": r3['ms_per_step'],
+                         "value": r3['updates_per_s'], "ms_per_step": r3['ms_per_step'], "tile_rows": t3[0][0],
                          "roofline": roofline(k3, r3['kernels'][k3][0], swept_points(r3['plan']), 4),
                          "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]}}
         log('  %.3f ms/step, %.3e updates/s' % (r3['ms_per_step'], r3['updates_per_s']))

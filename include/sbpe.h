@@ -61,7 +61,7 @@ enum { SBPE_FACE_X1LO = 0, SBPE_FACE_X1HI = 1, SBPE_FACE_X2LO = 2, SBPE_FACE_X2H
 enum { SBPE_BC_TRACTION = 0, SBPE_BC_ROBIN = 1, SBPE_BC_DISPLACEMENT = 2, SBPE_BC_INTERFACE = 3 };
 /* time functions tau(t) multiplying separable data g(x) tau(t):
  *   ZERO: 0;  ONE: 1;  COS: cos(p0 t + p1);  RICKER: (1 - 2 a) exp(-a), a = (pi p0 (t - p1))^2
- *   (Ricker wavelet with peak frequency p0 centred at p1, Sec. 7.3). */
+ *   (Ricker wavelet with peak frequency p0 centred at p1, Sec. 7.4). */
 enum { SBPE_TIME_ZERO = 0, SBPE_TIME_ONE = 1, SBPE_TIME_COS = 2, SBPE_TIME_RICKER = 3 };
 
 /* Create a context bound to HIP device `device` and stream `stream` (NULL = the
@@ -163,7 +163,7 @@ sbpe_status sbpe_set_forcing(sbpe_ctx_t ctx, int block, const double* F, int tim
 
 /* Point force f = (f1, f2) amp W(t) delta(X - X(x0)) at reference position
  * (x1, x2) in [0,1]^2 with Ricker time function W of peak frequency peak_hz
- * centred at t0 (Sec. 7.3).  The discrete delta uses four-point moment-matching
+ * centred at t0 (Sec. 7.4).  The discrete delta uses four-point moment-matching
  * weights per direction (exact for cubics). */
 sbpe_status sbpe_add_source(sbpe_ctx_t ctx, int block, double x1, double x2, double f1, double f2,
                             double amp, double peak_hz, double t0);
@@ -272,7 +272,7 @@ sbpe_status sbpe_lincomb(sbpe_ctx_t ctx, int nterms, const double* coefs, const 
                          long long count);
 
 /* u[b] += scale * (H rho~)^{-1} S^T r, the adjoint of the receiver sampling
- * (Sec. 7.3) in the scaled variables: r is FP64 device [nrec][2] in the order
+ * (Sec. 7.4) in the scaled variables: r is FP64 device [nrec][2] in the order
  * of sbpe_add_receivers, u the device displacement fields of every block. */
 sbpe_status sbpe_receiver_adjoint(sbpe_ctx_t ctx, const void* r, void* const* u, double scale);
 

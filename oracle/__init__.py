@@ -23,7 +23,7 @@ definitions literally:
                 Sec. 6 eq. scheme_interface), assembled face by face.
 * ``timestep``  classical RK4 on (u, u_t) and the Christoffel time step (Sec. 7).
 * ``sources``   Ricker wavelet, moment-matching point source and receivers
-                (Sec. 7.3).
+                (Sec. 7.4; the discrete delta function is cited in Sec. 7.3-7.4).
 
 Parity status of every function is recorded in its module docstring; all
 functions are pinned by ``tests/test_oracle_*.py``.

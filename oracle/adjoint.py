@@ -126,7 +126,8 @@ def coef_gradient(P, k, w, Y, t=0.0, homogeneous=True):
 
 # --------------------------------------------------------------- the misfit
 def _sample_ops(spec, P):
-    """Receiver sampling as (block, idx, w) per receiver (moment weights, Sec. 7.3)."""
+    """Receiver sampling as (block, idx, w) per receiver (moment weights; the
+    discrete delta function is cited in Sec. 7.3-7.4)."""
     from .sources import weights_2d
     ops = []
     for (bid, x1, x2) in spec.get('receivers', []):

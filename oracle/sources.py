@@ -1,8 +1,8 @@
 """Point sources, receivers and the Ricker wavelet (oracle, test infrastructure only).
 
 * Ricker wavelet W(t) = (1 - 2 pi^2 a^2 (t - t0)^2) exp(-pi^2 a^2 (t - t0)^2)
-  with peak frequency a (Sec. 7.3).
-* Point force f_J = dir_J amp W(t) delta(X - X0) (Sec. 7.3).  The paper cites a
+  with peak frequency a (Sec. 7.4).
+* Point force f_J = dir_J amp W(t) delta(X - X0) (Sec. 7.4).  The paper cites a
   discrete delta function without printing it; the reading used here is the
   tensor product of 1-D weights on the four nearest grid points of each
   reference direction (shifted inward at faces) that satisfy the moment
@@ -13,7 +13,7 @@
 
 Parity status: pinned (tests/test_oracle_time.py: moment conditions, exactness
 for cubic polynomials, source/receiver adjointness, alpha_M / alpha_P = 2.40 of
-Sec. 7.3).
+Sec. 7.4).
 """
 import numpy as np
 

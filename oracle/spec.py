@@ -3,7 +3,7 @@
 A spec is a dict of NumPy arrays and tuples (the seeded workloads produce them):
 order, blocks [X1, X2, rho, C10, bc = 4 x (kind, g, time_fn, time_params, U),
 forcing], interfaces, interface_data, dissipation, sources, receivers.  Time functions: 0 zero, 1 one,
-2 cos(p0 t + p1), 3 Ricker(peak p0, centre p1) (Sec. 7.3).
+2 cos(p0 t + p1), 3 Ricker(peak p0, centre p1) (Sec. 7.4).
 """
 import numpy as np
 

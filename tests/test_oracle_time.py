@@ -6,7 +6,7 @@
   by the semidiscrete scheme; RK4 inside its stability region does not let it
   grow; an oversize step does (failure injection for the energy guard).
 * Christoffel (Sec. 3.1): isotropic P speed sqrt((lambda + 2 mu)/rho).
-* Ricker (Sec. 7.3): alpha_M / alpha_P = 2.40 (golden value printed in the paper).
+* Ricker (Sec. 7.4): alpha_M / alpha_P = 2.40 (golden value printed in the paper).
 * Point source / receiver: moment conditions, cubic exactness, adjointness.
 * Manufactured solution: observed convergence rates of the fourth- and
   second-order schemes (Sec. 7.1 reports 3.56 and 1.96 on its own geometry).

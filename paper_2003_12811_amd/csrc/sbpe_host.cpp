@@ -2159,17 +2159,15 @@ extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, 
     g.wide = c->op == SBPE_OP_WIDE ? 1 : 0;
     g.alpha = alpha;
     g.tau = c->d_tau;
-    long off = 0;
     for (int b = 0; b < nb; ++b) {
-        g.off[b] = off;
-        off += c->blocks[b].np();
+        g.n1[b] = c->blocks[b].n1;
+        g.n2[b] = c->blocks[b].n2;
         g.z[b] = z[b];
         g.y[b] = y[b];
         g.a[b] = a[b];
         g.gc[b] = static_cast<double*>(gc[b]);
         g.grt[b] = static_cast<double*>(grt[b]);
     }
-    g.off[nb] = off;
     const int e = launch_grad(c->dtype, c->order, g, c->stream);
     if (e != 0) return fail(c, SBPE_EHIP, std::string("gradient launch: ") + hip_error_string(e));
     return SBPE_OK;

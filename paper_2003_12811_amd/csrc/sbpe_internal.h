@@ -169,7 +169,9 @@ struct GradArgs {
     int nblocks;
     int homogeneous;      // displacement data left out of delta = y - g(t)
     int wide;             // wide-stencil operator: the i = k terms are D_i c D_i
-    long off[MAX_APPLY_BLOCKS + 1];   // first flat point of each block in the launch
+    int n1[MAX_APPLY_BLOCKS], n2[MAX_APPLY_BLOCKS];   // block sizes
+    long off[MAX_APPLY_BLOCKS + 1];   // first interior point of each block (interior launch; set by the launcher)
+    long boff[MAX_APPLY_BLOCKS + 1];  // first band point of each block (band launch; set by the launcher)
     double alpha;
     const double* tau;    // tabulated time functions at t (row 0)
     const void* z[MAX_APPLY_BLOCKS];

@@ -1981,6 +1981,14 @@ __device__ __forceinline__ void d2_coef_grad_pairs(gcp<T> z0, gcp<T> z1, gcp<T> 
     }
 }
 
+// distance from the faces beyond which every row of the coefficient gradient
+// is an interior row (the D2^FC closure plus the stencil half width)
+template <int ORD>
+__host__ __device__ constexpr int grad_lo() {
+    using O = Op<ORD>;
+    return (O::R0 + O::HALF > O::W) ? O::R0 + O::HALF : O::W;
+}
+
 // (D1^ T (H^ z))_p = sum_r D1^[r][p] H^_r z_r along a line (D1^ = h D1)
 template <typename T, int ORD>
 __device__ double d1t_weighted(gcp<T> z, long st, int p, int n) {
@@ -2010,15 +2018,23 @@ __device__ double d1t_weighted(gcp<T> z, long st, int p, int n) {
     return acc;
 }
 
+// Points closer than grad_lo<ORD>() to a face (closure rows and faces): the
+// general rows; k_grad_int below takes the rest.  A workgroup takes 64 band
+// points; wave w evaluates term group w for all of them (0: x1 i = k terms,
+// 1: x2 i = k terms, 2: mixed terms, 3: face terms), so the long chains of
+// closure-row loads are spread over four waves, and wave 0 adds the groups
+// (through LDS) and the rho~ term.
 template <typename T, int ORD>
 __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     using O = Op<ORD>;
-    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    __shared__ double s_g[4][10][64];
+    const int part = (int)(threadIdx.x >> 6);
+    const long gid = (long)blockIdx.x * 64 + (threadIdx.x & 63);
     // block of this point and its operands, read from the kernel argument
     // with static indices only (a runtime index would copy the argument to
     // per-lane scratch memory)
     int b = 0;
-    long end = G.off[1];
+    long end = G.boff[1];
     gcp<T> z = gc<T>(G.z[0]);
     gcp<T> y = gc<T>(G.y[0]);
     gcp<T> a = gc<T>(G.a[0]);
@@ -2027,37 +2043,50 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     long base = 0;
 #pragma unroll
     for (int k = 1; k < MAX_APPLY_BLOCKS; ++k)
-        if (k < G.nblocks && gid >= G.off[k]) {
+        if (k < G.nblocks && gid >= G.boff[k]) {
             b = k;
-            base = G.off[k];
-            end = G.off[k + 1];
+            base = G.boff[k];
+            end = G.boff[k + 1];
             z = gc<T>(G.z[k]);
             y = gc<T>(G.y[k]);
             a = gc<T>(G.a[k]);
             gcb = G.gc[k];
             grb = G.grt[k];
         }
-    if (gid >= end) return;
+    const bool valid = gid < end;
     BlockRef B = ((const GLB BlockDesc*)G.blocks)[b];
     const int n1 = B.n1, n2 = B.n2;
     const long np = (long)n1 * n2;
-    const long p = gid - base;
-    const int j = (int)(p / n1), i = (int)(p - (long)j * n1);
+    constexpr int LO = grad_lo<ORD>();
+    int i, j;
+    const int kb = valid ? (int)(gid - base) : 0;
+    if (n1 > 2 * LO && n2 > 2 * LO) {
+        frame_ij(kb, n1, n2, LO, i, j);     // the band of width LO
+    } else {
+        j = kb / n1;                        // no interior: every point
+        i = kb - j * n1;
+    }
+    const long p = (long)j * n1 + i;
     const double h1 = B.h1, h2 = B.h2;
     const double hn1 = hnorm<ORD>(i, n1), hn2 = hnorm<ORD>(j, n2);
     const long row = (long)j * n1;
     double g[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double tzx[2], tzy[2], dyx[2], dyy[2];   // (D^T H z) and D y along x1 and x2 at p
+    double tzx[2] = {0, 0}, tzy[2] = {0, 0}, dyx[2] = {0, 0}, dyy[2] = {0, 0};   // (D^T H z), D y at p
+    const bool nx = part == 2 || (part == 0 && G.wide), ny = part == 2 || (part == 1 && G.wide);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        tzx[c] = d1t_weighted<T, ORD>(z + c * np + row, 1, i, n1);
-        tzy[c] = d1t_weighted<T, ORD>(z + c * np + i, n1, j, n2);
-        dyx[c] = (double)d1_line<T, ORD>(y + c * np + row, 1, i, n1);
-        dyy[c] = (double)d1_line<T, ORD>(y + c * np + i, n1, j, n2);
+        if (valid && nx) {
+            tzx[c] = d1t_weighted<T, ORD>(z + c * np + row, 1, i, n1);
+            dyx[c] = (double)d1_line<T, ORD>(y + c * np + row, 1, i, n1);
+        }
+        if (valid && ny) {
+            tzy[c] = d1t_weighted<T, ORD>(z + c * np + i, n1, j, n2);
+            dyy[c] = (double)d1_line<T, ORD>(y + c * np + i, n1, j, n2);
+        }
     }
     // i = k terms (stored fields: x1 C1111, C1112, C1212; x2 C2121, C2122, C2222)
-    {
-        const double fx = h2 * hn2 / h1, fy = h1 * hn1 / h2;
+    if (valid && part == 0) {
+        const double fx = h2 * hn2 / h1;
         double a00, a01, a11;
         if (G.wide) {
             // z^T H D_1 b D_1 y: dB/db_p = (D_1^T H z)(p) (D_1 y)(p), as for the mixed terms
@@ -2070,6 +2099,10 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
         g[K_C1111] += fx * a00;
         g[K_C1112] += fx * a01;
         g[K_C1212] += fx * a11;
+    }
+    if (valid && part == 1) {
+        const double fy = h1 * hn1 / h2;
+        double a00, a01, a11;
         if (G.wide) {
             a00 = tzy[0] * dyy[0];
             a01 = tzy[0] * dyy[1] + tzy[1] * dyy[0];
@@ -2082,7 +2115,7 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
         g[K_C2222] += fy * a11;
     }
     // mixed terms: M_ab = c_1a2b (C1121, C1122, C1221, C1222)
-    {
+    if (valid && part == 2) {
         const int km[2][2] = {{K_C1121, K_C1122}, {K_C1221, K_C1222}};
 #pragma unroll
         for (int aa = 0; aa < 2; ++aa)
@@ -2091,7 +2124,7 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     }
     // faces through this point
 #pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < 4 && valid && part == 3; ++f) {
         const int ax = f >> 1, sd = f & 1;
         const bool on = ax == 0 ? (i == (sd ? n1 - 1 : 0)) : (j == (sd ? n2 - 1 : 0));
         if (!on) continue;
@@ -2161,12 +2194,114 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
                 }
         }
     }
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) s_g[part][k][lane] = g[k];
+    __syncthreads();
+    if (part != 0 || !valid) return;
     const double Hp = h1 * h2 * hn1 * hn2;
     const double al = G.alpha;
     gp<double> gq = (gp<double>)gcb;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) gq[(long)k * np + p] += al * g[k];
+    for (int k = 0; k < 10; ++k)
+        gq[(long)k * np + p] += al * (s_g[0][k][lane] + s_g[1][k][lane] + s_g[2][k][lane] + s_g[3][k][lane]);
     ((gp<double>)grb)[p] += -al * Hp * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
+}
+
+
+// Interior points (>= grad_lo<ORD>() from every face): only interior rows of
+// D1 and D2^FC, no faces, unit norm weights around the point.
+template <typename T, int ORD>
+__global__ void __launch_bounds__(256) k_grad_int(GradArgs G) {
+    using O = Op<ORD>;
+    constexpr int HF = O::HALF;
+    constexpr int LO = grad_lo<ORD>();
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    int b = 0;
+    long end = G.off[1];
+    gcp<T> z = gc<T>(G.z[0]);
+    gcp<T> y = gc<T>(G.y[0]);
+    gcp<T> a = gc<T>(G.a[0]);
+    double* gcb = G.gc[0];
+    double* grb = G.grt[0];
+    long base = 0;
+#pragma unroll
+    for (int k = 1; k < MAX_APPLY_BLOCKS; ++k)
+        if (k < G.nblocks && gid >= G.off[k]) {
+            b = k;
+            base = G.off[k];
+            end = G.off[k + 1];
+            z = gc<T>(G.z[k]);
+            y = gc<T>(G.y[k]);
+            a = gc<T>(G.a[k]);
+            gcb = G.gc[k];
+            grb = G.grt[k];
+        }
+    if (gid >= end) return;
+    BlockRef B = ((const GLB BlockDesc*)G.blocks)[b];
+    const int n1 = B.n1, n2 = B.n2;
+    const long np = (long)n1 * n2;
+    const int ni1 = n1 - 2 * LO;
+    const int q = (int)(gid - base);
+    const int j = LO + q / ni1, i = LO + q % ni1;
+    const long p = (long)j * n1 + i;
+    const double h1 = B.h1, h2 = B.h2;
+    // windows of z (+-H) and y (+-2H) along both lines through p
+    double zx[2][2 * HF + 1], zy[2][2 * HF + 1], yx[2][4 * HF + 1], yy[2][4 * HF + 1];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int k = 0; k <= 2 * HF; ++k) {
+            zx[c][k] = (double)z[c * np + p + (k - HF)];
+            zy[c][k] = (double)z[c * np + p + (long)(k - HF) * n1];
+        }
+#pragma unroll
+        for (int k = 0; k <= 4 * HF; ++k) {
+            yx[c][k] = (double)y[c * np + p + (k - 2 * HF)];
+            yy[c][k] = (double)y[c * np + p + (long)(k - 2 * HF) * n1];
+        }
+    }
+    // interior rows: h D1 y at p and (h D1^T z)_p (norm weights 1 around p)
+    double tzx[2], tzy[2], dyx[2], dyy[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        tzx[c] = tzy[c] = dyx[c] = dyy[c] = 0.0;
+#pragma unroll
+        for (int k = 1; k <= HF; ++k) {
+            const double w = O::d1i(HF + k);
+            tzx[c] += w * (zx[c][HF - k] - zx[c][HF + k]);
+            tzy[c] += w * (zy[c][HF - k] - zy[c][HF + k]);
+            dyx[c] += w * (yx[c][2 * HF + k] - yx[c][2 * HF - k]);
+            dyy[c] += w * (yy[c][2 * HF + k] - yy[c][2 * HF - k]);
+        }
+    }
+    double g[10];
+    const double fx = h2 / h1, fy = h1 / h2;
+    if (G.wide) {
+        g[K_C1111] = fx * tzx[0] * dyx[0];
+        g[K_C1112] = fx * (tzx[0] * dyx[1] + tzx[1] * dyx[0]);
+        g[K_C1212] = fx * tzx[1] * dyx[1];
+        g[K_C2121] = fy * tzy[0] * dyy[0];
+        g[K_C2122] = fy * (tzy[0] * dyy[1] + tzy[1] * dyy[0]);
+        g[K_C2222] = fy * tzy[1] * dyy[1];
+    } else {
+        g[K_C1111] = fx * d2_coef_grad_win<ORD>(zx[0], yx[0]);
+        g[K_C1112] = fx * (d2_coef_grad_win<ORD>(zx[0], yx[1]) + d2_coef_grad_win<ORD>(zx[1], yx[0]));
+        g[K_C1212] = fx * d2_coef_grad_win<ORD>(zx[1], yx[1]);
+        g[K_C2121] = fy * d2_coef_grad_win<ORD>(zy[0], yy[0]);
+        g[K_C2122] = fy * (d2_coef_grad_win<ORD>(zy[0], yy[1]) + d2_coef_grad_win<ORD>(zy[1], yy[0]));
+        g[K_C2222] = fy * d2_coef_grad_win<ORD>(zy[1], yy[1]);
+    }
+    const int km[2][2] = {{K_C1121, K_C1122}, {K_C1221, K_C1222}};
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) g[km[aa][bb]] = tzx[aa] * dyy[bb] + tzy[bb] * dyx[aa];
+    const double al = G.alpha;
+    gp<double> gq = (gp<double>)gcb;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gq[(long)k * np + p] += al * g[k];
+    ((gp<double>)grb)[p] += -al * h1 * h2 * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
 }
 
 // y = sum_k c_k x_k (elementwise; y may be one of the x_k)
@@ -2407,17 +2542,34 @@ int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks
     return static_cast<int>(hipGetLastError());
 }
 
+template <typename T, int ORD>
+static void launch_grad_t(GradArgs g, hipStream_t s) {
+    // interior and band point counts per block (cumulative)
+    constexpr int LO = grad_lo<ORD>();
+    long oi = 0, ob = 0;
+    for (int b = 0; b < g.nblocks; ++b) {
+        const long n1 = g.n1[b], n2 = g.n2[b];
+        const long ni = (n1 > 2 * LO && n2 > 2 * LO) ? (n1 - 2 * LO) * (n2 - 2 * LO) : 0;
+        g.off[b] = oi;
+        g.boff[b] = ob;
+        oi += ni;
+        ob += n1 * n2 - ni;
+    }
+    g.off[g.nblocks] = oi;
+    g.boff[g.nblocks] = ob;
+    if (oi > 0) hipLaunchKernelGGL((k_grad_int<T, ORD>), dim3((unsigned)((oi + 255) / 256)), dim3(256), 0, s, g);
+    if (ob > 0) hipLaunchKernelGGL((k_grad<T, ORD>), dim3((unsigned)((ob + 63) / 64)), dim3(256), 0, s, g);
+}
+
 int launch_grad(int dtype, int order, const GradArgs& g, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const long n = g.off[g.nblocks];
-    if (n <= 0) return 0;
-    const dim3 grid((unsigned)((n + 255) / 256)), bl(256);
+    if (g.nblocks <= 0) return 0;
     if (dtype == 0) {
-        if (order == 4) hipLaunchKernelGGL((k_grad<double, 4>), grid, bl, 0, s, g);
-        else hipLaunchKernelGGL((k_grad<double, 2>), grid, bl, 0, s, g);
+        if (order == 4) launch_grad_t<double, 4>(g, s);
+        else launch_grad_t<double, 2>(g, s);
     } else {
-        if (order == 4) hipLaunchKernelGGL((k_grad<float, 4>), grid, bl, 0, s, g);
-        else hipLaunchKernelGGL((k_grad<float, 2>), grid, bl, 0, s, g);
+        if (order == 4) launch_grad_t<float, 4>(g, s);
+        else launch_grad_t<float, 2>(g, s);
     }
     return (int)hipGetLastError();
 }

@@ -2020,14 +2020,17 @@ __device__ double d1t_weighted(gcp<T> z, long st, int p, int n) {
 
 // Points closer than grad_lo<ORD>() to a face (closure rows and faces): the
 // general rows; k_grad_int below takes the rest.  A workgroup takes 64 band
-// points; wave w evaluates term group w for all of them (0: x1 i = k terms,
-// 1: x2 i = k terms, 2: mixed terms, 3: face terms), so the long chains of
-// closure-row loads are spread over four waves, and wave 0 adds the groups
-// (through LDS) and the rho~ term.
+// points; wave w evaluates term group w for all of them (0-2: the x1 i = k
+// terms of the component pairs (1,1), (1,2) + (2,1), (2,2); 3-5: the same along
+// x2; 6: mixed terms; 7: face terms), so the long chains of closure-row loads
+// are spread over eight waves, and wave 0 adds the groups (through LDS) and
+// the rho~ term.
+constexpr int GRAD_PARTS = 8;
+
 template <typename T, int ORD>
-__global__ void __launch_bounds__(256) k_grad(GradArgs G) {
+__global__ void __launch_bounds__(GRAD_PARTS * 64) k_grad(GradArgs G) {
     using O = Op<ORD>;
-    __shared__ double s_g[4][10][64];
+    __shared__ double s_g[GRAD_PARTS][10][64];
     const int part = (int)(threadIdx.x >> 6);
     const long gid = (long)blockIdx.x * 64 + (threadIdx.x & 63);
     // block of this point and its operands, read from the kernel argument
@@ -2072,7 +2075,7 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     const long row = (long)j * n1;
     double g[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     double tzx[2] = {0, 0}, tzy[2] = {0, 0}, dyx[2] = {0, 0}, dyy[2] = {0, 0};   // (D^T H z), D y at p
-    const bool nx = part == 2 || (part == 0 && G.wide), ny = part == 2 || (part == 1 && G.wide);
+    const bool nx = part == 6 || (part <= 2 && G.wide), ny = part == 6 || (part >= 3 && part <= 5 && G.wide);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         if (valid && nx) {
@@ -2085,37 +2088,40 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
         }
     }
     // i = k terms (stored fields: x1 C1111, C1112, C1212; x2 C2121, C2122, C2222)
-    if (valid && part == 0) {
-        const double fx = h2 * hn2 / h1;
-        double a00, a01, a11;
+    if (valid && part <= 5) {
+        const bool ax2 = part >= 3;
+        const int pr = ax2 ? part - 3 : part;              // pair: (1,1), (1,2) + (2,1), (2,2)
+        const double f = ax2 ? h1 * hn1 / h2 : h2 * hn2 / h1;
+        // member-wise selects: indexing a local array with a runtime choice would put it in scratch memory
+        const double tz0 = ax2 ? tzy[0] : tzx[0], tz1 = ax2 ? tzy[1] : tzx[1];
+        const double dy0 = ax2 ? dyy[0] : dyx[0], dy1 = ax2 ? dyy[1] : dyx[1];
+        double gv;
         if (G.wide) {
-            // z^T H D_1 b D_1 y: dB/db_p = (D_1^T H z)(p) (D_1 y)(p), as for the mixed terms
-            a00 = tzx[0] * dyx[0];
-            a01 = tzx[0] * dyx[1] + tzx[1] * dyx[0];
-            a11 = tzx[1] * dyx[1];
+            // z^T H D_i b D_i y: dB/db_p = (D_i^T H z)(p) (D_i y)(p), as for the mixed terms
+            gv = pr == 0 ? tz0 * dy0 : (pr == 1 ? tz0 * dy1 + tz1 * dy0 : tz1 * dy1);
         } else {
-            d2_coef_grad_pairs<T, ORD>(z + row, z + np + row, y + row, y + np + row, 1, i, n1, a00, a01, a11);
+            const long st = ax2 ? n1 : 1;
+            const long l0 = ax2 ? (long)i : row;            // start of the line through p
+            const int pp = ax2 ? j : i, nn = ax2 ? n2 : n1;
+            if (pr == 0) {
+                gv = d2_coef_grad<T, ORD>(z + l0, y + l0, st, pp, nn);
+            } else if (pr == 1) {
+                gv = d2_coef_grad<T, ORD>(z + l0, y + np + l0, st, pp, nn) +
+                     d2_coef_grad<T, ORD>(z + np + l0, y + l0, st, pp, nn);
+            } else {
+                gv = d2_coef_grad<T, ORD>(z + np + l0, y + np + l0, st, pp, nn);
+            }
         }
-        g[K_C1111] += fx * a00;
-        g[K_C1112] += fx * a01;
-        g[K_C1212] += fx * a11;
-    }
-    if (valid && part == 1) {
-        const double fy = h1 * hn1 / h2;
-        double a00, a01, a11;
-        if (G.wide) {
-            a00 = tzy[0] * dyy[0];
-            a01 = tzy[0] * dyy[1] + tzy[1] * dyy[0];
-            a11 = tzy[1] * dyy[1];
-        } else {
-            d2_coef_grad_pairs<T, ORD>(z + i, z + np + i, y + i, y + np + i, n1, j, n2, a00, a01, a11);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k == pr) {
+                if (ax2) g[k == 0 ? K_C2121 : (k == 1 ? K_C2122 : K_C2222)] += f * gv;
+                else g[k == 0 ? K_C1111 : (k == 1 ? K_C1112 : K_C1212)] += f * gv;
+            }
         }
-        g[K_C2121] += fy * a00;
-        g[K_C2122] += fy * a01;
-        g[K_C2222] += fy * a11;
     }
     // mixed terms: M_ab = c_1a2b (C1121, C1122, C1221, C1222)
-    if (valid && part == 2) {
+    if (valid && part == 6) {
         const int km[2][2] = {{K_C1121, K_C1122}, {K_C1221, K_C1222}};
 #pragma unroll
         for (int aa = 0; aa < 2; ++aa)
@@ -2124,7 +2130,7 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     }
     // faces through this point
 #pragma unroll 1
-    for (int f = 0; f < 4 && valid && part == 3; ++f) {
+    for (int f = 0; f < 4 && valid && part == 7; ++f) {
         const int ax = f >> 1, sd = f & 1;
         const bool on = ax == 0 ? (i == (sd ? n1 - 1 : 0)) : (j == (sd ? n2 - 1 : 0));
         if (!on) continue;
@@ -2203,8 +2209,12 @@ __global__ void __launch_bounds__(256) k_grad(GradArgs G) {
     const double al = G.alpha;
     gp<double> gq = (gp<double>)gcb;
 #pragma unroll
-    for (int k = 0; k < 10; ++k)
-        gq[(long)k * np + p] += al * (s_g[0][k][lane] + s_g[1][k][lane] + s_g[2][k][lane] + s_g[3][k][lane]);
+    for (int k = 0; k < 10; ++k) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < GRAD_PARTS; ++w) sum += s_g[w][k][lane];
+        gq[(long)k * np + p] += al * sum;
+    }
     ((gp<double>)grb)[p] += -al * Hp * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
 }
 
@@ -2558,7 +2568,7 @@ static void launch_grad_t(GradArgs g, hipStream_t s) {
     g.off[g.nblocks] = oi;
     g.boff[g.nblocks] = ob;
     if (oi > 0) hipLaunchKernelGGL((k_grad_int<T, ORD>), dim3((unsigned)((oi + 255) / 256)), dim3(256), 0, s, g);
-    if (ob > 0) hipLaunchKernelGGL((k_grad<T, ORD>), dim3((unsigned)((ob + 63) / 64)), dim3(256), 0, s, g);
+    if (ob > 0) hipLaunchKernelGGL((k_grad<T, ORD>), dim3((unsigned)((ob + 63) / 64)), dim3(GRAD_PARTS * 64), 0, s, g);
 }
 
 int launch_grad(int dtype, int order, const GradArgs& g, void* stream) {

@@ -47,16 +47,17 @@ def log(*a):
 
 # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)
 # of the 1025^2 workload; ignored once the kernel source has changed
-TRAFFIC_PROFILE = os.path.join(ROOT, 'profiles', 'hbm_traffic_c2_1025.md')
+TRAFFIC_PROFILES = {n: os.path.join(ROOT, 'profiles', 'hbm_traffic_c2_%d.md' % n) for n in (1025, 2049)}
 
 
-def roofline(kind, ms, points, wbytes, traffic_key=None, tile_rows=None):
+def roofline(kind, ms, points, wbytes, traffic_key=None, tile_rows=None, n=1025):
     byts = WORDS[kind] * wbytes * points
     gbs = byts / (ms * 1e-3) / 1e9
     traffic = None
     if traffic_key is not None:
         from paper_2003_12811_amd import profiling
-        t = profiling.read_traffic(TRAFFIC_PROFILE, tile_rows=tile_rows or 10)
+        path = TRAFFIC_PROFILES.get(n)
+        t = profiling.read_traffic(path, tile_rows=tile_rows or 10) if path else None
         traffic = t.get(traffic_key) if t else None
     return {"bound": "hbm", "kernel": kind, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
@@ -325,7 +326,7 @@ def main():
                    "tile_rows": tuned64[0][0], "frame_loop": tuned64[0][1],
                    "launch_shape_ms_per_step": tuned64[1]},
         "roofline": roofline(k, r64['kernels'][k][0], pts, 8,
-                             traffic_key=('%s/f64/o4' % k) if args.n == 1025 else None, tile_rows=tuned64[0][0]),
+                             traffic_key='%s/f64/o4' % k, tile_rows=tuned64[0][0], n=args.n),
         "kernels_ms": {kk: v[0] for kk, v in r64['kernels'].items() if v[1]},
         "ms_per_step_with_events": r64['ms_per_step_with_events'],
         "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8),
@@ -366,7 +367,8 @@ def main():
                                          % (args.large_n, args.large_n),
                              "value": rh['updates_per_s'], "ms_per_step": rh['ms_per_step'],
                              "tile_rows": th[0][0], "frame_loop": th[0][1],
-                             "roofline": roofline(kh, rh['kernels'][kh][0], swept_points(rh['plan']), 8),
+                             "roofline": roofline(kh, rh['kernels'][kh][0], swept_points(rh['plan']), 8,
+                                                  traffic_key='%s/f64/o4' % kh, tile_rows=th[0][0], n=args.large_n),
                              "kernels_ms": {kk: v[0] for kk, v in rh['kernels'].items() if v[1]}}
         log('  %.3f ms/step, %.3e updates/s' % (rh['ms_per_step'], rh['updates_per_s']))
     if not args.no_large:

@@ -100,12 +100,13 @@ def tune_launch(spec, dtype, tiles=TILE_CANDIDATES, loops=FRAME_LOOP_CANDIDATES,
     return best, table
 
 
-def run_gpu(spec, dtype, steps, warmup, apply_reps=0, shape=(0, 1)):
+def run_gpu(spec, dtype, steps, warmup, apply_reps=0, shape=(0, 0)):
     import torch
     from paper_2003_12811_amd import sbpe as S
     from paper_2003_12811_amd.solver import Solver
     sol = Solver(spec, dtype, tile_rows=shape[0])
-    sol.set_frame_loop(shape[1])
+    if shape[1]:
+        sol.set_frame_loop(shape[1])
     dt = sol.dt_cfl(spec.get('cfl', 0.5))
     sol.set_state(None, None, 0.0)
     plan = S.sbpe_plan_info(sol.ctx)
@@ -272,8 +273,8 @@ def main():
     ap.add_argument('--no-hbm', action='store_true')
     ap.add_argument('--tile-rows', type=int, default=0,
                     help='interior tile height of the 1025^2 runs (0: pick the launch shape by timing candidates)')
-    ap.add_argument('--frame-loop', type=int, default=1,
-                    help='frame groups per frame workgroup, used with --tile-rows')
+    ap.add_argument('--frame-loop', type=int, default=0,
+                    help='frame groups per frame workgroup, used with --tile-rows (0: the library default)')
     ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')

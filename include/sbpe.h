@@ -101,10 +101,10 @@ sbpe_status sbpe_voigt_to_c10(const double* voigt, size_t npts, double* C10);
 sbpe_status sbpe_set_tile_rows(sbpe_ctx_t ctx, int rows);
 
 /* Frame groups per frame workgroup of a one-launch sweep (another launch-shape
- * parameter; results do not depend on it): 1 (default) .. 64; a group is 16
- * frame points (8 with the wide operator).  May be called at any time; it
- * applies to the context's own sweeps (batches use 1).  SBPE_EINVAL outside
- * 1..64. */
+ * parameter; results do not depend on it): 1 .. 64, default 2 (FP64) or 4
+ * (FP32); a group is 16 frame points (8 with the wide operator).  May be
+ * called at any time; it applies to the context's own sweeps (batches use the
+ * default of their dtype).  SBPE_EINVAL outside 1..64. */
 sbpe_status sbpe_set_frame_loop(sbpe_ctx_t ctx, int groups);
 
 /* Second-derivative operator of the i = k terms DD_ii(c) of the elastic

@@ -159,7 +159,7 @@ struct sbpe_ctx {
     int op = SBPE_OP_NARROW;        // second-derivative operator of the i = k terms
     bool dissipative = false;       // some face carries a dissipative Robin term V u_t
     int tile_rows = 0;              // output rows per interior tile (0: the default)
-    int frame_loop = 1;             // one-launch sweeps: frame groups per frame workgroup
+    int frame_loop = 1;             // one-launch sweeps: frame groups per frame workgroup (set at create)
     double beta = 1.0;
     bool host_only = false;
     std::string err;
@@ -842,6 +842,11 @@ static void set_time_fn(int kind, const double* p, TimeFn& tf) {
 // ================================================================ C ABI
 extern "C" {
 
+// Frame groups per frame workgroup of a one-launch sweep unless set: measured
+// at 513^2 and 1025^2 with the default tiles, 2 (FP64) and 4 (FP32) beat 1 by
+// 8-20 %.
+static int default_frame_loop(int dtype) { return dtype == SBPE_F32 ? 4 : 2; }
+
 sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double beta, sbpe_ctx_t* out) {
     if (!out) return fail(nullptr, SBPE_EINVAL, "out is NULL");
     if (dtype != SBPE_F64 && dtype != SBPE_F32) return fail(nullptr, SBPE_EINVAL, "dtype must be SBPE_F64 or SBPE_F32");
@@ -852,6 +857,7 @@ sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double b
     c->stream = static_cast<hipStream_t>(stream);
     c->dtype = dtype;
     c->order = order;
+    c->frame_loop = default_frame_loop(dtype);
     c->beta = beta;
     c->host_only = device < 0;
     if (!c->host_only) {
@@ -2094,7 +2100,7 @@ extern "C" sbpe_status sbpe_batch_advance(sbpe_batch_t b, int nsteps) {
         p1.nblocks = (int)b->desc.size();
         p1.pass = PASS_RK1;
         p1.wide = b->op == SBPE_OP_WIDE ? 1 : 0;
-        p1.floop = 1;
+        p1.floop = default_frame_loop(b->dtype);
         p1.step = b->step + k;
         p1.rec_base = 0;
         p1.wa[0] = 1.0;

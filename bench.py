@@ -235,7 +235,16 @@ def cpu_baseline(n, steps):
     if r.returncode != 0:
         log(r.stderr[-2000:])
         return None
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    # the host it ran on
+    try:
+        with open('/proc/cpuinfo') as f:
+            models = [ln.split(':', 1)[1].strip() for ln in f if ln.startswith('model name')]
+        out['cpu_model'] = models[0] if models else None
+    except OSError:
+        out['cpu_model'] = None
+    out['host_cpus'] = os.cpu_count()
+    return out
 
 
 def cpu_baseline_child(n, steps):

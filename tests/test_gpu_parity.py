@@ -311,3 +311,47 @@ def test_tile_rows_do_not_change_results():
             sol.close()
     for u, v, r, _ in out[1:]:
         assert np.array_equal(u, out[0][0]) and np.array_equal(v, out[0][1]) and np.array_equal(r, out[0][2])
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_full_size_c3_self_adjoint(dtype):
+    """The 2x2 x 2049^2 workload at its full size, through the launch path the
+    benchmark times there (tiles and frame on two streams, interfaces through
+    the frame operator's partner columns), checked by properties that hold at
+    any size: H rho~ L is symmetric (w . H L u = u . H L w, the self-adjointness
+    of Sec. 5-6) and negative semidefinite (u . H L u <= 0)."""
+    from oracle import sbp
+    n = 2049
+    say('full size C3 self-adjointness', dtype)
+    spec = W.spec_c3(n=n)
+    sol = solver(spec, dtype)
+    try:
+        assert not S.sbpe_plan_info(sol.ctx)['fused_sweep']
+        x1, x2 = W.reference_grid(n, n)
+        rng = np.random.default_rng(3)
+
+        def field():
+            out = []
+            for _ in spec['blocks']:
+                a, b, c, d = rng.uniform(1, 6, 4)
+                f = np.stack([np.sin(a * x1 + b * x2 + c), np.cos(d * x1 - a * x2)])
+                out.append(rounded(f + 1e-2 * rng.normal(size=f.shape), dtype))
+            return out
+        us, ws = field(), field()
+        lu = [x.double().cpu().numpy() for x in sol.apply(us, homogeneous=True)]
+        lw = [x.double().cpu().numpy() for x in sol.apply(ws, homogeneous=True)]
+        s_wu = s_uw = s_uu = scale = 0.0
+        for k, blk in enumerate(spec['blocks']):
+            _, J, _ = S.sbpe_get_block_fields(sol.ctx, k)
+            h = 1.0 / (n - 1)
+            Hr = np.outer(sbp.norm(n, h, 4), sbp.norm(n, h, 4)) * J * blk['rho']   # H rho~
+            s_wu += float(np.sum(Hr * (ws[k] * lu[k]).sum(0)))
+            s_uw += float(np.sum(Hr * (us[k] * lw[k]).sum(0)))
+            s_uu += float(np.sum(Hr * (us[k] * lu[k]).sum(0)))
+            scale += float(np.sum(Hr * np.abs(ws[k] * lu[k]).sum(0)))
+        asym = abs(s_wu - s_uw) / scale
+        say('  w.HLu %.6e  u.HLw %.6e  relative asymmetry %.2e  u.HLu %.4e' % (s_wu, s_uw, asym, s_uu))
+        assert asym < {'f64': 1e-12, 'f32': 1e-5}[dtype]
+        assert s_uu < 0
+    finally:
+        sol.close()

@@ -274,3 +274,24 @@ def test_wide_gradient_matches_oracle_adjoint():
     er, ec, eJ = rel(g_rho, go_rho), rel(g_c10, go_c10), abs(J - Jo) / Jo
     say('  J %.6e (oracle %.6e)  rel err J %.2e  rho %.2e  C10 %.2e' % (J, Jo, eJ, er, ec))
     assert eJ < 1e-9 and er < 1e-8 and ec < 1e-8
+
+
+@pytest.mark.parametrize("order,n1,n2", [(4, 13, 13), (4, 14, 25), (2, 6, 6), (2, 7, 9)])
+def test_wide_apply_smallest_blocks(order, n1, n2):
+    """The smallest blocks of each order (one interior column or row, or none
+    with 8 rows at second order): the wide frame rows reach across most of
+    the block and the probing windows of both ends overlap."""
+    say('wide apply smallest block', order, n1, n2)
+    spec = mixed_spec(n1, n2, order)
+    spec['sources'] = []
+    P = build(spec)
+    sol = solver(spec, 'f64')
+    try:
+        rng = np.random.default_rng(12)
+        u = rng.normal(size=(2, n2, n1))
+        got = sol.apply([u], t=0.21)[0].cpu().numpy()
+        err = rel(got, P.rhs([u], 0.21)[0])
+        say('  rel L2', err)
+        assert err < 1e-11
+    finally:
+        sol.close()

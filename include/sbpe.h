@@ -243,7 +243,8 @@ sbpe_status sbpe_plan_info(sbpe_ctx_t ctx, long long* info);
  * to rho and C.  H L is symmetric (the energy analysis of Sec. 5 and 6), so
  * with the adjoint variables scaled as zhat = z / (H rho~) the adjoint state
  * is advanced with the forward operator itself (sbpe_apply, homogeneous).
- * Blocks with interface faces are not supported (SBPE_EINVAL). */
+ * Either operator (sbpe_set_operator) is supported; blocks with interface
+ * faces and contexts with dissipative faces are not (SBPE_EINVAL). */
 
 /* For every block b, accumulate the gradient of one RK4 stage:
  *   gc[b]  += alpha * d/dc (z^T H L(c) y)   (10 stored transformed-stiffness
@@ -284,7 +285,7 @@ sbpe_status sbpe_receiver_adjoint(sbpe_ctx_t ctx, const void* r, void* const* u,
  * that of sbpe_advance, so a member's result does not depend on which other
  * members share the launch.  Members join and leave between calls to
  * sbpe_batch_advance; the caller decides admission (for example by an HBM
- * budget).  All members must use the batch's device, dtype and order.  A
+ * budget).  All members must use the batch's device, dtype, order and operator.  A
  * batch is driven from one host thread.
  *
  * Errors: SBPE_EINVAL for bad arguments, SBPE_ESTATE when a context is not

@@ -817,6 +817,7 @@ static sbpe_status fill_tau(sbpe_ctx* c, int nsteps, double t0, double dt) {
         HIPCHECK(c, hipStreamSynchronize(c->stream));
         (void)hipFree(c->d_tau);
         c->d_tau = nullptr;
+        c->tau_cap = 0;     // a failed allocation leaves no table behind
         if (hipMalloc(&c->d_tau, (size_t)nsteps * c->nitems * 3 * sizeof(double)) != hipSuccess)
             return fail(c, SBPE_ENOMEM, "time-function table");
         c->tau_cap = nsteps;
@@ -2054,6 +2055,7 @@ static sbpe_status batch_rebuild(sbpe_batch* b) {
         (void)hipFree(b->d_desc);
         b->d_desc = nullptr;
         const size_t cap = std::max(b->desc.size(), 2 * b->desc_cap);
+        b->desc_cap = 0;    // a failed allocation leaves no table behind
         if (hipMalloc(&b->d_desc, cap * sizeof(BlockDesc)) != hipSuccess) return bfail(b, SBPE_ENOMEM, "descriptor table");
         b->desc_cap = cap;
     }

@@ -339,11 +339,15 @@ def main():
                              traffic_key='%s/f64/o4' % k, tile_rows=tuned64[0][0], n=args.n),
         "kernels_ms": {kk: v[0] for kk, v in r64['kernels'].items() if v[1]},
         "ms_per_step_with_events": r64['ms_per_step_with_events'],
-        "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8),
+        "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8,
+                                   traffic_key='interior_apply/f64/o4', tile_rows=tuned64[0][0], n=args.n),
         "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'],
                 "tile_rows": tuned32[0][0], "frame_loop": tuned32[0][1],
-                "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4),
-                "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4)},
+                "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4,
+                                     traffic_key='%s/f32/o4' % dominant(r32), tile_rows=tuned32[0][0], n=args.n),
+                "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4,
+                                           traffic_key='interior_apply/f32/o4', tile_rows=tuned32[0][0],
+                                           n=args.n)},
     }
     # (left out of profiler calibration runs, whose copy probe must stay the largest copy)
     cbw = None if args.copy_probe_mib else copy_bandwidth()

@@ -11,6 +11,9 @@ What the paper fixes (and what a plausible mistake would break):
 * Sec. 3.3.1: transformed isotropic stiffness in closed form.
 * Sec. 3.3: affine maps give exact metric terms; Nanson's formula.
 * eq. n-C_conversion: Jhat T_jl = nu_i c_ijkl D_k (the reference-frame traction).
+* eq. borrowing_phys (Sec. 4.5): the volume quadrature bounds h_1/d times the
+  face quadrature, sharply at corners; this fixes the weights of the
+  displacement and interface penalties.
 """
 import numpy as np
 import pytest
@@ -201,3 +204,41 @@ def test_reference_frame_traction_identity(order):
                         Du.reshape(2, 2, -1)[..., idx]) * nu
         got = fo['Jhat'] * B.traction(f, u)
         assert np.allclose(got, ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_positivity_property_fixes_the_penalty_weights(order):
+    """eq. borrowing_phys (Sec. 4.5): for any nonnegative energy density
+    q = s_IJ C_IJKL s_KL, the volume quadrature of J q bounds (1/d) times the
+    sum over faces of h_1 (the first norm weight along the face normal) times
+    the face quadrature of J q.  The bound is attained at a single corner
+    point, where faces of both axes meet, and is off by exactly d = 2 inside
+    one face: together these pin d, each axis' h_1 (n1 != n2) and the face
+    quadrature that the displacement and interface penalties are built from."""
+    B = _block(order, 23, 31, seed=7)
+    C = B.C.reshape(2, 2, 2, 2, -1)
+
+    def density(s):
+        return np.einsum('IJp,IJKLp,KLp->p', s, C, s)
+
+    def vol(q):
+        return np.sum((B.J * B.H).ravel() * q)
+
+    def bound(q):
+        return sum(fo['h_1'] * np.sum(fo['Hf'] * fo['Jf'] * q[fo['idx']]) for fo in B._face_ops) / E.DIM
+
+    rng = np.random.default_rng(1)
+    s = rng.normal(size=(2, 2, B.npts))
+    q = density(s)
+    assert q.min() > -1e-12 * q.max()
+    assert vol(q) > bound(q) > 0
+    n1 = B.n1
+    for p, ratio in ((0, 1.0), (n1 - 1, 1.0), (B.npts - 1, 1.0), (7 * n1, 2.0), (n1 - 1 + 11 * n1, 2.0),
+                     (9, 2.0), (B.npts - 5, 2.0)):
+        m = np.zeros(B.npts)
+        m[p] = 1.0
+        q = density(s * m)
+        assert vol(q) == pytest.approx(ratio * bound(q), rel=1e-13), p
+    m = np.zeros(B.npts)
+    m[5 * n1 + 6] = 1.0
+    assert bound(density(s * m)) == 0.0 and vol(density(s * m)) > 0

@@ -288,6 +288,38 @@ def spec_c1(n=65, order=4):
                 mms=mm, T=0.5, cfl=0.5)
 
 
+def spec_mms(n=65, order=4, kinds=(TRACTION, DISPLACEMENT, TRACTION, DISPLACEMENT), mapping=None,
+             data_sign=1.0, drop_displacement_data=False):
+    """The C1 manufactured solution on a block with a chosen boundary kind per
+    face: traction faces carry the exact traction n_I C_IJKL d_K u_L, and
+    displacement faces the exact boundary displacement g = u (Sec. 5.2,
+    eq. dirichlet_ansatz), both times cos(omega t).  mapping (default the
+    identity) may curve the block; the material stays constant in physical
+    space.  data_sign multiplies the displacement data and
+    drop_displacement_data leaves it out: both give a problem whose discrete
+    solution does not converge to the manufactured one."""
+    m = Identity() if mapping is None else mapping
+    X1, X2 = grid(m, n, n)
+    C10c = voigt_to_c10(np.array(VOIGT_C1))
+    mm = mms_c1(X1, X2, C10c)
+    C10 = C10c[:, None, None] * np.ones((1, n, n))
+    bc = []
+    for f, kind in enumerate(kinds):
+        idx = face_flat_index(f, n, n)
+        if kind == DISPLACEMENT:
+            if drop_displacement_data:
+                bc.append((DISPLACEMENT, None, T_ZERO, None, None))
+                continue
+            g = data_sign * mm['u'].reshape(2, -1)[:, idx]
+        else:
+            g = traction_data(mm, idx, outward_normal(m, f, n, n))
+        bc.append((kind, np.ascontiguousarray(g), T_COS, (mm['omega'], 0.0), None))
+    blk = dict(X1=X1, X2=X2, rho=np.ones((n, n)), C10=C10, bc=bc,
+               forcing=(mm['f'], T_COS, (mm['omega'], 0.0)))
+    return dict(order=order, blocks=[blk], interfaces=[], sources=[], receivers=[],
+                mms=mm, T=0.5, cfl=0.5)
+
+
 def spec_fault(n=33, order=4, jump_data=True):
     """Two Cartesian blocks [0, 1/2] x [0, 1] and [1/2, 1] x [0, 1] of n^2
     points each, joined along x1 = 1/2, with different constant materials and a

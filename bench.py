@@ -1,24 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the RK4-advanced SBP-SAT anisotropic elastic solver on one MI355X.
 
-Workload (the single-GPU configuration the headline metric is quoted on): one
-curvilinear block of 1025 x 1025 points with Gaussian topography, smooth random
-SPD stiffness and density (8 Fourier modes per field, seed 0), displacement SAT
-on the bottom face and traction SATs elsewhere, a 10 Hz Ricker point force and
-16 surface receivers; classical RK4 at CFL 0.5.  A step is one full RK4 step
-(four right-hand-side evaluations fused into two sweeps over the grid,
-sources, receivers).  Inputs are resident in HBM before timing starts.  The
-launch shape (tile height, frame groups per frame workgroup) is picked by
-timing candidates first; it does not change the results.  The
-throughput comes from the timed steps alone; the launch durations of the
-roofline come from the same number of steps run again with HIP events around
-every launch (the events lengthen a 1025^2 step by 12-19 %).
+Workload of the headline line (the largest configuration that fits one GPU,
+at the paper's precision): 2 x 2 conforming curvilinear blocks of 2049 x 2049
+points (16.8 M points) of one smooth global map, smooth random SPD stiffness
+and density with a contrast of 3 between neighbouring blocks, interface SATs
+between the blocks, traction on the top and left outer faces, displacement on
+the bottom and right ones, a 10 Hz Ricker point force and 16 surface
+receivers; 4th-order operators, classical RK4 at CFL 0.5, FP64.  A step is
+one full RK4 step (four right-hand-side evaluations fused into two sweeps
+over the grid, sources, receivers).  Inputs are resident in HBM and every
+per-call table is sized before timing starts.  The launch shape (tile height,
+frame groups per frame workgroup) is picked by timing candidates first; it
+does not change the results.  The headline's timed steps run with HIP events
+around every launch on the launch's own stream, which give the launch
+durations of the roofline (at 1.7 ms per step they cost well under 1 %).
 
-Prints one JSON line on stdout; progress goes to stderr.  The primary result is
-FP64; the FP32 variant, the plain operator apply, the same workload with the
-wide-stencil operator, working sets larger than the MALL (one 2049^2 block in
-FP64, 2x2 blocks of 2049^2 in FP32) and a served stream of shots (continuous batching against
-sequential plain solves, p50/p99 latency) are reported beside it.
+Prints one JSON line on stdout; progress goes to stderr.  Beside the headline:
+the 1025^2 single-block workload in FP64 and FP32 with the plain operator
+apply, the headline workload in FP32, the 1025^2 workload with the
+wide-stencil operator, a served stream of shots (continuous batching against
+sequential plain solves, p50/p99 latency), the misfit gradient, and the
+oracle timed on the host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -39,6 +42,11 @@ PEAK_HBM_GBS = 8000.0
 #   second sweep: a1, a2 in (4) + 11 coefficients + u, v in (4) + u, v out (4)
 #   apply       : u in (2) + 11 coefficients + a out (2)
 WORDS = {'interior_rk1': 19, 'interior_rk2': 23, 'interior_apply': 15}
+# the same launches counted in the unit of one right-hand-side apply (2 words
+# in, 11 coefficient words, 2 words out = 15 words per point): each RK sweep
+# applies the operator to two fields
+APPLY_WORDS = 15
+APPLIES = {'interior_rk1': 2, 'interior_rk2': 2, 'interior_apply': 1}
 
 
 def log(*a):
@@ -46,22 +54,32 @@ def log(*a):
 
 
 # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-# of the 1025^2 workload; ignored once the kernel source has changed
-TRAFFIC_PROFILES = {n: os.path.join(ROOT, 'profiles', 'hbm_traffic_c2_%d.md' % n) for n in (1025, 2049)}
+# per workload; ignored once the kernel source or the tile height differs
+TRAFFIC_PROFILES = {'c2_1025': os.path.join(ROOT, 'profiles', 'hbm_traffic_c2_1025.md'),
+                    'c2_2049': os.path.join(ROOT, 'profiles', 'hbm_traffic_c2_2049.md'),
+                    'c3_2049': os.path.join(ROOT, 'profiles', 'hbm_traffic_c3_2049.md')}
 
 
-def roofline(kind, ms, points, wbytes, traffic_key=None, tile_rows=None, n=1025):
-    byts = WORDS[kind] * wbytes * points
+def roofline(kind, ms, points, wbytes, traffic_key=None, tile_rows=None, profile=None):
+    """HBM roofline of one launch kind.  `achieved` counts the launch's work
+    in right-hand-side applies of 15 words per point; `achieved_own_bytes`
+    counts the words the fused launch itself must move (fewer: a sweep shares
+    the coefficient reads of its two applies)."""
+    byts = APPLIES[kind] * APPLY_WORDS * wbytes * points
+    own = WORDS[kind] * wbytes * points
     gbs = byts / (ms * 1e-3) / 1e9
+    gbs_own = own / (ms * 1e-3) / 1e9
     traffic = None
-    if traffic_key is not None:
+    if traffic_key is not None and profile is not None:
         from paper_2003_12811_amd import profiling
-        path = TRAFFIC_PROFILES.get(n)
-        t = profiling.read_traffic(path, tile_rows=tile_rows or 10) if path else None
+        t = profiling.read_traffic(TRAFFIC_PROFILES[profile], tile_rows=tile_rows or 10)
         traffic = t.get(traffic_key) if t else None
     return {"bound": "hbm", "kernel": kind, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "avg_ms": round(ms, 5), "bytes_per_launch": byts}
+            "avg_ms": round(ms, 5), "bytes_per_launch": byts,
+            "achieved_own_bytes": round(gbs_own, 1), "frac_own_bytes": round(gbs_own / PEAK_HBM_GBS, 4),
+            "own_bytes_per_launch": own,
+            "traffic_over_own_bytes": round(traffic / own, 4) if traffic else None}
 
 
 TILE_CANDIDATES = (10, 14, 16, 18, 20, 24)
@@ -80,6 +98,7 @@ def tune_launch(spec, dtype, tiles=TILE_CANDIDATES, loops=FRAME_LOOP_CANDIDATES,
         sol = Solver(spec, dtype, tile_rows=rows)
         dt = sol.dt_cfl(spec.get('cfl', 0.5))
         sol.set_state(None, None, 0.0)
+        sol.reserve(len(loops) * (10 + steps))
         for fl in loops:
             sol.set_frame_loop(fl)
             sol.advance(10, dt)
@@ -100,7 +119,11 @@ def tune_launch(spec, dtype, tiles=TILE_CANDIDATES, loops=FRAME_LOOP_CANDIDATES,
     return best, table
 
 
-def run_gpu(spec, dtype, steps, warmup, apply_reps=0, shape=(0, 0)):
+def run_gpu(spec, dtype, steps, warmup, apply_reps=0, shape=(0, 0), events_in_timed=False):
+    """Advance the workload: warmup steps, then `steps` timed steps.  With
+    events_in_timed the timed steps carry HIP events around every launch and
+    give the launch durations too; otherwise the same number of steps is run
+    again with events (at 1025^2 the events lengthen a step by 12-19 %)."""
     import torch
     from paper_2003_12811_amd import sbpe as S
     from paper_2003_12811_amd.solver import Solver
@@ -109,32 +132,38 @@ def run_gpu(spec, dtype, steps, warmup, apply_reps=0, shape=(0, 0)):
         sol.set_frame_loop(shape[1])
     dt = sol.dt_cfl(spec.get('cfl', 0.5))
     sol.set_state(None, None, 0.0)
+    # every table the advance calls use is sized here, outside the timed region
+    sol.reserve(warmup + 2 * steps)
     plan = S.sbpe_plan_info(sol.ctx)
     npts = sum(b['X1'].size for b in spec['blocks'])
     sol.advance(warmup, dt)
     sol.synchronize()
     torch.cuda.synchronize()
-    # the timed steps, without per-launch events (they cost 12-19 % of a
-    # 1025^2 step), give the throughput ...
+    if events_in_timed:
+        S.sbpe_set_kernel_timing(sol.ctx, 1)
+        S.sbpe_get_kernel_timing(sol.ctx)
     t0 = time.perf_counter()
     sol.advance(steps, dt)
     sol.synchronize()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    # ... then the same number of steps again with HIP events around every
-    # launch, on the launch's own stream, give the launch durations
-    S.sbpe_set_kernel_timing(sol.ctx, 1)
-    S.sbpe_get_kernel_timing(sol.ctx)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    sol.advance(steps, dt)
-    sol.synchronize()
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    kt = S.sbpe_get_kernel_timing(sol.ctx)
+    if events_in_timed:
+        kt = S.sbpe_get_kernel_timing(sol.ctx)
+        ev_ms = 1e3 * wall / steps
+    else:
+        S.sbpe_set_kernel_timing(sol.ctx, 1)
+        S.sbpe_get_kernel_timing(sol.ctx)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sol.advance(steps, dt)
+        sol.synchronize()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        kt = S.sbpe_get_kernel_timing(sol.ctx)
+        ev_ms = 1e3 * (t3 - t2) / steps
     res = dict(dtype=dtype, points=npts, steps=steps, wall_s=wall, ms_per_step=1e3 * wall / steps,
-               ms_per_step_with_events=1e3 * (t3 - t2) / steps,
+               ms_per_step_with_events=ev_ms,
                updates_per_s=npts * steps / wall, dt=dt, kernels=kt, plan=plan)
     if apply_reps:
         u = [torch.zeros((2,) + b['X1'].shape, dtype=sol.tdtype, device=sol.device) for b in spec['blocks']]
@@ -226,11 +255,11 @@ def dominant(res):
     return kind
 
 
-def cpu_baseline(n, steps):
+def cpu_baseline(n, steps, dt):
     """Oracle RK4 steps on the host (single thread), in a child process."""
     env = dict(os.environ, OMP_NUM_THREADS='1', OPENBLAS_NUM_THREADS='1', MKL_NUM_THREADS='1')
-    cmd = [sys.executable, os.path.abspath(__file__), '--cpu-baseline-child', '--n', str(n),
-           '--cpu-steps', str(steps)]
+    cmd = [sys.executable, os.path.abspath(__file__), '--cpu-baseline-child', '--cpu-n', str(n),
+           '--cpu-steps', str(steps), '--cpu-dt', repr(dt)]
     r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
     if r.returncode != 0:
         log(r.stderr[-2000:])
@@ -247,15 +276,18 @@ def cpu_baseline(n, steps):
     return out
 
 
-def cpu_baseline_child(n, steps):
+def cpu_baseline_child(n, steps, dt):
+    """The oracle on the headline recipe with blocks of n^2 points (the full
+    2049^2 blocks take about a minute per RK4 step in the oracle): points x
+    steps / wall time of `steps` literal RK4 steps after one warm-up step.  The
+    time step (the headline run's) does not change the cost of a step."""
     import numpy as np
     from paper_2003_12811_amd import workloads as W
     from oracle import spec as OS, timestep as T
-    spec = W.spec_c2(n=n)
+    spec = W.spec_c3(n=n)
     P = OS.build(spec)
-    dt = T.dt_cfl(P, 0.5)
-    u = [np.zeros((2, n, n))]
-    v = [np.zeros((2, n, n))]
+    u = [np.zeros((2, n, n)) for _ in spec['blocks']]
+    v = [np.zeros((2, n, n)) for _ in spec['blocks']]
     t = 0.0
     u, v = T.rk4_step(P, u, v, t, dt)       # warm-up step
     t += dt
@@ -264,9 +296,21 @@ def cpu_baseline_child(n, steps):
         u, v = T.rk4_step(P, u, v, t, dt)
         t += dt
     wall = time.perf_counter() - t0
-    print(json.dumps({"value": n * n * steps / wall, "unit": "grid-point updates/s", "cores": 1,
-                      "kind": "oracle", "sample": "%d RK4 steps of the %dx%d workload (FP64, NumPy/SciPy, "
-                      "one thread), %.1f s" % (steps, n, n, wall)}))
+    npts = len(spec['blocks']) * n * n
+    print(json.dumps({"value": npts * steps / wall, "unit": "grid-point updates/s", "cores": 1,
+                      "kind": "oracle", "sample": "%d RK4 steps of the headline recipe at reduced block size "
+                      "(2x2 blocks of %dx%d, %d points; FP64, NumPy/SciPy, one thread), %.1f s; the oracle's "
+                      "cost per point and step does not depend on the block size" % (steps, n, n, npts, wall)}))
+
+
+def section(spec, dtype, args, tiles, loops, tune_steps, apply_reps, events_in_timed, fixed, steps=None):
+    """Tune the launch shape (unless fixed on the command line) and run one workload."""
+    shape, table = fixed if args.tile_rows else tune_launch(spec, dtype, tiles=tiles, loops=loops,
+                                                            steps=tune_steps)
+    r = run_gpu(spec, dtype, steps or args.steps, args.warmup, apply_reps=apply_reps, shape=shape,
+                events_in_timed=events_in_timed)
+    log('  %.4f ms/step, %.3e updates/s' % (r['ms_per_step'], r['updates_per_s']))
+    return r, shape, table
 
 
 def main():
@@ -274,17 +318,20 @@ def main():
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=400)
     ap.add_argument('--warmup', type=int, default=40)
-    ap.add_argument('--n', type=int, default=1025)
+    ap.add_argument('--n', type=int, default=2049, help='block size of the 2x2-block headline workload')
+    ap.add_argument('--c2-n', type=int, default=1025, help='size of the single-block workload')
+    ap.add_argument('--cpu-n', type=int, default=513, help='block size of the oracle sample')
     ap.add_argument('--cpu-steps', type=int, default=10)
+    ap.add_argument('--cpu-dt', type=float, default=1e-4)
+    ap.add_argument('--headline-only', action='store_true', help='only the headline workload')
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--no-large', action='store_true')
+    ap.add_argument('--no-c2', action='store_true')
+    ap.add_argument('--no-f32', action='store_true')
     ap.add_argument('--no-wide', action='store_true')
-    ap.add_argument('--no-hbm', action='store_true')
     ap.add_argument('--tile-rows', type=int, default=0,
-                    help='interior tile height of the 1025^2 runs (0: pick the launch shape by timing candidates)')
+                    help='interior tile height of every run (0: pick the launch shape by timing candidates)')
     ap.add_argument('--frame-loop', type=int, default=0,
                     help='frame groups per frame workgroup, used with --tile-rows (0: the library default)')
-    ap.add_argument('--large-n', type=int, default=2049)
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
     ap.add_argument('--no-gradient', action='store_true')
@@ -297,107 +344,92 @@ def main():
                          'the HBM byte counters of a profiler)')
     args = ap.parse_args()
     if args.cpu_baseline_child:
-        cpu_baseline_child(args.n, args.cpu_steps)
+        cpu_baseline_child(args.cpu_n, args.cpu_steps, args.cpu_dt)
         return
     world = int(os.environ.get('WORLD_SIZE', '1'))
     if args.gpus != 1 or world != 1:
         print('bench.py measures one GPU only: run it with --gpus 1 (sharding the blocks over '
               'several GPUs is not implemented)', file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_c2 = args.no_f32 = args.no_wide = True
+        args.no_serve = args.no_gradient = True
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
     from paper_2003_12811_amd import workloads as W
-    log('building workload %dx%d' % (args.n, args.n))
-    spec = W.spec_c2(n=args.n)
     fixed = ((args.tile_rows, args.frame_loop), {})
-    tuned64, tuned32 = fixed, fixed
-    if not args.tile_rows:
-        log('launch shape, fp64')
-        tuned64 = tune_launch(spec, 'f64')
-        log('launch shape, fp32')
-        tuned32 = tune_launch(spec, 'f32')
-    log('fp64 run')
-    r64 = run_gpu(spec, 'f64', args.steps, args.warmup, apply_reps=50, shape=tuned64[0])
-    log('  %.3f ms/step, %.3e updates/s' % (r64['ms_per_step'], r64['updates_per_s']))
-    log('fp32 run')
-    r32 = run_gpu(spec, 'f32', args.steps, args.warmup, apply_reps=50, shape=tuned32[0])
-    log('  %.3f ms/step, %.3e updates/s' % (r32['ms_per_step'], r32['updates_per_s']))
-    pts = swept_points(r64['plan'])
-    k = dominant(r64)
+    n = args.n
+    log('building the headline workload: 2x2 blocks of %dx%d' % (n, n))
+    t0 = time.time()
+    sp3 = W.spec_c3(n=n)
+    log('  built in %.1f s' % (time.time() - t0))
+    log('headline, fp64')
+    r3, sh3, tb3 = section(sp3, 'f64', args, (10, 20), (1,), 20, 0, True, fixed)
+    k3 = dominant(r3)
+    pts3 = swept_points(r3['plan'])
     line = {
-        "metric": "grid-point updates/s", "value": r64['updates_per_s'], "unit": "grid-point updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64['ms_per_step'],
+        "metric": "grid-point updates/s", "value": r3['updates_per_s'], "unit": "grid-point updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r3['ms_per_step'],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "single curvilinear block %dx%d, Gaussian topography, random smooth SPD C/rho "
-                               "(seed 0), displacement bottom + traction SATs, 10 Hz Ricker force, 16 receivers, "
-                               "4th-order SBP-SAT, RK4 CFL 0.5" % (args.n, args.n),
-                   "points": r64['points'], "dt": r64['dt'], "parallelism": "1 GPU",
-                   "tile_rows": tuned64[0][0], "frame_loop": tuned64[0][1],
-                   "launch_shape_ms_per_step": tuned64[1]},
-        "roofline": roofline(k, r64['kernels'][k][0], pts, 8,
-                             traffic_key='%s/f64/o4' % k, tile_rows=tuned64[0][0], n=args.n),
-        "kernels_ms": {kk: v[0] for kk, v in r64['kernels'].items() if v[1]},
-        "ms_per_step_with_events": r64['ms_per_step_with_events'],
-        "apply_roofline": roofline('interior_apply', r64['apply_kernels']['interior_apply'][0], pts, 8,
-                                   traffic_key='interior_apply/f64/o4', tile_rows=tuned64[0][0], n=args.n),
-        "f32": {"value": r32['updates_per_s'], "ms_per_step": r32['ms_per_step'],
-                "tile_rows": tuned32[0][0], "frame_loop": tuned32[0][1],
-                "roofline": roofline(dominant(r32), r32['kernels'][dominant(r32)][0], pts, 4,
-                                     traffic_key='%s/f32/o4' % dominant(r32), tile_rows=tuned32[0][0], n=args.n),
-                "apply_roofline": roofline('interior_apply', r32['apply_kernels']['interior_apply'][0], pts, 4,
-                                           traffic_key='interior_apply/f32/o4', tile_rows=tuned32[0][0],
-                                           n=args.n)},
+        "config": {"workload": "2x2 conforming curvilinear blocks of %dx%d (one smooth global map), random smooth "
+                               "SPD C/rho (seed 0) with contrast 3 between neighbouring blocks, interface SATs, "
+                               "traction top/left and displacement bottom/right, 10 Hz Ricker force, 16 surface "
+                               "receivers, 4th-order SBP-SAT, RK4 CFL 0.5" % (n, n),
+                   "points": r3['points'], "dt": r3['dt'], "parallelism": "1 GPU",
+                   "tile_rows": sh3[0], "frame_loop": sh3[1], "launch_shape_ms_per_step": tb3},
+        "roofline": roofline(k3, r3['kernels'][k3][0], pts3, 8, traffic_key='%s/f64/o4' % k3, tile_rows=sh3[0],
+                             profile='c3_2049'),
+        "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]},
     }
     # (left out of profiler calibration runs, whose copy probe must stay the largest copy)
     cbw = None if args.copy_probe_mib else copy_bandwidth()
     if cbw:
         log('copy bandwidth %.1f GB/s' % cbw)
-    if not args.no_wide:
-        log('wide-stencil operator, fp64')
-        spw = dict(spec)
-        spw['operator'] = 'wide'
-        tw = fixed if args.tile_rows else tune_launch(spw, 'f64', loops=(1, 2, 4, 8))
-        rw = run_gpu(spw, 'f64', args.steps, args.warmup, apply_reps=50, shape=tw[0])
-        kw = dominant(rw)
-        line["wide"] = {"workload": "the same %dx%d workload with the wide-stencil operator D_i c D_i, FP64"
-                                    % (args.n, args.n),
-                        "value": rw['updates_per_s'], "ms_per_step": rw['ms_per_step'],
-                        "tile_rows": tw[0][0], "frame_loop": tw[0][1],
-                        "roofline": roofline(kw, rw['kernels'][kw][0], swept_points(rw['plan']), 8),
-                        "apply_roofline": roofline('interior_apply', rw['apply_kernels']['interior_apply'][0],
-                                                   swept_points(rw['plan']), 8),
-                        "kernels_ms": {kk: v[0] for kk, v in rw['kernels'].items() if v[1]}}
-        log('  %.3f ms/step, %.3e updates/s' % (rw['ms_per_step'], rw['updates_per_s']))
-    if not args.no_hbm:
-        # the roofline case beyond the MALL in FP64: one 2049^2 block of the same recipe
-        # (about 0.8 GB per sweep; the 1025^2 working set fits the 256 MB MALL)
-        log('hbm-bound working set: %dx%d, fp64' % (args.large_n, args.large_n))
-        sph = W.spec_c2(n=args.large_n)
-        th = fixed if args.tile_rows else tune_launch(sph, 'f64', tiles=(10, 20), loops=(1, 2, 4), steps=20)
-        rh = run_gpu(sph, 'f64', max(args.steps // 4, 20), 10, shape=th[0])
-        kh = dominant(rh)
-        line["hbm_bound"] = {"workload": "the same recipe on one %dx%d block, FP64 (working set beyond the MALL)"
-                                         % (args.large_n, args.large_n),
-                             "value": rh['updates_per_s'], "ms_per_step": rh['ms_per_step'],
-                             "tile_rows": th[0][0], "frame_loop": th[0][1],
-                             "roofline": roofline(kh, rh['kernels'][kh][0], swept_points(rh['plan']), 8,
-                                                  traffic_key='%s/f64/o4' % kh, tile_rows=th[0][0], n=args.large_n),
-                             "kernels_ms": {kk: v[0] for kk, v in rh['kernels'].items() if v[1]}}
-        log('  %.3f ms/step, %.3e updates/s' % (rh['ms_per_step'], rh['updates_per_s']))
-    if not args.no_large:
-        log('large working set: 2x2 blocks of %d^2, fp32' % args.large_n)
-        t0 = time.time()
-        sp3 = W.spec_c3(n=args.large_n)
-        log('  workload built in %.1f s' % (time.time() - t0))
-        t3 = fixed if args.tile_rows else tune_launch(sp3, 'f32', tiles=(10, 20), loops=(1,), steps=20)
-        r3 = run_gpu(sp3, 'f32', max(args.steps // 4, 20), 10, shape=t3[0])
-        k3 = dominant(r3)
-        line["large"] = {"workload": "2x2 blocks of %d^2 with interfaces, FP32" % args.large_n,
-                         "value": r3['updates_per_s'], "ms_per_step": r3['ms_per_step'], "tile_rows": t3[0][0],
-                         "roofline": roofline(k3, r3['kernels'][k3][0], swept_points(r3['plan']), 4),
-                         "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]}}
-        log('  %.3f ms/step, %.3e updates/s' % (r3['ms_per_step'], r3['updates_per_s']))
+    if not args.no_f32:
+        log('headline workload, fp32')
+        r, sh, _ = section(sp3, 'f32', args, (10, 20), (1,), 20, 0, True, fixed)
+        k = dominant(r)
+        line["c3_f32"] = {"workload": "the headline workload in FP32", "value": r['updates_per_s'],
+                          "ms_per_step": r['ms_per_step'], "tile_rows": sh[0],
+                          "roofline": roofline(k, r['kernels'][k][0], swept_points(r['plan']), 4),
+                          "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
+    del sp3
+    if not args.no_c2:
+        log('building the single-block workload %dx%d' % (args.c2_n, args.c2_n))
+        spec = W.spec_c2(n=args.c2_n)
+        c2 = "single curvilinear block %dx%d, Gaussian topography, random smooth SPD C/rho (seed 0), " \
+             "displacement bottom + traction SATs, 10 Hz Ricker force, 16 receivers" % (args.c2_n, args.c2_n)
+        prof = 'c2_%d' % args.c2_n if 'c2_%d' % args.c2_n in TRAFFIC_PROFILES else None
+        dtypes = ('f64',) if args.no_f32 else ('f64', 'f32')
+        for dt_ in dtypes:
+            log('single block, %s' % dt_)
+            r, sh, tb = section(spec, dt_, args, TILE_CANDIDATES, FRAME_LOOP_CANDIDATES, 60, 50, False, fixed)
+            k = dominant(r)
+            pts = swept_points(r['plan'])
+            wb = 8 if dt_ == 'f64' else 4
+            line["c2_%s" % dt_] = {
+                "workload": c2 + ", %s" % dt_.upper(), "value": r['updates_per_s'], "ms_per_step": r['ms_per_step'],
+                "ms_per_step_with_events": r['ms_per_step_with_events'],
+                "tile_rows": sh[0], "frame_loop": sh[1], "launch_shape_ms_per_step": tb,
+                "roofline": roofline(k, r['kernels'][k][0], pts, wb, traffic_key='%s/%s/o4' % (k, dt_),
+                                     tile_rows=sh[0], profile=prof),
+                "apply_roofline": roofline('interior_apply', r['apply_kernels']['interior_apply'][0], pts, wb,
+                                           traffic_key='interior_apply/%s/o4' % dt_, tile_rows=sh[0], profile=prof),
+                "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
+        if not args.no_wide:
+            log('wide-stencil operator, fp64')
+            spw = dict(spec)
+            spw['operator'] = 'wide'
+            r, sh, _ = section(spw, 'f64', args, TILE_CANDIDATES, (1, 2, 4, 8), 60, 50, False, fixed)
+            k = dominant(r)
+            line["wide"] = {"workload": "the single-block workload with the wide-stencil operator D_i c D_i, FP64",
+                            "value": r['updates_per_s'], "ms_per_step": r['ms_per_step'],
+                            "tile_rows": sh[0], "frame_loop": sh[1],
+                            "roofline": roofline(k, r['kernels'][k][0], swept_points(r['plan']), 8),
+                            "apply_roofline": roofline('interior_apply', r['apply_kernels']['interior_apply'][0],
+                                                       swept_points(r['plan']), 8),
+                            "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
     if not args.no_serve:
         from paper_2003_12811_amd import serve
         log('served stream vs sequential plain solves')
@@ -407,14 +439,15 @@ def main():
         log('misfit gradient (513^2, 2000 steps, checkpoints every 100)')
         line["gradient"] = gradient_timing()
     if not args.no_cpu_baseline:
-        log('cpu baseline (oracle, 1 thread, %d steps)' % args.cpu_steps)
-        line["cpu_baseline"] = cpu_baseline(args.n, args.cpu_steps)
+        log('cpu baseline (oracle, 1 thread, %d steps of 2x2 blocks of %d^2)' % (args.cpu_steps, args.cpu_n))
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps, r3['dt'])
     # every roofline also against the measured copy bandwidth
-    for sec in (line, line["f32"], line.get("wide", {}), line.get("hbm_bound", {}), line.get("large", {})):
+    for sec in [line] + [line[k] for k in ("c3_f32", "c2_f64", "c2_f32", "wide") if k in line]:
         for key in ("roofline", "apply_roofline"):
             if key in sec and cbw:
                 sec[key]["copy_gbs"] = round(cbw, 1)
                 sec[key]["frac_of_copy"] = round(sec[key]["achieved"] / cbw, 4)
+                sec[key]["frac_of_copy_own_bytes"] = round(sec[key]["achieved_own_bytes"] / cbw, 4)
     print(json.dumps(line), flush=True)
 
 

@@ -72,7 +72,10 @@ enum { SBPE_TIME_ZERO = 0, SBPE_TIME_ONE = 1, SBPE_TIME_COS = 2, SBPE_TIME_RICKE
  * every call that needs a GPU returns SBPE_ESTATE. */
 sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double beta, sbpe_ctx_t* out);
 
-/* Free all device memory owned by the context (after synchronising its stream). */
+/* Free all device memory owned by the context (after synchronising its
+ * stream).  A context that is a member of a batch is refused with
+ * SBPE_ESTATE and left intact: remove it with sbpe_batch_remove first (the
+ * batch's descriptors point at its fields and its sweeps may still run). */
 sbpe_status sbpe_destroy(sbpe_ctx_t ctx);
 
 /* Message of the last failed call on this context (never NULL; static storage
@@ -199,6 +202,14 @@ sbpe_status sbpe_bind_state(sbpe_ctx_t ctx, void* const* u, void* const* v, doub
 
 /* Advance the bound state by nsteps classical RK4 steps of size dt (Sec. 7.1). */
 sbpe_status sbpe_advance(sbpe_ctx_t ctx, int nsteps, double dt);
+
+/* Size the per-call tables of sbpe_advance ahead of time: the time-function
+ * table for calls of up to nsteps steps and the receiver record for nsteps
+ * more steps after those already recorded.  An sbpe_advance call that fits
+ * then allocates nothing and does not synchronise the stream (only what does
+ * not fit is grown, with an allocation and a stream synchronisation).
+ * SBPE_EINVAL for nsteps < 0, SBPE_ENOMEM if the device memory is not there. */
+sbpe_status sbpe_reserve_steps(sbpe_ctx_t ctx, int nsteps);
 
 /* Current time of the bound state. */
 sbpe_status sbpe_get_time(sbpe_ctx_t ctx, double* t);

@@ -195,6 +195,7 @@ struct sbpe_ctx {
     void* batch = nullptr;
     // kernel timing: pending (kind, start, stop) event records and sums
     bool frame_sp = false;          // frame rows run from the assembled operator
+    double frame_check = -1.0;      // relative difference of the assembled operator to the frame kernel
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -698,15 +699,15 @@ static PassArgs base_args(const sbpe_ctx* c) {
 
 // Per-context sweep data in the block descriptors (time step, time-function
 // table, receiver buffer).  Uploaded only when something changed.
-static sbpe_status refresh_desc(sbpe_ctx* c, double dt) {
+static sbpe_status refresh_desc(sbpe_ctx* c, double dt, const double* tau) {
     bool changed = false;
     const long nrec = (long)c->receivers.size();
     for (size_t b = 0; b < c->desc.size(); ++b) {
         BlockDesc& D = c->desc[b];
         double* rec = nrec > 0 ? c->d_rec : nullptr;
-        if (D.dt != dt || D.tau != c->d_tau || D.rec != rec) changed = true;
+        if (D.dt != dt || D.tau != tau || D.rec != rec) changed = true;
         D.dt = dt;
-        D.tau = c->d_tau;
+        D.tau = tau;
         D.rec = rec;
     }
     if (!changed) return SBPE_OK;
@@ -812,18 +813,47 @@ static sbpe_status finish_passes(sbpe_ctx* c) {
 static bool check_ctx(sbpe_ctx* c) { return c != nullptr; }
 
 // tabulate the time functions of nsteps steps starting at t0 into d_tau
+static sbpe_status grow_tau(sbpe_ctx* c, long steps);
 static sbpe_status fill_tau(sbpe_ctx* c, int nsteps, double t0, double dt) {
-    if (nsteps > c->tau_cap) {
-        HIPCHECK(c, hipStreamSynchronize(c->stream));
-        (void)hipFree(c->d_tau);
-        c->d_tau = nullptr;
-        c->tau_cap = 0;     // a failed allocation leaves no table behind
-        if (hipMalloc(&c->d_tau, (size_t)nsteps * c->nitems * 3 * sizeof(double)) != hipSuccess)
-            return fail(c, SBPE_ENOMEM, "time-function table");
-        c->tau_cap = nsteps;
-    }
+    const sbpe_status s = grow_tau(c, nsteps);
+    if (s) return s;
     const int e = launch_tau(c->d_items, c->nitems, nsteps, t0, dt, c->d_tau, c->stream);
     if (e != 0) return fail(c, SBPE_EHIP, std::string("tau launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+// receiver record capacity of at least `steps` steps; the recorded rows are
+// kept (a reallocation synchronises the stream)
+static sbpe_status grow_receivers(sbpe_ctx* c, long steps) {
+    const long nrec = (long)c->receivers.size();
+    const long slots = nrec * 16 * 2;
+    if (nrec == 0 || steps <= c->rec_cap) return SBPE_OK;
+    const long cap = std::max<long>(steps, 2 * c->rec_cap);
+    double* nd = nullptr;
+    if (hipMalloc(&nd, cap * slots * sizeof(double)) != hipSuccess) return fail(c, SBPE_ENOMEM, "receiver buffer");
+    if (c->d_rec && c->rec_steps > 0 &&
+        hipMemcpyAsync(nd, c->d_rec, c->rec_steps * slots * sizeof(double), hipMemcpyDeviceToDevice, c->stream) !=
+            hipSuccess) {
+        (void)hipFree(nd);
+        return fail(c, SBPE_EHIP, "receiver buffer copy");
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->d_rec);
+    c->d_rec = nd;
+    c->rec_cap = cap;
+    return SBPE_OK;
+}
+
+// time-function table capacity of at least `steps` steps (contents not kept)
+static sbpe_status grow_tau(sbpe_ctx* c, long steps) {
+    if (steps <= c->tau_cap) return SBPE_OK;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->d_tau);
+    c->d_tau = nullptr;
+    c->tau_cap = 0;     // a failed allocation leaves no table behind
+    if (hipMalloc(&c->d_tau, (size_t)steps * c->nitems * 3 * sizeof(double)) != hipSuccess)
+        return fail(c, SBPE_ENOMEM, "time-function table");
+    c->tau_cap = steps;
     return SBPE_OK;
 }
 
@@ -884,6 +914,9 @@ sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double b
 
 sbpe_status sbpe_destroy(sbpe_ctx_t c) {
     if (!c) return SBPE_OK;
+    // a batch member's fields and tables are referenced by the batch's
+    // descriptors and may be in use by its enqueued sweeps
+    if (c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch: sbpe_batch_remove it first");
     if (!c->host_only) {
         (void)hipStreamSynchronize(c->stream);
         for (auto& B : c->blocks) {
@@ -1197,24 +1230,27 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
     };
     // Probes: for every block bp, component and colour (cx, cy), unit vectors
     // of that colour in block bp (zero elsewhere), the frame kernel, and the
-    // frame outputs of every block gathered into slice pi of one device
-    // buffer; then the two constant probes (row sums).  Everything is
-    // enqueued first and copied to the host once.
+    // frame outputs of every block gathered into G[b] and copied to slice pi
+    // of a pinned host buffer per block; then the two constant probes (row
+    // sums).  The stream is synchronised every PROBE_CHUNK probes, so at most
+    // that many probes (a few hundred small launches) are in flight, and the
+    // device holds only the probe, result and gather buffers of each block.
     const int NPC = nb * 2 * P * P;
     const int NPR = NPC + 2;
-    std::vector<void*> Ga(nb, nullptr);
-    std::vector<std::vector<char>> Ha(nb);
+    constexpr int PROBE_CHUNK = 32;
+    std::vector<void*> Ha(nb, nullptr);
+    std::vector<size_t> Hbytes(nb, 0);
     auto cleanup_all = [&]() {
-        for (int b = 0; b < nb; ++b) (void)hipFree(Ga[b]);
+        for (int b = 0; b < nb; ++b) (void)hipHostFree(Ha[b]);
         cleanup();
     };
     for (int b = 0; b < nb; ++b) {
-        const size_t bytes = (size_t)NPR * 2 * (size_t)std::max(c->desc[b].frame_n, 1) * es;
-        if (hipMalloc(&Ga[b], bytes) != hipSuccess) {
+        Hbytes[b] = (size_t)NPR * 2 * (size_t)std::max(c->desc[b].frame_n, 1) * es;
+        if (hipHostMalloc(&Ha[b], Hbytes[b], hipHostMallocDefault) != hipSuccess) {
+            Ha[b] = nullptr;
             cleanup_all();
-            return fail(c, SBPE_ENOMEM, "frame operator assembly buffers");
+            return fail(c, SBPE_ENOMEM, "frame operator assembly: pinned host buffers");
         }
-        Ha[b].resize(bytes);
     }
     auto probe = [&](int pi, int bp, int comp, int cx, int cy, int period) -> sbpe_status {
         for (int b = 0; b < nb; ++b) {
@@ -1228,10 +1264,16 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
         for (int b = 0; b < nb; ++b) {
             const HostBlock& H = c->blocks[b];
             const int fn = c->desc[b].frame_n;
-            char* dst = static_cast<char*>(Ga[b]) + (size_t)pi * 2 * (size_t)fn * es;
-            e = launch_frame_gather(c->dtype, Y[b], H.n1, H.n2, R, fn, dst, c->stream);
+            const size_t slice = 2 * (size_t)fn * es;
+            if ((size_t)(pi + 1) * slice > Hbytes[b]) return fail(c, SBPE_EINVAL, "probe slice out of range");
+            e = launch_frame_gather(c->dtype, Y[b], H.n1, H.n2, R, fn, G[b], c->stream);
             if (e) return fail(c, SBPE_EHIP, std::string("probe gather: ") + hip_error_string(e));
+            if (fn > 0 && hipMemcpyAsync(static_cast<char*>(Ha[b]) + (size_t)pi * slice, G[b], slice,
+                                         hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+                return fail(c, SBPE_EHIP, "frame operator probe copy");
         }
+        if ((pi + 1) % PROBE_CHUNK == 0 && hipStreamSynchronize(c->stream) != hipSuccess)
+            return fail(c, SBPE_EHIP, "frame operator probes");
         return SBPE_OK;
     };
     {
@@ -1241,25 +1283,18 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
                 for (int cy = 0; cy < P && !st; ++cy)
                     for (int cx = 0; cx < P && !st; ++cx) st = probe(pi++, bp, comp, cx, cy, P);
         for (int comp = 0; comp < 2 && !st; ++comp) st = probe(NPC + comp, -1, comp, 0, 0, 0);
+        if (!st && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(c, SBPE_EHIP, "frame operator probes");
         if (st) {
+            (void)hipStreamSynchronize(c->stream);
             cleanup_all();
             return st;
-        }
-        for (int b = 0; b < nb; ++b)
-            if (hipMemcpyAsync(Ha[b].data(), Ga[b], Ha[b].size(), hipMemcpyDeviceToHost, c->stream) != hipSuccess) {
-                cleanup_all();
-                return fail(c, SBPE_EHIP, "frame operator probe copy");
-            }
-        if (hipStreamSynchronize(c->stream) != hipSuccess) {
-            cleanup_all();
-            return fail(c, SBPE_EHIP, "frame operator probes");
         }
     }
     // value of frame row r (2 k + q) of block b in probe pi
     auto hv = [&](int b, int pi, long r) -> double {
         const size_t idx = (size_t)pi * 2 * (size_t)c->desc[b].frame_n + (size_t)r;
-        return c->dtype == SBPE_F64 ? reinterpret_cast<const double*>(Ha[b].data())[idx]
-                                    : (double)reinterpret_cast<const float*>(Ha[b].data())[idx];
+        return c->dtype == SBPE_F64 ? static_cast<const double*>(Ha[b])[idx]
+                                    : (double)static_cast<const float*>(Ha[b])[idx];
     };
     // column of the unit vector of probe pi that row (b; i, j) sees, or false
     // if none of its window does (a row reaching beyond the probing period)
@@ -1363,8 +1398,8 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
         D.fr_val = H.d_fr_val;
         D.fr_rsum = H.d_fr_rsum;
     }
-    for (int b = 0; b < nb; ++b) (void)hipFree(Ga[b]);
-    Ga.assign(nb, nullptr);
+    for (int b = 0; b < nb; ++b) (void)hipHostFree(Ha[b]);
+    Ha.assign(nb, nullptr);
     if (bad) {
         cleanup();
         return fail(c, SBPE_EHIP, "frame operator assembly: a frame row reaches beyond the probe window");
@@ -1414,16 +1449,27 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
                 for (size_t k = 0; k < dst.size(); ++k) dst[k] = val(b, (long)k);
             }
         }
+        // FP64: max norm; FP32: relative L2 over the frame rows, the norm of
+        // the library's FP32 accuracy target (rounding of the probed entries
+        // and the two summation orders differ by a few units in the last place
+        // per row, which the max over ~10^5 rows would amplify)
+        double ss_ref = 0.0, ss_err = 0.0;
         for (int b = 0; b < nb; ++b)
             for (size_t k = 0; k < ref[b].size(); ++k) {
+                const double d = ref[b][k] - got[b][k];
                 scale = std::max(scale, std::fabs(ref[b][k]));
-                err = std::max(err, std::fabs(ref[b][k] - got[b][k]));
+                err = std::max(err, std::fabs(d));
+                ss_ref += ref[b][k] * ref[b][k];
+                ss_err += d * d;
             }
-        const double tol = c->dtype == SBPE_F64 ? 1e-11 : 1e-4;
-        if (err > tol * std::max(scale, 1e-300)) {
+        const double rel = c->dtype == SBPE_F64 ? err / std::max(scale, 1e-300)
+                                                : std::sqrt(ss_err / std::max(ss_ref, 1e-300));
+        c->frame_check = rel;
+        const double tol = c->dtype == SBPE_F64 ? 1e-11 : 1e-5;
+        if (!(rel <= tol)) {
             cleanup();
             char buf[160];
-            std::snprintf(buf, sizeof buf, "frame operator assembly check failed: %.3e relative", err / scale);
+            std::snprintf(buf, sizeof buf, "frame operator assembly check failed: %.3e relative", rel);
             return fail(c, SBPE_EHIP, buf);
         }
     }
@@ -1578,7 +1624,7 @@ sbpe_status sbpe_apply(sbpe_ctx_t c, const void* const* u, void* const* a, doubl
         if (s2) return s2;
     }
     {
-        sbpe_status s2 = refresh_desc(c, c->desc.empty() ? 0.0 : c->desc[0].dt);
+        sbpe_status s2 = refresh_desc(c, c->desc.empty() ? 0.0 : c->desc[0].dt, c->d_tau);
         if (s2) return s2;
     }
     PassArgs pa = base_args(c);
@@ -1651,36 +1697,20 @@ sbpe_status sbpe_set_energy_guard(sbpe_ctx_t c, int every, double rel_growth) {
     return SBPE_OK;
 }
 
-sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
-    if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
-    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
-    sbpe_status s = need_gpu(c);
-    if (s) return s;
-    if (!c->bound) return fail(c, SBPE_ESTATE, "no state bound");
-    if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(c, SBPE_EINVAL, "bad nsteps or dt");
-    const long nrec = (long)c->receivers.size();
-    const long slots = nrec * 16 * 2;
-    if (nrec > 0 && c->rec_steps + nsteps > c->rec_cap) {
-        long cap = std::max<long>(c->rec_steps + nsteps, 2 * c->rec_cap);
-        double* nd = nullptr;
-        if (hipMalloc(&nd, cap * slots * sizeof(double)) != hipSuccess) return fail(c, SBPE_ENOMEM, "receiver buffer");
-        if (c->d_rec && c->rec_steps > 0)
-            HIPCHECK(c, hipMemcpyAsync(nd, c->d_rec, c->rec_steps * slots * sizeof(double), hipMemcpyDeviceToDevice,
-                                       c->stream));
-        HIPCHECK(c, hipStreamSynchronize(c->stream));
-        (void)hipFree(c->d_rec);
-        c->d_rec = nd;
-        c->rec_cap = cap;
-    }
+// The steps of an advance call once the receiver
+// record holds them: the time functions of every step tabulated into `tau`
+// (at least nsteps * nitems * 3 doubles), then two sweeps per step.
+static sbpe_status advance_steps(sbpe_ctx* c, int nsteps, double dt, double* tau) {
+    sbpe_status s;
     double e0 = 0.0;
     if (c->guard_every > 0) {
         s = energy_now(c, &e0);
         if (s) return s;
     }
     if (nsteps > 0) {
-        s = fill_tau(c, nsteps, c->t, dt);
-        if (s) return s;
-        s = refresh_desc(c, dt);
+        const int e = launch_tau(c->d_items, c->nitems, nsteps, c->t, dt, tau, c->stream);
+        if (e != 0) return fail(c, SBPE_EHIP, std::string("tau launch: ") + hip_error_string(e));
+        s = refresh_desc(c, dt, tau);
         if (s) return s;
     }
     for (int k = 0; k < nsteps; ++k) {
@@ -1719,6 +1749,38 @@ sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
     }
     c->rec_steps += nsteps;
     return finish_passes(c);
+}
+
+static sbpe_status check_advance(sbpe_ctx* c, int nsteps, double dt) {
+    if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (!c->bound) return fail(c, SBPE_ESTATE, "no state bound");
+    if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(c, SBPE_EINVAL, "bad nsteps or dt");
+    return SBPE_OK;
+}
+
+sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
+    sbpe_status s = check_advance(c, nsteps, dt);
+    if (s) return s;
+    s = grow_receivers(c, c->rec_steps + nsteps);
+    if (s) return s;
+    if (nsteps > 0) {
+        s = grow_tau(c, nsteps);
+        if (s) return s;
+    }
+    return advance_steps(c, nsteps, dt, c->d_tau);
+}
+
+sbpe_status sbpe_reserve_steps(sbpe_ctx_t c, int nsteps) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (nsteps < 0) return fail(c, SBPE_EINVAL, "negative nsteps");
+    s = grow_tau(c, nsteps);
+    if (s) return s;
+    return grow_receivers(c, c->rec_steps + nsteps);
 }
 
 sbpe_status sbpe_get_time(sbpe_ctx_t c, double* t) {

@@ -1,0 +1,6 @@
+// Sweep, frame and gradient kernels of precision F32, order 2.
+#include "sbpe_launch_impl.h"
+
+namespace sbpe {
+template struct Launch<float, 2>;
+}  // namespace sbpe

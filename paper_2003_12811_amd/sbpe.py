@@ -57,6 +57,7 @@ _PROTOS = {
     'sbpe_apply': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _I],
     'sbpe_bind_state': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D],
     'sbpe_advance': [_P, _I, _D],
+    'sbpe_reserve_steps': [_P, _I],
     'sbpe_get_time': [_P, _DP],
     'sbpe_read_receivers': [_P, _DP, _I, _IP],
     'sbpe_energy': [_P, _DP],
@@ -138,7 +139,7 @@ def sbpe_create(device, stream, dtype, order, beta=1.0):
 
 
 def sbpe_destroy(ctx):
-    _check(None, lib().sbpe_destroy(ctx))
+    _check(ctx, lib().sbpe_destroy(ctx))
 
 
 def sbpe_last_error(ctx):
@@ -247,6 +248,10 @@ def sbpe_bind_state(ctx, u_ptrs, v_ptrs, t=0.0):
 
 def sbpe_advance(ctx, nsteps, dt):
     _check(ctx, lib().sbpe_advance(ctx, nsteps, dt))
+
+
+def sbpe_reserve_steps(ctx, nsteps):
+    _check(ctx, lib().sbpe_reserve_steps(ctx, nsteps))
 
 
 def sbpe_get_time(ctx):

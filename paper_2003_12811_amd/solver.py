@@ -96,6 +96,11 @@ class Solver:
     def advance(self, nsteps, dt):
         S.sbpe_advance(self.ctx, nsteps, dt)
 
+    def reserve(self, nsteps):
+        """Size the time-function table and the receiver record for advance
+        calls of up to nsteps steps, so that they allocate nothing."""
+        S.sbpe_reserve_steps(self.ctx, nsteps)
+
     def apply(self, us, t=0.0, homogeneous=False, out=None):
         """a = rho~^{-1}(L u + data(t)) for device tensors us (one per block)."""
         torch = self.torch

@@ -75,7 +75,7 @@ def test_gradient_matches_oracle_adjoint():
     go_c10 = _c10_from_full(go_C)
     er, ec, eJ = rel(g_rho, go_rho), rel(g_c10, go_c10), abs(J - Jo) / Jo
     say('  J %.6e (oracle %.6e)  rel err J %.2e  rho %.2e  C10 %.2e' % (J, Jo, eJ, er, ec))
-    assert eJ < 1e-9 and er < 1e-8 and ec < 1e-8
+    assert eJ < 1e-10 and er < 1e-10 and ec < 1e-10
 
 
 def _fd_check(spec, spec_obs, nsteps, dt, ndir, ckpt, tol, eps=1e-5):

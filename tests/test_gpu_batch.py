@@ -103,6 +103,7 @@ def test_batch_alone_equals_mix(dtype):
         assert np.array_equal(u, ref_u) and np.array_equal(v, ref_v)
         assert np.array_equal(a2.receivers(), ref_r)
         assert np.abs(ref_u).max() > 0
+        S.sbpe_batch_remove(bt, o2.ctx)             # a member must leave before its context is destroyed
         for s in (a2, o1, o2, o3):
             s.close()
     finally:
@@ -122,6 +123,12 @@ def test_batch_member_rules():
             S.sbpe_batch_add(bt, a.ctx, 10, a.dt)    # already a member
         with pytest.raises(S.SbpeError):
             S.sbpe_batch_advance(bt, 11)             # beyond its remaining steps
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_destroy(a.ctx)                    # still referenced by the batch
+        assert e.value.code == S.ESTATE
+        S.sbpe_batch_advance(bt, 4)                  # the member is intact and still advances
+        S.sbpe_batch_synchronize(bt)
+        assert S.sbpe_batch_remaining(bt, a.ctx) == 6
         S.sbpe_batch_remove(bt, a.ctx)
         with pytest.raises(S.SbpeError):
             S.sbpe_batch_add(bt32, a.ctx, 10, a.dt)  # dtype differs

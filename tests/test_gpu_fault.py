@@ -16,6 +16,7 @@ import pytest
 from oracle import timestep as T
 from oracle.spec import build
 from paper_2003_12811_amd import workloads as W
+from parity import band_max_rel
 
 pytestmark = pytest.mark.gpu
 TOL = {'f64': 1e-11, 'f32': 1e-5}
@@ -82,9 +83,11 @@ def test_apply_jump_data_reversed_interface(dtype, order):
         got0 = [x.double().cpu().numpy() for x in sol.apply(zs, t=t)]
         ref0 = P.rhs(zs, t)
         err0 = rel(np.concatenate([g.ravel() for g in got0]), np.concatenate([r.ravel() for r in ref0]))
-        say('  rel L2 %.3e, data part alone %.3e' % (err, err0))
+        eb, eb0 = band_max_rel(got, ref, order), band_max_rel(got0, ref0, order)
+        say('  rel L2 %.3e, data part alone %.3e; band max %.3e, %.3e' % (err, err0, eb, eb0))
         assert np.linalg.norm(np.concatenate([r.ravel() for r in ref0])) > 0
         assert err < TOL[dtype] and err0 < TOL[dtype]
+        assert eb < TOL[dtype] and eb0 < TOL[dtype]
     finally:
         sol.close()
 

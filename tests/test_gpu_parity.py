@@ -13,9 +13,9 @@ from paper_2003_12811_amd import sbpe as S
 from paper_2003_12811_amd import workloads as W
 
 from oracle.spec import build, receivers
+from parity import TOL, band_max_rel
 
 pytestmark = pytest.mark.gpu
-TOL = {'f64': 1e-11, 'f32': 1e-5}
 
 
 def say(*a):
@@ -77,9 +77,9 @@ def test_apply_single_block_all_bcs(dtype, order, shape):
             ref = (L / B.rho.ravel()).reshape(2, n2, n1)
         else:
             ref = P.rhs([u], t)[0]
-        err = rel(got, ref)
-        say('  t', t, 'hom', hom, 'rel L2', err)
-        assert err < TOL[dtype]
+        err, eb = rel(got, ref), band_max_rel(got, ref, order)
+        say('  t', t, 'hom', hom, 'rel L2', err, 'band max', eb)
+        assert err < TOL[dtype] and eb < TOL[dtype]
     sol.close()
 
 
@@ -95,8 +95,9 @@ def test_apply_multiblock_c3_geometry(dtype, n):
     got = [x.double().cpu().numpy() for x in sol.apply(us, t=0.11)]
     ref = P.rhs(us, 0.11)
     err = rel(np.concatenate([g.ravel() for g in got]), np.concatenate([r.ravel() for r in ref]))
-    say('  rel L2', err)
-    assert err < TOL[dtype]
+    eb = band_max_rel(got, ref, 4)
+    say('  rel L2', err, 'band max', eb)
+    assert err < TOL[dtype] and eb < TOL[dtype]
     sol.close()
 
 
@@ -126,8 +127,9 @@ def test_apply_reversed_interface(order):
     got = [x.cpu().numpy() for x in sol.apply(us)]
     ref = P.rhs(us, 0.0)
     err = rel(np.concatenate([g.ravel() for g in got]), np.concatenate([r.ravel() for r in ref]))
-    say('  rel L2', err)
-    assert err < 1e-11
+    eb = band_max_rel(got, ref, order)
+    say('  rel L2', err, 'band max', eb)
+    assert err < 1e-11 and eb < 1e-11
     sol.close()
 
 
@@ -249,9 +251,9 @@ def test_full_size_c2_apply(dtype):
                 1e-3 * np.random.default_rng(0).normal(size=(2, n, n)), dtype)
     got = sol.apply([u], t=0.1)[0].double().cpu().numpy()
     ref = P.rhs([u], 0.1)[0]
-    err = rel(got, ref)
-    say('  rel L2', err)
-    assert err < TOL[dtype]
+    err, eb = rel(got, ref), band_max_rel(got, ref, 4)
+    say('  rel L2', err, 'band max', eb)
+    assert err < TOL[dtype] and eb < TOL[dtype]
     sol.close()
 
 
@@ -311,6 +313,48 @@ def test_tile_rows_do_not_change_results():
             sol.close()
     for u, v, r, _ in out[1:]:
         assert np.array_equal(u, out[0][0]) and np.array_equal(v, out[0][1]) and np.array_equal(r, out[0][2])
+
+
+@pytest.fixture(scope='module')
+def c3_full():
+    """The 2x2 x 2049^2 workload and its oracle (about a minute of CPU time)."""
+    spec = W.spec_c3(n=2049)
+    return spec, build(spec)
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_full_size_c3_apply_and_energy(dtype, c3_full):
+    """The 2x2 x 2049^2 workload at its full size, element by element against
+    the oracle: one right-hand side inside the Ricker pulse (interfaces,
+    displacement and traction faces, the point source), in the two-stream
+    launch path the benchmark times, and the FP64 energy of a state."""
+    spec, P = c3_full
+    n = 2049
+    say('full size C3 apply and energy', dtype)
+    sol = solver(spec, dtype)
+    try:
+        assert not S.sbpe_plan_info(sol.ctx)['fused_sweep']
+        x1, x2 = W.reference_grid(n, n)
+        rng = np.random.default_rng(9)
+        us, vs = [], []
+        for _ in spec['blocks']:
+            a, b, c, d = rng.uniform(1, 6, 4)
+            us.append(rounded(np.stack([np.sin(a * x1 + b * x2 + c), np.cos(d * x1 - a * x2)]) +
+                              1e-3 * rng.normal(size=(2, n, n)), dtype))
+            vs.append(rounded(np.stack([np.cos(b * x1 - c * x2), np.sin(c * x1 + d * x2)]), dtype))
+        t = 0.1
+        got = [x.double().cpu().numpy() for x in sol.apply(us, t=t)]
+        ref = P.rhs(us, t)
+        err = rel(np.concatenate([g.ravel() for g in got]), np.concatenate([r.ravel() for r in ref]))
+        eb = band_max_rel(got, ref, 4)
+        say('  apply rel L2 %.3e  band max %.3e' % (err, eb))
+        assert err < TOL[dtype] and eb < TOL[dtype]
+        sol.set_state(us, vs, 0.0)
+        e_lib, e_or = sol.energy(), P.energy(us, vs)
+        say('  energy lib %.12e oracle %.12e rel %.2e' % (e_lib, e_or, abs(e_lib / e_or - 1)))
+        assert abs(e_lib / e_or - 1) < TOL[dtype]
+    finally:
+        sol.close()
 
 
 @pytest.mark.parametrize("dtype", ['f64', 'f32'])

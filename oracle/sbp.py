@@ -31,22 +31,38 @@ The paper cites, but does not print, the coefficients.  Readings used here:
   (b, u) polynomial pairs of total degree <= 3 (second-order closure) while row
   0 keeps the end-point order q-1 of the adapted operators.  All weights are
   positive, so every dR/db_s is positive semidefinite (Lemma 1 holds).
+* 6th order: the diagonal norm of a six-row closure with boundary order 3,
+  H = h diag(13649/43200, 12013/8640, 2711/4320, 5359/4320, 7877/8640,
+  43801/43200, 1, ...), which the order conditions fix uniquely; they leave
+  one free entry of Q = H D1, set to the minimiser of the H-weighted squared
+  degree-4 residual of the closure rows (``_Q6_UPPER``); interior
+  (-1/60, 3/20, -3/4, 0, 3/4, -3/20, 1/60)/h.  R(b) has windows of differences
+  of orders 4, 5, 6 with B the mean of the three middle b values (weight
+  1/80), of the two middle ones (1/600) and the centre value (1/3600): the
+  unique non-negative weights that give a seven-point sixth-order interior.
+  The five order-4 windows at each end are scaled by ``_G4_BND``, the unique
+  factors making rows 1..8 exact for (b, u) pairs of total degree <= 4 (a
+  third-order closure); all are positive.
 
 Parity status: pinned (tests/test_oracle_sbp.py checks the SBP identities in
 exact rational arithmetic, polynomial exactness, symmetry and positive
-semidefiniteness of R, and the constant-coefficient textbook stencils).
+semidefiniteness of R, and the constant-coefficient textbook stencils;
+tests/test_oracle_sixth.py re-derives every order-6 choice in exact
+arithmetic and checks the 2-D operator's self-adjointness and convergence).
 """
 from fractions import Fraction as Fr
 
 import numpy as np
 import scipy.sparse as sps
 
-ORDERS = (2, 4)
+ORDERS = (2, 4, 6)
 
 # ---------------------------------------------------------------- norms
 _H_CLOSURE = {
     2: [Fr(1, 2)],
     4: [Fr(17, 48), Fr(59, 48), Fr(43, 48), Fr(49, 48)],
+    # the unique diagonal norm of a 6-row closure with third-order boundary rows
+    6: [Fr(13649, 43200), Fr(12013, 8640), Fr(2711, 4320), Fr(5359, 4320), Fr(7877, 8640), Fr(43801, 43200)],
 }
 
 # ------------------------------------------------------ first derivative
@@ -60,7 +76,57 @@ _D1_CLOSURE = {
 _D1_INTERIOR = {
     2: (1, [Fr(-1, 2), Fr(0), Fr(1, 2)]),
     4: (2, [Fr(1, 12), Fr(-2, 3), Fr(0), Fr(2, 3), Fr(-1, 12)]),
+    6: (3, [Fr(-1, 60), Fr(3, 20), Fr(-3, 4), Fr(0), Fr(3, 4), Fr(-3, 20), Fr(1, 60)]),
 }
+
+# Order 6: Q = H D1 on the six closure rows.  The order conditions
+# (D1 x^k = k x^(k-1), k <= 3, on rows 0..5) with Q + Q^T = diag(-1, 0, ...)
+# fix H uniquely and leave one free entry, Q_45.  It is set to the minimiser of
+# the H-weighted square of the degree-4 residuals of the closure rows,
+# sum_r H_r ((D1 x^4)_r - 4 x_r^3)^2, inside the interval where every boundary
+# weight of the remainder below is non-negative.  Entries (r, c), r < c < 6;
+# Q_rr = 0 except Q_00 = -1/2; Q_rc = -Q_cr; columns 6..8 follow from the
+# interior rows by skew symmetry.
+_Q6_UPPER = {
+    (0, 1): Fr(5124475092222703052468879, 7931626489314500743872000),
+    (0, 2): Fr(-14688227387107654735453, 247863327791078148246000),
+    (0, 3): Fr(-159267246833799759813661, 1321937748219083457312000),
+    (0, 4): Fr(18306575045382041159483, 991453311164312592984000),
+    (0, 5): Fr(120512309461734500607719, 7931626489314500743872000),
+    (1, 2): Fr(345639531999877949576339, 793162648931450074387200),
+    (1, 3): Fr(28465971813079192963909, 99145331116431259298400),
+    (1, 4): Fr(-21963203401877827569241, 528775099287633382924800),
+    (1, 5): Fr(-34968740224280558358577, 991453311164312592984000),
+    (2, 3): Fr(179724104434047613799819, 396581324465725037193600),
+    (2, 4): Fr(-8637026328486517498841, 99145331116431259298400),
+    (2, 5): Fr(13808676868217278023299, 1321937748219083457312000),
+    (3, 4): Fr(540747751505546378368499, 793162648931450074387200),
+    (3, 5): Fr(-9742420893013796487329, 123931663895539074123000),
+    (4, 5): Fr(5591070156686698065364559, 7931626489314500743872000)
+}
+
+
+def _d1_closure_6():
+    H = _H_CLOSURE[6]
+    half, st = _D1_INTERIOR[6]
+    rows = []
+    for r in range(6):
+        row = []
+        for c in range(9):
+            if c < 6:
+                q = Fr(-1, 2) if (r, c) == (0, 0) else (Fr(0) if r == c else
+                                                        (_Q6_UPPER[(r, c)] if r < c else -_Q6_UPPER[(c, r)]))
+            else:
+                k = r - c                # Q_rc = -Q_cr, row c interior: Q_cr = d_{r-c}
+                q = -st[k + half] if -half <= k <= half else Fr(0)
+            row.append(q / H[r])
+        while row and row[-1] == 0:
+            row.pop()
+        rows.append(row)
+    return rows
+
+
+_D1_CLOSURE[6] = _d1_closure_6()
 
 # remainder windows: (difference stencil, interior weight, boundary weights,
 #                     list of (offset within window, share) defining B)
@@ -70,14 +136,26 @@ _R_WINDOWS = {
          [Fr(181507, 1719312), Fr(293, 4214), Fr(185, 3528)],
          [(1, Fr(1, 2)), (2, Fr(1, 2))]),
         ([1, -4, 6, -4, 1], Fr(1, 144), [], [(2, Fr(1))])],
+    # order 6: windows of widths 5, 6, 7 (alpha = 4, 5, 6); the interior
+    # weights are the unique ones that make the interior stencil seven points
+    # wide and sixth-order accurate; the five width-5 windows at each end are
+    # scaled by the factors _G4_BND, the unique ones that make rows 1.. of
+    # D2^FC exact for all (b, u) polynomial pairs of total degree <= 4 (a
+    # third-order closure) given the D1 above; every factor is positive
+    6: [([1, -4, 6, -4, 1], Fr(1, 80), None, [(1, Fr(1, 3)), (2, Fr(1, 3)), (3, Fr(1, 3))]),
+        ([-1, 5, -10, 10, -5, 1], Fr(1, 600), [], [(2, Fr(1, 2)), (3, Fr(1, 2))]),
+        ([1, -6, 15, -20, 15, -6, 1], Fr(1, 3600), [], [(3, Fr(1))])],
 }
+_G4_BND = [Fr(237685172925523195733757321662141117118767, 31602998592421529376702770327325284401500), Fr(227139847450989727703237846776878932224483, 31602998592421529376702770327325284401500), Fr(23788947390956941843, 15300205419202354830), Fr(53028109694882963204, 68850924386410596735), Fr(145701618090536539739, 137701848772821193470)]
+_R_WINDOWS[6][0] = (_R_WINDOWS[6][0][0], _R_WINDOWS[6][0][1], [g * _R_WINDOWS[6][0][1] for g in _G4_BND],
+                    _R_WINDOWS[6][0][3])
 
-MIN_POINTS = {2: 3, 4: 13}
+MIN_POINTS = {2: 3, 4: 13, 6: 19}
 
 
 def _check(n, order):
     if order not in ORDERS:
-        raise ValueError("order must be 2 or 4")
+        raise ValueError("order must be 2, 4 or 6")
     if n < MIN_POINTS[order]:
         raise ValueError(f"need at least {MIN_POINTS[order]} points for order {order}")
 

@@ -13,11 +13,12 @@ import pytest
 
 from oracle import sbp
 
-ORD = [2, 4]
+ORD = [2, 4, 6]
+R0 = {2: 1, 4: 6, 6: 9}          # closure rows of D2^FC (rows that differ from the interior stencil)
 
 
 @pytest.mark.parametrize("order", ORD)
-@pytest.mark.parametrize("n", [13, 17, 24])
+@pytest.mark.parametrize("n", [19, 24, 29])
 def test_sbp_identity_exact(order, n):
     H = sbp.norm_exact(n, order)
     D = sbp.d1_exact(n, order)
@@ -71,7 +72,7 @@ def test_d2fc_polynomial_orders(order):
     total degree <= q (order q-1, the adapted operator, Sec. 4.1)."""
     n = 25
     q = order // 2
-    r0 = 1 if order == 2 else 6
+    r0 = R0[order]
     interior = list(range(r0, n - r0))
     closure = list(range(1, r0)) + list(range(n - r0, n - 1))
     ends = [0, n - 1]
@@ -86,15 +87,15 @@ def test_d2fc_polynomial_orders(order):
                 assert _d2_exact_vs_poly(order, n, pb, pu, closure) < tol, (pb, pu)
             if tot <= q:
                 assert _d2_exact_vs_poly(order, n, pb, pu, ends) < tol, (pb, pu)
-    # and the end point is genuinely of lower order for the cubic (order 4 only)
-    if order == 4:
-        assert _d2_exact_vs_poly(order, n, 0, 3, ends) > 1e-6
+    # and the end point is genuinely of lower order (orders 4 and 6)
+    if order >= 4:
+        assert _d2_exact_vs_poly(order, n, 0, q + 1, ends) > 1e-6
 
 
 @pytest.mark.parametrize("order", ORD)
 def test_remainder_structure(order):
     """R(b) symmetric, every dR/db_s PSD (Lemma 1), R 1 = R x = 0."""
-    n = 17
+    n = 25
     h = 1.0 / (n - 1)
     x = np.arange(n) * h
     rng = np.random.default_rng(0)
@@ -112,12 +113,13 @@ def test_remainder_structure(order):
 
 @pytest.mark.parametrize("order", ORD)
 def test_constant_coefficient_textbook(order):
-    n = 21
+    n = 31
     h = 1.0 / (n - 1)
     D2 = sbp.d2fc(np.ones(n), h, order).toarray() * h * h
-    st = {2: [1.0, -2.0, 1.0], 4: [-1 / 12, 4 / 3, -5 / 2, 4 / 3, -1 / 12]}[order]
+    st = {2: [1.0, -2.0, 1.0], 4: [-1 / 12, 4 / 3, -5 / 2, 4 / 3, -1 / 12],
+          6: [1 / 90, -3 / 20, 3 / 2, -49 / 18, 3 / 2, -3 / 20, 1 / 90]}[order]
     k = len(st) // 2
-    for r in range(8, n - 8):
+    for r in range(R0[order], n - R0[order]):
         row = np.zeros(n)
         row[r - k:r + k + 1] = st
         assert np.allclose(D2[r], row, atol=1e-12)

@@ -211,6 +211,20 @@ sbpe_status sbpe_advance(sbpe_ctx_t ctx, int nsteps, double dt);
  * SBPE_EINVAL for nsteps < 0, SBPE_ENOMEM if the device memory is not there. */
 sbpe_status sbpe_reserve_steps(sbpe_ctx_t ctx, int nsteps);
 
+/* sbpe_advance that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The time functions of the call are tabulated into
+ * a device scratch array of the library, 1 MiB per GPU, held from the first
+ * sbpe_create on that GPU until the process ends; at most
+ * floor(131072 / (3 * nitems)) steps fit one call, where nitems is 9 per
+ * block plus one per source (SBPE_EINVAL beyond that, with the limit in the
+ * message).  The receiver record must already hold nsteps more steps
+ * (sbpe_reserve_steps; SBPE_ESTATE otherwise).  Results equal those of
+ * sbpe_advance bit for bit.  Every context on one GPU shares the scratch
+ * array: calls that overlap in time on one GPU (contexts on different
+ * streams, or host threads) race and must be serialised by the caller. */
+sbpe_status sbpe_advance_noalloc(sbpe_ctx_t ctx, int nsteps, double dt);
+
 /* Current time of the bound state. */
 sbpe_status sbpe_get_time(sbpe_ctx_t ctx, double* t);
 

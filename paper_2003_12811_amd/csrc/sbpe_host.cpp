@@ -901,6 +901,12 @@ sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double b
             delete c;
             return fail(nullptr, SBPE_EHIP, "hipSetDevice failed");
         }
+        // device address of the no-allocation scratch on this device (once per device)
+        const int se = scratch_init(device);
+        if (se != 0) {
+            delete c;
+            return fail(nullptr, SBPE_EHIP, std::string("scratch symbol lookup: ") + hip_error_string(se));
+        }
         if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_main, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess) {
@@ -1771,6 +1777,28 @@ sbpe_status sbpe_advance(sbpe_ctx_t c, int nsteps, double dt) {
         if (s) return s;
     }
     return advance_steps(c, nsteps, dt, c->d_tau);
+}
+
+sbpe_status sbpe_advance_noalloc(sbpe_ctx_t c, int nsteps, double dt) {
+    sbpe_status s = check_advance(c, nsteps, dt);
+    if (s) return s;
+    const long nrec = (long)c->receivers.size();
+    if (nrec > 0 && c->rec_steps + nsteps > c->rec_cap) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "receiver record holds %ld more steps, %d asked: sbpe_reserve_steps first",
+                      c->rec_cap - c->rec_steps, nsteps);
+        return fail(c, SBPE_ESTATE, buf);
+    }
+    const size_t per_step = (size_t)c->nitems * 3;
+    if ((size_t)nsteps * per_step > NOALLOC_SCRATCH_DOUBLES) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "at most %zu steps per call fit the no-allocation time-function table (%d asked)",
+                      NOALLOC_SCRATCH_DOUBLES / std::max<size_t>(per_step, 1), nsteps);
+        return fail(c, SBPE_EINVAL, buf);
+    }
+    double* tau = scratch_ptr(c->device);
+    if (!tau) return fail(c, SBPE_ESTATE, "no-allocation scratch not set up on this device");
+    return advance_steps(c, nsteps, dt, tau);
 }
 
 sbpe_status sbpe_reserve_steps(sbpe_ctx_t c, int nsteps) {

@@ -212,5 +212,11 @@ struct RecAdjArgs {
 };
 int launch_rec_adjoint(int dtype, const RecAdj* ent, int nent, const double* r, const RecAdjArgs& a, void* stream);
 const char* hip_error_string(int code);
+// device scratch of the no-allocation advance (sbpe_advance_noalloc): doubles
+// per GPU, the device address of the array on `device` (looked up once per
+// device by scratch_init with that device current; null before)
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(1) << 17;   // 1 MiB
+int scratch_init(int device);
+double* scratch_ptr(int device);
 
 }  // namespace sbpe

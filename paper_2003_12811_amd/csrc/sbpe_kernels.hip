@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <mutex>
 
 #include "sbpe_device.h"
 #include "sbpe_launch.h"
@@ -184,6 +185,37 @@ int launch_frame_sp(int dtype, int order, const PassArgs& a0, int total_frame_wg
     const dim3 g((unsigned)((pts + FRAME_WG / FRAME_LANES - 1) / (FRAME_WG / FRAME_LANES))), b(FRAME_WG);
     with_launch(dtype, order, [&](auto L) { decltype(L)::frame_sp(a, g, b, s); });
     return (int)hipGetLastError();
+}
+
+// ------------------------------------------------- no-allocation scratch
+// The time-function table of sbpe_advance_noalloc lives in this file-scope
+// device array: one copy per GPU, kept until the process ends and shared by
+// every context on that GPU.  In host code `scratch` is only a stand-in for
+// the symbol; its device address is looked up once per device (with that
+// device current) and only that address is handed to kernels.
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+int scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return 0;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+    return 0;
+}
+
+double* scratch_ptr(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 const char* hip_error_string(int code) { return hipGetErrorString(static_cast<hipError_t>(code)); }

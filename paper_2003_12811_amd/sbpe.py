@@ -58,6 +58,7 @@ _PROTOS = {
     'sbpe_bind_state': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D],
     'sbpe_advance': [_P, _I, _D],
     'sbpe_reserve_steps': [_P, _I],
+    'sbpe_advance_noalloc': [_P, _I, _D],
     'sbpe_get_time': [_P, _DP],
     'sbpe_read_receivers': [_P, _DP, _I, _IP],
     'sbpe_energy': [_P, _DP],
@@ -248,6 +249,10 @@ def sbpe_bind_state(ctx, u_ptrs, v_ptrs, t=0.0):
 
 def sbpe_advance(ctx, nsteps, dt):
     _check(ctx, lib().sbpe_advance(ctx, nsteps, dt))
+
+
+def sbpe_advance_noalloc(ctx, nsteps, dt):
+    _check(ctx, lib().sbpe_advance_noalloc(ctx, nsteps, dt))
 
 
 def sbpe_reserve_steps(ctx, nsteps):

@@ -328,6 +328,7 @@ def main():
     ap.add_argument('--no-c2', action='store_true')
     ap.add_argument('--no-f32', action='store_true')
     ap.add_argument('--no-wide', action='store_true')
+    ap.add_argument('--no-order6', action='store_true')
     ap.add_argument('--tile-rows', type=int, default=0,
                     help='interior tile height of every run (0: pick the launch shape by timing candidates)')
     ap.add_argument('--frame-loop', type=int, default=0,
@@ -335,10 +336,13 @@ def main():
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
     ap.add_argument('--no-gradient', action='store_true')
-    ap.add_argument('--serve-shots', type=int, default=48)
-    ap.add_argument('--serve-rate', type=float, default=200.0,
-                    help='mean arrival rate of the served stream (shots/s); the default saturates the GPU')
+    # the serving workload (256 shots of 257^2 .. 2049^2, 1500 steps, 20/s) scaled down to a
+    # bench-length run with the same offered load: 64 shots, 300 steps, 100/s
+    ap.add_argument('--serve-shots', type=int, default=64)
+    ap.add_argument('--serve-rate', type=float, default=100.0,
+                    help='mean arrival rate of the served stream (shots/s)')
     ap.add_argument('--serve-steps', type=int, default=300)
+    ap.add_argument('--serve-sizes', default='257,513,1025,2049')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='first run a plain device-to-device copy of this many MiB (calibrates '
                          'the HBM byte counters of a profiler)')
@@ -352,7 +356,7 @@ def main():
               'several GPUs is not implemented)', file=sys.stderr)
         sys.exit(2)
     if args.headline_only:
-        args.no_cpu_baseline = args.no_c2 = args.no_f32 = args.no_wide = True
+        args.no_cpu_baseline = args.no_c2 = args.no_f32 = args.no_wide = args.no_order6 = True
         args.no_serve = args.no_gradient = True
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
@@ -430,11 +434,29 @@ def main():
                             "apply_roofline": roofline('interior_apply', r['apply_kernels']['interior_apply'][0],
                                                        swept_points(r['plan']), 8),
                             "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
+        if not args.no_order6:
+            log('sixth-order operators, fp64')
+            sp6 = W.spec_c2(n=args.c2_n, order=6)
+            r, sh, _ = section(sp6, 'f64', args, (10, 20), (1, 2, 4), 60, 50, False, fixed)
+            k = dominant(r)
+            line["order6"] = {"workload": "the single-block workload with the sixth-order operators, FP64",
+                              "value": r['updates_per_s'], "ms_per_step": r['ms_per_step'],
+                              "tile_rows": sh[0], "frame_loop": sh[1],
+                              "roofline": roofline(k, r['kernels'][k][0], swept_points(r['plan']), 8),
+                              "apply_roofline": roofline('interior_apply', r['apply_kernels']['interior_apply'][0],
+                                                         swept_points(r['plan']), 8),
+                              "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
     if not args.no_serve:
         from paper_2003_12811_amd import serve
         log('served stream vs sequential plain solves')
-        line["serving"] = serve.serve_and_compare(args.serve_shots, args.serve_rate, [257, 513, 1025],
-                                                  args.serve_steps)
+        sv = serve.serve_and_compare(args.serve_shots, args.serve_rate,
+                                     [int(x) for x in args.serve_sizes.split(',')], args.serve_steps)
+        sv["scale_down"] = ("the 256-shot stream (20/s, 1500 steps) with 64 shots of 300 steps arriving at "
+                            "100/s: the same offered grid-point updates per second")
+        if "c2_f32" in line:
+            sv["plain_f32_updates_per_s"] = line["c2_f32"]["value"]
+            sv["served_over_plain_f32"] = sv["served"]["updates_per_s"] / line["c2_f32"]["value"]
+        line["serving"] = sv
     if not args.no_gradient:
         log('misfit gradient (513^2, 2000 steps, checkpoints every 100)')
         line["gradient"] = gradient_timing()
@@ -442,7 +464,7 @@ def main():
         log('cpu baseline (oracle, 1 thread, %d steps of 2x2 blocks of %d^2)' % (args.cpu_steps, args.cpu_n))
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps, r3['dt'])
     # every roofline also against the measured copy bandwidth
-    for sec in [line] + [line[k] for k in ("c3_f32", "c2_f64", "c2_f32", "wide") if k in line]:
+    for sec in [line] + [line[k] for k in ("c3_f32", "c2_f64", "c2_f32", "wide", "order6") if k in line]:
         for key in ("roofline", "apply_roofline"):
             if key in sec and cbw:
                 sec[key]["copy_gbs"] = round(cbw, 1)

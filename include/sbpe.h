@@ -65,8 +65,10 @@ enum { SBPE_BC_TRACTION = 0, SBPE_BC_ROBIN = 1, SBPE_BC_DISPLACEMENT = 2, SBPE_B
 enum { SBPE_TIME_ZERO = 0, SBPE_TIME_ONE = 1, SBPE_TIME_COS = 2, SBPE_TIME_RICKER = 3 };
 
 /* Create a context bound to HIP device `device` and stream `stream` (NULL = the
- * default stream).  dtype: SBPE_F64 or SBPE_F32.  order: 2 or 4 (interior order
- * of the SBP operators, Sec. 4).  beta >= 1 scales the displacement and
+ * default stream).  dtype: SBPE_F64 or SBPE_F32.  order: 2, 4 or 6 (interior
+ * order of the SBP operators, Sec. 4; the paper's three orders, Sec. 7.1).
+ * Order 6 supports every call except the wide-stencil operator and the
+ * coefficient gradient (SBPE_EINVAL).  beta >= 1 scales the displacement and
  * interface penalties (Theorem 2; the paper uses beta = 1).  device = -1 makes
  * a host-only context: setup and the sbpe_host_* / sbpe_get_* queries work,
  * every call that needs a GPU returns SBPE_ESTATE. */
@@ -86,7 +88,8 @@ const char* sbpe_last_error(sbpe_ctx_t ctx);
  * [n2][n1]) and stiffness C10 ([10][n2][n1]: the major-symmetric components
  * C1111, C1112, C1121, C1122, C1212, C1221, C1222, C2121, C2122, C2222; minor
  * symmetry is not assumed, Sec. 3).  Arrays are copied.  All faces start as
- * homogeneous traction.  n1, n2 >= 13 for order 4, >= 6 for order 2, and
+ * homogeneous traction.  n1, n2 >= 19 for order 6, >= 13 for order 4, >= 6
+ * for order 2, and
  * n1 n2 <= 2^28 (SBPE_EINVAL otherwise, before the arrays are read). */
 sbpe_status sbpe_add_block(sbpe_ctx_t ctx, int n1, int n2, const double* X1, const double* X2,
                            const double* rho, const double* C10, int* block_id);
@@ -329,7 +332,10 @@ const char* sbpe_batch_last_error(sbpe_batch_t batch);
  * sbpe_advance, sbpe_apply and sbpe_bind_state on it fail with SBPE_ESTATE.
  * The members of a batch share device, dtype, order and operator
  * (sbpe_set_operator; the first member of an empty batch sets it): a context
- * that differs is refused with SBPE_EINVAL. */
+ * that differs is refused with SBPE_EINVAL, and so is a context finalized
+ * without the assembled frame operator (more than 16 blocks, or the
+ * environment variable SBPE_FRAME=stencil at sbpe_finalize, which runs the
+ * frame band of its own sweeps with the stencil kernel instead). */
 sbpe_status sbpe_batch_add(sbpe_batch_t batch, sbpe_ctx_t ctx, int nsteps, double dt);
 
 /* Remove a member (normally once its remaining step count is 0).  Work later

@@ -75,19 +75,37 @@ __device__ __forceinline__ void entries_at(BlockRef B, int beg, int end, long p,
 
 template <int ORD> struct Op;
 template <> struct Op<4> {
-    static constexpr int R0 = O4_R0, W = O4_W, NB = O4_NB, HALF = 2, REACH = 4;
+    static constexpr int R0 = O4_R0, W = O4_W, NB = O4_NB, HALF = 2, REACH = 4, D1W = 6;
     __host__ __device__ static constexpr double d2c(int r, int m, int s) { return D2T4.t[r][m][s]; }
     __host__ __device__ static constexpr double d1b(int r, int c) { return O4_D1B[r][c]; }
     __host__ __device__ static constexpr double d1i(int k) { return O4_D1I[k]; }
     __host__ __device__ static constexpr double hb(int k) { return O4_H[k]; }
 };
 template <> struct Op<2> {
-    static constexpr int R0 = O2_R0, W = O2_W, NB = O2_NB, HALF = 1, REACH = 2;
+    static constexpr int R0 = O2_R0, W = O2_W, NB = O2_NB, HALF = 1, REACH = 2, D1W = 6;
     __host__ __device__ static constexpr double d2c(int r, int m, int s) { return D2T2.t[r][m][s]; }
     __host__ __device__ static constexpr double d1b(int r, int c) { return O2_D1B[r][c]; }
     __host__ __device__ static constexpr double d1i(int k) { return O2_D1I[k]; }
     __host__ __device__ static constexpr double hb(int k) { return O2_H[k]; }
 };
+template <> struct Op<6> {
+    static constexpr int R0 = O6_R0, W = O6_W, NB = O6_NB, HALF = 3, REACH = 6, D1W = O6_D1W;
+    __host__ __device__ static constexpr double d2c(int r, int m, int s) { return D2T6.t[r][m][s]; }
+    __host__ __device__ static constexpr double d1b(int r, int c) { return O6_D1B[r][c]; }
+    __host__ __device__ static constexpr double d1i(int k) { return O6_D1I[k]; }
+    __host__ __device__ static constexpr double hb(int k) { return O6_H[k]; }
+};
+
+// h (D1 u)_i at an interior point from the values at offsets +-1 .. +-H:
+// sum_o d1i(H + o) (u(+o) - u(-o)); at(o) returns the value at offset o
+template <int ORD, typename T, typename F>
+__device__ __forceinline__ T d1_sym(F&& at) {
+    using O = Op<ORD>;
+    T acc = static_cast<T>(O::d1i(O::HALF + 1)) * (at(1) - at(-1));
+#pragma unroll
+    for (int o = 2; o <= O::HALF; ++o) acc += static_cast<T>(O::d1i(O::HALF + o)) * (at(o) - at(-o));
+    return acc;
+}
 
 // weight of u_{i+2} - u_{i-2} in the interior first derivative (0 at order 2)
 template <int ORD>
@@ -99,12 +117,14 @@ __host__ __device__ constexpr double d1_outer() {
 // closure table entries with runtime indices
 template <int ORD>
 __device__ __forceinline__ double table_d2c(int r, int m, int s) {
-    if constexpr (ORD == 4) return D2T4.t[r][m][s];
+    if constexpr (ORD == 6) return D2T6.t[r][m][s];
+    else if constexpr (ORD == 4) return D2T4.t[r][m][s];
     else return D2T2.t[r][m][s];
 }
 template <int ORD>
 __device__ __forceinline__ double table_d1b(int r, int c) {
-    if constexpr (ORD == 4) return O4_D1B[r][c];
+    if constexpr (ORD == 6) return O6_D1B[r][c];
+    else if constexpr (ORD == 4) return O4_D1B[r][c];
     else return O2_D1B[r][c];
 }
 
@@ -189,7 +209,7 @@ template <int ORD, int RR, typename F>
 __device__ __forceinline__ void d1_closure_foreach(bool lo, int n, F&& f) {
     using O = Op<ORD>;
 #pragma unroll
-    for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < O::D1W; ++c)
         if (O::d1b(RR, c) != 0.0) f(lo ? c : n - 1 - c, lo ? O::d1b(RR, c) : -O::d1b(RR, c));
 }
 
@@ -223,11 +243,25 @@ __device__ __forceinline__ T d1_line(gcp<T> u, long st, int r, int n) {
     return acc;
 }
 
+template <typename T, int ORD>
+__device__ __forceinline__ void d2_weights(const T* b, T* k);
+template <typename T, int ORD>
+__device__ __forceinline__ T d2_edges(const T* k, const T* u);
+
 // h^2 (D2^FC(b) u)_r at an interior row; b, u point at the row.
 template <typename T, int ORD, typename PB, typename PU>
 __device__ __forceinline__ T d2_interior(PB b, PU u, long st) {
     const T u0 = u[0];
-    if constexpr (ORD == 4) {
+    if constexpr (ORD == 6) {
+        T bb[7], kk[6], uu[7];
+#pragma unroll
+        for (int o = 0; o < 7; ++o) {
+            bb[o] = b[(o - 3) * st];
+            uu[o] = u[(o - 3) * st];
+        }
+        d2_weights<T, 6>(bb, kk);
+        return d2_edges<T, 6>(kk, uu);
+    } else if constexpr (ORD == 4) {
         const T bm2 = b[-2 * st], bm1 = b[-st], b0 = b[0], bp1 = b[st], bp2 = b[2 * st];
         const T s6 = T(1) / T(6), e8 = T(0.125), hf = T(0.5);
         const T km2 = s6 * bm1 - e8 * (bm2 + b0);
@@ -245,7 +279,16 @@ __device__ __forceinline__ T d2_interior(PB b, PU u, long st) {
 // u_m - u_0 for m = -H..-1, 1..H, from b on the 2H+1 points of the row.
 template <typename T, int ORD>
 __device__ __forceinline__ void d2_weights(const T* b, T* k) {
-    if constexpr (ORD == 4) {
+    if constexpr (ORD == 6) {
+        // weights of u_{i+m} - u_i, m = -3, -2, -1, 1, 2, 3, from b_{i-3} .. b_{i+3}
+        const T a = T(11) / T(360), e = T(0.025), f = T(0.05), g = T(0.3), c7 = T(0.175), c17 = T(0.425);
+        k[0] = a * (b[0] + b[3]) - e * (b[1] + b[2]);
+        k[1] = g * b[2] - f * (b[0] + b[4]) - c7 * (b[1] + b[3]);
+        k[2] = e * (b[0] + b[5]) + g * (b[1] + b[4]) + c17 * (b[2] + b[3]);
+        k[3] = e * (b[1] + b[6]) + g * (b[2] + b[5]) + c17 * (b[3] + b[4]);
+        k[4] = g * b[4] - f * (b[2] + b[6]) - c7 * (b[3] + b[5]);
+        k[5] = a * (b[3] + b[6]) - e * (b[4] + b[5]);
+    } else if constexpr (ORD == 4) {
         const T s6 = T(1) / T(6), e8 = T(0.125), hf = T(0.5);
         k[0] = s6 * b[1] - e8 * (b[0] + b[2]);
         k[1] = s6 * (b[0] + b[3]) + hf * (b[1] + b[2]);
@@ -259,7 +302,11 @@ __device__ __forceinline__ void d2_weights(const T* b, T* k) {
 }
 template <typename T, int ORD>
 __device__ __forceinline__ T d2_edges(const T* k, const T* u) {
-    if constexpr (ORD == 4) {
+    if constexpr (ORD == 6) {
+        const T u0 = u[3];
+        return k[0] * (u[0] - u0) + k[1] * (u[1] - u0) + k[2] * (u[2] - u0) + k[3] * (u[4] - u0) +
+               k[4] * (u[5] - u0) + k[5] * (u[6] - u0);
+    } else if constexpr (ORD == 4) {
         const T u0 = u[2];
         return k[0] * (u[0] - u0) + k[1] * (u[1] - u0) + k[2] * (u[3] - u0) + k[3] * (u[4] - u0);
     } else {
@@ -274,6 +321,18 @@ __device__ __forceinline__ T d2_closure(gcp<T> b, gcp<T> u, long st, bool lo, in
     using O = Op<ORD>;
     const T ur = u[(long)(lo ? RR : n - 1 - RR) * st];
     T acc = 0;
+    if constexpr (ORD == 6) {
+        // the order-6 closure rows are 12 wide: a loop over the table keeps
+        // the frame kernels small (they run at setup and on the frame band only)
+        for (int m = 0; m < O::W; ++m) {
+            if (m == RR) continue;
+            T cf = 0;
+#pragma unroll 4
+            for (int s = 0; s < O::W; ++s) cf += static_cast<T>(table_d2c<ORD>(RR, m, s)) * b[(long)(lo ? s : n - 1 - s) * st];
+            acc += cf * (u[(long)(lo ? m : n - 1 - m) * st] - ur);
+        }
+        return acc;
+    }
 #pragma unroll
     for (int m = 0; m < O::W; ++m) {
         if (m == RR) continue;
@@ -321,7 +380,8 @@ __device__ __forceinline__ T wide_line(gcp<T> b, gcp<T> u, long st, int r, int n
 
 template <typename T, int ORD>
 __device__ __forceinline__ T second_line(bool wide, gcp<T> b, gcp<T> u, long st, int r, int n) {
-    return wide ? wide_line<T, ORD>(b, u, st, r, n) : d2_line<T, ORD>(b, u, st, r, n);
+    if constexpr (ORD == 6) return d2_line<T, ORD>(b, u, st, r, n);   // the wide operator is built for orders 2, 4
+    else return wide ? wide_line<T, ORD>(b, u, st, r, n) : d2_line<T, ORD>(b, u, st, r, n);
 }
 
 // -------------------------------------------------- volume at one point
@@ -1107,8 +1167,6 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
     constexpr int NX = PASS == PASS_RK2 ? (SPLIT ? 2 : 4) : 0;   // state words read back per point
     constexpr int NWAVE = SPLIT ? 2 : 1;
     constexpr int R = Frame<ORD>::R;
-    constexpr T C1 = static_cast<T>(O::d1i(HF + 1));
-    constexpr T C2 = static_cast<T>(d1_outer<ORD>());
     __shared__ T s_xw[NWAVE][NW][NS][64];
     __shared__ T s_bw[NWAVE][3][64];
     __shared__ T s_gw[NWAVE][NS][64];
@@ -1233,11 +1291,6 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
     const T i11 = ih1 * ih1, i22 = ih2 * ih2, i12 = ih1 * ih2;
     const T dt = static_cast<T>(B.dt);
 
-    // interior first derivative (times h) from the four neighbours
-    auto d1 = [&](T um2, T um1, T up1, T up2) -> T {
-        if constexpr (HF == 2) return C1 * (up1 - um1) + C2 * (up2 - um2);
-        else return C1 * (up1 - um1);
-    };
     // loads for output row j: the leading row j + H of the windows and the
     // per-point operands of row j, issued one row ahead of their use
     auto load_lead = [&](int j, Lead<T, NS, NX>& L) {
@@ -1283,9 +1336,10 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int x = 2 * f + q;
-                w1[q] = d1(HF > 1 ? s_x[s][x][lane - 2 < 0 ? 0 : lane - 2] : T(0),
-                           s_x[s][x][lane - 1 < 0 ? 0 : lane - 1], s_x[s][x][lane + 1 > 63 ? 63 : lane + 1],
-                           HF > 1 ? s_x[s][x][lane + 2 > 63 ? 63 : lane + 2] : T(0));
+                w1[q] = d1_sym<ORD, T>([&](int o) {
+                    const int l = lane + o;
+                    return s_x[s][x][l < 0 ? 0 : (l > 63 ? 63 : l)];
+                });
             }
             ew[2 * f][s] = mw[0][s] * w1[0] + mw[2][s] * w1[1];
             ew[2 * f + 1][s] = mw[1][s] * w1[0] + mw[3][s] * w1[1];
@@ -1372,8 +1426,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
                 T w2[2];
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    w2[q] = d1(HF > 1 ? wcol[q][0] : T(0), wcol[q][HF - 1], wcol[q][HF + 1],
-                               HF > 1 ? wcol[q][NW - 1] : T(0));
+                    w2[q] = d1_sym<ORD, T>([&](int o) { return wcol[q][HF + o]; });
                     wc[2 * f + q] = wcol[q][HF];
                 }
                 s_g[2 * f][lane] = mw[0][s0] * w2[0] + mw[1][s0] * w2[1];
@@ -1421,11 +1474,11 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
         T L[NF][2];
 #pragma unroll
         for (int x = 0; x < NS; ++x) {
-            const int lm2 = lane - 2 < 0 ? 0 : lane - 2, lm1 = lane - 1 < 0 ? 0 : lane - 1;
-            const int lp1 = lane + 1 > 63 ? 63 : lane + 1, lp2 = lane + 2 > 63 ? 63 : lane + 2;
-            const T ag = d1(HF > 1 ? s_g[x][lm2] : T(0), s_g[x][lm1], s_g[x][lp1], HF > 1 ? s_g[x][lp2] : T(0));
-            const T ae = d1(HF > 1 ? ew[x][K % NW] : T(0), ew[x][(K + HF - 1) % NW], ew[x][(K + HF + 1) % NW],
-                            HF > 1 ? ew[x][(K + 2 * HF) % NW] : T(0));
+            const T ag = d1_sym<ORD, T>([&](int o) {
+                const int l = lane + o;
+                return s_g[x][l < 0 ? 0 : (l > 63 ? 63 : l)];
+            });
+            const T ae = d1_sym<ORD, T>([&](int o) { return ew[x][(K + HF + o) % NW]; });
             L[x >> 1][x & 1] = lx[x >> 1][x & 1] + (ag + ae) * i12;
         }
         // (6) data, pass arithmetic, stores
@@ -1524,6 +1577,10 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
         if constexpr (NW > 3) {
             step(std::integral_constant<int, 3 % NW>{}, j0 + 3);
             step(std::integral_constant<int, 4 % NW>{}, j0 + 4);
+        }
+        if constexpr (NW > 5) {
+            step(std::integral_constant<int, 5 % NW>{}, j0 + 5);
+            step(std::integral_constant<int, 6 % NW>{}, j0 + 6);
         }
     }
 }

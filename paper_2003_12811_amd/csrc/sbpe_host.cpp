@@ -24,33 +24,44 @@
 namespace sbpe {
 
 // ------------------------------------------------------------- 1-D tables
-static int nb_of(int order) { return order == 4 ? O4_NB : O2_NB; }
+static int nb_of(int order) { return order == 6 ? O6_NB : order == 4 ? O4_NB : O2_NB; }
+// closure depth of D2^FC, columns of a D1 closure row, and the frame width
+static int r0_of(int order) { return order == 6 ? O6_R0 : order == 4 ? O4_R0 : O2_R0; }
+static int frame_of(int order) { return order == 6 ? Frame<6>::R : order == 4 ? Frame<4>::R : Frame<2>::R; }
+// fewest points per direction of a block (closures of both ends apart)
+static int min_points(int order) { return order == 6 ? 19 : order == 4 ? 13 : 6; }
+constexpr int D1W_MAX = 9;
 
 double norm_weight(int order, int n, int k) {
     const int nb = nb_of(order);
-    const double* H = order == 4 ? O4_H : O2_H;
+    const double* H = order == 6 ? O6_H : order == 4 ? O4_H : O2_H;
     if (k < nb) return H[k];
     if (k > n - 1 - nb) return H[n - 1 - k];
     return 1.0;
 }
 
-// row r of the dimensionless D1: start column and weights (up to 6)
-static int d1_row(int order, int r, int n, int& start, double w[6]) {
+// closure row r of the dimensionless D1 (first `cols` columns)
+static double d1_closure(int order, int r, int c) {
+    return order == 6 ? O6_D1B[r][c] : order == 4 ? O4_D1B[r][c] : O2_D1B[r][c];
+}
+
+// row r of the dimensionless D1: start column and weights (up to D1W_MAX)
+static int d1_row(int order, int r, int n, int& start, double w[D1W_MAX]) {
     const int nb = nb_of(order);
-    const double(*B)[6] = order == 4 ? O4_D1B : O2_D1B;
+    const int cols = order == 6 ? O6_D1W : 6;
     if (r < nb) {
         start = 0;
-        for (int c = 0; c < 6; ++c) w[c] = B[r][c];
-        return 6;
+        for (int c = 0; c < cols; ++c) w[c] = d1_closure(order, r, c);
+        return cols;
     }
     if (r > n - 1 - nb) {
         const int rr = n - 1 - r;
-        start = n - 6;
-        for (int k = 0; k < 6; ++k) w[k] = -B[rr][5 - k];
-        return 6;
+        start = n - cols;
+        for (int k = 0; k < cols; ++k) w[k] = -d1_closure(order, rr, cols - 1 - k);
+        return cols;
     }
-    const int half = order == 4 ? 2 : 1;
-    const double* I = order == 4 ? O4_D1I : O2_D1I;
+    const int half = order / 2;
+    const double* I = order == 6 ? O6_D1I : order == 4 ? O4_D1I : O2_D1I;
     start = r - half;
     for (int k = 0; k < 2 * half + 1; ++k) w[k] = I[k];
     return 2 * half + 1;
@@ -60,7 +71,7 @@ void dense_d1(int order, int n, double* D) {
     std::fill(D, D + (size_t)n * n, 0.0);
     for (int r = 0; r < n; ++r) {
         int s0;
-        double w[6];
+        double w[D1W_MAX];
         const int len = d1_row(order, r, n, s0, w);
         for (int k = 0; k < len; ++k)
             if (s0 + k >= 0 && s0 + k < n) D[(size_t)r * n + s0 + k] += w[k];
@@ -68,7 +79,11 @@ void dense_d1(int order, int n, double* D) {
 }
 
 void derive_d2_closure(int order, double* T) {
-    if (order == 4) {
+    if (order == 6) {
+        for (int r = 0; r < O6_R0; ++r)
+            for (int m = 0; m < O6_W; ++m)
+                for (int s = 0; s < O6_W; ++s) T[((size_t)r * O6_W + m) * O6_W + s] = D2T6.t[r][m][s];
+    } else if (order == 4) {
         for (int r = 0; r < O4_R0; ++r)
             for (int m = 0; m < O4_W; ++m)
                 for (int s = 0; s < O4_W; ++s) T[((size_t)r * O4_W + m) * O4_W + s] = D2T4.t[r][m][s];
@@ -83,7 +98,7 @@ void derive_d2_closure(int order, double* T) {
 static void d1_apply(int order, int n, double h, const double* u, long st, double* out, long ost) {
     for (int r = 0; r < n; ++r) {
         int s0;
-        double w[6];
+        double w[D1W_MAX];
         const int len = d1_row(order, r, n, s0, w);
         double acc = 0.0;
         for (int k = 0; k < len; ++k) acc += w[k] * u[(long)(s0 + k) * st];
@@ -476,7 +491,7 @@ static long frame_index(const HostBlock& B, int R, int i, int j) {
 }
 
 static sbpe_status build_plan(sbpe_ctx* c) {
-    const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
+    const int R = frame_of(c->order);
     const int nb = (int)c->blocks.size();
     // interior tiles: 64 lanes, of which the central 64 - 2 * half-width are written
     const int tile_w = TILE_LANES - 2 * (c->order / 2);
@@ -881,7 +896,7 @@ static int default_frame_loop(int dtype) { return dtype == SBPE_F32 ? 4 : 2; }
 sbpe_status sbpe_create(int device, void* stream, int dtype, int order, double beta, sbpe_ctx_t* out) {
     if (!out) return fail(nullptr, SBPE_EINVAL, "out is NULL");
     if (dtype != SBPE_F64 && dtype != SBPE_F32) return fail(nullptr, SBPE_EINVAL, "dtype must be SBPE_F64 or SBPE_F32");
-    if (order != 2 && order != 4) return fail(nullptr, SBPE_EINVAL, "order must be 2 or 4");
+    if (order != 2 && order != 4 && order != 6) return fail(nullptr, SBPE_EINVAL, "order must be 2, 4 or 6");
     if (!(beta >= 1.0)) return fail(nullptr, SBPE_EINVAL, "beta must be >= 1 (Theorem 2)");
     sbpe_ctx* c = new sbpe_ctx;
     c->device = device;
@@ -975,7 +990,7 @@ sbpe_status sbpe_add_block(sbpe_ctx_t c, int n1, int n2, const double* X1, const
                            const double* C10, int* block_id) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
-    const int nmin = c->order == 4 ? 13 : 6;
+    const int nmin = min_points(c->order);
     if (n1 < nmin || n2 < nmin) return fail(c, SBPE_EINVAL, "block too small for the operator order");
     // the kernels address a field with 32-bit byte offsets and the frame operator
     // encodes a partner point in 28 bits: at most 2^28 points per block
@@ -1023,6 +1038,8 @@ sbpe_status sbpe_set_operator(sbpe_ctx_t c, int op) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (c->finalized) return fail(c, SBPE_ESTATE, "context already finalized");
     if (op != SBPE_OP_NARROW && op != SBPE_OP_WIDE) return fail(c, SBPE_EINVAL, "operator must be narrow or wide");
+    if (op == SBPE_OP_WIDE && c->order == 6)
+        return fail(c, SBPE_EINVAL, "the wide-stencil operator is built for orders 2 and 4");
     c->op = op;
     return SBPE_OK;
 }
@@ -1189,18 +1206,23 @@ sbpe_status sbpe_add_receivers(sbpe_ctx_t c, int block, int n, const double* x1,
 // whose window (offsets -5 .. 5) holds every row.  Two probes with constant
 // fields give the row sums.  The result is checked against the frame kernel
 // on a random field.
-static int probe_window(int i, int n, int color, int P) {
+static int probe_window(int i, int n, int color, int P, int r0) {
     const int back = (P - 1) / 2;
-    int lo = i < 6 ? 0 : (i > n - 7 ? n - P : i - back);
+    int lo = i < r0 ? 0 : (i > n - 1 - r0 ? n - P : i - back);
     lo = std::max(0, std::min(lo, std::max(0, n - P)));
     const int p = lo + ((color - lo % P) % P + P) % P;
     return p < n ? p : -1;
 }
 
 static sbpe_status assemble_frame(sbpe_ctx* c) {
-    const int P = (c->op == SBPE_OP_WIDE && c->order == 4) ? 11 : 9;
-    const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
-    const int reach = c->order == 4 ? 4 : 2;
+    // order 6: closure rows reach columns 0..11, so every frame row fits a
+    // window of 13 (offsets -6 .. 6 away from the ends)
+    const int P = c->order == 6 ? 13 : (c->op == SBPE_OP_WIDE && c->order == 4) ? 11 : 9;
+    const int R = frame_of(c->order);
+    const int r0 = r0_of(c->order);
+    // points next to a face that the displacement / interface SAT reaches (the
+    // nonzeros of the first D1 row)
+    const int reach = c->order == 6 ? 6 : c->order == 4 ? 4 : 2;
     const int nb = (int)c->blocks.size();
     if (nb > MAX_APPLY_BLOCKS) return SBPE_OK;     // general frame kernel
     const size_t es = esize(c);
@@ -1308,7 +1330,7 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
         const int bp = pi / (2 * P * P), comp = (pi / (P * P)) % 2, cy = (pi / P) % P, cx = pi % P;
         const HostBlock& H = c->blocks[b];
         if (b == bp) {
-            const int ii = probe_window(i, H.n1, cx, P), jj = probe_window(j, H.n2, cy, P);
+            const int ii = probe_window(i, H.n1, cx, P, r0), jj = probe_window(j, H.n2, cy, P, r0);
             if (ii < 0 || jj < 0) return false;
             col = 2 * (jj * H.n1 + ii) + comp;
             return true;
@@ -1330,7 +1352,7 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
                 ip = tp;
                 jp = F.pface == 2 ? 0 : Pb.n2 - 1;
             }
-            const int ii = probe_window(ip, Pb.n1, cx, P), jj = probe_window(jp, Pb.n2, cy, P);
+            const int ii = probe_window(ip, Pb.n1, cx, P, r0), jj = probe_window(jp, Pb.n2, cy, P, r0);
             if (ii >= 0 && jj >= 0) {
                 col = -1 - ((f << 29) | (comp << 28) | (jj * Pb.n1 + ii));
                 return true;
@@ -1584,8 +1606,16 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
     sbpe_status s = build_plan(c);
     if (s) return s;
     if (!c->host_only) {
-        s = assemble_frame(c);
-        if (s) return s;
+        // SBPE_FRAME=stencil leaves the frame operator unassembled: every sweep
+        // then runs the frame band with the stencil kernel on the second
+        // stream (a measurement switch; contexts with dissipative faces, which
+        // only the assembled operator applies, always assemble it)
+        const char* fe = std::getenv("SBPE_FRAME");
+        const bool stencil = fe && std::strcmp(fe, "stencil") == 0 && !c->dissipative;
+        if (!stencil) {
+            s = assemble_frame(c);
+            if (s) return s;
+        }
     }
     c->finalized = true;
     return SBPE_OK;
@@ -1877,7 +1907,7 @@ sbpe_status sbpe_plan_info(sbpe_ctx_t c, long long* info) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (!c->finalized) return fail(c, SBPE_ESTATE, "context not finalized");
     if (!info) return fail(c, SBPE_EINVAL, "NULL info");
-    const int R = c->order == 4 ? Frame<4>::R : Frame<2>::R;
+    const int R = frame_of(c->order);
     long long ip = 0, fp = 0;
     for (const auto& B : c->blocks) {
         ip += (long long)(B.n1 - 2 * R) * (B.n2 - 2 * R);
@@ -1893,23 +1923,36 @@ sbpe_status sbpe_plan_info(sbpe_ctx_t c, long long* info) {
 }
 
 sbpe_status sbpe_host_d1_line(int order, int n, const double* u, double* out) {
-    if ((order != 2 && order != 4) || n < (order == 4 ? 13 : 6) || !u || !out)
+    if ((order != 2 && order != 4 && order != 6) || n < min_points(order) || !u || !out)
         return fail(nullptr, SBPE_EINVAL, "bad arguments");
     d1_apply(order, n, 1.0 / (n - 1), u, 1, out, 1);
     return SBPE_OK;
 }
 
 sbpe_status sbpe_host_d2fc_line(int order, int n, const double* b, const double* u, double* out) {
-    if ((order != 2 && order != 4) || n < (order == 4 ? 13 : 6) || !b || !u || !out)
+    if ((order != 2 && order != 4 && order != 6) || n < min_points(order) || !b || !u || !out)
         return fail(nullptr, SBPE_EINVAL, "bad arguments");
-    const int R0 = order == 4 ? O4_R0 : O2_R0, W = order == 4 ? O4_W : O2_W;
+    const int R0 = r0_of(order), W = order == 6 ? O6_W : order == 4 ? O4_W : O2_W;
     std::vector<double> T((size_t)R0 * W * W);
     derive_d2_closure(order, T.data());
     const double ih2 = double(n - 1) * double(n - 1);
     for (int r = 0; r < n; ++r) {
         double acc = 0.0;
         if (r >= R0 && r <= n - 1 - R0) {
-            if (order == 4) {
+            if (order == 6) {
+                // interior row of h^2 D2(b) in edge form, b and u on offsets -3 .. 3
+                const double* B = b + r;
+                const double* U = u + r;
+                const double k[6] = {
+                    11.0 / 360 * (B[-3] + B[0]) - (B[-2] + B[-1]) / 40,
+                    -(B[-3] + B[1]) / 20 + 0.3 * B[-1] - 7.0 / 40 * (B[-2] + B[0]),
+                    (B[-3] + B[2]) / 40 + 0.3 * (B[-2] + B[1]) + 17.0 / 40 * (B[-1] + B[0]),
+                    (B[-2] + B[3]) / 40 + 0.3 * (B[-1] + B[2]) + 17.0 / 40 * (B[0] + B[1]),
+                    -(B[-1] + B[3]) / 20 + 0.3 * B[1] - 7.0 / 40 * (B[0] + B[2]),
+                    11.0 / 360 * (B[0] + B[3]) - (B[1] + B[2]) / 40};
+                const int off[6] = {-3, -2, -1, 1, 2, 3};
+                for (int e = 0; e < 6; ++e) acc += k[e] * (U[off[e]] - U[0]);
+            } else if (order == 4) {
                 const double* B = b + r;
                 const double* U = u + r;
                 const double km2 = B[-1] / 6 - 0.125 * (B[-2] + B[0]);
@@ -1997,7 +2040,7 @@ extern "C" {
 sbpe_status sbpe_batch_create(int device, void* stream, int dtype, int order, sbpe_batch_t* out) {
     if (!out) return bfail(nullptr, SBPE_EINVAL, "out is NULL");
     if (dtype != SBPE_F64 && dtype != SBPE_F32) return bfail(nullptr, SBPE_EINVAL, "bad dtype");
-    if (order != 2 && order != 4) return bfail(nullptr, SBPE_EINVAL, "order must be 2 or 4");
+    if (order != 2 && order != 4 && order != 6) return bfail(nullptr, SBPE_EINVAL, "order must be 2, 4 or 6");
     int n = 0;
     if (device < 0 || hipGetDeviceCount(&n) != hipSuccess || device >= n) return bfail(nullptr, SBPE_EHIP, "no such HIP device");
     if (hipSetDevice(device) != hipSuccess) return bfail(nullptr, SBPE_EHIP, "hipSetDevice failed");
@@ -2040,6 +2083,8 @@ sbpe_status sbpe_batch_add(sbpe_batch_t b, sbpe_ctx_t c, int nsteps, double dt) 
     if (!b->members.empty() && c->op != b->op)
         return bfail(b, SBPE_EINVAL, "context operator (narrow or wide) differs from the batch members'");
     if (nsteps <= 0 || !(dt > 0) || !std::isfinite(dt)) return bfail(b, SBPE_EINVAL, "bad nsteps or dt");
+    if (!c->frame_sp)
+        return bfail(b, SBPE_EINVAL, "batches sweep the assembled frame operator, which this context does not hold");
     // time functions for all its steps, receiver rows for all its steps
     sbpe_status s = fill_tau(c, nsteps, c->t, dt);
     if (s) return bfail(b, s, c->err);
@@ -2236,6 +2281,7 @@ extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, 
     if (s) return s;
     if (c->dissipative)
         return fail(c, SBPE_EINVAL, "coefficient gradients with dissipative faces are not supported (the scheme is not self-adjoint)");
+    if (c->order == 6) return fail(c, SBPE_EINVAL, "coefficient gradients are built for orders 2 and 4");
     const int nb = (int)c->blocks.size();
     if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "at most 16 blocks");
     if (!z || !y || !a || !gc || !grt) return fail(c, SBPE_EINVAL, "NULL pointer array");

@@ -1,0 +1,7 @@
+// Interior and one-launch sweep kernels of precision F32, order 6.
+#include "sbpe_launch_impl.h"
+
+namespace sbpe {
+template void Launch<float, 6>::interior(const PassArgs&, int, hipStream_t);
+template void Launch<float, 6>::pass(const PassArgs&, int, int, hipStream_t);
+}  // namespace sbpe

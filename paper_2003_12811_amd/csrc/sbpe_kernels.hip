@@ -72,9 +72,11 @@ template <typename F>
 static void with_launch(int dtype, int order, F&& f) {
     if (dtype == 0) {
         if (order == 4) f(Launch<double, 4>{});
+        else if (order == 6) f(Launch<double, 6>{});
         else f(Launch<double, 2>{});
     } else {
         if (order == 4) f(Launch<float, 4>{});
+        else if (order == 6) f(Launch<float, 6>{});
         else f(Launch<float, 2>{});
     }
 }
@@ -115,12 +117,15 @@ int launch_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt
 int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
                   int npartial, double* result_dev, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 g(npartial), bl(256);
     if (dtype == 0) {
-        if (order == 4) hipLaunchKernelGGL((k_energy_partial<double, 4>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
-        else hipLaunchKernelGGL((k_energy_partial<double, 2>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
+        if (order == 4) hipLaunchKernelGGL((k_energy_partial<double, 4>), g, bl, 0, s, blocks_dev, nblocks, partial_dev);
+        else if (order == 6) hipLaunchKernelGGL((k_energy_partial<double, 6>), g, bl, 0, s, blocks_dev, nblocks, partial_dev);
+        else hipLaunchKernelGGL((k_energy_partial<double, 2>), g, bl, 0, s, blocks_dev, nblocks, partial_dev);
     } else {
-        if (order == 4) hipLaunchKernelGGL((k_energy_partial<float, 4>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
-        else hipLaunchKernelGGL((k_energy_partial<float, 2>), dim3(npartial), dim3(256), 0, s, blocks_dev, nblocks, partial_dev);
+        if (order == 4) hipLaunchKernelGGL((k_energy_partial<float, 4>), g, bl, 0, s, blocks_dev, nblocks, partial_dev);
+        else if (order == 6) hipLaunchKernelGGL((k_energy_partial<float, 6>), g, bl, 0, s, blocks_dev, nblocks, partial_dev);
+        else hipLaunchKernelGGL((k_energy_partial<float, 2>), g, bl, 0, s, blocks_dev, nblocks, partial_dev);
     }
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, partial_dev, npartial, result_dev);
     return static_cast<int>(hipGetLastError());

@@ -1,6 +1,8 @@
 // Typed launchers of the large kernels.  Each (precision, order) pair is
-// instantiated in a translation unit of its own (sbpe_inst_<type>_o<order>.hip),
-// so the library builds in parallel; sbpe_kernels.hip dispatches to them.
+// instantiated in two translation units of its own, the sweeps
+// (sbpe_inst_<type>_o<order>_sweep.hip) and the frame and gradient kernels
+// (..._frame.hip), so the library builds in parallel; sbpe_kernels.hip
+// dispatches to them.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -29,5 +31,7 @@ extern template struct Launch<double, 4>;
 extern template struct Launch<double, 2>;
 extern template struct Launch<float, 4>;
 extern template struct Launch<float, 2>;
+extern template struct Launch<double, 6>;
+extern template struct Launch<float, 6>;
 
 }  // namespace sbpe

@@ -1,6 +1,6 @@
 // Definitions of the typed launchers (sbpe_launch.h); included only by the
-// sbpe_inst_*.hip translation units, each of which instantiates one
-// (precision, order) pair.
+// sbpe_inst_*.hip translation units, each of which instantiates some of the
+// members of one (precision, order) pair.
 #pragma once
 #include "sbpe_device.h"
 #include "sbpe_launch.h"
@@ -83,16 +83,28 @@ static void launch_frame_sp_t(const PassArgs& a, dim3 g, dim3 b, hipStream_t s) 
     else hipLaunchKernelGGL((k_frame_sp<T, ORD, PASS_RK2>), g, b, 0, s, a);
 }
 
+// The wide-stencil operator and the coefficient gradient are built for
+// orders 2 and 4 (the host refuses them at order 6).
 template <typename T, int ORD>
 void Launch<T, ORD>::interior(const PassArgs& a, int total_tiles, hipStream_t s) {
-    if (a.wide) launch_wide_t<T, ORD>(a, total_tiles, s);
-    else launch_march_t<T, ORD>(a, total_tiles, s);
+    if constexpr (ORD != 6) {
+        if (a.wide) {
+            launch_wide_t<T, ORD>(a, total_tiles, s);
+            return;
+        }
+    }
+    launch_march_t<T, ORD>(a, total_tiles, s);
 }
 
 template <typename T, int ORD>
 void Launch<T, ORD>::pass(const PassArgs& a, int total_tiles, int total_frame_wg, hipStream_t s) {
-    if (a.wide) launch_pass_wide_t<T, ORD>(a, total_tiles, total_frame_wg, s);
-    else launch_pass_t<T, ORD>(a, total_tiles, total_frame_wg, s);
+    if constexpr (ORD != 6) {
+        if (a.wide) {
+            launch_pass_wide_t<T, ORD>(a, total_tiles, total_frame_wg, s);
+            return;
+        }
+    }
+    launch_pass_t<T, ORD>(a, total_tiles, total_frame_wg, s);
 }
 
 template <typename T, int ORD>
@@ -107,7 +119,7 @@ void Launch<T, ORD>::frame_sp(const PassArgs& a, dim3 g, dim3 b, hipStream_t s) 
 
 template <typename T, int ORD>
 void Launch<T, ORD>::grad(GradArgs g, hipStream_t s) {
-    launch_grad_t<T, ORD>(g, s);
+    if constexpr (ORD != 6) launch_grad_t<T, ORD>(g, s);
 }
 
 }  // namespace sbpe

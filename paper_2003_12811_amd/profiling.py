@@ -8,7 +8,7 @@ Two kinds of summary are written as short Markdown files:
   per dispatch): every counter is scaled by what the same counter reads for a
   plain device-to-device copy of known size run in the same process
   (``bench.py --copy-probe-mib``), and the result is recorded per kernel
-  together with the SHA-256 of the kernel source it was measured on.
+  together with the SHA-256 of the device sources it was measured on.
 
 ``read_traffic`` returns the recorded bytes per launch only while the kernel
 source is unchanged, so a stale measurement is never reported.
@@ -24,13 +24,18 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, 'csrc', 'sbpe_kernels.hip')
+# every source that decides the device code of the kernels
+KERNEL_SOURCE = [os.path.join(HERE, 'csrc', f) for f in
+                 ('sbpe_device.h', 'sbpe_kernels.hip', 'sbpe_launch_impl.h', 'sbpe_tables.h', 'sbpe_internal.h')]
 COPY_KERNEL = '__amd_rocclr_copyBuffer'
 
 
-def source_hash(path=KERNEL_SOURCE):
-    with open(path, 'rb') as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def source_hash(paths=KERNEL_SOURCE):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, 'rb') as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def kernel_kind(name):

@@ -7,7 +7,7 @@ apply comparison also bounds the error on that band alone, in the max norm.
 import numpy as np
 
 TOL = {'f64': 1e-11, 'f32': 1e-5}
-BAND = {4: 6, 2: 2}       # closure rows of D2^FC plus the SAT reach: the frame width
+BAND = {6: 9, 4: 6, 2: 2}    # closure rows of D2^FC plus the SAT reach: the frame width
 
 
 def rel(a, b):

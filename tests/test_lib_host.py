@@ -30,8 +30,8 @@ def test_exports_every_declared_symbol():
     assert not missing, missing
 
 
-@pytest.mark.parametrize("order", [2, 4])
-@pytest.mark.parametrize("n", [13, 20, 41])
+@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("n", [19, 20, 41])
 def test_library_line_operators_match_oracle(order, n):
     rng = np.random.default_rng(n + order)
     b = 1.0 + rng.uniform(0, 1, n)
@@ -48,9 +48,9 @@ def _host_ctx(order=4, dtype=S.F64):
     return S.sbpe_create(-1, None, dtype, order, 1.0)
 
 
-@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("order", [2, 4, 6])
 def test_setup_matches_oracle(order):
-    n1, n2 = 19, 16
+    n1, n2 = (19, 16) if order < 6 else (23, 20)
     X1, X2 = W.grid(W.GaussianTopography(0.15, 0.2), n1, n2)
     rho, C10 = W.paper_random_material((n2, n1), 4)
     ctx = _host_ctx(order)
@@ -128,9 +128,22 @@ def test_error_codes():
     with pytest.raises(S.SbpeError):
         S.sbpe_create(-1, None, 7, 4, 1.0)
     with pytest.raises(S.SbpeError):
-        S.sbpe_create(-1, None, S.F64, 6, 1.0)
+        S.sbpe_create(-1, None, S.F64, 8, 1.0)
     with pytest.raises(S.SbpeError):
         S.sbpe_create(-1, None, S.F64, 4, 0.5)
+    # order 6: no wide-stencil operator; blocks of at least 19 points per direction
+    ctx = _host_ctx(6)
+    try:
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_set_operator(ctx, S.OP_WIDE)
+        assert e.value.code == S.EINVAL
+        Xs1, Xs2 = W.grid(W.Identity(), 18, 25)
+        rs, Cs = W.paper_random_material((25, 18), 2)
+        with pytest.raises(S.SbpeError) as e:
+            S.sbpe_add_block(ctx, Xs1, Xs2, rs, Cs)
+        assert e.value.code == S.EINVAL
+    finally:
+        S.sbpe_destroy(ctx)
 
 
 def test_set_operator_states():

@@ -324,6 +324,9 @@ def main():
     ap.add_argument('--cpu-steps', type=int, default=10)
     ap.add_argument('--cpu-dt', type=float, default=1e-4)
     ap.add_argument('--headline-only', action='store_true', help='only the headline workload')
+    ap.add_argument('--no-headline', action='store_true',
+                    help='skip the headline workload (profiler passes over the other sections); the '
+                         'printed line then carries the single-block FP64 result as its value')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-c2', action='store_true')
     ap.add_argument('--no-f32', action='store_true')
@@ -363,42 +366,45 @@ def main():
     from paper_2003_12811_amd import workloads as W
     fixed = ((args.tile_rows, args.frame_loop), {})
     n = args.n
-    log('building the headline workload: 2x2 blocks of %dx%d' % (n, n))
-    t0 = time.time()
-    sp3 = W.spec_c3(n=n)
-    log('  built in %.1f s' % (time.time() - t0))
-    log('headline, fp64')
-    r3, sh3, tb3 = section(sp3, 'f64', args, (10, 20), (1,), 20, 0, True, fixed)
-    k3 = dominant(r3)
-    pts3 = swept_points(r3['plan'])
-    line = {
-        "metric": "grid-point updates/s", "value": r3['updates_per_s'], "unit": "grid-point updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r3['ms_per_step'],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "2x2 conforming curvilinear blocks of %dx%d (one smooth global map), random smooth "
-                               "SPD C/rho (seed 0) with contrast 3 between neighbouring blocks, interface SATs, "
-                               "traction top/left and displacement bottom/right, 10 Hz Ricker force, 16 surface "
-                               "receivers, 4th-order SBP-SAT, RK4 CFL 0.5" % (n, n),
-                   "points": r3['points'], "dt": r3['dt'], "parallelism": "1 GPU",
-                   "tile_rows": sh3[0], "frame_loop": sh3[1], "launch_shape_ms_per_step": tb3},
-        "roofline": roofline(k3, r3['kernels'][k3][0], pts3, 8, traffic_key='%s/f64/o4' % k3, tile_rows=sh3[0],
-                             profile='c3_2049'),
-        "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]},
-    }
-    # (left out of profiler calibration runs, whose copy probe must stay the largest copy)
-    cbw = None if args.copy_probe_mib else copy_bandwidth()
-    if cbw:
-        log('copy bandwidth %.1f GB/s' % cbw)
-    if not args.no_f32:
-        log('headline workload, fp32')
-        r, sh, _ = section(sp3, 'f32', args, (10, 20), (1,), 20, 0, True, fixed)
-        k = dominant(r)
-        line["c3_f32"] = {"workload": "the headline workload in FP32", "value": r['updates_per_s'],
-                          "ms_per_step": r['ms_per_step'], "tile_rows": sh[0],
-                          "roofline": roofline(k, r['kernels'][k][0], swept_points(r['plan']), 4),
-                          "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
-    del sp3
+    line = {"metric": "grid-point updates/s", "unit": "grid-point updates/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic"}
+    cbw = None
+    if not args.no_headline:
+        log('building the headline workload: 2x2 blocks of %dx%d' % (n, n))
+        t0 = time.time()
+        sp3 = W.spec_c3(n=n)
+        log('  built in %.1f s' % (time.time() - t0))
+        log('headline, fp64')
+        r3, sh3, tb3 = section(sp3, 'f64', args, (10, 20), (1,), 20, 0, True, fixed)
+        k3 = dominant(r3)
+        pts3 = swept_points(r3['plan'])
+        line.update({
+            "value": r3['updates_per_s'], "ms_per_step": r3['ms_per_step'],
+            "config": {"workload": "2x2 conforming curvilinear blocks of %dx%d (one smooth global map), random smooth "
+                                   "SPD C/rho (seed 0) with contrast 3 between neighbouring blocks, interface SATs, "
+                                   "traction top/left and displacement bottom/right, 10 Hz Ricker force, 16 surface "
+                                   "receivers, 4th-order SBP-SAT, RK4 CFL 0.5" % (n, n),
+                       "points": r3['points'], "dt": r3['dt'], "parallelism": "1 GPU",
+                       "tile_rows": sh3[0], "frame_loop": sh3[1], "launch_shape_ms_per_step": tb3},
+            "roofline": roofline(k3, r3['kernels'][k3][0], pts3, 8, traffic_key='%s/f64/o4' % k3, tile_rows=sh3[0],
+                                 profile='c3_2049'),
+            "kernels_ms": {kk: v[0] for kk, v in r3['kernels'].items() if v[1]},
+        })
+        # (left out of profiler calibration runs, whose copy probe must stay the largest copy)
+        cbw = None if args.copy_probe_mib else copy_bandwidth()
+        if cbw:
+            log('copy bandwidth %.1f GB/s' % cbw)
+        if not args.no_f32:
+            log('headline workload, fp32')
+            r, sh, _ = section(sp3, 'f32', args, (10, 20), (1,), 20, 0, True, fixed)
+            k = dominant(r)
+            line["c3_f32"] = {"workload": "the headline workload in FP32", "value": r['updates_per_s'],
+                              "ms_per_step": r['ms_per_step'], "tile_rows": sh[0],
+                              "roofline": roofline(k, r['kernels'][k][0], swept_points(r['plan']), 4),
+                              "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
+        del sp3
+
     if not args.no_c2:
         log('building the single-block workload %dx%d' % (args.c2_n, args.c2_n))
         spec = W.spec_c2(n=args.c2_n)
@@ -446,6 +452,10 @@ def main():
                               "apply_roofline": roofline('interior_apply', r['apply_kernels']['interior_apply'][0],
                                                          swept_points(r['plan']), 8),
                               "kernels_ms": {kk: v[0] for kk, v in r['kernels'].items() if v[1]}}
+    if args.no_headline and "c2_f64" in line:
+        line.update(value=line["c2_f64"]["value"], ms_per_step=line["c2_f64"]["ms_per_step"],
+                    config={"workload": line["c2_f64"]["workload"], "parallelism": "1 GPU"},
+                    roofline=line["c2_f64"]["roofline"])
     if not args.no_serve:
         from paper_2003_12811_amd import serve
         log('served stream vs sequential plain solves')
@@ -462,8 +472,11 @@ def main():
         line["gradient"] = gradient_timing()
     if not args.no_cpu_baseline:
         log('cpu baseline (oracle, 1 thread, %d steps of 2x2 blocks of %d^2)' % (args.cpu_steps, args.cpu_n))
-        line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps, r3['dt'])
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps,
+                                            args.cpu_dt if args.no_headline else r3['dt'])
     # every roofline also against the measured copy bandwidth
+    if cbw is None and not args.copy_probe_mib:
+        cbw = copy_bandwidth()
     for sec in [line] + [line[k] for k in ("c3_f32", "c2_f64", "c2_f32", "wide", "order6") if k in line]:
         for key in ("roofline", "apply_roofline"):
             if key in sec and cbw:

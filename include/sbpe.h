@@ -228,6 +228,13 @@ sbpe_status sbpe_reserve_steps(sbpe_ctx_t ctx, int nsteps);
  * streams, or host threads) race and must be serialised by the caller. */
 sbpe_status sbpe_advance_noalloc(sbpe_ctx_t ctx, int nsteps, double dt);
 
+/* Device memory of the context: *held = bytes it holds now (coefficient
+ * fields, RK workspace, face data, frame operator, tables, receiver record),
+ * *peak = the most it has held at once (finalize's probing buffers
+ * included).  Caller-owned state buffers are not counted.  Either pointer
+ * may be NULL. */
+sbpe_status sbpe_device_bytes(sbpe_ctx_t ctx, long long* held, long long* peak);
+
 /* Current time of the bound state. */
 sbpe_status sbpe_get_time(sbpe_ctx_t ctx, double* t);
 

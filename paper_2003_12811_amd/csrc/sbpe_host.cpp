@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -211,6 +212,10 @@ struct sbpe_ctx {
     // kernel timing: pending (kind, start, stop) event records and sums
     bool frame_sp = false;          // frame rows run from the assembled operator
     double frame_check = -1.0;      // relative difference of the assembled operator to the frame kernel
+    // device memory held by the context: size of every allocation, their
+    // sum, and the largest sum so far (sbpe_device_bytes)
+    std::unordered_map<void*, size_t> dev_sizes;
+    size_t dev_held = 0, dev_peak = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -229,6 +234,31 @@ static sbpe_status fail(sbpe_ctx* c, sbpe_status code, const std::string& msg) {
 
 static size_t esize(const sbpe_ctx* c) { return c->dtype == SBPE_F64 ? 8 : 4; }
 
+// device allocations of a context, counted for sbpe_device_bytes
+template <typename P>
+static hipError_t dmalloc(sbpe_ctx* c, P** p, size_t bytes) {
+    void* v = nullptr;
+    const hipError_t e = hipMalloc(&v, bytes);
+    *p = static_cast<P*>(v);
+    if (e == hipSuccess) {
+        c->dev_sizes[v] = bytes;
+        c->dev_held += bytes;
+        c->dev_peak = std::max(c->dev_peak, c->dev_held);
+    }
+    return e;
+}
+
+static void dfree(sbpe_ctx* c, const void* p) {
+    if (!p) return;
+    void* v = const_cast<void*>(p);
+    auto it = c->dev_sizes.find(v);
+    if (it != c->dev_sizes.end()) {
+        c->dev_held -= it->second;
+        c->dev_sizes.erase(it);
+    }
+    (void)hipFree(v);
+}
+
 #define HIPCHECK(ctx, expr)                                                                       \
     do {                                                                                          \
         hipError_t e_ = (expr);                                                                   \
@@ -239,7 +269,7 @@ static size_t esize(const sbpe_ctx* c) { return c->dtype == SBPE_F64 ? 8 : 4; }
 // upload a double host array to device memory of the context dtype
 static sbpe_status upload(sbpe_ctx* c, const std::vector<double>& h, void** d) {
     const size_t n = h.size();
-    if (hipMalloc(d, n * esize(c)) != hipSuccess) return fail(c, SBPE_ENOMEM, "device allocation failed");
+    if (dmalloc(c, d, n * esize(c)) != hipSuccess) return fail(c, SBPE_ENOMEM, "device allocation failed");
     if (c->dtype == SBPE_F64) {
         HIPCHECK(c, hipMemcpy(*d, h.data(), n * 8, hipMemcpyHostToDevice));
     } else {
@@ -656,19 +686,19 @@ static sbpe_status build_plan(sbpe_ctx* c) {
     c->nitems = (int)items.size();
     c->nrecadj = (int)radj.size();
     if (!radj.empty()) {
-        HIPCHECK(c, hipMalloc(&c->d_recadj, radj.size() * sizeof(RecAdj)));
+        HIPCHECK(c, dmalloc(c, &c->d_recadj, radj.size() * sizeof(RecAdj)));
         HIPCHECK(c, hipMemcpy(c->d_recadj, radj.data(), radj.size() * sizeof(RecAdj), hipMemcpyHostToDevice));
     }
-    HIPCHECK(c, hipMalloc(&c->d_entries, flat.size() * sizeof(Entry)));
+    HIPCHECK(c, dmalloc(c, &c->d_entries, flat.size() * sizeof(Entry)));
     HIPCHECK(c, hipMemcpy(c->d_entries, flat.data(), flat.size() * sizeof(Entry), hipMemcpyHostToDevice));
-    HIPCHECK(c, hipMalloc(&c->d_tile_ranges, tr.size() * sizeof(Range)));
+    HIPCHECK(c, dmalloc(c, &c->d_tile_ranges, tr.size() * sizeof(Range)));
     HIPCHECK(c, hipMemcpy(c->d_tile_ranges, tr.data(), tr.size() * sizeof(Range), hipMemcpyHostToDevice));
-    HIPCHECK(c, hipMalloc(&c->d_frame_ranges, fr.size() * sizeof(Range)));
+    HIPCHECK(c, dmalloc(c, &c->d_frame_ranges, fr.size() * sizeof(Range)));
     HIPCHECK(c, hipMemcpy(c->d_frame_ranges, fr.data(), fr.size() * sizeof(Range), hipMemcpyHostToDevice));
-    HIPCHECK(c, hipMalloc(&c->d_items, items.size() * sizeof(TimeFn)));
+    HIPCHECK(c, dmalloc(c, &c->d_items, items.size() * sizeof(TimeFn)));
     HIPCHECK(c, hipMemcpy(c->d_items, items.data(), items.size() * sizeof(TimeFn), hipMemcpyHostToDevice));
     c->tau_cap = 1;
-    HIPCHECK(c, hipMalloc(&c->d_tau, (size_t)c->nitems * 3 * sizeof(double)));
+    HIPCHECK(c, dmalloc(c, &c->d_tau, (size_t)c->nitems * 3 * sizeof(double)));
     HIPCHECK(c, hipMemset(c->d_tau, 0, (size_t)c->nitems * 3 * sizeof(double)));
     for (int b = 0; b < nb; ++b) {
         BlockDesc& D = c->desc[b];
@@ -683,11 +713,11 @@ static sbpe_status build_plan(sbpe_ctx* c) {
         D.rec = nullptr;
         D.rec_stride = (long)c->receivers.size() * 16 * 2;
     }
-    HIPCHECK(c, hipMalloc(&c->d_desc, nb * sizeof(BlockDesc)));
+    HIPCHECK(c, dmalloc(c, &c->d_desc, nb * sizeof(BlockDesc)));
     HIPCHECK(c, hipMemcpy(c->d_desc, c->desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice));
     c->npartial = 1024;
-    HIPCHECK(c, hipMalloc(&c->d_epart, c->npartial * sizeof(double)));
-    HIPCHECK(c, hipMalloc(&c->d_eout, sizeof(double)));
+    HIPCHECK(c, dmalloc(c, &c->d_epart, c->npartial * sizeof(double)));
+    HIPCHECK(c, dmalloc(c, &c->d_eout, sizeof(double)));
     return SBPE_OK;
 }
 
@@ -845,15 +875,15 @@ static sbpe_status grow_receivers(sbpe_ctx* c, long steps) {
     if (nrec == 0 || steps <= c->rec_cap) return SBPE_OK;
     const long cap = std::max<long>(steps, 2 * c->rec_cap);
     double* nd = nullptr;
-    if (hipMalloc(&nd, cap * slots * sizeof(double)) != hipSuccess) return fail(c, SBPE_ENOMEM, "receiver buffer");
+    if (dmalloc(c, &nd, cap * slots * sizeof(double)) != hipSuccess) return fail(c, SBPE_ENOMEM, "receiver buffer");
     if (c->d_rec && c->rec_steps > 0 &&
         hipMemcpyAsync(nd, c->d_rec, c->rec_steps * slots * sizeof(double), hipMemcpyDeviceToDevice, c->stream) !=
             hipSuccess) {
-        (void)hipFree(nd);
+        dfree(c, nd);
         return fail(c, SBPE_EHIP, "receiver buffer copy");
     }
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    (void)hipFree(c->d_rec);
+    dfree(c, c->d_rec);
     c->d_rec = nd;
     c->rec_cap = cap;
     return SBPE_OK;
@@ -863,10 +893,10 @@ static sbpe_status grow_receivers(sbpe_ctx* c, long steps) {
 static sbpe_status grow_tau(sbpe_ctx* c, long steps) {
     if (steps <= c->tau_cap) return SBPE_OK;
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    (void)hipFree(c->d_tau);
+    dfree(c, c->d_tau);
     c->d_tau = nullptr;
     c->tau_cap = 0;     // a failed allocation leaves no table behind
-    if (hipMalloc(&c->d_tau, (size_t)steps * c->nitems * 3 * sizeof(double)) != hipSuccess)
+    if (dmalloc(c, &c->d_tau, (size_t)steps * c->nitems * 3 * sizeof(double)) != hipSuccess)
         return fail(c, SBPE_ENOMEM, "time-function table");
     c->tau_cap = steps;
     return SBPE_OK;
@@ -941,27 +971,27 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
     if (!c->host_only) {
         (void)hipStreamSynchronize(c->stream);
         for (auto& B : c->blocks) {
-            (void)hipFree(B.d_coef);
-            (void)hipFree(B.d_force);
-            (void)hipFree(B.d_a1);
-            (void)hipFree(B.d_a2);
+            dfree(c, B.d_coef);
+            dfree(c, B.d_force);
+            dfree(c, B.d_a1);
+            dfree(c, B.d_a2);
             for (int f = 0; f < 4; ++f)
-                for (int k = 0; k < 5; ++k) (void)hipFree(B.d_face[f][k]);
-            (void)hipFree(B.d_fr_rowptr);
-            (void)hipFree(B.d_fr_col);
-            (void)hipFree(B.d_fr_val);
-            (void)hipFree(B.d_fr_rsum);
+                for (int k = 0; k < 5; ++k) dfree(c, B.d_face[f][k]);
+            dfree(c, B.d_fr_rowptr);
+            dfree(c, B.d_fr_col);
+            dfree(c, B.d_fr_val);
+            dfree(c, B.d_fr_rsum);
         }
-        (void)hipFree(c->d_desc);
-        (void)hipFree(c->d_entries);
-        (void)hipFree(c->d_tile_ranges);
-        (void)hipFree(c->d_frame_ranges);
-        (void)hipFree(c->d_items);
-        (void)hipFree(c->d_recadj);
-        (void)hipFree(c->d_tau);
-        (void)hipFree(c->d_rec);
-        (void)hipFree(c->d_epart);
-        (void)hipFree(c->d_eout);
+        dfree(c, c->d_desc);
+        dfree(c, c->d_entries);
+        dfree(c, c->d_tile_ranges);
+        dfree(c, c->d_frame_ranges);
+        dfree(c, c->d_items);
+        dfree(c, c->d_recadj);
+        dfree(c, c->d_tau);
+        dfree(c, c->d_rec);
+        dfree(c, c->d_epart);
+        dfree(c, c->d_eout);
         for (auto e : c->ev_pool) (void)hipEventDestroy(e);
         (void)hipStreamSynchronize(c->side);
         (void)hipEventDestroy(c->ev_main);
@@ -1230,17 +1260,17 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
     sbpe_status st = SBPE_OK;
     auto cleanup = [&]() {
         for (int b = 0; b < nb; ++b) {
-            (void)hipFree(X[b]);
-            (void)hipFree(Y[b]);
-            (void)hipFree(G[b]);
+            dfree(c, X[b]);
+            dfree(c, Y[b]);
+            dfree(c, G[b]);
             (void)hipHostFree(Hh[b]);
         }
     };
     for (int b = 0; b < nb; ++b) {
         const long np = c->blocks[b].np();
         const int fn = c->desc[b].frame_n;
-        if (hipMalloc(&X[b], 2 * np * es) != hipSuccess || hipMalloc(&Y[b], 2 * np * es) != hipSuccess ||
-            hipMalloc(&G[b], 2 * (size_t)std::max(fn, 1) * es) != hipSuccess ||
+        if (dmalloc(c, &X[b], 2 * np * es) != hipSuccess || dmalloc(c, &Y[b], 2 * np * es) != hipSuccess ||
+            dmalloc(c, &G[b], 2 * (size_t)std::max(fn, 1) * es) != hipSuccess ||
             hipHostMalloc(&Hh[b], 2 * (size_t)std::max(fn, 1) * es) != hipSuccess) {
             cleanup();
             return fail(c, SBPE_ENOMEM, "frame operator assembly buffers");
@@ -1407,8 +1437,8 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
             }
         }
         if (bad) break;
-        if (hipMalloc(&H.d_fr_rowptr, rp.size() * sizeof(int)) != hipSuccess ||
-            hipMalloc(&H.d_fr_col, cl.size() * sizeof(int)) != hipSuccess) {
+        if (dmalloc(c, &H.d_fr_rowptr, rp.size() * sizeof(int)) != hipSuccess ||
+            dmalloc(c, &H.d_fr_col, cl.size() * sizeof(int)) != hipSuccess) {
             cleanup_all();
             return fail(c, SBPE_ENOMEM, "frame operator");
         }
@@ -1453,7 +1483,7 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
                 return st;
             }
             HIPCHECK(c, hipMemcpy(X[b], tmp, 2 * np * es, hipMemcpyDeviceToDevice));
-            (void)hipFree(tmp);
+            dfree(c, tmp);
         }
         double scale = 0.0, err = 0.0;
         for (int pass = 0; pass < 2; ++pass) {
@@ -1554,8 +1584,8 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
                 s = upload(c, JF, &B.d_force);
                 if (s) return s;
             }
-            if (hipMalloc(&B.d_a1, 2 * np * esize(c)) != hipSuccess ||
-                hipMalloc(&B.d_a2, 2 * np * esize(c)) != hipSuccess)
+            if (dmalloc(c, &B.d_a1, 2 * np * esize(c)) != hipSuccess ||
+                dmalloc(c, &B.d_a2, 2 * np * esize(c)) != hipSuccess)
                 return fail(c, SBPE_ENOMEM, "device allocation failed");
             for (int f = 0; f < 4; ++f) {
                 HostFace& F = B.face[f];
@@ -1841,6 +1871,13 @@ sbpe_status sbpe_reserve_steps(sbpe_ctx_t c, int nsteps) {
     return grow_receivers(c, c->rec_steps + nsteps);
 }
 
+sbpe_status sbpe_device_bytes(sbpe_ctx_t c, long long* held, long long* peak) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (held) *held = (long long)c->dev_held;
+    if (peak) *peak = (long long)c->dev_peak;
+    return SBPE_OK;
+}
+
 sbpe_status sbpe_get_time(sbpe_ctx_t c, double* t) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (!t) return fail(c, SBPE_EINVAL, "NULL t");
@@ -2093,12 +2130,12 @@ sbpe_status sbpe_batch_add(sbpe_batch_t b, sbpe_ctx_t c, int nsteps, double dt) 
     if (nrec > 0 && c->rec_steps + nsteps > c->rec_cap) {
         const long cap = c->rec_steps + nsteps;
         double* nd = nullptr;
-        if (hipMalloc(&nd, cap * slots * sizeof(double)) != hipSuccess) return bfail(b, SBPE_ENOMEM, "receiver buffer");
+        if (dmalloc(c, &nd, cap * slots * sizeof(double)) != hipSuccess) return bfail(b, SBPE_ENOMEM, "receiver buffer");
         if (c->d_rec && c->rec_steps > 0)
             BHIPCHECK(b, hipMemcpyAsync(nd, c->d_rec, c->rec_steps * slots * sizeof(double), hipMemcpyDeviceToDevice,
                                         c->stream));
         BHIPCHECK(b, hipStreamSynchronize(c->stream));
-        (void)hipFree(c->d_rec);
+        dfree(c, c->d_rec);
         c->d_rec = nd;
         c->rec_cap = cap;
     }

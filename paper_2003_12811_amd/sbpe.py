@@ -58,6 +58,7 @@ _PROTOS = {
     'sbpe_bind_state': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _D],
     'sbpe_advance': [_P, _I, _D],
     'sbpe_reserve_steps': [_P, _I],
+    'sbpe_device_bytes': [_P, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)],
     'sbpe_advance_noalloc': [_P, _I, _D],
     'sbpe_get_time': [_P, _DP],
     'sbpe_read_receivers': [_P, _DP, _I, _IP],
@@ -253,6 +254,12 @@ def sbpe_advance(ctx, nsteps, dt):
 
 def sbpe_advance_noalloc(ctx, nsteps, dt):
     _check(ctx, lib().sbpe_advance_noalloc(ctx, nsteps, dt))
+
+
+def sbpe_device_bytes(ctx):
+    held, peak = ctypes.c_longlong(), ctypes.c_longlong()
+    _check(ctx, lib().sbpe_device_bytes(ctx, ctypes.byref(held), ctypes.byref(peak)))
+    return held.value, peak.value
 
 
 def sbpe_reserve_steps(ctx, nsteps):

@@ -31,12 +31,32 @@ from . import sbpe as S
 from . import workloads as W
 
 WORDS_RESIDENT = 11 + 4 + 4   # coefficients, RK workspace (a1, a2), state (u, v) per point
+WORDS_PROBE = 4               # finalize's probe and result fields (freed before the shot runs)
+FRAME_R = {2: 2, 4: 6, 6: 9}  # depth of the boundary band (frame) per order
+PROBES = {2: 81, 4: 81, 6: 169}   # probing colours per component: a frame row has at most 2 x this many entries
 
 
-def shot_bytes(n, nrec, steps, dtype):
-    """Device memory of one admitted shot (fields, state, receiver rows)."""
+def shot_bytes(n, nrec, steps, dtype, order=4):
+    """Upper bound of the device memory a shot needs while it is set up and
+    run: resident fields and state, finalize's probe fields, the frame
+    operator (at most one entry per probe and row), face data, tables and
+    receiver rows.  Admission reserves it; once the shot is set up the
+    reservation is replaced by the library's exact figure
+    (sbpe_device_bytes) plus the state tensors."""
     w = 8 if dtype == 'f64' else 4
-    return WORDS_RESIDENT * n * n * w + steps * nrec * 16 * 2 * 8 + 64 * n * 8
+    R = FRAME_R[order]
+    frame = 2 * R * n + 2 * R * max(0, n - 2 * R)
+    csr = 2 * frame * (2 * PROBES[order] * (w + 4) + 4 + 2 * w)
+    faces = 4 * n * 16 * w
+    return ((WORDS_RESIDENT + WORDS_PROBE) * n * n * w + csr + faces + steps * nrec * 16 * 2 * 8
+            + steps * 64 * 3 * 8 + (1 << 20))
+
+
+def exact_bytes(shot):
+    """Device memory of a set-up shot: the library's (sbpe_device_bytes) and
+    its two state tensors."""
+    held, _ = S.sbpe_device_bytes(shot.ctx)
+    return held + 2 * shot.u.numel() * shot.u.element_size()
 
 
 def make_requests(nshots, rate, sizes, steps, seed=0, nrec=64):
@@ -138,7 +158,7 @@ class Server:
                 req = todo.get()
                 if req is None:
                     return
-                need = shot_bytes(req['n'], req['nrec'], req['steps'], self.dtype)
+                need = shot_bytes(req['n'], req['nrec'], req['steps'], self.dtype, self.order)
                 while True:           # wait for HBM budget
                     with lock:
                         if used[0] + need <= self.budget or used[0] == 0:
@@ -148,7 +168,13 @@ class Server:
                 try:
                     req['t_setup'] = now()
                     shot = Shot(req, self.spec_fn(req), self.dtype, self.device, self.aux)
-                    shot.need = need
+                    # the reservation becomes the shot's exact device memory
+                    # (its receiver rows for every step are reserved at admission)
+                    S.sbpe_reserve_steps(shot.ctx, req['steps'])
+                    exact = exact_bytes(shot)
+                    with lock:
+                        used[0] += exact - need
+                    shot.need = exact
                     ready.put(shot)
                 except Exception as e:     # reported, never silently dropped
                     with lock:

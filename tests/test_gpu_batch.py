@@ -221,3 +221,31 @@ def test_large_batch_two_stream_sweeps_equal_plain_advance():
         S.sbpe_batch_destroy(bt)
         for s in plain + batched:
             s.close()
+
+
+@pytest.mark.parametrize("dtype,order", [('f32', 4), ('f64', 4), ('f64', 6)])
+def test_device_bytes_and_admission_bound(dtype, order):
+    """sbpe_device_bytes counts the context's device memory: at least the 11
+    coefficient fields and the RK workspace (15 words per point), the frame
+    operator on top, more at finalize's peak (probe fields); the server's
+    admission bound covers the peak plus the state tensors, and a shot's
+    exact figure is what the server books once it is set up."""
+    st = _stream()
+    n, steps, nrec = 129, 40, 8
+    req = dict(id=0, arrival=0.0, n=n, seed=3, steps=steps, nrec=nrec)
+    shot = serve.Shot(req, W.spec_shot(n, 3, order=order, nrec=nrec), dtype, 0, st)
+    try:
+        w = 8 if dtype == 'f64' else 4
+        held0, peak0 = S.sbpe_device_bytes(shot.ctx)
+        assert peak0 >= held0 + 4 * n * n * w        # the probe fields were held on top during finalize
+        S.sbpe_reserve_steps(shot.ctx, steps)
+        held, peak = S.sbpe_device_bytes(shot.ctx)
+        exact = serve.exact_bytes(shot)
+        bound = serve.shot_bytes(n, nrec, steps, dtype, order)
+        say('  %s order %d: held %d, peak %d, exact with state %d, admission bound %d' % (
+            dtype, order, held, peak, exact, bound))
+        assert held >= 15 * n * n * w and held > held0
+        assert exact == held + 4 * n * n * w
+        assert bound >= peak + 4 * n * n * w
+    finally:
+        shot.close()

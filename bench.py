@@ -255,6 +255,42 @@ def dominant(res):
     return kind
 
 
+def c1_latency(reps=5):
+    """Time to solution of the plain-method workload: the 65^2 Cartesian block
+    with constant anisotropic C, manufactured solution and traction SATs,
+    advanced from t = 0 to t = 0.5 at CFL 0.5 in FP64 (setup, then the solve
+    from resident inputs; median of reps solves after one warm-up solve)."""
+    import numpy as np
+    import torch
+    from paper_2003_12811_amd import workloads as W
+    from paper_2003_12811_amd.solver import Solver
+    spec = W.spec_c1(n=65)
+    t0 = time.perf_counter()
+    sol = Solver(spec, 'f64')
+    setup_s = time.perf_counter() - t0
+    nsteps = int(np.ceil(spec['T'] / sol.dt_cfl(spec['cfl']) - 1e-12))
+    dt = spec['T'] / nsteps
+    u0 = spec['mms']['u']
+    sol.reserve(nsteps)
+    times = []
+    for k in range(reps + 1):
+        sol.set_state([u0], None, 0.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sol.advance(nsteps, dt)
+        sol.synchronize()
+        times.append(time.perf_counter() - t1)
+    ug, _ = sol.state_numpy()
+    sol.close()
+    exact = u0 * np.cos(spec['mms']['omega'] * spec['T'])
+    solve = sorted(times[1:])[len(times[1:]) // 2]
+    return {"workload": "65x65 Cartesian block, constant anisotropic C, manufactured solution, traction SATs "
+                        "with analytic data and forcing, 4th order, RK4 at CFL 0.5 to t = 0.5, FP64",
+            "steps": nsteps, "setup_s": round(setup_s, 4), "solve_ms": round(1e3 * solve, 3),
+            "ms_per_step": round(1e3 * solve / nsteps, 4),
+            "rel_l2_error_vs_exact": float(np.linalg.norm(ug[0] - exact) / np.linalg.norm(exact))}
+
+
 def cpu_baseline(n, steps, dt):
     """Oracle RK4 steps on the host (single thread), in a child process."""
     env = dict(os.environ, OMP_NUM_THREADS='1', OPENBLAS_NUM_THREADS='1', MKL_NUM_THREADS='1')
@@ -339,6 +375,7 @@ def main():
     ap.add_argument('--cpu-baseline-child', action='store_true')
     ap.add_argument('--no-serve', action='store_true')
     ap.add_argument('--no-gradient', action='store_true')
+    ap.add_argument('--no-c1', action='store_true')
     # the serving workload (256 shots of 257^2 .. 2049^2, 1500 steps, 20/s) scaled down to a
     # bench-length run with the same offered load: 64 shots, 300 steps, 100/s
     ap.add_argument('--serve-shots', type=int, default=64)
@@ -466,7 +503,13 @@ def main():
         if "c2_f32" in line:
             sv["plain_f32_updates_per_s"] = line["c2_f32"]["value"]
             sv["served_over_plain_f32"] = sv["served"]["updates_per_s"] / line["c2_f32"]["value"]
+            # the device alone: batched sweeps timed with HIP events, against
+            # the plain FP32 rate of one 1025^2 solve
+            sv["served_device_over_plain_f32"] = sv["served"]["device_updates_per_s"] / line["c2_f32"]["value"]
         line["serving"] = sv
+    if not args.no_c1:
+        log('plain-method workload (65^2, to t = 0.5): time to solution')
+        line["c1_latency"] = c1_latency()
     if not args.no_gradient:
         log('misfit gradient (513^2, 2000 steps, checkpoints every 100)')
         line["gradient"] = gradient_timing()

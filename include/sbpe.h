@@ -228,6 +228,23 @@ sbpe_status sbpe_reserve_steps(sbpe_ctx_t ctx, int nsteps);
  * streams, or host threads) race and must be serialised by the caller. */
 sbpe_status sbpe_advance_noalloc(sbpe_ctx_t ctx, int nsteps, double dt);
 
+/* Device memory from the caller.  Every device allocation of the context
+ * (coefficient fields, RK workspace, face data, frame operator, tables,
+ * receiver record) is then alloc(bytes, user), and is given back with
+ * release(ptr, user); the context keeps no hipMalloc'ed memory of its own
+ * (the no-allocation advance's scratch array aside).  alloc returns device
+ * memory of the context's device aligned to 256 bytes, or NULL (the call
+ * that needed it then fails with SBPE_ENOMEM).  Before release the context
+ * waits for its streams, so the memory may be reused at once, on any stream.
+ * Both callbacks run on the thread that makes the library call.  Set them
+ * before sbpe_finalize, before the context allocates anything (SBPE_ESTATE
+ * otherwise); both NULL restores hipMalloc/hipFree.  For callers whose memory
+ * comes from a framework's allocator (PyTorch's caching allocator: retiring
+ * a context then returns its memory without a device-wide hipFree). */
+typedef void* (*sbpe_alloc_fn)(size_t bytes, void* user);
+typedef void (*sbpe_release_fn)(void* ptr, void* user);
+sbpe_status sbpe_set_allocator(sbpe_ctx_t ctx, sbpe_alloc_fn alloc, sbpe_release_fn release, void* user);
+
 /* Device memory of the context: *held = bytes it holds now (coefficient
  * fields, RK workspace, face data, frame operator, tables, receiver record),
  * *peak = the most it has held at once (finalize's probing buffers

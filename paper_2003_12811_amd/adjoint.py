@@ -23,7 +23,8 @@ gradient is the exact derivative of the discrete map (up to rounding):
 
 ``MisfitGradient`` wraps one forward/adjoint pair for a fixed time step (the
 step must not depend on the parameters being differentiated), and
-``SeismicMisfit`` exposes it as a ``torch.autograd.Function``.
+``SeismicMisfit`` exposes it as a ``torch.autograd.Function``: its forward
+runs the forward pass (with checkpoints) only, its backward the adjoint.
 """
 import numpy as np
 
@@ -194,16 +195,26 @@ def _torch_function():
             mg = MisfitGradient(sp, nsteps, dt, d_obs=d_obs, checkpoint_every=checkpoint_every)
             try:
                 J = mg.forward()
-                g_rho, g_c10 = mg.gradient()
-            finally:
+            except Exception:
                 mg.close()
-            ctx.save_for_backward(torch.from_numpy(g_rho), torch.from_numpy(g_c10))
+                raise
+            # the adjoint pass runs only when a gradient is asked for; the
+            # forward run's checkpoints and residuals stay on the device until then
+            ctx.mg = mg if (ctx.needs_input_grad[0] or ctx.needs_input_grad[1]) else None
+            if ctx.mg is None:
+                mg.close()
             return torch.tensor(J, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gJ):
-            g_rho, g_c10 = ctx.saved_tensors
-            return gJ * g_rho, gJ * g_c10, None, None, None, None, None
+            mg, ctx.mg = ctx.mg, None
+            if mg is None:
+                return None, None, None, None, None, None, None
+            try:
+                g_rho, g_c10 = mg.gradient()
+            finally:
+                mg.close()
+            return (gJ * torch.from_numpy(g_rho), gJ * torch.from_numpy(g_c10), None, None, None, None, None)
 
     return SeismicMisfit
 

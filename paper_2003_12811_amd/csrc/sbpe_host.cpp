@@ -216,6 +216,10 @@ struct sbpe_ctx {
     // sum, and the largest sum so far (sbpe_device_bytes)
     std::unordered_map<void*, size_t> dev_sizes;
     size_t dev_held = 0, dev_peak = 0;
+    // caller-provided device memory (sbpe_set_allocator), or hipMalloc/hipFree
+    sbpe_alloc_fn ualloc = nullptr;
+    sbpe_release_fn urelease = nullptr;
+    void* uarg = nullptr;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -238,7 +242,18 @@ static size_t esize(const sbpe_ctx* c) { return c->dtype == SBPE_F64 ? 8 : 4; }
 template <typename P>
 static hipError_t dmalloc(sbpe_ctx* c, P** p, size_t bytes) {
     void* v = nullptr;
-    const hipError_t e = hipMalloc(&v, bytes);
+    hipError_t e;
+    if (c->ualloc) {
+        v = bytes > 0 ? c->ualloc(bytes, c->uarg) : nullptr;
+        e = (v || bytes == 0) ? hipSuccess : hipErrorOutOfMemory;
+        if ((reinterpret_cast<uintptr_t>(v) & 255u) != 0) {   // the kernels assume 256-byte alignment
+            c->urelease(v, c->uarg);
+            v = nullptr;
+            e = hipErrorInvalidValue;
+        }
+    } else {
+        e = hipMalloc(&v, bytes);
+    }
     *p = static_cast<P*>(v);
     if (e == hipSuccess) {
         c->dev_sizes[v] = bytes;
@@ -256,14 +271,23 @@ static void dfree(sbpe_ctx* c, const void* p) {
         c->dev_held -= it->second;
         c->dev_sizes.erase(it);
     }
-    (void)hipFree(v);
+    if (c->urelease) {
+        // hipFree waits for the device; memory handed back to the caller may
+        // be reused at once, so every launch that can still read it must end
+        (void)hipStreamSynchronize(c->stream);
+        if (c->side) (void)hipStreamSynchronize(c->side);
+        c->urelease(v, c->uarg);
+    } else {
+        (void)hipFree(v);
+    }
 }
 
 #define HIPCHECK(ctx, expr)                                                                       \
     do {                                                                                          \
         hipError_t e_ = (expr);                                                                   \
         if (e_ != hipSuccess)                                                                     \
-            return fail(ctx, SBPE_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? SBPE_ENOMEM : SBPE_EHIP,                 \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                       \
     } while (0)
 
 // upload a double host array to device memory of the context dtype
@@ -970,6 +994,7 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
     if (c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch: sbpe_batch_remove it first");
     if (!c->host_only) {
         (void)hipStreamSynchronize(c->stream);
+        (void)hipStreamSynchronize(c->side);
         for (auto& B : c->blocks) {
             dfree(c, B.d_coef);
             dfree(c, B.d_force);
@@ -1003,6 +1028,17 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
 }
 
 const char* sbpe_last_error(sbpe_ctx_t c) { return c ? c->err.c_str() : g_static_err.c_str(); }
+
+sbpe_status sbpe_set_allocator(sbpe_ctx_t c, sbpe_alloc_fn alloc, sbpe_release_fn release, void* user) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (!alloc != !release) return fail(c, SBPE_EINVAL, "allocate and release callbacks must be given together");
+    if (c->finalized || !c->dev_sizes.empty())
+        return fail(c, SBPE_ESTATE, "the allocator is set before the context allocates (before sbpe_finalize)");
+    c->ualloc = alloc;
+    c->urelease = release;
+    c->uarg = user;
+    return SBPE_OK;
+}
 
 sbpe_status sbpe_voigt_to_c10(const double* V, size_t npts, double* C10) {
     if (!V || !C10) return fail(nullptr, SBPE_EINVAL, "NULL array");

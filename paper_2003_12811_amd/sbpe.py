@@ -35,7 +35,12 @@ _I = ctypes.c_int
 _DP = ctypes.POINTER(ctypes.c_double)
 _IP = ctypes.POINTER(ctypes.c_int)
 
+# device-memory callbacks of sbpe_set_allocator
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _PROTOS = {
+    'sbpe_set_allocator': [_P, ALLOC_FN, RELEASE_FN, _P],
     'sbpe_create': [_I, _P, _I, _I, _D, ctypes.POINTER(_P)],
     'sbpe_destroy': [_P],
     'sbpe_add_block': [_P, _I, _I, _DP, _DP, _DP, _DP, _IP],
@@ -353,6 +358,16 @@ def sbpe_get_kernel_timing(ctx):
     cnt = (ctypes.c_int * 6)()
     _check(ctx, lib().sbpe_get_kernel_timing(ctx, _dp(ms), cnt))
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def sbpe_set_allocator(ctx, alloc, release):
+    """Route the context's device allocations through alloc(nbytes) -> pointer
+    (0 on failure) and release(pointer).  Returns the ctypes callback objects,
+    which the caller keeps alive until the context is destroyed."""
+    a = ALLOC_FN(lambda n, user: alloc(n) or None)
+    r = RELEASE_FN(lambda ptr, user: release(ptr))
+    _check(ctx, lib().sbpe_set_allocator(ctx, a, r, None))
+    return a, r
 
 
 def sbpe_plan_info(ctx):

@@ -29,6 +29,7 @@ import numpy as np
 
 from . import sbpe as S
 from . import workloads as W
+from .solver import TorchMemory
 
 WORDS_RESIDENT = 11 + 4 + 4   # coefficients, RK workspace (a1, a2), state (u, v) per point
 WORDS_PROBE = 4               # finalize's probe and result fields (freed before the shot runs)
@@ -68,14 +69,18 @@ def make_requests(nshots, rate, sizes, steps, seed=0, nrec=64):
 
 
 class Shot:
-    """A library context for one shot, with its state tensors on the device."""
+    """A library context for one shot, with its state tensors on the device.
+    The context's device memory comes from PyTorch's caching allocator, so a
+    retired shot's memory returns to the cache without a device-wide free."""
 
     def __init__(self, req, spec, dtype, device, stream):
         import torch
         self.req = req
+        self.memory = TorchMemory(torch, torch.device('cuda', device))
         self.ctx = S.sbpe_create(device, stream.cuda_stream, S.F64 if dtype == 'f64' else S.F32,
                                  spec['order'], 1.0)
         try:
+            self._callbacks = S.sbpe_set_allocator(self.ctx, self.memory.alloc, self.memory.release)
             for b in spec['blocks']:
                 bid = S.sbpe_add_block(self.ctx, b['X1'], b['X2'], b['rho'], b['C10'])
                 for f, (kind, g, tfn, tp, U) in enumerate(b['bc']):
@@ -98,6 +103,7 @@ class Shot:
             S.sbpe_bind_state(self.ctx, [self.u.data_ptr()], [self.v.data_ptr()], 0.0)
         except Exception:
             S.sbpe_destroy(self.ctx)
+            self.ctx = None
             raise
         self.nrec = sum(len(r[1]) for r in spec.get('receivers', []))
         self.points = sum(b['X1'].size for b in spec['blocks'])
@@ -211,6 +217,9 @@ class Server:
         members = {}
         n_left = len(reqs)            # shots not yet handed to the reaper or failed
         self.launched_points_steps = 0
+        # device time of the batched sweeps: HIP events on the batch stream
+        # around every chunk (the batch joins its side stream into it)
+        chunk_events = []
         while n_left > 0:
             t = now()
             while pending and pending[0]['arrival'] <= t:
@@ -232,7 +241,12 @@ class Server:
                 continue
             info = S.sbpe_batch_info(self.batch)
             k = min(self.chunk, info['min_remaining'])
+            e0 = self.torch.cuda.Event(enable_timing=True)
+            e1 = self.torch.cuda.Event(enable_timing=True)
+            e0.record(self.stream)
             S.sbpe_batch_advance(self.batch, k)
+            e1.record(self.stream)
+            chunk_events.append((e0, e1))
             self.launched_points_steps += info['points'] * k
             for s in [s for s in members.values() if S.sbpe_batch_remaining(self.batch, s.ctx) == 0]:
                 S.sbpe_batch_remove(self.batch, s.ctx)
@@ -248,26 +262,52 @@ class Server:
         wall = now()
         lat = np.array([r['latency'] for r in done]) if done else np.zeros(1)
         total_pts = sum(r['points'] * r['steps'] for r in done)
+        device_s = 1e-3 * sum(a.elapsed_time(b) for a, b in chunk_events)
         return dict(shots=done, failed=failed, wall_s=wall,
                     p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                    shots_per_s=len(done) / wall, updates_per_s=total_pts / wall)
+                    shots_per_s=len(done) / wall, updates_per_s=total_pts / wall,
+                    device_s=device_s, device_updates_per_s=self.launched_points_steps / device_s if device_s else 0.0)
 
 
 def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_receivers=True, log=None):
     """The same shots, in arrival order, one at a time with sbpe_advance
-    (each starts when it has arrived and the previous one has finished)."""
+    (each starts when it has arrived and the previous one has finished).  A
+    worker thread sets up the next shot while the current one runs, as the
+    server's setup workers do, so both forms overlap host setup with device
+    work and differ only in how the device is used."""
     import torch
-    stream = torch.cuda.Stream(device=device)
     reqs = [dict(r) for r in sorted(requests, key=lambda r: r['arrival'])]
     start = time.perf_counter()
     now = lambda: time.perf_counter() - start
-    for r in reqs:
-        wait = r['arrival'] - now()
-        if wait > 0:
-            time.sleep(wait)
-        shot = Shot(r, spec_fn(r), dtype, device, stream)
+    built = queue.Queue(maxsize=1)
+
+    def builder():
+        for r in reqs:
+            wait = r['arrival'] - now()
+            if wait > 0:
+                time.sleep(wait)
+            try:
+                st = torch.cuda.Stream(device=device)    # the shot's own stream
+                shot = Shot(r, spec_fn(r), dtype, device, st)
+                shot.stream = st
+                built.put((r, shot))
+            except Exception as e:       # reported by the consumer
+                built.put((r, e))
+
+    th = threading.Thread(target=builder, daemon=True)
+    th.start()
+    device_s = 0.0
+    for _ in reqs:
+        r, shot = built.get()
+        if isinstance(shot, Exception):
+            raise shot
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(shot.stream)
         S.sbpe_advance(shot.ctx, r['steps'], shot.dt)
+        e1.record(shot.stream)
         rec = shot.receivers()
+        device_s += 1e-3 * e0.elapsed_time(e1)
         r['t_done'] = now()
         r['latency'] = r['t_done'] - r['arrival']
         r['points'] = shot.points
@@ -276,15 +316,17 @@ def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_r
         shot.close()
         if log and r['id'] % 16 == 0:
             log('sequential: shot %d done at %.2f s' % (r['id'], r['t_done']))
+    th.join()
     wall = now()
     lat = np.array([r['latency'] for r in reqs])
     total_pts = sum(r['points'] * r['steps'] for r in reqs)
     return dict(shots=reqs, wall_s=wall, p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                shots_per_s=len(reqs) / wall, updates_per_s=total_pts / wall)
+                shots_per_s=len(reqs) / wall, updates_per_s=total_pts / wall,
+                device_s=device_s, device_updates_per_s=total_pts / device_s if device_s else 0.0)
 
 
 def summarize(res):
-    keys = ('wall_s', 'p50_s', 'p99_s', 'shots_per_s', 'updates_per_s')
+    keys = ('wall_s', 'p50_s', 'p99_s', 'shots_per_s', 'updates_per_s', 'device_s', 'device_updates_per_s')
     return {k: res[k] for k in keys} | {'shots': len(res['shots'])}
 
 

@@ -15,10 +15,32 @@ def _torch():
     return torch
 
 
-class Solver:
-    """One context of the library built from a spec."""
+class TorchMemory:
+    """Device memory of a context from PyTorch's caching allocator: each
+    allocation is a uint8 tensor kept alive until the library releases it."""
 
-    def __init__(self, spec, dtype='f64', device=0, beta=1.0, stream=None, tile_rows=0):
+    def __init__(self, torch, device):
+        self.torch, self.device, self.live = torch, device, {}
+
+    def alloc(self, nbytes):
+        t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def release(self, ptr):
+        self.live.pop(ptr, None)
+
+    def nbytes(self):
+        return sum(t.numel() for t in self.live.values())
+
+
+class Solver:
+    """One context of the library built from a spec.  memory='torch' (the
+    default) takes the context's device memory from PyTorch's allocator,
+    memory='hip' lets the library call hipMalloc."""
+
+    def __init__(self, spec, dtype='f64', device=0, beta=1.0, stream=None, tile_rows=0, memory='torch'):
         torch = _torch()
         self.torch = torch
         self.spec = spec
@@ -27,9 +49,12 @@ class Solver:
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
+        self.memory = TorchMemory(torch, self.device) if memory == 'torch' else None
         self.ctx = S.sbpe_create(device, stream.cuda_stream, S.F64 if dtype == 'f64' else S.F32,
                                  spec['order'], beta)
         try:
+            if self.memory is not None:
+                self._callbacks = S.sbpe_set_allocator(self.ctx, self.memory.alloc, self.memory.release)
             if tile_rows:
                 S.sbpe_set_tile_rows(self.ctx, tile_rows)
             self._setup(spec)

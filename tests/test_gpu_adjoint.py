@@ -165,3 +165,28 @@ def test_autograd_function_matches():
     assert float(J) == pytest.approx(J2, rel=1e-12)
     assert np.allclose(rho.grad.numpy(), g_rho, rtol=0, atol=1e-14 * np.abs(g_rho).max())
     assert np.allclose(C10.grad.numpy(), g_c10, rtol=0, atol=1e-14 * np.abs(g_c10).max())
+
+
+def test_autograd_forward_runs_no_adjoint():
+    # the adjoint runs in backward only: a misfit evaluated without gradients
+    # (inputs that do not require them, or a backward never called) gives
+    # the same J and leaves no open context behind
+    import gc
+    import torch
+    n, nsteps = 33, 40
+    spec = W.spec_c5(n=n, nrec=6)
+    spec_obs = W.spec_c5(n=n, nrec=6, perturbed=True)
+    dt = _dt(spec)
+    d_obs = _observed(spec_obs, nsteps, dt)
+    rho = torch.tensor(spec['blocks'][0]['rho'])
+    C10 = torch.tensor(spec['blocks'][0]['C10'])
+    J = ADJ.seismic_misfit(rho, C10, spec, nsteps, dt, d_obs, 10)
+    rho_g = rho.clone().requires_grad_(True)
+    J1 = ADJ.seismic_misfit(rho_g, C10, spec, nsteps, dt, d_obs, 10)
+    assert float(J) == pytest.approx(float(J1), rel=1e-14)
+    assert J1.grad_fn is not None and J1.grad_fn.mg is not None
+    del J1
+    gc.collect()
+    J2 = ADJ.seismic_misfit(rho_g, C10, spec, nsteps, dt, d_obs, 10)
+    J2.backward()
+    assert rho_g.grad is not None and float(rho_g.grad.abs().max()) > 0

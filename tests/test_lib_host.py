@@ -280,3 +280,28 @@ def test_stiffness_psd_check_against_eigenvalues():
     V = np.array(W.VOIGT_C1)
     A = M.full_from_c10(W.voigt_to_c10(V)).reshape(4, 4)
     assert _finalize_status(A) == 0
+
+
+def test_allocator_states():
+    """Callbacks come in pairs and are set before the context allocates;
+    host-only contexts never call them."""
+    n = 15
+    X1, X2 = W.grid(W.Identity(), n, n)
+    rho, C10 = W.paper_random_material((n, n), 0)
+    calls = []
+    ctx = _host_ctx()
+    try:
+        import ctypes
+        lib = S.lib()
+        a = S.ALLOC_FN(lambda nb, u: calls.append(nb) or None)
+        r = S.RELEASE_FN(lambda p, u: calls.append(p))
+        assert lib.sbpe_set_allocator(ctx, a, S.RELEASE_FN(), None) == S.EINVAL
+        assert lib.sbpe_set_allocator(ctx, S.ALLOC_FN(), r, None) == S.EINVAL
+        S.sbpe_set_allocator(ctx, lambda nb: calls.append(nb) or 0, lambda p: calls.append(p))
+        assert lib.sbpe_set_allocator(ctx, S.ALLOC_FN(), S.RELEASE_FN(), None) == S.OK
+        S.sbpe_add_block(ctx, X1, X2, rho, C10)
+        S.sbpe_finalize(ctx)
+        assert lib.sbpe_set_allocator(ctx, a, r, None) == S.ESTATE
+    finally:
+        S.sbpe_destroy(ctx)
+    assert calls == []

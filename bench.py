@@ -397,7 +397,7 @@ def main():
         sys.exit(2)
     if args.headline_only:
         args.no_cpu_baseline = args.no_c2 = args.no_f32 = args.no_wide = args.no_order6 = True
-        args.no_serve = args.no_gradient = True
+        args.no_serve = args.no_gradient = args.no_c1 = True
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
     from paper_2003_12811_amd import workloads as W

@@ -320,7 +320,8 @@ sbpe_status sbpe_grad_to_physical(sbpe_ctx_t ctx, int block, const void* gc, con
                                   double* g_rho);
 
 /* y = sum_k coefs[k] x[k] elementwise over count values of the context dtype
- * (device pointers, 1 <= nterms <= 4, y may be one of the x[k]). */
+ * (device pointers, 1 <= nterms <= 6, y may be one of the x[k]); the sums are
+ * formed in FP64. */
 sbpe_status sbpe_lincomb(sbpe_ctx_t ctx, int nterms, const double* coefs, const void* const* x, void* y,
                          long long count);
 

@@ -65,9 +65,6 @@ class MisfitGradient:
     def _new(self):
         return self.torch.empty(self.shape, dtype=self.tdt, device=self.dev)
 
-    def _lin(self, coefs, xs, out):
-        S.sbpe_lincomb(self.sol.ctx, coefs, [x.data_ptr() for x in xs], out.data_ptr(), self.count)
-
     def _apply(self, x, t, homogeneous, out):
         S.sbpe_apply(self.sol.ctx, [x.data_ptr()], [out.data_ptr()], t, homogeneous)
 
@@ -100,7 +97,13 @@ class MisfitGradient:
             Yu_i = L kv_i (scaled variables),
         then uh <- uh + sum_i Yu_i and vh <- vh + sum_i ku_i.  The states of a
         checkpoint segment are recomputed with ``sbpe_advance``; every work
-        buffer is allocated once.
+        buffer is allocated once.  The buffers are laid out so that every
+        pair of combinations is one ``sbpe_lincomb`` over both halves:
+        stage i holds Z_i = (U_i, V_i, A_i) and M_i = (Yu_i, ku_i, kv_i), the
+        adjoint state W = (uh, vh), so that
+            (U_{i+1}, V_{i+1}) = (u, v) + dt c_{i+1} (V_i, A_i)  = Z_0[0:2] + dt c_{i+1} Z_i[1:3],
+            (ku_i, kv_i) = dt b_i W + dt c_{i+1} M_{i+1}[0:2],
+            W <- W + sum_i M_i[0:2].
         """
         torch = self.torch
         sol = self.sol
@@ -112,19 +115,17 @@ class MisfitGradient:
         res = torch.as_tensor(np.ascontiguousarray(self.residuals), dtype=torch.float64, device=self.dev)
         rstride = self.nrec * 2 * 8
         N = self.nsteps
-        new = self._new
-        uh, vh, yu, yv = new().zero_(), new().zero_(), new(), new()
-        U = [None] + [new() for _ in range(3)]
-        V = [None] + [new() for _ in range(3)]
-        A = [new() for _ in range(4)]
-        ku = [new() for _ in range(4)]
-        kv = [new() for _ in range(4)]
-        Yu = [new() for _ in range(4)]
-        seg_u = [new() for _ in range(self.K)]
-        seg_v = [new() for _ in range(self.K)]
-        lin = self._lin
+        triple = lambda: torch.empty((3,) + tuple(self.shape), dtype=self.tdt, device=self.dev)
+        W = torch.zeros((2,) + tuple(self.shape), dtype=self.tdt, device=self.dev)
+        Wn = torch.empty_like(W)
+        Z = [triple() for _ in range(4)]
+        M = [triple() for _ in range(4)]
+        seg_u = [self._new() for _ in range(self.K)]
+        seg_v = [self._new() for _ in range(self.K)]
+        n2c = 2 * self.count
+        lin = lambda coefs, xs, out: S.sbpe_lincomb(ctx, coefs, [x.data_ptr() for x in xs], out.data_ptr(), n2c)
         if self.nrec:
-            S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (N - 1) * rstride, [uh.data_ptr()], 1.0)
+            S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (N - 1) * rstride, [W[0].data_ptr()], 1.0)
         for (cu, cv, ct, c0) in reversed(self.checkpoints):
             k = min(self.K, N - c0)
             # the segment's states
@@ -137,33 +138,27 @@ class MisfitGradient:
                 seg_v[s_].copy_(sol.v[0])
             for s_ in range(k - 1, -1, -1):
                 n = c0 + s_                     # reversing the step from y_n to y_{n+1}
-                u, v, t = seg_u[s_], seg_v[s_], ct + s_ * h
+                t = ct + s_ * h
+                Z[0][0].copy_(seg_u[s_])
+                Z[0][1].copy_(seg_v[s_])
                 # stages of the step
-                U[0], V[0] = u, v
                 for i in range(4):
-                    self._apply(U[i], t + C_RK[i] * h, False, A[i])
+                    self._apply(Z[i][0], t + C_RK[i] * h, False, Z[i][2])
                     if i < 3:
-                        lin([1.0, C_RK[i + 1] * h], [u, V[i]], U[i + 1])
-                        lin([1.0, C_RK[i + 1] * h], [v, A[i]], V[i + 1])
+                        lin([1.0, C_RK[i + 1] * h], [Z[0], Z[i][1]], Z[i + 1])
                 # stage adjoints, last stage first
                 for i in range(3, -1, -1):
                     if i == 3:
-                        lin([h * B_RK[3]], [uh], ku[3])
-                        lin([h * B_RK[3]], [vh], kv[3])
+                        lin([h * B_RK[3]], [W], M[3][1])
                     else:
-                        lin([h * B_RK[i], h * C_RK[i + 1]], [uh, Yu[i + 1]], ku[i])
-                        lin([h * B_RK[i], h * C_RK[i + 1]], [vh, ku[i + 1]], kv[i])
-                    self._apply(kv[i], 0.0, True, Yu[i])
-                    S.sbpe_grad_accumulate(ctx, [kv[i].data_ptr()], [U[i].data_ptr()], [A[i].data_ptr()], 1.0,
-                                           t + C_RK[i] * h, False, [gc.data_ptr()], [grt.data_ptr()])
-                lin([1.0, 1.0, 1.0, 1.0], [uh, Yu[3], Yu[2], Yu[1]], yu)
-                lin([1.0, 1.0], [yu, Yu[0]], yu)
-                lin([1.0, 1.0, 1.0, 1.0], [vh, ku[3], ku[2], ku[1]], yv)
-                lin([1.0, 1.0], [yv, ku[0]], yv)
-                uh, yu = yu, uh
-                vh, yv = yv, vh
+                        lin([h * B_RK[i], h * C_RK[i + 1]], [W, M[i + 1]], M[i][1])
+                    self._apply(M[i][2], 0.0, True, M[i][0])
+                    S.sbpe_grad_accumulate(ctx, [M[i][2].data_ptr()], [Z[i][0].data_ptr()], [Z[i][2].data_ptr()],
+                                           1.0, t + C_RK[i] * h, False, [gc.data_ptr()], [grt.data_ptr()])
+                lin([1.0, 1.0, 1.0, 1.0, 1.0], [W, M[3], M[2], M[1], M[0]], Wn)
+                W, Wn = Wn, W
                 if n > 0 and self.nrec:
-                    S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (n - 1) * rstride, [uh.data_ptr()], 1.0)
+                    S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (n - 1) * rstride, [W[0].data_ptr()], 1.0)
         g10, grho = S.sbpe_grad_to_physical(ctx, 0, gc.data_ptr(), grt.data_ptr())
         return grho, g10
 

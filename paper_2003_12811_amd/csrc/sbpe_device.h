@@ -2354,17 +2354,19 @@ __global__ void __launch_bounds__(256) k_grad_int(GradArgs G) {
     ((gp<double>)grb)[p] += -al * h1 * h2 * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
 }
 
-// y = sum_k c_k x_k (elementwise; y may be one of the x_k)
+// y = sum_k c_k x_k (elementwise, at most LINCOMB_MAX terms; y may be one of the x_k)
+struct LincombArgs {
+    double c[LINCOMB_MAX];
+    const void* x[LINCOMB_MAX];
+};
 template <typename T>
-__global__ void __launch_bounds__(256) k_lincomb(int nterms, double c0, double c1, double c2, double c3,
-                                                 const T* x0, const T* x1, const T* x2, const T* x3, T* y,
-                                                 long count) {
+__global__ void __launch_bounds__(256) k_lincomb(int nterms, LincombArgs a, T* y, long count) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= count) return;
-    double acc = c0 * (double)x0[i];
-    if (nterms > 1) acc += c1 * (double)x1[i];
-    if (nterms > 2) acc += c2 * (double)x2[i];
-    if (nterms > 3) acc += c3 * (double)x3[i];
+    double acc = a.c[0] * (double)((const T*)a.x[0])[i];
+#pragma unroll
+    for (int k = 1; k < LINCOMB_MAX; ++k)
+        if (k < nterms) acc += a.c[k] * (double)((const T*)a.x[k])[i];
     y[i] = static_cast<T>(acc);
 }
 

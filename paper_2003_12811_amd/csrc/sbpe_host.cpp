@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -451,10 +452,10 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
 }
 
 // v_max^2 = max over xi of the largest eigenvalue of xi_i c_ijkl xi_k / rho~ at point p
-static double christoffel_lmax(const HostBlock& B, long p, double th) {
+// largest eigenvalue of the acoustic tensor over rho~ at point p, direction (cs, sn)
+static double christoffel_lmax_cs(const HostBlock& B, long p, double cs, double sn) {
     const long np = B.np();
     const double* q = B.coef.data();
-    const double cs = std::cos(th), sn = std::sin(th);
     // Gamma_jl = sum_ik xi_i c_ijkl xi_k
     const double c1111 = q[K_C1111 * np + p], c1112 = q[K_C1112 * np + p], c1212 = q[K_C1212 * np + p];
     const double c2121 = q[K_C2121 * np + p], c2122 = q[K_C2122 * np + p], c2222 = q[K_C2222 * np + p];
@@ -468,6 +469,10 @@ static double christoffel_lmax(const HostBlock& B, long p, double th) {
     return 0.5 * (tr + std::sqrt(df * df + 4 * G01 * G01)) * q[K_IRHO * np + p];
 }
 
+static double christoffel_lmax(const HostBlock& B, long p, double th) {
+    return christoffel_lmax_cs(B, p, std::cos(th), std::sin(th));
+}
+
 static double block_vmax2(const HostBlock& B) {
     // coarse sweep over directions at every point, then golden-section
     // refinement of the best candidates (lambda_max is smooth near its maximum)
@@ -475,12 +480,17 @@ static double block_vmax2(const HostBlock& B) {
     const long np = B.np();
     std::vector<double> best(np);
     std::vector<int> bk(np);
+    double cs[nang], sn[nang];
+    for (int k = 0; k < nang; ++k) {
+        cs[k] = std::cos(M_PI * k / nang);
+        sn[k] = std::sin(M_PI * k / nang);
+    }
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < np; ++p) {
         double bv = -1.0;
         int kk = 0;
         for (int k = 0; k < nang; ++k) {
-            const double v = christoffel_lmax(B, p, M_PI * k / nang);
+            const double v = christoffel_lmax_cs(B, p, cs[k], sn[k]);
             if (v > bv) {
                 bv = v;
                 kk = k;
@@ -492,7 +502,8 @@ static double block_vmax2(const HostBlock& B) {
     const long keep = std::min<long>(256, np);
     std::vector<long> idx(np);
     for (long p = 0; p < np; ++p) idx[p] = p;
-    std::partial_sort(idx.begin(), idx.begin() + keep, idx.end(), [&](long a, long b) { return best[a] > best[b]; });
+    // the keep largest (their order does not matter: the result is a maximum)
+    std::nth_element(idx.begin(), idx.begin() + (keep - 1), idx.end(), [&](long a, long b) { return best[a] > best[b]; });
     double vmax = 0.0;
     const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
     for (long q = 0; q < keep; ++q) {
@@ -1588,10 +1599,16 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
         }
     if (c->dissipative && c->blocks.size() > (size_t)MAX_APPLY_BLOCKS)
         return fail(c, SBPE_EINVAL, "dissipative faces need at most 16 blocks");
+    // SBPE_SETUP_TIMING=1 prints the wall time of each setup phase to stderr
+    const bool timing = std::getenv("SBPE_SETUP_TIMING") != nullptr;
+    const auto t_start = std::chrono::steady_clock::now();
+    auto since = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
+    double t_metrics = 0, t_upload = 0, t_plan = 0;
     for (size_t b = 0; b < c->blocks.size(); ++b) {
         sbpe_status s = setup_block(c, (int)b);
         if (s) return s;
     }
+    t_metrics = since();
     // interfaces: conforming faces must share Jhat (Sec. 6)
     for (size_t b = 0; b < c->blocks.size(); ++b)
         for (int f = 0; f < 4; ++f) {
@@ -1669,8 +1686,10 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
             }
         }
     }
+    t_upload = since();
     sbpe_status s = build_plan(c);
     if (s) return s;
+    t_plan = since();
     if (!c->host_only) {
         // SBPE_FRAME=stencil leaves the frame operator unassembled: every sweep
         // then runs the frame band with the stencil kernel on the second
@@ -1683,6 +1702,9 @@ sbpe_status sbpe_finalize(sbpe_ctx_t c) {
             if (s) return s;
         }
     }
+    if (timing)
+        std::fprintf(stderr, "sbpe_finalize: metrics and c %.4f s, uploads %.4f s, plan %.4f s, frame operator %.4f s\n",
+                     t_metrics, t_upload - t_metrics, t_plan - t_upload, since() - t_plan);
     c->finalized = true;
     return SBPE_OK;
 }
@@ -2435,7 +2457,8 @@ extern "C" sbpe_status sbpe_lincomb(sbpe_ctx_t c, int nterms, const double* coef
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     sbpe_status s = need_gpu(c);
     if (s) return s;
-    if (nterms < 1 || nterms > 4 || !coefs || !x || !y || count < 0) return fail(c, SBPE_EINVAL, "bad arguments");
+    if (nterms < 1 || nterms > LINCOMB_MAX || !coefs || !x || !y || count < 0)
+        return fail(c, SBPE_EINVAL, "bad arguments");
     for (int k = 0; k < nterms; ++k)
         if (!x[k]) return fail(c, SBPE_EINVAL, "NULL input");
     const int e = launch_lincomb(c->dtype, nterms, coefs, x, y, (long)count, c->stream);

@@ -196,6 +196,7 @@ int launch_frame_sp(int dtype, int order, const PassArgs& a, int total_frame_wg,
 // says whether a grid of that many tiles is swept that way
 bool sweep_fused(int total_tiles);
 int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int total_frame_wg, void* stream);
+constexpr int LINCOMB_MAX = 6;   // terms of sbpe_lincomb
 int launch_lincomb(int dtype, int nterms, const double* coefs, const void* const* x, void* y, long count,
                    void* stream);
 // one interpolation point of one receiver: u[block][c][p] += scale * w * r[rec][c]

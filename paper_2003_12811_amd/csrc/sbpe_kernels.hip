@@ -142,14 +142,13 @@ int launch_lincomb(int dtype, int nterms, const double* c, const void* const* x,
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (count <= 0) return 0;
     const dim3 grid((unsigned)((count + 255) / 256)), bl(256);
-    const void* xs[4] = {x[0], nterms > 1 ? x[1] : x[0], nterms > 2 ? x[2] : x[0], nterms > 3 ? x[3] : x[0]};
-    const double cs[4] = {c[0], nterms > 1 ? c[1] : 0.0, nterms > 2 ? c[2] : 0.0, nterms > 3 ? c[3] : 0.0};
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_lincomb<double>, grid, bl, 0, s, nterms, cs[0], cs[1], cs[2], cs[3], (const double*)xs[0],
-                           (const double*)xs[1], (const double*)xs[2], (const double*)xs[3], (double*)y, count);
-    else
-        hipLaunchKernelGGL(k_lincomb<float>, grid, bl, 0, s, nterms, cs[0], cs[1], cs[2], cs[3], (const float*)xs[0],
-                           (const float*)xs[1], (const float*)xs[2], (const float*)xs[3], (float*)y, count);
+    LincombArgs a;
+    for (int k = 0; k < LINCOMB_MAX; ++k) {
+        a.c[k] = k < nterms ? c[k] : 0.0;
+        a.x[k] = k < nterms ? x[k] : x[0];
+    }
+    if (dtype == 0) hipLaunchKernelGGL(k_lincomb<double>, grid, bl, 0, s, nterms, a, (double*)y, count);
+    else hipLaunchKernelGGL(k_lincomb<float>, grid, bl, 0, s, nterms, a, (float*)y, count);
     return (int)hipGetLastError();
 }
 

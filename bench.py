@@ -383,6 +383,7 @@ def main():
                     help='mean arrival rate of the served stream (shots/s)')
     ap.add_argument('--serve-steps', type=int, default=300)
     ap.add_argument('--serve-sizes', default='257,513,1025,2049')
+    ap.add_argument('--serve-workers', type=int, default=4, help='setup threads of both serving forms')
     ap.add_argument('--copy-probe-mib', type=int, default=0,
                     help='first run a plain device-to-device copy of this many MiB (calibrates '
                          'the HBM byte counters of a profiler)')
@@ -497,7 +498,8 @@ def main():
         from paper_2003_12811_amd import serve
         log('served stream vs sequential plain solves')
         sv = serve.serve_and_compare(args.serve_shots, args.serve_rate,
-                                     [int(x) for x in args.serve_sizes.split(',')], args.serve_steps)
+                                     [int(x) for x in args.serve_sizes.split(',')], args.serve_steps,
+                                     workers=args.serve_workers)
         sv["scale_down"] = ("the 256-shot stream (20/s, 1500 steps) with 64 shots of 300 steps arriving at "
                             "100/s: the same offered grid-point updates per second")
         if "c2_f32" in line:

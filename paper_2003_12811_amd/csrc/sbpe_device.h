@@ -1594,7 +1594,7 @@ __device__ __forceinline__ void march_body(const PassArgs& A, int bid) {
 // A frame workgroup takes floop consecutive frame groups (nt / FRAME_LANES
 // points each): fewer, longer frame workgroups in front of the tiles.
 template <typename T, int ORD, int PASS, bool SPLIT>
-__global__ void __launch_bounds__(SPLIT ? 128 : 64, PASS == PASS_APPLY ? 2 : 1) k_pass(PassArgs A, int nframe, int floop) {
+__global__ void __launch_bounds__(SPLIT ? 128 : 64) k_pass(PassArgs A, int nframe, int floop) {
     const int bid = (int)blockIdx.x;
     if (bid < nframe) {
         for (int r = 0; r < floop; ++r) frame_sp_body<T, ORD, PASS>(A, bid * floop + r, SPLIT ? 128 : 64);

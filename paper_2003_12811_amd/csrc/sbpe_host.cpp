@@ -15,6 +15,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <utility>
 #include <unordered_map>
 #include <string>
 #include <vector>
@@ -122,6 +124,29 @@ struct HostFace {
     std::vector<double> jhat;   // computed
 };
 
+// Per-point host arrays of a block that setup writes in full in parallel
+// loops: their allocator leaves new elements uninitialised, so sizing them
+// costs no serial zero fill (hundreds of MB at 2049^2).
+template <typename V>
+struct NoInitAlloc : std::allocator<V> {
+    template <typename U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <typename U>
+    NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+    template <typename U>
+    void construct(U* p) noexcept {
+        ::new (static_cast<void*>(p)) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U* p, Args&&... args) {
+        ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+    }
+};
+using hvec = std::vector<double, NoInitAlloc<double>>;
+
 struct HostBlock {
     int n1 = 0, n2 = 0;
     double h1 = 0, h2 = 0;
@@ -130,10 +155,10 @@ struct HostBlock {
     TimeFn ftf{TF_ZERO, 0, {0.0, 0.0}};
     HostFace face[4];
     // computed at finalize
-    std::vector<double> coef;   // [NCOEF][np]
-    std::vector<double> J;
-    std::vector<double> Fm;     // F[I][i] = dx_i/dX_I per point, [4][np] (gradients)
-    std::vector<double> c10t;   // transformed stiffness, C10 layout
+    hvec coef;   // [NCOEF][np]
+    hvec J;
+    hvec Fm;     // F[I][i] = dx_i/dX_I per point, [4][np] (gradients)
+    hvec c10t;   // transformed stiffness, C10 layout
     // device memory owned by the context
     void* d_coef = nullptr;
     void* d_force = nullptr;
@@ -292,7 +317,8 @@ static void dfree(sbpe_ctx* c, const void* p) {
     } while (0)
 
 // upload a double host array to device memory of the context dtype
-static sbpe_status upload(sbpe_ctx* c, const std::vector<double>& h, void** d) {
+template <typename Vec>
+static sbpe_status upload(sbpe_ctx* c, const Vec& h, void** d) {
     const size_t n = h.size();
     if (dmalloc(c, d, n * esize(c)) != hipSuccess) return fail(c, SBPE_ENOMEM, "device allocation failed");
     if (c->dtype == SBPE_F64) {
@@ -359,7 +385,7 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
     B.h1 = 1.0 / (n1 - 1);
     B.h2 = 1.0 / (n2 - 1);
     // A[i][I] = dX_I / dx_i
-    std::vector<double> A00(np), A01(np), A10(np), A11(np);
+    hvec A00(np), A01(np), A10(np), A11(np);
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < n2; ++j) {
         d1_apply(o, n1, B.h1, &B.X1[(long)j * n1], 1, &A00[(long)j * n1], 1);
@@ -370,10 +396,11 @@ static sbpe_status setup_block(sbpe_ctx* c, int b) {
         d1_apply(o, n2, B.h2, &B.X1[i], n1, &A10[i], n1);
         d1_apply(o, n2, B.h2, &B.X2[i], n1, &A11[i], n1);
     }
-    B.J.assign(np, 0.0);
-    B.Fm.assign((size_t)4 * np, 0.0);
-    B.coef.assign((size_t)NCOEF * np, 0.0);
-    B.c10t.assign((size_t)10 * np, 0.0);
+    // every entry is written below (setup fails before any is read otherwise)
+    B.J.resize(np);
+    B.Fm.resize((size_t)4 * np);
+    B.coef.resize((size_t)NCOEF * np);
+    B.c10t.resize((size_t)10 * np);
     long bad_j = -1, bad_c = -1;
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < np; ++p) {

@@ -269,54 +269,51 @@ class Server:
                     device_s=device_s, device_updates_per_s=self.launched_points_steps / device_s if device_s else 0.0)
 
 
-def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_receivers=True, log=None):
+def run_sequential(requests, dtype='f32', device=0, spec_fn=default_spec, keep_receivers=True, log=None,
+                   workers=2):
     """The same shots, in arrival order, one at a time with sbpe_advance
-    (each starts when it has arrived and the previous one has finished).  A
-    worker thread sets up the next shot while the current one runs, as the
-    server's setup workers do, so both forms overlap host setup with device
-    work and differ only in how the device is used."""
+    (each starts when it has arrived and the previous one has finished).
+    `workers` threads set up the next shots while the current one runs, as
+    the server's setup workers do, so both forms overlap host setup with
+    device work and differ only in how the device is used."""
+    import concurrent.futures
     import torch
     reqs = [dict(r) for r in sorted(requests, key=lambda r: r['arrival'])]
     start = time.perf_counter()
     now = lambda: time.perf_counter() - start
-    built = queue.Queue(maxsize=1)
+    def build(r):
+        wait = r['arrival'] - now()
+        if wait > 0:
+            time.sleep(wait)
+        st = torch.cuda.Stream(device=device)     # the shot's own stream
+        shot = Shot(r, spec_fn(r), dtype, device, st)
+        shot.stream = st
+        return shot
 
-    def builder():
-        for r in reqs:
-            wait = r['arrival'] - now()
-            if wait > 0:
-                time.sleep(wait)
-            try:
-                st = torch.cuda.Stream(device=device)    # the shot's own stream
-                shot = Shot(r, spec_fn(r), dtype, device, st)
-                shot.stream = st
-                built.put((r, shot))
-            except Exception as e:       # reported by the consumer
-                built.put((r, e))
-
-    th = threading.Thread(target=builder, daemon=True)
-    th.start()
     device_s = 0.0
-    for _ in reqs:
-        r, shot = built.get()
-        if isinstance(shot, Exception):
-            raise shot
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(shot.stream)
-        S.sbpe_advance(shot.ctx, r['steps'], shot.dt)
-        e1.record(shot.stream)
-        rec = shot.receivers()
-        device_s += 1e-3 * e0.elapsed_time(e1)
-        r['t_done'] = now()
-        r['latency'] = r['t_done'] - r['arrival']
-        r['points'] = shot.points
-        if keep_receivers:
-            r['receivers'] = rec
-        shot.close()
-        if log and r['id'] % 16 == 0:
-            log('sequential: shot %d done at %.2f s' % (r['id'], r['t_done']))
-    th.join()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as pool:
+        futs, nxt = {}, 0
+        for k, r in enumerate(reqs):
+            # at most `workers` shots set up ahead of the one on the device
+            while nxt < len(reqs) and nxt <= k + workers:
+                futs[nxt] = pool.submit(build, reqs[nxt])
+                nxt += 1
+            shot = futs.pop(k).result()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(shot.stream)
+            S.sbpe_advance(shot.ctx, r['steps'], shot.dt)
+            e1.record(shot.stream)
+            rec = shot.receivers()
+            device_s += 1e-3 * e0.elapsed_time(e1)
+            r['t_done'] = now()
+            r['latency'] = r['t_done'] - r['arrival']
+            r['points'] = shot.points
+            if keep_receivers:
+                r['receivers'] = rec
+            shot.close()
+            if log and r['id'] % 16 == 0:
+                log('sequential: shot %d done at %.2f s' % (r['id'], r['t_done']))
     wall = now()
     lat = np.array([r['latency'] for r in reqs])
     total_pts = sum(r['points'] * r['steps'] for r in reqs)
@@ -383,7 +380,8 @@ def serve_and_compare(shots, rate, sizes, steps, nrec=64, dtype='f32', budget_gb
     log('  served:', json.dumps(out['served']))
     if not args.no_sequential:
         log('sequential plain solves')
-        seq = run_sequential([dict(r) for r in reqs], dtype=args.dtype, log=log if shots > 64 else None)
+        seq = run_sequential([dict(r) for r in reqs], dtype=args.dtype, log=log if shots > 64 else None,
+                             workers=args.workers)
         out['sequential'] = summarize(seq)
         log('  sequential:', json.dumps(out['sequential']))
         by_id = {r['id']: r['receivers'] for r in seq['shots']}

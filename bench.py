@@ -291,6 +291,49 @@ def c1_latency(reps=5):
             "rel_l2_error_vs_exact": float(np.linalg.norm(ug[0] - exact) / np.linalg.norm(exact))}
 
 
+def bench_3d(n=97, steps=20, dtype='f64'):
+    """One curvilinear 3-D block of n^3 points (random major-symmetric
+    stiffness, displacement on x3 = 0 and traction elsewhere, a body force),
+    4th order, RK4 at CFL 0.5: time per step of the 3-D point kernel."""
+    import numpy as np
+    import torch
+    from paper_2003_12811_amd import sbpe as S
+    from paper_2003_12811_amd import workloads as W
+    X = W.grid3(n, n, n)
+    rho, C = W.random_material3(X[0].shape, 0)
+    ctx = S.sbpe3_create(0, torch.cuda.current_stream().cuda_stream, S.F64 if dtype == 'f64' else S.F32, 4)
+    try:
+        S.sbpe3_set_block(ctx, *X, rho, C)
+        S.sbpe3_set_bc(ctx, 4, S.BC_DISPLACEMENT)
+        F = np.zeros((3,) + X[0].shape)
+        F[2] = np.exp(-((X[0] - 0.5) ** 2 + (X[1] - 0.5) ** 2 + (X[2] - 0.7) ** 2) / 0.01)
+        S.sbpe3_set_forcing(ctx, F, S.TIME_RICKER, (10.0, 0.1))
+        S.sbpe3_finalize(ctx)
+        dt = S.sbpe3_dt_cfl(ctx, 0.5)
+        tdt = torch.float64 if dtype == 'f64' else torch.float32
+        u = torch.zeros((3,) + X[0].shape, dtype=tdt, device='cuda')
+        v = torch.zeros_like(u)
+        S.sbpe3_bind_state(ctx, u.data_ptr(), v.data_ptr(), 0.0)
+        S.sbpe3_advance(ctx, 3, dt)
+        S.sbpe3_synchronize(ctx)
+        t0 = time.perf_counter()
+        S.sbpe3_advance(ctx, steps, dt)
+        S.sbpe3_synchronize(ctx)
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+    finally:
+        S.sbpe3_destroy(ctx)
+    pts = n ** 3
+    wb = 8 if dtype == 'f64' else 4
+    # own words per point and step: first sweep u, v (6) + 46 coefficients + a1, a2 (6);
+    # second sweep a1, a2 (6) + 46 + u, v in (6) and out (6)
+    own = (58 + 64) * wb * pts
+    return {"workload": "one curvilinear 3-D block of %d^3 points, random major-symmetric stiffness, displacement "
+                        "on x3 = 0 and traction elsewhere, body force, 4th order, RK4 at CFL 0.5, %s" % (n, dtype.upper()),
+            "ms_per_step": round(ms, 4), "value": pts / (ms * 1e-3),
+            "own_bytes_per_step": own, "achieved_own_gbs": round(own / (ms * 1e-3) / 1e9, 1),
+            "frac_own_bytes": round(own / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def cpu_baseline(n, steps, dt):
     """Oracle RK4 steps on the host (single thread), in a child process."""
     env = dict(os.environ, OMP_NUM_THREADS='1', OPENBLAS_NUM_THREADS='1', MKL_NUM_THREADS='1')
@@ -376,6 +419,8 @@ def main():
     ap.add_argument('--no-serve', action='store_true')
     ap.add_argument('--no-gradient', action='store_true')
     ap.add_argument('--no-c1', action='store_true')
+    ap.add_argument('--no-3d', action='store_true')
+    ap.add_argument('--n3d', type=int, default=97, help='points per direction of the 3-D block')
     # the serving workload (256 shots of 257^2 .. 2049^2, 1500 steps, 20/s) scaled down to a
     # bench-length run with the same offered load: 64 shots, 300 steps, 100/s
     ap.add_argument('--serve-shots', type=int, default=64)
@@ -398,7 +443,7 @@ def main():
         sys.exit(2)
     if args.headline_only:
         args.no_cpu_baseline = args.no_c2 = args.no_f32 = args.no_wide = args.no_order6 = True
-        args.no_serve = args.no_gradient = args.no_c1 = True
+        args.no_serve = args.no_gradient = args.no_c1 = args.no_3d = True
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
     from paper_2003_12811_amd import workloads as W
@@ -509,6 +554,9 @@ def main():
             # the plain FP32 rate of one 1025^2 solve
             sv["served_device_over_plain_f32"] = sv["served"]["device_updates_per_s"] / line["c2_f32"]["value"]
         line["serving"] = sv
+    if not args.no_3d:
+        log('3-D block, fp64')
+        line["block3d"] = bench_3d(args.n3d)
     if not args.no_c1:
         log('plain-method workload (65^2, to t = 0.5): time to solution')
         line["c1_latency"] = c1_latency()

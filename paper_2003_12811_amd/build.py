@@ -16,7 +16,7 @@ HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 
 # the host runtime, the launchers and small kernels, and one translation unit
 # per (precision, order) pair of the large kernels; compiled in parallel
-SOURCES = ['sbpe_host.cpp', 'sbpe_kernels.hip'] + sorted(
+SOURCES = ['sbpe_host.cpp', 'sbpe_kernels.hip', 'sbpe3_kernels.hip'] + sorted(
     os.path.basename(p) for p in glob.glob(os.path.join(CSRC, 'sbpe_inst_*.hip')))
 HOST_ONLY_FLAGS = {'sbpe_host.cpp': ['-fopenmp']}
 # packed FP32 instructions are disabled for every device compile

@@ -1,0 +1,353 @@
+// The scheme on a single curvilinear 3-D block (d = 3): one right-hand-side
+// evaluation per grid point, fused with the two-sweep RK4 passes of the 2-D
+// path (sbpe_internal.h).  Reference-frame forms, as in 2-D:
+//   * volume: DD_ik(c_ijkl) u_l = sum_i D_ii^FC(c_ijil) u_l + sum_{i != k} D_i (c_ijkl D_k u_l)
+//     (Sec. 4.6-4.7), every 1-D row boundary-aware (the closure tables of
+//     sbpe_tables.h through the line helpers of sbpe_device.h);
+//   * traction face (Sec. 5.1): r_j -= (1/w_a) (nu_a c_ajkl D_k u_l - Jhat g_j);
+//   * displacement face (Sec. 5.2, d = 3): with delta = u - g on the face,
+//     the normal part of sum_k H^{-1} D_k^T (e_f H_f nu_a c_alkj delta_l) on the
+//     REACH points next to the face, its two tangential parts
+//     (1/w_a) H_t^{-1} D_t^T H_t (nu_a c_altj delta_l) at the face, and the
+//     penalty -(beta d / w_a^2) c_ajal delta_l;
+//   * r = rho~ a: a = rho~^{-1} (r + J f).
+// One thread per (point, field): the two fields of an RK sweep (u and v, or
+// A1 and A2) sit in neighbouring lanes and exchange their results.  This is a
+// correctness-first point kernel: every stencil value comes from global memory
+// (the caches serve the repeats).
+#include <hip/hip_runtime.h>
+
+#include "sbpe_device.h"
+
+namespace sbpe {
+
+namespace {
+
+__device__ __forceinline__ int sym3(int j, int l) {
+    const int a = j < l ? j : l, b = j < l ? l : j;
+    return a == 0 ? b : (a == 1 ? 2 + b : 5);
+}
+// stored field of c_ijil (narrow, direction i) and of c_ijkl, i != k
+__device__ __forceinline__ int fN(int i, int j, int l) { return 6 * i + sym3(j, l); }
+__device__ __forceinline__ int fM(int i, int k, int j, int l) {
+    const int a = i < k ? i : k, b = i < k ? k : i;
+    const int P = a == 0 ? (b == 1 ? 0 : 1) : 2;
+    return i < k ? 18 + 9 * P + 3 * j + l : 18 + 9 * P + 3 * l + j;
+}
+
+struct Geo3 {
+    int n[3];
+    long st[3];
+    long np;
+    double h[3];
+};
+
+__device__ __forceinline__ Geo3 geo3(const Args3& A) {
+    Geo3 g;
+    g.n[0] = A.n1;
+    g.n[1] = A.n2;
+    g.n[2] = A.n3;
+    g.st[0] = 1;
+    g.st[1] = A.n1;
+    g.st[2] = (long)A.n1 * A.n2;
+    g.np = g.st[2] * A.n3;
+    g.h[0] = A.h1;
+    g.h[1] = A.h2;
+    g.h[2] = A.h3;
+    return g;
+}
+
+// h (D_k x)(p) along direction k for the point with coordinate c[k] on its line
+template <typename T, int ORD>
+__device__ __forceinline__ T d1_at(gcp<T> x, const Geo3& g, long p, const int* c, int k) {
+    return d1_line<T, ORD>(x + (p - (long)c[k] * g.st[k]), g.st[k], c[k], g.n[k]);
+}
+
+// volume terms of L x at point p (coordinates c)
+template <typename T, int ORD>
+__device__ __forceinline__ void volume3(const Args3& A, const Geo3& g, gcp<T> x, long p, const int* c, T r[3]) {
+    gcp<T> cf = gc<T>(A.coef);
+    const long np = g.np;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const long l0 = p - (long)c[i] * g.st[i];     // start of the line along i
+        const T s = T(1.0 / (g.h[i] * g.h[i]));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T acc = 0;
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                acc += d2_line<T, ORD>(cf + (long)fN(i, j, l) * np + l0, x + (long)l * np + l0, g.st[i], c[i], g.n[i]);
+            r[j] += acc * s;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k == i) continue;
+            const T s = T(1.0 / (g.h[i] * g.h[k]));
+            T acc[3] = {0, 0, 0};
+            int cq[3] = {c[0], c[1], c[2]};
+            d1_foreach<ORD>(c[i], g.n[i], [&](int ii, double w) {
+                const long q = p + (long)(ii - c[i]) * g.st[i];
+                cq[i] = ii;
+                T dk[3];
+#pragma unroll
+                for (int l = 0; l < 3; ++l) dk[l] = d1_at<T, ORD>(x + (long)l * np, g, q, cq, k);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    T m = 0;
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) m += cf[(long)fM(i, k, j, l) * np + q] * dk[l];
+                    acc[j] += static_cast<T>(w) * m;
+                }
+            });
+#pragma unroll
+            for (int j = 0; j < 3; ++j) r[j] += acc[j] * s;
+        }
+}
+
+// index along face f of the point with coordinates c (the lower tangential direction fast)
+__device__ __forceinline__ int face_t(int a, const int* c, const Geo3& g) {
+    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    return c[t1] + g.n[t1] * c[t2];
+}
+
+// displacement-type delta at the face point q (coordinates cq) of face f
+template <typename T, bool DATA>
+__device__ __forceinline__ void delta3(const Args3& A, const Geo3& g, gcp<T> x, int f, long q, const int* cq,
+                                       double tau, T d[3]) {
+    if (!DATA) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) d[l] = x[(long)l * g.np + q];
+        return;
+    }
+    const Face3& F = A.face[f];
+    const int t = face_t(f >> 1, cq, g);
+    gcp<T> gg = gc<T>(F.g);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) d[l] = gg ? static_cast<T>(-tau * (double)gg[(long)l * F.nf + t]) : T(0);
+}
+
+// SAT contribution of face f to r at point p (coordinates c, distance dn from the face)
+template <typename T, int ORD, bool DATA>
+__device__ void face3(const Args3& A, const Geo3& g, gcp<T> x, int f, long p, const int* c, int dn, double tau, T r[3]) {
+    using O = Op<ORD>;
+    const Face3& F = A.face[f];
+    const int a = f >> 1;
+    const T nu = (f & 1) ? T(1) : T(-1);
+    gcp<T> cf = gc<T>(A.coef);
+    const long np = g.np;
+    const T iw = T(1.0 / F.w);
+    if (F.kind == BC_TRACTION) {
+        if (dn != 0) return;
+        if (DATA) {
+            if (!F.g) return;
+            gcp<T> gg = gc<T>(F.g);
+            const int t = face_t(a, c, g);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) r[j] += static_cast<T>(tau * (double)gg[(long)j * F.nf + t]);
+            return;
+        }
+        T du[3][3];     // h-scaled D_k u_l at the face point, [k][l]
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) du[k][l] = d1_at<T, ORD>(x + (long)l * np, g, p, c, k) * T(1.0 / g.h[k]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T tr = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    const int fld = k == a ? fN(a, j, l) : fM(a, k, j, l);
+                    tr += cf[(long)fld * np + p] * du[k][l];
+                }
+            r[j] -= iw * nu * tr;
+        }
+        return;
+    }
+    // displacement face
+    if (DATA && !F.g) return;
+    int cq[3] = {c[0], c[1], c[2]};
+    cq[a] = (f & 1) ? g.n[a] - 1 : 0;
+    const long q = p + (long)(cq[a] - c[a]) * g.st[a];
+    T d[3];
+    delta3<T, DATA>(A, g, x, f, q, cq, tau, d);
+    if (dn < O::REACH) {
+        const double hn = hnorm<ORD>(dn, g.n[a]);
+        const T cfn = static_cast<T>(-O::d1b(0, dn) / (g.h[a] * g.h[a] * hn));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T s = 0;
+#pragma unroll
+            for (int l = 0; l < 3; ++l) s += cf[(long)fN(a, l, j) * np + q] * d[l];
+            r[j] += cfn * s;
+        }
+    }
+    if (dn != 0) return;
+    // tangential parts: (1/w) (H_t^{-1} D_t^T H_t qv)(t), qv_j = nu c_altj delta_l
+    for (int tt = 0; tt < 3; ++tt) {
+        if (tt == a) continue;
+        auto qv = [&](long qq, const int* cc, T out[3]) {
+            T e[3];
+            delta3<T, DATA>(A, g, x, f, qq, cc, tau, e);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T s = 0;
+#pragma unroll
+                for (int l = 0; l < 3; ++l) s += cf[(long)fM(a, tt, l, j) * np + qq] * e[l];
+                out[j] = nu * s;
+            }
+        };
+        T q0[3];
+        qv(q, cq, q0);
+        T dq[3] = {0, 0, 0};
+        int cc[3] = {cq[0], cq[1], cq[2]};
+        d1_foreach<ORD>(cq[tt], g.n[tt], [&](int k2, double w) {
+            cc[tt] = k2;
+            const long qq = q + (long)(k2 - cq[tt]) * g.st[tt];
+            T qk[3];
+            qv(qq, cc, qk);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dq[j] += static_cast<T>(w) * (qk[j] - q0[j]);
+        });
+        const T iht = T(1.0 / g.h[tt]);
+        const int nt = g.n[tt];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T s = -dq[j] * iht;
+            if (cq[tt] == 0) s -= q0[j] * T(1.0 / (g.h[tt] * hnorm<ORD>(0, nt)));
+            if (cq[tt] == nt - 1) s += q0[j] * T(1.0 / (g.h[tt] * hnorm<ORD>(nt - 1, nt)));
+            r[j] += iw * s;
+        }
+    }
+    // penalty
+    const T pen = static_cast<T>(A.beta * 3.0) * iw * iw;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T s = 0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) s += cf[(long)fN(a, j, l) * np + q] * d[l];
+        r[j] -= pen * s;
+    }
+}
+
+template <typename T, int ORD, bool DATA>
+__device__ __forceinline__ void sats3(const Args3& A, const Geo3& g, gcp<T> x, long p, const int* c, const double* tw,
+                                      T r[3]) {
+    using O = Op<ORD>;
+    for (int f = 0; f < 6; ++f) {
+        const int a = f >> 1;
+        const int dn = (f & 1) ? g.n[a] - 1 - c[a] : c[a];
+        if (dn >= O::REACH) continue;
+        if (DATA && tw[f] == 0.0) continue;
+        face3<T, ORD, DATA>(A, g, x, f, p, c, dn, DATA ? tw[f] : 0.0, r);
+    }
+}
+
+// data at p with the weighted time values tw (6 faces, then the forcing)
+template <typename T, int ORD>
+__device__ __forceinline__ void data3(const Args3& A, const Geo3& g, long p, const int* c, const double* tw, T r[3]) {
+    sats3<T, ORD, true>(A, g, gcp<T>(nullptr), p, c, tw, r);
+    if (A.force && tw[6] != 0.0) {
+        gcp<T> Fp = gc<T>(A.force);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r[j] += static_cast<T>(tw[6] * (double)Fp[(long)j * g.np + p]);
+    }
+}
+
+}  // namespace
+
+template <typename T, int ORD>
+__global__ void __launch_bounds__(256) k_point3(Args3 A) {
+    const Geo3 g = geo3(A);
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int fld = (int)(gid & 1);                 // field of this lane
+    const long pr = gid >> 1;
+    const bool valid = pr < g.np;
+    const long p = valid ? pr : 0;
+    int c[3];
+    c[2] = (int)(p / g.st[2]);
+    const long rem = p - (long)c[2] * g.st[2];
+    c[1] = (int)(rem / g.n[0]);
+    c[0] = (int)(rem - (long)c[1] * g.n[0]);
+    const bool apply = A.pass == PASS_APPLY;
+    // input field of this lane
+    const void* xin = apply ? A.in : (A.pass == PASS_RK1 ? (fld ? A.v : A.u) : (fld ? A.a2 : A.a1));
+    gcp<T> x = gc<T>(xin);
+    T L[3] = {0, 0, 0}, D[3] = {0, 0, 0};
+    if (valid && !(apply && fld)) {
+        volume3<T, ORD>(A, g, x, p, c, L);
+        sats3<T, ORD, false>(A, g, x, p, c, nullptr, L);
+    }
+    // data: lane 0 with the first weights, lane 1 with the second (sbpe_apply: lane 1 with the first)
+    if (valid) {
+        const double* tw = (apply || !fld) ? A.tfa : A.tfb;
+        if (!(apply && !fld)) data3<T, ORD>(A, g, p, c, tw, D);
+    }
+    T oL[3], oD[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        oL[j] = __shfl_xor(L[j], 1);
+        oD[j] = __shfl_xor(D[j], 1);
+    }
+    if (!valid) return;
+    const T irho = gc<T>(A.coef)[(long)45 * g.np + p];
+    const long np = g.np;
+    if (apply) {
+        if (fld) return;
+        gp<T> o = gm<T>(A.out);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) o[(long)j * np + p] = irho * (L[j] + oD[j]);
+        return;
+    }
+    const T dt = static_cast<T>(A.dt);
+    // field 0 (lane 0) and field 1 (lane 1) results
+    const T* L0 = fld ? oL : L;
+    const T* L1 = fld ? L : oL;
+    const T* D0 = fld ? oD : D;
+    const T* D1 = fld ? D : oD;
+    if (A.pass == PASS_RK1) {
+        // lane 0 writes a1 = irho (L u + d(t)), lane 1 a2 = irho (L u + dt/2 L v + d(t + dt/2))
+        gp<T> o = gm<T>(fld ? A.a2 : A.a1);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            o[(long)j * np + p] = fld ? irho * (L0[j] + T(0.5) * dt * L1[j] + D1[j]) : irho * (L0[j] + D0[j]);
+        return;
+    }
+    // RK2: lane 0 writes u, lane 1 writes v (all three components)
+    gcp<T> A1 = gc<T>(A.a1);
+    gcp<T> A2 = gc<T>(A.a2);
+    gp<T> uu = gm<T>(A.uo);
+    gp<T> vv = gm<T>(A.vo);
+    const T dt2 = dt * dt;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const long q = (long)j * np + p;
+        const T a1 = A1[q], a2 = A2[q];
+        const T a3 = a2 + T(0.25) * dt2 * irho * L0[j];
+        const T a4 = T(2) * a2 - a1 + T(0.5) * dt2 * irho * (L1[j] + D1[j]);
+        const T uo = gc<T>(A.u)[q], vo = gc<T>(A.v)[q];
+        if (fld == 0) uu[q] = uo + dt * vo + dt2 / T(6) * (a1 + a2 + a3);
+        else vv[q] = vo + dt / T(6) * (a1 + T(2) * a2 + T(2) * a3 + a4);
+    }
+}
+
+int launch_point3(int dtype, int order, const Args3& a, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long np = (long)a.n1 * a.n2 * a.n3;
+    const dim3 g((unsigned)((2 * np + 255) / 256)), b(256);
+    if (dtype == 0) {
+        if (order == 4) hipLaunchKernelGGL((k_point3<double, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_point3<double, 2>), g, b, 0, s, a);
+    } else {
+        if (order == 4) hipLaunchKernelGGL((k_point3<float, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_point3<float, 2>), g, b, 0, s, a);
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace sbpe

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/sbpe.h"
+#include "../../include/sbpe3.h"
 #include "sbpe_internal.h"
 #include "sbpe_tables.h"
 
@@ -2512,3 +2513,490 @@ extern "C" sbpe_status sbpe_receiver_adjoint(sbpe_ctx_t c, const void* r, void* 
     if (e != 0) return fail(c, SBPE_EHIP, std::string("receiver adjoint launch: ") + hip_error_string(e));
     return SBPE_OK;
 }
+
+// ================================================================ 3-D
+// One curvilinear 3-D block (include/sbpe3.h): setup on the host (metric,
+// c = F J C F, face scale factors), then the point kernel of sbpe3_kernels.hip.
+
+struct sbpe3_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int dtype = SBPE_F64, order = 4;
+    double beta = 1.0;
+    std::string err;
+    int n[3] = {0, 0, 0};
+    double h[3] = {0, 0, 0};
+    std::vector<double> X[3], rho, C81;
+    struct Face {
+        int kind = BC_TRACTION;
+        std::vector<double> g;     // [3][nf] as given
+        TimeFn tf{TF_ZERO, 0, {0.0, 0.0}};
+    } face[6];
+    std::vector<double> force;     // [3][np] as given
+    TimeFn ftf{TF_ZERO, 0, {0.0, 0.0}};
+    std::vector<double> coef;      // host copy of the stored coefficients [46][np]
+    void* d_coef = nullptr;
+    void* d_force = nullptr;
+    void* d_g[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    void* d_a1 = nullptr;
+    void* d_a2 = nullptr;
+    double w[6] = {0, 0, 0, 0, 0, 0};
+    bool finalized = false, bound = false;
+    void* u = nullptr;
+    void* v = nullptr;
+    double t = 0.0;
+    long np() const { return (long)n[0] * n[1] * n[2]; }
+    int nf(int f) const {
+        const int a = f >> 1;
+        return a == 0 ? n[1] * n[2] : (a == 1 ? n[0] * n[2] : n[0] * n[1]);
+    }
+};
+
+static sbpe_status fail3(sbpe3_ctx* c, sbpe_status code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_static_err = msg;
+    return code;
+}
+
+static double tf_host(const TimeFn& f, double t) {
+    switch (f.kind) {
+        case TF_ONE: return 1.0;
+        case TF_COS: return std::cos(f.p[0] * t + f.p[1]);
+        case TF_RICKER: {
+            const double a = (M_PI * f.p[0] * (t - f.p[1])) * (M_PI * f.p[0] * (t - f.p[1]));
+            return (1.0 - 2.0 * a) * std::exp(-a);
+        }
+        default: return 0.0;
+    }
+}
+
+// positive semidefinite test of a symmetric m x m matrix (pivoted Cholesky)
+static bool psd_n(std::vector<double> a, int m, double tol_rel) {
+    double dmax = 0.0;
+    for (int i = 0; i < m; ++i) dmax = std::max(dmax, a[(size_t)i * m + i]);
+    const double tol = tol_rel * std::max(1.0, dmax);
+    std::vector<int> perm(m);
+    for (int i = 0; i < m; ++i) perm[i] = i;
+    for (int k = 0; k < m; ++k) {
+        int p = k;
+        for (int i = k + 1; i < m; ++i)
+            if (a[(size_t)i * m + i] > a[(size_t)p * m + p]) p = i;
+        if (p != k) {
+            for (int j = 0; j < m; ++j) std::swap(a[(size_t)k * m + j], a[(size_t)p * m + j]);
+            for (int i = 0; i < m; ++i) std::swap(a[(size_t)i * m + k], a[(size_t)i * m + p]);
+        }
+        const double d = a[(size_t)k * m + k];
+        if (d <= tol) {
+            for (int i = k; i < m; ++i)
+                for (int j = k; j < m; ++j)
+                    if (std::fabs(a[(size_t)i * m + j]) > tol) return false;
+            return true;
+        }
+        for (int i = k + 1; i < m; ++i) {
+            const double l = a[(size_t)i * m + k] / d;
+            for (int j = k + 1; j < m; ++j) a[(size_t)i * m + j] -= l * a[(size_t)k * m + j];
+        }
+    }
+    return true;
+}
+
+// largest eigenvalue of a symmetric 3 x 3 matrix (trigonometric closed form)
+static double lmax3(const double G[3][3]) {
+    const double p1 = G[0][1] * G[0][1] + G[0][2] * G[0][2] + G[1][2] * G[1][2];
+    const double q = (G[0][0] + G[1][1] + G[2][2]) / 3.0;
+    if (p1 == 0.0) return std::max(G[0][0], std::max(G[1][1], G[2][2]));
+    const double p2 = (G[0][0] - q) * (G[0][0] - q) + (G[1][1] - q) * (G[1][1] - q) + (G[2][2] - q) * (G[2][2] - q) +
+                      2.0 * p1;
+    const double p = std::sqrt(p2 / 6.0);
+    double B[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) B[i][j] = (G[i][j] - (i == j ? q : 0.0)) / p;
+    const double r = 0.5 * (B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                            B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                            B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]));
+    const double phi = r <= -1.0 ? M_PI / 3.0 : (r >= 1.0 ? 0.0 : std::acos(r) / 3.0);
+    return q + 2.0 * p * std::cos(phi);
+}
+
+static int f3N(int i, int j, int l) {
+    const int a = std::min(j, l), b = std::max(j, l);
+    return 6 * i + (a == 0 ? b : (a == 1 ? 2 + b : 5));
+}
+static int f3M(int i, int k, int j, int l) {
+    const int a = std::min(i, k), b = std::max(i, k);
+    const int P = a == 0 ? (b == 1 ? 0 : 1) : 2;
+    return i < k ? 18 + 9 * P + 3 * j + l : 18 + 9 * P + 3 * l + j;
+}
+
+template <typename P>
+static hipError_t d3malloc(P** p, size_t bytes) {
+    void* v = nullptr;
+    const hipError_t e = hipMalloc(&v, bytes);
+    *p = static_cast<P*>(v);
+    return e;
+}
+
+static sbpe_status upload3(sbpe3_ctx* c, const double* h, size_t n, void** d) {
+    const size_t es = c->dtype == SBPE_F64 ? 8 : 4;
+    if (d3malloc(d, n * es) != hipSuccess) return fail3(c, SBPE_ENOMEM, "device allocation failed");
+    hipError_t e;
+    if (c->dtype == SBPE_F64) {
+        e = hipMemcpy(*d, h, n * 8, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> f(n);
+        for (size_t k = 0; k < n; ++k) f[k] = (float)h[k];
+        e = hipMemcpy(*d, f.data(), n * 4, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return fail3(c, SBPE_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    return SBPE_OK;
+}
+
+extern "C" {
+
+sbpe_status sbpe3_create(int device, void* stream, int dtype, int order, double beta, sbpe3_ctx_t* out) {
+    if (!out) return fail3(nullptr, SBPE_EINVAL, "NULL output");
+    *out = nullptr;
+    if (dtype != SBPE_F64 && dtype != SBPE_F32) return fail3(nullptr, SBPE_EINVAL, "bad dtype");
+    if (order != 2 && order != 4) return fail3(nullptr, SBPE_EINVAL, "3-D blocks take orders 2 and 4");
+    if (!(beta >= 1.0)) return fail3(nullptr, SBPE_EINVAL, "beta must be >= 1");
+    if (device < 0) return fail3(nullptr, SBPE_EINVAL, "bad device");
+    auto* c = new sbpe3_ctx;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->dtype = dtype;
+    c->order = order;
+    c->beta = beta;
+    *out = c;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe3_destroy(sbpe3_ctx_t c) {
+    if (!c) return SBPE_OK;
+    if (c->finalized) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->d_coef);
+        (void)hipFree(c->d_force);
+        for (int f = 0; f < 6; ++f) (void)hipFree(c->d_g[f]);
+        (void)hipFree(c->d_a1);
+        (void)hipFree(c->d_a2);
+    }
+    delete c;
+    return SBPE_OK;
+}
+
+const char* sbpe3_last_error(sbpe3_ctx_t c) { return c ? c->err.c_str() : g_static_err.c_str(); }
+
+sbpe_status sbpe3_set_block(sbpe3_ctx_t c, int n1, int n2, int n3, const double* X1, const double* X2,
+                            const double* X3, const double* rho, const double* C81) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail3(c, SBPE_ESTATE, "context already finalized");
+    const int nmin = min_points(c->order);
+    if (n1 < nmin || n2 < nmin || n3 < nmin) return fail3(c, SBPE_EINVAL, "block too small for the operator order");
+    if ((long)n1 * n2 * n3 > (1L << 28)) return fail3(c, SBPE_EINVAL, "block has more than 2^28 points");
+    if (!X1 || !X2 || !X3 || !rho || !C81) return fail3(c, SBPE_EINVAL, "NULL array");
+    c->n[0] = n1;
+    c->n[1] = n2;
+    c->n[2] = n3;
+    const long np = c->np();
+    c->X[0].assign(X1, X1 + np);
+    c->X[1].assign(X2, X2 + np);
+    c->X[2].assign(X3, X3 + np);
+    c->rho.assign(rho, rho + np);
+    c->C81.assign(C81, C81 + 81 * np);
+    for (int f = 0; f < 6; ++f) c->face[f] = sbpe3_ctx::Face{};
+    c->force.clear();
+    return SBPE_OK;
+}
+
+sbpe_status sbpe3_set_bc(sbpe3_ctx_t c, int face, int bc, const double* g, int time_fn, const double* tp) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail3(c, SBPE_ESTATE, "context already finalized");
+    if (c->n[0] == 0) return fail3(c, SBPE_ESTATE, "no block");
+    if (face < 0 || face > 5) return fail3(c, SBPE_EINVAL, "bad face");
+    if (bc != SBPE_BC_TRACTION && bc != SBPE_BC_DISPLACEMENT)
+        return fail3(c, SBPE_EINVAL, "3-D faces are traction or displacement");
+    if (time_fn < SBPE_TIME_ZERO || time_fn > SBPE_TIME_RICKER) return fail3(c, SBPE_EINVAL, "bad time function");
+    auto& F = c->face[face];
+    F.kind = bc;
+    if (g) F.g.assign(g, g + 3L * c->nf(face));
+    else F.g.clear();
+    set_time_fn(time_fn, tp, F.tf);
+    return SBPE_OK;
+}
+
+sbpe_status sbpe3_set_forcing(sbpe3_ctx_t c, const double* F, int time_fn, const double* tp) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail3(c, SBPE_ESTATE, "context already finalized");
+    if (c->n[0] == 0) return fail3(c, SBPE_ESTATE, "no block");
+    if (time_fn < SBPE_TIME_ZERO || time_fn > SBPE_TIME_RICKER) return fail3(c, SBPE_EINVAL, "bad time function");
+    if (F) c->force.assign(F, F + 3 * c->np());
+    else c->force.clear();
+    set_time_fn(time_fn, tp, c->ftf);
+    return SBPE_OK;
+}
+
+sbpe_status sbpe3_finalize(sbpe3_ctx_t c) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (c->finalized) return fail3(c, SBPE_ESTATE, "context already finalized");
+    if (c->n[0] == 0) return fail3(c, SBPE_ESTATE, "no block");
+    const int o = c->order;
+    const long np = c->np();
+    const int* n = c->n;
+    const long st[3] = {1, n[0], (long)n[0] * n[1]};
+    for (int i = 0; i < 3; ++i) c->h[i] = 1.0 / (n[i] - 1);
+    // A[i][I] = dX_I / dx_i along every line of direction i
+    std::vector<hvec> A(9);
+    for (auto& a : A) a.resize(np);
+    for (int i = 0; i < 3; ++i) {
+        const int j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+#pragma omp parallel for schedule(static) collapse(2)
+        for (int b = 0; b < n[j2]; ++b)
+            for (int a = 0; a < n[j1]; ++a) {
+                const long s0 = (long)a * st[j1] + (long)b * st[j2];
+                for (int I = 0; I < 3; ++I)
+                    d1_apply(o, n[i], c->h[i], &c->X[I][s0], st[i], &A[3 * i + I][s0], st[i]);
+            }
+    }
+    c->coef.assign((size_t)NCOEF3 * np, 0.0);
+    std::vector<double> Jv(np);
+    long bad_j = -1, bad_c = -1;
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < np; ++p) {
+        double M[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int I = 0; I < 3; ++I) M[i][I] = A[3 * i + I][p];
+        const double J = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                         M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                         M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+        if (!(J > 0.0)) {
+#pragma omp critical
+            bad_j = (bad_j < 0 || p < bad_j) ? p : bad_j;
+            continue;
+        }
+        Jv[p] = J;
+        // F[I][i] = dx_i / dX_I = (M^{-1})[I][i]
+        double F[3][3];
+        for (int I = 0; I < 3; ++I)
+            for (int i = 0; i < 3; ++i) {
+                const int r1 = (i + 1) % 3, r2 = (i + 2) % 3, c1 = (I + 1) % 3, c2 = (I + 2) % 3;
+                F[I][i] = (M[r1][c1] * M[r2][c2] - M[r1][c2] * M[r2][c1]) / J;
+            }
+        const double* C = c->C81.data();
+        std::vector<double> Cm(81);
+        for (int k = 0; k < 81; ++k) Cm[k] = C[(long)k * np + p];
+        bool sym = true;
+        for (int a = 0; a < 9 && sym; ++a)
+            for (int b = 0; b < 9; ++b)
+                if (std::fabs(Cm[a * 9 + b] - Cm[b * 9 + a]) > 1e-12 * (std::fabs(Cm[a * 9 + b]) + 1.0)) sym = false;
+        if (!sym || !psd_n(Cm, 9, 1e-10)) {
+#pragma omp critical
+            bad_c = (bad_c < 0 || p < bad_c) ? p : bad_c;
+            continue;
+        }
+        // c_ijkl = J F_Ii C_IjKl F_Kk
+        auto cc = [&](int i, int j, int k, int l) {
+            double s = 0.0;
+            for (int I = 0; I < 3; ++I)
+                for (int K = 0; K < 3; ++K) s += F[I][i] * Cm[((I * 3 + j) * 3 + K) * 3 + l] * F[K][k];
+            return J * s;
+        };
+        double* q = c->coef.data();
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                for (int l = j; l < 3; ++l) q[(long)f3N(i, j, l) * np + p] = cc(i, j, i, l);
+        for (int i = 0; i < 3; ++i)
+            for (int k = i + 1; k < 3; ++k)
+                for (int j = 0; j < 3; ++j)
+                    for (int l = 0; l < 3; ++l) q[(long)f3M(i, k, j, l) * np + p] = cc(i, j, k, l);
+        q[(long)45 * np + p] = 1.0 / (J * c->rho[p]);
+    }
+    if (bad_j >= 0) return fail3(c, SBPE_ENONPOS_J, "discrete Jacobian <= 0 at point " + std::to_string(bad_j));
+    if (bad_c >= 0)
+        return fail3(c, SBPE_ENOT_PSD, "stiffness not major symmetric positive semidefinite at point " + std::to_string(bad_c));
+    if (hipSetDevice(c->device) != hipSuccess) return fail3(c, SBPE_EHIP, "hipSetDevice failed");
+    sbpe_status s = upload3(c, c->coef.data(), c->coef.size(), &c->d_coef);
+    if (s) return s;
+    if (!c->force.empty()) {
+        std::vector<double> JF(3 * np);
+        for (int j = 0; j < 3; ++j)
+            for (long p = 0; p < np; ++p) JF[(size_t)j * np + p] = Jv[p] * c->force[(size_t)j * np + p];
+        s = upload3(c, JF.data(), JF.size(), &c->d_force);
+        if (s) return s;
+    }
+    // faces: first norm weight of the normal direction, Jhat = |a_t1 x a_t2|
+    for (int f = 0; f < 6; ++f) {
+        const int a = f >> 1, t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+        c->w[f] = c->h[a] * norm_weight(o, n[a], 0);
+        auto& F = c->face[f];
+        if (F.g.empty()) continue;
+        const int nf = c->nf(f);
+        std::vector<double> g(F.g);
+        if (F.kind == SBPE_BC_TRACTION) {
+            const int cn = (f & 1) ? n[a] - 1 : 0;
+            for (int b = 0; b < n[t2]; ++b)
+                for (int aa = 0; aa < n[t1]; ++aa) {
+                    const long p = (long)cn * st[a] + (long)aa * st[t1] + (long)b * st[t2];
+                    const double x[3] = {A[3 * t1][p], A[3 * t1 + 1][p], A[3 * t1 + 2][p]};
+                    const double y[3] = {A[3 * t2][p], A[3 * t2 + 1][p], A[3 * t2 + 2][p]};
+                    const double cr[3] = {x[1] * y[2] - x[2] * y[1], x[2] * y[0] - x[0] * y[2], x[0] * y[1] - x[1] * y[0]};
+                    const double jh = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+                    const int t = aa + n[t1] * b;
+                    for (int j = 0; j < 3; ++j) g[(size_t)j * nf + t] *= jh / c->w[f];
+                }
+        }
+        s = upload3(c, g.data(), g.size(), &c->d_g[f]);
+        if (s) return s;
+    }
+    const size_t es = c->dtype == SBPE_F64 ? 8 : 4;
+    if (d3malloc(&c->d_a1, 3 * np * es) != hipSuccess || d3malloc(&c->d_a2, 3 * np * es) != hipSuccess)
+        return fail3(c, SBPE_ENOMEM, "device allocation failed");
+    c->finalized = true;
+    return SBPE_OK;
+}
+
+// dt = cfl min h / v_max, v_max^2 = max over directions xi and points of
+// lambda_max(xi_i c_ijkl xi_k) / rho~ (2000 directions of a Fibonacci sphere)
+sbpe_status sbpe3_dt_cfl(sbpe3_ctx_t c, double cfl, double* dt) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->finalized) return fail3(c, SBPE_ESTATE, "context not finalized");
+    if (!dt || !(cfl > 0)) return fail3(c, SBPE_EINVAL, "bad arguments");
+    const long np = c->np();
+    const int ndir = 2000;
+    std::vector<double> xi(3 * ndir);
+    for (int d = 0; d < ndir; ++d) {
+        const double k = d + 0.5, z = 1.0 - 2.0 * k / ndir, r = std::sqrt(1.0 - z * z);
+        const double ph = M_PI * (1.0 + std::sqrt(5.0)) * k;
+        xi[3 * d] = r * std::cos(ph);
+        xi[3 * d + 1] = r * std::sin(ph);
+        xi[3 * d + 2] = z;
+    }
+    const double* q = c->coef.data();
+    double best = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : best)
+    for (long p = 0; p < np; ++p) {
+        double cc[3][3][3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < 3; ++j)
+                    for (int l = 0; l < 3; ++l)
+                        cc[i][j][k][l] = i == k ? q[(long)f3N(i, j, l) * np + p] : q[(long)f3M(i, k, j, l) * np + p];
+        const double irho = q[(long)45 * np + p];
+        for (int d = 0; d < ndir; ++d) {
+            double G[3][3];
+            for (int j = 0; j < 3; ++j)
+                for (int l = 0; l < 3; ++l) {
+                    double s = 0.0;
+                    for (int i = 0; i < 3; ++i)
+                        for (int k = 0; k < 3; ++k) s += xi[3 * d + i] * cc[i][j][k][l] * xi[3 * d + k];
+                    G[j][l] = s;
+                }
+            best = std::max(best, lmax3(G) * irho);
+        }
+    }
+    *dt = cfl * std::min(c->h[0], std::min(c->h[1], c->h[2])) / std::sqrt(best);
+    return SBPE_OK;
+}
+
+static Args3 args3(const sbpe3_ctx* c) {
+    Args3 a;
+    std::memset(&a, 0, sizeof a);
+    a.n1 = c->n[0];
+    a.n2 = c->n[1];
+    a.n3 = c->n[2];
+    a.h1 = c->h[0];
+    a.h2 = c->h[1];
+    a.h3 = c->h[2];
+    a.beta = c->beta;
+    a.coef = c->d_coef;
+    a.force = c->d_force;
+    for (int f = 0; f < 6; ++f) {
+        a.face[f].kind = c->face[f].kind;
+        a.face[f].nf = c->nf(f);
+        a.face[f].w = c->w[f];
+        a.face[f].g = c->d_g[f];
+    }
+    a.a1 = c->d_a1;
+    a.a2 = c->d_a2;
+    return a;
+}
+
+// time values of the 6 face items and the forcing at time t
+static void tvals3(const sbpe3_ctx* c, double t, double out[7]) {
+    for (int f = 0; f < 6; ++f) out[f] = c->face[f].g.empty() ? 0.0 : tf_host(c->face[f].tf, t);
+    out[6] = c->force.empty() ? 0.0 : tf_host(c->ftf, t);
+}
+
+sbpe_status sbpe3_apply(sbpe3_ctx_t c, const void* u, void* a, double t, int homogeneous) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->finalized) return fail3(c, SBPE_ESTATE, "context not finalized");
+    if (!u || !a || u == a) return fail3(c, SBPE_EINVAL, "bad operands");
+    Args3 A = args3(c);
+    A.pass = PASS_APPLY;
+    A.in = u;
+    A.out = a;
+    if (!homogeneous) tvals3(c, t, A.tfa);
+    const int e = launch_point3(c->dtype, c->order, A, c->stream);
+    if (e) return fail3(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+sbpe_status sbpe3_bind_state(sbpe3_ctx_t c, void* u, void* v, double t) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->finalized) return fail3(c, SBPE_ESTATE, "context not finalized");
+    if (!u || !v || u == v) return fail3(c, SBPE_EINVAL, "bad state buffers");
+    c->u = u;
+    c->v = v;
+    c->t = t;
+    c->bound = true;
+    return SBPE_OK;
+}
+
+// classical RK4 in the two sweeps of sbpe_internal.h, data at t, t + dt/2, t + dt
+sbpe_status sbpe3_advance(sbpe3_ctx_t c, int nsteps, double dt) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->bound) return fail3(c, SBPE_ESTATE, "no bound state");
+    if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail3(c, SBPE_EINVAL, "bad nsteps or dt");
+    for (int k = 0; k < nsteps; ++k) {
+        const double t = c->t;
+        double v0[7], vh[7], v1[7];
+        tvals3(c, t, v0);
+        tvals3(c, t + 0.5 * dt, vh);
+        tvals3(c, t + dt, v1);
+        Args3 A = args3(c);
+        A.dt = dt;
+        A.u = c->u;
+        A.v = c->v;
+        A.uo = c->u;
+        A.vo = c->v;
+        A.pass = PASS_RK1;
+        for (int q = 0; q < 7; ++q) {
+            A.tfa[q] = v0[q];
+            A.tfb[q] = vh[q];
+        }
+        int e = launch_point3(c->dtype, c->order, A, c->stream);
+        if (e) return fail3(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+        A.pass = PASS_RK2;
+        for (int q = 0; q < 7; ++q) {
+            A.tfa[q] = 0.0;
+            A.tfb[q] = 2.0 / (dt * dt) * (v0[q] - 2.0 * vh[q] + v1[q]);
+        }
+        e = launch_point3(c->dtype, c->order, A, c->stream);
+        if (e) return fail3(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
+        c->t = t + dt;
+    }
+    return SBPE_OK;
+}
+
+sbpe_status sbpe3_get_time(sbpe3_ctx_t c, double* t) {
+    if (!c || !t) return fail3(c, SBPE_EINVAL, "NULL argument");
+    *t = c->t;
+    return SBPE_OK;
+}
+
+sbpe_status sbpe3_synchronize(sbpe3_ctx_t c) {
+    if (!c) return fail3(nullptr, SBPE_EINVAL, "NULL context");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail3(c, SBPE_EHIP, "hipStreamSynchronize failed");
+    return SBPE_OK;
+}
+
+}  // extern "C"

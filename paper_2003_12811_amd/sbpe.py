@@ -89,6 +89,19 @@ _PROTOS = {
     'sbpe_batch_remaining': [_P, _P, _IP],
     'sbpe_batch_info': [_P, _IP, _IP, ctypes.POINTER(ctypes.c_longlong)],
     'sbpe_batch_synchronize': [_P],
+    # the 3-D path (include/sbpe3.h)
+    'sbpe3_create': [_I, _P, _I, _I, _D, ctypes.POINTER(_P)],
+    'sbpe3_destroy': [_P],
+    'sbpe3_set_block': [_P, _I, _I, _I, _DP, _DP, _DP, _DP, _DP],
+    'sbpe3_set_bc': [_P, _I, _I, _DP, _I, _DP],
+    'sbpe3_set_forcing': [_P, _DP, _I, _DP],
+    'sbpe3_finalize': [_P],
+    'sbpe3_dt_cfl': [_P, _D, _DP],
+    'sbpe3_apply': [_P, _P, _P, _D, _I],
+    'sbpe3_bind_state': [_P, _P, _P, _D],
+    'sbpe3_advance': [_P, _I, _D],
+    'sbpe3_get_time': [_P, _DP],
+    'sbpe3_synchronize': [_P],
 }
 
 
@@ -108,6 +121,8 @@ def lib():
         L.sbpe_last_error.restype = ctypes.c_char_p
         L.sbpe_batch_last_error.argtypes = [_P]
         L.sbpe_batch_last_error.restype = ctypes.c_char_p
+        L.sbpe3_last_error.argtypes = [_P]
+        L.sbpe3_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -420,3 +435,77 @@ def sbpe_batch_info(batch):
 
 def sbpe_batch_synchronize(batch):
     _bcheck(batch, lib().sbpe_batch_synchronize(batch))
+
+
+# ------------------------------------------------------------------- 3-D
+def _check3(ctx, code):
+    if code != OK:
+        msg = lib().sbpe3_last_error(ctx)
+        raise SbpeError(code, msg.decode() if msg else '')
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def sbpe3_create(device, stream, dtype, order, beta=1.0):
+    out = _P()
+    _check3(None, lib().sbpe3_create(device, _P(int(stream)) if stream else None, dtype, order, beta,
+                                     ctypes.byref(out)))
+    return out
+
+
+def sbpe3_destroy(ctx):
+    _check3(ctx, lib().sbpe3_destroy(ctx))
+
+
+def sbpe3_set_block(ctx, X1, X2, X3, rho, C81):
+    X1, X2, X3, rho, C81 = (_c64(a) for a in (X1, X2, X3, rho, C81))
+    n3, n2, n1 = X1.shape
+    if C81.shape != (81, n3, n2, n1) and C81.shape != (3, 3, 3, 3, n3, n2, n1):
+        raise ValueError('C81 must be [81][n3][n2][n1]')
+    _check3(ctx, lib().sbpe3_set_block(ctx, n1, n2, n3, _dp(X1), _dp(X2), _dp(X3), _dp(rho), _dp(C81)))
+
+
+def sbpe3_set_bc(ctx, face, bc, g=None, time_fn=TIME_ZERO, time_params=None):
+    g = None if g is None else _c64(g)
+    tp = None if time_params is None else _c64(time_params)
+    _check3(ctx, lib().sbpe3_set_bc(ctx, face, bc, _dp(g), time_fn, _dp(tp)))
+
+
+def sbpe3_set_forcing(ctx, F, time_fn=TIME_ONE, time_params=None):
+    F = None if F is None else _c64(F)
+    tp = None if time_params is None else _c64(time_params)
+    _check3(ctx, lib().sbpe3_set_forcing(ctx, _dp(F), time_fn, _dp(tp)))
+
+
+def sbpe3_finalize(ctx):
+    _check3(ctx, lib().sbpe3_finalize(ctx))
+
+
+def sbpe3_dt_cfl(ctx, cfl):
+    dt = ctypes.c_double()
+    _check3(ctx, lib().sbpe3_dt_cfl(ctx, cfl, ctypes.byref(dt)))
+    return dt.value
+
+
+def sbpe3_apply(ctx, u_ptr, a_ptr, t=0.0, homogeneous=False):
+    _check3(ctx, lib().sbpe3_apply(ctx, _P(int(u_ptr)), _P(int(a_ptr)), t, 1 if homogeneous else 0))
+
+
+def sbpe3_bind_state(ctx, u_ptr, v_ptr, t=0.0):
+    _check3(ctx, lib().sbpe3_bind_state(ctx, _P(int(u_ptr)), _P(int(v_ptr)), t))
+
+
+def sbpe3_advance(ctx, nsteps, dt):
+    _check3(ctx, lib().sbpe3_advance(ctx, nsteps, dt))
+
+
+def sbpe3_get_time(ctx):
+    t = ctypes.c_double()
+    _check3(ctx, lib().sbpe3_get_time(ctx, ctypes.byref(t)))
+    return t.value
+
+
+def sbpe3_synchronize(ctx):
+    _check3(ctx, lib().sbpe3_synchronize(ctx))

@@ -458,3 +458,35 @@ def smooth_direction(X1, X2, seed, nmodes=4, kmax=3):
             s += a[m] * np.cos(2.0 * np.pi * (kx[m] * X1 + ky[m] * X2) + ph[m])
         out.append(s / nmodes)
     return out[0], np.stack(out[1:])
+
+
+# ---------------------------------------------------------------- 3-D inputs
+def grid3(n1, n2, n3, eps=0.04):
+    """Curvilinear map of the unit cube: arrays (n3, n2, n1), x1 fastest."""
+    x3, x2, x1 = np.meshgrid(np.linspace(0, 1, n3), np.linspace(0, 1, n2), np.linspace(0, 1, n1), indexing='ij')
+    bump = eps * np.sin(np.pi * x1) * np.sin(np.pi * x2) * np.sin(np.pi * x3)
+    return x1 + bump, x2 + 0.6 * bump + eps * x3 * x1, x3 - 0.8 * bump
+
+
+def random_material3(shape, seed, minor=False):
+    """rho (shape) and C [81][shape]: a random positive definite 9 x 9 matrix
+    (major symmetric; with minor=True from a 6 x 6 Voigt matrix, so also minor
+    symmetric) times a smooth positive variation."""
+    rng = np.random.default_rng(seed)
+    if minor:
+        Q = rng.normal(size=(6, 6))
+        V = Q @ Q.T / 6 + np.eye(6)
+        vi = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+        M = np.zeros((9, 9))
+        for a, (i, j) in enumerate(vi):
+            for b, (k, l) in enumerate(vi):
+                for (p, q) in {(i, j), (j, i)}:
+                    for (r, s) in {(k, l), (l, k)}:
+                        M[3 * p + q, 3 * r + s] = V[a, b]
+    else:
+        Q = rng.normal(size=(9, 9))
+        M = Q @ Q.T / 9 + np.eye(9)
+    k = np.arange(int(np.prod(shape))).reshape(shape)
+    var = 1.0 + 0.2 * np.sin(0.37 * k)
+    rho = 1.0 + 0.3 * np.cos(0.11 * k)
+    return rho, M.reshape(81, *([1] * len(shape))) * var

@@ -1,0 +1,158 @@
+"""The 3-D path (include/sbpe3.h) against the 3-D oracle, through the C ABI.
+
+One curvilinear block with a random major-symmetric stiffness, traction and
+displacement faces carrying data with a time function, and a body force:
+* one right-hand-side evaluation (sbpe3_apply) at orders 2 and 4, FP64 (1e-11
+  relative L2, and the max norm on the points next to the faces) and FP32
+  (1e-5, on inputs shared bit for bit), with and without the data;
+* RK4 steps (sbpe3_advance, the two-sweep form) against the oracle's literal
+  classical RK4 (Sec. 7.1).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import elastic3d as E3
+from oracle import spec as OS
+from oracle import timestep as T
+from paper_2003_12811_amd import sbpe as S
+from paper_2003_12811_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = {'f64': 1e-11, 'f32': 1e-5}
+KINDS = [S.BC_DISPLACEMENT, S.BC_TRACTION, S.BC_TRACTION, S.BC_DISPLACEMENT, S.BC_TRACTION, S.BC_DISPLACEMENT]
+TFN = [(S.TIME_COS, (3.0, 0.2)), (S.TIME_RICKER, (4.0, 0.1)), (S.TIME_COS, (2.0, -0.4)), (S.TIME_ONE, None),
+       (S.TIME_COS, (1.5, 0.7)), (S.TIME_ZERO, None)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _case(n, order, seed=4):
+    X = W.grid3(*n)
+    rho, C = W.random_material3(X[0].shape, seed)
+    rng = np.random.default_rng(seed)
+    faces = []
+    for f in range(6):
+        a = f >> 1
+        nt = [m for k, m in enumerate(n) if k != a]
+        g = rng.normal(size=(3, nt[0] * nt[1]))
+        faces.append((KINDS[f], g) + TFN[f])
+    F = rng.normal(size=(3,) + X[0].shape)
+    return X, rho, C, faces, (F, S.TIME_COS, (1.3, 0.5))
+
+
+def _oracle(X, rho, C, faces, force, order):
+    B = E3.Block3D(*X, rho, C.reshape((3, 3, 3, 3) + X[0].shape), order=order)
+    P = E3.Problem3D(B)
+    for f, (kind, g, tk, tp) in enumerate(faces):
+        P.set_bc(f, E3.DISPLACEMENT if kind == S.BC_DISPLACEMENT else E3.TRACTION, g=g, tfun=OS.tfun(tk, tp))
+    Fs, tk, tp = force
+    P.forcing = (Fs, OS.tfun(tk, tp))
+    return P
+
+
+def _library(X, rho, C, faces, force, order, dtype):
+    import torch
+    ctx = S.sbpe3_create(0, torch.cuda.current_stream().cuda_stream, S.F64 if dtype == 'f64' else S.F32, order)
+    S.sbpe3_set_block(ctx, *X, rho, C)
+    for f, (kind, g, tk, tp) in enumerate(faces):
+        S.sbpe3_set_bc(ctx, f, kind, g, tk, tp)
+    Fs, tk, tp = force
+    S.sbpe3_set_forcing(ctx, Fs, tk, tp)
+    S.sbpe3_finalize(ctx)
+    return ctx
+
+
+def _band_max(a, b, n, depth):
+    """max |a - b| / max |b| over the points within `depth` of a face"""
+    m = np.zeros(a.shape[1:], dtype=bool)
+    for ax in range(3):
+        sl = [slice(None)] * 3
+        sl[ax] = slice(0, depth)
+        m[tuple(sl)] = True
+        sl[ax] = slice(-depth, None)
+        m[tuple(sl)] = True
+    return np.abs(a - b)[:, m].max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+@pytest.mark.parametrize("order,n", [(2, (9, 10, 8)), (4, (13, 15, 14))])
+def test_apply_matches_oracle(order, n, dtype):
+    import torch
+    X, rho, C, faces, force = _case(n, order)
+    P = _oracle(X, rho, C, faces, force, order)
+    ctx = _library(X, rho, C, faces, force, order, dtype)
+    tdt = torch.float64 if dtype == 'f64' else torch.float32
+    try:
+        rng = np.random.default_rng(7)
+        u = rng.normal(size=(3,) + X[0].shape)
+        if dtype == 'f32':
+            u = u.astype(np.float32).astype(np.float64)     # the oracle takes the rounded input
+        ud = torch.tensor(u, dtype=tdt, device='cuda')
+        ad = torch.empty_like(ud)
+        for t, hom in ((0.37, False), (0.0, True)):
+            S.sbpe3_apply(ctx, ud.data_ptr(), ad.data_ptr(), t, hom)
+            S.sbpe3_synchronize(ctx)
+            ag = ad.double().cpu().numpy()
+            if hom:
+                B = P.block
+                ao = (P.total_operator(u) / B.rho.ravel()).reshape(ag.shape)
+            else:
+                ao = P.rhs([u], t)[0]
+            e, eb = rel(ag, ao), _band_max(ag, ao, n, 6 if order == 4 else 2)
+            say('3-D apply order %d %s %s: rel L2 %.2e, band max %.2e' % (order, dtype, 'hom' if hom else 'data', e, eb))
+            assert e < TOL[dtype] and eb < 10 * TOL[dtype]
+    finally:
+        S.sbpe3_destroy(ctx)
+
+
+@pytest.mark.parametrize("dtype", ['f64', 'f32'])
+def test_advance_matches_oracle_rk4(dtype):
+    import torch
+    order, n, nsteps = 4, (13, 14, 13), 6
+    X, rho, C, faces, force = _case(n, order, seed=8)
+    P = _oracle(X, rho, C, faces, force, order)
+    ctx = _library(X, rho, C, faces, force, order, dtype)
+    tdt = torch.float64 if dtype == 'f64' else torch.float32
+    try:
+        dt = S.sbpe3_dt_cfl(ctx, 0.5)
+        rng = np.random.default_rng(2)
+        u0 = 0.1 * rng.normal(size=(3,) + X[0].shape)
+        v0 = 0.1 * rng.normal(size=(3,) + X[0].shape)
+        if dtype == 'f32':
+            u0, v0 = (x.astype(np.float32).astype(np.float64) for x in (u0, v0))
+        ud = torch.tensor(u0, dtype=tdt, device='cuda')
+        vd = torch.tensor(v0, dtype=tdt, device='cuda')
+        S.sbpe3_bind_state(ctx, ud.data_ptr(), vd.data_ptr(), 0.1)
+        S.sbpe3_advance(ctx, nsteps, dt)
+        S.sbpe3_synchronize(ctx)
+        assert abs(S.sbpe3_get_time(ctx) - (0.1 + nsteps * dt)) < 1e-12
+        u, v, t = [u0], [v0], 0.1
+        for _ in range(nsteps):
+            u, v = T.rk4_step(P, u, v, t, dt)
+            t += dt
+        eu = rel(ud.double().cpu().numpy(), u[0])
+        ev = rel(vd.double().cpu().numpy(), v[0])
+        say('3-D advance %s, %d steps of %.3e: rel L2 u %.2e v %.2e' % (dtype, nsteps, dt, eu, ev))
+        assert eu < TOL[dtype] and ev < TOL[dtype]
+    finally:
+        S.sbpe3_destroy(ctx)
+
+
+def test_dt_matches_oracle():
+    import torch
+    X, rho, C, faces, force = _case((13, 13, 13), 4)
+    P = _oracle(X, rho, C, faces, force, 4)
+    ctx = _library(X, rho, C, faces, force, 4, 'f64')
+    try:
+        assert S.sbpe3_dt_cfl(ctx, 0.5) == pytest.approx(E3.dt_cfl(P.block, 0.5), rel=1e-10)
+    finally:
+        S.sbpe3_destroy(ctx)
+    torch.cuda.synchronize()

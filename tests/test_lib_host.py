@@ -25,6 +25,10 @@ def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, 'include', 'sbpe.h')).read()
     names = set(re.findall(r'\b(sbpe_[a-z0-9_]+)\s*\(', hdr))
     assert len(names) >= 25
+    hdr3 = open(os.path.join(ROOT, 'include', 'sbpe3.h')).read()
+    names3 = set(re.findall(r'\b(sbpe3_[a-z0-9_]+)\s*\(', hdr3))
+    assert len(names3) >= 12
+    names |= names3
     L = S.lib()
     missing = [n for n in sorted(names) if not hasattr(L, n)]
     assert not missing, missing

@@ -459,7 +459,7 @@ def main():
         sp3 = W.spec_c3(n=n)
         log('  built in %.1f s' % (time.time() - t0))
         log('headline, fp64')
-        r3, sh3, tb3 = section(sp3, 'f64', args, (10, 20), (1,), 20, 0, True, fixed)
+        r3, sh3, tb3 = section(sp3, 'f64', args, (20,), (1,), 20, 0, True, fixed)
         k3 = dominant(r3)
         pts3 = swept_points(r3['plan'])
         line.update({

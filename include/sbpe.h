@@ -312,6 +312,29 @@ sbpe_status sbpe_plan_info(sbpe_ctx_t ctx, long long* info);
 sbpe_status sbpe_grad_accumulate(sbpe_ctx_t ctx, const void* const* z, const void* const* y, const void* const* a,
                                  double alpha, double t, int homogeneous, void* const* gc, void* const* grt);
 
+/* The four stages of one classical RK4 step (Sec. 7.1) in one call: stage s =
+ * 0..3 at time t + c_s dt, c = (0, 1/2, 1/2, 1), accumulates as
+ * sbpe_grad_accumulate with z[s*nb + b], y[s*nb + b], a[s*nb + b] and
+ * alpha[s] (nb = number of blocks; alpha: 4 host values).  The stages are
+ * summed before they are added to gc and grt, so results equal four single
+ * calls up to rounding.  Band partial sums go to a context buffer of
+ * 4 * 11 * (points within the closure width of a face) FP64 values, allocated
+ * on the first call and kept (the allocation synchronises the stream).
+ * Errors as sbpe_grad_accumulate. */
+sbpe_status sbpe_grad_accumulate_rk4(sbpe_ctx_t ctx, const void* const* z, const void* const* y,
+                                     const void* const* a, const double* alpha, double t, double dt,
+                                     int homogeneous, void* const* gc, void* const* grt);
+
+/* Device pointers to the RK4 stage slopes of block `block` in the context's
+ * workspace ([2][n2][n1] each, context dtype, owned by the context): after
+ * sbpe_advance, *a1 = rho~^{-1} (L u + data(t)) and *a2 = rho~^{-1}
+ * (L (u + dt/2 v) + data(t + dt/2)) of its last step, evaluated at that
+ * step's initial state (u, v).  Valid until the next call on the context that
+ * sweeps (sbpe_advance, batches) or evaluates the energy.  The discrete adjoint
+ * rebuilds the stage displacements u + dt/2 v + dt^2/4 a1 and
+ * u + dt v + dt^2/2 a2 from them.  SBPE_ESTATE before sbpe_finalize. */
+sbpe_status sbpe_stage_slopes(sbpe_ctx_t ctx, int block, void** a1, void** a2);
+
 /* Chain rule of one block to the physical parameters, c = F J C F and
  * rho~ = J rho (Sec. 3.2.1): gc, grt device arrays as above; g_c10 host
  * [10][n2][n1] in the C10 order of sbpe_add_block (C treated as major
@@ -324,6 +347,24 @@ sbpe_status sbpe_grad_to_physical(sbpe_ctx_t ctx, int block, const void* gc, con
  * formed in FP64. */
 sbpe_status sbpe_lincomb(sbpe_ctx_t ctx, int nterms, const double* coefs, const void* const* x, void* y,
                          long long count);
+
+/* Stage values of one classical RK4 step (Sec. 7.1) of u'' = a(u), rebuilt
+ * elementwise over count values of the context dtype (device pointers) from
+ * the state (u0, v0) at t, the state (u1, v1) at t + dt and the first two
+ * stage slopes a1, a2 (sbpe_stage_slopes):
+ *   out[0] U2 = u0 + dt/2 v0,   out[1] U3 = U2 + dt^2/4 a1,
+ *   out[2] U4 = u0 + dt v0 + dt^2/2 a2,   out[3] = a1,   out[4] = a2,
+ *   out[5] a3 = 6 (u1 - u0 - dt v0) / dt^2 - a1 - a2,
+ *   out[6] a4 = 6 (v1 - v0) / dt - a1 - 2 a2 - 2 a3,
+ * the last two solved from the step's update u1 = u0 + dt v0 + dt^2/6 (a1 +
+ * a2 + a3), v1 = v0 + dt/6 (a1 + 2 a2 + 2 a3 + a4).  Arithmetic in FP64; the
+ * difference u1 - u0 - dt v0 is of size dt^2 a, so a3 carries a relative
+ * rounding error of about 6 eps / (omega dt)^2 for a solution of angular
+ * frequency omega (1e-13 in FP64 for the differentiation workload's step).
+ * out: 7 pointers, NULL entries are not written; u1, v1 may be NULL when
+ * out[5] and out[6] are.  SBPE_EINVAL for dt <= 0 or a missing input. */
+sbpe_status sbpe_rk4_stages(sbpe_ctx_t ctx, const void* u0, const void* v0, const void* u1, const void* v1,
+                            const void* a1, const void* a2, double dt, void* const* out, long long count);
 
 /* u[b] += scale * (H rho~)^{-1} S^T r, the adjoint of the receiver sampling
  * (Sec. 7.4) in the scaled variables: r is FP64 device [nrec][2] in the order

@@ -7,16 +7,21 @@ gradient is the exact derivative of the discrete map (up to rounding):
 
 * Forward: ``sbpe_advance`` with a checkpoint of (u, v, t) every
   ``checkpoint_every`` steps; J from the recorded receiver traces.
-* Reverse, segment by segment from the last checkpoint: the segment's states
-  are recomputed with ``sbpe_advance``, each step's stages with the stage form
-  of RK4 (``sbpe_apply`` with the data at the stage times, ``sbpe_lincomb``
-  for the stage combinations), then each step is reversed: with b = (1/6, 1/3, 1/3, 1/6), c = (0, 1/2, 1/2, 1), the
-  stage-slope adjoints k_i = dt b_i y^ are propagated from the last stage to
-  the first through (u, v) -> (L^T v, u).  Because H L is symmetric (the energy
-  analysis of Sec. 5), in the variables y^ = y / (H rho~) the transpose is the
-  forward operator itself, so ``sbpe_apply`` (homogeneous) advances the
-  adjoint state.  Each stage adds its parameter term with
-  ``sbpe_grad_accumulate``; the receiver residuals enter through
+* Reverse, segment by segment from the last checkpoint: the segment's steps
+  are recomputed in the stage form of RK4 (``sbpe_apply`` with the data at
+  the stage times, ``sbpe_lincomb`` for the stage combinations), keeping each
+  step's stage displacements U_i and stage values A_i.  Then each step is
+  reversed.  With b = (1/6, 1/3, 1/3, 1/6) and c = (0, 1/2, 1/2, 1), the
+  stage-slope adjoints of classical RK4 are k^_{5-j} = dt b_{5-j} Y^_j, with
+  Y^_j the stages of one RK4 step of y' = A^T y from the adjoint state y^,
+  which that step advances.  Because H L is symmetric (the energy analysis of
+  Sec. 5), in the variables y^ = y / (H rho~) L^T = L, so A^T = s A s with
+  s (u, v) = (v, u): the adjoint step is one forward step of the homogeneous
+  problem on the swapped state (v^, u^), which ``sbpe_advance`` on a data-free
+  context performs with its two sweeps.  The stage displacements of that step
+  (rebuilt from ``sbpe_stage_slopes``) are the velocity parts of the stage
+  adjoints, which ``sbpe_grad_accumulate_rk4`` pairs with the forward U_i and
+  A_i of the step; the receiver residuals enter through
   ``sbpe_receiver_adjoint``.
 * ``sbpe_grad_to_physical`` maps the gradients with respect to the stored
   c = F J C F and rho~ = J rho to C (C10 layout) and rho.
@@ -26,6 +31,8 @@ step must not depend on the parameters being differentiated), and
 ``SeismicMisfit`` exposes it as a ``torch.autograd.Function``: its forward
 runs the forward pass (with checkpoints) only, its backward the adjoint.
 """
+import ctypes
+
 import numpy as np
 
 from . import sbpe as S
@@ -33,6 +40,19 @@ from .solver import Solver
 
 B_RK = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
 C_RK = (0.0, 0.5, 0.5, 1.0)
+
+
+def homogeneous_spec(spec):
+    """The problem of `spec` with every data term removed (boundary data,
+    forcing, sources, receivers, interface jump data): the same operator."""
+    sp = {k: v for k, v in spec.items() if k not in ('sources', 'receivers', 'interface_data')}
+    blocks = []
+    for b in spec['blocks']:
+        nb = {k: v for k, v in b.items() if k != 'forcing'}
+        nb['bc'] = [(kind, None, None, None, U) for (kind, g, tfn, tp, U) in b['bc']]
+        blocks.append(nb)
+    sp['blocks'] = blocks
+    return sp
 
 
 class MisfitGradient:
@@ -50,6 +70,7 @@ class MisfitGradient:
         self.torch = torch
         self.spec, self.nsteps, self.dt = spec, nsteps, dt
         self.K = max(1, int(checkpoint_every))
+        self.dtype = dtype
         self.sol = Solver(spec, dtype, device=device)
         self.dev = self.sol.device
         self.tdt = self.sol.tdtype
@@ -62,9 +83,6 @@ class MisfitGradient:
         self.sol.close()
 
     # ------------------------------------------------------------ helpers
-    def _new(self):
-        return self.torch.empty(self.shape, dtype=self.tdt, device=self.dev)
-
     def _apply(self, x, t, homogeneous, out):
         S.sbpe_apply(self.sol.ctx, [x.data_ptr()], [out.data_ptr()], t, homogeneous)
 
@@ -91,75 +109,93 @@ class MisfitGradient:
     def gradient(self):
         """(dJ/drho (n2, n1), dJ/dC10 (10, n2, n1)) after ``forward``.
 
-        Per step, with stage slopes k_i = (V_i, A_i) and their adjoints
-        (ku_i, kv_i), from the last stage to the first:
-            ku_i = dt b_i uh + dt c_{i+1} Yu_{i+1},  kv_i = dt b_i vh + dt c_{i+1} ku_{i+1},
-            Yu_i = L kv_i (scaled variables),
-        then uh <- uh + sum_i Yu_i and vh <- vh + sum_i ku_i.  The states of a
-        checkpoint segment are recomputed with ``sbpe_advance``; every work
-        buffer is allocated once.  The buffers are laid out so that every
-        pair of combinations is one ``sbpe_lincomb`` over both halves:
-        stage i holds Z_i = (U_i, V_i, A_i) and M_i = (Yu_i, ku_i, kv_i), the
-        adjoint state W = (uh, vh), so that
-            (U_{i+1}, V_{i+1}) = (u, v) + dt c_{i+1} (V_i, A_i)  = Z_0[0:2] + dt c_{i+1} Z_i[1:3],
-            (ku_i, kv_i) = dt b_i W + dt c_{i+1} M_{i+1}[0:2],
-            W <- W + sum_i M_i[0:2].
+        Forward stages of step n from (u, v) at time t: the segment is rerun
+        with ``sbpe_advance`` one step at a time, and ``sbpe_rk4_stages``
+        rebuilds each step's stage displacements U_1..U_4 and slopes
+        A_1..A_4 from its end states and the slopes a1, a2 the sweeps leave
+        (``sbpe_stage_slopes``); a step's nine fields (U_1, v, U_2, U_3, U_4,
+        A_1..A_4) are kept until it is reversed.  Adjoint state: (u^, v^) is
+        held swapped, as the bound state (u', v') = (v^, u^) of a data-free
+        context.  Reversing step n:
+            keep (u', v'),  one homogeneous RK4 step of (u', v'),
+            U'_2, U'_3, U'_4 from ``sbpe_rk4_stages`` of that step,
+            gradient += the four stage terms with z_i = U'_{5-i}, alpha_i = dt b_i,
+        then the receiver residuals of step n - 1 are added to u^.  Memory:
+        nine fields per step of a segment (checkpoint_every steps) and two
+        contexts.
         """
         torch = self.torch
         sol = self.sol
         ctx = sol.ctx
         h = self.dt
         n2, n1 = self.shape[1:]
+        shape = tuple(self.shape)
         gc = torch.zeros((10, n2, n1), dtype=torch.float64, device=self.dev)
         grt = torch.zeros((n2, n1), dtype=torch.float64, device=self.dev)
         res = torch.as_tensor(np.ascontiguousarray(self.residuals), dtype=torch.float64, device=self.dev)
         rstride = self.nrec * 2 * 8
         N = self.nsteps
-        triple = lambda: torch.empty((3,) + tuple(self.shape), dtype=self.tdt, device=self.dev)
-        W = torch.zeros((2,) + tuple(self.shape), dtype=self.tdt, device=self.dev)
-        Wn = torch.empty_like(W)
-        Z = [triple() for _ in range(4)]
-        M = [triple() for _ in range(4)]
-        seg_u = [self._new() for _ in range(self.K)]
-        seg_v = [self._new() for _ in range(self.K)]
-        n2c = 2 * self.count
-        lin = lambda coefs, xs, out: S.sbpe_lincomb(ctx, coefs, [x.data_ptr() for x in xs], out.data_ptr(), n2c)
-        if self.nrec:
-            S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (N - 1) * rstride, [W[0].data_ptr()], 1.0)
-        for (cu, cv, ct, c0) in reversed(self.checkpoints):
-            k = min(self.K, N - c0)
-            # the segment's states
-            sol.set_state([cu], [cv], ct)
-            seg_u[0].copy_(cu)
-            seg_v[0].copy_(cv)
-            for s_ in range(1, k):
-                sol.advance(1, h)
-                seg_u[s_].copy_(sol.u[0])
-                seg_v[s_].copy_(sol.v[0])
-            for s_ in range(k - 1, -1, -1):
-                n = c0 + s_                     # reversing the step from y_n to y_{n+1}
-                t = ct + s_ * h
-                Z[0][0].copy_(seg_u[s_])
-                Z[0][1].copy_(seg_v[s_])
-                # stages of the step
-                for i in range(4):
-                    self._apply(Z[i][0], t + C_RK[i] * h, False, Z[i][2])
-                    if i < 3:
-                        lin([1.0, C_RK[i + 1] * h], [Z[0], Z[i][1]], Z[i + 1])
-                # stage adjoints, last stage first
-                for i in range(3, -1, -1):
-                    if i == 3:
-                        lin([h * B_RK[3]], [W], M[3][1])
-                    else:
-                        lin([h * B_RK[i], h * C_RK[i + 1]], [W, M[i + 1]], M[i][1])
-                    self._apply(M[i][2], 0.0, True, M[i][0])
-                    S.sbpe_grad_accumulate(ctx, [M[i][2].data_ptr()], [Z[i][0].data_ptr()], [Z[i][2].data_ptr()],
-                                           1.0, t + C_RK[i] * h, False, [gc.data_ptr()], [grt.data_ptr()])
-                lin([1.0, 1.0, 1.0, 1.0, 1.0], [W, M[3], M[2], M[1], M[0]], Wn)
-                W, Wn = Wn, W
-                if n > 0 and self.nrec:
-                    S.sbpe_receiver_adjoint(ctx, res.data_ptr() + (n - 1) * rstride, [W[0].data_ptr()], 1.0)
-        g10, grho = S.sbpe_grad_to_physical(ctx, 0, gc.data_ptr(), grt.data_ptr())
+        cnt = self.count
+        new = lambda *lead: torch.empty(lead + shape, dtype=self.tdt, device=self.dev)
+        seg = [new(9) for _ in range(self.K)]      # U1, v, U2, U3, U4, A1, A2, A3, A4 of each step
+        X = new(2)                                  # forward state (u, v)
+        Y = new(2)                                  # adjoint state (u', v') = (v^, u^)
+        P = new(5)                                  # U'_1 = u', v', U'_2, U'_3, U'_4
+        a1f, a2f = S.sbpe_stage_slopes(ctx, 0)
+        adj = Solver(homogeneous_spec(self.spec), self.dtype, device=self.dev.index)
+        try:
+            actx = adj.ctx
+            Y.zero_()
+            S.sbpe_bind_state(actx, [Y[0].data_ptr()], [Y[1].data_ptr()], 0.0)
+            a1p, a2p = S.sbpe_stage_slopes(actx, 0)
+            # the per-step calls go straight to the library with their
+            # arguments converted once: a step's kernels take tens of
+            # microseconds, the argument marshalling of the wrappers as long
+            L, A = S.lib(), S.ptr_array
+            one = np.ones(1)
+            one_p = one.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            alphas = np.array([h * b for b in B_RK])
+            alphas_p = alphas.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            X_p, Y_p = A([X.data_ptr()]), A([Y.data_ptr()])
+            fwd = [(E[0].data_ptr(), E[1].data_ptr(), A([E[i].data_ptr() for i in range(2, 9)]),
+                    A([E[i].data_ptr() for i in (0, 2, 3, 4)]), A([E[i].data_ptr() for i in (5, 6, 7, 8)]))
+                   for E in seg]
+            adj_out = A([P[i].data_ptr() for i in (2, 3, 4)] + [None] * 4)
+            z_p = A([P[i].data_ptr() for i in (4, 3, 2, 0)])
+            gc_p, grt_p, y1_p = A([gc.data_ptr()]), A([grt.data_ptr()]), A([Y[1].data_ptr()])
+            pP, p0, p1 = P.data_ptr(), P[0].data_ptr(), P[1].data_ptr()
+            x0, x1 = X[0].data_ptr(), X[1].data_ptr()
+            r0 = res.data_ptr()
+            chk = S.check
+            if self.nrec:
+                chk(ctx, L.sbpe_receiver_adjoint(ctx, r0 + (N - 1) * rstride, y1_p, 1.0))
+            for (cu, cv, ct, c0) in reversed(self.checkpoints):
+                k = min(self.K, N - c0)
+                # the segment's forward stages
+                X[0].copy_(cu)
+                X[1].copy_(cv)
+                S.sbpe_bind_state(ctx, [x0], [x1], ct)
+                for s_ in range(k):
+                    e0, e1, e_out = fwd[s_][:3]
+                    chk(ctx, L.sbpe_lincomb(ctx, 1, one_p, X_p, e0, 2 * cnt))
+                    chk(ctx, L.sbpe_advance(ctx, 1, h))
+                    chk(ctx, L.sbpe_rk4_stages(ctx, e0, e1, x0, x1, a1f, a2f, h, e_out, cnt))
+                # reversed steps, last first
+                for s_ in range(k - 1, -1, -1):
+                    n = c0 + s_                     # reversing the step from y_n to y_{n+1}
+                    t = ct + s_ * h
+                    y_p, a_p = fwd[s_][3:]
+                    chk(ctx, L.sbpe_lincomb(ctx, 1, one_p, Y_p, pP, 2 * cnt))
+                    chk(actx, L.sbpe_advance(actx, 1, h))
+                    chk(ctx, L.sbpe_rk4_stages(ctx, p0, p1, None, None, a1p, a2p, h, adj_out, cnt))
+                    chk(ctx, L.sbpe_grad_accumulate_rk4(ctx, z_p, y_p, a_p, alphas_p, t, h, 0, gc_p, grt_p))
+                    if n > 0 and self.nrec:
+                        chk(ctx, L.sbpe_receiver_adjoint(ctx, r0 + (n - 1) * rstride, y1_p, 1.0))
+            g10, grho = S.sbpe_grad_to_physical(ctx, 0, gc.data_ptr(), grt.data_ptr())
+        finally:
+            adj.close()
+            # the forward context's own state buffers again
+            S.sbpe_bind_state(ctx, [sol.u[0].data_ptr()], [sol.v[0].data_ptr()], N * h)
         return grho, g10
 
 

@@ -2067,20 +2067,45 @@ __device__ double d1t_weighted(gcp<T> z, long st, int p, int n) {
 // the rho~ term.
 constexpr int GRAD_PARTS = 8;
 
+// operand of stage s (uniform) and block k, read from the kernel argument with
+// static indices only (a runtime index would copy the argument to per-lane
+// scratch memory)
+__device__ __forceinline__ const void* grad_operand(const void* const (&f)[GRAD_STAGES_MAX][MAX_APPLY_BLOCKS], int s,
+                                                    int k) {
+    const void* r = f[0][k];
+#pragma unroll
+    for (int q = 1; q < GRAD_STAGES_MAX; ++q)
+        if (q == s) r = f[q][k];
+    return r;
+}
+__device__ __forceinline__ double grad_alpha(const GradArgs& G, int s, int& tcol) {
+    double al = G.alpha[0];
+    tcol = G.tcol[0];
+#pragma unroll
+    for (int q = 1; q < GRAD_STAGES_MAX; ++q)
+        if (q == s) {
+            al = G.alpha[q];
+            tcol = G.tcol[q];
+        }
+    return al;
+}
+
+// A launch accumulates the stages 0 .. nstages-1 (blockIdx.y = stage); with
+// more than one stage each stage writes its sums to G.part and
+// k_grad_band_sum adds them up in stage order.
 template <typename T, int ORD>
 __global__ void __launch_bounds__(GRAD_PARTS * 64) k_grad(GradArgs G) {
     using O = Op<ORD>;
     __shared__ double s_g[GRAD_PARTS][10][64];
     const int part = (int)(threadIdx.x >> 6);
+    const int st = (int)blockIdx.y;
     const long gid = (long)blockIdx.x * 64 + (threadIdx.x & 63);
-    // block of this point and its operands, read from the kernel argument
-    // with static indices only (a runtime index would copy the argument to
-    // per-lane scratch memory)
+    // block of this point and its operands
     int b = 0;
     long end = G.boff[1];
-    gcp<T> z = gc<T>(G.z[0]);
-    gcp<T> y = gc<T>(G.y[0]);
-    gcp<T> a = gc<T>(G.a[0]);
+    gcp<T> z = gc<T>(grad_operand(G.z, st, 0));
+    gcp<T> y = gc<T>(grad_operand(G.y, st, 0));
+    gcp<T> a = gc<T>(grad_operand(G.a, st, 0));
     double* gcb = G.gc[0];
     double* grb = G.grt[0];
     long base = 0;
@@ -2090,12 +2115,14 @@ __global__ void __launch_bounds__(GRAD_PARTS * 64) k_grad(GradArgs G) {
             b = k;
             base = G.boff[k];
             end = G.boff[k + 1];
-            z = gc<T>(G.z[k]);
-            y = gc<T>(G.y[k]);
-            a = gc<T>(G.a[k]);
+            z = gc<T>(grad_operand(G.z, st, k));
+            y = gc<T>(grad_operand(G.y, st, k));
+            a = gc<T>(grad_operand(G.a, st, k));
             gcb = G.gc[k];
             grb = G.grt[k];
         }
+    int tcol;
+    const double al = grad_alpha(G, st, tcol);
     const bool valid = gid < end;
     BlockRef B = ((const GLB BlockDesc*)G.blocks)[b];
     const int n1 = B.n1, n2 = B.n2;
@@ -2210,7 +2237,7 @@ __global__ void __launch_bounds__(GRAD_PARTS * 64) k_grad(GradArgs G) {
         } else if (F.kind == BC_DISPLACEMENT) {
             double del[2] = {(double)y[p], (double)y[np + p]};
             if (!G.homogeneous && F.g) {
-                const double tau = ((const GLB double*)G.tau)[3 * F.item_g];
+                const double tau = ((const GLB double*)G.tau)[3 * F.item_g + tcol];
                 gcp<T> gg = gc<T>(F.g);
                 del[0] -= tau * (double)gg[t];
                 del[1] -= tau * (double)gg[F.nf + t];
@@ -2246,16 +2273,72 @@ __global__ void __launch_bounds__(GRAD_PARTS * 64) k_grad(GradArgs G) {
     __syncthreads();
     if (part != 0 || !valid) return;
     const double Hp = h1 * h2 * hn1 * hn2;
-    const double al = G.alpha;
-    gp<double> gq = (gp<double>)gcb;
+    const double rt = -al * Hp * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
+    if (G.nstages == 1) {
+        gp<double> gq = (gp<double>)gcb;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
-        double sum = 0.0;
+        for (int k = 0; k < 10; ++k) {
+            double sum = 0.0;
 #pragma unroll
-        for (int w = 0; w < GRAD_PARTS; ++w) sum += s_g[w][k][lane];
-        gq[(long)k * np + p] += al * sum;
+            for (int w = 0; w < GRAD_PARTS; ++w) sum += s_g[w][k][lane];
+            gq[(long)k * np + p] += al * sum;
+        }
+        ((gp<double>)grb)[p] += rt;
+    } else {
+        gp<double> pt = (gp<double>)G.part + (long)st * GRAD_TERMS * G.nband + gid;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < GRAD_PARTS; ++w) sum += s_g[w][k][lane];
+            pt[(long)k * G.nband] = al * sum;
+        }
+        pt[(long)10 * G.nband] = rt;
     }
-    ((gp<double>)grb)[p] += -al * Hp * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
+}
+
+// Band points of a multi-stage launch: the stages' partial sums added in
+// stage order, then to the gradient fields.
+template <int ORD>
+__global__ void __launch_bounds__(256) k_grad_band_sum(GradArgs G) {
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= G.nband) return;
+    int b = 0;
+    double* gcb = G.gc[0];
+    double* grb = G.grt[0];
+    long base = 0;
+#pragma unroll
+    for (int k = 1; k < MAX_APPLY_BLOCKS; ++k)
+        if (k < G.nblocks && gid >= G.boff[k]) {
+            b = k;
+            base = G.boff[k];
+            gcb = G.gc[k];
+            grb = G.grt[k];
+        }
+    BlockRef B = ((const GLB BlockDesc*)G.blocks)[b];
+    const int n1 = B.n1, n2 = B.n2;
+    constexpr int LO = grad_lo<ORD>();
+    int i, j;
+    const int kb = (int)(gid - base);
+    if (n1 > 2 * LO && n2 > 2 * LO) {
+        frame_ij(kb, n1, n2, LO, i, j);
+    } else {
+        j = kb / n1;
+        i = kb - j * n1;
+    }
+    const long np = (long)n1 * n2;
+    const long p = (long)j * n1 + i;
+    gcp<double> pt = (gcp<double>)G.part + gid;
+    const long sst = (long)GRAD_TERMS * G.nband;
+#pragma unroll
+    for (int k = 0; k <= 10; ++k) {
+        double sum = pt[(long)k * G.nband];
+#pragma unroll
+        for (int q = 1; q < GRAD_STAGES_MAX; ++q)
+            if (q < G.nstages) sum += pt[q * sst + (long)k * G.nband];
+        if (k < 10) ((gp<double>)gcb)[(long)k * np + p] += sum;
+        else ((gp<double>)grb)[p] += sum;
+    }
 }
 
 
@@ -2269,9 +2352,6 @@ __global__ void __launch_bounds__(256) k_grad_int(GradArgs G) {
     const long gid = (long)blockIdx.x * 256 + threadIdx.x;
     int b = 0;
     long end = G.off[1];
-    gcp<T> z = gc<T>(G.z[0]);
-    gcp<T> y = gc<T>(G.y[0]);
-    gcp<T> a = gc<T>(G.a[0]);
     double* gcb = G.gc[0];
     double* grb = G.grt[0];
     long base = 0;
@@ -2281,9 +2361,6 @@ __global__ void __launch_bounds__(256) k_grad_int(GradArgs G) {
             b = k;
             base = G.off[k];
             end = G.off[k + 1];
-            z = gc<T>(G.z[k]);
-            y = gc<T>(G.y[k]);
-            a = gc<T>(G.a[k]);
             gcb = G.gc[k];
             grb = G.grt[k];
         }
@@ -2296,62 +2373,82 @@ __global__ void __launch_bounds__(256) k_grad_int(GradArgs G) {
     const int j = LO + q / ni1, i = LO + q % ni1;
     const long p = (long)j * n1 + i;
     const double h1 = B.h1, h2 = B.h2;
-    // windows of z (+-H) and y (+-2H) along both lines through p
-    double zx[2][2 * HF + 1], zy[2][2 * HF + 1], yx[2][4 * HF + 1], yy[2][4 * HF + 1];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-#pragma unroll
-        for (int k = 0; k <= 2 * HF; ++k) {
-            zx[c][k] = (double)z[c * np + p + (k - HF)];
-            zy[c][k] = (double)z[c * np + p + (long)(k - HF) * n1];
-        }
-#pragma unroll
-        for (int k = 0; k <= 4 * HF; ++k) {
-            yx[c][k] = (double)y[c * np + p + (k - 2 * HF)];
-            yy[c][k] = (double)y[c * np + p + (long)(k - 2 * HF) * n1];
-        }
-    }
-    // interior rows: h D1 y at p and (h D1^T z)_p (norm weights 1 around p)
-    double tzx[2], tzy[2], dyx[2], dyy[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        tzx[c] = tzy[c] = dyx[c] = dyy[c] = 0.0;
-#pragma unroll
-        for (int k = 1; k <= HF; ++k) {
-            const double w = O::d1i(HF + k);
-            tzx[c] += w * (zx[c][HF - k] - zx[c][HF + k]);
-            tzy[c] += w * (zy[c][HF - k] - zy[c][HF + k]);
-            dyx[c] += w * (yx[c][2 * HF + k] - yx[c][2 * HF - k]);
-            dyy[c] += w * (yy[c][2 * HF + k] - yy[c][2 * HF - k]);
-        }
-    }
-    double g[10];
     const double fx = h2 / h1, fy = h1 / h2;
-    if (G.wide) {
-        g[K_C1111] = fx * tzx[0] * dyx[0];
-        g[K_C1112] = fx * (tzx[0] * dyx[1] + tzx[1] * dyx[0]);
-        g[K_C1212] = fx * tzx[1] * dyx[1];
-        g[K_C2121] = fy * tzy[0] * dyy[0];
-        g[K_C2122] = fy * (tzy[0] * dyy[1] + tzy[1] * dyy[0]);
-        g[K_C2222] = fy * tzy[1] * dyy[1];
-    } else {
-        g[K_C1111] = fx * d2_coef_grad_win<ORD>(zx[0], yx[0]);
-        g[K_C1112] = fx * (d2_coef_grad_win<ORD>(zx[0], yx[1]) + d2_coef_grad_win<ORD>(zx[1], yx[0]));
-        g[K_C1212] = fx * d2_coef_grad_win<ORD>(zx[1], yx[1]);
-        g[K_C2121] = fy * d2_coef_grad_win<ORD>(zy[0], yy[0]);
-        g[K_C2122] = fy * (d2_coef_grad_win<ORD>(zy[0], yy[1]) + d2_coef_grad_win<ORD>(zy[1], yy[0]));
-        g[K_C2222] = fy * d2_coef_grad_win<ORD>(zy[1], yy[1]);
-    }
     const int km[2][2] = {{K_C1121, K_C1122}, {K_C1221, K_C1222}};
+    // sums over the stages, added to the gradient fields once
+    double gt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double rt = 0.0;
+#pragma unroll 1
+    for (int st = 0; st < G.nstages; ++st) {
+        gcp<T> z = gc<T>(grad_operand(G.z, st, 0));
+        gcp<T> y = gc<T>(grad_operand(G.y, st, 0));
+        gcp<T> a = gc<T>(grad_operand(G.a, st, 0));
 #pragma unroll
-    for (int aa = 0; aa < 2; ++aa)
+        for (int k = 1; k < MAX_APPLY_BLOCKS; ++k)
+            if (k == b) {
+                z = gc<T>(grad_operand(G.z, st, k));
+                y = gc<T>(grad_operand(G.y, st, k));
+                a = gc<T>(grad_operand(G.a, st, k));
+            }
+        // windows of z (+-H) and y (+-2H) along both lines through p
+        double zx[2][2 * HF + 1], zy[2][2 * HF + 1], yx[2][4 * HF + 1], yy[2][4 * HF + 1];
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb) g[km[aa][bb]] = tzx[aa] * dyy[bb] + tzy[bb] * dyx[aa];
-    const double al = G.alpha;
+        for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int k = 0; k <= 2 * HF; ++k) {
+                zx[c][k] = (double)z[c * np + p + (k - HF)];
+                zy[c][k] = (double)z[c * np + p + (long)(k - HF) * n1];
+            }
+#pragma unroll
+            for (int k = 0; k <= 4 * HF; ++k) {
+                yx[c][k] = (double)y[c * np + p + (k - 2 * HF)];
+                yy[c][k] = (double)y[c * np + p + (long)(k - 2 * HF) * n1];
+            }
+        }
+        // interior rows: h D1 y at p and (h D1^T z)_p (norm weights 1 around p)
+        double tzx[2], tzy[2], dyx[2], dyy[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            tzx[c] = tzy[c] = dyx[c] = dyy[c] = 0.0;
+#pragma unroll
+            for (int k = 1; k <= HF; ++k) {
+                const double w = O::d1i(HF + k);
+                tzx[c] += w * (zx[c][HF - k] - zx[c][HF + k]);
+                tzy[c] += w * (zy[c][HF - k] - zy[c][HF + k]);
+                dyx[c] += w * (yx[c][2 * HF + k] - yx[c][2 * HF - k]);
+                dyy[c] += w * (yy[c][2 * HF + k] - yy[c][2 * HF - k]);
+            }
+        }
+        double g[10];
+        if (G.wide) {
+            g[K_C1111] = fx * tzx[0] * dyx[0];
+            g[K_C1112] = fx * (tzx[0] * dyx[1] + tzx[1] * dyx[0]);
+            g[K_C1212] = fx * tzx[1] * dyx[1];
+            g[K_C2121] = fy * tzy[0] * dyy[0];
+            g[K_C2122] = fy * (tzy[0] * dyy[1] + tzy[1] * dyy[0]);
+            g[K_C2222] = fy * tzy[1] * dyy[1];
+        } else {
+            g[K_C1111] = fx * d2_coef_grad_win<ORD>(zx[0], yx[0]);
+            g[K_C1112] = fx * (d2_coef_grad_win<ORD>(zx[0], yx[1]) + d2_coef_grad_win<ORD>(zx[1], yx[0]));
+            g[K_C1212] = fx * d2_coef_grad_win<ORD>(zx[1], yx[1]);
+            g[K_C2121] = fy * d2_coef_grad_win<ORD>(zy[0], yy[0]);
+            g[K_C2122] = fy * (d2_coef_grad_win<ORD>(zy[0], yy[1]) + d2_coef_grad_win<ORD>(zy[1], yy[0]));
+            g[K_C2222] = fy * d2_coef_grad_win<ORD>(zy[1], yy[1]);
+        }
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) g[km[aa][bb]] = tzx[aa] * dyy[bb] + tzy[bb] * dyx[aa];
+        int tcol;
+        const double al = grad_alpha(G, st, tcol);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) gt[k] += al * g[k];
+        rt += -al * h1 * h2 * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
+    }
     gp<double> gq = (gp<double>)gcb;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) gq[(long)k * np + p] += al * g[k];
-    ((gp<double>)grb)[p] += -al * h1 * h2 * ((double)z[p] * (double)a[p] + (double)z[np + p] * (double)a[np + p]);
+    for (int k = 0; k < 10; ++k) gq[(long)k * np + p] += gt[k];
+    ((gp<double>)grb)[p] += rt;
 }
 
 // y = sum_k c_k x_k (elementwise, at most LINCOMB_MAX terms; y may be one of the x_k)
@@ -2368,6 +2465,32 @@ __global__ void __launch_bounds__(256) k_lincomb(int nterms, LincombArgs a, T* y
     for (int k = 1; k < LINCOMB_MAX; ++k)
         if (k < nterms) acc += a.c[k] * (double)((const T*)a.x[k])[i];
     y[i] = static_cast<T>(acc);
+}
+
+// Stage values of one classical RK4 step of u'' = a(u) from its end points
+// (u0, v0) -> (u1, v1) and its first two slopes a1, a2 (sbpe_rk4_stages):
+// U2 = u0 + dt/2 v0, U3 = U2 + dt^2/4 a1, U4 = u0 + dt v0 + dt^2/2 a2, copies
+// of a1 and a2, and the slopes a3, a4 solved from the step's update
+// u1 = u0 + dt v0 + dt^2/6 (a1 + a2 + a3), v1 = v0 + dt/6 (a1 + 2 a2 + 2 a3 + a4).
+template <typename T>
+__global__ void __launch_bounds__(256) k_rk4_stages(Rk4StageArgs a, long count) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const double dt = a.dt;
+    const double u0 = (double)((const T*)a.u0)[i], v0 = (double)((const T*)a.v0)[i];
+    const double a1 = (double)((const T*)a.a1)[i], a2 = (double)((const T*)a.a2)[i];
+    const double U2 = u0 + 0.5 * dt * v0;
+    if (a.out[0]) ((T*)a.out[0])[i] = static_cast<T>(U2);
+    if (a.out[1]) ((T*)a.out[1])[i] = static_cast<T>(U2 + 0.25 * dt * dt * a1);
+    if (a.out[2]) ((T*)a.out[2])[i] = static_cast<T>(u0 + dt * v0 + 0.5 * dt * dt * a2);
+    if (a.out[3]) ((T*)a.out[3])[i] = static_cast<T>(a1);
+    if (a.out[4]) ((T*)a.out[4])[i] = static_cast<T>(a2);
+    if (a.out[5] || a.out[6]) {
+        const double u1 = (double)((const T*)a.u1)[i], v1 = (double)((const T*)a.v1)[i];
+        const double a3 = 6.0 * (u1 - u0 - dt * v0) / (dt * dt) - a1 - a2;
+        if (a.out[5]) ((T*)a.out[5])[i] = static_cast<T>(a3);
+        if (a.out[6]) ((T*)a.out[6])[i] = static_cast<T>(6.0 * (v1 - v0) / dt - a1 - 2.0 * a2 - 2.0 * a3);
+    }
 }
 
 template <typename T>

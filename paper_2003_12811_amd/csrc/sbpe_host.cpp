@@ -232,6 +232,8 @@ struct sbpe_ctx {
     double* d_epart = nullptr;
     double* d_eout = nullptr;
     int npartial = 0;
+    double* d_gpart = nullptr;      // band partial sums of the four-stage gradient launch
+    long gpart_cap = 0;             // doubles of capacity
     int guard_every = 0;
     double guard_growth = 0.0;
     // member of a batch (sbpe_batch_add): the batch owns the stepping
@@ -1056,6 +1058,7 @@ sbpe_status sbpe_destroy(sbpe_ctx_t c) {
         dfree(c, c->d_rec);
         dfree(c, c->d_epart);
         dfree(c, c->d_eout);
+        dfree(c, c->d_gpart);
         for (auto e : c->ev_pool) (void)hipEventDestroy(e);
         (void)hipStreamSynchronize(c->side);
         (void)hipEventDestroy(c->ev_main);
@@ -2395,9 +2398,12 @@ extern "C" sbpe_status sbpe_batch_synchronize(sbpe_batch_t b) {
 }
 
 // -------------------------------------------------------------- gradients
-extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, const void* const* y,
-                                            const void* const* a, double alpha, double t, int homogeneous,
-                                            void* const* gc, void* const* grt) {
+// Gradient accumulation of nst stages: stage s takes z[s*nb + b], y[s*nb + b],
+// a[s*nb + b], alpha[s], and column tcol[s] of the time functions tabulated at
+// (t, dt) (columns: t, t + dt/2, t + dt).
+static sbpe_status grad_stages(sbpe_ctx* c, int nst, const void* const* z, const void* const* y,
+                               const void* const* a, const double* alpha, const int* tcol, double t, double dt,
+                               int homogeneous, void* const* gc, void* const* grt) {
     if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
     if (c && c->batch) return fail(c, SBPE_ESTATE, "context is a member of a batch");
     sbpe_status s = need_gpu(c);
@@ -2407,36 +2413,84 @@ extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, 
     if (c->order == 6) return fail(c, SBPE_EINVAL, "coefficient gradients are built for orders 2 and 4");
     const int nb = (int)c->blocks.size();
     if (nb > MAX_APPLY_BLOCKS) return fail(c, SBPE_EINVAL, "at most 16 blocks");
-    if (!z || !y || !a || !gc || !grt) return fail(c, SBPE_EINVAL, "NULL pointer array");
+    if (!z || !y || !a || !gc || !grt || !alpha) return fail(c, SBPE_EINVAL, "NULL pointer array");
     for (int b = 0; b < nb; ++b) {
-        if (!z[b] || !y[b] || !a[b] || !gc[b] || !grt[b]) return fail(c, SBPE_EINVAL, "NULL block pointer");
+        if (!gc[b] || !grt[b]) return fail(c, SBPE_EINVAL, "NULL block pointer");
+        for (int st = 0; st < nst; ++st)
+            if (!z[st * nb + b] || !y[st * nb + b] || !a[st * nb + b]) return fail(c, SBPE_EINVAL, "NULL block pointer");
         for (int f = 0; f < 4; ++f)
             if (c->blocks[b].face[f].kind == BC_INTERFACE)
                 return fail(c, SBPE_EINVAL, "coefficient gradients across interfaces are not supported");
     }
-    if (!homogeneous) {
-        s = fill_tau(c, 1, t, 0.0);
-        if (s) return s;
-    }
     GradArgs g;
     std::memset(&g, 0, sizeof g);
-    g.blocks = c->d_desc;
-    g.nblocks = nb;
-    g.homogeneous = homogeneous ? 1 : 0;
-    g.wide = c->op == SBPE_OP_WIDE ? 1 : 0;
-    g.alpha = alpha;
-    g.tau = c->d_tau;
     for (int b = 0; b < nb; ++b) {
         g.n1[b] = c->blocks[b].n1;
         g.n2[b] = c->blocks[b].n2;
-        g.z[b] = z[b];
-        g.y[b] = y[b];
-        g.a[b] = a[b];
+    }
+    if (nst > 1) {
+        // band partial sums of the stages
+        const long need = (long)nst * GRAD_TERMS * grad_band_points(c->order, g.n1, g.n2, nb);
+        if (need > c->gpart_cap) {
+            HIPCHECK(c, hipStreamSynchronize(c->stream));
+            dfree(c, c->d_gpart);
+            c->d_gpart = nullptr;
+            c->gpart_cap = 0;
+            if (dmalloc(c, &c->d_gpart, (size_t)need * sizeof(double)) != hipSuccess)
+                return fail(c, SBPE_ENOMEM, "gradient partial sums");
+            c->gpart_cap = need;
+        }
+    }
+    if (!homogeneous) {
+        s = fill_tau(c, 1, t, dt);
+        if (s) return s;
+    }
+    g.blocks = c->d_desc;
+    g.nblocks = nb;
+    g.nstages = nst;
+    g.homogeneous = homogeneous ? 1 : 0;
+    g.wide = c->op == SBPE_OP_WIDE ? 1 : 0;
+    g.tau = c->d_tau;
+    g.part = c->d_gpart;
+    for (int st = 0; st < nst; ++st) {
+        g.alpha[st] = alpha[st];
+        g.tcol[st] = tcol[st];
+        for (int b = 0; b < nb; ++b) {
+            g.z[st][b] = z[st * nb + b];
+            g.y[st][b] = y[st * nb + b];
+            g.a[st][b] = a[st * nb + b];
+        }
+    }
+    for (int b = 0; b < nb; ++b) {
         g.gc[b] = static_cast<double*>(gc[b]);
         g.grt[b] = static_cast<double*>(grt[b]);
     }
     const int e = launch_grad(c->dtype, c->order, g, c->stream);
     if (e != 0) return fail(c, SBPE_EHIP, std::string("gradient launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+extern "C" sbpe_status sbpe_grad_accumulate(sbpe_ctx_t c, const void* const* z, const void* const* y,
+                                            const void* const* a, double alpha, double t, int homogeneous,
+                                            void* const* gc, void* const* grt) {
+    const int tcol = 0;
+    return grad_stages(c, 1, z, y, a, &alpha, &tcol, t, 0.0, homogeneous, gc, grt);
+}
+
+extern "C" sbpe_status sbpe_grad_accumulate_rk4(sbpe_ctx_t c, const void* const* z, const void* const* y,
+                                                const void* const* a, const double* alpha, double t, double dt,
+                                                int homogeneous, void* const* gc, void* const* grt) {
+    static const int tcol[4] = {0, 1, 1, 2};     // stage times t, t + dt/2, t + dt/2, t + dt
+    return grad_stages(c, 4, z, y, a, alpha, tcol, t, dt, homogeneous, gc, grt);
+}
+
+extern "C" sbpe_status sbpe_stage_slopes(sbpe_ctx_t c, int block, void** a1, void** a2) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    if (!c->finalized) return fail(c, SBPE_ESTATE, "call sbpe_finalize first");
+    if (block < 0 || block >= (int)c->blocks.size()) return fail(c, SBPE_EINVAL, "no such block");
+    if (!a1 || !a2) return fail(c, SBPE_EINVAL, "NULL pointer");
+    *a1 = c->blocks[block].d_a1;
+    *a2 = c->blocks[block].d_a2;
     return SBPE_OK;
 }
 
@@ -2491,6 +2545,28 @@ extern "C" sbpe_status sbpe_lincomb(sbpe_ctx_t c, int nterms, const double* coef
         if (!x[k]) return fail(c, SBPE_EINVAL, "NULL input");
     const int e = launch_lincomb(c->dtype, nterms, coefs, x, y, (long)count, c->stream);
     if (e != 0) return fail(c, SBPE_EHIP, std::string("lincomb launch: ") + hip_error_string(e));
+    return SBPE_OK;
+}
+
+extern "C" sbpe_status sbpe_rk4_stages(sbpe_ctx_t c, const void* u0, const void* v0, const void* u1, const void* v1,
+                                       const void* a1, const void* a2, double dt, void* const* out,
+                                       long long count) {
+    if (!check_ctx(c)) return fail(nullptr, SBPE_EINVAL, "NULL context");
+    sbpe_status s = need_gpu(c);
+    if (s) return s;
+    if (!u0 || !v0 || !a1 || !a2 || !out || count < 0 || !(dt > 0.0)) return fail(c, SBPE_EINVAL, "bad arguments");
+    Rk4StageArgs a;
+    a.u0 = u0;
+    a.v0 = v0;
+    a.u1 = u1;
+    a.v1 = v1;
+    a.a1 = a1;
+    a.a2 = a2;
+    a.dt = dt;
+    for (int k = 0; k < 7; ++k) a.out[k] = out[k];
+    if ((out[5] || out[6]) && (!u1 || !v1)) return fail(c, SBPE_EINVAL, "the slopes a3, a4 need u1 and v1");
+    const int e = launch_rk4_stages(c->dtype, a, (long)count, c->stream);
+    if (e != 0) return fail(c, SBPE_EHIP, std::string("rk4 stages launch: ") + hip_error_string(e));
     return SBPE_OK;
 }
 

@@ -162,23 +162,31 @@ constexpr int TILE_Y_DEFAULT = 10;
 constexpr int FRAME_WG = 256;
 constexpr int FRAME_PTS = 32;   // frame points per group (the unit of the point-entry ranges)
 
-// Coefficient gradient of one RK4 stage (sbpe_grad_accumulate): for every block,
-// gc[b][k] += alpha d/dc_k (z^T H L(c) y) and grt[b] += -alpha H (z . a).
+// Coefficient gradient of RK4 stages (sbpe_grad_accumulate: one stage;
+// sbpe_grad_accumulate_rk4: the four stages of a step): for every block and
+// stage s, gc[b][k] += alpha[s] d/dc_k (z_s^T H L(c) y_s) and
+// grt[b] += -alpha[s] H (z_s . a_s).
+constexpr int GRAD_STAGES_MAX = 4;
+constexpr int GRAD_TERMS = 11;        // 10 coefficient fields and rho~
 struct GradArgs {
     const BlockDesc* blocks;
     int nblocks;
+    int nstages;          // 1 .. GRAD_STAGES_MAX
     int homogeneous;      // displacement data left out of delta = y - g(t)
     int wide;             // wide-stencil operator: the i = k terms are D_i c D_i
     int n1[MAX_APPLY_BLOCKS], n2[MAX_APPLY_BLOCKS];   // block sizes
     long off[MAX_APPLY_BLOCKS + 1];   // first interior point of each block (interior launch; set by the launcher)
     long boff[MAX_APPLY_BLOCKS + 1];  // first band point of each block (band launch; set by the launcher)
-    double alpha;
-    const double* tau;    // tabulated time functions at t (row 0)
-    const void* z[MAX_APPLY_BLOCKS];
-    const void* y[MAX_APPLY_BLOCKS];
-    const void* a[MAX_APPLY_BLOCKS];
+    long nband;                       // band points of all blocks (set by the launcher)
+    double alpha[GRAD_STAGES_MAX];
+    int tcol[GRAD_STAGES_MAX];        // column of row 0 of the time-function table holding stage s's time
+    const double* tau;    // tabulated time functions: row 0 = tau(t), tau(t + dt/2), tau(t + dt)
+    const void* z[GRAD_STAGES_MAX][MAX_APPLY_BLOCKS];
+    const void* y[GRAD_STAGES_MAX][MAX_APPLY_BLOCKS];
+    const void* a[GRAD_STAGES_MAX][MAX_APPLY_BLOCKS];
     double* gc[MAX_APPLY_BLOCKS];     // [10][n2][n1], the stored coefficient order K_C1111 .. K_C1222
     double* grt[MAX_APPLY_BLOCKS];    // [n2][n1], gradient with respect to rho~ = J rho
+    double* part;         // nstages > 1: band partial sums [nstages][GRAD_TERMS][band points]
 };
 
 // host-side launchers (sbpe_kernels.hip)
@@ -188,6 +196,8 @@ int launch_tau(const TimeFn* items, int nitems, int nsteps, double t0, double dt
 int launch_energy(int dtype, int order, const BlockDesc* blocks_dev, int nblocks, double* partial_dev,
                   int npartial, double* result_dev, void* stream);
 int launch_grad(int dtype, int order, const GradArgs& g, void* stream);
+// band points of the gradient launches (the partial sums of a multi-stage launch)
+long grad_band_points(int order, const int* n1, const int* n2, int nblocks);
 // frame operator assembly: probe fill, compaction of frame outputs, sparse frame kernel
 int launch_probe_fill(int dtype, void* x, int n1, int n2, int comp, int cx, int cy, int period, void* stream);
 int launch_frame_gather(int dtype, const void* y, int n1, int n2, int R, int frame_n, void* out, void* stream);
@@ -199,6 +209,17 @@ int launch_pass(int dtype, int order, const PassArgs& a, int total_tiles, int to
 constexpr int LINCOMB_MAX = 6;   // terms of sbpe_lincomb
 int launch_lincomb(int dtype, int nterms, const double* coefs, const void* const* x, void* y, long count,
                    void* stream);
+struct Rk4StageArgs {
+    const void* u0;
+    const void* v0;
+    const void* u1;
+    const void* v1;
+    const void* a1;
+    const void* a2;
+    void* out[7];       // U2, U3, U4, A1, A2, A3, A4 (null: not written)
+    double dt;
+};
+int launch_rk4_stages(int dtype, const Rk4StageArgs& a, long count, void* stream);
 // one interpolation point of one receiver: u[block][c][p] += scale * w * r[rec][c]
 struct RecAdj {
     int rec;

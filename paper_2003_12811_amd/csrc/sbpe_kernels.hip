@@ -138,6 +138,23 @@ int launch_grad(int dtype, int order, const GradArgs& g, void* stream) {
     return (int)hipGetLastError();
 }
 
+// band points of the gradient launches over these blocks
+template <int ORD>
+static long grad_band_points_t(const int* n1, const int* n2, int nblocks) {
+    constexpr int LO = grad_lo<ORD>();
+    long ob = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        const long m1 = n1[b], m2 = n2[b];
+        const long ni = (m1 > 2 * LO && m2 > 2 * LO) ? (m1 - 2 * LO) * (m2 - 2 * LO) : 0;
+        ob += m1 * m2 - ni;
+    }
+    return ob;
+}
+
+long grad_band_points(int order, const int* n1, const int* n2, int nblocks) {
+    return order == 2 ? grad_band_points_t<2>(n1, n2, nblocks) : grad_band_points_t<4>(n1, n2, nblocks);
+}
+
 int launch_lincomb(int dtype, int nterms, const double* c, const void* const* x, void* y, long count, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (count <= 0) return 0;
@@ -149,6 +166,15 @@ int launch_lincomb(int dtype, int nterms, const double* c, const void* const* x,
     }
     if (dtype == 0) hipLaunchKernelGGL(k_lincomb<double>, grid, bl, 0, s, nterms, a, (double*)y, count);
     else hipLaunchKernelGGL(k_lincomb<float>, grid, bl, 0, s, nterms, a, (float*)y, count);
+    return (int)hipGetLastError();
+}
+
+int launch_rk4_stages(int dtype, const Rk4StageArgs& a, long count, void* stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (count <= 0) return 0;
+    const dim3 grid((unsigned)((count + 255) / 256)), bl(256);
+    if (dtype == 0) hipLaunchKernelGGL(k_rk4_stages<double>, grid, bl, 0, s, a, count);
+    else hipLaunchKernelGGL(k_rk4_stages<float>, grid, bl, 0, s, a, count);
     return (int)hipGetLastError();
 }
 

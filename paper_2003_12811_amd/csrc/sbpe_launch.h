@@ -23,7 +23,7 @@ struct Launch {
     static void frame(const PassArgs& a, int total_frame_wg, hipStream_t s);
     // the assembled frame operator (k_frame_sp)
     static void frame_sp(const PassArgs& a, dim3 g, dim3 b, hipStream_t s);
-    // coefficient gradient of one stage (k_grad_int, k_grad)
+    // coefficient gradient of one or more stages (k_grad_int, k_grad, k_grad_band_sum)
     static void grad(GradArgs g, hipStream_t s);
 };
 

@@ -72,8 +72,15 @@ static void launch_grad_t(GradArgs g, hipStream_t s) {
     }
     g.off[g.nblocks] = oi;
     g.boff[g.nblocks] = ob;
+    g.nband = ob;
     if (oi > 0) hipLaunchKernelGGL((k_grad_int<T, ORD>), dim3((unsigned)((oi + 255) / 256)), dim3(256), 0, s, g);
-    if (ob > 0) hipLaunchKernelGGL((k_grad<T, ORD>), dim3((unsigned)((ob + 63) / 64)), dim3(GRAD_PARTS * 64), 0, s, g);
+    if (ob > 0) {
+        // one workgroup row per stage; several stages meet in k_grad_band_sum
+        hipLaunchKernelGGL((k_grad<T, ORD>), dim3((unsigned)((ob + 63) / 64), (unsigned)g.nstages),
+                           dim3(GRAD_PARTS * 64), 0, s, g);
+        if (g.nstages > 1)
+            hipLaunchKernelGGL((k_grad_band_sum<ORD>), dim3((unsigned)((ob + 255) / 256)), dim3(256), 0, s, g);
+    }
 }
 
 template <typename T, int ORD>

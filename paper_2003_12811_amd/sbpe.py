@@ -78,9 +78,13 @@ _PROTOS = {
     'sbpe_plan_info': [_P, ctypes.POINTER(ctypes.c_longlong)],
     'sbpe_grad_accumulate': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _D, _D, _I,
                              ctypes.POINTER(_P), ctypes.POINTER(_P)],
+    'sbpe_grad_accumulate_rk4': [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), _DP, _D, _D, _I,
+                                 ctypes.POINTER(_P), ctypes.POINTER(_P)],
+    'sbpe_stage_slopes': [_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P)],
     'sbpe_grad_to_physical': [_P, _I, _P, _P, _DP, _DP],
     'sbpe_lincomb': [_P, _I, _DP, ctypes.POINTER(_P), _P, ctypes.c_longlong],
     'sbpe_receiver_adjoint': [_P, _P, ctypes.POINTER(_P), _D],
+    'sbpe_rk4_stages': [_P, _P, _P, _P, _P, _P, _P, _D, ctypes.POINTER(_P), ctypes.c_longlong],
     'sbpe_batch_create': [_I, _P, _I, _I, ctypes.POINTER(_P)],
     'sbpe_batch_destroy': [_P],
     'sbpe_batch_add': [_P, _P, _I, _D],
@@ -131,6 +135,17 @@ def _check(ctx, code):
     if code != OK:
         msg = lib().sbpe_last_error(ctx)
         raise SbpeError(code, msg.decode() if msg else '')
+
+
+def check(ctx, code):
+    """Raise SbpeError for a failed status of a call made through ``lib()``."""
+    _check(ctx, code)
+
+
+def ptr_array(ptrs):
+    """ctypes array of device pointers (ints or None), for calls made through
+    ``lib()`` with arguments converted once."""
+    return (_P * len(ptrs))(*[None if p is None else int(p) for p in ptrs])
 
 
 def _dp(a):
@@ -344,6 +359,22 @@ def sbpe_grad_accumulate(ctx, z_ptrs, y_ptrs, a_ptrs, alpha, t, homogeneous, gc_
                                            1 if homogeneous else 0, _ptrs(gc_ptrs), _ptrs(grt_ptrs)))
 
 
+def sbpe_grad_accumulate_rk4(ctx, z_ptrs, y_ptrs, a_ptrs, alphas, t, dt, homogeneous, gc_ptrs, grt_ptrs):
+    """z_ptrs, y_ptrs, a_ptrs: 4 * nblocks device pointers, stage-major."""
+    al = np.ascontiguousarray(alphas, dtype=np.float64)
+    if al.shape != (4,):
+        raise ValueError('four stage weights')
+    _check(ctx, lib().sbpe_grad_accumulate_rk4(ctx, _ptrs(z_ptrs), _ptrs(y_ptrs), _ptrs(a_ptrs), _dp(al), t, dt,
+                                               1 if homogeneous else 0, _ptrs(gc_ptrs), _ptrs(grt_ptrs)))
+
+
+def sbpe_stage_slopes(ctx, block):
+    """(a1, a2) device pointers of the context's RK4 stage slopes of `block`."""
+    a1, a2 = _P(), _P()
+    _check(ctx, lib().sbpe_stage_slopes(ctx, block, ctypes.byref(a1), ctypes.byref(a2)))
+    return a1.value, a2.value
+
+
 def sbpe_grad_to_physical(ctx, block, gc_ptr, grt_ptr):
     n1, n2 = sbpe_block_size(ctx, block)
     g10 = np.empty((10, n2, n1))
@@ -355,6 +386,15 @@ def sbpe_grad_to_physical(ctx, block, gc_ptr, grt_ptr):
 def sbpe_lincomb(ctx, coefs, x_ptrs, y_ptr, count):
     c = np.ascontiguousarray(coefs, dtype=np.float64)
     _check(ctx, lib().sbpe_lincomb(ctx, len(c), _dp(c), _ptrs(x_ptrs), _P(int(y_ptr)), int(count)))
+
+
+def sbpe_rk4_stages(ctx, u0, v0, u1, v1, a1, a2, dt, outs, count):
+    """outs: 7 device pointers or None (U2, U3, U4, A1, A2, A3, A4)."""
+    if len(outs) != 7:
+        raise ValueError('seven outputs')
+    o = (_P * 7)(*[None if x is None else int(x) for x in outs])
+    p = [_P(None if x is None else int(x)) for x in (u0, v0, u1, v1, a1, a2)]
+    _check(ctx, lib().sbpe_rk4_stages(ctx, *p, dt, o, int(count)))
 
 
 def sbpe_receiver_adjoint(ctx, r_ptr, u_ptrs, scale=1.0):

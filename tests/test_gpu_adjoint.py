@@ -6,6 +6,9 @@
   (rho, C10): on a small block, and on the 513^2 differentiation workload
   (2000 steps, 100 receivers, checkpoints every 100 steps, 20 directions).
 * The torch.autograd.Function returns the same gradient.
+* Building blocks: the four-stage gradient launch against four one-stage
+  calls, the RK stage slopes a context exposes after a step, and the stage
+  values rebuilt from a step's end states.
 """
 import sys
 
@@ -190,3 +193,117 @@ def test_autograd_forward_runs_no_adjoint():
     J2 = ADJ.seismic_misfit(rho_g, C10, spec, nsteps, dt, d_obs, 10)
     J2.backward()
     assert rho_g.grad is not None and float(rho_g.grad.abs().max()) > 0
+
+
+def _rand_fields(shape, seed, k):
+    import torch
+    rng = np.random.default_rng(seed)
+    return [torch.tensor(rng.normal(size=shape), dtype=torch.float64, device='cuda') for _ in range(k)]
+
+
+@pytest.mark.parametrize('order,n', [(4, 45), (2, 45), (4, 13)])
+def test_grad_rk4_equals_four_single_stages(order, n):
+    # the four-stage launch (stage sums in registers, band partial sums
+    # added in stage order) against four one-stage calls at the stage
+    # times t + c_s dt, with displacement data on two faces; n = 13 has
+    # no interior points at order 4 (every point is a band point)
+    import torch
+    from paper_2003_12811_amd import sbpe as S
+    from paper_2003_12811_amd.solver import Solver
+    spec = W.spec_mms(n=n, order=order)
+    sol = Solver(spec, 'f64')
+    try:
+        shape = tuple(sol.u[0].shape)
+        n2, n1 = shape[1:]
+        z, y, a = (_rand_fields(shape, 100 * order + n + k, 4) for k in range(3))
+        al = [0.3, -0.7, 1.1, 0.25]
+        t, dt = 0.37, 0.01
+        out = [(torch.zeros((10, n2, n1), dtype=torch.float64, device='cuda'),
+                torch.zeros((n2, n1), dtype=torch.float64, device='cuda')) for _ in range(2)]
+        for s_ in range(4):
+            S.sbpe_grad_accumulate(sol.ctx, [z[s_].data_ptr()], [y[s_].data_ptr()], [a[s_].data_ptr()], al[s_],
+                                   t + ADJ.C_RK[s_] * dt, False, [out[0][0].data_ptr()], [out[0][1].data_ptr()])
+        S.sbpe_grad_accumulate_rk4(sol.ctx, [x.data_ptr() for x in z], [x.data_ptr() for x in y],
+                                   [x.data_ptr() for x in a], al, t, dt, False, [out[1][0].data_ptr()],
+                                   [out[1][1].data_ptr()])
+        torch.cuda.synchronize()
+        for f1, f4 in zip(out[0], out[1]):
+            r, q = f1.cpu().numpy(), f4.cpu().numpy()
+            err = np.abs(q - r).max() / np.abs(r).max()
+            say('order %d n %d: four-stage vs single stages, max rel %.2e' % (order, n, err))
+            assert err < 1e-13
+    finally:
+        sol.close()
+
+
+def test_stage_slopes_after_one_step():
+    # the RK workspace after one sbpe_advance step from (u, v) at time t:
+    # a1 = rho~^{-1}(L u + data(t)), a2 = rho~^{-1}(L (u + dt/2 v) + data(t + dt/2))
+    import torch
+    from paper_2003_12811_amd import sbpe as S
+    from paper_2003_12811_amd.solver import Solver
+    spec = W.spec_mms(n=37)
+    sol = Solver(spec, 'f64')
+    try:
+        shape = tuple(sol.u[0].shape)
+        u, v = _rand_fields(shape, 7, 2)
+        t, dt = 0.2, 1e-3
+        sol.set_state([u], [v], t)
+        sol.advance(1, dt)
+        n = int(np.prod(shape))
+        got = []
+        for p in S.sbpe_stage_slopes(sol.ctx, 0):
+            got.append(torch.empty(shape, dtype=torch.float64, device='cuda'))
+            S.sbpe_lincomb(sol.ctx, [1.0], [p], got[-1].data_ptr(), n)
+        e1 = sol.apply([u], t)[0]
+        e2 = sol.apply([u + 0.5 * dt * v], t + 0.5 * dt)[0]
+        torch.cuda.synchronize()
+        for g, e in zip(got, (e1, e2)):
+            err = float((g - e).abs().max() / e.abs().max())
+            say('stage slope: max rel %.2e' % err)
+            assert err < 1e-12
+        with pytest.raises(S.SbpeError):
+            S.sbpe_stage_slopes(sol.ctx, 1)
+    finally:
+        sol.close()
+
+
+def test_rk4_stages_rebuild_the_step():
+    # one sbpe_advance step from random (u, v) with boundary data and forcing;
+    # the rebuilt stage displacements against their definitions and the
+    # rebuilt slopes a3, a4 against sbpe_apply at U3 (t + dt/2) and U4 (t + dt)
+    import torch
+    from paper_2003_12811_amd import sbpe as S
+    from paper_2003_12811_amd.solver import Solver
+    spec = W.spec_mms(n=37)
+    sol = Solver(spec, 'f64')
+    try:
+        shape = tuple(sol.u[0].shape)
+        n = int(np.prod(shape))
+        u, v = _rand_fields(shape, 11, 2)
+        t, dt = 0.2, sol.dt_cfl(0.5)
+        sol.set_state([u], [v], t)
+        sol.advance(1, dt)
+        a1, a2 = S.sbpe_stage_slopes(sol.ctx, 0)
+        out = torch.empty((7,) + shape, dtype=torch.float64, device='cuda')
+        S.sbpe_rk4_stages(sol.ctx, u.data_ptr(), v.data_ptr(), sol.u[0].data_ptr(), sol.v[0].data_ptr(), a1, a2, dt,
+                          [out[i].data_ptr() for i in range(7)], n)
+        U2, U3, U4, A1, A2, A3, A4 = out
+        torch.cuda.synchronize()
+        e1 = sol.apply([u], t)[0]
+        e2 = sol.apply([U2], t + 0.5 * dt)[0]
+        e3 = sol.apply([U3], t + 0.5 * dt)[0]
+        e4 = sol.apply([U4], t + dt)[0]
+        torch.cuda.synchronize()
+        mx = lambda a, b: float((a - b).abs().max() / b.abs().max())
+        assert mx(U2, u + 0.5 * dt * v) < 1e-15
+        assert mx(U3, u + 0.5 * dt * v + 0.25 * dt * dt * A1) < 1e-15
+        assert mx(U4, u + dt * v + 0.5 * dt * dt * A2) < 1e-15
+        errs = [mx(A1, e1), mx(A2, e2), mx(A3, e3), mx(A4, e4)]
+        say('rk4 stages: slopes max rel %s' % ' '.join('%.1e' % e for e in errs))
+        assert errs[0] < 1e-13 and errs[1] < 1e-12 and errs[2] < 1e-10 and errs[3] < 1e-10
+        with pytest.raises(S.SbpeError):
+            S.sbpe_rk4_stages(sol.ctx, u.data_ptr(), v.data_ptr(), None, None, a1, a2, dt,
+                              [None] * 5 + [out[5].data_ptr(), None], n)
+    finally:
+        sol.close()

@@ -22,8 +22,10 @@
  *   - Every call returns SBPE_OK or a negative sbpe_status (sbpe.h), validates
  *     its arguments on the host first, and leaves a message for
  *     sbpe3_last_error on failure.  Device memory of the context (46
- *     coefficient fields, face data, forcing, RK workspace) is allocated at
- *     sbpe3_finalize and freed by sbpe3_destroy.
+ *     coefficient fields, face data, forcing, RK workspace of 6 fields and
+ *     18 fields of mixed-term fluxes, D_i c_ijkl D_k evaluated as D_i of the
+ *     flux sum_kl c_ijkl D_k u_l) is allocated at sbpe3_finalize and freed by
+ *     sbpe3_destroy.
  *   - Orders 2 and 4; FP64 and FP32; one block per context; traction and
  *     displacement faces (no Robin, interface, source or receiver terms).
  */

@@ -12,9 +12,11 @@
 //     penalty -(beta d / w_a^2) c_ajal delta_l;
 //   * r = rho~ a: a = rho~^{-1} (r + J f).
 // One thread per (point, field): the two fields of an RK sweep (u and v, or
-// A1 and A2) sit in neighbouring lanes and exchange their results.  This is a
-// correctness-first point kernel: every stencil value comes from global memory
-// (the caches serve the repeats).
+// A1 and A2) sit in neighbouring lanes and exchange their results.  The mixed
+// terms run in flux form: k_flux3 stores F_ij = sum_{k != i} c_ijkl D_k u_l at
+// every point, and the point kernel takes sum_i D_i F_ij, the same operator
+// with one coefficient read per point instead of one per stencil point.
+// Every stencil value comes from global memory (the caches serve the repeats).
 #include <hip/hip_runtime.h>
 
 #include "sbpe_device.h"
@@ -63,9 +65,10 @@ __device__ __forceinline__ T d1_at(gcp<T> x, const Geo3& g, long p, const int* c
     return d1_line<T, ORD>(x + (p - (long)c[k] * g.st[k]), g.st[k], c[k], g.n[k]);
 }
 
-// volume terms of L x at point p (coordinates c)
+// volume terms of L x at point p (coordinates c); fl: the nine fluxes F_ij of x
 template <typename T, int ORD>
-__device__ __forceinline__ void volume3(const Args3& A, const Geo3& g, gcp<T> x, long p, const int* c, T r[3]) {
+__device__ __forceinline__ void volume3(const Args3& A, const Geo3& g, gcp<T> x, gcp<T> fl, long p, const int* c,
+                                        T r[3]) {
     gcp<T> cf = gc<T>(A.coef);
     const long np = g.np;
 #pragma unroll
@@ -81,31 +84,12 @@ __device__ __forceinline__ void volume3(const Args3& A, const Geo3& g, gcp<T> x,
             r[j] += acc * s;
         }
     }
+    // mixed terms: sum_i D_i F_ij with the fluxes of this lane's field
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (k == i) continue;
-            const T s = T(1.0 / (g.h[i] * g.h[k]));
-            T acc[3] = {0, 0, 0};
-            int cq[3] = {c[0], c[1], c[2]};
-            d1_foreach<ORD>(c[i], g.n[i], [&](int ii, double w) {
-                const long q = p + (long)(ii - c[i]) * g.st[i];
-                cq[i] = ii;
-                T dk[3];
-#pragma unroll
-                for (int l = 0; l < 3; ++l) dk[l] = d1_at<T, ORD>(x + (long)l * np, g, q, cq, k);
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    T m = 0;
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) m += cf[(long)fM(i, k, j, l) * np + q] * dk[l];
-                    acc[j] += static_cast<T>(w) * m;
-                }
-            });
-#pragma unroll
-            for (int j = 0; j < 3; ++j) r[j] += acc[j] * s;
-        }
+        for (int j = 0; j < 3; ++j)
+            r[j] += d1_at<T, ORD>(fl + (long)(3 * i + j) * np, g, p, c, i) * T(1.0 / g.h[i]);
 }
 
 // index along face f of the point with coordinates c (the lower tangential direction fast)
@@ -261,33 +245,67 @@ __device__ __forceinline__ void data3(const Args3& A, const Geo3& g, long p, con
 
 }  // namespace
 
-template <typename T, int ORD>
-__global__ void __launch_bounds__(256) k_point3(Args3 A) {
-    const Geo3 g = geo3(A);
-    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
-    const int fld = (int)(gid & 1);                 // field of this lane
-    const long pr = gid >> 1;
-    const bool valid = pr < g.np;
-    const long p = valid ? pr : 0;
-    int c[3];
+// input field of lane fld of a pass
+__device__ __forceinline__ const void* pass_field(const Args3& A, int fld) {
+    return A.pass == PASS_APPLY ? A.in : (A.pass == PASS_RK1 ? (fld ? A.v : A.u) : (fld ? A.a2 : A.a1));
+}
+
+__device__ __forceinline__ void point_coords(const Geo3& g, long p, int c[3]) {
     c[2] = (int)(p / g.st[2]);
     const long rem = p - (long)c[2] * g.st[2];
     c[1] = (int)(rem / g.n[0]);
     c[0] = (int)(rem - (long)c[1] * g.n[0]);
-    const bool apply = A.pass == PASS_APPLY;
-    // input field of this lane
-    const void* xin = apply ? A.in : (A.pass == PASS_RK1 ? (fld ? A.v : A.u) : (fld ? A.a2 : A.a1));
-    gcp<T> x = gc<T>(xin);
-    T L[3] = {0, 0, 0}, D[3] = {0, 0, 0};
-    if (valid && !(apply && fld)) {
-        volume3<T, ORD>(A, g, x, p, c, L);
-        sats3<T, ORD, false>(A, g, x, p, c, nullptr, L);
-    }
-    // data: lane 0 with the first weights, lane 1 with the second (sbpe_apply: lane 1 with the first)
-    if (valid) {
-        const double* tw = (apply || !fld) ? A.tfa : A.tfb;
-        if (!(apply && !fld)) data3<T, ORD>(A, g, p, c, tw, D);
-    }
+}
+
+// Mixed-term fluxes of one field at one point:
+// F_ij = sum_{k != i} (1/h_k) sum_l c_ijkl (h D_k x_l), boundary rows of D_k included.
+template <typename T, int ORD>
+__global__ void __launch_bounds__(256) k_flux3(Args3 A) {
+    const Geo3 g = geo3(A);
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int fld = (int)(gid & 1);
+    const long p = gid >> 1;
+    if (p >= g.np || (A.pass == PASS_APPLY && fld)) return;
+    int c[3];
+    point_coords(g, p, c);
+    gcp<T> x = gc<T>(pass_field(A, fld));
+    gcp<T> cf = gc<T>(A.coef);
+    const long np = g.np;
+    T G[3][3];      // (1/h_k) h D_k x_l
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) G[k][l] = d1_at<T, ORD>(x + (long)l * np, g, p, c, k) * T(1.0 / g.h[k]);
+    gp<T> fo = gm<T>(A.flux) + (long)fld * 9 * np + p;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            T f = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (k == i) continue;
+#pragma unroll
+                for (int l = 0; l < 3; ++l) f += cf[(long)fM(i, k, j, l) * np + p] * G[k][l];
+            }
+            fo[(long)(3 * i + j) * np] = f;
+        }
+}
+
+// Points at least interior_margin3<ORD>() from every face: only interior rows
+// of D1 and D2^FC and no face terms reach them.
+template <int ORD>
+__host__ __device__ constexpr int interior_margin3() {
+    using O = Op<ORD>;
+    constexpr int m = O::R0 > O::NB ? O::R0 : O::NB;
+    return m > O::REACH ? m : O::REACH;
+}
+
+// Pass epilogue of one (point, field) lane: the partner lane of the same point
+// holds the other field; L = operator, D = data of this lane's field.
+template <typename T>
+__device__ __forceinline__ void finish3(const Args3& A, const Geo3& g, long p, int fld, bool valid, const T L[3],
+                                        const T D[3]) {
     T oL[3], oD[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -297,7 +315,7 @@ __global__ void __launch_bounds__(256) k_point3(Args3 A) {
     if (!valid) return;
     const T irho = gc<T>(A.coef)[(long)45 * g.np + p];
     const long np = g.np;
-    if (apply) {
+    if (A.pass == PASS_APPLY) {
         if (fld) return;
         gp<T> o = gm<T>(A.out);
 #pragma unroll
@@ -336,16 +354,124 @@ __global__ void __launch_bounds__(256) k_point3(Args3 A) {
     }
 }
 
+// Interior points: D2^FC rows in edge form and interior D1 rows of the fluxes,
+// body force only.
+template <typename T, int ORD>
+__global__ void __launch_bounds__(256) k_point3_int(Args3 A) {
+    constexpr int M = interior_margin3<ORD>();
+    const Geo3 g = geo3(A);
+    const int m1 = g.n[0] - 2 * M, m2 = g.n[1] - 2 * M;
+    const long nint = (long)m1 * m2 * (g.n[2] - 2 * M);
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int fld = (int)(gid & 1);
+    const long q = gid >> 1;
+    const bool valid = q < nint;
+    const long qq = valid ? q : 0;
+    const int c2 = (int)(qq / ((long)m1 * m2));
+    const long rem = qq - (long)c2 * m1 * m2;
+    const int c1 = (int)(rem / m1), c0 = (int)(rem - (long)c1 * m1);
+    const long p = (long)(c0 + M) + (long)(c1 + M) * g.st[1] + (long)(c2 + M) * g.st[2];
+    const bool apply = A.pass == PASS_APPLY;
+    gcp<T> x = gc<T>(pass_field(A, fld));
+    gcp<T> fl = gc<T>(A.flux) + (long)fld * 9 * g.np;
+    gcp<T> cf = gc<T>(A.coef);
+    const long np = g.np;
+    T L[3] = {0, 0, 0}, D[3] = {0, 0, 0};
+    if (valid && !(apply && fld)) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const long st = g.st[i];
+            const T s2 = T(1.0 / (g.h[i] * g.h[i])), s1 = T(1.0 / g.h[i]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T acc = 0;
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    acc += d2_interior<T, ORD>(cf + (long)fN(i, j, l) * np + p, x + (long)l * np + p, st);
+                gcp<T> f = fl + (long)(3 * i + j) * np + p;
+                L[j] += acc * s2 + d1_sym<ORD, T>([&](int o) { return f[(long)o * st]; }) * s1;
+            }
+        }
+    }
+    if (valid && !(apply && !fld) && A.force) {
+        const double tf = (apply || !fld) ? A.tfa[6] : A.tfb[6];
+        gcp<T> Fp = gc<T>(A.force);
+        if (tf != 0.0) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) D[j] = static_cast<T>(tf * (double)Fp[(long)j * np + p]);
+        }
+    }
+    finish3<T>(A, g, p, fld, valid, L, D);
+}
+
+// The other points (all of them when the block has no interior box): every
+// row boundary-aware, face terms and data.
+template <typename T, int ORD>
+__global__ void __launch_bounds__(256) k_point3(Args3 A) {
+    constexpr int M = interior_margin3<ORD>();
+    const Geo3 g = geo3(A);
+    const bool box = g.n[0] > 2 * M && g.n[1] > 2 * M && g.n[2] > 2 * M;
+    const long plane = (long)g.n[0] * g.n[1];
+    const long nshell = box ? g.np - (long)(g.n[0] - 2 * M) * (g.n[1] - 2 * M) * (g.n[2] - 2 * M) : g.np;
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int fld = (int)(gid & 1);                 // field of this lane
+    const long q = gid >> 1;
+    const bool valid = q < nshell;
+    const long qq = valid ? q : 0;
+    int c[3];
+    if (!box || qq < 2 * M * plane) {
+        // whole planes: all of them, or the M lowest and M highest in x3
+        const int pl = (int)(qq / plane);
+        const long rem = qq - (long)pl * plane;
+        c[2] = (!box || pl < M) ? pl : g.n[2] - 2 * M + pl;
+        c[1] = (int)(rem / g.n[0]);
+        c[0] = (int)(rem - (long)c[1] * g.n[0]);
+    } else {
+        // the frame of width M of each remaining plane
+        const long fr = plane - (long)(g.n[0] - 2 * M) * (g.n[1] - 2 * M);
+        const long k = qq - 2 * M * plane;
+        const int sl = (int)(k / fr);
+        c[2] = M + sl;
+        frame_ij((int)(k - (long)sl * fr), g.n[0], g.n[1], M, c[0], c[1]);
+    }
+    const long p = (long)c[0] + (long)c[1] * g.st[1] + (long)c[2] * g.st[2];
+    const bool apply = A.pass == PASS_APPLY;
+    // input field of this lane and its fluxes
+    gcp<T> x = gc<T>(pass_field(A, fld));
+    gcp<T> fl = gc<T>(A.flux) + (long)fld * 9 * g.np;
+    T L[3] = {0, 0, 0}, D[3] = {0, 0, 0};
+    if (valid && !(apply && fld)) {
+        volume3<T, ORD>(A, g, x, fl, p, c, L);
+        sats3<T, ORD, false>(A, g, x, p, c, nullptr, L);
+    }
+    // data: lane 0 with the first weights, lane 1 with the second (sbpe_apply: lane 1 with the first)
+    if (valid) {
+        const double* tw = (apply || !fld) ? A.tfa : A.tfb;
+        if (!(apply && !fld)) data3<T, ORD>(A, g, p, c, tw, D);
+    }
+    finish3<T>(A, g, p, fld, valid, L, D);
+}
+
+template <typename T, int ORD>
+static void launch_point3_t(const Args3& a, hipStream_t s) {
+    constexpr int M = interior_margin3<ORD>();
+    const long np = (long)a.n1 * a.n2 * a.n3;
+    const bool box = a.n1 > 2 * M && a.n2 > 2 * M && a.n3 > 2 * M;
+    const long nint = box ? (long)(a.n1 - 2 * M) * (a.n2 - 2 * M) * (a.n3 - 2 * M) : 0;
+    const dim3 b(256);
+    hipLaunchKernelGGL((k_flux3<T, ORD>), dim3((unsigned)((2 * np + 255) / 256)), b, 0, s, a);
+    if (nint > 0) hipLaunchKernelGGL((k_point3_int<T, ORD>), dim3((unsigned)((2 * nint + 255) / 256)), b, 0, s, a);
+    hipLaunchKernelGGL((k_point3<T, ORD>), dim3((unsigned)((2 * (np - nint) + 255) / 256)), b, 0, s, a);
+}
+
 int launch_point3(int dtype, int order, const Args3& a, void* stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const long np = (long)a.n1 * a.n2 * a.n3;
-    const dim3 g((unsigned)((2 * np + 255) / 256)), b(256);
     if (dtype == 0) {
-        if (order == 4) hipLaunchKernelGGL((k_point3<double, 4>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_point3<double, 2>), g, b, 0, s, a);
+        if (order == 4) launch_point3_t<double, 4>(a, s);
+        else launch_point3_t<double, 2>(a, s);
     } else {
-        if (order == 4) hipLaunchKernelGGL((k_point3<float, 4>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_point3<float, 2>), g, b, 0, s, a);
+        if (order == 4) launch_point3_t<float, 4>(a, s);
+        else launch_point3_t<float, 2>(a, s);
     }
     return (int)hipGetLastError();
 }

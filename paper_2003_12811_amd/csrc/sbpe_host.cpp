@@ -2616,6 +2616,7 @@ struct sbpe3_ctx {
     void* d_g[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     void* d_a1 = nullptr;
     void* d_a2 = nullptr;
+    void* d_flux = nullptr;         // mixed-term fluxes of a pass's two fields [2][9][np]
     double w[6] = {0, 0, 0, 0, 0, 0};
     bool finalized = false, bound = false;
     void* u = nullptr;
@@ -2748,14 +2749,14 @@ sbpe_status sbpe3_create(int device, void* stream, int dtype, int order, double 
 
 sbpe_status sbpe3_destroy(sbpe3_ctx_t c) {
     if (!c) return SBPE_OK;
-    if (c->finalized) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->d_coef);
-        (void)hipFree(c->d_force);
-        for (int f = 0; f < 6; ++f) (void)hipFree(c->d_g[f]);
-        (void)hipFree(c->d_a1);
-        (void)hipFree(c->d_a2);
-    }
+    // a finalize that failed part way may have left some of these behind
+    if (c->finalized) (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->d_coef);
+    (void)hipFree(c->d_force);
+    for (int f = 0; f < 6; ++f) (void)hipFree(c->d_g[f]);
+    (void)hipFree(c->d_a1);
+    (void)hipFree(c->d_a2);
+    (void)hipFree(c->d_flux);
     delete c;
     return SBPE_OK;
 }
@@ -2924,7 +2925,8 @@ sbpe_status sbpe3_finalize(sbpe3_ctx_t c) {
         if (s) return s;
     }
     const size_t es = c->dtype == SBPE_F64 ? 8 : 4;
-    if (d3malloc(&c->d_a1, 3 * np * es) != hipSuccess || d3malloc(&c->d_a2, 3 * np * es) != hipSuccess)
+    if (d3malloc(&c->d_a1, 3 * np * es) != hipSuccess || d3malloc(&c->d_a2, 3 * np * es) != hipSuccess ||
+        d3malloc(&c->d_flux, 2 * 9 * np * es) != hipSuccess)
         return fail3(c, SBPE_ENOMEM, "device allocation failed");
     c->finalized = true;
     return SBPE_OK;
@@ -2993,6 +2995,7 @@ static Args3 args3(const sbpe3_ctx* c) {
     }
     a.a1 = c->d_a1;
     a.a2 = c->d_a2;
+    a.flux = c->d_flux;
     return a;
 }
 

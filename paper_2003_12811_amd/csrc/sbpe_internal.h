@@ -260,9 +260,11 @@ struct Args3 {
     void* vo;
     const void* in;     // sbpe3_apply operand and result
     void* out;
+    void* flux;         // [2][9][np] mixed-term fluxes of the pass's two fields (k_flux3)
     double tfa[7], tfb[7];   // weighted time values of the 6 face items and the forcing:
                              // first / second evaluation of the pass
 };
+// one pass: the mixed-term fluxes (k_flux3), then the point kernel (k_point3)
 int launch_point3(int dtype, int order, const Args3& a, void* stream);
 
 const char* hip_error_string(int code);

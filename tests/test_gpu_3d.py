@@ -2,7 +2,9 @@
 
 One curvilinear block with a random major-symmetric stiffness, traction and
 displacement faces carrying data with a time function, and a body force:
-* one right-hand-side evaluation (sbpe3_apply) at orders 2 and 4, FP64 (1e-11
+* one right-hand-side evaluation (sbpe3_apply) at orders 2 and 4, on blocks
+  whose points are all near a face and on blocks with an interior box (the
+  interior and the shell kernels), FP64 (1e-11
   relative L2, and the max norm on the points next to the faces) and FP32
   (1e-5, on inputs shared bit for bit), with and without the data;
 * RK4 steps (sbpe3_advance, the two-sweep form) against the oracle's literal
@@ -83,7 +85,7 @@ def _band_max(a, b, n, depth):
 
 
 @pytest.mark.parametrize("dtype", ['f64', 'f32'])
-@pytest.mark.parametrize("order,n", [(2, (9, 10, 8)), (4, (13, 15, 14))])
+@pytest.mark.parametrize("order,n", [(2, (9, 10, 8)), (4, (13, 15, 14)), (2, (17, 18, 16)), (4, (29, 27, 25))])
 def test_apply_matches_oracle(order, n, dtype):
     import torch
     X, rho, C, faces, force = _case(n, order)

@@ -116,7 +116,7 @@ __device__ __forceinline__ void delta3(const Args3& A, const Geo3& g, gcp<T> x, 
 
 // SAT contribution of face f to r at point p (coordinates c, distance dn from the face)
 template <typename T, int ORD, bool DATA>
-__device__ void face3(const Args3& A, const Geo3& g, gcp<T> x, int f, long p, const int* c, int dn, double tau, T r[3]) {
+__device__ __forceinline__ void face3(const Args3& A, const Geo3& g, gcp<T> x, int f, long p, const int* c, int dn, double tau, T r[3]) {
     using O = Op<ORD>;
     const Face3& F = A.face[f];
     const int a = f >> 1;
@@ -404,35 +404,152 @@ __global__ void __launch_bounds__(256) k_point3_int(Args3 A) {
     finish3<T>(A, g, p, fld, valid, L, D);
 }
 
-// The other points (all of them when the block has no interior box): every
-// row boundary-aware, face terms and data.
+// Slab of axis AX: points within M of a face x_AX = 0 or 1 and at least M
+// from the faces of the other two axes.  Only the rows along AX are closure
+// rows and only the faces of AX reach them.
+template <typename T, int ORD, int AX>
+__global__ void __launch_bounds__(256) k_point3_slab(Args3 A) {
+    using O = Op<ORD>;
+    constexpr int M = interior_margin3<ORD>();
+    constexpr int B1 = AX == 0 ? 1 : 0, B2 = AX == 2 ? 1 : 2;   // the other two axes, B1 fastest
+    const Geo3 g = geo3(A);
+    const int mb1 = g.n[B1] - 2 * M, mb2 = g.n[B2] - 2 * M;
+    const long per = (long)mb1 * mb2;
+    const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int fld = (int)(gid & 1);
+    const long q = gid >> 1;
+    const bool valid = q < 2 * M * per;
+    const long qq = valid ? q : 0;
+    int c[3];
+    if (AX == 0) {
+        // x1 layers fastest, so that neighbouring lanes read neighbouring addresses
+        const int layer = (int)(qq % (2 * M));
+        const long rem = qq / (2 * M);
+        c[0] = layer < M ? layer : g.n[0] - 2 * M + layer;
+        c[2] = M + (int)(rem / mb1);
+        c[1] = M + (int)(rem - (long)(c[2] - M) * mb1);
+    } else {
+        const int layer = (int)(qq / per);
+        const long rem = qq - (long)layer * per;
+        c[AX] = layer < M ? layer : g.n[AX] - 2 * M + layer;
+        c[B2] = M + (int)(rem / mb1);
+        c[B1] = M + (int)(rem - (long)(c[B2] - M) * mb1);
+    }
+    const long p = (long)c[0] + (long)c[1] * g.st[1] + (long)c[2] * g.st[2];
+    const bool apply = A.pass == PASS_APPLY;
+    gcp<T> x = gc<T>(pass_field(A, fld));
+    gcp<T> fl = gc<T>(A.flux) + (long)fld * 9 * g.np;
+    gcp<T> cf = gc<T>(A.coef);
+    const long np = g.np;
+    // the face of AX within reach, if any
+    const int hi = c[AX] >= M ? 1 : 0;
+    const int dn = hi ? g.n[AX] - 1 - c[AX] : c[AX];
+    const int f = 2 * AX + hi;
+    T L[3] = {0, 0, 0}, D[3] = {0, 0, 0};
+    if (valid && !(apply && fld)) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const long st = g.st[i];
+            const T s2 = T(1.0 / (g.h[i] * g.h[i])), s1 = T(1.0 / g.h[i]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T acc = 0, mx;
+                gcp<T> fj = fl + (long)(3 * i + j) * np;
+                if (i == AX) {
+                    const long l0 = p - (long)c[i] * st;
+#pragma unroll
+                    for (int l = 0; l < 3; ++l)
+                        acc += d2_line<T, ORD>(cf + (long)fN(i, j, l) * np + l0, x + (long)l * np + l0, st, c[i], g.n[i]);
+                    mx = d1_at<T, ORD>(fj, g, p, c, i);
+                } else {
+#pragma unroll
+                    for (int l = 0; l < 3; ++l)
+                        acc += d2_interior<T, ORD>(cf + (long)fN(i, j, l) * np + p, x + (long)l * np + p, st);
+                    mx = d1_sym<ORD, T>([&](int o) { return fj[p + (long)o * st]; });
+                }
+                L[j] += acc * s2 + mx * s1;
+            }
+        }
+        if (dn < O::REACH) face3<T, ORD, false>(A, g, x, f, p, c, dn, 0.0, L);
+    }
+    if (valid && !(apply && !fld)) {
+        const double* tw = (apply || !fld) ? A.tfa : A.tfb;
+        if (dn < O::REACH && tw[f] != 0.0) face3<T, ORD, true>(A, g, gcp<T>(nullptr), f, p, c, dn, tw[f], D);
+        if (A.force && tw[6] != 0.0) {
+            gcp<T> Fp = gc<T>(A.force);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) D[j] += static_cast<T>(tw[6] * (double)Fp[(long)j * np + p]);
+        }
+    }
+    finish3<T>(A, g, p, fld, valid, L, D);
+}
+
+// Coordinate of index l of the 2M boundary layers of an axis of n points.
+__device__ __forceinline__ int layer_coord(int l, int n, int M) { return l < M ? l : n - 2 * M + l; }
+
+// The points near the faces of two or three axes (edges and corners), or all
+// points when the block has no interior box: every row boundary-aware, face
+// terms and data.
 template <typename T, int ORD>
 __global__ void __launch_bounds__(256) k_point3(Args3 A) {
     constexpr int M = interior_margin3<ORD>();
     const Geo3 g = geo3(A);
     const bool box = g.n[0] > 2 * M && g.n[1] > 2 * M && g.n[2] > 2 * M;
-    const long plane = (long)g.n[0] * g.n[1];
-    const long nshell = box ? g.np - (long)(g.n[0] - 2 * M) * (g.n[1] - 2 * M) * (g.n[2] - 2 * M) : g.np;
+    constexpr long L2 = 4L * M * M;       // (2M)^2 layer pairs
+    const long nb0 = box ? L2 * (g.n[0] - 2 * M) : 0, nb1 = box ? L2 * (g.n[1] - 2 * M) : 0,
+               nb2 = box ? L2 * (g.n[2] - 2 * M) : 0;
+    const long nedge = box ? nb0 + nb1 + nb2 + 2L * M * L2 : g.np;
     const long gid = (long)blockIdx.x * 256 + threadIdx.x;
     const int fld = (int)(gid & 1);                 // field of this lane
     const long q = gid >> 1;
-    const bool valid = q < nshell;
-    const long qq = valid ? q : 0;
+    const bool valid = q < nedge;
+    long k = valid ? q : 0;
     int c[3];
-    if (!box || qq < 2 * M * plane) {
-        // whole planes: all of them, or the M lowest and M highest in x3
-        const int pl = (int)(qq / plane);
-        const long rem = qq - (long)pl * plane;
-        c[2] = (!box || pl < M) ? pl : g.n[2] - 2 * M + pl;
+    if (!box) {
+        c[2] = (int)(k / g.st[2]);
+        const long rem = k - (long)c[2] * g.st[2];
         c[1] = (int)(rem / g.n[0]);
         c[0] = (int)(rem - (long)c[1] * g.n[0]);
     } else {
-        // the frame of width M of each remaining plane
-        const long fr = plane - (long)(g.n[0] - 2 * M) * (g.n[1] - 2 * M);
-        const long k = qq - 2 * M * plane;
-        const int sl = (int)(k / fr);
-        c[2] = M + sl;
-        frame_ij((int)(k - (long)sl * fr), g.n[0], g.n[1], M, c[0], c[1]);
+        // bars along x1, x2, x3 (interior coordinate along the bar, boundary
+        // layers on the other two axes), then the corners
+        int a = 3;
+        if (k < nb0) {
+            a = 0;
+        } else if (k < nb0 + nb1) {
+            a = 1;
+            k -= nb0;
+        } else if (k < nb0 + nb1 + nb2) {
+            a = 2;
+            k -= nb0 + nb1;
+        } else {
+            k -= nb0 + nb1 + nb2;
+        }
+        // the x1 coordinate varies fastest in every part
+        if (a == 0) {
+            const int ma = g.n[0] - 2 * M;
+            const int l = (int)(k / ma);
+            c[0] = M + (int)(k - (long)l * ma);
+            c[1] = layer_coord(l % (2 * M), g.n[1], M);
+            c[2] = layer_coord(l / (2 * M), g.n[2], M);
+        } else if (a == 1) {
+            const int m1 = g.n[1] - 2 * M;
+            const long r = k / (2 * M);
+            c[0] = layer_coord((int)(k - r * 2 * M), g.n[0], M);
+            c[1] = M + (int)(r % m1);
+            c[2] = layer_coord((int)(r / m1), g.n[2], M);
+        } else if (a == 2) {
+            const long r = k / (2 * M);
+            c[0] = layer_coord((int)(k - r * 2 * M), g.n[0], M);
+            c[1] = layer_coord((int)(r % (2 * M)), g.n[1], M);
+            c[2] = M + (int)(r / (2 * M));
+        } else {
+            // corner: boundary layers on all three axes
+            const int l = (int)k;
+            c[0] = layer_coord(l % (2 * M), g.n[0], M);
+            c[1] = layer_coord((l / (2 * M)) % (2 * M), g.n[1], M);
+            c[2] = layer_coord(l / (4 * M * M), g.n[2], M);
+        }
     }
     const long p = (long)c[0] + (long)c[1] * g.st[1] + (long)c[2] * g.st[2];
     const bool apply = A.pass == PASS_APPLY;
@@ -453,27 +570,40 @@ __global__ void __launch_bounds__(256) k_point3(Args3 A) {
 }
 
 template <typename T, int ORD>
-static void launch_point3_t(const Args3& a, hipStream_t s) {
+static int launch_point3_t(const Args3& a, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
     constexpr int M = interior_margin3<ORD>();
     const long np = (long)a.n1 * a.n2 * a.n3;
     const bool box = a.n1 > 2 * M && a.n2 > 2 * M && a.n3 > 2 * M;
-    const long nint = box ? (long)(a.n1 - 2 * M) * (a.n2 - 2 * M) * (a.n3 - 2 * M) : 0;
     const dim3 b(256);
-    hipLaunchKernelGGL((k_flux3<T, ORD>), dim3((unsigned)((2 * np + 255) / 256)), b, 0, s, a);
-    if (nint > 0) hipLaunchKernelGGL((k_point3_int<T, ORD>), dim3((unsigned)((2 * nint + 255) / 256)), b, 0, s, a);
-    hipLaunchKernelGGL((k_point3<T, ORD>), dim3((unsigned)((2 * (np - nint) + 255) / 256)), b, 0, s, a);
+    auto grid = [](long pts) { return dim3((unsigned)((2 * pts + 255) / 256)); };
+    hipLaunchKernelGGL((k_flux3<T, ORD>), grid(np), b, 0, s, a);
+    if (!box) {
+        hipLaunchKernelGGL((k_point3<T, ORD>), grid(np), b, 0, s, a);
+        return (int)hipGetLastError();
+    }
+    // the edge and corner points (few, each a long chain) beside the rest
+    const long m[3] = {a.n1 - 2 * M, a.n2 - 2 * M, a.n3 - 2 * M};
+    const long edges = 4L * M * M * (m[0] + m[1] + m[2]) + 8L * M * M * M;
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL((k_point3<T, ORD>), grid(edges), b, 0, side, a);
+    hipLaunchKernelGGL((k_point3_int<T, ORD>), grid(m[0] * m[1] * m[2]), b, 0, s, a);
+    hipLaunchKernelGGL((k_point3_slab<T, ORD, 0>), grid(2L * M * m[1] * m[2]), b, 0, s, a);
+    hipLaunchKernelGGL((k_point3_slab<T, ORD, 1>), grid(2L * M * m[0] * m[2]), b, 0, s, a);
+    hipLaunchKernelGGL((k_point3_slab<T, ORD, 2>), grid(2L * M * m[0] * m[1]), b, 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    return (int)e;
 }
 
-int launch_point3(int dtype, int order, const Args3& a, void* stream) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (dtype == 0) {
-        if (order == 4) launch_point3_t<double, 4>(a, s);
-        else launch_point3_t<double, 2>(a, s);
-    } else {
-        if (order == 4) launch_point3_t<float, 4>(a, s);
-        else launch_point3_t<float, 2>(a, s);
-    }
-    return (int)hipGetLastError();
+int launch_point3(int dtype, int order, const Args3& a, void* stream, void* side, void* fork, void* join) {
+    hipStream_t s = static_cast<hipStream_t>(stream), sd = static_cast<hipStream_t>(side);
+    hipEvent_t f = static_cast<hipEvent_t>(fork), j = static_cast<hipEvent_t>(join);
+    if (dtype == 0) return order == 4 ? launch_point3_t<double, 4>(a, s, sd, f, j) : launch_point3_t<double, 2>(a, s, sd, f, j);
+    return order == 4 ? launch_point3_t<float, 4>(a, s, sd, f, j) : launch_point3_t<float, 2>(a, s, sd, f, j);
 }
 
 }  // namespace sbpe

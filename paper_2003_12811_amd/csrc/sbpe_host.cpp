@@ -2617,6 +2617,8 @@ struct sbpe3_ctx {
     void* d_a1 = nullptr;
     void* d_a2 = nullptr;
     void* d_flux = nullptr;         // mixed-term fluxes of a pass's two fields [2][9][np]
+    hipStream_t side = nullptr;     // the edge and corner points of a pass run here
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double w[6] = {0, 0, 0, 0, 0, 0};
     bool finalized = false, bound = false;
     void* u = nullptr;
@@ -2737,12 +2739,20 @@ sbpe_status sbpe3_create(int device, void* stream, int dtype, int order, double 
     if (order != 2 && order != 4) return fail3(nullptr, SBPE_EINVAL, "3-D blocks take orders 2 and 4");
     if (!(beta >= 1.0)) return fail3(nullptr, SBPE_EINVAL, "beta must be >= 1");
     if (device < 0) return fail3(nullptr, SBPE_EINVAL, "bad device");
+    if (hipSetDevice(device) != hipSuccess) return fail3(nullptr, SBPE_EHIP, "hipSetDevice failed");
     auto* c = new sbpe3_ctx;
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
     c->dtype = dtype;
     c->order = order;
     c->beta = beta;
+    // side stream of the edge and corner points (default priority)
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        sbpe3_destroy(c);
+        return fail3(nullptr, SBPE_EHIP, "stream/event creation failed");
+    }
     *out = c;
     return SBPE_OK;
 }
@@ -2757,6 +2767,12 @@ sbpe_status sbpe3_destroy(sbpe3_ctx_t c) {
     (void)hipFree(c->d_a1);
     (void)hipFree(c->d_a2);
     (void)hipFree(c->d_flux);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
     return SBPE_OK;
 }
@@ -3014,7 +3030,7 @@ sbpe_status sbpe3_apply(sbpe3_ctx_t c, const void* u, void* a, double t, int hom
     A.in = u;
     A.out = a;
     if (!homogeneous) tvals3(c, t, A.tfa);
-    const int e = launch_point3(c->dtype, c->order, A, c->stream);
+    const int e = launch_point3(c->dtype, c->order, A, c->stream, c->side, c->ev_fork, c->ev_join);
     if (e) return fail3(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
     return SBPE_OK;
 }
@@ -3052,14 +3068,14 @@ sbpe_status sbpe3_advance(sbpe3_ctx_t c, int nsteps, double dt) {
             A.tfa[q] = v0[q];
             A.tfb[q] = vh[q];
         }
-        int e = launch_point3(c->dtype, c->order, A, c->stream);
+        int e = launch_point3(c->dtype, c->order, A, c->stream, c->side, c->ev_fork, c->ev_join);
         if (e) return fail3(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
         A.pass = PASS_RK2;
         for (int q = 0; q < 7; ++q) {
             A.tfa[q] = 0.0;
             A.tfb[q] = 2.0 / (dt * dt) * (v0[q] - 2.0 * vh[q] + v1[q]);
         }
-        e = launch_point3(c->dtype, c->order, A, c->stream);
+        e = launch_point3(c->dtype, c->order, A, c->stream, c->side, c->ev_fork, c->ev_join);
         if (e) return fail3(c, SBPE_EHIP, std::string("kernel launch: ") + hip_error_string(e));
         c->t = t + dt;
     }

@@ -264,8 +264,9 @@ struct Args3 {
     double tfa[7], tfb[7];   // weighted time values of the 6 face items and the forcing:
                              // first / second evaluation of the pass
 };
-// one pass: the mixed-term fluxes (k_flux3), then the point kernel (k_point3)
-int launch_point3(int dtype, int order, const Args3& a, void* stream);
+// one pass: the mixed-term fluxes (k_flux3), then the interior-box, slab and
+// edge point kernels; the edges run on `side` between the events fork and join
+int launch_point3(int dtype, int order, const Args3& a, void* stream, void* side, void* fork, void* join);
 
 const char* hip_error_string(int code);
 // device scratch of the no-allocation advance (sbpe_advance_noalloc): doubles

@@ -19,6 +19,7 @@
 // Every stencil value comes from global memory (the caches serve the repeats).
 #include <hip/hip_runtime.h>
 
+#include "sbpe3_internal.h"
 #include "sbpe_device.h"
 
 namespace sbpe {

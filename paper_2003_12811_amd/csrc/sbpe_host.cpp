@@ -24,6 +24,7 @@
 #include "../../include/sbpe.h"
 #include "../../include/sbpe3.h"
 #include "sbpe_internal.h"
+#include "sbpe3_internal.h"
 #include "sbpe_tables.h"
 
 namespace sbpe {

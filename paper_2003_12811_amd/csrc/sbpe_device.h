@@ -1914,6 +1914,35 @@ __device__ __forceinline__ double d2_edge_dw(int e, int o) {
     }
 }
 
+// Closure rows of d2_coef_grad for the coefficient at distance P from the end
+// of a line (lo: the lower end, else the mirrored upper end): with P a
+// compile-time index the table weights are constants and their zeros drop out.
+template <typename T, int ORD, int P>
+__device__ __forceinline__ double d2_closure_grad_at(gcp<T> z, gcp<T> y, long st, int n, bool lo) {
+    using O = Op<ORD>;
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < O::R0; ++r) {
+        const int ir = lo ? r : n - 1 - r;
+        const double yr = (double)y[(long)ir * st];
+        double sum = 0.0;
+#pragma unroll
+        for (int m = 0; m < O::W; ++m) {
+            if (m == r) continue;
+            const double w = O::d2c(r, m, P);
+            if (w != 0.0) sum += w * ((double)y[(long)(lo ? m : n - 1 - m) * st] - yr);
+        }
+        acc += hnorm<ORD>(ir, n) * (double)z[(long)ir * st] * sum;
+    }
+    return acc;
+}
+template <typename T, int ORD, int P>
+__device__ __forceinline__ double d2_closure_grad(int p, gcp<T> z, gcp<T> y, long st, int n, bool lo) {
+    if (p == P) return d2_closure_grad_at<T, ORD, P>(z, y, st, n, lo);
+    if constexpr (P + 1 < Op<ORD>::W) return d2_closure_grad<T, ORD, P + 1>(p, z, y, st, n, lo);
+    else return 0.0;
+}
+
 // sum_r H^_r z_r sum_m dk_rm/db_p (y_m - y_r) along a line (stride st, n points)
 template <typename T, int ORD>
 __device__ double d2_coef_grad(gcp<T> z, gcp<T> y, long st, int p, int n) {
@@ -1936,36 +1965,8 @@ __device__ double d2_coef_grad(gcp<T> z, gcp<T> y, long st, int p, int n) {
         acc += hnorm<ORD>(r, n) * (double)z[(long)r * st] * sum;
     }
     // closure rows at the lower end (coefficient index p) and the upper end (n-1-p)
-    if (p < O::W) {
-#pragma unroll
-        for (int r = 0; r < O::R0; ++r) {
-            const double yr = (double)y[(long)r * st];
-            double sum = 0.0;
-#pragma unroll
-            for (int m = 0; m < O::W; ++m) {
-                if (m == r) continue;
-                const double w = table_d2c<ORD>(r, m, p);
-                if (w != 0.0) sum += w * ((double)y[(long)m * st] - yr);
-            }
-            acc += hnorm<ORD>(r, n) * (double)z[(long)r * st] * sum;
-        }
-    }
-    if (n - 1 - p < O::W) {
-        const int pp = n - 1 - p;
-#pragma unroll
-        for (int r = 0; r < O::R0; ++r) {
-            const int rr = n - 1 - r;
-            const double yr = (double)y[(long)rr * st];
-            double sum = 0.0;
-#pragma unroll
-            for (int m = 0; m < O::W; ++m) {
-                if (m == r) continue;
-                const double w = table_d2c<ORD>(r, m, pp);
-                if (w != 0.0) sum += w * ((double)y[(long)(n - 1 - m) * st] - yr);
-            }
-            acc += hnorm<ORD>(rr, n) * (double)z[(long)rr * st] * sum;
-        }
-    }
+    if (p < O::W) acc += d2_closure_grad<T, ORD, 0>(p, z, y, st, n, true);
+    if (n - 1 - p < O::W) acc += d2_closure_grad<T, ORD, 0>(n - 1 - p, z, y, st, n, false);
     return acc;
 }
 

@@ -309,3 +309,25 @@ def test_allocator_states():
     finally:
         S.sbpe_destroy(ctx)
     assert calls == []
+
+
+def test_homogeneous_spec_keeps_the_operator_and_drops_the_data():
+    # the adjoint's data-free context: same blocks, material, boundary kinds,
+    # Robin matrices, interfaces and operator; no boundary data, forcing,
+    # sources, receivers or interface jump data
+    from paper_2003_12811_amd import adjoint as ADJ
+    spec = W.spec_mms(n=17)
+    spec['sources'] = [(0, 0.5, 0.5, 0.0, 1.0, 1.0, 10.0, 0.1)]
+    spec['receivers'] = [(0, np.array([0.3]), np.array([0.7]))]
+    spec['interface_data'] = [(0, None, None, 0, None)]
+    spec['operator'] = 'wide'
+    h = ADJ.homogeneous_spec(spec)
+    assert 'sources' not in h and 'receivers' not in h and 'interface_data' not in h
+    assert h['operator'] == 'wide' and h['order'] == spec['order'] and h['interfaces'] == spec['interfaces']
+    for b, hb in zip(spec['blocks'], h['blocks']):
+        assert hb.get('forcing') is None and b.get('forcing') is not None
+        assert hb['X1'] is b['X1'] and hb['rho'] is b['rho'] and hb['C10'] is b['C10']
+        for (kind, g, tfn, tp, U), (hk, hg, htf, htp, hU) in zip(b['bc'], hb['bc']):
+            assert hk == kind and hU is U and hg is None and htf is None and htp is None
+    # the input is left as it was
+    assert spec['blocks'][0]['bc'][1][1] is not None and 'sources' in spec

@@ -880,15 +880,19 @@ __global__ void __launch_bounds__(256) k_frame_gather(const T* y, int n1, int n2
     ((gp<T>)out)[2 * k + 1] = ((gcp<T>)y)[np + p];
 }
 
-// FRAME_LANES lanes per frame point, half per component row.  Frame points are
-// numbered globally in groups of FRAME_PTS per block (the k_frame workgroup
-// layout, so the point-entry ranges carry over); a workgroup of nt threads
-// takes points fwg * nt / FRAME_LANES .. (fwg + 1) * nt / FRAME_LANES - 1.
-// Every load that does not depend on the row's entries is issued first, and
-// the row is gathered FRAME_UNROLL entries per lane at a time (all column and
-// weight loads, then all gathers), so a row costs few round trips to memory.
+// FRAME_LANES lanes per frame point.  Frame points are numbered globally in
+// groups of FRAME_PTS per block (the k_frame workgroup layout, so the
+// point-entry ranges carry over); a workgroup of nt threads takes points
+// fwg * nt / FRAME_LANES .. (fwg + 1) * nt / FRAME_LANES - 1.  The operator
+// is stored in 2x2 blocks, one per neighbouring point: every lane takes a
+// share of the point's blocks for both component rows (one column index and
+// one gather of each input component per block), the lanes' sums meet by
+// shuffles, and lanes 0 .. FRAME_LANES/2 - 1 go on with the first component
+// row, the others with the second.  Every load that does not depend on the
+// point's blocks is issued first, and the blocks are gathered FRAME_UNROLL
+// per lane at a time (all column and weight loads, then all gathers).
 constexpr int FRAME_LANES = 8;
-constexpr int FRAME_UNROLL = 8;
+constexpr int FRAME_UNROLL = 4;
 
 template <typename T, int ORD, int PASS>
 __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt) {
@@ -943,52 +947,62 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
         uo = gc<T>(B.u)[qp];
         vo = gc<T>(B.v)[qp];
     }
-    T acc[NF];
+    // both component rows of the point, summed over this lane's blocks
+    T ab[NF][2];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = T(0);
+    for (int f = 0; f < NF; ++f) ab[f][0] = ab[f][1] = T(0);
     if (valid) {
-        const int row = 2 * k + q;
-        const GLB int* rp = (const GLB int*)B.fr_rowptr;
+        const GLB int* bp = (const GLB int*)B.fr_rowptr;
         const GLB int* cl = (const GLB int*)B.fr_col;
         gcp<T> vl = gc<T>(B.fr_val);
-        const int e0 = rp[row], e1 = rp[row + 1];
+        const int e0 = bp[k], e1 = bp[k + 1];
         bool partner = false;
-        for (int e = e0 + sl; e < e1; e += RL * U) {
+        for (int e = e0 + lane; e < e1; e += FRAME_LANES * U) {
             int cc[U];
-            T ww[U];
+            T ww[U][4];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int ee = e + RL * u;
-                const int ec = ee < e1 ? ee : e0;          // e0 < e1 here: a valid entry
+                const int ee = e + FRAME_LANES * u;
+                const int ec = ee < e1 ? ee : e0;          // e0 < e1 here: a valid block
                 cc[u] = cl[ec];
-                ww[u] = vl[ec];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ww[u][r] = vl[4 * (long)ec + r];
             }
-            T xv[U][NF];
-            int qq[U];
+            T xv[U][NF][2];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const bool in = e + RL * u < e1;
+                const bool in = e + FRAME_LANES * u < e1;
                 const int c = cc[u];
                 partner |= in && c < 0;
-                if (!(in && c >= 0)) ww[u] = T(0);
-                qq[u] = c >= 0 ? (c & 1) : 0;
-                const long ix = c >= 0 ? (long)qq[u] * np + (c >> 1) : p;
+                if (!(in && c >= 0))
 #pragma unroll
-                for (int f = 0; f < NF; ++f) xv[u][f] = xf[f][ix];
+                    for (int r = 0; r < 4; ++r) ww[u][r] = T(0);
+                const long ix = c >= 0 ? (long)c : p;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    xv[u][f][0] = xf[f][ix];
+                    xv[u][f][1] = xf[f][np + ix];
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int f = 0; f < NF; ++f) acc[f] += ww[u] * (xv[u][f] - (qq[u] ? xp[f][1] : xp[f][0]));
+                for (int f = 0; f < NF; ++f) {
+                    const T d0 = xv[u][f][0] - xp[f][0], d1 = xv[u][f][1] - xp[f][1];
+                    ab[f][0] += ww[u][0] * d0 + ww[u][1] * d1;
+                    ab[f][1] += ww[u][2] * d0 + ww[u][3] * d1;
+                }
         }
         if (partner) {
-            // columns in a partner block across an interface
-            for (int e = e0 + sl; e < e1; e += RL) {
+            // blocks of a partner block's point across an interface
+            for (int e = e0 + lane; e < e1; e += FRAME_LANES) {
                 const int c = cl[e];
                 if (c >= 0) continue;
-                const T w = vl[e];
+                T w[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w[r] = vl[4 * (long)e + r];
                 const int v = -1 - c;
-                const int ff = v >> 29, qq = (v >> 28) & 1;
+                const int ff = v >> 29;
                 const long pp = v & ((1 << 28) - 1);
                 const GLB FaceDesc& F = B.face[ff];
                 const int pb = F.partner;
@@ -1005,15 +1019,25 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
                     pf[1] = gc<T>(P.a2);
                 }
 #pragma unroll
-                for (int f = 0; f < NF; ++f) acc[f] += w * (pf[f][qq * npp + pp] - xp[f][qq]);
+                for (int f = 0; f < NF; ++f) {
+                    const T d0 = pf[f][pp] - xp[f][0], d1 = pf[f][npp + pp] - xp[f][1];
+                    ab[f][0] += w[0] * d0 + w[1] * d1;
+                    ab[f][1] += w[2] * d0 + w[3] * d1;
+                }
             }
         }
     }
-    // reduce the lanes of the row
+    // reduce the lanes of the point; each lane keeps its component row
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
-        for (int m = 1; m < RL; m <<= 1) acc[f] += __shfl_xor(acc[f], m);
+        for (int m = 1; m < FRAME_LANES; m <<= 1) {
+            ab[f][0] += __shfl_xor(ab[f][0], m);
+            ab[f][1] += __shfl_xor(ab[f][1], m);
+        }
+    T acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = q ? ab[f][1] : ab[f][0];
     if (valid) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[f] += s0 * xp[f][0] + s1 * xp[f][1];

@@ -1516,14 +1516,52 @@ static sbpe_status assemble_frame(sbpe_ctx* c) {
             }
         }
         if (bad) break;
-        if (dmalloc(c, &H.d_fr_rowptr, rp.size() * sizeof(int)) != hipSuccess ||
-            dmalloc(c, &H.d_fr_col, cl.size() * sizeof(int)) != hipSuccess) {
+        // 2x2 blocks: the two component rows of point k (rows 2k, 2k + 1)
+        // merged by neighbouring point; block e holds the column of its
+        // point's first component (a partner point's code with the component
+        // bit clear) and the values K[row][component] at 4e + 2 row + component
+        auto bkey = [](int col) { return col >= 0 ? col >> 1 : -1 - ((-1 - col) & ~(1 << 28)); };
+        auto bcomp = [](int col) { return col >= 0 ? col & 1 : ((-1 - col) >> 28) & 1; };
+        std::vector<int> bpt(fn + 1, 0);
+#pragma omp parallel
+        {
+            std::vector<int> keys;
+#pragma omp for schedule(static)
+            for (long k = 0; k < fn; ++k) {
+                keys.clear();
+                for (int e = rp[2 * k]; e < rp[2 * k + 2]; ++e) keys.push_back(bkey(cl[e]));
+                std::sort(keys.begin(), keys.end());
+                bpt[k + 1] = (int)(std::unique(keys.begin(), keys.end()) - keys.begin());
+            }
+        }
+        for (long k = 0; k < fn; ++k) bpt[k + 1] += bpt[k];
+        std::vector<int> bcl(std::max(bpt[fn], 1), 0);
+        std::vector<double> bvv(4 * (size_t)std::max(bpt[fn], 1), 0.0);
+#pragma omp parallel
+        {
+            std::vector<int> keys;
+#pragma omp for schedule(static)
+            for (long k = 0; k < fn; ++k) {
+                keys.clear();
+                for (int e = rp[2 * k]; e < rp[2 * k + 2]; ++e) keys.push_back(bkey(cl[e]));
+                std::sort(keys.begin(), keys.end());
+                keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+                for (size_t m = 0; m < keys.size(); ++m) bcl[bpt[k] + m] = keys[m];
+                for (int r = 0; r < 2; ++r)
+                    for (int e = rp[2 * k + r]; e < rp[2 * k + r + 1]; ++e) {
+                        const long m = std::lower_bound(keys.begin(), keys.end(), bkey(cl[e])) - keys.begin();
+                        bvv[4 * (size_t)(bpt[k] + m) + 2 * r + bcomp(cl[e])] += vv[e];
+                    }
+            }
+        }
+        if (dmalloc(c, &H.d_fr_rowptr, bpt.size() * sizeof(int)) != hipSuccess ||
+            dmalloc(c, &H.d_fr_col, bcl.size() * sizeof(int)) != hipSuccess) {
             cleanup_all();
             return fail(c, SBPE_ENOMEM, "frame operator");
         }
-        HIPCHECK(c, hipMemcpy(H.d_fr_rowptr, rp.data(), rp.size() * sizeof(int), hipMemcpyHostToDevice));
-        HIPCHECK(c, hipMemcpy(H.d_fr_col, cl.data(), cl.size() * sizeof(int), hipMemcpyHostToDevice));
-        st = upload(c, vv, &H.d_fr_val);
+        HIPCHECK(c, hipMemcpy(H.d_fr_rowptr, bpt.data(), bpt.size() * sizeof(int), hipMemcpyHostToDevice));
+        HIPCHECK(c, hipMemcpy(H.d_fr_col, bcl.data(), bcl.size() * sizeof(int), hipMemcpyHostToDevice));
+        st = upload(c, bvv, &H.d_fr_val);
         if (!st) st = upload(c, rs, &H.d_fr_rsum);
         if (st) {
             cleanup_all();

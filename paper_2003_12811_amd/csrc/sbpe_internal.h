@@ -88,12 +88,14 @@ struct BlockDesc {
     double* rec;              // receiver slots [steps][nrec*16][2], or null
     long rec_stride;          // doubles per step in rec
     // assembled frame operator rho~^{-1} L restricted to the frame rows (null
-    // until assembled): CSR over rows 2k + q (frame point k, component q);
-    // col >= 0: own block, 2 p + q'; col < 0: -1 - ((f << 29) | (q' << 28) | p)
-    // for point p of the interface partner across face f
+    // until assembled), in 2x2 blocks: frame point k holds the blocks
+    // fr_rowptr[k] .. fr_rowptr[k + 1] - 1, one per neighbouring point; block
+    // e's column is p (point p of this block) or -1 - ((f << 29) | p) (point p
+    // of the interface partner across face f), its values K[q][q'] (output
+    // component q, input component q') are fr_val[4 e + 2 q + q']
     const int* fr_rowptr;
     const int* fr_col;
-    const void* fr_val;       // [nnz] in the context dtype
+    const void* fr_val;       // [4 blocks] in the context dtype
     const void* fr_rsum;      // [2 frame_n][2] row sums per input component
 };
 

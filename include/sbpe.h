@@ -99,7 +99,8 @@ sbpe_status sbpe_add_block(sbpe_ctx_t ctx, int n1, int n2, const double* X1, con
 sbpe_status sbpe_voigt_to_c10(const double* voigt, size_t npts, double* C10);
 
 /* Output rows per interior tile, a launch-shape parameter (results do not
- * depend on it): 0 (default) = 10, else 1..256.  Which height runs fastest
+ * depend on it): 0 (default) = 10, or order + 1 on small grids (fewer than
+ * 384 default tiles and 384 frame groups), else 1..256.  Which height runs fastest
  * depends on the grid and dtype through how the tiles fill the machine; the
  * benchmark picks it by timing a few candidates.  Call before sbpe_finalize
  * (SBPE_ESTATE after it; SBPE_EINVAL outside 0..256).  The environment
@@ -108,7 +109,8 @@ sbpe_status sbpe_set_tile_rows(sbpe_ctx_t ctx, int rows);
 
 /* Frame groups per frame workgroup of a one-launch sweep (another launch-shape
  * parameter; results do not depend on it): 1 .. 64, default 2 (FP64) or 4
- * (FP32); a group is 16 frame points (8 with the wide operator).  May be
+ * (FP32), 1 on small grids (as for sbpe_set_tile_rows); a group is 16 frame
+ * points (8 with the wide operator).  May be
  * called at any time; it applies to the context's own sweeps (batches use the
  * default of their dtype).  SBPE_EINVAL outside 1..64. */
 sbpe_status sbpe_set_frame_loop(sbpe_ctx_t ctx, int groups);

@@ -315,6 +315,35 @@ def test_tile_rows_do_not_change_results():
         assert np.array_equal(u, out[0][0]) and np.array_equal(v, out[0][1]) and np.array_equal(r, out[0][2])
 
 
+def test_small_grid_default_shape():
+    """On a small grid the default launch shape is tiles of order + 1 rows and
+    one frame group per frame workgroup; a run in it has the bits of a run in
+    the large-grid default shape (10 rows, 2 groups)."""
+    n, nsteps = 129, 20
+    spec = W.spec_c2(n=n, nrec=8)
+    say('small-grid default shape', n)
+    out = []
+    for rows, loop in ((0, 0), (10, 2)):
+        sol = solver(spec, 'f64', tile_rows=rows)
+        if loop:
+            sol.set_frame_loop(loop)
+        try:
+            plan = S.sbpe_plan_info(sol.ctx)
+            interior = n - 2 * plan['frame_width']
+            if not loop:
+                # 60 written columns per tile, 5 rows per tile at order 4
+                assert plan['interior_workgroups'] == -(-interior // 60) * -(-interior // 5)
+            dt = T.dt_cfl(build(spec), 0.5) if not out else out[0][3]
+            sol.set_state(None, None, 0.0)
+            sol.advance(nsteps, dt)
+            u, v = sol.state_numpy()
+            out.append((u[0], v[0], sol.receivers(), dt))
+        finally:
+            sol.close()
+    u, v, r, _ = out[1]
+    assert np.array_equal(u, out[0][0]) and np.array_equal(v, out[0][1]) and np.array_equal(r, out[0][2])
+
+
 @pytest.fixture(scope='module')
 def c3_full():
     """The 2x2 x 2049^2 workload and its oracle (about a minute of CPU time)."""

@@ -894,7 +894,12 @@ __global__ void __launch_bounds__(256) k_frame_gather(const T* y, int n1, int n2
 constexpr int FRAME_LANES = 8;
 constexpr int FRAME_UNROLL = 4;
 
-template <typename T, int ORD, int PASS>
+// ROW_BRANCH: pick the lane's component row by a branch (inside the one-launch
+// sweep kernels, where a select on it is lowered to a run-time index into
+// scratch memory) or by a select (the stand-alone frame kernel, where the
+// branch costs registers: 172 against 160 in the FP64 RK2 kernel, two waves
+// per SIMD instead of three).
+template <typename T, int ORD, int PASS, bool ROW_BRANCH = true>
 __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt) {
     constexpr int R = Frame<ORD>::R;
     constexpr int RL = FRAME_LANES / 2;        // lanes per component row
@@ -1036,8 +1041,18 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
             ab[f][1] += __shfl_xor(ab[f][1], m);
         }
     T acc[NF];
+    if constexpr (ROW_BRANCH) {
+        if (q) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = q ? ab[f][1] : ab[f][0];
+            for (int f = 0; f < NF; ++f) acc[f] = ab[f][1];
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[f] = ab[f][0];
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f] = q ? ab[f][1] : ab[f][0];
+    }
     if (valid) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[f] += s0 * xp[f][0] + s1 * xp[f][1];
@@ -1128,7 +1143,7 @@ __device__ __forceinline__ void frame_sp_body(const PassArgs& A, int fwg, int nt
 
 template <typename T, int ORD, int PASS>
 __global__ void __launch_bounds__(FRAME_WG) k_frame_sp(PassArgs A) {
-    frame_sp_body<T, ORD, PASS>(A, blockIdx.x, FRAME_WG);
+    frame_sp_body<T, ORD, PASS, false>(A, blockIdx.x, FRAME_WG);
 }
 
 // ------------------------------------------------------------- interior

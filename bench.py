@@ -551,18 +551,24 @@ def main():
     if not args.no_serve:
         from paper_2003_12811_amd import serve
         log('served stream vs sequential plain solves')
-        sv = serve.serve_and_compare(args.serve_shots, args.serve_rate,
-                                     [int(x) for x in args.serve_sizes.split(',')], args.serve_steps,
-                                     workers=args.serve_workers)
-        sv["scale_down"] = ("the 256-shot stream (20/s, 1500 steps) with 64 shots of 300 steps arriving at "
-                            "100/s: the same offered grid-point updates per second")
-        if "c2_f32" in line:
-            sv["plain_f32_updates_per_s"] = line["c2_f32"]["value"]
-            sv["served_over_plain_f32"] = sv["served"]["updates_per_s"] / line["c2_f32"]["value"]
-            # the device alone: batched sweeps timed with HIP events, against
-            # the plain FP32 rate of one 1025^2 solve
-            sv["served_device_over_plain_f32"] = sv["served"]["device_updates_per_s"] / line["c2_f32"]["value"]
-        line["serving"] = sv
+        # a failure of this section (a shot whose setup fails) is reported in
+        # the line instead of ending the run before it is printed
+        try:
+            sv = serve.serve_and_compare(args.serve_shots, args.serve_rate,
+                                         [int(x) for x in args.serve_sizes.split(',')], args.serve_steps,
+                                         workers=args.serve_workers)
+            sv["scale_down"] = ("the 256-shot stream (20/s, 1500 steps) with 64 shots of 300 steps arriving at "
+                                "100/s: the same offered grid-point updates per second")
+            if "c2_f32" in line:
+                sv["plain_f32_updates_per_s"] = line["c2_f32"]["value"]
+                sv["served_over_plain_f32"] = sv["served"]["updates_per_s"] / line["c2_f32"]["value"]
+                # the device alone: batched sweeps timed with HIP events, against
+                # the plain FP32 rate of one 1025^2 solve
+                sv["served_device_over_plain_f32"] = sv["served"]["device_updates_per_s"] / line["c2_f32"]["value"]
+            line["serving"] = sv
+        except Exception as e:
+            log('serving section failed: %r' % (e,))
+            line["serving"] = {"error": repr(e)}
     if not args.no_3d:
         log('3-D block, fp64')
         line["block3d"] = bench_3d(args.n3d)
